@@ -1,0 +1,231 @@
+"""ctypes wrapper of the FP64 CPU reference (test infrastructure only).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this module.  It converts the seeded workload description into the
+reference's plain double arrays and calls ``libmgref.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+DEFAULTS = dict(
+    # Eq.(14) pose weights (appendix 'Pose Reaching Cost')
+    a0=2000.0, a1=350.0, a2=100.0, a3=100.0,
+    # Eq.(16) smoothness weights (appendix 'Path-Length Minimization & Smoothness Costs')
+    a6=5000.0, a7=50.0, a8=5000.0, a9=1.0,
+    # Eq.(17): weight 5000 for every soft constraint (appendix 'cuRobo Parameters'), band 0.1
+    w_bound=5000.0, eta2=0.1,
+    # Eq.(10)/(11): activation distance 2.5 cm, weight 5000 (appendix 'cuRobo Parameters')
+    w_coll=5000.0, eta=0.025,
+    # first-pass time step of the dt re-optimisation (appendix 'Time-step Descretization and Temporal Weight Scaling')
+    dt=0.25,
+    vel_all=0, swept=0, sweep_steps=4,
+)
+# Line search constants (Reading: the Nocedal & Wright defaults).
+ETA1 = 1e-4
+ETA_W = 0.9
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+class _Robot(C.Structure):
+    _fields_ = [("n_links", C.c_int), ("dof", C.c_int), ("parent", _ip), ("joint", _ip),
+                ("fixed_tf", _dp), ("n_spheres", C.c_int), ("sphere_link", _ip),
+                ("sphere", _dp), ("n_ee", C.c_int), ("ee_link", _ip), ("ee_tf", _dp),
+                ("q_lo", _dp), ("q_hi", _dp)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("a0", C.c_double), ("a1", C.c_double), ("a2", C.c_double), ("a3", C.c_double),
+                ("a6", C.c_double), ("a7", C.c_double), ("a8", C.c_double), ("a9", C.c_double),
+                ("w_bound", C.c_double), ("eta2", C.c_double), ("w_coll", C.c_double),
+                ("eta", C.c_double), ("dt", C.c_double), ("vel_all", C.c_int),
+                ("swept", C.c_int), ("sweep_steps", C.c_int)]
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.environ.get("MGREF_LIB") or _build.ensure()
+        L = C.CDLL(path)
+        L.mgref_traj_cost.restype = C.c_double
+        L.mgref_box_sdf.restype = C.c_double
+        L.mgref_dc.restype = C.c_double
+        L.mgref_bound.restype = C.c_double
+        L.mgref_ls_select.restype = C.c_int
+        L.mgref_linesearch.restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_ip)
+
+
+class Ref:
+    """Reference evaluator bound to one robot and one parameter set."""
+
+    def __init__(self, robot, **params):
+        p = dict(DEFAULTS)
+        p.update(params)
+        self.params = p
+        self._keep = []
+        def keep(x):
+            self._keep.append(x[0])
+            return x[1]
+        self.robot = robot
+        self._rb = _Robot(n_links=robot.n_links, dof=robot.dof,
+                          parent=keep(_i(robot.parent)), joint=keep(_i(robot.joint)),
+                          fixed_tf=keep(_d(robot.fixed_tf)), n_spheres=robot.n_spheres,
+                          sphere_link=keep(_i(robot.sphere_link)), sphere=keep(_d(robot.sphere)),
+                          n_ee=robot.n_ee, ee_link=keep(_i(robot.ee_link)),
+                          ee_tf=keep(_d(robot.ee_tf)), q_lo=keep(_d(robot.q_lo)),
+                          q_hi=keep(_d(robot.q_hi)))
+        self._pr = _Params(**p)
+
+    # -- kinematics and geometry ---------------------------------------
+    def fk(self, q):
+        rb = self.robot
+        q, qp = _d(q)
+        tf = np.zeros((rb.n_links, 12)); sp = np.zeros((rb.n_spheres, 3)); ee = np.zeros((rb.n_ee, 7))
+        lib().mgref_fk(C.byref(self._rb), qp, _d(tf)[1], _d(sp)[1], _d(ee)[1])
+        return tf, sp, ee
+
+    def pose_error(self, qT, goal):
+        pe = np.zeros(self.robot.n_ee); re = np.zeros(self.robot.n_ee)
+        g, gp = _d(goal)
+        q, qp = _d(qT)
+        lib().mgref_pose_error(C.byref(self._rb), qp, gp, _d(pe)[1], _d(re)[1])
+        return pe, re
+
+    # -- costs -----------------------------------------------------------
+    def traj_cost(self, boxes, q0, goal, q, grad=True):
+        """Cost, gradient [T,D] (or None), min clearance, terms[4]."""
+        pose, dims = boxes
+        pose, pp = _d(np.asarray(pose).reshape(-1, 7)); dims, dp = _d(np.asarray(dims).reshape(-1, 3))
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, self.robot.dof)
+        T = q.shape[0]
+        g = np.zeros_like(q) if grad else None
+        mc = C.c_double(0.0)
+        terms = np.zeros(4)
+        q0a, q0p = _d(q0)
+        ga, gp_ = _d(goal)
+        c = lib().mgref_traj_cost(C.byref(self._rb), C.byref(self._pr), pose.shape[0], pp, dp,
+                                  q0p, gp_, T, _d(q)[1], _d(g)[1] if grad else None,
+                                  C.byref(mc), _d(terms)[1])
+        return c, g, mc.value, terms
+
+    def cost_grad_batch(self, boxes, q0, goal, T, q, nthreads=1, grad=True):
+        pose, dims = boxes
+        pose, pp = _d(np.asarray(pose).reshape(-1, 7)); dims, dp = _d(np.asarray(dims).reshape(-1, 3))
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        S = q.size // (T * self.robot.dof)
+        cost = np.zeros(S); mc = np.zeros(S)
+        g = np.zeros_like(q) if grad else None
+        lib().mgref_cost_grad_batch(C.byref(self._rb), C.byref(self._pr), pose.shape[0], pp, dp,
+                                    _d(q0)[1], _d(goal)[1], T, S, _d(q)[1], _d(cost)[1],
+                                    _d(g)[1] if grad else None, _d(mc)[1], int(nthreads))
+        return cost, g, mc
+
+    # -- solver pieces -----------------------------------------------------
+    def linesearch(self, boxes, q0, goal, x, c0, g0, d, alpha, mode=1, eta1=ETA1, eta_w=ETA_W):
+        pose, dims = boxes
+        pose, pp = _d(np.asarray(pose).reshape(-1, 7)); dims, dp = _d(np.asarray(dims).reshape(-1, 3))
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, self.robot.dof)
+        T = x.shape[0]
+        xo = np.zeros_like(x); go = np.zeros_like(x)
+        co = C.c_double(0.0); mco = C.c_double(0.0)
+        al = np.asarray(alpha, dtype=np.float64)
+        i = lib().mgref_linesearch(C.byref(self._rb), C.byref(self._pr), pose.shape[0], pp, dp,
+                                   _d(q0)[1], _d(goal)[1], T, _d(x)[1], C.c_double(c0),
+                                   _d(g0)[1], _d(d)[1], len(al), _d(al)[1], int(mode),
+                                   C.c_double(eta1), C.c_double(eta_w), _d(xo)[1],
+                                   C.byref(co), _d(go)[1], C.byref(mco))
+        return i, xo, co.value, go, mco.value
+
+    def solve(self, boxes, q0, goal, T, x, iters, m, alpha, mode=1, eta1=ETA1, eta_w=ETA_W,
+              nthreads=1, trace=False):
+        pose, dims = boxes
+        pose, pp = _d(np.asarray(pose).reshape(-1, 7)); dims, dp = _d(np.asarray(dims).reshape(-1, 3))
+        x = np.array(x, dtype=np.float64, copy=True)
+        S = x.size // (T * self.robot.dof)
+        best = np.zeros(S)
+        tr = np.zeros((iters, S)) if trace else None
+        al = np.asarray(alpha, dtype=np.float64)
+        lib().mgref_solve(C.byref(self._rb), C.byref(self._pr), pose.shape[0], pp, dp,
+                          _d(q0)[1], _d(goal)[1], T, S, x.ctypes.data_as(_dp), iters, m, len(al),
+                          _d(al)[1], int(mode), C.c_double(eta1), C.c_double(eta_w),
+                          _d(best)[1], _d(tr)[1] if trace else None, int(nthreads))
+        return x, best, tr
+
+
+# -- standalone helpers (no robot needed) -----------------------------------
+
+def box_sdf(pose, dims, c):
+    g = np.zeros(3)
+    v = lib().mgref_box_sdf(_d(pose)[1], _d(dims)[1], _d(c)[1], _d(g)[1])
+    return v, g
+
+
+def dc(d, eta):
+    s = C.c_double(0.0)
+    return lib().mgref_dc(C.c_double(d), C.c_double(eta), C.byref(s)), s.value
+
+
+def bound(x, lo, hi, eta2):
+    s = C.c_double(0.0)
+    return lib().mgref_bound(C.c_double(x), C.c_double(lo), C.c_double(hi), C.c_double(eta2),
+                             C.byref(s)), s.value
+
+
+def mat_to_quat(R):
+    q = np.zeros(4)
+    lib().mgref_mat_to_quat(_d(np.asarray(R, dtype=np.float64).reshape(9))[1], _d(q)[1])
+    return q
+
+
+def derivatives(q0, q, dt):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    T, D = q.shape
+    v = np.zeros((T + 1, D)); a = np.zeros((T + 1, D)); j = np.zeros((T + 1, D))
+    lib().mgref_derivatives(T, D, _d(q0)[1], _d(q)[1], C.c_double(dt), _d(v)[1], _d(a)[1], _d(j)[1])
+    return v, a, j
+
+
+def lbfgs_step(n, m, reset, state, x, g):
+    """state: dict with count, head, S, Y, rho, x_prev, g_prev (mutated)."""
+    cnt = C.c_int(state["count"]); hd = C.c_int(state["head"])
+    d = np.zeros(n)
+    lib().mgref_lbfgs_step(n, m, int(reset), C.byref(cnt), C.byref(hd),
+                           state["S"].ctypes.data_as(_dp), state["Y"].ctypes.data_as(_dp),
+                           state["rho"].ctypes.data_as(_dp), state["x_prev"].ctypes.data_as(_dp),
+                           state["g_prev"].ctypes.data_as(_dp), _d(x)[1], _d(g)[1], _d(d)[1])
+    state["count"], state["head"] = cnt.value, hd.value
+    return d
+
+
+def new_lbfgs_state(n, m):
+    mm = max(m, 1)
+    return dict(count=0, head=0, S=np.zeros((mm, n)), Y=np.zeros((mm, n)), rho=np.zeros(mm),
+                x_prev=np.zeros(n), g_prev=np.zeros(n))
+
+
+def ls_select(alpha, c0, g0d, c, gd, mode, eta1=ETA1, eta_w=ETA_W):
+    al = np.asarray(alpha, dtype=np.float64)
+    return lib().mgref_ls_select(len(al), _d(al)[1], C.c_double(c0), C.c_double(g0d),
+                                 _d(c)[1], _d(gd)[1], int(mode), C.c_double(eta1),
+                                 C.c_double(eta_w))

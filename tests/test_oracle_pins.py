@@ -1,0 +1,571 @@
+"""Pins of the FP64 reference against facts fixed outside itself.
+
+Each test compares the reference with the paper's printed closed forms and
+constants, textbook identities, brute force on tiny inputs or an independent
+library route (numpy polynomial fits, scipy rotations), so that a dropped
+term, a wrong sign or index or a transposed operand fails at least one test.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from oracle import ref
+from paper_2310_17274_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
+
+
+def tf4(m12):
+    M = np.eye(4)
+    M[:3, :] = np.asarray(m12).reshape(3, 4)
+    return M
+
+
+def rotz4(t):
+    M = np.eye(4)
+    M[:2, :2] = [[math.cos(t), -math.sin(t)], [math.sin(t), math.cos(t)]]
+    return M
+
+
+def independent_fk(robot, q):
+    """Link transforms by 4x4 homogeneous products, written in the test."""
+    T = []
+    for l in range(robot.n_links):
+        P = np.eye(4) if robot.parent[l] < 0 else T[robot.parent[l]]
+        J = P @ tf4(robot.fixed_tf[l])
+        if robot.joint[l] >= 0:
+            J = J @ rotz4(q[robot.joint[l]])
+        T.append(J)
+    return T
+
+
+def quat_wxyz(R):
+    x, y, z, w = Rotation.from_matrix(R).as_quat()
+    return np.array([w, x, y, z])
+
+
+def same_quat(a, b, tol):
+    return min(np.abs(a - b).max(), np.abs(a + b).max()) < tol
+
+
+@pytest.fixture(scope="module")
+def arm(oracle_lib):
+    return wl.make_arm(seed=0, n_spheres=20)
+
+
+# --------------------------------------------------------------------------
+# Constants printed in the paper
+
+def test_defaults_match_paper_constants():
+    g = json.load(open(GOLDEN))
+    d = ref.DEFAULTS
+    for k in ("a0", "a1", "a2", "a3"):
+        assert d[k] == g["pose_weights"][k]
+    for k in ("a6", "a7", "a8", "a9"):
+        assert d[k] == g["smooth_weights"][k]
+    assert d["eta2"] == g["bound_band"]["eta2"]
+    assert d["w_bound"] == d["w_coll"] == g["soft_constraint_weight"]["w"]
+    assert d["eta"] == g["activation_distance"]["eta"]
+    assert d["dt"] == g["first_pass_dt"]["dt"]
+    assert tuple(g["line_search_magnitudes"]["alpha"]) == wl.ALPHA_4
+    assert wl.ALPHA_4[0] == g["noisy_step"]["alpha0"] == wl.ALPHA_8[0]
+
+
+# --------------------------------------------------------------------------
+# P1 kinematics
+
+def test_fk_zero_angles_is_product_of_fixed_transforms(arm):
+    r = ref.Ref(arm)
+    tf, sp, ee = r.fk(np.zeros(arm.dof))
+    P = np.eye(4)
+    for l in range(arm.n_links):
+        P = P @ tf4(arm.fixed_tf[l])
+        np.testing.assert_allclose(tf[l].reshape(3, 4), P[:3], atol=1e-14)
+
+
+def test_fk_matches_homogeneous_products_and_is_orthonormal(arm):
+    r = ref.Ref(arm)
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        q = rng.uniform(-2.8, 2.8, arm.dof)
+        tf, sp, ee = r.fk(q)
+        T = independent_fk(arm, q)
+        for l in range(arm.n_links):
+            np.testing.assert_allclose(tf[l].reshape(3, 4), T[l][:3], atol=1e-13)
+            R = tf[l].reshape(3, 4)[:, :3]
+            np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-12)
+        for m in range(arm.n_spheres):
+            c = T[arm.sphere_link[m]] @ np.append(arm.sphere[m, :3], 1.0)
+            np.testing.assert_allclose(sp[m], c[:3], atol=1e-13)
+        E = T[arm.ee_link[0]] @ tf4(arm.ee_tf[0])
+        np.testing.assert_allclose(ee[0, :3], E[:3, 3], atol=1e-13)
+        assert same_quat(ee[0, 3:], quat_wxyz(E[:3, :3]), 1e-12)
+
+
+def test_tab6_revolute_z_closed_form(oracle_lib):
+    """Tab.6 'Revolute Z' full link transformation F * Rz(theta), typed from
+    the table entry by entry."""
+    rng = np.random.default_rng(3)
+    for _ in range(10):
+        R = Rotation.random(random_state=rng.integers(1 << 30)).as_matrix()
+        f = np.concatenate([R, rng.normal(size=(3, 1))], axis=1).reshape(-1)
+        th = rng.uniform(-3, 3)
+        robot = wl.Robot(parent=np.array([-1], np.int32), joint=np.array([0], np.int32),
+                         fixed_tf=f[None, :], sphere_link=np.array([0], np.int32),
+                         sphere=np.array([[0.0, 0.0, 0.0, 0.05]]), ee_link=np.array([0], np.int32),
+                         ee_tf=np.array([[1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0.0]]),
+                         q_lo=np.array([-3.0]), q_hi=np.array([3.0]))
+        tf, _, _ = ref.Ref(robot).fk(np.array([th]))
+        c, s = math.cos(th), math.sin(th)
+        expect = [f[0] * c + f[1] * s, -f[0] * s + f[1] * c, f[2], f[3],
+                  f[4] * c + f[5] * s, -f[4] * s + f[5] * c, f[6], f[7],
+                  f[8] * c + f[9] * s, -f[8] * s + f[9] * c, f[10], f[11]]
+        np.testing.assert_allclose(tf[0], expect, atol=1e-13)
+
+
+def test_first_joint_rotates_everything_about_base_z(arm):
+    r = ref.Ref(arm)
+    rng = np.random.default_rng(11)
+    q = rng.uniform(-2, 2, arm.dof)
+    phi = 0.7
+    _, sp0, ee0 = r.fk(q)
+    q1 = q.copy(); q1[0] += phi
+    _, sp1, ee1 = r.fk(q1)
+    Rz = rotz4(phi)[:3, :3]
+    np.testing.assert_allclose(sp1, sp0 @ Rz.T, atol=1e-13)
+    np.testing.assert_allclose(ee1[0, :3], Rz @ ee0[0, :3], atol=1e-13)
+
+
+def test_distance_to_joint_axis_invariant_under_that_joint(arm):
+    r = ref.Ref(arm)
+    rng = np.random.default_rng(12)
+    q = rng.uniform(-2, 2, arm.dof)
+    for j in range(arm.dof):
+        tf, sp, _ = r.fk(q)
+        z, o = tf[j].reshape(3, 4)[:, 2], tf[j].reshape(3, 4)[:, 3]
+        q2 = q.copy(); q2[j] += 0.9
+        tf2, sp2, _ = r.fk(q2)
+        for m in np.nonzero(arm.sphere_link >= j)[0]:
+            d1 = np.linalg.norm(np.cross(z, sp[m] - o))
+            d2 = np.linalg.norm(np.cross(z, sp2[m] - o))
+            assert abs(d1 - d2) < 1e-12
+            assert abs(np.dot(z, sp[m] - o) - np.dot(z, sp2[m] - o)) < 1e-12
+
+
+def test_shepperd_against_scipy(oracle_lib):
+    rots = Rotation.random(200, random_state=5)
+    # include the near-180-degree rotations that stress the branches
+    extra = Rotation.from_rotvec(np.array([[math.pi - 1e-9, 0, 0], [0, math.pi, 0],
+                                           [0, 0, math.pi], [1, 1, 1]]) *
+                                 np.array([[1], [1], [1], [math.pi / math.sqrt(3)]]))
+    for R in list(rots.as_matrix()) + list(extra.as_matrix()):
+        assert same_quat(ref.mat_to_quat(R), quat_wxyz(R), 1e-12)
+
+
+# --------------------------------------------------------------------------
+# P2 cuboid signed distance
+
+def brute_sdf(pose, dims, c, h=2e-3):
+    """Dense sampling of the box surface; sign from a containment test."""
+    R = Rotation.from_quat([pose[4], pose[5], pose[6], pose[3]]).as_matrix()
+    p = R.T @ (np.asarray(c) - pose[:3])
+    half = np.asarray(dims) / 2
+    best = np.inf
+    for ax in range(3):
+        o1, o2 = [i for i in range(3) if i != ax]
+        u = np.arange(-half[o1], half[o1] + h / 2, h)
+        v = np.arange(-half[o2], half[o2] + h / 2, h)
+        U, V = np.meshgrid(u, v, indexing="ij")
+        for sgn in (-1, 1):
+            pts = np.zeros(U.shape + (3,))
+            pts[..., ax] = sgn * half[ax]
+            pts[..., o1] = U
+            pts[..., o2] = V
+            best = min(best, np.linalg.norm(pts - p, axis=-1).min())
+    inside = np.all(np.abs(p) <= half)
+    return -best if inside else best
+
+
+def test_sdf_brute_force(oracle_lib):
+    rng = np.random.default_rng(21)
+    for _ in range(25):
+        q = Rotation.random(random_state=rng.integers(1 << 30)).as_quat()
+        pose = np.array([*rng.uniform(-0.2, 0.2, 3), q[3], q[0], q[1], q[2]])
+        dims = rng.uniform(0.05, 0.3, 3)
+        c = pose[:3] + rng.uniform(-0.3, 0.3, 3)
+        v, g = ref.box_sdf(pose, dims, c)
+        bf = brute_sdf(pose, dims, c)
+        assert abs(v - bf) <= 2e-3 * math.sqrt(2) / 2 + 1e-9, (v, bf)
+        assert abs(np.linalg.norm(g) - 1.0) < 1e-12
+
+
+def test_sdf_special_cases(oracle_lib):
+    q = Rotation.from_rotvec([0.3, -0.2, 0.5]).as_quat()
+    pose = np.array([0.1, -0.2, 0.3, q[3], q[0], q[1], q[2]])
+    dims = np.array([0.2, 0.4, 0.6])
+    R = Rotation.from_quat(q).as_matrix()
+    center = pose[:3]
+    assert ref.box_sdf(pose, dims, center)[0] == pytest.approx(-0.1, abs=1e-14)
+    # on the +y face
+    assert ref.box_sdf(pose, dims, center + R @ [0.05, 0.2, 0.1])[0] == pytest.approx(0, abs=1e-14)
+    # outside along +z: |p_z| - h_z
+    v, g = ref.box_sdf(pose, dims, center + R @ [0.0, 0.0, 0.5])
+    assert v == pytest.approx(0.2, abs=1e-14)
+    np.testing.assert_allclose(g, R[:, 2], atol=1e-14)
+    # outside a corner: Euclidean distance to the corner
+    corner = np.array([0.1, -0.2, 0.3])
+    off = np.array([0.03, -0.04, 0.12])
+    v, g = ref.box_sdf(pose, dims, center + R @ (corner + off))
+    assert v == pytest.approx(np.linalg.norm(off), abs=1e-14)
+    # inside nearer the -x face
+    v, g = ref.box_sdf(pose, dims, center + R @ [-0.07, 0.0, 0.0])
+    assert v == pytest.approx(-0.03, abs=1e-14)
+    np.testing.assert_allclose(g, -R[:, 0], atol=1e-14)
+
+
+def test_sdf_gradient_finite_difference(oracle_lib):
+    rng = np.random.default_rng(22)
+    q = Rotation.random(random_state=4).as_quat()
+    pose = np.array([0.0, 0.0, 0.0, q[3], q[0], q[1], q[2]])
+    dims = np.array([0.2, 0.3, 0.4])
+    for _ in range(40):
+        c = rng.uniform(-0.4, 0.4, 3)
+        v, g = ref.box_sdf(pose, dims, c)
+        h = 1e-7
+        fd = np.array([(ref.box_sdf(pose, dims, c + h * e)[0] - ref.box_sdf(pose, dims, c - h * e)[0]) / (2 * h)
+                       for e in np.eye(3)])
+        if np.linalg.norm(fd - g) > 1e-5:
+            # only allowed on the interior medial planes, where sdf has a kink
+            R = Rotation.from_quat(q).as_matrix()
+            a = np.abs(R.T @ c) - dims / 2
+            s = np.sort(a)
+            assert a.max() < 0 and s[2] - s[1] < 1e-6
+        else:
+            assert np.linalg.norm(fd - g) < 1e-5
+
+
+# --------------------------------------------------------------------------
+# P3 activation profiles, Eq.(10) and Eq.(17)
+
+def test_collision_profile_eq10(oracle_lib):
+    eta = 0.025
+    e = 1e-9
+    assert ref.dc(e, eta)[0] == pytest.approx(0.5 * eta, abs=1e-8)
+    assert ref.dc(-e, eta)[0] == pytest.approx(0.5 * eta, abs=1e-8)
+    assert ref.dc(-eta + e, eta)[0] == pytest.approx(0.0, abs=1e-8)
+    assert ref.dc(-eta - e, eta)[0] == 0.0
+    assert ref.dc(e, eta)[1] == pytest.approx(1.0) and ref.dc(-e, eta)[1] == pytest.approx(1.0, abs=1e-6)
+    assert ref.dc(-eta + e, eta)[1] == pytest.approx(0.0, abs=1e-6)
+    assert ref.dc(0.3, eta)[0] - ref.dc(0.1, eta)[0] == pytest.approx(0.2)
+    xs = np.linspace(-0.05, 0.05, 2001)
+    vals = [ref.dc(x, eta)[0] for x in xs]
+    assert np.all(np.diff(vals) >= 0)
+    for x in xs[::50]:
+        h = 1e-7
+        fd = (ref.dc(x + h, eta)[0] - ref.dc(x - h, eta)[0]) / (2 * h)
+        assert fd == pytest.approx(ref.dc(x, eta)[1], abs=1e-5)
+
+
+def test_bound_profile_eq17(oracle_lib):
+    lo, hi, eta2 = -2.8, 2.8, 0.1
+    e = 1e-9
+    for edge, inward in ((lo, +1), (hi, -1)):
+        assert ref.bound(edge - inward * e, lo, hi, eta2)[0] == pytest.approx(0.5 * eta2, abs=1e-8)
+        assert ref.bound(edge + inward * e, lo, hi, eta2)[0] == pytest.approx(0.5 * eta2, abs=1e-8)
+        assert ref.bound(edge + inward * (eta2 - e), lo, hi, eta2)[0] == pytest.approx(0, abs=1e-8)
+        assert ref.bound(edge - inward * e, lo, hi, eta2)[1] == pytest.approx(-inward)
+        assert ref.bound(edge + inward * e, lo, hi, eta2)[1] == pytest.approx(-inward, abs=1e-6)
+    assert ref.bound(0.0, lo, hi, eta2) == (0.0, 0.0)
+    assert ref.bound(3.8, lo, hi, eta2)[0] == pytest.approx(1.0 + 0.05)
+    for x in np.linspace(-3.2, 3.2, 97):
+        h = 1e-7
+        fd = (ref.bound(x + h, lo, hi, eta2)[0] - ref.bound(x - h, lo, hi, eta2)[0]) / (2 * h)
+        assert fd == pytest.approx(ref.bound(x, lo, hi, eta2)[1], abs=1e-5)
+
+
+# --------------------------------------------------------------------------
+# P4 five-point stencils
+
+def poly_derivs(vals, h):
+    """Derivatives at the centre of the degree-4 interpolant through five
+    equally spaced samples (numpy polynomial fit, independent of the stencil
+    coefficients)."""
+    x = np.arange(-2, 3) * h
+    p = np.polynomial.Polynomial.fit(x, vals, 4).convert()
+    return p.deriv(1)(0.0), p.deriv(2)(0.0), p.deriv(3)(0.0)
+
+
+def test_stencils_equal_interpolant_derivatives(oracle_lib):
+    rng = np.random.default_rng(31)
+    T, D, h = 9, 3, 0.25
+    q0 = rng.normal(size=D)
+    q = rng.normal(size=(T, D))
+    v, a, j = ref.derivatives(q0, q, h)
+    X = np.concatenate([np.tile(q0, (3, 1)), q, np.tile(q[-1], (2, 1))])  # tau=-2..T+2
+    for tau in range(T + 1):
+        for d in range(D):
+            pv, pa, pj = poly_derivs(X[tau:tau + 5, d], h)
+            assert v[tau, d] == pytest.approx(pv, rel=1e-9, abs=1e-9)
+            assert a[tau, d] == pytest.approx(pa, rel=1e-9, abs=1e-9)
+            assert j[tau, d] == pytest.approx(pj, rel=1e-9, abs=1e-9)
+
+
+def test_stencil_polynomial_exactness(oracle_lib):
+    T, h = 12, 0.25
+    t = np.arange(0, T + 1) * h
+    c0, c1, c2, c3 = 0.3, -0.7, 0.4, 0.9
+    for deg in (1, 2, 3):
+        f = c0 + c1 * t + (c2 * t ** 2 if deg >= 2 else 0) + (c3 * t ** 3 if deg >= 3 else 0)
+        v, a, j = ref.derivatives(np.array([f[0]]), f[1:, None], h)
+        inner = slice(3, T - 2)   # stencils that touch no padded state
+        if deg == 1:
+            np.testing.assert_allclose(v[inner, 0], c1, atol=1e-12)
+            np.testing.assert_allclose(a[inner, 0], 0.0, atol=1e-10)
+            np.testing.assert_allclose(j[inner, 0], 0.0, atol=1e-9)
+        if deg == 2:
+            np.testing.assert_allclose(a[inner, 0], 2 * c2, atol=1e-10)
+            np.testing.assert_allclose(j[inner, 0], 0.0, atol=1e-9)
+        if deg == 3:
+            np.testing.assert_allclose(j[inner, 0], 6 * c3, atol=1e-9)   # constant jerk of a cubic
+
+
+# --------------------------------------------------------------------------
+# Cost assembly
+
+def make_problem(seed=0, T=6, n_boxes=6, n_spheres=20):
+    robot = wl.make_arm(seed=0, n_spheres=n_spheres)
+    rng = np.random.default_rng(seed)
+    r = ref.Ref(robot)
+    q0 = rng.uniform(-1, 1, robot.dof)
+    q = q0 + np.cumsum(rng.normal(0, 0.15, (T, robot.dof)), axis=0)
+    q[:, 1] = np.linspace(2.72, 2.76, T)           # inside the upper joint-limit band
+    q[-1, 3] = -2.83                               # beyond the lower limit
+    # boxes centred near some sphere centres so that several pairs are
+    # penetrating or inside the activation band
+    _, sp, _ = r.fk(q[T // 2])
+    pick = rng.choice(robot.n_spheres, n_boxes, replace=False)
+    quat = Rotation.random(n_boxes, random_state=seed).as_quat()
+    pose = np.concatenate([sp[pick] + rng.normal(0, 0.08, (n_boxes, 3)),
+                           quat[:, [3, 0, 1, 2]]], axis=1)
+    dims = rng.uniform(0.05, 0.25, (n_boxes, 3))
+    goal = np.concatenate([rng.uniform(-0.5, 0.5, 3), Rotation.random(random_state=seed + 1).as_quat()[[3, 0, 1, 2]]])
+    return robot, (pose, dims), q0, goal[None, :], q
+
+
+def test_cost_assembly_by_terms(oracle_lib):
+    robot, boxes, q0, goal, q = make_problem()
+    r = ref.Ref(robot)
+    c, g, mc, terms = r.traj_cost(boxes, q0, goal, q)
+    P = r.params
+    assert np.all(terms > 0)
+    assert c == pytest.approx(terms.sum(), rel=1e-14)
+    # smoothness from interpolant derivatives of the padded trajectory
+    T, D = q.shape
+    X = np.concatenate([np.tile(q0, (3, 1)), q, np.tile(q[-1], (2, 1))])
+    cs = 0.0
+    for tau in range(T + 1):
+        for d in range(D):
+            pv, pa, pj = poly_derivs(X[tau:tau + 5, d], P["dt"])
+            if tau == T:
+                cs += P["a6"] * math.log(math.cosh(P["a7"] * pv))
+            cs += P["a8"] * pa ** 2 + P["a9"] * pj ** 2
+    assert terms[0] == pytest.approx(cs, rel=1e-9)
+    # joint limits: sum over waypoints and joints of the Eq.(17) profile
+    cb = sum(ref.bound(q[t, d], robot.q_lo[d], robot.q_hi[d], P["eta2"])[0] for t in range(T) for d in range(D))
+    assert terms[1] == pytest.approx(P["w_bound"] * cb, rel=1e-12)
+    # collision: sum over waypoints, spheres and cuboids; centres from the
+    # test's own homogeneous products
+    cc, mcx = 0.0, P["eta"]
+    for t in range(T):
+        Tl = independent_fk(robot, q[t])
+        for m in range(robot.n_spheres):
+            cen = (Tl[robot.sphere_link[m]] @ np.append(robot.sphere[m, :3], 1))[:3]
+            for k in range(len(boxes[0])):
+                sdf = ref.box_sdf(boxes[0][k], boxes[1][k], cen)[0]
+                cc += ref.dc(robot.sphere[m, 3] - sdf, P["eta"])[0]
+                mcx = min(mcx, sdf - robot.sphere[m, 3])
+    assert terms[2] == pytest.approx(P["w_coll"] * cc, rel=1e-12)
+    assert mc == pytest.approx(mcx, abs=1e-14)
+    assert mc < 0   # the trajectory collides
+
+
+def test_pose_cost_closed_forms(oracle_lib):
+    """Pose term at T = 1 with no obstacles and joints inside the limits:
+    a pure offset delta costs a0 logcosh(a2 delta); a pure rotation by phi
+    costs a1 logcosh(a3 * 2 sin(phi/4)) (quaternion chord of angle phi)."""
+    robot = wl.make_arm(seed=0, n_spheres=4)
+    r = ref.Ref(robot)
+    P = r.params
+    q = np.array([0.3, -0.5, 0.2, 1.0, -0.4, 0.6, 0.1])
+    _, _, ee = r.fk(q)
+    none = (np.zeros((0, 7)), np.zeros((0, 3)))
+    c, g, mc, terms = r.traj_cost(none, q, ee, q[None, :])
+    assert terms[3] == pytest.approx(0.0, abs=1e-9)
+    assert np.abs(g).max() < 1e-6
+    goal = ee.copy(); goal[0, :3] += [0.01, -0.02, 0.005]
+    delta = np.linalg.norm([0.01, -0.02, 0.005])
+    assert r.traj_cost(none, q, goal, q[None, :])[3][3] == pytest.approx(P["a0"] * math.log(math.cosh(P["a2"] * delta)), rel=1e-9)
+    for phi in (0.01, 0.3, 2.0, 3.1):
+        Rg = Rotation.from_rotvec(phi * np.array([0.6, 0.0, 0.8])) * Rotation.from_quat(ee[0, [4, 5, 6, 3]])
+        x, y, z, w = Rg.as_quat()
+        for sgn in (1, -1):
+            goal = ee.copy(); goal[0, 3:] = sgn * np.array([w, x, y, z])
+            expect = P["a1"] * math.log(math.cosh(P["a3"] * 2 * math.sin(phi / 4)))
+            assert r.traj_cost(none, q, goal, q[None, :])[3][3] == pytest.approx(expect, rel=1e-9)
+
+
+# --------------------------------------------------------------------------
+# P5 exact gradient against central finite differences
+
+@pytest.mark.parametrize("case", ["to", "to_vel_all", "ik"])
+def test_gradient_matches_central_differences(oracle_lib, case):
+    T = 1 if case == "ik" else 6
+    robot, boxes, q0, goal, q = make_problem(seed=5, T=T)
+    r = ref.Ref(robot, vel_all=1 if case == "to_vel_all" else 0)
+    c, g, _, terms = r.traj_cost(boxes, q0, goal, q)
+    assert terms[2] > 0 and terms[3] > 0
+    h = 1e-6
+    fd = np.zeros_like(q)
+    for idx in np.ndindex(q.shape):
+        qp = q.copy(); qp[idx] += h
+        qm = q.copy(); qm[idx] -= h
+        fd[idx] = (r.traj_cost(boxes, q0, goal, qp, grad=False)[0] - r.traj_cost(boxes, q0, goal, qm, grad=False)[0]) / (2 * h)
+    assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+def test_two_arm_tree_gradient(oracle_lib):
+    robot = wl.make_two_arm(seed=0, n_spheres=24)
+    r = ref.Ref(robot)
+    rng = np.random.default_rng(8)
+    T = 4
+    q0 = rng.uniform(-1, 1, robot.dof)
+    q = q0 + np.cumsum(rng.normal(0, 0.2, (T, robot.dof)), axis=0)
+    _, sp, _ = r.fk(q[1])
+    # centres off the boxes' interior medial planes, where the distance kinks
+    pose = np.concatenate([sp[:5] + [0.031, -0.012, 0.022], np.tile([1.0, 0, 0, 0], (5, 1))], axis=1)
+    boxes = (pose, rng.uniform(0.08, 0.14, (5, 3)))
+    goal = np.array([[0.3, 0.2, 0.4, 1, 0, 0, 0], [-0.2, 0.4, 0.5, 0, 1, 0, 0]], dtype=float)
+    c, g, _, terms = r.traj_cost(boxes, q0, goal, q)
+    assert terms[2] > 0
+    # joints of one arm do not move the other arm's spheres or goal
+    h = 1e-6
+    fd = np.zeros_like(q)
+    for idx in np.ndindex(q.shape):
+        qp = q.copy(); qp[idx] += h
+        qm = q.copy(); qm[idx] -= h
+        fd[idx] = (r.traj_cost(boxes, q0, goal, qp, grad=False)[0] - r.traj_cost(boxes, q0, goal, qm, grad=False)[0]) / (2 * h)
+    assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(fd)
+
+
+# --------------------------------------------------------------------------
+# P6 L-BFGS two-loop = dense BFGS inverse-Hessian recursion
+
+def test_two_loop_equals_dense_bfgs(oracle_lib):
+    rng = np.random.default_rng(41)
+    n, m = 12, 4
+    A = rng.normal(size=(n, n)); A = A @ A.T + n * np.eye(n)
+    st = ref.new_lbfgs_state(n, m)
+    xs = [rng.normal(size=n) for _ in range(7)]
+    pairs = []
+    d = ref.lbfgs_step(n, m, True, st, xs[0], A @ xs[0])
+    g0 = A @ xs[0]
+    assert np.allclose(d, -min(1.0, 0.1 / np.abs(g0).max()) * g0)
+    for k in range(1, 7):
+        x, g = xs[k], A @ xs[k]
+        pairs.append((xs[k] - xs[k - 1], A @ (xs[k] - xs[k - 1])))
+        d = ref.lbfgs_step(n, m, False, st, x, g)
+        used = pairs[-m:]
+        s_new, y_new = used[-1]
+        H = (s_new @ y_new) / (y_new @ y_new) * np.eye(n)
+        for s, y in used:   # oldest -> newest, N&W eq. 6.17
+            rho = 1.0 / (y @ s)
+            V = np.eye(n) - rho * np.outer(y, s)
+            H = V.T @ H @ V + rho * np.outer(s, s)
+        np.testing.assert_allclose(d, -H @ g, rtol=1e-9, atol=1e-12)
+        assert st["count"] == min(k, m)
+
+
+def test_lbfgs_curvature_guard_and_gd(oracle_lib):
+    n, m = 5, 3
+    st = ref.new_lbfgs_state(n, m)
+    x0 = np.zeros(n); g0 = np.ones(n)
+    ref.lbfgs_step(n, m, True, st, x0, g0)
+    # y . s < 0: the pair is rejected, the direction stays the scaled gradient
+    x1 = np.full(n, 0.1); g1 = np.full(n, 0.5)
+    d = ref.lbfgs_step(n, m, False, st, x1, g1)
+    assert st["count"] == 0
+    np.testing.assert_allclose(d, -min(1, 0.1 / 0.5) * g1)
+    # history 0 is gradient descent with the same scaling
+    st0 = ref.new_lbfgs_state(n, 0)
+    ref.lbfgs_step(n, 0, True, st0, x0, g0)
+    d = ref.lbfgs_step(n, 0, False, st0, x1, np.full(n, 2.0))
+    np.testing.assert_allclose(d, -0.05 * np.full(n, 2.0))
+
+
+# --------------------------------------------------------------------------
+# P7 line-search selection (Alg.1)
+
+def test_linesearch_selection_table(oracle_lib):
+    al = [0.01, 0.3, 0.7, 1.0]
+    c0, g0d = 10.0, -4.0
+    # Armijo threshold c0 + 1e-4 * alpha * g0d
+    c = np.array([9.0, 8.0, 12.0, 9.99])
+    gd = np.array([-4.0, -1.0, 0.5, -3.7])
+    assert ref.ls_select(al, c0, g0d, c, gd, 0) == 3             # largest Armijo
+    assert ref.ls_select(al, c0, g0d, c, gd, 1) == 1             # -3.7 < 0.9 * -4: Wolfe fails at k=3
+    gd2 = np.array([-4.0, -1.0, 0.5, -3.5])
+    assert ref.ls_select(al, c0, g0d, c, gd2, 1) == 3
+    assert ref.ls_select(al, c0, g0d, c, gd, 2) == 1             # |-1| <= 3.6
+    c_bad = np.array([11.0, 12.0, 13.0, 14.0])
+    assert ref.ls_select(al, c0, g0d, c_bad, gd, 0) == 0         # noisy fallback
+    assert ref.ls_select([1.0], c0, g0d, np.array([9.0]), np.array([0.0]), 1) == 0
+    # Armijo edge: exactly on the threshold counts as satisfied
+    thr = c0 + 1e-4 * 1.0 * g0d
+    assert ref.ls_select(al, c0, g0d, np.array([99, 99, 99, thr]), gd, 0) == 3
+
+
+def test_linesearch_weak_wolfe_bug_guard(oracle_lib):
+    """Mode 1 rejects a candidate whose slope is still too negative."""
+    al = [0.01, 0.3, 0.7, 1.0]
+    c = np.array([9.0, 8.0, 7.0, 6.0])
+    gd = np.array([-4.0, -3.0, -3.9, -3.8])
+    assert ref.ls_select(al, 10.0, -4.0, c, gd, 1) == 1
+
+
+# --------------------------------------------------------------------------
+# P8 solve sanity: empty world, reachable goal
+
+@pytest.mark.parametrize("T", [1, 32])
+def test_solve_reaches_reachable_goal(oracle_lib, T):
+    robot = wl.make_arm(seed=0, n_spheres=8)
+    r = ref.Ref(robot)
+    rng = np.random.default_rng(51)
+    qs = rng.uniform(-1.5, 1.5, robot.dof)
+    _, _, ee = r.fk(qs)
+    none = (np.zeros((0, 7)), np.zeros((0, 3)))
+    S = 3
+    if T == 1:
+        q0 = np.zeros(robot.dof)
+        x = np.stack([qs + rng.normal(0, 0.15, robot.dof) for _ in range(S)])[:, None, :]
+    else:
+        q0 = qs + rng.normal(0, 0.2, robot.dof)
+        fr = (np.arange(1, T + 1) / T)[:, None]
+        x = np.stack([q0 * (1 - fr) + (qs + rng.normal(0, 0.1, robot.dof)) * fr for _ in range(S)])
+    xb, best, trace = r.solve(none, q0, ee, T, x.reshape(-1), 100, 4, wl.ALPHA_4, trace=True)
+    assert np.all(np.diff(trace, axis=0) <= 0)            # best cost never increases
+    xb = xb.reshape(S, T, robot.dof)
+    k = int(np.argmin(best))
+    pe, re_ = r.pose_error(xb[k, -1], ee)
+    if T == 1:
+        assert pe[0] < 1e-3 and re_[0] < 1e-2
+    else:
+        # the smoothness terms trade off against the pose term, so the
+        # trajectory ends within the success tolerance (5 mm / 0.05 rad),
+        # not exactly on the goal
+        assert pe[0] < 5e-3 and re_[0] < 5e-2
+    c_init = r.cost_grad_batch(none, q0, ee, T, x.reshape(-1), grad=False)[0]
+    assert best.max() < 0.1 * c_init.min()
