@@ -1,0 +1,196 @@
+/* mg.h -- C ABI of the MI355X (gfx950) batched trajectory-optimizer hot path.
+ *
+ * The library evaluates, for many seeds x waypoints x line-search candidates
+ * at once, the motion-generation objective of arXiv 2310.17274 (cuRobo),
+ * Sec. "Motion Generation as Optimization", Eq.(1) with its constraints
+ * turned into costs:
+ *   - forward kinematics of the robot's collision spheres (Sec. "Robot
+ *     Kinematics", Tab.6) and of the end effector;
+ *   - sphere-vs-cuboid world collision cost (Eq.(10), Eq.(11), Alg.10),
+ *     summed over cuboids and spheres, optionally swept between waypoints
+ *     (Sec. "Continuous Collision Checking");
+ *   - joint-limit cost (Eq.(17));
+ *   - five-point-stencil velocity / acceleration / jerk smoothness cost
+ *     (Eq.(16), appendix "Finite Difference for State Derivatives");
+ *   - pose-reaching cost at the last waypoint (Eq.(14));
+ * with a hand-written gradient (adjoint) that recomputes kinematics, and the
+ * solver built on it: the L-BFGS direction (Alg.6) and the parallel noisy
+ * line search (Alg.1) with best-iterate tracking (Sec. "Parallel L-BFGS
+ * Optimization").
+ *
+ * Conventions
+ *   - All floating point is fp32, integers are int32.
+ *   - A pose is 7 floats: x, y, z, qw, qx, qy, qz (unit quaternion).
+ *   - A transform is a 3x4 row-major matrix [R | p].
+ *   - Link l of the robot is T(parent(l)) * fixed_tf[l] * Rz(q[joint[l]]).
+ *   - A trajectory of problem p is T_p waypoints x D joints, row-major; the
+ *     trajectories of all seeds of all problems are concatenated in problem
+ *     order, then seed order ("rows" = sum_p S_p * T_p waypoint rows).
+ *   - "Device" pointers are HIP device memory; "host" pointers are host
+ *     memory read during the call only.  The caller owns every buffer it
+ *     passes; the library owns its context, batch tables and workspaces.
+ *   - stream is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *     and return; outputs are valid once the stream has executed it.
+ *   - Every function returns MG_OK or a negative mg_status and then writes
+ *     nothing; mg_last_error() describes the last failure of this thread.
+ *     NaN inputs propagate to NaN outputs and are not detected.
+ *   - A context is not thread safe; use one per thread or serialise calls.
+ */
+#ifndef MG_H
+#define MG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MG_OK = 0,
+  MG_ERR_ARG = -1,          /* null or inconsistent argument */
+  MG_ERR_SHAPE = -2,        /* a size outside the supported range */
+  MG_ERR_HIP = -3,          /* a HIP runtime call failed */
+  MG_ERR_OOM = -4,          /* device allocation failed */
+  MG_ERR_UNSUPPORTED = -5,  /* valid request this build does not implement */
+  MG_ERR_STATE = -6         /* call out of order (e.g. no world set) */
+} mg_status;
+
+typedef struct mg_ctx mg_ctx;       /* robot, cost parameters, worlds */
+typedef struct mg_batch mg_batch;   /* problem layout and solver workspaces */
+
+/* Robot description, all HOST pointers, copied by mg_create.
+ * Links are in topological order (parent[l] < l).  1 <= dof <= 16,
+ * n_links <= 16 along any root-to-link chain, 1 <= n_ee <= 2, radius > 0. */
+typedef struct {
+  int n_links;              /* L */
+  int dof;                  /* D */
+  int n_spheres;            /* M */
+  int n_ee;                 /* end effectors with a goal pose */
+  const int *parent;        /* [L] parent link or -1 (base frame = identity) */
+  const int *joint;         /* [L] joint index 0..D-1 rotating the link about z, or -1 */
+  const float *fixed_tf;    /* [L][12] joint frame in the parent link frame */
+  const int *sphere_link;   /* [M] */
+  const float *sphere;      /* [M][4] center in the link frame, radius */
+  const int *ee_link;       /* [n_ee] */
+  const float *ee_tf;       /* [n_ee][12] tool frame in the link frame */
+  const float *q_lo;        /* [D] joint limits (Eq.(2)) */
+  const float *q_hi;        /* [D] */
+} mg_robot_desc;
+
+/* Cost and solver parameters.  mg_default_params() fills the paper's values:
+ * a0..a3 = 2000, 350, 100, 100 (Eq.(14)); a6..a9 = 5000, 50, 5000, 1
+ * (Eq.(16)); w_bound = w_coll = 5000 and eta = 0.025 m (appendix "cuRobo
+ * Parameters"); eta2 = 0.1 (Eq.(17)); dt = 0.25 s (Alg.4 first pass). */
+typedef struct {
+  float a0, a1, a2, a3;     /* pose: a0 logcosh(a2 |dp|) + a1 logcosh(a3 d_rot) */
+  float a6, a7, a8, a9;     /* smoothness weights of Eq.(16) */
+  float w_bound, eta2;      /* joint-limit weight and band */
+  float w_coll, eta;        /* collision weight and activation distance */
+  float dt;                 /* waypoint spacing of the stencils */
+  int vel_all;              /* 0: velocity term at the last waypoint only; 1: all */
+  int swept;                /* 1: swept-sphere (continuous) collision */
+  int sweep_steps;          /* max sphere-tracing samples per half segment */
+  float ls_eta1;            /* Armijo constant (default 1e-4) */
+  float ls_eta_w;           /* Wolfe constant (default 0.9) */
+  float success_pos;        /* success: position error <= (default 0.005 m) */
+  float success_rot;        /* success: rotation angle <= (default 0.05 rad) */
+} mg_params;
+
+void mg_default_params(mg_params *out);
+
+/* Create a context on the current HIP device.  Copies robot tables and
+ * parameters to the device.  Not capturable (allocates, synchronises). */
+mg_status mg_create(const mg_robot_desc *robot, const mg_params *params, mg_ctx **out);
+void mg_destroy(mg_ctx *ctx);
+
+/* Replace the parameters (same robot).  Host-only; affects later calls. */
+mg_status mg_set_params(mg_ctx *ctx, const mg_params *params);
+
+/* Set the cuboid worlds (Sec. "World Representation": oriented bounding
+ * boxes).  offsets: HOST [n_worlds+1] prefix sums of cuboid counts;
+ * pose: DEVICE [n][7] box-to-world poses; dims: DEVICE [n][3] full side
+ * lengths (> 0).  The cuboids are converted on stream into the library's own
+ * layout; pose/dims may be reused by the caller once the stream reaches this
+ * point.  Reallocates (not capturable) only when n or n_worlds grow. */
+mg_status mg_set_worlds(mg_ctx *ctx, int n_worlds, const int *offsets,
+                        const float *pose, const float *dims, void *stream);
+
+/* Describe a batch of P problems, all HOST arrays [P]: seeds per problem
+ * (>= 1), horizon T (1..64; 1 = inverse kinematics), world index.  K_max
+ * (1..16) bounds the line-search candidates and m_max (0..16) the L-BFGS
+ * history of later calls.  Allocates tables and workspaces (not capturable). */
+mg_status mg_batch_create(mg_ctx *ctx, int P, const int *seeds, const int *horizon,
+                          const int *world, int K_max, int m_max, mg_batch **out);
+void mg_batch_destroy(mg_batch *batch);
+/* Totals of a batch: seeds and waypoint rows (floats per array = rows * D). */
+int mg_batch_seeds(const mg_batch *batch);
+int mg_batch_rows(const mg_batch *batch);
+
+/* Cost (and gradient) of every seed's trajectory (Eq.(1) as soft costs).
+ *   q_start DEVICE [P][D]   start configuration theta_0 (unused for T = 1)
+ *   goal    DEVICE [P][n_ee][7]
+ *   q       DEVICE [rows][D] trajectories
+ *   cost    DEVICE [seeds]  total cost per seed
+ *   grad    DEVICE [rows][D] d cost / d q, or NULL for cost only
+ *   min_clear DEVICE [seeds] min over waypoints, spheres and cuboids of
+ *           min(signed distance - radius, eta), or NULL; a trajectory is
+ *           collision free iff its value is >= 0.  Capturable. */
+mg_status mg_cost_grad(mg_ctx *ctx, mg_batch *batch, const float *q_start,
+                       const float *goal, const float *q, float *cost, float *grad,
+                       float *min_clear, void *stream);
+
+/* L-BFGS direction (Alg.6; Nocedal & Wright two-loop recursion) for every
+ * seed: dir = -H g with history m <= m_max kept in the batch.  reset != 0
+ * starts a new history (first iteration).  x, g, dir: DEVICE [rows][D].
+ * Pairs with <y,s> <= 1e-10 |s||y| are not stored; H0 = gamma I with gamma
+ * = <s,y>/<y,y> of the newest pair, or min(1, 0.1/|g|_inf) without one.
+ * Capturable. */
+mg_status mg_lbfgs_step(mg_ctx *ctx, mg_batch *batch, int m, int reset,
+                        const float *x, const float *g, float *dir, void *stream);
+
+/* Parallel noisy line search (Alg.1) for every seed: candidates
+ * clip(x + alpha_k dir, q_lo, q_hi), k < K, are costed with gradients in one
+ * launch; the largest k meeting the conditions is chosen, else k = 0 (the
+ * paper's 0.01 noisy step).  mode 0: Armijo c_k <= c0 + eta1 alpha_k <g0,d>;
+ * 1: + weak Wolfe <g_k,d> >= eta_w <g0,d>; 2: + strong Wolfe
+ * |<g_k,d>| <= eta_w |<g0,d>|.
+ *   alpha   HOST [K], K <= K_max
+ *   x, g0, dir DEVICE [rows][D]; c0 DEVICE [seeds]
+ *   x_out, g_out DEVICE [rows][D]; c_out DEVICE [seeds] (may alias x, g0, c0)
+ *   chosen  DEVICE [seeds] or NULL; min_clear DEVICE [seeds] or NULL.
+ * Capturable. */
+mg_status mg_linesearch(mg_ctx *ctx, mg_batch *batch, const float *q_start,
+                        const float *goal, const float *x, const float *c0,
+                        const float *g0, const float *dir, int K, const float *alpha,
+                        int mode, float *x_out, float *c_out, float *g_out, int *chosen,
+                        float *min_clear, void *stream);
+
+/* Full solve (Sec. "Parallel L-BFGS Optimization"): iters iterations of
+ * direction + line search + best tracking for every seed, in place.
+ *   x        DEVICE [rows][D]: seeds on entry, best iterate per seed on exit
+ *   best_cost DEVICE [seeds]; best_seed DEVICE [P] (argmin, lowest index on
+ *            ties) or NULL; success DEVICE [P] (best seed within
+ *            success_pos / success_rot of the goal and collision free) or NULL.
+ * use_graph != 0 captures graph_inner iterations in a hipGraph and replays it
+ * (the first call for a new argument set captures; later calls replay);
+ * use_graph == 0 launches every kernel directly.  Not capturable itself. */
+mg_status mg_solve(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
+                   float *x, int iters, int m, int K, const float *alpha, int mode,
+                   int graph_inner, int use_graph, float *best_cost, int *best_seed,
+                   int *success, void *stream);
+
+/* Measurement hooks.  mg_set_timing(batch, 1) clears the batch's timing
+ * record and from then on brackets every direct evaluation-kernel launch
+ * made for the batch with a pair of HIP events on the launch stream
+ * (launches captured into a graph are not timed); 0 turns it off.
+ * mg_eval_time waits for the recorded events and returns the mean kernel
+ * time in microseconds over the last <= 256 recorded launches and how many
+ * that was.  Not capturable. */
+mg_status mg_set_timing(mg_batch *batch, int enable);
+mg_status mg_eval_time(mg_batch *batch, float *mean_us, int *count);
+
+/* Message for the last non-OK status returned on this thread. */
+const char *mg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

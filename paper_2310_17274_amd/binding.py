@@ -1,0 +1,218 @@
+"""Python binding of libmg with the C ABI's names (include/mg.h).
+
+Argument marshalling only: torch provides device memory and the current
+stream; every step of the method runs in the HIP kernels of libmg.so.
+
+    ctx = Context(robot)                    # mg_create
+    ctx.mg_set_worlds(worlds)               # mg_set_worlds
+    b = ctx.batch(seeds, horizon, world)    # mg_batch_create
+    cost, grad, mc = ctx.mg_cost_grad(b, q_start, goal, q)
+    d = ctx.mg_lbfgs_step(b, m, reset, x, g)
+    out = ctx.mg_linesearch(b, q_start, goal, x, c0, g0, d, alpha, mode)
+    res = ctx.mg_solve(b, q_start, goal, x, iters, m, alpha, ...)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+_fp = C.POINTER(C.c_float)
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _f32(t, device):
+    return torch.as_tensor(np.asarray(t), dtype=torch.float32, device=device).contiguous()
+
+
+def default_params(**over) -> _lib.Params:
+    p = _lib.Params()
+    _lib.lib().mg_default_params(C.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+class Batch:
+    """A batch of problems (mg_batch): seeds, horizon and world per problem."""
+
+    def __init__(self, ctx: "Context", seeds, horizon, world, K_max=16, m_max=8):
+        self.ctx = ctx
+        self.seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+        self.horizon = np.ascontiguousarray(horizon, dtype=np.int32)
+        self.world = np.ascontiguousarray(world, dtype=np.int32)
+        self.P = int(self.seeds.shape[0])
+        self.K_max, self.m_max = K_max, m_max
+        h = C.c_void_p()
+        ip = C.POINTER(C.c_int)
+        check(_lib.lib().mg_batch_create(ctx.handle, self.P, self.seeds.ctypes.data_as(ip),
+                                         self.horizon.ctypes.data_as(ip),
+                                         self.world.ctypes.data_as(ip), K_max, m_max, C.byref(h)))
+        self.handle = h
+        self.n_seeds = int(self.seeds.sum())
+        self.rows = int((self.seeds * self.horizon).sum())
+        assert self.n_seeds == _lib.lib().mg_batch_seeds(h)
+        assert self.rows == _lib.lib().mg_batch_rows(h)
+
+    def mg_set_timing(self, enable: bool):
+        check(_lib.lib().mg_set_timing(self.handle, int(bool(enable))))
+
+    def mg_eval_time(self):
+        """(mean microseconds, count) of the recorded evaluation launches."""
+        us, n = C.c_float(0.0), C.c_int(0)
+        check(_lib.lib().mg_eval_time(self.handle, C.byref(us), C.byref(n)))
+        return us.value, n.value
+
+    def close(self):
+        if self.handle:
+            _lib.lib().mg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """Robot + parameters + worlds on the current device (mg_ctx)."""
+
+    def __init__(self, robot, params: _lib.Params | None = None, device="cuda"):
+        L = _lib.lib()
+        self.device = torch.device(device)
+        self.robot = robot
+        self.dof = robot.dof
+        self._keep = []
+
+        def fa(a):
+            a = np.ascontiguousarray(a, dtype=np.float32)
+            self._keep.append(a)
+            return a.ctypes.data_as(_fp)
+
+        def ia(a):
+            a = np.ascontiguousarray(a, dtype=np.int32)
+            self._keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_int))
+
+        desc = _lib.RobotDesc(n_links=robot.n_links, dof=robot.dof, n_spheres=robot.n_spheres,
+                              n_ee=robot.n_ee, parent=ia(robot.parent), joint=ia(robot.joint),
+                              fixed_tf=fa(robot.fixed_tf), sphere_link=ia(robot.sphere_link),
+                              sphere=fa(robot.sphere), ee_link=ia(robot.ee_link), ee_tf=fa(robot.ee_tf),
+                              q_lo=fa(robot.q_lo), q_hi=fa(robot.q_hi))
+        self.params = params if params is not None else default_params()
+        h = C.c_void_p()
+        check(L.mg_create(C.byref(desc), C.byref(self.params), C.byref(h)))
+        self.handle = h
+        self._keep = []
+        self._worlds = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.lib().mg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mg_set_params(self, params: _lib.Params):
+        check(_lib.lib().mg_set_params(self.handle, C.byref(params)))
+        self.params = params
+
+    def mg_set_worlds(self, worlds):
+        off = np.ascontiguousarray(worlds.offsets, dtype=np.int32)
+        pose = _f32(worlds.pose, self.device).reshape(-1)
+        dims = _f32(worlds.dims, self.device).reshape(-1)
+        check(_lib.lib().mg_set_worlds(self.handle, int(off.shape[0] - 1),
+                                       off.ctypes.data_as(C.POINTER(C.c_int)),
+                                       _ptr(pose), _ptr(dims), _stream()))
+        self._worlds = (pose, dims)   # kept until the stream has used them
+
+    def batch(self, seeds, horizon, world, K_max=16, m_max=8) -> Batch:
+        return Batch(self, seeds, horizon, world, K_max, m_max)
+
+    # -- hot path ------------------------------------------------------------
+    def mg_cost_grad(self, b: Batch, q_start, goal, q, grad=True, min_clear=True):
+        dev = self.device
+        cost = torch.empty(b.n_seeds, dtype=torch.float32, device=dev)
+        g = torch.empty_like(q) if grad else None
+        mc = torch.empty(b.n_seeds, dtype=torch.float32, device=dev) if min_clear else None
+        check(_lib.lib().mg_cost_grad(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(q),
+                                      _ptr(cost), _ptr(g), _ptr(mc), _stream()))
+        return cost, g, mc
+
+    def mg_lbfgs_step(self, b: Batch, m, reset, x, g, out=None):
+        d = torch.empty_like(x) if out is None else out
+        check(_lib.lib().mg_lbfgs_step(self.handle, b.handle, int(m), int(reset), _ptr(x), _ptr(g),
+                                       _ptr(d), _stream()))
+        return d
+
+    def mg_linesearch(self, b: Batch, q_start, goal, x, c0, g0, d, alpha, mode=1, out=None):
+        al = (C.c_float * len(alpha))(*alpha)
+        if out is None:
+            out = (torch.empty_like(x), torch.empty_like(c0), torch.empty_like(g0),
+                   torch.empty(b.n_seeds, dtype=torch.int32, device=self.device),
+                   torch.empty(b.n_seeds, dtype=torch.float32, device=self.device))
+        xo, co, go, ch, mc = out
+        check(_lib.lib().mg_linesearch(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(x),
+                                       _ptr(c0), _ptr(g0), _ptr(d), len(alpha), al, int(mode),
+                                       _ptr(xo), _ptr(co), _ptr(go), _ptr(ch), _ptr(mc), _stream()))
+        return xo, co, go, ch, mc
+
+    def mg_solve(self, b: Batch, q_start, goal, x, iters, m, alpha, mode=1, graph_inner=25,
+                 use_graph=True, outputs=None):
+        """Solve in place on x; returns (x, best_cost, best_seed, success)."""
+        al = (C.c_float * len(alpha))(*alpha)
+        if outputs is None:
+            outputs = (torch.empty(b.n_seeds, dtype=torch.float32, device=self.device),
+                       torch.empty(b.P, dtype=torch.int32, device=self.device),
+                       torch.empty(b.P, dtype=torch.int32, device=self.device))
+        bc, bs, ok = outputs
+        check(_lib.lib().mg_solve(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(x), int(iters),
+                                  int(m), len(alpha), al, int(mode), int(graph_inner),
+                                  int(bool(use_graph)), _ptr(bc), _ptr(bs), _ptr(ok), _stream()))
+        return x, bc, bs, ok
+
+
+class MgCost(torch.autograd.Function):
+    """Total cost per seed as a differentiable function of the trajectories.
+
+    forward runs the cost-only evaluation; backward runs the hand-written
+    adjoint, which recomputes kinematics instead of saving link transforms,
+    and scales each seed's rows by the incoming gradient of its cost.
+    """
+
+    @staticmethod
+    def forward(fctx, q, ctx: Context, b: Batch, q_start, goal):
+        cost, _, _ = ctx.mg_cost_grad(b, q_start, goal, q.detach().contiguous(), grad=False,
+                                      min_clear=False)
+        fctx.mg = (ctx, b, q_start, goal)
+        fctx.save_for_backward(q)
+        return cost
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        (q,) = fctx.saved_tensors
+        ctx, b, q_start, goal = fctx.mg
+        _, g, _ = ctx.mg_cost_grad(b, q_start, goal, q.detach().contiguous(), grad=True,
+                                   min_clear=False)
+        rows_per_seed = torch.as_tensor(np.repeat(b.horizon, b.seeds), device=q.device)
+        scale = torch.repeat_interleave(grad_out, rows_per_seed)
+        return g * scale.view(-1, 1).to(g.dtype), None, None, None, None

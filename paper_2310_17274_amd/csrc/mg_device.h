@@ -1,0 +1,201 @@
+// mg_device.h -- device helpers shared by the gfx950 kernels of libmg:
+// cuboid loads through the constant address space, stable logcosh,
+// DPP / lane-swap reductions, 3x4 transform algebra, Shepperd quaternions
+// and the exact sphere-cuboid term of the collision cost.
+#pragma once
+
+#include "mg_internal.h"
+
+namespace mg {
+namespace {
+
+
+// Cuboids are read through the constant address space: every lane of a wave
+// reads the same cuboid, so the loads become scalar loads into SGPRs and the
+// cuboid reaches the whole wave as instruction operands.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const v4f cv4f;
+typedef __attribute__((address_space(4))) const float cfloat;
+
+__device__ __forceinline__ float logcosh_f(float x) {
+  const float ax = fabsf(x);
+  if (ax < 1.0f) {
+    // log(cosh x) = log1p(2 sinh^2(x/2)): no cancellation for small x
+    const float s = sinhf(0.5f * ax);
+    return log1pf(2.0f * s * s);
+  }
+  return ax + log1pf(expf(-2.0f * ax)) - 0.693147180559945f;
+}
+
+// tanh(k r) / r with its limit k at r = 0.
+__device__ __forceinline__ float tanh_over(float k, float r) {
+  return r > 0.0f ? tanhf(k * r) / r : k;
+}
+
+// ---- cross-lane reductions (DPP within rows of 16, lane swaps across rows) ----
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float swap16_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v), false, false);
+  return __builtin_bit_cast(float, (int)r[0]) + __builtin_bit_cast(float, (int)r[1]);
+}
+
+__device__ __forceinline__ float swap32_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v), false, false);
+  return __builtin_bit_cast(float, (int)r[0]) + __builtin_bit_cast(float, (int)r[1]);
+}
+
+__device__ __forceinline__ float swap16_min(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v), false, false);
+  return fminf(__builtin_bit_cast(float, (int)r[0]), __builtin_bit_cast(float, (int)r[1]));
+}
+
+__device__ __forceinline__ float swap32_min(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v), false, false);
+  return fminf(__builtin_bit_cast(float, (int)r[0]), __builtin_bit_cast(float, (int)r[1]));
+}
+
+// Sum over aligned groups of WIDTH lanes; every lane of a group gets the same
+// bits (each step adds the same two partial sums in either order).
+template <int WIDTH>
+__device__ __forceinline__ float group_sum(float v) {
+  if (WIDTH >= 2) v += dpp<0xB1>(v);      // quad_perm [1,0,3,2]
+  if (WIDTH >= 4) v += dpp<0x4E>(v);      // quad_perm [2,3,0,1]
+  if (WIDTH >= 8) v += dpp<0x141>(v);     // row_half_mirror
+  if (WIDTH >= 16) v += dpp<0x140>(v);    // row_mirror
+  if (WIDTH >= 32) v = swap16_sum(v);
+  if (WIDTH >= 64) v = swap32_sum(v);
+  return v;
+}
+
+template <int WIDTH>
+__device__ __forceinline__ float group_min(float v) {
+  if (WIDTH >= 2) v = fminf(v, dpp<0xB1>(v));
+  if (WIDTH >= 4) v = fminf(v, dpp<0x4E>(v));
+  if (WIDTH >= 8) v = fminf(v, dpp<0x141>(v));
+  if (WIDTH >= 16) v = fminf(v, dpp<0x140>(v));
+  if (WIDTH >= 32) v = swap16_min(v);
+  if (WIDTH >= 64) v = swap32_min(v);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) { return group_sum<kWave>(v); }
+__device__ __forceinline__ float wave_min(float v) { return group_min<kWave>(v); }
+
+// T <- T * F for 3x4 row-major affine transforms (F read from memory).
+__device__ __forceinline__ void compose(float* T, const float* __restrict__ F) {
+  const float4 f0 = *reinterpret_cast<const float4*>(F + 0);
+  const float4 f1 = *reinterpret_cast<const float4*>(F + 4);
+  const float4 f2 = *reinterpret_cast<const float4*>(F + 8);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float t0 = T[r * 4 + 0], t1 = T[r * 4 + 1], t2 = T[r * 4 + 2], t3 = T[r * 4 + 3];
+    T[r * 4 + 0] = t0 * f0.x + t1 * f1.x + t2 * f2.x;
+    T[r * 4 + 1] = t0 * f0.y + t1 * f1.y + t2 * f2.y;
+    T[r * 4 + 2] = t0 * f0.z + t1 * f1.z + t2 * f2.z;
+    T[r * 4 + 3] = t0 * f0.w + t1 * f1.w + t2 * f2.w + t3;
+  }
+}
+
+// T <- T * F with F read through the constant address space (wave-uniform
+// address: scalar loads).
+__device__ __forceinline__ void compose_u(float* T, cfloat* F) {
+  const v4f f0 = *(cv4f*)(F + 0);
+  const v4f f1 = *(cv4f*)(F + 4);
+  const v4f f2 = *(cv4f*)(F + 8);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float t0 = T[r * 4 + 0], t1 = T[r * 4 + 1], t2 = T[r * 4 + 2], t3 = T[r * 4 + 3];
+    T[r * 4 + 0] = t0 * f0.x + t1 * f1.x + t2 * f2.x;
+    T[r * 4 + 1] = t0 * f0.y + t1 * f1.y + t2 * f2.y;
+    T[r * 4 + 2] = t0 * f0.z + t1 * f1.z + t2 * f2.z;
+    T[r * 4 + 3] = t0 * f0.w + t1 * f1.w + t2 * f2.w + t3;
+  }
+}
+
+// T <- T * Rz: mixes the first two columns (Tab.6, revolute z) given sin, cos.
+__device__ __forceinline__ void rotz(float* T, float s, float c) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float a = T[r * 4 + 0], b = T[r * 4 + 1];
+    T[r * 4 + 0] = a * c + b * s;
+    T[r * 4 + 1] = b * c - a * s;
+  }
+}
+
+__device__ __forceinline__ void identity(float* T) {
+#pragma unroll
+  for (int i = 0; i < 12; ++i) T[i] = 0.0f;
+  T[0] = T[5] = T[10] = 1.0f;
+}
+
+// Rotation matrix (row-major 3x3 inside a 3x4) -> unit quaternion wxyz,
+// Shepperd's method.
+__device__ __forceinline__ void mat_to_quat(const float* T, float& qw, float& qx, float& qy, float& qz) {
+  const float r00 = T[0], r01 = T[1], r02 = T[2];
+  const float r10 = T[4], r11 = T[5], r12 = T[6];
+  const float r20 = T[8], r21 = T[9], r22 = T[10];
+  const float tr = r00 + r11 + r22;
+  if (tr >= r00 && tr >= r11 && tr >= r22) {
+    const float w = 0.5f * sqrtf(1.0f + tr), f = 0.25f * __builtin_amdgcn_rcpf(w);
+    qw = w; qx = (r21 - r12) * f; qy = (r02 - r20) * f; qz = (r10 - r01) * f;
+  } else if (r00 >= r11 && r00 >= r22) {
+    const float x = 0.5f * sqrtf(1.0f + r00 - r11 - r22), f = 0.25f * __builtin_amdgcn_rcpf(x);
+    qx = x; qw = (r21 - r12) * f; qy = (r01 + r10) * f; qz = (r02 + r20) * f;
+  } else if (r11 >= r22) {
+    const float y = 0.5f * sqrtf(1.0f - r00 + r11 - r22), f = 0.25f * __builtin_amdgcn_rcpf(y);
+    qy = y; qw = (r02 - r20) * f; qx = (r01 + r10) * f; qz = (r12 + r21) * f;
+  } else {
+    const float z = 0.5f * sqrtf(1.0f - r00 - r11 + r22), f = 0.25f * __builtin_amdgcn_rcpf(z);
+    qz = z; qw = (r10 - r01) * f; qx = (r02 + r20) * f; qy = (r12 + r21) * f;
+  }
+}
+
+// One sphere against one cuboid, taken only when the cheap face test says
+// the sphere may be within r + eta: exact signed distance, Eq.(10) profile,
+// and d cost / d centre accumulated into g.
+__device__ __forceinline__ void near_pair(const v4f& A0, const v4f& A1, const v4f& A2, float px,
+                                          float py, float pz, float ax, float ay, float az, float m3,
+                                          float r, float w, float eta, float inv_eta, float& cost,
+                                          float& mc, float& gx, float& gy, float& gz) {
+  const float qx = fmaxf(ax, 0.0f), qy = fmaxf(ay, 0.0f), qz = fmaxf(az, 0.0f);
+  const float n2 = qx * qx + qy * qy + qz * qz;
+  float sdf, gpx = 0.0f, gpy = 0.0f, gpz = 0.0f;
+  if (n2 > 0.0f) {
+    const float n = sqrtf(n2), inv = __builtin_amdgcn_rcpf(n);
+    sdf = n;
+    gpx = (px >= 0.0f ? qx : -qx) * inv;
+    gpy = (py >= 0.0f ? qy : -qy) * inv;
+    gpz = (pz >= 0.0f ? qz : -qz) * inv;
+  } else {
+    sdf = m3;
+    if (ax >= ay && ax >= az) gpx = px >= 0.0f ? 1.0f : -1.0f;
+    else if (ay >= az) gpy = py >= 0.0f ? 1.0f : -1.0f;
+    else gpz = pz >= 0.0f ? 1.0f : -1.0f;
+  }
+  mc = fminf(mc, sdf - r);
+  const float pen = r - sdf;
+  if (pen > -eta) {
+    float dcv, slope;
+    if (pen > 0.0f) {
+      dcv = pen + 0.5f * eta;
+      slope = 1.0f;
+    } else {
+      const float u = pen + eta;
+      dcv = 0.5f * u * u * inv_eta;
+      slope = u * inv_eta;
+    }
+    cost += w * dcv;
+    // d cost / d c = -w slope A^T grad_p
+    const float f = -w * slope;
+    gx = fmaf(f, A0.x * gpx + A1.x * gpy + A2.x * gpz, gx);
+    gy = fmaf(f, A0.y * gpx + A1.y * gpy + A2.y * gpz, gy);
+    gz = fmaf(f, A0.z * gpx + A1.z * gpy + A2.z * gpz, gz);
+  }
+}
+
+}  // namespace
+}  // namespace mg

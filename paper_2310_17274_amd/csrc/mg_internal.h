@@ -1,0 +1,173 @@
+// mg_internal.h -- device-side tables and launch interfaces of libmg.
+//
+// Shared by the C ABI (mg_api.hip) and the kernels (mg_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mg {
+
+constexpr int kBlock = 256;      // threads per workgroup of the per-evaluation kernels
+constexpr int kWave = 64;        // CDNA wavefront
+constexpr int kMaxK = 16;        // line-search candidates per call
+constexpr int kMaxDof = 16;
+constexpr int kMaxT = 64;        // waypoints per trajectory
+constexpr int kMaxEE = 2;
+constexpr int kMaxHist = 16;     // L-BFGS history
+constexpr int kPerLane = kMaxT * kMaxDof / kWave;   // vector elements per lane in the solver kernels
+
+// Cost parameters (see mg_params in mg.h).
+struct Params {
+  float a0, a1, a2, a3;
+  float a6, a7, a8, a9;
+  float w_bound, eta2;
+  float w_coll, eta;
+  float dt;
+  int vel_all;
+  int swept;
+  int sweep_steps;
+  float ls_eta1, ls_eta_w;
+  float success_pos, success_rot;
+};
+
+// One motion problem of a batch.  Rows are waypoints: seed s of problem p
+// owns rows row0 + s*T .. row0 + (s+1)*T - 1.
+struct Problem {
+  int S, T, world, row0, seed0, pad0, pad1, pad2;
+};
+
+// Per seed: first row, horizon, problem.
+struct SeedInfo {
+  int row0, T, prob, pad;
+};
+
+// Robot tables on the device.
+struct Robot {
+  int dof, n_links, n_ee, n_spheres;
+  int serial;              // link l has parent l-1 and joint l (one shared chain)
+  const float* fixed_tf;   // [L][12]
+  const int* joint;        // [L]
+  const float* q_lo;       // [D]
+  const float* q_hi;       // [D]
+  const float* ee_tf;      // [n_ee][12]
+};
+
+// Sphere-group layout for G lanes per evaluation.  Group g owns up to maxs
+// spheres that all hang on one link; its lane walks the chain of transforms
+// from the base to that link (chain slots beyond its length are unused).
+struct Groups {
+  int G;
+  int depth;               // chain slots per group (template DEPTH)
+  int maxs;                // sphere slots per group (template MAXS)
+  const float* ftf;        // [G][depth][12] fixed transform of each chain slot
+  const int* jidx;         // [G][depth] joint rotating each chain slot, -1 = fixed
+  const int4* info;        // [G]: chain length, -, sphere count, end effector or -1
+  const float4* sphere;    // [G][maxs] center in link frame + radius
+  const int* red;          // [D+1] offsets, then slots g*depth+i summed into joint j
+};
+
+// Cuboid in the library layout: p = A c + b maps a world point into the box
+// frame (A = R^T, b = -R^T t); h = half side lengths.
+//   q[0] = A00 A01 A02 b0, q[1] = A10 A11 A12 b1, q[2] = A20 A21 A22 b2, q[3] = h0 h1 h2 0
+struct Box {
+  float4 q[4];
+};
+
+struct EvalArgs {
+  Robot rb;
+  Groups gr;
+  Params pr;
+  const Problem* prob;     // [P]
+  const int* chunk_prefix; // [P+1] workgroups before problem p (for this G)
+  int P;
+  int rows;
+  const Box* box;          // all worlds' cuboids
+  const int* world_off;    // [W+1]
+  const float* q_start;    // [P][D]
+  const float* goal;       // [P][n_ee][7]
+  const float* x;          // [rows][D]
+  const float* d;          // [rows][D] direction (candidate mode) or null
+  float alpha[kMaxK];
+  int K;
+  float* cost_e;           // [K][rows]
+  float* gd_e;             // [K][rows] (candidate mode)
+  float* mc_e;             // [K][rows]
+  float* grad_e;           // [K][rows][D] (gradient mode)
+  float* pe_e;             // [rows][2] position / rotation error at the last waypoint, or null
+};
+
+struct ReduceArgs {
+  const SeedInfo* seeds;
+  int n_seeds;
+  const float* cost_e;     // [rows]
+  const float* mc_e;       // [rows]
+  float* cost;             // [seeds]
+  float* min_clear;        // [seeds] or null
+};
+
+struct SelectArgs {
+  const SeedInfo* seeds;
+  int n_seeds, rows, dof, K, mode;
+  float alpha[kMaxK];
+  float eta1, eta_w;
+  const float* q_lo;
+  const float* q_hi;
+  const float* x;          // [rows][D]
+  const float* c0;         // [seeds]
+  const float* g0;         // [rows][D]
+  const float* d;          // [rows][D]
+  const float* cost_e;     // [K][rows]
+  const float* gd_e;
+  const float* mc_e;
+  const float* grad_e;     // [K][rows][D]
+  float* x_out;            // may alias x
+  float* c_out;            // may alias c0
+  float* g_out;            // may alias g0
+  int* chosen;             // or null
+  float* mc_out;           // or null
+  float* best_c;           // or null (no best tracking)
+  float* best_x;
+};
+
+struct LbfgsArgs {
+  const SeedInfo* seeds;
+  int n_seeds, rows, dof, m, reset;
+  const float* x;
+  const float* g;
+  float* dir;
+  float* S;                // [m_max][rows*D]
+  float* Y;
+  float* x_prev;           // [rows*D]
+  float* g_prev;
+  float* rho;              // [seeds][m_max]
+  int* meta;               // [seeds][2]: count, head
+  int* first;              // [seeds] or null: 1 forces a reset for that seed, then cleared
+  int m_max;
+};
+
+struct FinalArgs {
+  const Problem* prob;
+  int P, rows;
+  const float* best_c;     // [seeds]
+  const float* pe_e;       // [rows][2]
+  const float* mc_e;       // [rows]
+  float success_pos, success_rot;
+  int* best_seed;          // [P] or null
+  int* success;            // [P] or null
+};
+
+// Launchers (mg_kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_select(const SelectArgs& a, int max_n, hipStream_t s);
+hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s);
+bool eval_shape_supported(int G, int maxs);
+hipError_t launch_final(const FinalArgs& a, hipStream_t s);
+hipError_t launch_boxes(const float* pose, const float* dims, int n, Box* out, hipStream_t s);
+hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);
+hipError_t launch_fill_i32(int* dst, int v, size_t n, hipStream_t s);
+
+}  // namespace mg

@@ -1,0 +1,391 @@
+// mg_kernels.hip -- gfx950 kernels of the batched trajectory-optimizer hot path.
+//
+// eval_kernel      one launch evaluates cost (and gradient) of every
+//                  (candidate k, waypoint row): FK in registers, sphere-vs-
+//                  cuboid cost with cuboids read as wave-uniform scalar
+//                  loads, joint-limit, smoothness and pose costs, and the
+//                  hand-written adjoint with the chain transforms recomputed.
+// reduce_kernel    per-seed sums of a single evaluation.
+// select_kernel    parallel noisy line-search choice and best tracking.
+// lbfgs_kernel     two-loop L-BFGS direction, one wavefront per seed.
+// final_kernel     per-problem best seed and success verdict.
+#include "mg_device.h"
+#include "mg_eval.h"
+
+namespace mg {
+namespace {
+
+// --------------------------------------------------------------------------
+// Per-seed totals of one evaluation (K = 1).
+__global__ __launch_bounds__(kBlock) void reduce_kernel(const ReduceArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n_seeds) return;
+  const SeedInfo si = a.seeds[s];
+  float c = 0.0f, m = 3.0e38f;
+  for (int t = 0; t < si.T; ++t) {
+    c += a.cost_e[si.row0 + t];
+    m = fminf(m, a.mc_e[si.row0 + t]);
+  }
+  a.cost[s] = c;
+  if (a.min_clear) a.min_clear[s] = m;
+}
+
+// --------------------------------------------------------------------------
+// Line-search choice (Alg.1), one wavefront per seed; lane t holds waypoint
+// t of every candidate, all loads issued before the reductions.
+template <int PL>
+__global__ __launch_bounds__(kBlock) void select_kernel(const SelectArgs a) {
+  const int s = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (s >= a.n_seeds) return;        // whole wavefronts only
+  const SeedInfo si = a.seeds[s];
+  const int D = a.dof, n = si.T * D;
+  const size_t base = (size_t)si.row0 * D;
+
+  float ck[kMaxK], gk[kMaxK], mk[kMaxK];
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    ck[k] = 0.0f; gk[k] = 0.0f; mk[k] = 3.0e38f;
+    if (k < a.K && lane < si.T) {
+      const size_t e = (size_t)k * a.rows + si.row0 + lane;
+      ck[k] = a.cost_e[e];
+      gk[k] = a.gd_e[e];
+      mk[k] = a.mc_e[e];
+    }
+  }
+  float gdv[PL], xv[PL], dv[PL];
+  float g0d = 0.0f;
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int e = lane + u * kWave;
+    gdv[u] = xv[u] = dv[u] = 0.0f;
+    if (e < n) {
+      xv[u] = a.x[base + e];
+      dv[u] = a.d[base + e];
+      g0d = fmaf(a.g0[base + e], dv[u], g0d);
+    }
+  }
+  g0d = wave_sum(g0d);
+  const float c0 = a.c0[s];
+  int best = 0;
+  float cb = 0.0f, mcb = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    if (k < a.K) {
+      const float c = wave_sum(ck[k]), gd = wave_sum(gk[k]), m = wave_min(mk[k]);
+      bool ok = c <= c0 + a.eta1 * a.alpha[k] * g0d;
+      if (a.mode == 1) ok = ok && (gd >= a.eta_w * g0d);
+      if (a.mode == 2) ok = ok && (fabsf(gd) <= a.eta_w * fabsf(g0d));
+      if (k == 0 || ok) { best = k; cb = c; mcb = m; }
+    }
+  }
+  const float al = a.alpha[best];
+  const bool improve = a.best_c && cb < a.best_c[s];
+  const float* gsrc = a.grad_e + ((size_t)best * a.rows + si.row0) * D;
+#pragma unroll
+  for (int u = 0; u < PL; ++u) gdv[u] = (lane + u * kWave < n) ? gsrc[lane + u * kWave] : 0.0f;
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int e = lane + u * kWave;
+    if (e < n) {
+      const int j = e % D;
+      const float v = fminf(fmaxf(fmaf(al, dv[u], xv[u]), a.q_lo[j]), a.q_hi[j]);
+      a.x_out[base + e] = v;
+      a.g_out[base + e] = gdv[u];
+      if (improve) a.best_x[base + e] = v;
+    }
+  }
+  if (lane == 0) {
+    a.c_out[s] = cb;
+    if (a.chosen) a.chosen[s] = best;
+    if (a.mc_out) a.mc_out[s] = mcb;
+    if (improve) a.best_c[s] = cb;
+  }
+}
+
+// --------------------------------------------------------------------------
+// L-BFGS direction (Alg.6), one wavefront per seed.  The seed's vectors
+// (n = T*D <= 64*PL) and its history (m <= MH pairs) are loaded into
+// registers up front; the two loops then run on registers and DPP sums.
+template <int PL, int MH>
+__global__ __launch_bounds__(kBlock) void lbfgs_kernel(const LbfgsArgs a) {
+  const int s = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (s >= a.n_seeds) return;
+  const SeedInfo si = a.seeds[s];
+  const int n = si.T * a.dof;
+  const size_t base = (size_t)si.row0 * a.dof;
+  const size_t stride = (size_t)a.rows * a.dof;
+  const int m = a.m;
+
+  int count = a.meta[2 * s + 0], head = a.meta[2 * s + 1];
+  bool reset = a.reset != 0;
+  if (a.first && a.first[s]) reset = true;
+  if (reset) { count = 0; head = 0; }
+
+  float xv[PL], gv[PL], sv[PL], yv[PL];
+  float Sh[MH][PL], Yh[MH][PL], rh[MH];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int e = lane + u * kWave;
+    const bool in = e < n;
+    xv[u] = in ? a.x[base + e] : 0.0f;
+    gv[u] = in ? a.g[base + e] : 0.0f;
+    sv[u] = (in && !reset) ? xv[u] - a.x_prev[base + e] : 0.0f;
+    yv[u] = (in && !reset) ? gv[u] - a.g_prev[base + e] : 0.0f;
+  }
+  // history slot c (newest first) sits in ring index (head - 1 - c) mod m
+#pragma unroll
+  for (int c = 0; c < MH; ++c) {
+    rh[c] = 0.0f;
+#pragma unroll
+    for (int u = 0; u < PL; ++u) { Sh[c][u] = 0.0f; Yh[c][u] = 0.0f; }
+    if (c < count) {
+      const int i = ((head - 1 - c) % m + m) % m;
+      rh[c] = a.rho[(size_t)s * a.m_max + i];
+#pragma unroll
+      for (int u = 0; u < PL; ++u) {
+        const int e = lane + u * kWave;
+        if (e < n) {
+          Sh[c][u] = a.S[(size_t)i * stride + base + e];
+          Yh[c][u] = a.Y[(size_t)i * stride + base + e];
+        }
+      }
+    }
+  }
+  // curvature pair of the last step
+  if (!reset && m > 0) {
+    float sy = 0.0f, ss = 0.0f, yy = 0.0f;
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      sy = fmaf(sv[u], yv[u], sy);
+      ss = fmaf(sv[u], sv[u], ss);
+      yy = fmaf(yv[u], yv[u], yy);
+    }
+    sy = wave_sum(sy); ss = wave_sum(ss); yy = wave_sum(yy);
+    if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy) && sy > 0.0f) {
+#pragma unroll
+      for (int u = 0; u < PL; ++u) {
+        const int e = lane + u * kWave;
+        if (e < n) {
+          a.S[(size_t)head * stride + base + e] = sv[u];
+          a.Y[(size_t)head * stride + base + e] = yv[u];
+        }
+      }
+      if (lane == 0) a.rho[(size_t)s * a.m_max + head] = 1.0f / sy;
+      // shift the register copy: the new pair becomes slot 0
+#pragma unroll
+      for (int c = MH - 1; c > 0; --c) {
+        rh[c] = rh[c - 1];
+#pragma unroll
+        for (int u = 0; u < PL; ++u) { Sh[c][u] = Sh[c - 1][u]; Yh[c][u] = Yh[c - 1][u]; }
+      }
+      rh[0] = 1.0f / sy;
+#pragma unroll
+      for (int u = 0; u < PL; ++u) { Sh[0][u] = sv[u]; Yh[0][u] = yv[u]; }
+      head = (head + 1) % m;
+      count = count < m ? count + 1 : m;
+    }
+  }
+  // two-loop recursion
+  float q[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) q[u] = gv[u];
+  float al[MH];
+#pragma unroll
+  for (int c = 0; c < MH; ++c) {
+    al[c] = 0.0f;
+    if (c < count) {
+      float dsq = 0.0f;
+#pragma unroll
+      for (int u = 0; u < PL; ++u) dsq = fmaf(Sh[c][u], q[u], dsq);
+      const float ai = rh[c] * wave_sum(dsq);
+      al[c] = ai;
+#pragma unroll
+      for (int u = 0; u < PL; ++u) q[u] = fmaf(-ai, Yh[c][u], q[u]);
+    }
+  }
+  float gamma;
+  if (count > 0) {
+    float sy = 0.0f, yy = 0.0f;
+#pragma unroll
+    for (int u = 0; u < PL; ++u) { sy = fmaf(Sh[0][u], Yh[0][u], sy); yy = fmaf(Yh[0][u], Yh[0][u], yy); }
+    gamma = wave_sum(sy) / wave_sum(yy);
+  } else {
+    float gi = 0.0f;
+#pragma unroll
+    for (int u = 0; u < PL; ++u) gi = fmaxf(gi, fabsf(gv[u]));
+    gi = -wave_min(-gi);
+    gamma = gi > 0.0f ? fminf(1.0f, 0.1f / gi) : 1.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < PL; ++u) q[u] *= gamma;
+#pragma unroll
+  for (int c = MH - 1; c >= 0; --c) {
+    if (c < count) {
+      float dyr = 0.0f;
+#pragma unroll
+      for (int u = 0; u < PL; ++u) dyr = fmaf(Yh[c][u], q[u], dyr);
+      const float b = rh[c] * wave_sum(dyr);
+#pragma unroll
+      for (int u = 0; u < PL; ++u) q[u] = fmaf(al[c] - b, Sh[c][u], q[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int e = lane + u * kWave;
+    if (e < n) {
+      a.dir[base + e] = -q[u];
+      a.x_prev[base + e] = xv[u];
+      a.g_prev[base + e] = gv[u];
+    }
+  }
+  if (lane == 0) {
+    a.meta[2 * s + 0] = count;
+    a.meta[2 * s + 1] = head;
+    if (a.first) a.first[s] = 0;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Per problem: best seed (lowest index on ties) and success verdict.
+__global__ __launch_bounds__(kBlock) void final_kernel(const FinalArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.P) return;
+  const Problem pb = a.prob[p];
+  int bs = 0;
+  float bc = a.best_c[pb.seed0];
+  for (int s = 1; s < pb.S; ++s) {
+    const float c = a.best_c[pb.seed0 + s];
+    if (c < bc) { bc = c; bs = s; }
+  }
+  if (a.best_seed) a.best_seed[p] = bs;
+  if (a.success) {
+    const int r0 = pb.row0 + bs * pb.T;
+    float m = 3.0e38f;
+    for (int t = 0; t < pb.T; ++t) m = fminf(m, a.mc_e[r0 + t]);
+    const int rl = r0 + pb.T - 1;
+    const bool ok = a.pe_e[(size_t)rl * 2 + 0] <= a.success_pos &&
+                    a.pe_e[(size_t)rl * 2 + 1] <= a.success_rot && m >= 0.0f;
+    a.success[p] = ok ? 1 : 0;
+  }
+}
+
+// Cuboid pose (xyz + wxyz) and full sides -> library layout.
+__global__ __launch_bounds__(kBlock) void boxes_kernel(const float* __restrict__ pose,
+                                                       const float* __restrict__ dims, int n,
+                                                       Box* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* pz = pose + 7 * i;
+  float w = pz[3], x = pz[4], y = pz[5], z = pz[6];
+  const float inv = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
+  w *= inv; x *= inv; y *= inv; z *= inv;
+  // R (box -> world)
+  const float r00 = 1 - 2 * (y * y + z * z), r01 = 2 * (x * y - w * z), r02 = 2 * (x * z + w * y);
+  const float r10 = 2 * (x * y + w * z), r11 = 1 - 2 * (x * x + z * z), r12 = 2 * (y * z - w * x);
+  const float r20 = 2 * (x * z - w * y), r21 = 2 * (y * z + w * x), r22 = 1 - 2 * (x * x + y * y);
+  const float tx = pz[0], ty = pz[1], tz = pz[2];
+  Box b;
+  // A = R^T, b = -R^T t
+  b.q[0] = make_float4(r00, r10, r20, -(r00 * tx + r10 * ty + r20 * tz));
+  b.q[1] = make_float4(r01, r11, r21, -(r01 * tx + r11 * ty + r21 * tz));
+  b.q[2] = make_float4(r02, r12, r22, -(r02 * tx + r12 * ty + r22 * tz));
+  b.q[3] = make_float4(0.5f * dims[3 * i + 0], 0.5f * dims[3 * i + 1], 0.5f * dims[3 * i + 2], 0.0f);
+  out[i] = b;
+}
+
+__global__ __launch_bounds__(kBlock) void copy_kernel(const float* __restrict__ src,
+                                                      float* __restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBlock) void fill_i32_kernel(int* __restrict__ dst, int v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
+int blocks_for(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > 65535) b = 65535;
+  return (int)b;
+}
+
+}  // namespace
+
+// Sphere slots per group supported by the evaluation kernel for G lanes.
+bool eval_shape_supported(int G, int maxs) {
+  return (G == 8 && (maxs == 8 || maxs == 16)) || (G == 16 && (maxs == 4 || maxs == 8 || maxs == 16)) ||
+         (G == 32 && (maxs == 2 || maxs == 4 || maxs == 8));
+}
+
+hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s) {
+  if (a.rb.serial) {
+    if (a.gr.depth == 8) return launch_eval_d8s(a, grid_x, cand, grad, s);
+    if (a.gr.depth == 16) return launch_eval_d16s(a, grid_x, cand, grad, s);
+  } else {
+    if (a.gr.depth == 8) return launch_eval_d8t(a, grid_x, cand, grad, s);
+    if (a.gr.depth == 16) return launch_eval_d16t(a, grid_x, cand, grad, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  reduce_kernel<<<(a.n_seeds + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const SelectArgs& a, int max_n, hipStream_t s) {
+  const int wpb = kBlock / kWave;
+  const dim3 grid((a.n_seeds + wpb - 1) / wpb);
+  if (max_n <= 64) select_kernel<1><<<grid, kBlock, 0, s>>>(a);
+  else if (max_n <= 128) select_kernel<2><<<grid, kBlock, 0, s>>>(a);
+  else if (max_n <= 256) select_kernel<4><<<grid, kBlock, 0, s>>>(a);
+  else if (max_n <= 512) select_kernel<8><<<grid, kBlock, 0, s>>>(a);
+  else select_kernel<16><<<grid, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int MH>
+hipError_t launch_lbfgs_h(const LbfgsArgs& a, int max_n, hipStream_t s) {
+  const int wpb = kBlock / kWave;
+  const dim3 grid((a.n_seeds + wpb - 1) / wpb);
+  if (max_n <= 64) lbfgs_kernel<1, MH><<<grid, kBlock, 0, s>>>(a);
+  else if (max_n <= 128) lbfgs_kernel<2, MH><<<grid, kBlock, 0, s>>>(a);
+  else if (max_n <= 256) lbfgs_kernel<4, MH><<<grid, kBlock, 0, s>>>(a);
+  else if (max_n <= 512) lbfgs_kernel<8, MH><<<grid, kBlock, 0, s>>>(a);
+  else lbfgs_kernel<16, MH><<<grid, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s) {
+  if (a.m <= 4) return launch_lbfgs_h<4>(a, max_n, s);
+  return launch_lbfgs_h<kMaxHist>(a, max_n, s);
+}
+
+hipError_t launch_final(const FinalArgs& a, hipStream_t s) {
+  final_kernel<<<(a.P + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_boxes(const float* pose, const float* dims, int n, Box* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  boxes_kernel<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(pose, dims, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  copy_kernel<<<blocks_for(n), kBlock, 0, s>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* dst, int v, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  fill_i32_kernel<<<blocks_for(n), kBlock, 0, s>>>(dst, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace mg
