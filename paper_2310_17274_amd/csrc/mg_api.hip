@@ -62,26 +62,16 @@ void dev_free(T*& p) {
   p = nullptr;
 }
 
-// Sphere groups for G lanes per evaluation (see mg::Groups).
-struct GroupVariant {
-  int G = 0, maxs = 0;
-  bool ok = false;
-  float* ftf = nullptr;
-  int* jidx = nullptr;
-  int4* info = nullptr;
-  float4* sphere = nullptr;
-  int* red = nullptr;
-};
-
-constexpr int kNumVariants = 3;
-constexpr int kVariantG[kNumVariants] = {8, 16, 32};
+// Cuboid slices per evaluation group offered by the evaluation kernel.
+constexpr int kNumSlices = 3;
+constexpr int kSlices[kNumSlices] = {1, 2, 4};
 
 }  // namespace
 
 struct mg_ctx {
   int device = 0;
-  int L = 0, D = 0, M = 0, n_ee = 0, depth = 8;
-  bool serial = false;   // link l has parent l-1 and joint l
+  int L = 0, D = 0, M = 0, n_ee = 0;
+  int lpe = 8, maxs = 4;     // lanes per evaluation, sphere slots per link
   std::vector<int> parent, joint, sphere_link, ee_link;
   std::vector<float> fixed_tf, sphere, ee_tf, q_lo, q_hi;
   mg::Params params{};
@@ -90,7 +80,8 @@ struct mg_ctx {
   float* d_q_lo = nullptr;
   float* d_q_hi = nullptr;
   float* d_ee_tf = nullptr;
-  GroupVariant var[kNumVariants];
+  int4* d_lane_info = nullptr;
+  float4* d_lane_sphere = nullptr;
   Box* d_box = nullptr;
   int box_cap = 0, n_boxes = 0;
   int* d_world_off = nullptr;
@@ -104,8 +95,8 @@ struct mg_batch {
   std::vector<int> seeds, horizon, world;
   mg::Problem* d_prob = nullptr;
   mg::SeedInfo* d_seed = nullptr;
-  int* d_chunk[kNumVariants] = {nullptr, nullptr, nullptr};
-  int chunks[kNumVariants] = {0, 0, 0};
+  int* d_chunk[kNumSlices] = {nullptr, nullptr, nullptr};
+  int chunks[kNumSlices] = {0, 0, 0};
   int max_n = 0;      // largest T*D of a seed
   float *cost_e = nullptr, *gd_e = nullptr, *mc_e = nullptr, *grad_e = nullptr, *pe_e = nullptr;
   float *c_cur = nullptr, *g_cur = nullptr, *dir = nullptr, *best_c = nullptr, *best_x = nullptr;
@@ -119,7 +110,7 @@ struct mg_batch {
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
   int ev_next = 0, ev_count = 0;
-  int variant = -1;   // forced G variant (-1: automatic)
+  int slices = -1;    // forced cuboid slices index (-1: automatic)
 };
 
 namespace {
@@ -127,125 +118,58 @@ namespace {
 mg::Robot dev_robot(const mg_ctx* c) {
   mg::Robot r;
   r.dof = c->D;
-  r.serial = c->serial ? 1 : 0;
   r.n_links = c->L;
   r.n_ee = c->n_ee;
   r.n_spheres = c->M;
   r.fixed_tf = c->d_fixed_tf;
-  r.joint = c->d_joint;
   r.q_lo = c->d_q_lo;
   r.q_hi = c->d_q_hi;
   r.ee_tf = c->d_ee_tf;
   return r;
 }
 
-// Partition the spheres into G groups, each on a single link, so that the
-// largest group is as small as possible; every end-effector link gets a
-// group (possibly without spheres) that evaluates its pose term.
-mg_status build_groups(mg_ctx* c, int vi) {
-  GroupVariant& v = c->var[vi];
-  const int G = kVariantG[vi];
-  v.G = G;
-  v.ok = false;
+// Lane layout: lane l of an evaluation owns link l.  Each lane records the
+// lanes where its chain starts and ends, its spheres and its end effector.
+mg_status build_lanes(mg_ctx* c) {
+  c->lpe = c->L <= 8 ? 8 : 16;
   std::vector<int> count(c->L, 0);
   for (int m = 0; m < c->M; ++m) count[c->sphere_link[m]]++;
-  std::vector<int> need(c->L, 0);
-  for (int l = 0; l < c->L; ++l) need[l] = count[l] > 0 ? 1 : 0;
-  for (int e = 0; e < c->n_ee; ++e) need[c->ee_link[e]] = 1;
-  int used = 0;
-  for (int l = 0; l < c->L; ++l) used += need[l];
-  if (used > G) return MG_OK;  // infeasible for this G
-  std::vector<int> ng = need;
-  for (int extra = G - used; extra > 0; --extra) {
-    int best = -1, best_load = 0;
-    for (int l = 0; l < c->L; ++l) {
-      if (!ng[l] || count[l] == 0) continue;
-      const int load = (count[l] + ng[l] - 1) / ng[l];
-      if (load > best_load) { best_load = load; best = l; }
-    }
-    if (best < 0 || best_load <= 1) break;
-    ng[best]++;
+  int most = 0;
+  for (int l = 0; l < c->L; ++l) most = std::max(most, count[l]);
+  c->maxs = most <= 4 ? 4 : most <= 8 ? 8 : 16;
+  if (most > 16) return fail(MG_ERR_UNSUPPORTED, "a link carries %d spheres (at most 16)", most);
+  const int lpe = c->lpe, maxs = c->maxs;
+  std::vector<int4> info(lpe);
+  std::vector<float4> sph((size_t)lpe * maxs, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+  std::vector<int> fill(lpe, 0);
+  for (int l = 0; l < lpe; ++l) {
+    if (l >= c->L) { info[l] = make_int4(l, l + 1, 0, -1); continue; }
+    int start = l;
+    while (c->parent[start] >= 0) start = c->parent[start];
+    int end = l + 1;
+    while (end < c->L && c->parent[end] == end - 1) ++end;
+    int ee = -1;
+    for (int e = 0; e < c->n_ee; ++e)
+      if (c->ee_link[e] == l) ee = e;
+    info[l] = make_int4(start, end, count[l], ee);
   }
-  int largest = 0;
-  for (int l = 0; l < c->L; ++l)
-    if (ng[l]) largest = std::max(largest, (count[l] + ng[l] - 1) / ng[l]);
-  int maxs = 0;
-  for (int cand : {2, 4, 8, 16})
-    if (largest <= cand && mg::eval_shape_supported(G, cand)) { maxs = cand; break; }
-  if (maxs == 0) return MG_OK;  // groups too large for this G
-  v.maxs = maxs;
-  const int depth = c->depth;
-  // spheres of each link in input order
-  std::vector<std::vector<int>> by_link(c->L);
-  for (int m = 0; m < c->M; ++m) by_link[c->sphere_link[m]].push_back(m);
-  // unused chain slots hold identity transforms with no joint
-  std::vector<float> ftf((size_t)G * depth * 12, 0.0f);
-  for (size_t q = 0; q < (size_t)G * depth; ++q) ftf[q * 12 + 0] = ftf[q * 12 + 5] = ftf[q * 12 + 10] = 1.0f;
-  std::vector<int> jidx((size_t)G * depth, -1), chain((size_t)G * depth, -1);
-  std::vector<int4> info(G, make_int4(0, 0, 0, -1));
-  std::vector<float4> sph((size_t)G * maxs, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
-  int g = 0;
-  for (int l = 0; l < c->L; ++l) {
-    if (!ng[l]) continue;
-    std::vector<int> path;   // base .. l
-    for (int x = l; x >= 0; x = c->parent[x]) path.push_back(x);
-    std::reverse(path.begin(), path.end());
-    if ((int)path.size() > depth)
-      return fail(MG_ERR_SHAPE, "chain of link %d has %zu links > %d", l, path.size(), depth);
-    const int n = count[l];
-    for (int part = 0; part < ng[l]; ++part) {
-      const int b = n * part / ng[l], e = n * (part + 1) / ng[l];
-      for (size_t i = 0; i < path.size(); ++i) {
-        chain[g * depth + i] = path[i];
-        jidx[g * depth + i] = c->joint[path[i]];
-        for (int q = 0; q < 12; ++q) ftf[((size_t)g * depth + i) * 12 + q] = c->fixed_tf[path[i] * 12 + q];
-      }
-      int ee = -1;
-      if (part == 0)
-        for (int k = 0; k < c->n_ee; ++k)
-          if (c->ee_link[k] == l) ee = k;
-      info[g] = make_int4((int)path.size(), 0, e - b, ee);
-      for (int i = b; i < e; ++i) {
-        const int m = by_link[l][i];
-        sph[(size_t)g * maxs + (i - b)] =
-            make_float4(c->sphere[4 * m + 0], c->sphere[4 * m + 1], c->sphere[4 * m + 2], c->sphere[4 * m + 3]);
-      }
-      ++g;
-    }
+  for (int m = 0; m < c->M; ++m) {
+    const int l = c->sphere_link[m];
+    sph[(size_t)l * maxs + fill[l]++] =
+        make_float4(c->sphere[4 * m + 0], c->sphere[4 * m + 1], c->sphere[4 * m + 2], c->sphere[4 * m + 3]);
   }
-  // unused lanes keep empty groups (no chain, no spheres)
-  // reduction lists: joint j sums slots (g, i) whose chain link carries j
-  std::vector<int> off(c->D + 1, 0), slots;
-  for (int j = 0; j < c->D; ++j) {
-    off[j] = (int)slots.size();
-    for (int gg = 0; gg < G; ++gg)
-      for (int i = 0; i < info[gg].x; ++i)
-        if (jidx[gg * depth + i] == j) slots.push_back(gg * depth + i);
-  }
-  off[c->D] = (int)slots.size();
-  std::vector<int> red = off;
-  red.insert(red.end(), slots.begin(), slots.end());
   mg_status st;
-  if ((st = dev_upload(&v.ftf, ftf)) != MG_OK) return st;
-  if ((st = dev_upload(&v.jidx, jidx)) != MG_OK) return st;
-  if ((st = dev_upload(&v.info, info)) != MG_OK) return st;
-  if ((st = dev_upload(&v.sphere, sph)) != MG_OK) return st;
-  if ((st = dev_upload(&v.red, red)) != MG_OK) return st;
-  v.ok = true;
-  return MG_OK;
+  if ((st = dev_upload(&c->d_lane_info, info)) != MG_OK) return st;
+  return dev_upload(&c->d_lane_sphere, sph);
 }
 
-mg::Groups dev_groups(const mg_ctx* c, int vi) {
-  mg::Groups g;
-  g.G = c->var[vi].G;
-  g.depth = c->depth;
-  g.maxs = c->var[vi].maxs;
-  g.ftf = c->var[vi].ftf;
-  g.jidx = c->var[vi].jidx;
-  g.info = c->var[vi].info;
-  g.sphere = c->var[vi].sphere;
-  g.red = c->var[vi].red;
-  return g;
+mg::Lanes dev_lanes(const mg_ctx* c) {
+  mg::Lanes ln;
+  ln.lpe = c->lpe;
+  ln.maxs = c->maxs;
+  ln.info = c->d_lane_info;
+  ln.sphere = c->d_lane_sphere;
+  return ln;
 }
 
 mg::Params to_dev(const mg_params& p) {
@@ -267,37 +191,34 @@ mg_status check_params(const mg_params* p) {
   return MG_OK;
 }
 
-// G variant for a call evaluating n_evals rows x candidates: the fewest
-// lanes per evaluation (least repeated kinematics) that still gives every
-// SIMD about four wavefronts; MG_LANES_PER_EVAL forces a choice.
-int pick_variant(const mg_batch* b, long n_evals) {
-  const mg_ctx* c = b->ctx;
-  if (b->variant >= 0 && c->var[b->variant].ok) return b->variant;
-  const char* env = getenv("MG_LANES_PER_EVAL");
+// Cuboid slices for a call evaluating n_evals rows x candidates: the fewest
+// slices (least repeated kinematics) that still give every SIMD about four
+// wavefronts; MG_CUBOID_SLICES forces a choice.
+int pick_slices(const mg_batch* b, long n_evals) {
+  if (b->slices >= 0) return b->slices;
+  const char* env = getenv("MG_CUBOID_SLICES");
   if (env) {
-    const int G = atoi(env);
-    for (int i = 0; i < kNumVariants; ++i)
-      if (kVariantG[i] == G && c->var[i].ok) return i;
+    const int h = atoi(env);
+    for (int i = 0; i < kNumSlices; ++i)
+      if (kSlices[i] == h) return i;
   }
-  const long target_lanes = 256L * 4 * 4 * mg::kWave;   // CUs x SIMDs x waves x lanes
-  int pick = -1;
-  for (int i = 0; i < kNumVariants; ++i) {
-    if (!c->var[i].ok) continue;
-    pick = i;
-    if (n_evals * kVariantG[i] >= target_lanes) break;
-  }
-  return pick;
+  const long waves1 = (n_evals * b->ctx->lpe + mg::kWave - 1) / mg::kWave;
+  const long target = 256L * 4 * 4;   // CUs x SIMDs x waves
+  for (int i = 0; i < kNumSlices; ++i)
+    if (waves1 * kSlices[i] >= target) return i;
+  return kNumSlices - 1;
 }
 
-mg::EvalArgs eval_args(const mg_ctx* c, const mg_batch* b, int vi, const float* q_start,
+mg::EvalArgs eval_args(const mg_ctx* c, const mg_batch* b, int hi, const float* q_start,
                        const float* goal, const float* x, const float* d, int K, const float* alpha) {
   mg::EvalArgs a;
   memset(&a, 0, sizeof(a));
   a.rb = dev_robot(c);
-  a.gr = dev_groups(c, vi);
+  a.ln = dev_lanes(c);
   a.pr = c->params;
+  a.slices = kSlices[hi];
   a.prob = b->d_prob;
-  a.chunk_prefix = b->d_chunk[vi];
+  a.chunk_prefix = b->d_chunk[hi];
   a.P = b->P;
   a.rows = b->rows;
   a.box = c->d_box;
@@ -329,9 +250,8 @@ mg_status common_checks(mg_ctx* c, mg_batch* b) {
 mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
                        const float* x, const float* d, int K, const float* alpha, bool grad,
                        float* grad_out, float* pe_out, hipStream_t s) {
-  const int vi = pick_variant(b, (long)b->rows * K);
-  if (vi < 0) return fail(MG_ERR_UNSUPPORTED, "robot needs more sphere groups than lanes per evaluation");
-  mg::EvalArgs a = eval_args(c, b, vi, q_start, goal, x, d, K, alpha);
+  const int hi = pick_slices(b, (long)b->rows * K);
+  mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, x, d, K, alpha);
   if (grad_out) a.grad_e = grad_out;
   a.pe_e = pe_out;
   const int slot = b->ev_next;
@@ -344,7 +264,7 @@ mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
     timed = cs == hipStreamCaptureStatusNone;
   }
   if (timed) HIP_TRY(hipEventRecord(b->ev_start[slot], s));
-  HIP_TRY(mg::launch_eval(a, b->chunks[vi], d != nullptr, grad, s));
+  HIP_TRY(mg::launch_eval(a, b->chunks[hi], d != nullptr, grad, s));
   if (timed) {
     HIP_TRY(hipEventRecord(b->ev_stop[slot], s));
     b->ev_next = (slot + 1) % (int)b->ev_start.size();
@@ -442,6 +362,14 @@ mg_status mg_create(const mg_robot_desc* r, const mg_params* params, mg_ctx** ou
   }
   for (int j = 0; j < r->dof; ++j)
     if (jcount[j] != 1) return fail(MG_ERR_ARG, "joint %d drives %d links (must be 1)", j, jcount[j]);
+  // kinematic layout of the evaluation kernel: link l is driven by joint l and
+  // hangs from link l-1 or from the base (chains that start at the base)
+  if (r->n_links != r->dof || r->n_links > 16)
+    return fail(MG_ERR_UNSUPPORTED, "need one joint per link and at most 16 links (got %d links, %d joints)",
+                r->n_links, r->dof);
+  for (int l = 0; l < r->n_links; ++l)
+    if (r->joint[l] != l || (r->parent[l] != -1 && r->parent[l] != l - 1))
+      return fail(MG_ERR_UNSUPPORTED, "link %d: need joint[l] = l and parent[l] in {-1, l-1}", l);
   for (int m = 0; m < r->n_spheres; ++m) {
     if (r->sphere_link[m] < 0 || r->sphere_link[m] >= r->n_links) return fail(MG_ERR_ARG, "sphere_link[%d] out of range", m);
     if (!(r->sphere[4 * m + 3] > 0)) return fail(MG_ERR_ARG, "sphere %d radius must be > 0", m);
@@ -464,32 +392,14 @@ mg_status mg_create(const mg_robot_desc* r, const mg_params* params, mg_ctx** ou
   c->q_lo.assign(r->q_lo, r->q_lo + c->D);
   c->q_hi.assign(r->q_hi, r->q_hi + c->D);
   c->params = to_dev(*params);
-  int maxdepth = 0;
-  for (int l = 0; l < c->L; ++l) {
-    int dpt = 0;
-    for (int x = l; x >= 0; x = c->parent[x]) ++dpt;
-    maxdepth = std::max(maxdepth, dpt);
-  }
-  if (maxdepth > 16) { delete c; return fail(MG_ERR_SHAPE, "kinematic chain deeper than 16 links"); }
-  c->depth = maxdepth <= 8 ? 8 : 16;
-  c->serial = c->L == c->D;
-  for (int l = 0; l < c->L; ++l) c->serial = c->serial && c->parent[l] == l - 1 && c->joint[l] == l;
   if ((st = dev_upload(&c->d_fixed_tf, c->fixed_tf)) != MG_OK ||
       (st = dev_upload(&c->d_joint, c->joint)) != MG_OK ||
       (st = dev_upload(&c->d_q_lo, c->q_lo)) != MG_OK ||
       (st = dev_upload(&c->d_q_hi, c->q_hi)) != MG_OK ||
-      (st = dev_upload(&c->d_ee_tf, c->ee_tf)) != MG_OK) {
+      (st = dev_upload(&c->d_ee_tf, c->ee_tf)) != MG_OK ||
+      (st = build_lanes(c)) != MG_OK) {
     mg_destroy(c);
     return st;
-  }
-  bool any = false;
-  for (int vi = 0; vi < kNumVariants; ++vi) {
-    if ((st = build_groups(c, vi)) != MG_OK) { mg_destroy(c); return st; }
-    any = any || c->var[vi].ok;
-  }
-  if (!any) {
-    mg_destroy(c);
-    return fail(MG_ERR_UNSUPPORTED, "robot spheres do not fit 32 groups of at most 4 (or 16 of 8, 8 of 16)");
   }
   hipError_t e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) { mg_destroy(c); return fail(MG_ERR_HIP, "hipStreamCreate: %s", hipGetErrorString(e)); }
@@ -501,7 +411,7 @@ void mg_destroy(mg_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   dev_free(c->d_fixed_tf); dev_free(c->d_joint); dev_free(c->d_q_lo); dev_free(c->d_q_hi); dev_free(c->d_ee_tf);
-  for (auto& v : c->var) { dev_free(v.ftf); dev_free(v.jidx); dev_free(v.info); dev_free(v.sphere); dev_free(v.red); }
+  dev_free(c->d_lane_info); dev_free(c->d_lane_sphere);
   dev_free(c->d_box); dev_free(c->d_world_off);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
@@ -589,12 +499,13 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
   auto bail = [&](mg_status s) { mg_batch_destroy(b); return s; };
   if ((st = dev_upload(&b->d_prob, prob)) != MG_OK) return bail(st);
   if ((st = dev_upload(&b->d_seed, sinfo)) != MG_OK) return bail(st);
-  for (int vi = 0; vi < kNumVariants; ++vi) {
-    const int epw = mg::kBlock / kVariantG[vi];
+  for (int hi = 0; hi < kNumSlices; ++hi) {
+    // evaluations per workgroup: (waves / slices) groups of (wave / lanes) rows
+    const int epb = (mg::kBlock / mg::kWave / kSlices[hi]) * (mg::kWave / c->lpe);
     std::vector<int> pre(P + 1, 0);
-    for (int p = 0; p < P; ++p) pre[p + 1] = pre[p] + (seeds[p] * horizon[p] + epw - 1) / epw;
-    b->chunks[vi] = pre[P];
-    if ((st = dev_upload(&b->d_chunk[vi], pre)) != MG_OK) return bail(st);
+    for (int p = 0; p < P; ++p) pre[p + 1] = pre[p] + (seeds[p] * horizon[p] + epb - 1) / epb;
+    b->chunks[hi] = pre[P];
+    if ((st = dev_upload(&b->d_chunk[hi], pre)) != MG_OK) return bail(st);
   }
   const size_t R = rows, RD = rows * c->D, KR = (size_t)K_max * rows, mm = std::max(m_max, 1);
   if ((st = dev_alloc(&b->cost_e, KR)) != MG_OK || (st = dev_alloc(&b->gd_e, KR)) != MG_OK ||

@@ -1,0 +1,8 @@
+// Evaluation kernel instantiations: 8 lanes per evaluation, 8 sphere slots per link.
+#include "mg_eval.h"
+
+namespace mg {
+hipError_t launch_eval_l8s8(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s) {
+  return launch_eval_shape<8, 8>(a, grid_x, cand, grad, s);
+}
+}  // namespace mg

@@ -44,29 +44,24 @@ struct SeedInfo {
   int row0, T, prob, pad;
 };
 
-// Robot tables on the device.
+// Robot tables on the device.  Link l is driven by joint l and its parent is
+// link l-1 or the base, so the links form chains that start at the base
+// (a serial arm, or several arms on one base).
 struct Robot {
   int dof, n_links, n_ee, n_spheres;
-  int serial;              // link l has parent l-1 and joint l (one shared chain)
   const float* fixed_tf;   // [L][12]
-  const int* joint;        // [L]
   const float* q_lo;       // [D]
   const float* q_hi;       // [D]
   const float* ee_tf;      // [n_ee][12]
 };
 
-// Sphere-group layout for G lanes per evaluation.  Group g owns up to maxs
-// spheres that all hang on one link; its lane walks the chain of transforms
-// from the base to that link (chain slots beyond its length are unused).
-struct Groups {
-  int G;
-  int depth;               // chain slots per group (template DEPTH)
-  int maxs;                // sphere slots per group (template MAXS)
-  const float* ftf;        // [G][depth][12] fixed transform of each chain slot
-  const int* jidx;         // [G][depth] joint rotating each chain slot, -1 = fixed
-  const int4* info;        // [G]: chain length, -, sphere count, end effector or -1
-  const float4* sphere;    // [G][maxs] center in link frame + radius
-  const int* red;          // [D+1] offsets, then slots g*depth+i summed into joint j
+// Lane layout of the evaluation kernel: lane l of an evaluation owns link l,
+// its spheres and (if l < D) joint l.
+struct Lanes {
+  int lpe;                 // lanes per evaluation: 8 or 16
+  int maxs;                // sphere slots per link: 4, 8 or 16
+  const int4* info;        // [lpe]: chain start lane, chain end lane, spheres, end effector or -1
+  const float4* sphere;    // [lpe][maxs] center in link frame + radius
 };
 
 // Cuboid in the library layout: p = A c + b maps a world point into the box
@@ -78,10 +73,11 @@ struct Box {
 
 struct EvalArgs {
   Robot rb;
-  Groups gr;
+  Lanes ln;
   Params pr;
+  int slices;              // waves that split one evaluation group's cuboids: 1, 2 or 4
   const Problem* prob;     // [P]
-  const int* chunk_prefix; // [P+1] workgroups before problem p (for this G)
+  const int* chunk_prefix; // [P+1] workgroups before problem p (for this lane layout)
   int P;
   int rows;
   const Box* box;          // all worlds' cuboids
@@ -164,7 +160,7 @@ hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipS
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_select(const SelectArgs& a, int max_n, hipStream_t s);
 hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s);
-bool eval_shape_supported(int G, int maxs);
+
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);
 hipError_t launch_boxes(const float* pose, const float* dims, int n, Box* out, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);

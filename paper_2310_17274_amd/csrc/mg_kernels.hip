@@ -315,20 +315,14 @@ int blocks_for(size_t n) {
 
 }  // namespace
 
-// Sphere slots per group supported by the evaluation kernel for G lanes.
-bool eval_shape_supported(int G, int maxs) {
-  return (G == 8 && (maxs == 8 || maxs == 16)) || (G == 16 && (maxs == 4 || maxs == 8 || maxs == 16)) ||
-         (G == 32 && (maxs == 2 || maxs == 4 || maxs == 8));
-}
-
 hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s) {
-  if (a.rb.serial) {
-    if (a.gr.depth == 8) return launch_eval_d8s(a, grid_x, cand, grad, s);
-    if (a.gr.depth == 16) return launch_eval_d16s(a, grid_x, cand, grad, s);
-  } else {
-    if (a.gr.depth == 8) return launch_eval_d8t(a, grid_x, cand, grad, s);
-    if (a.gr.depth == 16) return launch_eval_d16t(a, grid_x, cand, grad, s);
-  }
+  const int L = a.ln.lpe, S = a.ln.maxs;
+  if (L == 8 && S == 4) return launch_eval_l8s4(a, grid_x, cand, grad, s);
+  if (L == 8 && S == 8) return launch_eval_l8s8(a, grid_x, cand, grad, s);
+  if (L == 8 && S == 16) return launch_eval_l8s16(a, grid_x, cand, grad, s);
+  if (L == 16 && S == 4) return launch_eval_l16s4(a, grid_x, cand, grad, s);
+  if (L == 16 && S == 8) return launch_eval_l16s8(a, grid_x, cand, grad, s);
+  if (L == 16 && S == 16) return launch_eval_l16s16(a, grid_x, cand, grad, s);
   return hipErrorInvalidValue;
 }
 
