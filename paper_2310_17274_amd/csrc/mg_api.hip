@@ -273,10 +273,27 @@ mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
   return MG_OK;
 }
 
+mg::LbfgsArgs lbfgs_args(mg_ctx* c, mg_batch* b, int m, int reset, const float* x, const float* g,
+                         float* dir, int* first) {
+  mg::LbfgsArgs a;
+  memset(&a, 0, sizeof(a));
+  a.seeds = b->d_seed;
+  a.n_seeds = b->n_seeds;
+  a.rows = b->rows;
+  a.dof = c->D;
+  a.m = m;
+  a.reset = reset;
+  a.x = x; a.g = g; a.dir = dir;
+  a.S = b->S; a.Y = b->Y; a.x_prev = b->x_prev; a.g_prev = b->g_prev;
+  a.rho = b->rho; a.meta = b->meta; a.first = first;
+  a.m_max = b->m_max;
+  return a;
+}
+
 mg_status enqueue_select(mg_ctx* c, mg_batch* b, const float* x, const float* c0, const float* g0,
                          const float* d, int K, const float* alpha, int mode, float* x_out,
                          float* c_out, float* g_out, int* chosen, float* mc_out, bool track,
-                         hipStream_t s) {
+                         const mg::LbfgsArgs* fuse, hipStream_t s) {
   mg::SelectArgs a;
   memset(&a, 0, sizeof(a));
   a.seeds = b->d_seed;
@@ -295,24 +312,13 @@ mg_status enqueue_select(mg_ctx* c, mg_batch* b, const float* x, const float* c0
   a.x_out = x_out; a.c_out = c_out; a.g_out = g_out; a.chosen = chosen; a.mc_out = mc_out;
   a.best_c = track ? b->best_c : nullptr;
   a.best_x = track ? b->best_x : nullptr;
-  HIP_TRY(mg::launch_select(a, b->max_n, s));
+  HIP_TRY(mg::launch_select(a, b->max_n, fuse, s));
   return MG_OK;
 }
 
 mg_status enqueue_lbfgs(mg_ctx* c, mg_batch* b, int m, int reset, const float* x, const float* g,
                         float* dir, int* first, hipStream_t s) {
-  mg::LbfgsArgs a;
-  memset(&a, 0, sizeof(a));
-  a.seeds = b->d_seed;
-  a.n_seeds = b->n_seeds;
-  a.rows = b->rows;
-  a.dof = c->D;
-  a.m = m;
-  a.reset = reset;
-  a.x = x; a.g = g; a.dir = dir;
-  a.S = b->S; a.Y = b->Y; a.x_prev = b->x_prev; a.g_prev = b->g_prev;
-  a.rho = b->rho; a.meta = b->meta; a.first = first;
-  a.m_max = b->m_max;
+  const mg::LbfgsArgs a = lbfgs_args(c, b, m, reset, x, g, dir, first);
   HIP_TRY(mg::launch_lbfgs(a, b->max_n, s));
   return MG_OK;
 }
@@ -609,20 +615,24 @@ mg_status mg_linesearch(mg_ctx* c, mg_batch* b, const float* q_start, const floa
     return fail(MG_ERR_ARG, "null argument");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if ((st = enqueue_eval(c, b, q_start, goal, x, dir, K, alpha, true, nullptr, nullptr, s)) != MG_OK) return st;
-  return enqueue_select(c, b, x, c0, g0, dir, K, alpha, mode, x_out, c_out, g_out, chosen, min_clear, false, s);
+  return enqueue_select(c, b, x, c0, g0, dir, K, alpha, mode, x_out, c_out, g_out, chosen, min_clear, false,
+                        nullptr, s);
 }
 
 }  // extern "C"
 
 namespace {
 
+// One solver iteration: candidates of the current direction are costed
+// (eval), the line search picks the next iterate, tracks the best and, in the
+// same kernel, computes the next L-BFGS direction.
 mg_status enqueue_iteration(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* x,
                             int m, int K, const float* alpha, int mode, hipStream_t s) {
   mg_status st;
-  if ((st = enqueue_lbfgs(c, b, m, 0, x, b->g_cur, b->dir, b->first, s)) != MG_OK) return st;
   if ((st = enqueue_eval(c, b, q_start, goal, x, b->dir, K, alpha, true, nullptr, nullptr, s)) != MG_OK) return st;
+  const mg::LbfgsArgs la = lbfgs_args(c, b, m, 0, x, b->g_cur, b->dir, b->first);
   return enqueue_select(c, b, x, b->c_cur, b->g_cur, b->dir, K, alpha, mode, x, b->c_cur, b->g_cur,
-                        nullptr, nullptr, true, s);
+                        nullptr, nullptr, true, &la, s);
 }
 
 template <typename T>
@@ -656,6 +666,7 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
   HIP_TRY(mg::launch_copy(b->c_cur, b->best_c, b->n_seeds, s));
   HIP_TRY(mg::launch_copy(x, b->best_x, RD, s));
   HIP_TRY(mg::launch_fill_i32(b->first, 1, b->n_seeds, s));
+  if ((st = enqueue_lbfgs(c, b, m, 1, x, b->g_cur, b->dir, b->first, s)) != MG_OK) return st;
 
   int done = 0;
   if (use_graph && iters >= graph_inner) {

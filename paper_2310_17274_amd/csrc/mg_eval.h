@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
     // ---- pose reaching cost at the last waypoint (Eq.(14)) ----
     if (li.w >= 0 && t == pb.T - 1) {
       float E[12];
-  #pragma unroll
+#pragma unroll
       for (int i = 0; i < 12; ++i) E[i] = T[i];
       compose(E, a.rb.ee_tf + li.w * 12);
       float qt[4];
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
         const int w1 = t + 1, Tn = pb.T;
         const float q0 = a.q_start[(size_t)p * D + lj];
         float X[9];
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < 9; ++u) {
           const int sgi = w1 - 4 + u;
           const int wv = sgi < 1 ? 1 : (sgi < Tn ? sgi : Tn);
@@ -204,11 +204,11 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
         const float kv[5] = {1.0f, -8.0f, 0.0f, 8.0f, -1.0f};
         const float ka[5] = {-1.0f, 16.0f, -30.0f, 16.0f, -1.0f};
         const float kj[5] = {-1.0f, 2.0f, 0.0f, -2.0f, 1.0f};
-  #pragma unroll
+#pragma unroll
         for (int c = 0; c < 5; ++c) {
           const int tau = w1 - 2 + c;          // stencil centre, states X[c..c+4]
           float v = 0.0f, ac = 0.0f, jk = 0.0f;
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < 5; ++i) {
             v = fmaf(kv[i], X[c + i], v);
             ac = fmaf(ka[i], X[c + i], ac);
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
           }
           if (mine) jc += a.pr.a8 * ac * ac + a.pr.a9 * jk * jk;
           const float ga = 2.0f * a.pr.a8 * ac * ca, gjk = 2.0f * a.pr.a9 * jk * cj;
-  #pragma unroll
+#pragma unroll
           for (int i = 0; i < 5; ++i) {
             const int s = tau - 2 + i;         // state touched by stencil entry i
             if (in && s >= 1 && (s < Tn ? s : Tn) == w1) js += gv * kv[i] + ga * ka[i] + gjk * kj[i];

@@ -158,7 +158,8 @@ struct FinalArgs {
 // Launchers (mg_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
-hipError_t launch_select(const SelectArgs& a, int max_n, hipStream_t s);
+// fuse (optional): compute the next L-BFGS direction from the chosen iterate
+hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, hipStream_t s);
 hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s);
 
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);

@@ -31,88 +31,13 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(const ReduceArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// Line-search choice (Alg.1), one wavefront per seed; lane t holds waypoint
-// t of every candidate, all loads issued before the reductions.
-template <int PL>
-__global__ __launch_bounds__(kBlock) void select_kernel(const SelectArgs a) {
-  const int s = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (s >= a.n_seeds) return;        // whole wavefronts only
-  const SeedInfo si = a.seeds[s];
-  const int D = a.dof, n = si.T * D;
-  const size_t base = (size_t)si.row0 * D;
-
-  float ck[kMaxK], gk[kMaxK], mk[kMaxK];
-#pragma unroll
-  for (int k = 0; k < kMaxK; ++k) {
-    ck[k] = 0.0f; gk[k] = 0.0f; mk[k] = 3.0e38f;
-    if (k < a.K && lane < si.T) {
-      const size_t e = (size_t)k * a.rows + si.row0 + lane;
-      ck[k] = a.cost_e[e];
-      gk[k] = a.gd_e[e];
-      mk[k] = a.mc_e[e];
-    }
-  }
-  float gdv[PL], xv[PL], dv[PL];
-  float g0d = 0.0f;
-#pragma unroll
-  for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave;
-    gdv[u] = xv[u] = dv[u] = 0.0f;
-    if (e < n) {
-      xv[u] = a.x[base + e];
-      dv[u] = a.d[base + e];
-      g0d = fmaf(a.g0[base + e], dv[u], g0d);
-    }
-  }
-  g0d = wave_sum(g0d);
-  const float c0 = a.c0[s];
-  int best = 0;
-  float cb = 0.0f, mcb = 0.0f;
-#pragma unroll
-  for (int k = 0; k < kMaxK; ++k) {
-    if (k < a.K) {
-      const float c = wave_sum(ck[k]), gd = wave_sum(gk[k]), m = wave_min(mk[k]);
-      bool ok = c <= c0 + a.eta1 * a.alpha[k] * g0d;
-      if (a.mode == 1) ok = ok && (gd >= a.eta_w * g0d);
-      if (a.mode == 2) ok = ok && (fabsf(gd) <= a.eta_w * fabsf(g0d));
-      if (k == 0 || ok) { best = k; cb = c; mcb = m; }
-    }
-  }
-  const float al = a.alpha[best];
-  const bool improve = a.best_c && cb < a.best_c[s];
-  const float* gsrc = a.grad_e + ((size_t)best * a.rows + si.row0) * D;
-#pragma unroll
-  for (int u = 0; u < PL; ++u) gdv[u] = (lane + u * kWave < n) ? gsrc[lane + u * kWave] : 0.0f;
-#pragma unroll
-  for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave;
-    if (e < n) {
-      const int j = e % D;
-      const float v = fminf(fmaxf(fmaf(al, dv[u], xv[u]), a.q_lo[j]), a.q_hi[j]);
-      a.x_out[base + e] = v;
-      a.g_out[base + e] = gdv[u];
-      if (improve) a.best_x[base + e] = v;
-    }
-  }
-  if (lane == 0) {
-    a.c_out[s] = cb;
-    if (a.chosen) a.chosen[s] = best;
-    if (a.mc_out) a.mc_out[s] = mcb;
-    if (improve) a.best_c[s] = cb;
-  }
-}
-
-// --------------------------------------------------------------------------
-// L-BFGS direction (Alg.6), one wavefront per seed.  The seed's vectors
-// (n = T*D <= 64*PL) and its history (m <= MH pairs) are loaded into
-// registers up front; the two loops then run on registers and DPP sums.
+// L-BFGS direction (Alg.6) of one seed held by one wavefront.  The seed's
+// vectors (n = T*D <= 64*PL, lane-strided) are in registers; its history
+// (m <= MH pairs) is loaded into registers up front, then the two loops run
+// on registers and DPP sums.  Writes dir, the new history and x/g_prev.
 template <int PL, int MH>
-__global__ __launch_bounds__(kBlock) void lbfgs_kernel(const LbfgsArgs a) {
-  const int s = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (s >= a.n_seeds) return;
-  const SeedInfo si = a.seeds[s];
+__device__ __forceinline__ void lbfgs_seed(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
+                                           const float* xv, const float* gv) {
   const int n = si.T * a.dof;
   const size_t base = (size_t)si.row0 * a.dof;
   const size_t stride = (size_t)a.rows * a.dof;
@@ -123,14 +48,12 @@ __global__ __launch_bounds__(kBlock) void lbfgs_kernel(const LbfgsArgs a) {
   if (a.first && a.first[s]) reset = true;
   if (reset) { count = 0; head = 0; }
 
-  float xv[PL], gv[PL], sv[PL], yv[PL];
+  float sv[PL], yv[PL];
   float Sh[MH][PL], Yh[MH][PL], rh[MH];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     const int e = lane + u * kWave;
     const bool in = e < n;
-    xv[u] = in ? a.x[base + e] : 0.0f;
-    gv[u] = in ? a.g[base + e] : 0.0f;
     sv[u] = (in && !reset) ? xv[u] - a.x_prev[base + e] : 0.0f;
     yv[u] = (in && !reset) ? gv[u] - a.g_prev[base + e] : 0.0f;
   }
@@ -247,6 +170,101 @@ __global__ __launch_bounds__(kBlock) void lbfgs_kernel(const LbfgsArgs a) {
   }
 }
 
+template <int PL, int MH>
+__global__ __launch_bounds__(kBlock) void lbfgs_kernel(const LbfgsArgs a) {
+  const int s = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (s >= a.n_seeds) return;        // whole wavefronts only
+  const SeedInfo si = a.seeds[s];
+  const int n = si.T * a.dof;
+  const size_t base = (size_t)si.row0 * a.dof;
+  float xv[PL], gv[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int e = lane + u * kWave;
+    xv[u] = e < n ? a.x[base + e] : 0.0f;
+    gv[u] = e < n ? a.g[base + e] : 0.0f;
+  }
+  lbfgs_seed<PL, MH>(a, s, lane, si, xv, gv);
+}
+
+// --------------------------------------------------------------------------
+// Line-search choice (Alg.1), one wavefront per seed; lane t holds waypoint
+// t of every candidate, all loads issued before the reductions.  With FUSED
+// the same wavefront then computes the next L-BFGS direction from the chosen
+// iterate, which is still in its registers.
+template <int PL, int MH, bool FUSED>
+__global__ __launch_bounds__(kBlock) void select_kernel(const SelectArgs a, const LbfgsArgs la) {
+  const int s = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (s >= a.n_seeds) return;        // whole wavefronts only
+  const SeedInfo si = a.seeds[s];
+  const int D = a.dof, n = si.T * D;
+  const size_t base = (size_t)si.row0 * D;
+
+  float ck[kMaxK], gk[kMaxK], mk[kMaxK];
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    ck[k] = 0.0f; gk[k] = 0.0f; mk[k] = 3.0e38f;
+    if (k < a.K && lane < si.T) {
+      const size_t e = (size_t)k * a.rows + si.row0 + lane;
+      ck[k] = a.cost_e[e];
+      gk[k] = a.gd_e[e];
+      mk[k] = a.mc_e[e];
+    }
+  }
+  float gdv[PL], xv[PL], dv[PL];
+  float g0d = 0.0f;
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int e = lane + u * kWave;
+    gdv[u] = xv[u] = dv[u] = 0.0f;
+    if (e < n) {
+      xv[u] = a.x[base + e];
+      dv[u] = a.d[base + e];
+      g0d = fmaf(a.g0[base + e], dv[u], g0d);
+    }
+  }
+  g0d = wave_sum(g0d);
+  const float c0 = a.c0[s];
+  int best = 0;
+  float cb = 0.0f, mcb = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    if (k < a.K) {
+      const float c = wave_sum(ck[k]), gd = wave_sum(gk[k]), m = wave_min(mk[k]);
+      bool ok = c <= c0 + a.eta1 * a.alpha[k] * g0d;
+      if (a.mode == 1) ok = ok && (gd >= a.eta_w * g0d);
+      if (a.mode == 2) ok = ok && (fabsf(gd) <= a.eta_w * fabsf(g0d));
+      if (k == 0 || ok) { best = k; cb = c; mcb = m; }
+    }
+  }
+  const float al = a.alpha[best];
+  const bool improve = a.best_c && cb < a.best_c[s];
+  const float* gsrc = a.grad_e + ((size_t)best * a.rows + si.row0) * D;
+#pragma unroll
+  for (int u = 0; u < PL; ++u) gdv[u] = (lane + u * kWave < n) ? gsrc[lane + u * kWave] : 0.0f;
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const int e = lane + u * kWave;
+    const int j = e % D;
+    const float v = e < n ? fminf(fmaxf(fmaf(al, dv[u], xv[u]), a.q_lo[j]), a.q_hi[j]) : 0.0f;
+    xv[u] = v;
+    if (e < n) {
+      a.x_out[base + e] = v;
+      a.g_out[base + e] = gdv[u];
+      if (improve) a.best_x[base + e] = v;
+    }
+  }
+  if (lane == 0) {
+    a.c_out[s] = cb;
+    if (a.chosen) a.chosen[s] = best;
+    if (a.mc_out) a.mc_out[s] = mcb;
+    if (improve) a.best_c[s] = cb;
+  }
+  if constexpr (FUSED) lbfgs_seed<PL, MH>(la, s, lane, si, xv, gdv);
+}
+
 // --------------------------------------------------------------------------
 // Per problem: best seed (lowest index on ties) and success verdict.
 __global__ __launch_bounds__(kBlock) void final_kernel(const FinalArgs a) {
@@ -331,15 +349,22 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_select(const SelectArgs& a, int max_n, hipStream_t s) {
+template <int PL>
+hipError_t launch_select_pl(const SelectArgs& a, const LbfgsArgs* la, hipStream_t s) {
   const int wpb = kBlock / kWave;
   const dim3 grid((a.n_seeds + wpb - 1) / wpb);
-  if (max_n <= 64) select_kernel<1><<<grid, kBlock, 0, s>>>(a);
-  else if (max_n <= 128) select_kernel<2><<<grid, kBlock, 0, s>>>(a);
-  else if (max_n <= 256) select_kernel<4><<<grid, kBlock, 0, s>>>(a);
-  else if (max_n <= 512) select_kernel<8><<<grid, kBlock, 0, s>>>(a);
-  else select_kernel<16><<<grid, kBlock, 0, s>>>(a);
+  if (!la) select_kernel<PL, 4, false><<<grid, kBlock, 0, s>>>(a, LbfgsArgs{});
+  else if (la->m <= 4) select_kernel<PL, 4, true><<<grid, kBlock, 0, s>>>(a, *la);
+  else select_kernel<PL, kMaxHist, true><<<grid, kBlock, 0, s>>>(a, *la);
   return hipGetLastError();
+}
+
+hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, hipStream_t s) {
+  if (max_n <= 64) return launch_select_pl<1>(a, fuse, s);
+  if (max_n <= 128) return launch_select_pl<2>(a, fuse, s);
+  if (max_n <= 256) return launch_select_pl<4>(a, fuse, s);
+  if (max_n <= 512) return launch_select_pl<8>(a, fuse, s);
+  return launch_select_pl<16>(a, fuse, s);
 }
 
 template <int MH>
