@@ -16,6 +16,7 @@ timed on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -49,11 +50,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", choices=["eval", "copy"],
+                    help="profiling driver instead of the benchmark: 'eval' runs --launches "
+                         "line searches of the benchmark shape (one evaluation launch each), "
+                         "'copy' copies 256 MiB five times (HBM byte-counter calibration)")
+    ap.add_argument("--launches", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
               "plan is described in DESIGN.md and not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.profile == "copy":
+        return profile_copy()
 
     import torch
     from paper_2310_17274_amd import workloads as wl
@@ -79,6 +87,9 @@ def main():
     outs = (torch.empty(b.n_seeds, dtype=torch.float32, device=dev),
             torch.empty(b.P, dtype=torch.int32, device=dev),
             torch.empty(b.P, dtype=torch.int32, device=dev))
+
+    if args.profile == "eval":
+        return profile_eval(ctx, b, q_start, goal, x0, alpha, args.launches)
 
     def solve(use_graph):
         x.copy_(x0)
@@ -111,23 +122,14 @@ def main():
     torch.cuda.synchronize()
     ms_plain = ev0.elapsed_time(ev1) / n_plain
 
-    # evaluation kernel time: HIP events around each launch on its stream,
-    # over direct line-search launches of the solve's shape (the same kernel
-    # and grid as inside the graph: 32 seeds x 32 waypoints x 8 candidates)
+    # evaluation kernel time: HIP events on the launch stream around 30
+    # back-to-back launches of the solve's evaluation kernel and grid
+    # (32 seeds x 32 waypoints x 8 candidates, cost + adjoint)
     c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
-    ls_out = (torch.empty_like(x0), torch.empty_like(c0), torch.empty_like(g0),
-              torch.empty(b.n_seeds, dtype=torch.int32, device=dev),
-              torch.empty(b.n_seeds, dtype=torch.float32, device=dev))
-    for _ in range(3):
-        ctx.mg_linesearch(b, q_start, goal, x0, c0, g0, dvec, alpha, 1, out=ls_out)
-    torch.cuda.synchronize()
-    b.mg_set_timing(True)
-    for _ in range(30):
-        ctx.mg_linesearch(b, q_start, goal, x0, c0, g0, dvec, alpha, 1, out=ls_out)
-    torch.cuda.synchronize()
-    eval_us, n_ev = b.mg_eval_time()
-    b.mg_set_timing(False)
+    n_ev = 30
+    ctx.mg_time_eval(b, q_start, goal, x0, dvec, alpha, launches=3)
+    eval_us = ctx.mg_time_eval(b, q_start, goal, x0, dvec, alpha, launches=n_ev)
 
     best = outs[0].cpu().numpy()
     evals_per_step = S * T * K * iters
@@ -160,7 +162,7 @@ def main():
         "best_cost_min": float(best.min()),
         "roofline": {"bound": "alu", "kernel": "eval_kernel (cost + adjoint, 8 candidates)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
                      "eval_kernel_us": eval_us, "eval_launches_timed": n_ev,
                      "flop_per_eval": fl, "evals_per_launch": S * T * K},
     }
@@ -168,6 +170,59 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(robot, worlds, batch, alpha, iters, args.cpu_seconds)
     print(json.dumps(line), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_kernel_cost_adjoint_32x32x8_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2310_17274_amd", "csrc", f)
+                  for f in ("mg_eval.h", "mg_device.h", "mg_internal.h")]
+
+
+def kernel_digest():
+    """sha256 over the evaluation kernel's sources."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per evaluation launch from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, or None when the kernel sources changed since
+    the counters were taken (or no summary exists)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            fields = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if fields.get("source_digest", "").strip() != kernel_digest():
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
+def profile_eval(ctx, b, q_start, goal, x0, alpha, launches):
+    """Evaluation launches of the benchmark shape for hardware-counter runs."""
+    import torch
+    c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
+    dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
+    for _ in range(launches):
+        ctx.mg_linesearch(b, q_start, goal, x0, c0, g0, dvec, alpha, 1)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "eval", "launches": launches, "kernel_digest": kernel_digest()}), flush=True)
+
+
+def profile_copy():
+    """Plain device-to-device copy of 256 MiB, five times: the reference
+    reading of the HBM byte counters."""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "copy", "bytes": n * 4, "copies": 5}), flush=True)
 
 
 def cpu_baseline(robot, worlds, batch, alpha, iters, seconds):

@@ -86,8 +86,8 @@ typedef struct {
   float w_coll, eta;        /* collision weight and activation distance */
   float dt;                 /* waypoint spacing of the stencils */
   int vel_all;              /* 0: velocity term at the last waypoint only; 1: all */
-  int swept;                /* 1: swept-sphere (continuous) collision */
-  int sweep_steps;          /* max sphere-tracing samples per half segment */
+  int swept;                /* 1: swept-sphere (continuous) collision, Alg.11-12 */
+  int sweep_steps;          /* max sphere-tracing samples per half segment, 0..64 */
   float ls_eta1;            /* Armijo constant (default 1e-4) */
   float ls_eta_w;           /* Wolfe constant (default 0.9) */
   float success_pos;        /* success: position error <= (default 0.005 m) */
@@ -177,6 +177,28 @@ mg_status mg_solve(mg_ctx *ctx, mg_batch *batch, const float *q_start, const flo
                    int graph_inner, int use_graph, float *best_cost, int *best_seed,
                    int *success, void *stream);
 
+/* Particle-based optimization (Sec. "Particle-Based Optimization", Alg.5,
+ * Eq.(12)-(13)), run before L-BFGS to move the seeds to a good region.
+ * mg_batch_reserve_particles allocates the per-row particle costs for up to
+ * n_particles (1..1024) particles per seed (not capturable).  mg_particles
+ * runs n_iters rounds; each round, for every seed,
+ *   theta_i = clip(mean + sqrt(var) * eps_i, q_lo, q_hi),  i < n_particles
+ * is costed (cost only, one launch over all seeds and particles), then with
+ * w = softmax(-(C - min C) / beta) (exponential utility)
+ *   mean' = (1 - k_mu) mean + k_mu sum_i w_i theta_i
+ *   var'  = (1 - k_sigma) var + k_sigma sum_i w_i (theta_i - mean)^2.
+ * The printed variance update lacks k_sigma and squares theta rather than
+ * its deviation; it is read as the weighted variance about the previous
+ * mean.  beta <= 0 uses 0.1 (max C - min C) + 1e-12 per seed.
+ *   mean, var DEVICE [rows][D] in/out (var per element, rad^2)
+ *   eps       DEVICE [n_iters][n_particles][rows][D] standard normal draws
+ *   costs_out DEVICE [n_iters][seeds][n_particles] particle costs, or NULL
+ * MG_ERR_STATE if n_particles exceeds the reservation.  Capturable. */
+mg_status mg_batch_reserve_particles(mg_batch *batch, int n_particles);
+mg_status mg_particles(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
+                       float *mean, float *var, int n_particles, int n_iters, const float *eps,
+                       float beta, float k_mu, float k_sigma, float *costs_out, void *stream);
+
 /* Measurement hooks.  mg_set_timing(batch, 1) clears the batch's timing
  * record and from then on brackets every direct evaluation-kernel launch
  * made for the batch with a pair of HIP events on the launch stream
@@ -186,6 +208,14 @@ mg_status mg_solve(mg_ctx *ctx, mg_batch *batch, const float *q_start, const flo
  * that was.  Not capturable. */
 mg_status mg_set_timing(mg_batch *batch, int enable);
 mg_status mg_eval_time(mg_batch *batch, float *mean_us, int *count);
+/* Launch the line-search evaluation kernel (the one mg_linesearch and
+ * mg_solve use for these K candidates) `launches` times back to back on
+ * stream between two HIP events, wait, and return the mean time per launch
+ * in microseconds.  Overwrites the batch's evaluation workspaces.  Not
+ * capturable (synchronises). */
+mg_status mg_time_eval(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
+                       const float *x, const float *dir, int K, const float *alpha,
+                       int launches, float *mean_us, void *stream);
 
 /* Message for the last non-OK status returned on this thread. */
 const char *mg_last_error(void);

@@ -615,3 +615,69 @@ void mgref_solve(const mgref_robot *rb, const mgref_params *pr,
   }
   (void)nthreads;
 }
+
+/* ------------------------------------------------------------------ */
+/* Particle-based optimization (Alg.5, Eq.(12)-(13)). */
+
+void mgref_particle_update(int n, int N, const double *cost, const double *theta,
+                           double *mu, double *var, double beta, double k_mu,
+                           double k_sigma, double *w_out) {
+  double cmin = cost[0], cmax = cost[0];
+  for (int i = 1; i < N; ++i) {
+    if (cost[i] < cmin) cmin = cost[i];
+    if (cost[i] > cmax) cmax = cost[i];
+  }
+  if (beta <= 0) beta = 0.1 * (cmax - cmin) + 1e-12;
+  double *w = (double *)malloc((size_t)N * sizeof(double));
+  double z = 0.0;
+  for (int i = 0; i < N; ++i) {
+    w[i] = exp(-(cost[i] - cmin) / beta);
+    z += w[i];
+  }
+  for (int i = 0; i < N; ++i) w[i] /= z;
+  for (int e = 0; e < n; ++e) {
+    double m1 = 0.0, m2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const double th = theta[(size_t)i * n + e];
+      m1 += w[i] * th;
+      m2 += w[i] * (th - mu[e]) * (th - mu[e]);
+    }
+    var[e] = (1.0 - k_sigma) * var[e] + k_sigma * m2;
+    mu[e] = (1.0 - k_mu) * mu[e] + k_mu * m1;
+  }
+  if (w_out) memcpy(w_out, w, (size_t)N * sizeof(double));
+  free(w);
+}
+
+void mgref_particles(const mgref_robot *rb, const mgref_params *pr,
+                     int n_box, const double *box_pose, const double *box_dims,
+                     const double *q0, const double *goal, int T, int S, double *mu,
+                     double *var, int N, int n_iters, const double *eps, double beta,
+                     double k_mu, double k_sigma, double *cost_out, int nthreads) {
+  const int D = rb->dof, n = T * D;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
+#endif
+  for (int s = 0; s < S; ++s) {
+    double *theta = (double *)malloc((size_t)N * n * sizeof(double));
+    double *c = (double *)malloc((size_t)N * sizeof(double));
+    double *m = mu + (size_t)s * n, *v = var + (size_t)s * n;
+    for (int it = 0; it < n_iters; ++it) {
+      for (int i = 0; i < N; ++i) {
+        const double *z = eps + (((size_t)it * N + i) * S + s) * n;
+        double *th = theta + (size_t)i * n;
+        for (int e = 0; e < n; ++e) {
+          const int d = e % D;
+          double x = m[e] + sqrt(v[e]) * z[e];
+          th[e] = x < rb->q_lo[d] ? rb->q_lo[d] : (x > rb->q_hi[d] ? rb->q_hi[d] : x);
+        }
+        c[i] = mgref_traj_cost(rb, pr, n_box, box_pose, box_dims, q0, goal, T, th, NULL, NULL, NULL);
+        if (cost_out) cost_out[((size_t)it * S + s) * N + i] = c[i];
+      }
+      mgref_particle_update(n, N, c, theta, m, v, beta, k_mu, k_sigma, NULL);
+    }
+    free(theta);
+    free(c);
+  }
+  (void)nthreads;
+}

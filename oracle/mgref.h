@@ -133,6 +133,31 @@ void mgref_solve(const mgref_robot *rb, const mgref_params *pr,
                  double eta1, double eta_w, double *best_cost, double *trace,
                  int nthreads);
 
+/* Particle-based optimization (Sec. 'Particle-Based Optimization', Alg.5,
+ * Eq.(12)-(13)), update step of one seed with n elements and N particles:
+ * weights w = softmax(-(C - min C) / beta) (exponential utility), then
+ *   mu'  = (1 - k_mu) mu + k_mu sum_i w_i theta_i
+ *   var' = (1 - k_sigma) var + k_sigma sum_i w_i (theta_i - mu)^2
+ * with mu the mean before the update.  Readings: the printed variance update
+ * lacks k_sigma and squares theta instead of the deviation; it is taken as
+ * the weighted variance about the previous mean.  beta <= 0 selects
+ * beta = 0.1 (max C - min C) + 1e-12.  theta[N][n]; w_out[N] may be NULL. */
+void mgref_particle_update(int n, int N, const double *cost, const double *theta,
+                           double *mu, double *var, double beta, double k_mu,
+                           double k_sigma, double *w_out);
+
+/* Particle stage of one problem with S seeds of T waypoints: n_iters rounds
+ * of sampling theta_i = clip(mu + sqrt(var) * eps_i) (eps standard normal,
+ * given: [n_iters][N][S][T][D]), costing every particle (cost only) and the
+ * update above.  mu[S][T][D] holds the seeds on entry and the final means on
+ * exit; var[S][T][D] the initial and final variances.  cost_out (may be
+ * NULL) receives [n_iters][S][N] particle costs. */
+void mgref_particles(const mgref_robot *rb, const mgref_params *pr,
+                     int n_box, const double *box_pose, const double *box_dims,
+                     const double *q0, const double *goal, int T, int S, double *mu,
+                     double *var, int N, int n_iters, const double *eps, double beta,
+                     double k_mu, double k_sigma, double *cost_out, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

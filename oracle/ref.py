@@ -172,8 +172,52 @@ class Ref:
                           _d(best)[1], _d(tr)[1] if trace else None, int(nthreads))
         return x, best, tr
 
+    def particles(self, boxes, q0, goal, T, mu, var, eps, beta=None, k_mu=None, k_sigma=None,
+                  nthreads=1):
+        """Particle stage of one problem: mu, var [S,T,D] in; eps
+        [n_iters, N, S, T, D].  Returns (mu', var', costs [n_iters, S, N])."""
+        pd = dict(PARTICLE_DEFAULTS)
+        pd.update({k: v for k, v in dict(beta=beta, k_mu=k_mu, k_sigma=k_sigma).items() if v is not None})
+        pose, dims = boxes
+        pose, pp = _d(np.asarray(pose).reshape(-1, 7)); dims, dp = _d(np.asarray(dims).reshape(-1, 3))
+        mu = np.array(mu, dtype=np.float64, copy=True)
+        var = np.array(var, dtype=np.float64, copy=True)
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        n_iters, N = eps.shape[0], eps.shape[1]
+        S = mu.size // (T * self.robot.dof)
+        assert eps.size == n_iters * N * S * T * self.robot.dof
+        costs = np.zeros((n_iters, S, N))
+        lib().mgref_particles(C.byref(self._rb), C.byref(self._pr), pose.shape[0], pp, dp,
+                              _d(q0)[1], _d(goal)[1], T, S, mu.ctypes.data_as(_dp),
+                              var.ctypes.data_as(_dp), N, n_iters, eps.ctypes.data_as(_dp),
+                              C.c_double(pd["beta"]), C.c_double(pd["k_mu"]),
+                              C.c_double(pd["k_sigma"]), costs.ctypes.data_as(_dp), int(nthreads))
+        return mu, var, costs
+
+
+# Particle stage constants.  The paper gives none of them (Alg.5 takes sigma0
+# as an input); these are the documented builder choices: initial per-element
+# variance 0.05^2 rad^2, adaptive temperature (beta <= 0: 0.1 x cost range),
+# mean and variance step sizes 0.9 and 0.5.
+PARTICLE_DEFAULTS = dict(sigma0=0.05 ** 2, beta=0.0, k_mu=0.9, k_sigma=0.5)
+
 
 # -- standalone helpers (no robot needed) -----------------------------------
+
+def particle_update(cost, theta, mu, var, beta=0.0, k_mu=0.9, k_sigma=0.5):
+    """One Eq.(12)-(13) update: cost [N], theta [N, n], mu, var [n].
+    Returns (mu', var', w)."""
+    cost = np.ascontiguousarray(cost, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    N, n = theta.shape
+    mu = np.array(mu, dtype=np.float64, copy=True).reshape(n)
+    var = np.array(var, dtype=np.float64, copy=True).reshape(n)
+    w = np.zeros(N)
+    lib().mgref_particle_update(n, N, _d(cost)[1], _d(theta)[1], mu.ctypes.data_as(_dp),
+                                var.ctypes.data_as(_dp), C.c_double(beta), C.c_double(k_mu),
+                                C.c_double(k_sigma), w.ctypes.data_as(_dp))
+    return mu, var, w
+
 
 def box_sdf(pose, dims, c):
     g = np.zeros(3)

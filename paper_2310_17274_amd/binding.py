@@ -68,6 +68,9 @@ class Batch:
         assert self.n_seeds == _lib.lib().mg_batch_seeds(h)
         assert self.rows == _lib.lib().mg_batch_rows(h)
 
+    def mg_batch_reserve_particles(self, n_particles: int):
+        _lib.check(_lib.lib().mg_batch_reserve_particles(self.handle, int(n_particles)))
+
     def mg_set_timing(self, enable: bool):
         check(_lib.lib().mg_set_timing(self.handle, int(bool(enable))))
 
@@ -189,6 +192,27 @@ class Context:
                                   int(m), len(alpha), al, int(mode), int(graph_inner),
                                   int(bool(use_graph)), _ptr(bc), _ptr(bs), _ptr(ok), _stream()))
         return x, bc, bs, ok
+
+    def mg_time_eval(self, b: Batch, q_start, goal, x, d, alpha, launches=30):
+        """Mean microseconds per line-search evaluation launch, timed with
+        HIP events around `launches` back-to-back launches."""
+        al = (C.c_float * len(alpha))(*alpha)
+        us = C.c_float(0.0)
+        check(_lib.lib().mg_time_eval(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(x), _ptr(d),
+                                      len(alpha), al, int(launches), C.byref(us), _stream()))
+        return us.value
+
+    def mg_particles(self, b: Batch, q_start, goal, mean, var, eps, beta=0.0, k_mu=0.9,
+                     k_sigma=0.5, costs=False):
+        """Particle stage in place on mean and var ([rows, D]); eps is
+        [n_iters, N, rows, D].  Returns (mean, var, costs [n_iters, seeds, N]
+        or None)."""
+        n_iters, N = int(eps.shape[0]), int(eps.shape[1])
+        out = torch.empty((n_iters, b.n_seeds, N), dtype=torch.float32, device=self.device) if costs else None
+        check(_lib.lib().mg_particles(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(mean),
+                                      _ptr(var), N, n_iters, _ptr(eps), float(beta), float(k_mu),
+                                      float(k_sigma), _ptr(out) if costs else None, _stream()))
+        return mean, var, out
 
 
 class MgCost(torch.autograd.Function):

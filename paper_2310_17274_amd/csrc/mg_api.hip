@@ -111,6 +111,9 @@ struct mg_batch {
   std::vector<hipEvent_t> ev_start, ev_stop;
   int ev_next = 0, ev_count = 0;
   int slices = -1;    // forced cuboid slices index (-1: automatic)
+  // particle stage: per-row costs of every particle [p_cap][rows]
+  float* p_cost = nullptr;
+  int p_cap = 0;
 };
 
 namespace {
@@ -187,7 +190,8 @@ mg_status check_params(const mg_params* p) {
   if (!p) return fail(MG_ERR_ARG, "params is null");
   if (!(p->dt > 0)) return fail(MG_ERR_ARG, "dt must be > 0");
   if (!(p->eta >= 0) || !(p->eta2 > 0)) return fail(MG_ERR_ARG, "eta must be >= 0 and eta2 > 0");
-  if (p->swept) return fail(MG_ERR_UNSUPPORTED, "swept collision is not implemented in this build");
+  if (p->swept && (p->sweep_steps < 0 || p->sweep_steps > 64))
+    return fail(MG_ERR_ARG, "sweep_steps must be in [0, 64] (got %d)", p->sweep_steps);
   return MG_OK;
 }
 
@@ -195,6 +199,7 @@ mg_status check_params(const mg_params* p) {
 // slices (least repeated kinematics) that still give every SIMD about four
 // wavefronts; MG_CUBOID_SLICES forces a choice.
 int pick_slices(const mg_batch* b, long n_evals) {
+  if (b->ctx->params.swept) return 0;   // the swept kernels take whole worlds
   if (b->slices >= 0) return b->slices;
   const char* env = getenv("MG_CUBOID_SLICES");
   if (env) {
@@ -228,7 +233,7 @@ mg::EvalArgs eval_args(const mg_ctx* c, const mg_batch* b, int hi, const float* 
   a.x = x;
   a.d = d;
   a.K = K;
-  for (int k = 0; k < K; ++k) a.alpha[k] = alpha ? alpha[k] : 0.0f;
+  for (int k = 0; k < K && k < mg::kMaxK; ++k) a.alpha[k] = alpha ? alpha[k] : 0.0f;
   a.cost_e = b->cost_e;
   a.gd_e = b->gd_e;
   a.mc_e = b->mc_e;
@@ -544,7 +549,7 @@ void mg_batch_destroy(mg_batch* b) {
   dev_free(b->cost_e); dev_free(b->gd_e); dev_free(b->mc_e); dev_free(b->grad_e); dev_free(b->pe_e);
   dev_free(b->c_cur); dev_free(b->g_cur); dev_free(b->dir); dev_free(b->best_c); dev_free(b->best_x);
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
-  dev_free(b->rho); dev_free(b->meta);
+  dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost);
   delete b;
 }
 
@@ -582,6 +587,33 @@ mg_status mg_eval_time(mg_batch* b, float* mean_us, int* count) {
 }
 int mg_batch_rows(const mg_batch* b) { return b ? b->rows : 0; }
 
+mg_status mg_time_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
+                       const float* x, const float* dir, int K, const float* alpha, int launches,
+                       float* mean_us, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if ((st = check_K_alpha(b, K, alpha)) != MG_OK) return st;
+  if (!q_start || !goal || !x || !dir || !mean_us) return fail(MG_ERR_ARG, "null argument");
+  if (launches < 1) return fail(MG_ERR_ARG, "launches must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int hi = pick_slices(b, (long)b->rows * K);
+  const mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, x, dir, K, alpha);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  hipError_t err = hipEventRecord(e0, s);
+  for (int i = 0; i < launches && err == hipSuccess; ++i) err = mg::launch_eval(a, b->chunks[hi], true, true, s);
+  if (err == hipSuccess) err = hipEventRecord(e1, s);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(MG_ERR_HIP, "timing the evaluation kernel: %s", hipGetErrorString(err));
+  *mean_us = 1000.0f * ms / launches;
+  return MG_OK;
+}
+
 mg_status mg_cost_grad(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
                        const float* q, float* cost, float* grad, float* min_clear, void* stream) {
   mg_status st = common_checks(c, b);
@@ -617,6 +649,68 @@ mg_status mg_linesearch(mg_ctx* c, mg_batch* b, const float* q_start, const floa
   if ((st = enqueue_eval(c, b, q_start, goal, x, dir, K, alpha, true, nullptr, nullptr, s)) != MG_OK) return st;
   return enqueue_select(c, b, x, c0, g0, dir, K, alpha, mode, x_out, c_out, g_out, chosen, min_clear, false,
                         nullptr, s);
+}
+
+mg_status mg_batch_reserve_particles(mg_batch* b, int n_particles) {
+  if (!b) return fail(MG_ERR_ARG, "null batch");
+  if (n_particles < 1 || n_particles > mg::kMaxParticles)
+    return fail(MG_ERR_SHAPE, "n_particles = %d outside 1..%d", n_particles, mg::kMaxParticles);
+  if (n_particles <= b->p_cap) return MG_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  dev_free(b->p_cost);
+  b->p_cap = 0;
+  mg_status st = dev_alloc(&b->p_cost, (size_t)n_particles * b->rows);
+  if (st != MG_OK) return st;
+  b->p_cap = n_particles;
+  return MG_OK;
+}
+
+mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* mean,
+                       float* var, int n_particles, int n_iters, const float* eps, float beta,
+                       float k_mu, float k_sigma, float* costs_out, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if (n_particles < 1 || n_particles > b->p_cap)
+    return fail(MG_ERR_STATE, "n_particles = %d exceeds the %d reserved (mg_batch_reserve_particles)",
+                n_particles, b->p_cap);
+  if (n_iters < 0) return fail(MG_ERR_ARG, "n_iters must be >= 0");
+  if (!q_start || !goal || !mean || !var || (n_iters > 0 && !eps))
+    return fail(MG_ERR_ARG, "null q_start, goal, mean, var or eps");
+  if (!(k_mu >= 0.0f && k_mu <= 1.0f) || !(k_sigma >= 0.0f && k_sigma <= 1.0f))
+    return fail(MG_ERR_ARG, "k_mu and k_sigma must lie in [0, 1]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t draws = (size_t)n_particles * b->rows * c->D;
+  const int hi = pick_slices(b, (long)b->rows * n_particles);
+  for (int it = 0; it < n_iters; ++it) {
+    const float* e = eps + (size_t)it * draws;
+    mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, mean, e, n_particles, nullptr);
+    a.var = var;
+    a.d_stride = (size_t)b->rows * c->D;
+    a.cost_e = b->p_cost;
+    a.mc_e = nullptr;
+    a.gd_e = nullptr;
+    a.grad_e = nullptr;
+    HIP_TRY(mg::launch_eval(a, b->chunks[hi], true, false, s));
+    mg::ParticleArgs pa;
+    memset(&pa, 0, sizeof(pa));
+    pa.seeds = b->d_seed;
+    pa.n_seeds = b->n_seeds;
+    pa.rows = b->rows;
+    pa.dof = c->D;
+    pa.N = n_particles;
+    pa.beta = beta;
+    pa.k_mu = k_mu;
+    pa.k_sigma = k_sigma;
+    pa.q_lo = c->d_q_lo;
+    pa.q_hi = c->d_q_hi;
+    pa.cost_e = b->p_cost;
+    pa.eps = e;
+    pa.mean = mean;
+    pa.var = var;
+    pa.costs_out = costs_out ? costs_out + (size_t)it * b->n_seeds * n_particles : nullptr;
+    HIP_TRY(mg::launch_particle_update(pa, s));
+  }
+  return MG_OK;
 }
 
 }  // extern "C"

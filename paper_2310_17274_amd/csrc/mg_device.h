@@ -154,29 +154,35 @@ __device__ __forceinline__ void mat_to_quat(const float* T, float& qw, float& qx
   }
 }
 
-// One sphere against one cuboid, taken only when the cheap face test says
-// the sphere may be within r + eta: exact signed distance, Eq.(10) profile,
-// and d cost / d centre accumulated into g.
-__device__ __forceinline__ void near_pair(const v4f& A0, const v4f& A1, const v4f& A2, float px,
-                                          float py, float pz, float ax, float ay, float az, float m3,
-                                          float r, float w, float eta, float inv_eta, float& cost,
-                                          float& mc, float& gx, float& gy, float& gz) {
+// Exact signed distance of a box-frame point p to a box with half extents h,
+// given a = |p| - h componentwise (Sec. world collision: closest point and
+// inside/outside sign), and its gradient in the box frame.  Inside, the
+// gradient is the outward normal of the nearest face, lowest axis on ties.
+__device__ __forceinline__ float box_sdf(float px, float py, float pz, float ax, float ay, float az,
+                                         float& gpx, float& gpy, float& gpz) {
   const float qx = fmaxf(ax, 0.0f), qy = fmaxf(ay, 0.0f), qz = fmaxf(az, 0.0f);
   const float n2 = qx * qx + qy * qy + qz * qz;
-  float sdf, gpx = 0.0f, gpy = 0.0f, gpz = 0.0f;
+  gpx = gpy = gpz = 0.0f;
   if (n2 > 0.0f) {
     const float n = sqrtf(n2), inv = __builtin_amdgcn_rcpf(n);
-    sdf = n;
     gpx = (px >= 0.0f ? qx : -qx) * inv;
     gpy = (py >= 0.0f ? qy : -qy) * inv;
     gpz = (pz >= 0.0f ? qz : -qz) * inv;
-  } else {
-    sdf = m3;
-    if (ax >= ay && ax >= az) gpx = px >= 0.0f ? 1.0f : -1.0f;
-    else if (ay >= az) gpy = py >= 0.0f ? 1.0f : -1.0f;
-    else gpz = pz >= 0.0f ? 1.0f : -1.0f;
+    return n;
   }
-  mc = fminf(mc, sdf - r);
+  if (ax >= ay && ax >= az) gpx = px >= 0.0f ? 1.0f : -1.0f;
+  else if (ay >= az) gpy = py >= 0.0f ? 1.0f : -1.0f;
+  else gpz = pz >= 0.0f ? 1.0f : -1.0f;
+  return fmaxf(ax, fmaxf(ay, az));
+}
+
+// Eq.(10) smoothed penetration cost w d_c(r - sdf) added to cost; the box-frame
+// gradient (gpx, gpy, gpz) of sdf is rotated back to the world and
+// d cost / d point is accumulated into g.
+__device__ __forceinline__ void dc_term(const v4f& A0, const v4f& A1, const v4f& A2, float sdf,
+                                        float gpx, float gpy, float gpz, float r, float w,
+                                        float eta, float inv_eta, float& cost, float& gx, float& gy,
+                                        float& gz) {
   const float pen = r - sdf;
   if (pen > -eta) {
     float dcv, slope;
@@ -195,6 +201,20 @@ __device__ __forceinline__ void near_pair(const v4f& A0, const v4f& A1, const v4
     gy = fmaf(f, A0.y * gpx + A1.y * gpy + A2.y * gpz, gy);
     gz = fmaf(f, A0.z * gpx + A1.z * gpy + A2.z * gpz, gz);
   }
+}
+
+// One sphere against one cuboid, taken only when the cheap face test says
+// the sphere may be within r + eta: exact signed distance, Eq.(10) profile,
+// clearance, and d cost / d centre accumulated into g.  Returns the distance.
+__device__ __forceinline__ float near_pair(const v4f& A0, const v4f& A1, const v4f& A2, float px,
+                                           float py, float pz, float ax, float ay, float az,
+                                           float r, float w, float eta, float inv_eta, float& cost,
+                                           float& mc, float& gx, float& gy, float& gz) {
+  float gpx, gpy, gpz;
+  const float sdf = box_sdf(px, py, pz, ax, ay, az, gpx, gpy, gpz);
+  mc = fminf(mc, sdf - r);
+  dc_term(A0, A1, A2, sdf, gpx, gpy, gpz, r, w, eta, inv_eta, cost, gx, gy, gz);
+  return sdf;
 }
 
 }  // namespace

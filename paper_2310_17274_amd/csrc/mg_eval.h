@@ -45,6 +45,68 @@ __device__ __forceinline__ void suffix_step(float* W, bool active) {
   }
 }
 
+// Pose of this lane's link at its joint value q: the local transform
+// F_l Rz(q) from the Tab.6 closed form (columns 0 and 1 mix, 2 and 3 are
+// F's), then the prefix product along the chain (pos = lanes past the chain
+// start).  Lanes without a link hold the identity.
+template <int LPE>
+__device__ __forceinline__ void link_pose(const float* __restrict__ fixed_tf, int lj, bool on, int pos,
+                                          float q, float* T) {
+  const float sn = __sinf(q), cs = __cosf(q);
+  const float4 f0 = *reinterpret_cast<const float4*>(fixed_tf + lj * 12 + 0);
+  const float4 f1 = *reinterpret_cast<const float4*>(fixed_tf + lj * 12 + 4);
+  const float4 f2 = *reinterpret_cast<const float4*>(fixed_tf + lj * 12 + 8);
+  T[0] = f0.x * cs + f0.y * sn;  T[1] = f0.y * cs - f0.x * sn;  T[2] = f0.z;  T[3] = f0.w;
+  T[4] = f1.x * cs + f1.y * sn;  T[5] = f1.y * cs - f1.x * sn;  T[6] = f1.z;  T[7] = f1.w;
+  T[8] = f2.x * cs + f2.y * sn;  T[9] = f2.y * cs - f2.x * sn;  T[10] = f2.z; T[11] = f2.w;
+  if (!on) identity(T);
+  scan_step<1>(T, pos >= 1);
+  scan_step<2>(T, pos >= 2);
+  scan_step<4>(T, pos >= 4);
+  if (LPE > 8) scan_step<8>(T, pos >= 8);
+}
+
+// Continuous collision of one sphere against one cuboid (Alg.11-12 sphere
+// tracing): from the centre c toward the neighbouring waypoint's centre,
+// step by the clearance (by r + eta inside the band) while short of the
+// half-way point, at most sweep_steps samples per side, each costed with the
+// Eq.(10) profile.  (px, py, pz) is c in the box frame, sdf its distance.
+__device__ __forceinline__ void sweep_pair(const EvalArgs& a, int slot, const float* Tp,
+                                           const float* Tn, bool has_next, float cx, float cy,
+                                           float cz, const v4f& A0, const v4f& A1, const v4f& A2,
+                                           const v4f& Hh, float px, float py, float pz, float sdf,
+                                           float r, float w, float eta, float inv_eta, float& cost,
+                                           float& gx, float& gy, float& gz) {
+  const float4 ls = a.ln.sphere[slot];
+  const float rh = r + eta;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const float* Tb = side == 0 ? Tp : Tn;
+    if (side == 1 && !has_next) break;
+    float ux = Tb[0] * ls.x + Tb[1] * ls.y + Tb[2] * ls.z + Tb[3] - cx;
+    float uy = Tb[4] * ls.x + Tb[5] * ls.y + Tb[6] * ls.z + Tb[7] - cy;
+    float uz = Tb[8] * ls.x + Tb[9] * ls.y + Tb[10] * ls.z + Tb[11] - cz;
+    const float len = sqrtf(ux * ux + uy * uy + uz * uz);
+    if (!(len > 0.0f)) continue;
+    const float il = 1.0f / len;
+    ux *= il; uy *= il; uz *= il;
+    // unit direction in the box frame
+    const float vx = A0.x * ux + A0.y * uy + A0.z * uz;
+    const float vy = A1.x * ux + A1.y * uy + A1.z * uz;
+    const float vz = A2.x * ux + A2.y * uy + A2.z * uz;
+    const float half = 0.5f * len;
+    float j = sdf < rh ? rh : sdf - rh;
+    for (int st = 0; st < a.pr.sweep_steps && j < half; ++st) {
+      const float qx = fmaf(j, vx, px), qy = fmaf(j, vy, py), qz = fmaf(j, vz, pz);
+      float gpx, gpy, gpz;
+      const float s2 = box_sdf(qx, qy, qz, fabsf(qx) - Hh.x, fabsf(qy) - Hh.y, fabsf(qz) - Hh.z,
+                               gpx, gpy, gpz);
+      dc_term(A0, A1, A2, s2, gpx, gpy, gpz, r, w, eta, inv_eta, cost, gx, gy, gz);
+      j += s2 - rh > 0.0f ? s2 - rh : rh;
+    }
+  }
+}
+
 // Lane layout: lane l of an evaluation owns link l.  A wave holds 64/LPE
 // evaluations (consecutive waypoint rows of one problem, candidate k =
 // blockIdx.y); the 4 waves of a workgroup hold 4/H evaluation groups, each
@@ -55,7 +117,13 @@ __device__ __forceinline__ void suffix_step(float* W, bool active) {
 // pose.  Adjoint: lane l's link wrench (force and moment of the cost
 // gradients at its spheres and end effector) is summed over the links below
 // it by a suffix scan; joint l's derivative is z_l . (M - o_l x F) (Tab.7).
-template <int LPE, int MAXS, int H, bool CAND, bool GRAD>
+//
+// SW (continuous collision, Sec. continuous collision checking, Alg.11-12):
+// the lane also forms its link pose at the neighbouring waypoints (the start
+// configuration before waypoint 1), and each sphere is traced from its
+// centre toward the half-way point of both segments; the samples' cost
+// gradients act on the centre, as in the paper.
+template <int LPE, int MAXS, int H, bool CAND, bool GRAD, bool SW>
 __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
   constexpr int EPW = kWave / LPE;                 // evaluations per wave
   constexpr int GROUPS = (kBlock / kWave) / H;     // evaluation groups per workgroup
@@ -85,13 +153,16 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
   const int rl = valid ? rloc : nrows - 1;
   const int t = rl % pb.T;          // waypoint t+1 of its seed
   const int row = pb.row0 + rl;
-  const float alpha = CAND ? a.alpha[k] : 0.0f;
+  const float alpha = CAND ? a.alpha[k < kMaxK ? k : 0] : 0.0f;
+  const float* dk = CAND ? a.d + (size_t)k * a.d_stride : nullptr;
 
-  // candidate value of joint j at waypoint row r: clip(x + alpha d)
+  // candidate value of joint j at waypoint row r: clip(x + alpha d) for a
+  // line-search candidate, clip(x + sqrt(var) d_k) for a particle
   auto qval = [&](int r, int j) -> float {
-    float v = a.x[(size_t)r * D + j];
+    const size_t e = (size_t)r * D + j;
+    float v = a.x[e];
     if (CAND) {
-      v = fmaf(alpha, a.d[(size_t)r * D + j], v);
+      v = a.var ? fmaf(sqrtf(a.var[e]), dk[e], v) : fmaf(alpha, dk[e], v);
       v = fminf(fmaxf(v, a.rb.q_lo[j]), a.rb.q_hi[j]);
     }
     return v;
@@ -101,24 +172,23 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
   const bool on = l < L;
   const int lj = on ? l : 0;
   const float ql = qval(row, lj);
-  const float sn = __sinf(ql), cs = __cosf(ql);
 
-  // ---- forward kinematics: local transform, then prefix product ----
+  // ---- forward kinematics ----
   float T[12];
-  {
-    const float4 f0 = *reinterpret_cast<const float4*>(a.rb.fixed_tf + lj * 12 + 0);
-    const float4 f1 = *reinterpret_cast<const float4*>(a.rb.fixed_tf + lj * 12 + 4);
-    const float4 f2 = *reinterpret_cast<const float4*>(a.rb.fixed_tf + lj * 12 + 8);
-    // F * Rz(q): columns 0, 1 mix, 2 and 3 are F's (Tab.6, revolute z)
-    T[0] = f0.x * cs + f0.y * sn;  T[1] = f0.y * cs - f0.x * sn;  T[2] = f0.z;  T[3] = f0.w;
-    T[4] = f1.x * cs + f1.y * sn;  T[5] = f1.y * cs - f1.x * sn;  T[6] = f1.z;  T[7] = f1.w;
-    T[8] = f2.x * cs + f2.y * sn;  T[9] = f2.y * cs - f2.x * sn;  T[10] = f2.z; T[11] = f2.w;
-    if (!on) identity(T);
-    const int pos = l - li.x;
-    scan_step<1>(T, pos >= 1);
-    scan_step<2>(T, pos >= 2);
-    scan_step<4>(T, pos >= 4);
-    if (LPE > 8) scan_step<8>(T, pos >= 8);
+  link_pose<LPE>(a.rb.fixed_tf, lj, on, l - li.x, ql, T);
+
+  // link poses at the neighbouring waypoints (swept collision; one waypoint
+  // alone has no segments to trace)
+  float Tp[SW ? 12 : 1], Tn[SW ? 12 : 1];
+  const bool sweep = SW && pb.T > 1;
+  const bool has_next = sweep && t + 1 < pb.T;
+  if constexpr (SW) {
+    if (sweep) {
+      const float qp = t >= 1 ? qval(row - 1, lj) : a.q_start[(size_t)p * D + lj];
+      const float qn = has_next ? qval(row + 1, lj) : ql;
+      link_pose<LPE>(a.rb.fixed_tf, lj, on, l - li.x, qp, Tp);
+      link_pose<LPE>(a.rb.fixed_tf, lj, on, l - li.x, qn, Tn);
+    }
   }
 
   float cost = 0.0f;
@@ -252,6 +322,24 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
       cz[s] = used ? T[8] * ls.x + T[9] * ls.y + T[10] * ls.z + T[11] : 1e18f;
       rr[s] = used ? ls.w : 0.0f;
       rho[s] = rr[s] + eta;
+      if constexpr (SW) {
+        // every trace sample lies within half a segment of the centre and the
+        // distance is 1-Lipschitz, so r + eta + L/2 bounds the cull
+        if (sweep && used) {
+          const float bx = Tp[0] * ls.x + Tp[1] * ls.y + Tp[2] * ls.z + Tp[3] - cx[s];
+          const float by = Tp[4] * ls.x + Tp[5] * ls.y + Tp[6] * ls.z + Tp[7] - cy[s];
+          const float bz = Tp[8] * ls.x + Tp[9] * ls.y + Tp[10] * ls.z + Tp[11] - cz[s];
+          float l2 = bx * bx + by * by + bz * bz;
+          if (has_next) {
+            const float fx = Tn[0] * ls.x + Tn[1] * ls.y + Tn[2] * ls.z + Tn[3] - cx[s];
+            const float fy = Tn[4] * ls.x + Tn[5] * ls.y + Tn[6] * ls.z + Tn[7] - cy[s];
+            const float fz = Tn[8] * ls.x + Tn[9] * ls.y + Tn[10] * ls.z + Tn[11] - cz[s];
+            l2 = fmaxf(l2, fx * fx + fy * fy + fz * fz);
+          }
+          // (slightly widened so rounding never culls a sample the trace takes)
+          rho[s] += 0.5f * sqrtf(l2) * 1.0001f + 1e-6f;
+        }
+      }
     }
     const int w0 = a.world_off[pb.world], w1 = a.world_off[pb.world + 1];
     const int per = (w1 - w0 + H - 1) / H;
@@ -292,8 +380,12 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
             const float py = fmaf(A1.x, cx[s], fmaf(A1.y, cy[s], fmaf(A1.z, cz[s], A1.w)));
             const float pz = fmaf(A2.x, cx[s], fmaf(A2.y, cy[s], fmaf(A2.z, cz[s], A2.w)));
             float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-            near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y, fabsf(pz) - Hh.z,
-                      m3[s], rr[s], w, eta, inv_eta, cost, mc, gx, gy, gz);
+            const float sdf = near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y,
+                                        fabsf(pz) - Hh.z, rr[s], w, eta, inv_eta, cost, mc, gx, gy, gz);
+            if constexpr (SW) {
+              if (sweep) sweep_pair(a, l * MAXS + s, Tp, Tn, has_next, cx[s], cy[s], cz[s], A0, A1,
+                                    A2, Hh, px, py, pz, sdf, rr[s], w, eta, inv_eta, cost, gx, gy, gz);
+            }
             Fx += gx; Fy += gy; Fz += gz;
             Mx += cy[s] * gz - cz[s] * gy;
             My += cz[s] * gx - cx[s] * gz;
@@ -350,21 +442,32 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
     const size_t e = (size_t)k * a.rows + row;
     if (l == 0) {
       a.cost_e[e] = csum;
-      a.mc_e[e] = mcmin;
+      if (a.mc_e) a.mc_e[e] = mcmin;
       if (CAND && GRAD) a.gd_e[e] = gd;
     }
     if (GRAD && l < D) a.grad_e[e * D + l] = gradj;
   }
 }
 
+template <int LPE, int MAXS, int H, bool SW>
+hipError_t launch_eval_hs(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s) {
+  const dim3 grid(grid_x, cand ? a.K : 1), block(kBlock);
+  if (cand && grad) eval_kernel<LPE, MAXS, H, true, true, SW><<<grid, block, 0, s>>>(a);
+  else if (grad) eval_kernel<LPE, MAXS, H, false, true, SW><<<grid, block, 0, s>>>(a);
+  else if (!cand) eval_kernel<LPE, MAXS, H, false, false, SW><<<grid, block, 0, s>>>(a);
+  else eval_kernel<LPE, MAXS, H, true, false, SW><<<grid, block, 0, s>>>(a);   // particle costs
+  return hipGetLastError();
+}
+
+// Swept collision is built for whole-world waves only (one slice).
 template <int LPE, int MAXS, int H>
 hipError_t launch_eval_h(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s) {
-  const dim3 grid(grid_x, cand ? a.K : 1), block(kBlock);
-  if (cand && grad) eval_kernel<LPE, MAXS, H, true, true><<<grid, block, 0, s>>>(a);
-  else if (grad) eval_kernel<LPE, MAXS, H, false, true><<<grid, block, 0, s>>>(a);
-  else if (!cand) eval_kernel<LPE, MAXS, H, false, false><<<grid, block, 0, s>>>(a);
-  else return hipErrorInvalidValue;   // candidates without gradients are not used
-  return hipGetLastError();
+  if constexpr (H == 1) {
+    if (a.pr.swept) return launch_eval_hs<LPE, MAXS, 1, true>(a, grid_x, cand, grad, s);
+  } else {
+    if (a.pr.swept) return hipErrorInvalidValue;
+  }
+  return launch_eval_hs<LPE, MAXS, H, false>(a, grid_x, cand, grad, s);
 }
 
 template <int LPE, int MAXS>

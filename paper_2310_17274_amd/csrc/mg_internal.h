@@ -17,6 +17,7 @@ constexpr int kMaxDof = 16;
 constexpr int kMaxT = 64;        // waypoints per trajectory
 constexpr int kMaxEE = 2;
 constexpr int kMaxHist = 16;     // L-BFGS history
+constexpr int kMaxParticles = 1024;   // particles per seed of the particle stage
 constexpr int kPerLane = kMaxT * kMaxDof / kWave;   // vector elements per lane in the solver kernels
 
 // Cost parameters (see mg_params in mg.h).
@@ -86,6 +87,10 @@ struct EvalArgs {
   const float* goal;       // [P][n_ee][7]
   const float* x;          // [rows][D]
   const float* d;          // [rows][D] direction (candidate mode) or null
+  // particle mode (var != null): candidate k is clip(x + sqrt(var) d_k) with
+  // d_k = d + k * d_stride standard normal draws; alpha is not used
+  const float* var;        // [rows][D] per-element variance or null
+  size_t d_stride;
   float alpha[kMaxK];
   int K;
   float* cost_e;           // [K][rows]
@@ -144,6 +149,21 @@ struct LbfgsArgs {
   int m_max;
 };
 
+// Particle stage update (Eq.(12)-(13)) of every seed after its particles
+// were costed.
+struct ParticleArgs {
+  const SeedInfo* seeds;
+  int n_seeds, rows, dof, N;
+  float beta, k_mu, k_sigma;   // beta <= 0: 0.1 x the seed's cost range
+  const float* q_lo;
+  const float* q_hi;
+  const float* cost_e;     // [N][rows] per-row particle costs
+  const float* eps;        // [N][rows][D] this round's draws
+  float* mean;             // [rows][D] in/out
+  float* var;              // [rows][D] in/out
+  float* costs_out;        // [n_seeds][N] or null
+};
+
 struct FinalArgs {
   const Problem* prob;
   int P, rows;
@@ -162,6 +182,7 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, hipStream_t s);
 hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s);
 
+hipError_t launch_particle_update(const ParticleArgs& a, hipStream_t s);
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);
 hipError_t launch_boxes(const float* pose, const float* dims, int n, Box* out, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);

@@ -8,6 +8,7 @@
 // reduce_kernel    per-seed sums of a single evaluation.
 // select_kernel    parallel noisy line-search choice and best tracking.
 // lbfgs_kernel     two-loop L-BFGS direction, one wavefront per seed.
+// particle_update_kernel  particle-stage weights, mean and variance update.
 // final_kernel     per-problem best seed and success verdict.
 #include "mg_device.h"
 #include "mg_eval.h"
@@ -28,6 +29,76 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(const ReduceArgs a) {
   }
   a.cost[s] = c;
   if (a.min_clear) a.min_clear[s] = m;
+}
+
+// --------------------------------------------------------------------------
+// Particle-based optimization update (Alg.5, Eq.(12)-(13)) of one seed per
+// workgroup: particle costs from the per-row sums, exponential-utility
+// weights w = softmax(-(C - min C) / beta), then per element
+//   mean' = (1 - k_mu) mean + k_mu sum_i w_i theta_i
+//   var'  = (1 - k_sigma) var + k_sigma sum_i w_i (theta_i - mean)^2
+// with theta_i = clip(mean + sqrt(var) eps_i) formed exactly as the
+// evaluation kernel formed it.  Fixed-order reductions: deterministic.
+template <typename Op>
+__device__ __forceinline__ float block_reduce(float v, float* s_red, Op op) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) v = op(v, __shfl_xor(v, o, kWave));
+  __syncthreads();
+  if (lane == 0) s_red[wave] = v;
+  __syncthreads();
+  float r = s_red[0];
+  for (int w = 1; w < kBlock / kWave; ++w) r = op(r, s_red[w]);
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void particle_update_kernel(const ParticleArgs a) {
+  __shared__ float s_w[kMaxParticles];
+  __shared__ float s_red[kBlock / kWave];
+  const int seed = blockIdx.x;
+  const SeedInfo si = a.seeds[seed];
+  const int D = a.dof, N = a.N;
+  float cmin = 3.0e38f, cmax = -3.0e38f;
+  for (int i = threadIdx.x; i < N; i += kBlock) {
+    const float* ce = a.cost_e + (size_t)i * a.rows + si.row0;
+    float c = 0.0f;
+    for (int t = 0; t < si.T; ++t) c += ce[t];
+    s_w[i] = c;
+    if (a.costs_out) a.costs_out[(size_t)seed * N + i] = c;
+    cmin = fminf(cmin, c);
+    cmax = fmaxf(cmax, c);
+  }
+  cmin = block_reduce(cmin, s_red, [](float x, float y) { return fminf(x, y); });
+  cmax = block_reduce(cmax, s_red, [](float x, float y) { return fmaxf(x, y); });
+  const float beta = a.beta > 0.0f ? a.beta : 0.1f * (cmax - cmin) + 1e-12f;
+  const float inv_beta = 1.0f / beta;
+  float z = 0.0f;
+  for (int i = threadIdx.x; i < N; i += kBlock) {
+    const float w = expf(-(s_w[i] - cmin) * inv_beta);
+    s_w[i] = w;
+    z += w;
+  }
+  z = block_reduce(z, s_red, [](float x, float y) { return x + y; });
+  const float inv_z = 1.0f / z;
+  __syncthreads();
+  const int n = si.T * D;
+  const size_t base = (size_t)si.row0 * D, stride = (size_t)a.rows * D;
+  for (int e = threadIdx.x; e < n; e += kBlock) {
+    const float mu = a.mean[base + e], v = a.var[base + e], sd = sqrtf(v);
+    const int j = e % D;
+    const float lo = a.q_lo[j], hi = a.q_hi[j];
+    float m1 = 0.0f, m2 = 0.0f;
+    const float* ep = a.eps + base + e;
+    for (int i = 0; i < N; ++i) {
+      const float th = fminf(fmaxf(fmaf(sd, ep[(size_t)i * stride], mu), lo), hi);
+      const float w = s_w[i];
+      const float dv = th - mu;
+      m1 = fmaf(w, th, m1);
+      m2 = fmaf(w, dv * dv, m2);
+    }
+    a.var[base + e] = (1.0f - a.k_sigma) * v + a.k_sigma * (m2 * inv_z);
+    a.mean[base + e] = (1.0f - a.k_mu) * mu + a.k_mu * (m1 * inv_z);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -382,6 +453,12 @@ hipError_t launch_lbfgs_h(const LbfgsArgs& a, int max_n, hipStream_t s) {
 hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s) {
   if (a.m <= 4) return launch_lbfgs_h<4>(a, max_n, s);
   return launch_lbfgs_h<kMaxHist>(a, max_n, s);
+}
+
+hipError_t launch_particle_update(const ParticleArgs& a, hipStream_t s) {
+  if (a.N < 1 || a.N > kMaxParticles) return hipErrorInvalidValue;
+  particle_update_kernel<<<a.n_seeds, kBlock, 0, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_final(const FinalArgs& a, hipStream_t s) {

@@ -462,6 +462,161 @@ def test_two_arm_tree_gradient(oracle_lib):
 
 
 # --------------------------------------------------------------------------
+# P10 continuous (swept) collision, Sec. continuous collision checking
+
+def one_link_robot(radius=0.05):
+    """One revolute-z joint at the base carrying one sphere at (1, 0, 0)."""
+    eye = np.array([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], dtype=float)
+    return wl.Robot(parent=np.array([-1], np.int32), joint=np.array([0], np.int32),
+                    fixed_tf=eye[None], sphere_link=np.array([0], np.int32),
+                    sphere=np.array([[1.0, 0.0, 0.0, radius]]), ee_link=np.array([0], np.int32),
+                    ee_tf=eye[None], q_lo=np.array([-3.0]), q_hi=np.array([3.0]))
+
+
+COLLISION_ONLY = dict(a0=0.0, a1=0.0, a6=0.0, a8=0.0, a9=0.0, w_bound=0.0, w_coll=1.0)
+
+
+def test_swept_tunnelling_through_thin_wall(oracle_lib):
+    """Worked example.  The sphere (r = 0.05, eta = 0.025, rho = 0.075) sits
+    0.09 m on either side of a wall of half thickness 0.02 at waypoints 1 and 2
+    (start = waypoint 1), the chord between them along the wall normal.
+    Discrete: each waypoint has clearance 0.07 < rho, penetration -0.02, so
+    d_c = 0.005^2 / 0.05 = 5e-4 each.  Swept: from each waypoint the trace
+    starts one rho = 0.075 inside the segment (the centre is within the band),
+    lands 0.015 m past the wall's mid-plane (distance -0.005, penetration
+    0.055, d_c = 0.055 + 0.0125 = 0.0675), then jumps rho again, past the
+    half-way point 0.09, and stops.  Total 2 (5e-4 + 0.0675) = 0.136."""
+    robot = one_link_robot()
+    phi = math.asin(0.09)
+    wall = (np.array([[math.cos(phi), 0.0, 0.0, 1.0, 0.0, 0.0, 0.0]]), np.array([[1.0, 0.04, 1.0]]))
+    q = np.array([[-phi], [phi]])
+    goal = np.array([[0, 0, 0, 1, 0, 0, 0]], dtype=float)
+    disc = ref.Ref(robot, **COLLISION_ONLY).traj_cost(wall, q[0], goal, q)
+    swept = ref.Ref(robot, swept=1, sweep_steps=4, **COLLISION_ONLY).traj_cost(wall, q[0], goal, q)
+    assert disc[0] == pytest.approx(2 * 5e-4, rel=1e-9)
+    assert swept[0] == pytest.approx(0.136, rel=1e-9)
+    # clearance 0.07 - r at both waypoints; the trace samples do not enter the verdict
+    assert disc[2] == pytest.approx(0.02, rel=1e-9) and swept[2] == disc[2]
+    # one sample per side: more steps change nothing, none gives the discrete cost
+    swept8 = ref.Ref(robot, swept=1, sweep_steps=8, **COLLISION_ONLY).traj_cost(wall, q[0], goal, q)
+    swept0 = ref.Ref(robot, swept=1, sweep_steps=0, **COLLISION_ONLY).traj_cost(wall, q[0], goal, q)
+    assert swept8[0] == pytest.approx(0.136, rel=1e-9)
+    assert swept0[0] == pytest.approx(disc[0], rel=1e-12)
+
+
+def test_swept_reduces_to_discrete(oracle_lib):
+    """No motion (every waypoint at the start) or a single waypoint: no
+    segment to trace, so the swept cost and gradient equal the discrete."""
+    robot = wl.make_arm(seed=0, n_spheres=20)
+    worlds = wl.make_worlds(5, [30])
+    boxes = worlds.world(0)
+    rng = np.random.default_rng(3)
+    q0 = rng.uniform(-1, 1, 7)
+    goal = np.array([[0.3, 0.2, 0.4, 1, 0, 0, 0]], dtype=float)
+    d, s = ref.Ref(robot), ref.Ref(robot, swept=1, sweep_steps=4)
+    still = np.tile(q0, (6, 1))
+    for q in (still, q0[None, :] + 0.3):
+        cd, gd, mcd, _ = d.traj_cost(boxes, q0, goal, q)
+        cs, gs, mcs, _ = s.traj_cost(boxes, q0, goal, q)
+        assert cs == cd and np.array_equal(gs, gd) and mcs == mcd
+
+
+def test_swept_bounds_and_monotone_in_steps(oracle_lib):
+    """Each trace sample adds a non-negative term: the swept cost is at least
+    the discrete one and does not decrease with more samples; a trajectory far
+    from every cuboid costs nothing either way."""
+    robot = wl.make_arm(seed=0, n_spheres=20)
+    worlds = wl.make_worlds(5, [30])
+    boxes = worlds.world(0)
+    batch = wl.make_batch(robot, 17, [6], [12], [0], noise=0.2)
+    q0, goal = batch.q_start[0], batch.goal[0]
+    qs = batch.x0.reshape(6, 12, 7)
+    gained = 0
+    for q in qs:
+        costs = [ref.Ref(robot, swept=1, sweep_steps=k).traj_cost(boxes, q0, goal, q, grad=False)[3][2]
+                 for k in (0, 1, 2, 4, 8)]
+        assert all(b >= a for a, b in zip(costs, costs[1:]))
+        disc = ref.Ref(robot).traj_cost(boxes, q0, goal, q, grad=False)[3][2]
+        assert costs[0] == disc
+        gained += costs[-1] > disc
+    assert gained > 0
+    far = (worlds.pose[:3] + np.array([20.0, 0, 0, 0, 0, 0, 0]), worlds.dims[:3])
+    assert ref.Ref(robot, swept=1, sweep_steps=8).traj_cost(far, q0, goal, qs[0], grad=False)[3][2] == 0.0
+
+
+# --------------------------------------------------------------------------
+# P9 particle-based optimization, Alg.5 / Eq.(12)-(13)
+
+def test_particle_weights_are_the_exponential_utility_softmax(oracle_lib):
+    from scipy.special import softmax
+    rng = np.random.default_rng(4)
+    N, n = 64, 10
+    cost = rng.uniform(100, 200, N)
+    theta = rng.normal(0, 1, (N, n))
+    mu, var = rng.normal(0, 1, n), rng.uniform(0.1, 0.2, n)
+    for beta in (5.0, 30.0):
+        _, _, w = ref.particle_update(cost, theta, mu, var, beta=beta)
+        np.testing.assert_allclose(w, softmax(-cost / beta), rtol=1e-12)
+    # adaptive temperature 0.1 x range: invariant to shifting and scaling the costs
+    m1, v1, _ = ref.particle_update(cost, theta, mu, var)
+    m2, v2, _ = ref.particle_update(cost + 123.0, theta, mu, var)
+    m3, v3, _ = ref.particle_update(7.0 * cost, theta, mu, var)
+    np.testing.assert_allclose(m2, m1, rtol=1e-12); np.testing.assert_allclose(m3, m1, rtol=1e-12)
+    np.testing.assert_allclose(v2, v1, rtol=1e-12); np.testing.assert_allclose(v3, v1, rtol=1e-12)
+
+
+def test_particle_update_special_cases(oracle_lib):
+    rng = np.random.default_rng(5)
+    N, n, km, ks = 32, 12, 0.9, 0.5
+    theta = rng.normal(0, 1, (N, n))
+    mu, var = rng.normal(0, 1, n), rng.uniform(0.1, 0.2, n)
+    # equal costs: uniform weights, the plain sample mean and mean square deviation
+    m, v, w = ref.particle_update(np.full(N, 3.0), theta, mu, var, k_mu=km, k_sigma=ks)
+    np.testing.assert_allclose(w, 1.0 / N, rtol=1e-12)
+    np.testing.assert_allclose(m, (1 - km) * mu + km * theta.mean(axis=0), rtol=1e-12)
+    np.testing.assert_allclose(v, (1 - ks) * var + ks * ((theta - mu) ** 2).mean(axis=0), rtol=1e-12)
+    # one particle far cheaper than the rest: it takes all the weight
+    cost = np.full(N, 1e6); cost[7] = 0.0
+    m, v, _ = ref.particle_update(cost, theta, mu, var, beta=1.0, k_mu=km, k_sigma=ks)
+    np.testing.assert_allclose(m, (1 - km) * mu + km * theta[7], rtol=1e-12)
+    np.testing.assert_allclose(v, (1 - ks) * var + ks * (theta[7] - mu) ** 2, rtol=1e-12)
+    # every particle at the same point c: the weights sum to one whatever the costs
+    c = rng.normal(0, 1, n)
+    m, _, _ = ref.particle_update(rng.uniform(0, 9, N), np.tile(c, (N, 1)), mu, var, k_mu=km)
+    np.testing.assert_allclose(m, (1 - km) * mu + km * c, rtol=1e-12)
+
+
+def test_particle_stage_samples_and_costs(oracle_lib):
+    """Particles are clip(mu + sqrt(var) eps), costed by the trajectory cost;
+    zero noise leaves the mean in place and shrinks the variance."""
+    robot = wl.make_arm(seed=0, n_spheres=20)
+    worlds = wl.make_worlds(5, [30])
+    boxes = worlds.world(0)
+    batch = wl.make_batch(robot, 23, [3], [8], [0])
+    q0, goal = batch.q_start[0], batch.goal[0]
+    S, T, D, N, it = 3, 8, 7, 5, 1
+    mu = batch.x0.reshape(S, T, D)
+    var = np.full_like(mu, 0.6 ** 2)     # wide enough that some samples clip
+    rng = np.random.default_rng(6)
+    eps = rng.normal(0, 1, (it, N, S, T, D))
+    r = ref.Ref(robot)
+    m1, v1, costs = r.particles(boxes, q0, goal, T, mu, var, eps)
+    clipped = 0
+    for s in range(S):
+        th = np.clip(mu[s] + 0.6 * eps[0, :, s], robot.q_lo, robot.q_hi)
+        clipped += np.count_nonzero(th != mu[s] + 0.6 * eps[0, :, s])
+        for i in range(N):
+            assert costs[0, s, i] == pytest.approx(r.traj_cost(boxes, q0, goal, th[i], grad=False)[0], rel=1e-12)
+        me, ve, _ = ref.particle_update(costs[0, s], th.reshape(N, -1), mu[s].reshape(-1), var[s].reshape(-1))
+        np.testing.assert_allclose(m1[s].reshape(-1), me, rtol=1e-12)
+        np.testing.assert_allclose(v1[s].reshape(-1), ve, rtol=1e-12)
+    assert clipped > 0
+    m0, v0, _ = r.particles(boxes, q0, goal, T, mu, var, np.zeros_like(eps))
+    np.testing.assert_allclose(m0, mu, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(v0, 0.5 * var, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
 # P6 L-BFGS two-loop = dense BFGS inverse-Hessian recursion
 
 def test_two_loop_equals_dense_bfgs(oracle_lib):

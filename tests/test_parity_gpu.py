@@ -63,6 +63,11 @@ def make_case(kind, **kw):
         worlds = wl.make_worlds(9, counts)
         batch = wl.make_batch(robot, 7, seeds, horizon, np.arange(P))
         return Case(robot, worlds, batch, **kw)
+    if kind == "tree":
+        robot = wl.make_two_arm(seed=0, n_spheres=60)
+        worlds = wl.make_worlds(6, [80])
+        batch = wl.make_batch(robot, 61, [3], [20], [0])
+        return Case(robot, worlds, batch, **kw)
     raise ValueError(kind)
 
 
@@ -72,7 +77,7 @@ def gpu_cost_grad(case):
     return c.cpu().numpy(), g.cpu().numpy(), mc.cpu().numpy()
 
 
-@pytest.mark.parametrize("kind", ["plain", "adjoint_small", "ik", "uneven"])
+@pytest.mark.parametrize("kind", ["plain", "adjoint_small", "ik", "uneven", "tree"])
 def test_cost_grad_parity(kind):
     case = make_case(kind)
     c, g, mc = gpu_cost_grad(case)
@@ -96,6 +101,179 @@ def test_cost_grad_parity_with_collisions_and_limits():
     H.assert_cost_close(c, cr)
     H.assert_grad_close(g, gr, case.batch)
     H.assert_verdicts(mc, mcr)
+
+
+SWEPT = dict(swept=1, sweep_steps=4)
+
+
+@pytest.mark.parametrize("kind", ["adjoint_small", "uneven", "tree"])
+def test_swept_cost_grad_parity(kind):
+    """Continuous collision: trace samples toward both neighbouring waypoints
+    (the start before waypoint 1), horizons 2..64, worlds of 0..200 cuboids,
+    the two-arm tree."""
+    case = make_case(kind, params=SWEPT)
+    c, g, mc = gpu_cost_grad(case)
+    cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, case.robot.dof))
+    H.assert_cost_close(c, cr)
+    H.assert_grad_close(g, gr, case.batch)
+    H.assert_verdicts(mc, mcr)
+    # the trace adds cost somewhere in these workloads
+    cd, _, _ = H.oracle_cost_grad(ref.Ref(case.robot), case.worlds, case.batch,
+                                  case.batch.x0.reshape(-1, case.robot.dof), grad=False)
+    assert np.all(cr >= cd) and np.any(cr > cd)
+
+
+def test_swept_tunnelling_example_on_gpu():
+    """The thin-wall example worked by hand in the reference's pins: both
+    waypoints clear of the wall, the segment through it; swept cost 0.136
+    against 0.001 discrete (unit collision weight, other terms off)."""
+    from tests.test_oracle_pins import COLLISION_ONLY, one_link_robot
+    robot = one_link_robot()
+    phi = math.asin(0.09)
+    worlds = wl.Worlds(offsets=np.array([0, 1], np.int32),
+                       pose=np.array([[math.cos(phi), 0.0, 0.0, 1.0, 0.0, 0.0, 0.0]]),
+                       dims=np.array([[1.0, 0.04, 1.0]]))
+    batch = wl.Batch(seeds=np.array([1], np.int32), horizon=np.array([2], np.int32),
+                     world=np.array([0], np.int32), q_start=np.array([[-phi]]),
+                     goal=np.array([[[0, 0, 0, 1, 0, 0, 0]]], dtype=float), x0=np.array([-phi, phi]))
+    case = Case(robot, worlds, batch, params=dict(COLLISION_ONLY, **SWEPT))
+    c, g, mc = gpu_cost_grad(case)
+    assert c[0] == pytest.approx(0.136, rel=1e-4)
+    assert mc[0] == pytest.approx(0.02, rel=1e-4)
+    cd = Case(robot, worlds, batch, params=COLLISION_ONLY)
+    assert gpu_cost_grad(cd)[0][0] == pytest.approx(0.001, rel=1e-4)
+
+
+def test_large_tree_swept_linesearch_sampled():
+    """Two-arm tree (14 joints, 120 spheres) against 500 cuboids with swept
+    collision, 128 seeds x 48 waypoints x 4 candidates in one line-search
+    launch; sampled seeds checked one by one at the chosen candidate."""
+    robot, worlds, batch, meta = wl.cfg_large()
+    case = Case(robot, worlds, batch, params=SWEPT)
+    D, S, T = robot.dof, 128, 48
+    rng = np.random.default_rng(1)
+    d = rng.normal(0, 0.03, case.batch.x0.shape).astype(np.float32).astype(np.float64)
+    dd = _dev(d.reshape(-1, D))
+    c0, g0, _ = case.ctx.mg_cost_grad(case.b, case.q_start, case.goal, case.x)
+    alpha = meta["alpha"]
+    xo, co, go, ch, mco = case.ctx.mg_linesearch(case.b, case.q_start, case.goal, case.x, c0, g0, dd, alpha, mode=0)
+    torch.cuda.synchronize()
+    ch, co, go = ch.cpu().numpy(), co.cpu().numpy(), go.cpu().numpy().reshape(S, T, D)
+    x = case.batch.x0.reshape(S, T, D)
+    dv = d.reshape(S, T, D)
+    boxes = case.worlds.world(0)
+    for s in rng.choice(S, 3, replace=False):
+        k = int(ch[s])
+        xk = np.clip(x[s] + alpha[k] * dv[s], case.robot.q_lo, case.robot.q_hi)
+        cr, gr, _, _ = case.ref.traj_cost(boxes, case.batch.q_start[0], case.batch.goal[0], xk)
+        H.assert_cost_close([co[s]], [cr])
+        assert np.linalg.norm(go[s] - gr) <= H.GRAD_RTOL * np.linalg.norm(gr) + H.ABS_TOL
+
+
+def _particle_round_reference(case, mean, var, eps_round, costs_gpu, boxes, p=0):
+    """Reference checks of one particle round of problem p from the same
+    inputs: every particle's cost, and the update fed the GPU's costs.
+    mean, var [S, T, D]; eps_round [N, S, T, D]; costs_gpu [S, N]."""
+    S, T, D = mean.shape
+    N = eps_round.shape[0]
+    out_m, out_v = np.empty_like(mean), np.empty_like(var)
+    lo, hi = case.robot.q_lo, case.robot.q_hi
+    for s in range(S):
+        th = np.clip(mean[s] + np.sqrt(var[s]) * eps_round[:, s], lo, hi)
+        cr = np.array([case.ref.traj_cost(boxes, case.batch.q_start[p], case.batch.goal[p], th[i], grad=False)[0]
+                       for i in range(N)])
+        H.assert_cost_close(costs_gpu[s], cr, f"particle costs of seed {s}")
+        m, v, _ = ref.particle_update(costs_gpu[s], th.reshape(N, -1), mean[s].reshape(-1), var[s].reshape(-1))
+        out_m[s], out_v[s] = m.reshape(T, D), v.reshape(T, D)
+    return out_m, out_v
+
+
+def test_particle_stage_parity():
+    """Two rounds of 64 particles per seed (Alg.5): each round's particle
+    costs against the reference's, and the mean / variance update against
+    the reference update fed the GPU's costs (fp32 sums of 64 terms)."""
+    case = make_case("adjoint_small")
+    S, T, D, N = 5, 32, 7, 64
+    rng = np.random.default_rng(12)
+    eps = rng.normal(0, 1, (2, N, S * T, D)).astype(np.float32).astype(np.float64)
+    case.b.mg_batch_reserve_particles(N)
+    mean = case.x.clone()
+    var = torch.full_like(mean, 0.05 ** 2)
+    boxes = case.worlds.world(0)
+    for it in range(2):
+        m_in = mean.double().cpu().numpy().reshape(S, T, D)
+        v_in = var.double().cpu().numpy().reshape(S, T, D)
+        _, _, costs = case.ctx.mg_particles(case.b, case.q_start, case.goal, mean, var,
+                                            _dev(eps[it:it + 1]), costs=True)
+        torch.cuda.synchronize()
+        m_ref, v_ref = _particle_round_reference(case, m_in, v_in, eps[it].reshape(N, S, T, D),
+                                                 costs.cpu().numpy()[0], boxes)
+        np.testing.assert_allclose(mean.cpu().numpy().reshape(S, T, D), m_ref, rtol=0, atol=5e-6)
+        np.testing.assert_allclose(var.cpu().numpy().reshape(S, T, D), v_ref, rtol=2e-4, atol=1e-9)
+    # one call of two rounds is the same computation
+    mean2 = case.x.clone()
+    var2 = torch.full_like(mean2, 0.05 ** 2)
+    case.ctx.mg_particles(case.b, case.q_start, case.goal, mean2, var2, _dev(eps))
+    torch.cuda.synchronize()
+    assert torch.equal(mean2, mean) and torch.equal(var2, var)
+
+
+def test_particle_stage_end_to_end_against_reference():
+    """The whole two-round stage against the reference's own stage: the means
+    agree to a small fraction of the distance they moved."""
+    case = make_case("plain")
+    S, T, D, N = 4, 32, 7, 128
+    rng = np.random.default_rng(13)
+    eps = rng.normal(0, 1, (2, N, S * T, D)).astype(np.float32).astype(np.float64)
+    case.b.mg_batch_reserve_particles(N)
+    mean = case.x.clone()
+    var = torch.full_like(mean, 0.05 ** 2)
+    case.ctx.mg_particles(case.b, case.q_start, case.goal, mean, var, _dev(eps))
+    torch.cuda.synchronize()
+    x0 = case.batch.x0.reshape(S, T, D)
+    m_ref, v_ref, _ = case.ref.particles(case.worlds.world(0), case.batch.q_start[0], case.batch.goal[0], T,
+                                         x0, np.full_like(x0, np.float32(0.05 ** 2)),
+                                         eps.reshape(2, N, S, T, D))
+    mg = mean.cpu().numpy().reshape(S, T, D)
+    for s in range(S):
+        moved = np.abs(m_ref[s] - x0[s]).max()
+        assert moved > 1e-3
+        assert np.abs(mg[s] - m_ref[s]).max() <= 1e-2 * moved + 1e-5, s
+
+
+def test_large_tree_swept_particle_stage_sampled():
+    """Particle stage at full size: two-arm tree, 128 seeds x 48 waypoints,
+    256 particles, 2 rounds, 500 cuboids, swept collision.  Sampled particle
+    costs against the reference, the update of sampled seeds against the
+    reference update fed the GPU's costs."""
+    robot, worlds, batch, meta = wl.cfg_large()
+    case = Case(robot, worlds, batch, params=SWEPT)
+    S, T, D, N = 128, 48, robot.dof, 256
+    rng = np.random.default_rng(14)
+    eps = rng.normal(0, 1, (1, N, S * T, D)).astype(np.float32)
+    case.b.mg_batch_reserve_particles(N)
+    mean = case.x.clone()
+    var = torch.full_like(mean, 0.05 ** 2)
+    _, _, costs = case.ctx.mg_particles(case.b, case.q_start, case.goal, mean, var,
+                                        torch.from_numpy(eps).cuda(), costs=True)
+    torch.cuda.synchronize()
+    costs = costs.cpu().numpy()[0]
+    x0 = case.batch.x0.reshape(S, T, D)
+    e = eps[0].astype(np.float64).reshape(N, S, T, D)
+    sd = np.sqrt(np.float64(np.float32(0.05 ** 2)))
+    boxes = case.worlds.world(0)
+    for s, i in zip(rng.choice(S, 4, replace=False), rng.choice(N, 4, replace=False)):
+        th = np.clip(x0[s] + sd * e[i, s], robot.q_lo, robot.q_hi)
+        cr = case.ref.traj_cost(boxes, case.batch.q_start[0], case.batch.goal[0], th, grad=False)[0]
+        H.assert_cost_close([costs[s, i]], [cr], f"particle {i} of seed {s}")
+    mg = mean.cpu().numpy().reshape(S, T, D)
+    vg = var.cpu().numpy().reshape(S, T, D)
+    for s in rng.choice(S, 2, replace=False):
+        th = np.clip(x0[s] + sd * e[:, s], robot.q_lo, robot.q_hi)
+        m, v, _ = ref.particle_update(costs[s], th.reshape(N, -1), x0[s].reshape(-1),
+                                      np.full(T * D, sd * sd))
+        np.testing.assert_allclose(mg[s].reshape(-1), m, rtol=0, atol=5e-6)
+        np.testing.assert_allclose(vg[s].reshape(-1), v, rtol=2e-4, atol=1e-9)
 
 
 def test_cost_only_matches_cost_grad():
