@@ -55,6 +55,8 @@ def main():
                          "line searches of the benchmark shape (one evaluation launch each), "
                          "'copy' copies 256 MiB five times (HBM byte-counter calibration)")
     ap.add_argument("--launches", type=int, default=10)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the uneven-batch and inverse-kinematics measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
@@ -88,8 +90,13 @@ def main():
             torch.empty(b.P, dtype=torch.int32, device=dev),
             torch.empty(b.P, dtype=torch.int32, device=dev))
 
+    # launch-shape autotuner: fastest cuboid-slice layout for this batch
+    c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
+    dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
+    slices = ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha)
+
     if args.profile == "eval":
-        return profile_eval(ctx, b, q_start, goal, x0, alpha, args.launches)
+        return profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, args.launches)
 
     def solve(use_graph):
         x.copy_(x0)
@@ -125,8 +132,6 @@ def main():
     # evaluation kernel time: HIP events on the launch stream around 30
     # back-to-back launches of the solve's evaluation kernel and grid
     # (32 seeds x 32 waypoints x 8 candidates, cost + adjoint)
-    c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
-    dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
     n_ev = 30
     ctx.mg_time_eval(b, q_start, goal, x0, dvec, alpha, launches=3)
     eval_us = ctx.mg_time_eval(b, q_start, goal, x0, dvec, alpha, launches=n_ev)
@@ -162,11 +167,15 @@ def main():
         "best_cost_min": float(best.min()),
         "roofline": {"bound": "alu", "kernel": "eval_kernel (cost + adjoint, 8 candidates)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(slices),
                      "eval_kernel_us": eval_us, "eval_launches_timed": n_ev,
+                     "cuboid_slices": slices,
                      "flop_per_eval": fl, "evals_per_launch": S * T * K},
     }
 
+    if not args.no_extra:
+        line["uneven"] = bench_uneven(args.warmup)
+        line["ik"] = bench_ik(args.warmup)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(robot, worlds, batch, alpha, iters, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -174,7 +183,7 @@ def main():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_kernel_cost_adjoint_32x32x8_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2310_17274_amd", "csrc", f)
-                  for f in ("mg_eval.h", "mg_device.h", "mg_internal.h")]
+                  for f in ("mg_eval.h", "mg_eval_wl.h", "mg_device.h", "mg_internal.h")]
 
 
 def kernel_digest():
@@ -186,10 +195,11 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(slices):
     """HBM bytes per evaluation launch from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary, or None when the kernel sources changed since
-    the counters were taken (or no summary exists)."""
+    WRITE_SIZE counter summary, or None when the kernel sources or the
+    launch layout changed since the counters were taken (or no summary
+    exists)."""
     try:
         with open(TRAFFIC_FILE) as fh:
             fields = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
@@ -197,14 +207,133 @@ def measured_traffic():
         return None
     if fields.get("source_digest", "").strip() != kernel_digest():
         return None
+    if int(fields.get("cuboid_slices", "0")) != slices:
+        return None
     return float(fields["hbm_bytes_per_launch"])
 
 
-def profile_eval(ctx, b, q_start, goal, x0, alpha, launches):
-    """Evaluation launches of the benchmark shape for hardware-counter runs."""
+def _inputs(robot, batch, dev):
     import torch
+    D = robot.dof
+    q_start = torch.as_tensor(batch.q_start, dtype=torch.float32, device=dev).contiguous()
+    goal = torch.as_tensor(batch.goal.reshape(batch.n_problems, -1), dtype=torch.float32, device=dev).contiguous()
+    x0 = torch.as_tensor(batch.x0.reshape(-1, D), dtype=torch.float32, device=dev).contiguous()
+    return q_start, goal, x0
+
+
+def _time_solves(ctx, b, q_start, goal, x0, iters, alpha, use_graph, reps, warmup):
+    """Mean ms per call of mg_solve over `reps` calls (HIP events on the
+    current stream), and the last call's outputs."""
+    import torch
+    x = x0.clone()
+    dev = x0.device
+    outs = (torch.empty(b.n_seeds, dtype=torch.float32, device=dev),
+            torch.empty(b.P, dtype=torch.int32, device=dev),
+            torch.empty(b.P, dtype=torch.int32, device=dev))
+
+    def run():
+        x.copy_(x0)
+        ctx.mg_solve(b, q_start, goal, x, iters, 4, alpha, mode=1, graph_inner=25,
+                     use_graph=use_graph, outputs=outs)
+    for _ in range(warmup):
+        run()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, outs
+
+
+def bench_uneven(warmup):
+    """64 problems of uneven size (seeds U{4..64}, T in {24,32,48}, worlds of
+    U{5..200} cuboids, K = 4): one batched graph solve of all problems against
+    64 sequential per-problem solves with direct launches."""
+    import torch
+    from paper_2310_17274_amd import workloads as wl
+    from paper_2310_17274_amd.binding import Context
+    robot, worlds, batch, meta = wl.cfg_uneven()
+    robot, worlds, batch = wl.robot_f32(robot), wl.worlds_f32(worlds), wl.to_f32(batch)
+    dev = torch.device("cuda:0")
+    ctx = Context(robot)
+    ctx.mg_set_worlds(worlds)
+    alpha, iters, P, D = meta["alpha"], meta["iters"], batch.n_problems, robot.dof
+    b = ctx.batch(batch.seeds, batch.horizon, batch.world, K_max=len(alpha), m_max=4)
+    q_start, goal, x0 = _inputs(robot, batch, dev)
     c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
+    slices = ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha)
+    ms_b, _ = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, True, 3, max(1, warmup))
+    # plain: one batch per problem, every kernel launched directly
+    singles, r0 = [], 0
+    for p in range(P):
+        n = int(batch.seeds[p]) * int(batch.horizon[p])
+        bp = ctx.batch([batch.seeds[p]], [batch.horizon[p]], [batch.world[p]], K_max=len(alpha), m_max=4)
+        outs = (torch.empty(bp.n_seeds, dtype=torch.float32, device=dev),
+                torch.empty(1, dtype=torch.int32, device=dev), torch.empty(1, dtype=torch.int32, device=dev))
+        singles.append((bp, q_start[p:p + 1].contiguous(), goal[p:p + 1].contiguous(),
+                        x0[r0:r0 + n].clone(), outs))
+        r0 += n
+    xs = [s[3].clone() for s in singles]
+
+    def plain():
+        for (bp, qs, gl, xp, outs), x in zip(singles, xs):
+            x.copy_(xp)
+            ctx.mg_solve(bp, qs, gl, x, iters, 4, alpha, mode=1, use_graph=False, outputs=outs)
+    plain()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(torch.cuda.current_stream())
+    plain()
+    e1.record(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    ms_p = e0.elapsed_time(e1)
+    evals = int(np.sum(batch.seeds * batch.horizon)) * len(alpha) * iters
+    return {"workload": f"{P} problems, seeds U{{4..64}} (total {int(batch.seeds.sum())}), T in {{24,32,48}}, "
+                        f"{int(worlds.offsets[-1])} cuboids in {P} worlds, K={len(alpha)}, {iters} iterations",
+            "ms_per_solve_batched": ms_b / P, "ms_per_solve_plain": ms_p / P,
+            "speedup_batched_vs_plain": ms_p / ms_b, "evals_per_s_batched": evals / (ms_b * 1e-3),
+            "cuboid_slices": slices}
+
+
+def bench_ik(warmup):
+    """Collision-free inverse kinematics: 4096 goal poses x 32 seeds (T = 1),
+    40 oriented cuboids, K = 4, 100 iterations as graphs of 25."""
+    import torch
+    from paper_2310_17274_amd import workloads as wl
+    from paper_2310_17274_amd.binding import Context
+    robot, worlds, batch, meta = wl.cfg_ik()
+    robot, worlds, batch = wl.robot_f32(robot), wl.worlds_f32(worlds), wl.to_f32(batch)
+    dev = torch.device("cuda:0")
+    ctx = Context(robot)
+    ctx.mg_set_worlds(worlds)
+    alpha, iters, P = meta["alpha"], meta["iters"], batch.n_problems
+    b = ctx.batch(batch.seeds, batch.horizon, batch.world, K_max=len(alpha), m_max=4)
+    q_start, goal, x0 = _inputs(robot, batch, dev)
+    # reachable goals: end-effector poses of random configurations (the
+    # library's own forward kinematics)
+    qg = torch.as_tensor(wl.goal_configs(robot, 33, P), dtype=torch.float32, device=dev).contiguous()
+    goal = ctx.mg_ee_pose(qg).reshape(P, -1).contiguous()
+    c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
+    dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
+    slices = ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha)
+    ms, outs = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, True, 3, max(1, warmup))
+    ok = outs[2].float().mean().item()
+    return {"workload": f"{P} goals x {int(batch.seeds[0])} seeds, T=1, {int(worlds.offsets[-1])} oriented "
+                        f"cuboids, K={len(alpha)}, {iters} iterations (graphs of 25)",
+            "ik_per_s": P / (ms * 1e-3), "ms_per_batch": ms, "success_fraction": ok,
+            "evals_per_s": int(batch.seeds.sum()) * len(alpha) * iters / (ms * 1e-3),
+            "cuboid_slices": slices,
+            "note": "goals are end-effector poses of random configurations U(-2.5,2.5)^7 (reachable, "
+                    "not filtered for collisions); success = 5 mm / 0.05 rad and collision free"}
+
+
+def profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, launches):
+    """Evaluation launches of the benchmark shape for hardware-counter runs."""
+    import torch
     for _ in range(launches):
         ctx.mg_linesearch(b, q_start, goal, x0, c0, g0, dvec, alpha, 1)
     torch.cuda.synchronize()

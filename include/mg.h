@@ -177,6 +177,33 @@ mg_status mg_solve(mg_ctx *ctx, mg_batch *batch, const float *q_start, const flo
                    int graph_inner, int use_graph, float *best_cost, int *best_seed,
                    int *success, void *stream);
 
+/* Forward kinematics of the end effectors (Sec. "Robot Kinematics", Tab.6):
+ * pose (x, y, z, qw, qx, qy, qz; Shepperd's quaternion, sign unspecified)
+ * of every end effector at each of `rows` configurations.
+ *   q DEVICE [rows][D]; pose DEVICE [rows][n_ee][7].  Capturable. */
+mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *stream);
+
+/* Evaluation layouts.  Lane per link (layout 0): 8 or 16 lanes per
+ * evaluation, one per link, with the world's cuboids split over 1, 2 or 4
+ * waves ("slices").  Wave per link (layout 1): 64 evaluations per
+ * workgroup, one wave per link plus one for the joint terms, each wave
+ * skipping the cuboids that a ball around its link's spheres over all 64
+ * lanes cannot reach; needs at most 15 links and no swept collision.
+ * mg_batch_set_layout fixes a layout (-1: library default) and, for layout
+ * 0, a slice count (0: automatic).  Host-only; affects later calls.
+ *
+ * Autotuner for a batch's launch shape: times the line-search evaluation
+ * kernel for K candidates under every layout and slice count the library
+ * offers for this robot (mg_time_eval with `launches` launches each) and
+ * fixes the fastest for every later call on this batch.  *slices_out (may
+ * be NULL) receives the slice count, or 0 for the wave-per-link layout.
+ * Overwrites the batch's evaluation workspaces; not capturable.  Swept
+ * collision always uses the lane-per-link layout with one slice. */
+mg_status mg_batch_set_layout(mg_batch *batch, int layout, int slices);
+mg_status mg_autotune(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
+                      const float *x, const float *dir, int K, const float *alpha, int launches,
+                      int *slices_out, void *stream);
+
 /* Particle-based optimization (Sec. "Particle-Based Optimization", Alg.5,
  * Eq.(12)-(13)), run before L-BFGS to move the seeds to a good region.
  * mg_batch_reserve_particles allocates the per-row particle costs for up to

@@ -24,7 +24,7 @@ EXPORTS = ("mg_default_params", "mg_create", "mg_destroy", "mg_set_params", "mg_
            "mg_batch_create", "mg_batch_destroy", "mg_batch_seeds", "mg_batch_rows",
            "mg_cost_grad", "mg_lbfgs_step", "mg_linesearch", "mg_solve",
            "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
-           "mg_time_eval", "mg_last_error")
+           "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose", "mg_last_error")
 
 
 class RobotDesc(C.Structure):
@@ -84,13 +84,17 @@ def lib():
     L.mg_set_timing.argtypes = [_vp, C.c_int]
     L.mg_time_eval.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _fp, C.c_int,
                                C.POINTER(C.c_float), _vp]
+    L.mg_batch_set_layout.argtypes = [_vp, C.c_int, C.c_int]
+    L.mg_ee_pose.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
+    L.mg_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _fp, C.c_int,
+                              C.POINTER(C.c_int), _vp]
     L.mg_eval_time.argtypes = [_vp, C.POINTER(C.c_float), C.POINTER(C.c_int)]
     L.mg_last_error.argtypes = []
     L.mg_last_error.restype = C.c_char_p
     for name in ("mg_create", "mg_set_params", "mg_set_worlds", "mg_batch_create", "mg_cost_grad",
                  "mg_lbfgs_step", "mg_linesearch", "mg_solve", "mg_batch_seeds", "mg_batch_rows",
                  "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
-                 "mg_time_eval"):
+                 "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose"):
         getattr(L, name).restype = C.c_int
     _LIB = L
     return L

@@ -68,6 +68,11 @@ class Batch:
         assert self.n_seeds == _lib.lib().mg_batch_seeds(h)
         assert self.rows == _lib.lib().mg_batch_rows(h)
 
+    def mg_batch_set_layout(self, layout: int, slices: int = 0):
+        """Fix the evaluation layout (-1 default, 0 lane per link, 1 wave per
+        link) and, for layout 0, the cuboid slices (0 automatic, 1, 2, 4)."""
+        _lib.check(_lib.lib().mg_batch_set_layout(self.handle, int(layout), int(slices)))
+
     def mg_batch_reserve_particles(self, n_particles: int):
         _lib.check(_lib.lib().mg_batch_reserve_particles(self.handle, int(n_particles)))
 
@@ -193,6 +198,13 @@ class Context:
                                   int(bool(use_graph)), _ptr(bc), _ptr(bs), _ptr(ok), _stream()))
         return x, bc, bs, ok
 
+    def mg_ee_pose(self, q):
+        """End-effector poses [rows, n_ee, 7] (xyz + wxyz) of configurations q [rows, D]."""
+        rows = int(q.shape[0])
+        out = torch.empty((rows, self.robot.n_ee, 7), dtype=torch.float32, device=self.device)
+        check(_lib.lib().mg_ee_pose(self.handle, rows, _ptr(q), _ptr(out), _stream()))
+        return out
+
     def mg_time_eval(self, b: Batch, q_start, goal, x, d, alpha, launches=30):
         """Mean microseconds per line-search evaluation launch, timed with
         HIP events around `launches` back-to-back launches."""
@@ -201,6 +213,14 @@ class Context:
         check(_lib.lib().mg_time_eval(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(x), _ptr(d),
                                       len(alpha), al, int(launches), C.byref(us), _stream()))
         return us.value
+
+    def mg_autotune(self, b: Batch, q_start, goal, x, d, alpha, launches=10):
+        """Fix the fastest cuboid-slice layout for this batch; returns it."""
+        al = (C.c_float * len(alpha))(*alpha)
+        h = C.c_int(0)
+        check(_lib.lib().mg_autotune(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(x), _ptr(d),
+                                     len(alpha), al, int(launches), C.byref(h), _stream()))
+        return h.value
 
     def mg_particles(self, b: Batch, q_start, goal, mean, var, eps, beta=0.0, k_mu=0.9,
                      k_sigma=0.5, costs=False):

@@ -82,6 +82,9 @@ struct mg_ctx {
   float* d_ee_tf = nullptr;
   int4* d_lane_info = nullptr;
   float4* d_lane_sphere = nullptr;
+  int4* d_wl_info = nullptr;     // wave-per-link tables
+  int* d_wl_chain = nullptr;
+  float4* d_wl_ball = nullptr;
   Box* d_box = nullptr;
   int box_cap = 0, n_boxes = 0;
   int* d_world_off = nullptr;
@@ -111,6 +114,10 @@ struct mg_batch {
   std::vector<hipEvent_t> ev_start, ev_stop;
   int ev_next = 0, ev_count = 0;
   int slices = -1;    // forced cuboid slices index (-1: automatic)
+  int layout = -1;    // evaluation layout: -1 automatic, 0 lane per link, 1 wave per link
+  // wave-per-link chunks of 64 evaluations, per candidate count K
+  int* d_chunk_wl[mg::kMaxK + 1] = {};
+  int chunks_wl[mg::kMaxK + 1] = {};
   // particle stage: per-row costs of every particle [p_cap][rows]
   float* p_cost = nullptr;
   int p_cap = 0;
@@ -161,8 +168,42 @@ mg_status build_lanes(mg_ctx* c) {
     sph[(size_t)l * maxs + fill[l]++] =
         make_float4(c->sphere[4 * m + 0], c->sphere[4 * m + 1], c->sphere[4 * m + 2], c->sphere[4 * m + 3]);
   }
+  // wave-per-link: chain of every link (root first) and a ball around its
+  // spheres in the link frame (centre of their bounding box, radius to the
+  // farthest sphere surface)
+  std::vector<int4> wl_info(c->L);
+  std::vector<int> wl_chain((size_t)c->L * mg::kMaxDof, 0);
+  std::vector<float4> wl_ball(c->L, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+  for (int l = 0; l < c->L; ++l) {
+    std::vector<int> ch;
+    for (int u = l; u >= 0; u = c->parent[u]) ch.push_back(u);
+    if ((int)ch.size() > mg::kMaxDof) return fail(MG_ERR_UNSUPPORTED, "chain of link %d deeper than %d", l, mg::kMaxDof);
+    for (size_t i = 0; i < ch.size(); ++i) wl_chain[(size_t)l * mg::kMaxDof + i] = ch[ch.size() - 1 - i];
+    int ee = -1;
+    for (int e = 0; e < c->n_ee; ++e)
+      if (c->ee_link[e] == l) ee = e;
+    wl_info[l] = make_int4((int)ch.size(), count[l], ee, 0);
+    if (count[l] == 0) continue;
+    float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
+    for (int s = 0; s < count[l]; ++s) {
+      const float4 q = sph[(size_t)l * maxs + s];
+      const float v[3] = {q.x, q.y, q.z};
+      for (int i = 0; i < 3; ++i) { lo[i] = std::min(lo[i], v[i]); hi[i] = std::max(hi[i], v[i]); }
+    }
+    const float ctr[3] = {0.5f * (lo[0] + hi[0]), 0.5f * (lo[1] + hi[1]), 0.5f * (lo[2] + hi[2])};
+    double rad = 0.0;
+    for (int s = 0; s < count[l]; ++s) {
+      const float4 q = sph[(size_t)l * maxs + s];
+      const double dx = q.x - ctr[0], dy = q.y - ctr[1], dz = q.z - ctr[2];
+      rad = std::max(rad, std::sqrt(dx * dx + dy * dy + dz * dz) + q.w);
+    }
+    wl_ball[l] = make_float4(ctr[0], ctr[1], ctr[2], (float)(rad * 1.0001 + 1e-6));
+  }
   mg_status st;
   if ((st = dev_upload(&c->d_lane_info, info)) != MG_OK) return st;
+  if ((st = dev_upload(&c->d_wl_info, wl_info)) != MG_OK) return st;
+  if ((st = dev_upload(&c->d_wl_chain, wl_chain)) != MG_OK) return st;
+  if ((st = dev_upload(&c->d_wl_ball, wl_ball)) != MG_OK) return st;
   return dev_upload(&c->d_lane_sphere, sph);
 }
 
@@ -173,6 +214,30 @@ mg::Lanes dev_lanes(const mg_ctx* c) {
   ln.info = c->d_lane_info;
   ln.sphere = c->d_lane_sphere;
   return ln;
+}
+
+mg::WaveLinks dev_wave_links(const mg_ctx* c) {
+  mg::WaveLinks wl;
+  wl.info = c->d_wl_info;
+  wl.chain = c->d_wl_chain;
+  wl.sphere = c->d_lane_sphere;
+  wl.ball = c->d_wl_ball;
+  wl.maxs = c->maxs;
+  return wl;
+}
+
+// The wave-per-link layout needs a workgroup of L + 1 waves and takes no
+// swept collision.
+bool wl_possible(const mg_ctx* c) { return c->L + 1 <= 16 && !c->params.swept; }
+
+// Layout of an evaluation launch with K candidates.
+bool use_wl(const mg_batch* b, int K) {
+  const mg_ctx* c = b->ctx;
+  if (!wl_possible(c) || K > b->K_max) return false;
+  if (b->layout >= 0) return b->layout == 1;
+  const char* env = getenv("MG_EVAL_LAYOUT");
+  if (env) return atoi(env) == 1;
+  return false;
 }
 
 mg::Params to_dev(const mg_params& p) {
@@ -220,6 +285,7 @@ mg::EvalArgs eval_args(const mg_ctx* c, const mg_batch* b, int hi, const float* 
   memset(&a, 0, sizeof(a));
   a.rb = dev_robot(c);
   a.ln = dev_lanes(c);
+  a.wl = dev_wave_links(c);
   a.pr = c->params;
   a.slices = kSlices[hi];
   a.prob = b->d_prob;
@@ -252,6 +318,16 @@ mg_status common_checks(mg_ctx* c, mg_batch* b) {
   return MG_OK;
 }
 
+// Launch an evaluation in the batch's layout: lane per link (cuboid slices
+// index hi) or wave per link.
+hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool grad, hipStream_t s) {
+  if (use_wl(b, a.K)) {
+    a.chunk_prefix = b->d_chunk_wl[a.K];
+    return mg::launch_eval_wl(a, b->chunks_wl[a.K], cand, grad, s);
+  }
+  return mg::launch_eval(a, b->chunks[hi], cand, grad, s);
+}
+
 mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
                        const float* x, const float* d, int K, const float* alpha, bool grad,
                        float* grad_out, float* pe_out, hipStream_t s) {
@@ -269,7 +345,7 @@ mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
     timed = cs == hipStreamCaptureStatusNone;
   }
   if (timed) HIP_TRY(hipEventRecord(b->ev_start[slot], s));
-  HIP_TRY(mg::launch_eval(a, b->chunks[hi], d != nullptr, grad, s));
+  HIP_TRY(launch_layout(b, a, hi, d != nullptr, grad, s));
   if (timed) {
     HIP_TRY(hipEventRecord(b->ev_stop[slot], s));
     b->ev_next = (slot + 1) % (int)b->ev_start.size();
@@ -423,6 +499,7 @@ void mg_destroy(mg_ctx* c) {
   (void)hipDeviceSynchronize();
   dev_free(c->d_fixed_tf); dev_free(c->d_joint); dev_free(c->d_q_lo); dev_free(c->d_q_hi); dev_free(c->d_ee_tf);
   dev_free(c->d_lane_info); dev_free(c->d_lane_sphere);
+  dev_free(c->d_wl_info); dev_free(c->d_wl_chain); dev_free(c->d_wl_ball);
   dev_free(c->d_box); dev_free(c->d_world_off);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
@@ -518,6 +595,12 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
     b->chunks[hi] = pre[P];
     if ((st = dev_upload(&b->d_chunk[hi], pre)) != MG_OK) return bail(st);
   }
+  for (int K = 1; K <= K_max; ++K) {
+    std::vector<int> pre(P + 1, 0);
+    for (int p = 0; p < P; ++p) pre[p + 1] = pre[p] + (seeds[p] * horizon[p] * K + mg::kWave - 1) / mg::kWave;
+    b->chunks_wl[K] = pre[P];
+    if ((st = dev_upload(&b->d_chunk_wl[K], pre)) != MG_OK) return bail(st);
+  }
   const size_t R = rows, RD = rows * c->D, KR = (size_t)K_max * rows, mm = std::max(m_max, 1);
   if ((st = dev_alloc(&b->cost_e, KR)) != MG_OK || (st = dev_alloc(&b->gd_e, KR)) != MG_OK ||
       (st = dev_alloc(&b->mc_e, KR)) != MG_OK || (st = dev_alloc(&b->grad_e, KR * c->D)) != MG_OK ||
@@ -546,6 +629,7 @@ void mg_batch_destroy(mg_batch* b) {
   for (auto e : b->ev_stop) (void)hipEventDestroy(e);
   dev_free(b->d_prob); dev_free(b->d_seed);
   for (auto& p : b->d_chunk) dev_free(p);
+  for (auto& p : b->d_chunk_wl) dev_free(p);
   dev_free(b->cost_e); dev_free(b->gd_e); dev_free(b->mc_e); dev_free(b->grad_e); dev_free(b->pe_e);
   dev_free(b->c_cur); dev_free(b->g_cur); dev_free(b->dir); dev_free(b->best_c); dev_free(b->best_x);
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
@@ -602,7 +686,7 @@ mg_status mg_time_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   hipError_t err = hipEventRecord(e0, s);
-  for (int i = 0; i < launches && err == hipSuccess; ++i) err = mg::launch_eval(a, b->chunks[hi], true, true, s);
+  for (int i = 0; i < launches && err == hipSuccess; ++i) err = launch_layout(b, a, hi, true, true, s);
   if (err == hipSuccess) err = hipEventRecord(e1, s);
   if (err == hipSuccess) err = hipEventSynchronize(e1);
   float ms = 0.0f;
@@ -649,6 +733,73 @@ mg_status mg_linesearch(mg_ctx* c, mg_batch* b, const float* q_start, const floa
   if ((st = enqueue_eval(c, b, q_start, goal, x, dir, K, alpha, true, nullptr, nullptr, s)) != MG_OK) return st;
   return enqueue_select(c, b, x, c0, g0, dir, K, alpha, mode, x_out, c_out, g_out, chosen, min_clear, false,
                         nullptr, s);
+}
+
+mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
+                      const float* x, const float* dir, int K, const float* alpha, int launches,
+                      int* slices_out, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if ((st = check_K_alpha(b, K, alpha)) != MG_OK) return st;
+  if (!q_start || !goal || !x || !dir) return fail(MG_ERR_ARG, "null argument");
+  if (launches < 1) return fail(MG_ERR_ARG, "launches must be >= 1");
+  // candidates: lane per link with 1, 2 or 4 cuboid slices, wave per link
+  int best = 0;
+  float best_us = 3.0e38f;
+  const int n_opt = kNumSlices + (wl_possible(c) ? 1 : 0);
+  for (int o = 0; o < n_opt; ++o) {
+    b->layout = o < kNumSlices ? 0 : 1;
+    b->slices = o < kNumSlices ? o : 0;
+    float us = 0.0f;
+    // one untimed launch per layout first (code upload, caches)
+    if ((st = mg_time_eval(c, b, q_start, goal, x, dir, K, alpha, 1, &us, stream)) != MG_OK ||
+        (st = mg_time_eval(c, b, q_start, goal, x, dir, K, alpha, launches, &us, stream)) != MG_OK) {
+      b->slices = -1;
+      b->layout = -1;
+      return st;
+    }
+    if (us < best_us) { best_us = us; best = o; }
+  }
+  b->layout = best < kNumSlices ? 0 : 1;
+  b->slices = best < kNumSlices ? best : -1;
+  if (slices_out) *slices_out = best < kNumSlices ? kSlices[best] : 0;
+  return MG_OK;
+}
+
+mg_status mg_ee_pose(mg_ctx* c, int rows, const float* q, float* pose, void* stream) {
+  if (!c) return fail(MG_ERR_ARG, "null context");
+  if (rows < 0) return fail(MG_ERR_ARG, "rows must be >= 0");
+  if (rows > 0 && (!q || !pose)) return fail(MG_ERR_ARG, "null q or pose");
+  mg::EePoseArgs a;
+  memset(&a, 0, sizeof(a));
+  a.rows = rows;
+  a.dof = c->D;
+  a.n_ee = c->n_ee;
+  for (int e = 0; e < c->n_ee; ++e) a.ee_link[e] = c->ee_link[e];
+  a.fixed_tf = c->d_fixed_tf;
+  a.ee_tf = c->d_ee_tf;
+  a.chain = c->d_wl_chain;
+  a.info = c->d_wl_info;
+  a.q = q;
+  a.pose = pose;
+  HIP_TRY(mg::launch_ee_pose(a, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+mg_status mg_batch_set_layout(mg_batch* b, int layout, int slices) {
+  if (!b) return fail(MG_ERR_ARG, "null batch");
+  if (layout < -1 || layout > 1) return fail(MG_ERR_ARG, "layout must be -1, 0 or 1");
+  if (layout == 1 && !wl_possible(b->ctx))
+    return fail(MG_ERR_UNSUPPORTED, "the wave-per-link layout needs at most 15 links and no swept collision");
+  int hi = -1;
+  if (slices != 0) {
+    for (int i = 0; i < kNumSlices; ++i)
+      if (kSlices[i] == slices) hi = i;
+    if (hi < 0) return fail(MG_ERR_ARG, "slices must be 0 (automatic), 1, 2 or 4");
+  }
+  b->layout = layout;
+  b->slices = hi;
+  return MG_OK;
 }
 
 mg_status mg_batch_reserve_particles(mg_batch* b, int n_particles) {
@@ -767,7 +918,8 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
     std::vector<char> key;
     key_push(key, q_start); key_push(key, goal); key_push(key, x); key_push(key, m); key_push(key, K);
     key_push(key, mode); key_push(key, graph_inner); key_push(key, c->params);
-    key_push(key, c->d_box); key_push(key, c->d_world_off);
+    key_push(key, c->d_box); key_push(key, c->d_world_off); key_push(key, b->slices);
+    key_push(key, b->layout);
     for (int k = 0; k < K; ++k) key_push(key, alpha[k]);
     if (!b->gexec || key != b->gkey) {
       if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }

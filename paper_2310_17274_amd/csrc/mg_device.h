@@ -16,6 +16,9 @@ namespace {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(4))) const v4f cv4f;
 typedef __attribute__((address_space(4))) const float cfloat;
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const v4i cv4i;
+typedef __attribute__((address_space(4))) const int cint;
 
 __device__ __forceinline__ float logcosh_f(float x) {
   const float ax = fabsf(x);

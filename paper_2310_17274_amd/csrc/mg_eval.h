@@ -45,6 +45,116 @@ __device__ __forceinline__ void suffix_step(float* W, bool active) {
   }
 }
 
+// Pose reaching cost (Eq.(14)) of end effector ee whose link pose is T
+// (3x4): position term a0 logcosh(a2 |p_g - p|), rotation term
+// a1 logcosh(a3 |q_g - s q|) with s the sign of <q_g, q>.  The gradient
+// enters as a wrench on the link: force d cost / d p at the tool point and
+// the moment conjugate to a world-frame rotation.  pe_row >= 0 (and ee 0)
+// records the position and angle errors of that row.
+__device__ __forceinline__ void pose_term(const EvalArgs& a, int p, int ee, const float* T, int pe_row,
+                                          float& cost, float& Fx, float& Fy, float& Fz, float& Mx,
+                                          float& My, float& Mz) {
+  float E[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) E[i] = T[i];
+  compose(E, a.rb.ee_tf + ee * 12);
+  float qw, qx, qy, qz;
+  mat_to_quat(E, qw, qx, qy, qz);
+  const float* gl = a.goal + ((size_t)p * a.rb.n_ee + ee) * 7;
+  const float px = E[3], py = E[7], pz = E[11];
+  const float ex = gl[0] - px, ey = gl[1] - py, ez = gl[2] - pz;
+  const float n = sqrtf(ex * ex + ey * ey + ez * ez);
+  cost += a.pr.a0 * logcosh_f(a.pr.a2 * n);
+  const float fp = -a.pr.a0 * a.pr.a2 * tanh_over(a.pr.a2, n);
+  const float gpx = fp * ex, gpy = fp * ey, gpz = fp * ez;     // d cost / d p
+  const float dot = gl[3] * qw + gl[4] * qx + gl[5] * qy + gl[6] * qz;
+  const float sg = dot >= 0.0f ? 1.0f : -1.0f;
+  const float e0 = gl[3] - sg * qw, e1 = gl[4] - sg * qx;
+  const float e2 = gl[5] - sg * qy, e3 = gl[6] - sg * qz;
+  const float dr = sqrtf(e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3);
+  cost += a.pr.a1 * logcosh_f(a.pr.a3 * dr);
+  // d cost / d quaternion, then the moment conjugate to a world-frame
+  // rotation omega: d quat = 1/2 (0, omega) (x) quat
+  const float fq = -sg * a.pr.a1 * a.pr.a3 * tanh_over(a.pr.a3, dr);
+  const float gw = fq * e0, gvx = fq * e1, gvy = fq * e2, gvz = fq * e3;
+  const float tx = 0.5f * (qw * gvx - gw * qx + (qy * gvz - qz * gvy));
+  const float ty = 0.5f * (qw * gvy - gw * qy + (qz * gvx - qx * gvz));
+  const float tz = 0.5f * (qw * gvz - gw * qz + (qx * gvy - qy * gvx));
+  Fx += gpx; Fy += gpy; Fz += gpz;
+  Mx += py * gpz - pz * gpy + tx;
+  My += pz * gpx - px * gpz + ty;
+  Mz += px * gpy - py * gpx + tz;
+  if (a.pe_e && pe_row >= 0 && ee == 0) {
+    a.pe_e[(size_t)pe_row * 2 + 0] = n;
+    a.pe_e[(size_t)pe_row * 2 + 1] = 2.0f * acosf(fminf(fabsf(dot), 1.0f));
+  }
+}
+
+// Joint j at waypoint row `row` (waypoint t+1 of its seed): joint-limit cost
+// (Eq.(17), weight w_bound, band eta2) and the smoothness terms of Eq.(16)
+// whose five-point stencils (centred at t-1..t+3 on the padded trajectory:
+// the start before waypoint 1, the last waypoint after T) touch this state.
+// jc receives the terms this waypoint owns, js d cost / d q_j.  qj is the
+// (candidate) value at row, qval(r, j) the value at another row.
+template <typename QV>
+__device__ __forceinline__ void joint_terms(const EvalArgs& a, const Problem& pb, int p, int row, int t,
+                                            int j, float qj, QV&& qval, float& jc, float& js) {
+  const float lo_ = a.rb.q_lo[j], hi_ = a.rb.q_hi[j], e2 = a.pr.eta2, wb = a.pr.w_bound;
+  const float inv_e2 = 1.0f / e2;
+  float bc = 0.0f, bs = 0.0f;
+  if (qj < lo_) { bc += lo_ - qj + 0.5f * e2; bs -= 1.0f; }
+  else if (qj < lo_ + e2) { const float u = lo_ - qj + e2; bc += 0.5f * u * u * inv_e2; bs -= u * inv_e2; }
+  if (qj > hi_) { bc += qj - hi_ + 0.5f * e2; bs += 1.0f; }
+  else if (qj > hi_ - e2) { const float u = qj - hi_ + e2; bc += 0.5f * u * u * inv_e2; bs += u * inv_e2; }
+  jc += wb * bc;
+  js += wb * bs;
+  if (pb.T <= 1) return;
+  // padded states X(s), s = w-4..w+4 around this waypoint w = t+1
+  const int D = a.rb.dof;
+  const int w1 = t + 1, Tn = pb.T;
+  const float q0 = a.q_start[(size_t)p * D + j];
+  float X[9];
+#pragma unroll
+  for (int u = 0; u < 9; ++u) {
+    const int sgi = w1 - 4 + u;
+    const int wv = sgi < 1 ? 1 : (sgi < Tn ? sgi : Tn);
+    const float v = u == 4 ? qj : qval(row - t + wv - 1, j);
+    X[u] = sgi <= 0 ? q0 : v;
+  }
+  const float h = a.pr.dt;
+  const float cv = 1.0f / (12.0f * h), ca = 1.0f / (12.0f * h * h), cj = 1.0f / (2.0f * h * h * h);
+  const float kv[5] = {1.0f, -8.0f, 0.0f, 8.0f, -1.0f};
+  const float ka[5] = {-1.0f, 16.0f, -30.0f, 16.0f, -1.0f};
+  const float kj[5] = {-1.0f, 2.0f, 0.0f, -2.0f, 1.0f};
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    const int tau = w1 - 2 + c;          // stencil centre, states X[c..c+4]
+    float v = 0.0f, ac = 0.0f, jk = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      v = fmaf(kv[i], X[c + i], v);
+      ac = fmaf(ka[i], X[c + i], ac);
+      jk = fmaf(kj[i], X[c + i], jk);
+    }
+    v *= cv; ac *= ca; jk *= cj;
+    const bool in = tau >= 0 && tau <= Tn;
+    const bool mine = in && (tau == w1 || (tau == 0 && w1 == 1));   // cost owner
+    const bool vel = in && (a.pr.vel_all || tau == Tn);
+    float gv = 0.0f;
+    if (vel) {   // transcendentals only where the velocity term applies
+      gv = a.pr.a6 * a.pr.a7 * tanhf(a.pr.a7 * v) * cv;
+      if (mine) jc += a.pr.a6 * logcosh_f(a.pr.a7 * v);
+    }
+    if (mine) jc += a.pr.a8 * ac * ac + a.pr.a9 * jk * jk;
+    const float ga = 2.0f * a.pr.a8 * ac * ca, gjk = 2.0f * a.pr.a9 * jk * cj;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const int s = tau - 2 + i;         // state touched by stencil entry i
+      if (in && s >= 1 && (s < Tn ? s : Tn) == w1) js += gv * kv[i] + ga * ka[i] + gjk * kj[i];
+    }
+  }
+}
+
 // Pose of this lane's link at its joint value q: the local transform
 // F_l Rz(q) from the Tab.6 closed form (columns 0 and 1 mix, 2 and 3 are
 // F's), then the prefix product along the chain (pos = lanes past the chain
@@ -202,109 +312,14 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
   float gsm = 0.0f;
   if (slice == 0) {
     // ---- pose reaching cost at the last waypoint (Eq.(14)) ----
-    if (li.w >= 0 && t == pb.T - 1) {
-      float E[12];
-#pragma unroll
-      for (int i = 0; i < 12; ++i) E[i] = T[i];
-      compose(E, a.rb.ee_tf + li.w * 12);
-      float qt[4];
-      mat_to_quat(E, qt[0], qt[1], qt[2], qt[3]);
-      const float* gl = a.goal + ((size_t)p * a.rb.n_ee + li.w) * 7;
-      const float px = E[3], py = E[7], pz = E[11];
-      const float ex = gl[0] - px, ey = gl[1] - py, ez = gl[2] - pz;
-      const float n = sqrtf(ex * ex + ey * ey + ez * ez);
-      cost += a.pr.a0 * logcosh_f(a.pr.a2 * n);
-      const float fp = -a.pr.a0 * a.pr.a2 * tanh_over(a.pr.a2, n);
-      const float gpx = fp * ex, gpy = fp * ey, gpz = fp * ez;     // d cost / d p
-      const float dot = gl[3] * qt[0] + gl[4] * qt[1] + gl[5] * qt[2] + gl[6] * qt[3];
-      const float sg = dot >= 0.0f ? 1.0f : -1.0f;
-      const float e0 = gl[3] - sg * qt[0], e1 = gl[4] - sg * qt[1];
-      const float e2 = gl[5] - sg * qt[2], e3 = gl[6] - sg * qt[3];
-      const float dr = sqrtf(e0 * e0 + e1 * e1 + e2 * e2 + e3 * e3);
-      cost += a.pr.a1 * logcosh_f(a.pr.a3 * dr);
-      // d cost / d quaternion, then the moment conjugate to a world-frame
-      // rotation omega: d quat = 1/2 (0, omega) (x) quat
-      const float fq = -sg * a.pr.a1 * a.pr.a3 * tanh_over(a.pr.a3, dr);
-      const float gw = fq * e0, gvx = fq * e1, gvy = fq * e2, gvz = fq * e3;
-      const float w = qt[0], vx = qt[1], vy = qt[2], vz = qt[3];
-      const float tx = 0.5f * (w * gvx - gw * vx + (vy * gvz - vz * gvy));
-      const float ty = 0.5f * (w * gvy - gw * vy + (vz * gvx - vx * gvz));
-      const float tz = 0.5f * (w * gvz - gw * vz + (vx * gvy - vy * gvx));
-      Fx += gpx; Fy += gpy; Fz += gpz;
-      Mx += py * gpz - pz * gpy + tx;
-      My += pz * gpx - px * gpz + ty;
-      Mz += px * gpy - py * gpx + tz;
-      if (a.pe_e && valid && li.w == 0) {
-        a.pe_e[(size_t)row * 2 + 0] = n;
-        a.pe_e[(size_t)row * 2 + 1] = 2.0f * acosf(fminf(fabsf(dot), 1.0f));
-      }
-    }
-
+    if (li.w >= 0 && t == pb.T - 1)
+      pose_term(a, p, li.w, T, valid ? row : -1, cost, Fx, Fy, Fz, Mx, My, Mz);
     // ---- joint l: limit cost (Eq.(17)) and smoothness (Eq.(16)); every lane
     //      computes (clamped joint), lanes l >= D discard the result ----
-    {
-      const bool own = l < D;
-      float jc = 0.0f;
-      const float xq = ql;
-      const float lo_ = a.rb.q_lo[lj], hi_ = a.rb.q_hi[lj], e2 = a.pr.eta2, wb = a.pr.w_bound;
-      const float inv_e2 = 1.0f / e2;
-      float bc = 0.0f, bs = 0.0f;
-      if (xq < lo_) { bc += lo_ - xq + 0.5f * e2; bs -= 1.0f; }
-      else if (xq < lo_ + e2) { const float u = lo_ - xq + e2; bc += 0.5f * u * u * inv_e2; bs -= u * inv_e2; }
-      if (xq > hi_) { bc += xq - hi_ + 0.5f * e2; bs += 1.0f; }
-      else if (xq > hi_ - e2) { const float u = xq - hi_ + e2; bc += 0.5f * u * u * inv_e2; bs += u * inv_e2; }
-      jc += wb * bc;
-      float js = wb * bs;
-
-      if (pb.T > 1) {
-        // padded states X(s), s = w-4..w+4 around this waypoint w = t+1:
-        // start for s <= 0, last waypoint for s >= T
-        const int w1 = t + 1, Tn = pb.T;
-        const float q0 = a.q_start[(size_t)p * D + lj];
-        float X[9];
-#pragma unroll
-        for (int u = 0; u < 9; ++u) {
-          const int sgi = w1 - 4 + u;
-          const int wv = sgi < 1 ? 1 : (sgi < Tn ? sgi : Tn);
-          const float v = u == 4 ? ql : qval(row - t + wv - 1, lj);
-          X[u] = sgi <= 0 ? q0 : v;
-        }
-        const float h = a.pr.dt;
-        const float cv = 1.0f / (12.0f * h), ca = 1.0f / (12.0f * h * h), cj = 1.0f / (2.0f * h * h * h);
-        const float kv[5] = {1.0f, -8.0f, 0.0f, 8.0f, -1.0f};
-        const float ka[5] = {-1.0f, 16.0f, -30.0f, 16.0f, -1.0f};
-        const float kj[5] = {-1.0f, 2.0f, 0.0f, -2.0f, 1.0f};
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          const int tau = w1 - 2 + c;          // stencil centre, states X[c..c+4]
-          float v = 0.0f, ac = 0.0f, jk = 0.0f;
-#pragma unroll
-          for (int i = 0; i < 5; ++i) {
-            v = fmaf(kv[i], X[c + i], v);
-            ac = fmaf(ka[i], X[c + i], ac);
-            jk = fmaf(kj[i], X[c + i], jk);
-          }
-          v *= cv; ac *= ca; jk *= cj;
-          const bool in = tau >= 0 && tau <= Tn;
-          const bool mine = in && (tau == w1 || (tau == 0 && w1 == 1));   // cost owner
-          const bool vel = in && (a.pr.vel_all || tau == Tn);
-          float gv = 0.0f;
-          if (vel) {   // transcendentals only where the velocity term applies
-            gv = a.pr.a6 * a.pr.a7 * tanhf(a.pr.a7 * v) * cv;
-            if (mine) jc += a.pr.a6 * logcosh_f(a.pr.a7 * v);
-          }
-          if (mine) jc += a.pr.a8 * ac * ac + a.pr.a9 * jk * jk;
-          const float ga = 2.0f * a.pr.a8 * ac * ca, gjk = 2.0f * a.pr.a9 * jk * cj;
-#pragma unroll
-          for (int i = 0; i < 5; ++i) {
-            const int s = tau - 2 + i;         // state touched by stencil entry i
-            if (in && s >= 1 && (s < Tn ? s : Tn) == w1) js += gv * kv[i] + ga * ka[i] + gjk * kj[i];
-          }
-        }
-      }
-      cost += own ? jc : 0.0f;
-      gsm = own ? js : 0.0f;
-    }
+    float jc = 0.0f, js = 0.0f;
+    joint_terms(a, pb, p, row, t, lj, ql, qval, jc, js);
+    cost += l < D ? jc : 0.0f;
+    gsm = l < D ? js : 0.0f;
   }
 
   // ---- world collision (Eq.(10)/(11) without the speed factor, summed over

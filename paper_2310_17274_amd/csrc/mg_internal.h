@@ -65,6 +65,17 @@ struct Lanes {
   const float4* sphere;    // [lpe][maxs] center in link frame + radius
 };
 
+// Wave-per-link layout of the evaluation kernel: a workgroup holds 64
+// evaluations; wave l owns link l (its kinematic chain, spheres and end
+// effector) for all 64, the last wave owns the joint terms.
+struct WaveLinks {
+  const int4* info;        // [L]: chain depth, spheres, end effector or -1, 0
+  const int* chain;        // [L][kMaxDof]: links from the root down to l
+  const float4* sphere;    // [L][maxs] centre in link frame + radius
+  const float4* ball;      // [L] ball bounding the link's spheres (link frame): centre, radius
+  int maxs;
+};
+
 // Cuboid in the library layout: p = A c + b maps a world point into the box
 // frame (A = R^T, b = -R^T t); h = half side lengths.
 //   q[0] = A00 A01 A02 b0, q[1] = A10 A11 A12 b1, q[2] = A20 A21 A22 b2, q[3] = h0 h1 h2 0
@@ -75,6 +86,7 @@ struct Box {
 struct EvalArgs {
   Robot rb;
   Lanes ln;
+  WaveLinks wl;
   Params pr;
   int slices;              // waves that split one evaluation group's cuboids: 1, 2 or 4
   const Problem* prob;     // [P]
@@ -164,6 +176,18 @@ struct ParticleArgs {
   float* costs_out;        // [n_seeds][N] or null
 };
 
+// End-effector poses of every row (forward kinematics only).
+struct EePoseArgs {
+  int rows, dof, n_ee;
+  int ee_link[kMaxEE];
+  const float* fixed_tf;   // [L][12]
+  const float* ee_tf;      // [n_ee][12]
+  const int* chain;        // [L][kMaxDof] links from the root down to l
+  const int4* info;        // [L]: chain depth, ...
+  const float* q;          // [rows][D]
+  float* pose;             // [rows][n_ee][7]
+};
+
 struct FinalArgs {
   const Problem* prob;
   int P, rows;
@@ -177,6 +201,9 @@ struct FinalArgs {
 
 // Launchers (mg_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s);
+// wave-per-link layout: grid_x workgroups of 64 evaluations (chunk_prefix
+// counts 64-evaluation chunks of rows x K per problem)
+hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 // fuse (optional): compute the next L-BFGS direction from the chosen iterate
 hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, hipStream_t s);
@@ -184,6 +211,7 @@ hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s);
 
 hipError_t launch_particle_update(const ParticleArgs& a, hipStream_t s);
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);
+hipError_t launch_ee_pose(const EePoseArgs& a, hipStream_t s);
 hipError_t launch_boxes(const float* pose, const float* dims, int n, Box* out, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);
 hipError_t launch_fill_i32(int* dst, int v, size_t n, hipStream_t s);

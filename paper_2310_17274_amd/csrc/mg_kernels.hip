@@ -102,53 +102,78 @@ __global__ __launch_bounds__(kBlock) void particle_update_kernel(const ParticleA
 }
 
 // --------------------------------------------------------------------------
-// L-BFGS direction (Alg.6) of one seed held by one wavefront.  The seed's
-// vectors (n = T*D <= 64*PL, lane-strided) are in registers; its history
-// (m <= MH pairs) is loaded into registers up front, then the two loops run
-// on registers and DPP sums.  Writes dir, the new history and x/g_prev.
+// L-BFGS state of one seed in registers: history (newest first), the
+// previous iterate and gradient.  Loaded before anything it does not depend
+// on is computed, so the loads' latency overlaps that work.
 template <int PL, int MH>
-__device__ __forceinline__ void lbfgs_seed(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
-                                           const float* xv, const float* gv) {
+struct LbfgsRegs {
+  int count, head;
+  bool reset;
+  float xp[PL], gp[PL];
+  float Sh[MH][PL], Yh[MH][PL], rh[MH];
+};
+
+template <int PL, int MH>
+__device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
+                                           LbfgsRegs<PL, MH>& h) {
   const int n = si.T * a.dof;
   const size_t base = (size_t)si.row0 * a.dof;
   const size_t stride = (size_t)a.rows * a.dof;
   const int m = a.m;
-
-  int count = a.meta[2 * s + 0], head = a.meta[2 * s + 1];
-  bool reset = a.reset != 0;
-  if (a.first && a.first[s]) reset = true;
-  if (reset) { count = 0; head = 0; }
-
-  float sv[PL], yv[PL];
-  float Sh[MH][PL], Yh[MH][PL], rh[MH];
+  h.count = a.meta[2 * s + 0];
+  h.head = a.meta[2 * s + 1];
+  h.reset = a.reset != 0 || (a.first && a.first[s]);
+  if (h.reset) { h.count = 0; h.head = 0; }
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     const int e = lane + u * kWave;
-    const bool in = e < n;
-    sv[u] = (in && !reset) ? xv[u] - a.x_prev[base + e] : 0.0f;
-    yv[u] = (in && !reset) ? gv[u] - a.g_prev[base + e] : 0.0f;
+    const bool in = e < n && !h.reset;
+    h.xp[u] = in ? a.x_prev[base + e] : 0.0f;
+    h.gp[u] = in ? a.g_prev[base + e] : 0.0f;
   }
   // history slot c (newest first) sits in ring index (head - 1 - c) mod m
 #pragma unroll
   for (int c = 0; c < MH; ++c) {
-    rh[c] = 0.0f;
+    h.rh[c] = 0.0f;
 #pragma unroll
-    for (int u = 0; u < PL; ++u) { Sh[c][u] = 0.0f; Yh[c][u] = 0.0f; }
-    if (c < count) {
-      const int i = ((head - 1 - c) % m + m) % m;
-      rh[c] = a.rho[(size_t)s * a.m_max + i];
+    for (int u = 0; u < PL; ++u) { h.Sh[c][u] = 0.0f; h.Yh[c][u] = 0.0f; }
+    if (c < h.count) {
+      const int i = ((h.head - 1 - c) % m + m) % m;
+      h.rh[c] = a.rho[(size_t)s * a.m_max + i];
 #pragma unroll
       for (int u = 0; u < PL; ++u) {
         const int e = lane + u * kWave;
         if (e < n) {
-          Sh[c][u] = a.S[(size_t)i * stride + base + e];
-          Yh[c][u] = a.Y[(size_t)i * stride + base + e];
+          h.Sh[c][u] = a.S[(size_t)i * stride + base + e];
+          h.Yh[c][u] = a.Y[(size_t)i * stride + base + e];
         }
       }
     }
   }
+}
+
+// L-BFGS direction (Alg.6) of one seed held by one wavefront, from its
+// state in registers and the new iterate xv and gradient gv (lane-strided,
+// n = T*D <= 64*PL): stores the last step's pair when its curvature passes
+// the guard, runs the two loops on registers and DPP sums, and writes dir,
+// the new history and x/g_prev.
+template <int PL, int MH>
+__device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
+                                             const float* xv, const float* gv, LbfgsRegs<PL, MH>& h) {
+  const int n = si.T * a.dof;
+  const size_t base = (size_t)si.row0 * a.dof;
+  const size_t stride = (size_t)a.rows * a.dof;
+  const int m = a.m;
+  int count = h.count, head = h.head;
+  float sv[PL], yv[PL];
+#pragma unroll
+  for (int u = 0; u < PL; ++u) {
+    const bool in = lane + u * kWave < n && !h.reset;
+    sv[u] = in ? xv[u] - h.xp[u] : 0.0f;
+    yv[u] = in ? gv[u] - h.gp[u] : 0.0f;
+  }
   // curvature pair of the last step
-  if (!reset && m > 0) {
+  if (!h.reset && m > 0) {
     float sy = 0.0f, ss = 0.0f, yy = 0.0f;
 #pragma unroll
     for (int u = 0; u < PL; ++u) {
@@ -170,13 +195,13 @@ __device__ __forceinline__ void lbfgs_seed(const LbfgsArgs& a, int s, int lane, 
       // shift the register copy: the new pair becomes slot 0
 #pragma unroll
       for (int c = MH - 1; c > 0; --c) {
-        rh[c] = rh[c - 1];
+        h.rh[c] = h.rh[c - 1];
 #pragma unroll
-        for (int u = 0; u < PL; ++u) { Sh[c][u] = Sh[c - 1][u]; Yh[c][u] = Yh[c - 1][u]; }
+        for (int u = 0; u < PL; ++u) { h.Sh[c][u] = h.Sh[c - 1][u]; h.Yh[c][u] = h.Yh[c - 1][u]; }
       }
-      rh[0] = 1.0f / sy;
+      h.rh[0] = 1.0f / sy;
 #pragma unroll
-      for (int u = 0; u < PL; ++u) { Sh[0][u] = sv[u]; Yh[0][u] = yv[u]; }
+      for (int u = 0; u < PL; ++u) { h.Sh[0][u] = sv[u]; h.Yh[0][u] = yv[u]; }
       head = (head + 1) % m;
       count = count < m ? count + 1 : m;
     }
@@ -192,18 +217,18 @@ __device__ __forceinline__ void lbfgs_seed(const LbfgsArgs& a, int s, int lane, 
     if (c < count) {
       float dsq = 0.0f;
 #pragma unroll
-      for (int u = 0; u < PL; ++u) dsq = fmaf(Sh[c][u], q[u], dsq);
-      const float ai = rh[c] * wave_sum(dsq);
+      for (int u = 0; u < PL; ++u) dsq = fmaf(h.Sh[c][u], q[u], dsq);
+      const float ai = h.rh[c] * wave_sum(dsq);
       al[c] = ai;
 #pragma unroll
-      for (int u = 0; u < PL; ++u) q[u] = fmaf(-ai, Yh[c][u], q[u]);
+      for (int u = 0; u < PL; ++u) q[u] = fmaf(-ai, h.Yh[c][u], q[u]);
     }
   }
   float gamma;
   if (count > 0) {
     float sy = 0.0f, yy = 0.0f;
 #pragma unroll
-    for (int u = 0; u < PL; ++u) { sy = fmaf(Sh[0][u], Yh[0][u], sy); yy = fmaf(Yh[0][u], Yh[0][u], yy); }
+    for (int u = 0; u < PL; ++u) { sy = fmaf(h.Sh[0][u], h.Yh[0][u], sy); yy = fmaf(h.Yh[0][u], h.Yh[0][u], yy); }
     gamma = wave_sum(sy) / wave_sum(yy);
   } else {
     float gi = 0.0f;
@@ -219,10 +244,10 @@ __device__ __forceinline__ void lbfgs_seed(const LbfgsArgs& a, int s, int lane, 
     if (c < count) {
       float dyr = 0.0f;
 #pragma unroll
-      for (int u = 0; u < PL; ++u) dyr = fmaf(Yh[c][u], q[u], dyr);
-      const float b = rh[c] * wave_sum(dyr);
+      for (int u = 0; u < PL; ++u) dyr = fmaf(h.Yh[c][u], q[u], dyr);
+      const float b = h.rh[c] * wave_sum(dyr);
 #pragma unroll
-      for (int u = 0; u < PL; ++u) q[u] = fmaf(al[c] - b, Sh[c][u], q[u]);
+      for (int u = 0; u < PL; ++u) q[u] = fmaf(al[c] - b, h.Sh[c][u], q[u]);
     }
   }
 #pragma unroll
@@ -256,7 +281,9 @@ __global__ __launch_bounds__(kBlock) void lbfgs_kernel(const LbfgsArgs a) {
     xv[u] = e < n ? a.x[base + e] : 0.0f;
     gv[u] = e < n ? a.g[base + e] : 0.0f;
   }
-  lbfgs_seed<PL, MH>(a, s, lane, si, xv, gv);
+  LbfgsRegs<PL, MH> h;
+  lbfgs_load<PL, MH>(a, s, lane, si, h);
+  lbfgs_finish<PL, MH>(a, s, lane, si, xv, gv, h);
 }
 
 // --------------------------------------------------------------------------
@@ -272,6 +299,22 @@ __global__ __launch_bounds__(kBlock) void select_kernel(const SelectArgs a, cons
   const SeedInfo si = a.seeds[s];
   const int D = a.dof, n = si.T * D;
   const size_t base = (size_t)si.row0 * D;
+
+  // everything that does not depend on the choice is loaded first: the
+  // L-BFGS state and, for small K, every candidate's gradient
+  LbfgsRegs<PL, FUSED ? MH : 1> h;
+  if constexpr (FUSED) lbfgs_load<PL, MH>(la, s, lane, si, h);
+  constexpr int KG = PL <= 4 ? 8 : 1;
+  const bool pre = a.K <= KG;
+  float gall[KG][PL];
+#pragma unroll
+  for (int k = 0; k < KG; ++k)
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int e = lane + u * kWave;
+      gall[k][u] = (pre && k < a.K && e < n) ? a.grad_e[((size_t)k * a.rows + si.row0) * D + e] : 0.0f;
+    }
+  const float best_prev = a.best_c ? a.best_c[s] : 0.0f;
 
   float ck[kMaxK], gk[kMaxK], mk[kMaxK];
 #pragma unroll
@@ -311,10 +354,19 @@ __global__ __launch_bounds__(kBlock) void select_kernel(const SelectArgs a, cons
     }
   }
   const float al = a.alpha[best];
-  const bool improve = a.best_c && cb < a.best_c[s];
-  const float* gsrc = a.grad_e + ((size_t)best * a.rows + si.row0) * D;
+  const bool improve = a.best_c && cb < best_prev;
+  if (pre) {
 #pragma unroll
-  for (int u = 0; u < PL; ++u) gdv[u] = (lane + u * kWave < n) ? gsrc[lane + u * kWave] : 0.0f;
+    for (int k = 0; k < KG; ++k)
+      if (k == best) {
+#pragma unroll
+        for (int u = 0; u < PL; ++u) gdv[u] = gall[k][u];
+      }
+  } else {
+    const float* gsrc = a.grad_e + ((size_t)best * a.rows + si.row0) * D;
+#pragma unroll
+    for (int u = 0; u < PL; ++u) gdv[u] = (lane + u * kWave < n) ? gsrc[lane + u * kWave] : 0.0f;
+  }
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     const int e = lane + u * kWave;
@@ -333,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void select_kernel(const SelectArgs a, cons
     if (a.mc_out) a.mc_out[s] = mcb;
     if (improve) a.best_c[s] = cb;
   }
-  if constexpr (FUSED) lbfgs_seed<PL, MH>(la, s, lane, si, xv, gdv);
+  if constexpr (FUSED) lbfgs_finish<PL, MH>(la, s, lane, si, xv, gdv, h);
 }
 
 // --------------------------------------------------------------------------
@@ -358,6 +410,31 @@ __global__ __launch_bounds__(kBlock) void final_kernel(const FinalArgs a) {
                     a.pe_e[(size_t)rl * 2 + 1] <= a.success_rot && m >= 0.0f;
     a.success[p] = ok ? 1 : 0;
   }
+}
+
+// End-effector poses, one thread per (row, end effector): the chain from
+// the root (Tab.6 F * Rz per joint), the tool transform, Shepperd's
+// quaternion.
+__global__ __launch_bounds__(kBlock) void ee_pose_kernel(const EePoseArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.rows * a.n_ee) return;
+  const int r = i / a.n_ee, e = i - r * a.n_ee;
+  const int l = a.ee_link[e];
+  const int depth = a.info[l].x;
+  float T[12];
+  identity(T);
+  for (int c = 0; c < depth; ++c) {
+    const int u = a.chain[l * kMaxDof + c];
+    const float q = a.q[(size_t)r * a.dof + u];
+    compose(T, a.fixed_tf + u * 12);
+    rotz(T, __sinf(q), __cosf(q));
+  }
+  compose(T, a.ee_tf + e * 12);
+  float qw, qx, qy, qz;
+  mat_to_quat(T, qw, qx, qy, qz);
+  float* o = a.pose + (size_t)i * 7;
+  o[0] = T[3]; o[1] = T[7]; o[2] = T[11];
+  o[3] = qw; o[4] = qx; o[5] = qy; o[6] = qz;
 }
 
 // Cuboid pose (xyz + wxyz) and full sides -> library layout.
@@ -458,6 +535,13 @@ hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s) {
 hipError_t launch_particle_update(const ParticleArgs& a, hipStream_t s) {
   if (a.N < 1 || a.N > kMaxParticles) return hipErrorInvalidValue;
   particle_update_kernel<<<a.n_seeds, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ee_pose(const EePoseArgs& a, hipStream_t s) {
+  const int n = a.rows * a.n_ee;
+  if (n == 0) return hipSuccess;
+  ee_pose_kernel<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -302,6 +302,14 @@ def cfg_ik(seed: int = 3, n_goals: int = 4096, n_seeds: int = 32):
     return robot, worlds, batch, dict(name=f"ik-{n_goals}x{n_seeds}", alpha=ALPHA_4, iters=100)
 
 
+def goal_configs(robot: Robot, seed: int, n: int, spread: float = 2.5) -> np.ndarray:
+    """n joint configurations U(-spread, spread)^D (clipped to the limits);
+    their end-effector poses are goals reachable by construction."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    q = rng.uniform(-spread, spread, size=(n, robot.dof))
+    return np.clip(q, robot.q_lo, robot.q_hi)
+
+
 def cfg_uneven(seed: int = 4, n_problems: int = 64):
     """Uneven batch: per problem seeds U{4..64}, T in {24,32,48}, its own
     world of U{5..200} oriented cuboids."""

@@ -16,6 +16,9 @@ from tests import harness as H
 
 pytestmark = pytest.mark.gpu
 
+# evaluation layouts: 0 lane per link, 1 wave per link
+LAYOUTS = [0, 1]
+
 
 def _dev(a):
     return torch.as_tensor(np.asarray(a), dtype=torch.float32, device="cuda").contiguous()
@@ -24,7 +27,7 @@ def _dev(a):
 class Case:
     """Inputs of one workload on both sides."""
 
-    def __init__(self, robot, worlds, batch, params=None, K_max=16, m_max=8):
+    def __init__(self, robot, worlds, batch, params=None, K_max=16, m_max=8, layout=None):
         from paper_2310_17274_amd.binding import Context, default_params
         self.robot, self.worlds, self.batch = H.f32_inputs(robot, worlds, batch)
         params = params or {}
@@ -32,6 +35,8 @@ class Case:
         self.ctx.mg_set_worlds(self.worlds)
         b = self.batch
         self.b = self.ctx.batch(b.seeds, b.horizon, b.world, K_max=K_max, m_max=m_max)
+        if layout is not None:
+            self.b.mg_batch_set_layout(layout)
         D = self.robot.dof
         self.q_start = _dev(b.q_start)
         self.goal = _dev(b.goal.reshape(b.n_problems, -1))
@@ -77,9 +82,10 @@ def gpu_cost_grad(case):
     return c.cpu().numpy(), g.cpu().numpy(), mc.cpu().numpy()
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("kind", ["plain", "adjoint_small", "ik", "uneven", "tree"])
-def test_cost_grad_parity(kind):
-    case = make_case(kind)
+def test_cost_grad_parity(kind, layout):
+    case = make_case(kind, layout=layout)
     c, g, mc = gpu_cost_grad(case)
     cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, case.robot.dof))
     H.assert_cost_close(c, cr)
@@ -87,14 +93,15 @@ def test_cost_grad_parity(kind):
     H.assert_verdicts(mc, mcr)
 
 
-def test_cost_grad_parity_with_collisions_and_limits():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_cost_grad_parity_with_collisions_and_limits(layout):
     """Seeds pushed into obstacles and beyond joint limits so that every
     branch of the collision and limit profiles is exercised."""
     robot = wl.make_arm(seed=0, n_spheres=52)
     worlds = wl.make_worlds(11, [60])
     batch = wl.make_batch(robot, 13, [6], [16], [0], noise=0.4)
     batch.x0 = np.clip(batch.x0 * 1.3, -3.2, 3.2)
-    case = Case(robot, worlds, batch)
+    case = Case(robot, worlds, batch, layout=layout)
     c, g, mc = gpu_cost_grad(case)
     cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, 7))
     assert np.any(mcr < 0), "the case must contain collisions"
@@ -276,6 +283,29 @@ def test_large_tree_swept_particle_stage_sampled():
         np.testing.assert_allclose(vg[s].reshape(-1), v, rtol=2e-4, atol=1e-9)
 
 
+def test_autotuned_layout_keeps_parity():
+    """The autotuner picks one of the offered cuboid-slice layouts; the
+    evaluation stays within parity under the chosen layout, and the solve
+    under graphs still equals the solve with direct launches."""
+    case = make_case("uneven")
+    c0, g0, _ = case.ctx.mg_cost_grad(case.b, case.q_start, case.goal, case.x)
+    d = case.ctx.mg_lbfgs_step(case.b, 4, True, case.x, g0)
+    h = case.ctx.mg_autotune(case.b, case.q_start, case.goal, case.x, d, wl.ALPHA_4, launches=3)
+    assert h in (1, 2, 4)
+    c, g, mc = gpu_cost_grad(case)
+    cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, 7))
+    H.assert_cost_close(c, cr)
+    H.assert_grad_close(g, gr, case.batch)
+    outs = []
+    for use_graph in (True, False):
+        x = case.x.clone()
+        x, bc, bs, ok = case.ctx.mg_solve(case.b, case.q_start, case.goal, x, 30, 4, wl.ALPHA_4,
+                                          graph_inner=10, use_graph=use_graph)
+        torch.cuda.synchronize()
+        outs.append((x.cpu().numpy(), bc.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_cost_only_matches_cost_grad():
     case = make_case("adjoint_small")
     c1, _, mc1 = case.ctx.mg_cost_grad(case.b, case.q_start, case.goal, case.x, grad=False)
@@ -284,18 +314,20 @@ def test_cost_only_matches_cost_grad():
     assert torch.equal(c1, c2) and torch.equal(mc1, mc2)
 
 
-def test_cost_grad_is_deterministic():
-    case = make_case("uneven")
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_cost_grad_is_deterministic(layout):
+    case = make_case("uneven", layout=layout)
     a = gpu_cost_grad(case)
     b = gpu_cost_grad(case)
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
 
 
-def test_full_size_cost_adjoint_sampled():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_full_size_cost_adjoint_sampled(layout):
     """Full 32 seeds x 32 waypoints x 8 candidates workload through the
     line-search launch; candidates of sampled seeds checked one by one."""
-    case = make_case("adjoint")
+    case = make_case("adjoint", layout=layout)
     D = 7
     rng = np.random.default_rng(0)
     d = rng.normal(0, 0.05, case.batch.x0.shape).astype(np.float32).astype(np.float64)
@@ -342,13 +374,23 @@ def test_lbfgs_step_parity():
         x = (x + 0.05 * d_gpu).astype(np.float32).astype(np.float64)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_linesearch_parity(mode):
-    case = make_case("plain")
+def test_linesearch_parity(mode, layout):
+    _linesearch_parity(make_case("plain", layout=layout), wl.ALPHA_4, mode)
+
+
+@pytest.mark.parametrize("K", [3, 16])
+def test_linesearch_candidate_counts_wave_per_link(K):
+    """Candidate counts that do not divide the 64 lanes of a workgroup
+    (rows straddle workgroups) and the largest count."""
+    _linesearch_parity(make_case("plain", layout=1), [float(a) for a in np.linspace(0.01, 1.0, K)], 1)
+
+
+def _linesearch_parity(case, alpha, mode):
     D = 7
     c0, g0, _ = case.ctx.mg_cost_grad(case.b, case.q_start, case.goal, case.x)
     d = case.ctx.mg_lbfgs_step(case.b, 4, True, case.x, g0)
-    alpha = wl.ALPHA_4
     xo, co, go, ch, mco = case.ctx.mg_linesearch(case.b, case.q_start, case.goal, case.x, c0, g0, d, alpha, mode)
     torch.cuda.synchronize()
     c0n, g0n, dn = c0.cpu().numpy(), g0.cpu().numpy(), d.cpu().numpy()
@@ -369,8 +411,8 @@ def test_linesearch_parity(mode):
         assert np.linalg.norm(go[r] - gr) <= H.GRAD_RTOL * np.linalg.norm(gr) + H.ABS_TOL
 
 
-def _solve_case(use_graph, kind="plain", iters=100):
-    case = make_case(kind)
+def _solve_case(use_graph, kind="plain", iters=100, layout=None):
+    case = make_case(kind, layout=layout)
     x = case.x.clone()
     alpha = wl.ALPHA_4
     x, bc, bs, ok = case.ctx.mg_solve(case.b, case.q_start, case.goal, x, iters, 4, alpha, mode=1,
@@ -379,19 +421,21 @@ def _solve_case(use_graph, kind="plain", iters=100):
     return case, x.cpu().numpy(), bc.cpu().numpy(), bs.cpu().numpy(), ok.cpu().numpy()
 
 
-def test_solve_graph_equals_direct_launches():
-    _, x1, c1, s1, ok1 = _solve_case(True)
-    _, x2, c2, s2, ok2 = _solve_case(False)
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_solve_graph_equals_direct_launches(layout):
+    _, x1, c1, s1, ok1 = _solve_case(True, layout=layout)
+    _, x2, c2, s2, ok2 = _solve_case(False, layout=layout)
     assert np.array_equal(x1, x2) and np.array_equal(c1, c2)
     assert np.array_equal(s1, s2) and np.array_equal(ok1, ok2)
 
 
-def test_solve_results_are_reference_consistent():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_solve_results_are_reference_consistent(layout):
     """The solve is chaotic in fp32 vs fp64, so the reference re-evaluates
     the GPU's best trajectories: their cost must equal the reported best
     cost, it must not exceed the start cost, and the success verdict must
     agree with the reference's pose error and clearance of the best seed."""
-    case, x, bc, bs, ok = _solve_case(True)
+    case, x, bc, bs, ok = _solve_case(True, layout=layout)
     D, T = 7, 32
     cr, _, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, x.reshape(-1, D), grad=False)
     H.assert_cost_close(bc, cr, "best cost")
@@ -434,6 +478,24 @@ def test_ik_solve_reaches_reachable_goals():
         if abs(pe[0] - 0.005) > 1e-5 and abs(re_[0] - 0.05) > 1e-4:
             assert bool(ok[p]) == bool(pe[0] <= 0.005 and re_[0] <= 0.05), p
     assert ok.mean() >= 0.75
+
+
+@pytest.mark.parametrize("two_arm", [False, True])
+def test_ee_pose_matches_reference(two_arm):
+    robot = wl.make_two_arm(seed=0, n_spheres=24) if two_arm else wl.make_arm(seed=0, n_spheres=20)
+    robot = wl.robot_f32(robot)
+    from paper_2310_17274_amd.binding import Context
+    ctx = Context(robot)
+    q = wl.goal_configs(robot, 5, 200).astype(np.float32).astype(np.float64)
+    pose = ctx.mg_ee_pose(_dev(q)).cpu().numpy()
+    r = ref.Ref(robot)
+    for i in range(q.shape[0]):
+        _, _, ee = r.fk(q[i])
+        ee = ee.reshape(-1, 7)
+        np.testing.assert_allclose(pose[i, :, :3], ee[:, :3], atol=1e-5)
+        for e in range(ee.shape[0]):
+            qg, qr = pose[i, e, 3:], ee[e, 3:]
+            assert min(np.abs(qg - qr).max(), np.abs(qg + qr).max()) < 1e-5
 
 
 def test_autograd_function_matches_adjoint():
