@@ -55,6 +55,9 @@ def main():
                          "line searches of the benchmark shape (one evaluation launch each), "
                          "'copy' copies 256 MiB five times (HBM byte-counter calibration)")
     ap.add_argument("--launches", type=int, default=10)
+    ap.add_argument("--layout", type=int, choices=[0, 1], default=None,
+                    help="force the evaluation layout (0 lane per link, 1 wave per link) "
+                         "instead of the autotuner's choice")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the uneven-batch and inverse-kinematics measurements")
     args = ap.parse_args()
@@ -90,13 +93,16 @@ def main():
             torch.empty(b.P, dtype=torch.int32, device=dev),
             torch.empty(b.P, dtype=torch.int32, device=dev))
 
-    # launch-shape autotuner: fastest cuboid-slice layout for this batch
+    # launch-shape autotuner: fastest evaluation layout for this batch
     c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
-    slices = ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha)
+    layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
+    if args.layout is not None:
+        b.mg_batch_set_layout(args.layout)
+        layout = ("wave_per_link" if args.layout else "lane_per_link") + "/auto"
 
     if args.profile == "eval":
-        return profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, args.launches)
+        return profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, args.launches, layout)
 
     def solve(use_graph):
         x.copy_(x0)
@@ -165,17 +171,20 @@ def main():
         "speedup_batched_vs_plain": ms_plain / ms_batched,
         "wall_s_timed": wall,
         "best_cost_min": float(best.min()),
-        "roofline": {"bound": "alu", "kernel": "eval_kernel (cost + adjoint, 8 candidates)",
+        "roofline": {"bound": "alu",
+                     "kernel": ("eval_wl_kernel" if layout.startswith("wave") else "eval_kernel")
+                               + " (cost + adjoint, 8 candidates)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(slices),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(layout),
                      "eval_kernel_us": eval_us, "eval_launches_timed": n_ev,
-                     "cuboid_slices": slices,
+                     "layout": layout,
                      "flop_per_eval": fl, "evals_per_launch": S * T * K},
     }
 
     if not args.no_extra:
         line["uneven"] = bench_uneven(args.warmup)
         line["ik"] = bench_ik(args.warmup)
+        line["large"] = bench_large(args.warmup)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(robot, worlds, batch, alpha, iters, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -195,7 +204,13 @@ def kernel_digest():
     return h.hexdigest()
 
 
-def measured_traffic(slices):
+def layout_name(tuned):
+    """The autotuner's choice as 'lane_per_link/<slices>' or
+    'wave_per_link/<workgroups per 64 evaluations>'."""
+    return f"lane_per_link/{tuned}" if tuned > 0 else f"wave_per_link/{-tuned}"
+
+
+def measured_traffic(layout):
     """HBM bytes per evaluation launch from the committed FETCH_SIZE /
     WRITE_SIZE counter summary, or None when the kernel sources or the
     launch layout changed since the counters were taken (or no summary
@@ -207,7 +222,7 @@ def measured_traffic(slices):
         return None
     if fields.get("source_digest", "").strip() != kernel_digest():
         return None
-    if int(fields.get("cuboid_slices", "0")) != slices:
+    if fields.get("layout", "").strip() != layout:
         return None
     return float(fields["hbm_bytes_per_launch"])
 
@@ -265,7 +280,7 @@ def bench_uneven(warmup):
     q_start, goal, x0 = _inputs(robot, batch, dev)
     c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
-    slices = ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha)
+    layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
     ms_b, _ = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, True, 3, max(1, warmup))
     # plain: one batch per problem, every kernel launched directly
     singles, r0 = [], 0
@@ -296,7 +311,7 @@ def bench_uneven(warmup):
                         f"{int(worlds.offsets[-1])} cuboids in {P} worlds, K={len(alpha)}, {iters} iterations",
             "ms_per_solve_batched": ms_b / P, "ms_per_solve_plain": ms_p / P,
             "speedup_batched_vs_plain": ms_p / ms_b, "evals_per_s_batched": evals / (ms_b * 1e-3),
-            "cuboid_slices": slices}
+            "layout": layout}
 
 
 def bench_ik(warmup):
@@ -313,31 +328,84 @@ def bench_ik(warmup):
     alpha, iters, P = meta["alpha"], meta["iters"], batch.n_problems
     b = ctx.batch(batch.seeds, batch.horizon, batch.world, K_max=len(alpha), m_max=4)
     q_start, goal, x0 = _inputs(robot, batch, dev)
-    # reachable goals: end-effector poses of random configurations (the
-    # library's own forward kinematics)
-    qg = torch.as_tensor(wl.goal_configs(robot, 33, P), dtype=torch.float32, device=dev).contiguous()
-    goal = ctx.mg_ee_pose(qg).reshape(P, -1).contiguous()
+    # reachable goals: end-effector poses (the library's own forward
+    # kinematics) of the random configurations with the largest clearance
+    # (the library's own collision cost at T = 1) among 16 per goal
+    cand = wl.goal_configs(robot, 33, 16 * P)
+    qc = torch.as_tensor(cand, dtype=torch.float32, device=dev).contiguous()
+    bc = ctx.batch([cand.shape[0]], [1], [0], K_max=1, m_max=0)
+    _, _, clear = ctx.mg_cost_grad(bc, q_start[:1].contiguous(), goal[:1].contiguous(), qc, grad=False)
+    order = torch.argsort(clear, descending=True, stable=True)[:P]
+    goal_free = (clear[order] >= 0.0).float().mean().item()
+    goal = ctx.mg_ee_pose(qc[order].contiguous()).reshape(P, -1).contiguous()
     c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
-    slices = ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha)
+    layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
     ms, outs = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, True, 3, max(1, warmup))
     ok = outs[2].float().mean().item()
     return {"workload": f"{P} goals x {int(batch.seeds[0])} seeds, T=1, {int(worlds.offsets[-1])} oriented "
                         f"cuboids, K={len(alpha)}, {iters} iterations (graphs of 25)",
             "ik_per_s": P / (ms * 1e-3), "ms_per_batch": ms, "success_fraction": ok,
+            "goal_configs_collision_free": goal_free,
             "evals_per_s": int(batch.seeds.sum()) * len(alpha) * iters / (ms * 1e-3),
-            "cuboid_slices": slices,
-            "note": "goals are end-effector poses of random configurations U(-2.5,2.5)^7 (reachable, "
-                    "not filtered for collisions); success = 5 mm / 0.05 rad and collision free"}
+            "layout": layout,
+            "note": "goals are end-effector poses of the clearest of 16 random configurations "
+                    "U(-2.5,2.5)^7 each (reachable); success = 5 mm / 0.05 rad and collision free"}
 
 
-def profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, launches):
+def bench_large(warmup):
+    """Two-arm tree (14 joints, 120 spheres), 500 oriented cuboids, swept
+    collision (4 trace steps), 128 seeds x 48 waypoints: the particle stage
+    (2 rounds x 256 particles per seed) then 100 L-BFGS iterations with 4
+    line-search candidates (graphs of 25)."""
+    import torch
+    from paper_2310_17274_amd import workloads as wl
+    from paper_2310_17274_amd.binding import Context, default_params
+    robot, worlds, batch, meta = wl.cfg_large()
+    robot, worlds, batch = wl.robot_f32(robot), wl.worlds_f32(worlds), wl.to_f32(batch)
+    dev = torch.device("cuda:0")
+    ctx = Context(robot, default_params(swept=1, sweep_steps=4))
+    ctx.mg_set_worlds(worlds)
+    alpha, iters, P, D = meta["alpha"], meta["iters"], batch.n_problems, robot.dof
+    S, T, N, R = int(batch.seeds[0]), int(batch.horizon[0]), 256, 2
+    b = ctx.batch(batch.seeds, batch.horizon, batch.world, K_max=len(alpha), m_max=4)
+    b.mg_batch_reserve_particles(N)
+    q_start, goal, x0 = _inputs(robot, batch, dev)
+    c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
+    dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
+    layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha, launches=3))
+    eps = torch.as_tensor(wl.normal_draws(55, (R, N, S * T, D)), dtype=torch.float32, device=dev)
+    mean, var = x0.clone(), torch.empty_like(x0)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    stream = torch.cuda.current_stream()
+    for rep in range(max(1, warmup) + 1):
+        mean.copy_(x0)
+        var.fill_(0.05 ** 2)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        ctx.mg_particles(b, q_start, goal, mean, var, eps)
+        e1.record(stream)
+        ctx.mg_solve(b, q_start, goal, mean, iters, 4, alpha, mode=1, graph_inner=25, use_graph=True)
+        e2.record(stream)
+        torch.cuda.synchronize()
+    ms_p, ms_s = e0.elapsed_time(e1), e1.elapsed_time(e2)
+    return {"workload": f"two-arm tree ({D} joints, {robot.n_spheres} spheres), {int(worlds.offsets[-1])} "
+                        f"oriented cuboids, swept collision (4 steps), {S} seeds x T={T}; particle stage "
+                        f"{R} x {N}, then {iters} L-BFGS iterations with K={len(alpha)} (graphs of 25)",
+            "ms_particle_stage": ms_p, "ms_lbfgs_solve": ms_s, "ms_per_solve": ms_p + ms_s,
+            "particle_evals_per_s": R * N * S * T / (ms_p * 1e-3),
+            "lbfgs_evals_per_s": S * T * len(alpha) * iters / (ms_s * 1e-3),
+            "layout": layout}
+
+
+def profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, launches, layout):
     """Evaluation launches of the benchmark shape for hardware-counter runs."""
     import torch
     for _ in range(launches):
         ctx.mg_linesearch(b, q_start, goal, x0, c0, g0, dvec, alpha, 1)
     torch.cuda.synchronize()
-    print(json.dumps({"profile": "eval", "launches": launches, "kernel_digest": kernel_digest()}), flush=True)
+    print(json.dumps({"profile": "eval", "launches": launches, "kernel_digest": kernel_digest(),
+                      "layout": layout}), flush=True)
 
 
 def profile_copy():

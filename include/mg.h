@@ -189,14 +189,18 @@ mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *s
  * workgroup, one wave per link plus one for the joint terms, each wave
  * skipping the cuboids that a ball around its link's spheres over all 64
  * lanes cannot reach; needs at most 15 links and no swept collision.
- * mg_batch_set_layout fixes a layout (-1: library default) and, for layout
- * 0, a slice count (0: automatic).  Host-only; affects later calls.
+ * For small batches the wave-per-link layout can also split the cuboids
+ * over 2 or 4 workgroups per 64 evaluations; the last to finish adds the
+ * slices' sums in slice order (the batch keeps the scratch and counters).
+ * mg_batch_set_layout fixes a layout (-1: library default) and a slice count
+ * (0: automatic; 1, 2 or 4).  Host-only; affects later calls.
  *
  * Autotuner for a batch's launch shape: times the line-search evaluation
  * kernel for K candidates under every layout and slice count the library
  * offers for this robot (mg_time_eval with `launches` launches each) and
  * fixes the fastest for every later call on this batch.  *slices_out (may
- * be NULL) receives the slice count, or 0 for the wave-per-link layout.
+ * be NULL) receives the slice count for the lane-per-link layout, or minus
+ * the workgroups per 64 evaluations for the wave-per-link layout.
  * Overwrites the batch's evaluation workspaces; not capturable.  Swept
  * collision always uses the lane-per-link layout with one slice. */
 mg_status mg_batch_set_layout(mg_batch *batch, int layout, int slices);

@@ -352,13 +352,61 @@ static double sphere_box(const mgref_params *pr, const double *pose, const doubl
 
 /* ------------------------------------------------------------------ */
 
+/* Adds d cost / d q of a gradient g acting at world point c on link `link`:
+ * Tab.7 revolute z, d c / d q_j = z_j x (c - o_j) for every joint on the
+ * chain from the link to the base. */
+static void project_point(const mgref_robot *rb, const double *T_t, int link, const double *c,
+                          const double *g, double *gt) {
+  for (int l = link; l >= 0; l = rb->parent[l]) {
+    int j = rb->joint[l];
+    if (j < 0) continue;
+    const double *Tl = T_t + l * 12;
+    double z[3] = {Tl[2], Tl[6], Tl[10]}, o[3] = {Tl[3], Tl[7], Tl[11]};
+    double rel[3], dc[3];
+    for (int i = 0; i < 3; ++i) rel[i] = c[i] - o[i];
+    cross3(z, rel, dc);
+    gt[j] += dot3(g, dc);
+  }
+}
+
+/* Self-collision at one waypoint, Eq.(9): beta_1 times the largest
+ * penetration r_i + r_j - |x_i - x_j| over the checked pairs (0 if none
+ * overlaps); the gradient acts on the two spheres of the first pair reaching
+ * the maximum. */
+static double self_collision(const mgref_robot *rb, const mgref_params *pr, const double *T_t,
+                             const double *sp, double *gt) {
+  if (pr->n_self <= 0 || !pr->self_pairs) return 0.0;
+  double best = 0.0;
+  int bk = -1;
+  for (int k = 0; k < pr->n_self; ++k) {
+    const int i = pr->self_pairs[2 * k], j = pr->self_pairs[2 * k + 1];
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) d2 += (sp[i * 3 + a] - sp[j * 3 + a]) * (sp[i * 3 + a] - sp[j * 3 + a]);
+    const double pen = rb->sphere[i * 4 + 3] + rb->sphere[j * 4 + 3] - sqrt(d2);
+    if (pen > best) { best = pen; bk = k; }
+  }
+  if (gt && bk >= 0) {
+    const int i = pr->self_pairs[2 * bk], j = pr->self_pairs[2 * bk + 1];
+    double u[3], d2 = 0.0;
+    for (int a = 0; a < 3; ++a) { u[a] = sp[i * 3 + a] - sp[j * 3 + a]; d2 += u[a] * u[a]; }
+    const double d = sqrt(d2);
+    if (d > 0.0) {
+      double gi[3], gj[3];
+      for (int a = 0; a < 3; ++a) { gi[a] = -pr->w_self * u[a] / d; gj[a] = -gi[a]; }
+      project_point(rb, T_t, rb->sphere_link[i], sp + i * 3, gi, gt);
+      project_point(rb, T_t, rb->sphere_link[j], sp + j * 3, gj, gt);
+    }
+  }
+  return pr->w_self * best;
+}
+
 double mgref_traj_cost(const mgref_robot *rb, const mgref_params *pr,
                        int n_box, const double *box_pose, const double *box_dims,
                        const double *q0, const double *goal, int T,
                        const double *q, double *grad, double *min_clear,
                        double *terms) {
   const int D = rb->dof, L = rb->n_links, M = rb->n_spheres, E = rb->n_ee;
-  double c_smooth = 0.0, c_bound = 0.0, c_coll = 0.0, c_pose = 0.0;
+  double c_smooth = 0.0, c_bound = 0.0, c_coll = 0.0, c_pose = 0.0, c_self = 0.0;
   double mc = pr->eta;
   if (grad) memset(grad, 0, (size_t)T * D * sizeof(double));
   if (T > 1) c_smooth = smooth_cost(pr, D, T, q0, q, grad);
@@ -406,6 +454,8 @@ double mgref_traj_cost(const mgref_robot *rb, const mgref_params *pr,
         }
       }
     }
+    /* self-collision, Eq.(9) */
+    c_self += self_collision(rb, pr, T_t, sp + t * M * 3, gt);
     /* pose reaching cost at the last waypoint */
     if (t == T)
       for (int e = 0; e < E; ++e) {
@@ -437,8 +487,10 @@ double mgref_traj_cost(const mgref_robot *rb, const mgref_params *pr,
   free(sp);
   free(ee);
   if (min_clear) *min_clear = mc;
-  if (terms) { terms[0] = c_smooth; terms[1] = c_bound; terms[2] = c_coll; terms[3] = c_pose; }
-  return c_smooth + c_bound + c_coll + c_pose;
+  if (terms) {
+    terms[0] = c_smooth; terms[1] = c_bound; terms[2] = c_coll; terms[3] = c_pose; terms[4] = c_self;
+  }
+  return c_smooth + c_bound + c_coll + c_pose + c_self;
 }
 
 void mgref_cost_grad_batch(const mgref_robot *rb, const mgref_params *pr,

@@ -43,6 +43,9 @@ typedef struct {
   int vel_all;              /* 0: velocity logcosh term at t = T only; 1: at every t in [0,T] */
   int swept;                /* 1: continuous (swept) sphere collision, Sec. 'Continuous Collision Checking' */
   int sweep_steps;          /* maximum sphere-tracing samples per half segment */
+  double w_self;            /* self-collision weight beta_1, Eq.(9) */
+  int n_self;               /* sphere pairs checked for self-collision (the set S of Eq.(9)) */
+  const int *self_pairs;    /* [n_self][2] sphere indices, or NULL */
 } mgref_params;
 
 /* Forward kinematics of one configuration q[D] (Sec. 'Robot Kinematics', Alg.7, Tab.6).

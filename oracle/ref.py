@@ -27,6 +27,9 @@ DEFAULTS = dict(
     # first-pass time step of the dt re-optimisation (appendix 'Time-step Descretization and Temporal Weight Scaling')
     dt=0.25,
     vel_all=0, swept=0, sweep_steps=4,
+    # Eq.(9) self-collision: weight 5000 like every soft constraint; the
+    # checked sphere pairs are a robot property (none by default)
+    w_self=5000.0, n_self=0,
 )
 # Line search constants (Reading: the Nocedal & Wright defaults).
 ETA1 = 1e-4
@@ -48,7 +51,8 @@ class _Params(C.Structure):
                 ("a6", C.c_double), ("a7", C.c_double), ("a8", C.c_double), ("a9", C.c_double),
                 ("w_bound", C.c_double), ("eta2", C.c_double), ("w_coll", C.c_double),
                 ("eta", C.c_double), ("dt", C.c_double), ("vel_all", C.c_int),
-                ("swept", C.c_int), ("sweep_steps", C.c_int)]
+                ("swept", C.c_int), ("sweep_steps", C.c_int), ("w_self", C.c_double),
+                ("n_self", C.c_int), ("self_pairs", _ip)]
 
 
 def lib():
@@ -95,6 +99,12 @@ class Ref:
                           n_ee=robot.n_ee, ee_link=keep(_i(robot.ee_link)),
                           ee_tf=keep(_d(robot.ee_tf)), q_lo=keep(_d(robot.q_lo)),
                           q_hi=keep(_d(robot.q_hi)))
+        pairs = p.pop("self_pairs", None)
+        self.params = dict(p, self_pairs=pairs)
+        if pairs is not None and len(pairs):
+            pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+            p["n_self"] = pairs.shape[0]
+            p["self_pairs"] = keep(_i(pairs))
         self._pr = _Params(**p)
 
     # -- kinematics and geometry ---------------------------------------
@@ -114,14 +124,15 @@ class Ref:
 
     # -- costs -----------------------------------------------------------
     def traj_cost(self, boxes, q0, goal, q, grad=True):
-        """Cost, gradient [T,D] (or None), min clearance, terms[4]."""
+        """Cost, gradient [T,D] (or None), min clearance, terms[5]
+        (smoothness, joint limits, world collision, pose, self-collision)."""
         pose, dims = boxes
         pose, pp = _d(np.asarray(pose).reshape(-1, 7)); dims, dp = _d(np.asarray(dims).reshape(-1, 3))
         q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, self.robot.dof)
         T = q.shape[0]
         g = np.zeros_like(q) if grad else None
         mc = C.c_double(0.0)
-        terms = np.zeros(4)
+        terms = np.zeros(5)
         q0a, q0p = _d(q0)
         ga, gp_ = _d(goal)
         c = lib().mgref_traj_cost(C.byref(self._rb), C.byref(self._pr), pose.shape[0], pp, dp,

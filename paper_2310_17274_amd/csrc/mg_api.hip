@@ -118,6 +118,10 @@ struct mg_batch {
   // wave-per-link chunks of 64 evaluations, per candidate count K
   int* d_chunk_wl[mg::kMaxK + 1] = {};
   int chunks_wl[mg::kMaxK + 1] = {};
+  int wl_slices = 0;        // wave-per-link cuboid slices over workgroups (0: automatic)
+  int wl_slices_max = 1;    // largest the scratch below holds
+  float* wl_part = nullptr; // [chunks][slices][2 + D][64]
+  int* wl_count = nullptr;  // [chunks], zero between launches
   // particle stage: per-row costs of every particle [p_cap][rows]
   float* p_cost = nullptr;
   int p_cap = 0;
@@ -223,6 +227,8 @@ mg::WaveLinks dev_wave_links(const mg_ctx* c) {
   wl.sphere = c->d_lane_sphere;
   wl.ball = c->d_wl_ball;
   wl.maxs = c->maxs;
+  wl.part = nullptr;
+  wl.count = nullptr;
   return wl;
 }
 
@@ -320,10 +326,21 @@ mg_status common_checks(mg_ctx* c, mg_batch* b) {
 
 // Launch an evaluation in the batch's layout: lane per link (cuboid slices
 // index hi) or wave per link.
+// Wave-per-link slices: the forced count, else enough workgroups for two
+// per CU.
+int wl_slices(const mg_batch* b, int K) {
+  if (b->wl_slices > 0) return std::min(b->wl_slices, b->wl_slices_max);
+  int h = 1;
+  while (h < b->wl_slices_max && (long)b->chunks_wl[K] * h < 512) h *= 2;
+  return h;
+}
+
 hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool grad, hipStream_t s) {
   if (use_wl(b, a.K)) {
     a.chunk_prefix = b->d_chunk_wl[a.K];
-    return mg::launch_eval_wl(a, b->chunks_wl[a.K], cand, grad, s);
+    a.wl.part = b->wl_part;
+    a.wl.count = b->wl_count;
+    return mg::launch_eval_wl(a, b->chunks_wl[a.K], wl_slices(b, a.K), cand, grad, s);
   }
   return mg::launch_eval(a, b->chunks[hi], cand, grad, s);
 }
@@ -601,6 +618,19 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
     b->chunks_wl[K] = pre[P];
     if ((st = dev_upload(&b->d_chunk_wl[K], pre)) != MG_OK) return bail(st);
   }
+  {
+    // wave-per-link slice scratch: up to 4 slices while it stays under 64 MB
+    const size_t per = (size_t)b->chunks_wl[K_max] * (2 + c->D) * mg::kWave * sizeof(float);
+    b->wl_slices_max = 1;
+    while (b->wl_slices_max < 4 && per * b->wl_slices_max * 2 <= (64u << 20)) b->wl_slices_max *= 2;
+    if (b->wl_slices_max > 1) {
+      if ((st = dev_alloc(&b->wl_part, per / sizeof(float) * b->wl_slices_max)) != MG_OK ||
+          (st = dev_alloc(&b->wl_count, (size_t)b->chunks_wl[K_max])) != MG_OK)
+        return bail(st);
+      if (hipMemset(b->wl_count, 0, (size_t)b->chunks_wl[K_max] * sizeof(int)) != hipSuccess)
+        return bail(fail(MG_ERR_HIP, "initialising the slice counters failed"));
+    }
+  }
   const size_t R = rows, RD = rows * c->D, KR = (size_t)K_max * rows, mm = std::max(m_max, 1);
   if ((st = dev_alloc(&b->cost_e, KR)) != MG_OK || (st = dev_alloc(&b->gd_e, KR)) != MG_OK ||
       (st = dev_alloc(&b->mc_e, KR)) != MG_OK || (st = dev_alloc(&b->grad_e, KR * c->D)) != MG_OK ||
@@ -634,6 +664,7 @@ void mg_batch_destroy(mg_batch* b) {
   dev_free(b->c_cur); dev_free(b->g_cur); dev_free(b->dir); dev_free(b->best_c); dev_free(b->best_x);
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
   dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost);
+  dev_free(b->wl_part); dev_free(b->wl_count);
   delete b;
 }
 
@@ -743,26 +774,34 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
   if ((st = check_K_alpha(b, K, alpha)) != MG_OK) return st;
   if (!q_start || !goal || !x || !dir) return fail(MG_ERR_ARG, "null argument");
   if (launches < 1) return fail(MG_ERR_ARG, "launches must be >= 1");
-  // candidates: lane per link with 1, 2 or 4 cuboid slices, wave per link
+  // candidates: lane per link with 1, 2 or 4 cuboid slices per workgroup,
+  // wave per link with 1, 2 or 4 workgroups per 64 evaluations
   int best = 0;
   float best_us = 3.0e38f;
-  const int n_opt = kNumSlices + (wl_possible(c) ? 1 : 0);
+  int n_wl = 0;
+  if (wl_possible(c))
+    for (int h = 1; h <= b->wl_slices_max; h *= 2) ++n_wl;
+  const int n_opt = kNumSlices + n_wl;
   for (int o = 0; o < n_opt; ++o) {
     b->layout = o < kNumSlices ? 0 : 1;
     b->slices = o < kNumSlices ? o : 0;
+    b->wl_slices = o < kNumSlices ? 0 : 1 << (o - kNumSlices);
     float us = 0.0f;
     // one untimed launch per layout first (code upload, caches)
     if ((st = mg_time_eval(c, b, q_start, goal, x, dir, K, alpha, 1, &us, stream)) != MG_OK ||
         (st = mg_time_eval(c, b, q_start, goal, x, dir, K, alpha, launches, &us, stream)) != MG_OK) {
       b->slices = -1;
       b->layout = -1;
+      b->wl_slices = 0;
       return st;
     }
     if (us < best_us) { best_us = us; best = o; }
   }
   b->layout = best < kNumSlices ? 0 : 1;
   b->slices = best < kNumSlices ? best : -1;
-  if (slices_out) *slices_out = best < kNumSlices ? kSlices[best] : 0;
+  b->wl_slices = best < kNumSlices ? 0 : 1 << (best - kNumSlices);
+  // lane per link: the slice count; wave per link: minus the workgroups per chunk
+  if (slices_out) *slices_out = best < kNumSlices ? kSlices[best] : -b->wl_slices;
   return MG_OK;
 }
 
@@ -796,9 +835,12 @@ mg_status mg_batch_set_layout(mg_batch* b, int layout, int slices) {
     for (int i = 0; i < kNumSlices; ++i)
       if (kSlices[i] == slices) hi = i;
     if (hi < 0) return fail(MG_ERR_ARG, "slices must be 0 (automatic), 1, 2 or 4");
+    if (layout == 1 && slices > b->wl_slices_max)
+      return fail(MG_ERR_SHAPE, "this batch holds at most %d wave-per-link slices", b->wl_slices_max);
   }
   b->layout = layout;
-  b->slices = hi;
+  b->slices = layout == 1 ? -1 : hi;
+  b->wl_slices = layout == 1 ? slices : 0;
   return MG_OK;
 }
 
@@ -919,7 +961,7 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
     key_push(key, q_start); key_push(key, goal); key_push(key, x); key_push(key, m); key_push(key, K);
     key_push(key, mode); key_push(key, graph_inner); key_push(key, c->params);
     key_push(key, c->d_box); key_push(key, c->d_world_off); key_push(key, b->slices);
-    key_push(key, b->layout);
+    key_push(key, b->layout); key_push(key, b->wl_slices);
     for (int k = 0; k < K; ++k) key_push(key, alpha[k]);
     if (!b->gexec || key != b->gkey) {
       if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }

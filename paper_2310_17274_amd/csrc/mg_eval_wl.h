@@ -14,7 +14,10 @@
 // copy of the link's spheres, and the wave skips the cuboid when none
 // reaches it.  The adjoint recomputes the chain (Alg.8: no stored transforms)
 // and projects the link's wrench on every joint above it (Tab.7); the waves'
-// partial sums meet in LDS in a fixed order.
+// partial sums meet in LDS in a fixed order.  The world's cuboids can also
+// be split over gridDim.y workgroups of the same 64 evaluations (more
+// workgroups for small batches); the last of them to finish adds the slices'
+// sums in slice order.
 #pragma once
 
 #include "mg_eval.h"
@@ -24,11 +27,19 @@ namespace {
 
 __device__ __forceinline__ float wave_max(float v) { return -wave_min(-v); }
 
+__device__ __forceinline__ void part_store(float* p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float part_load(const float* p) {
+  return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Collision, pose and adjoint of link l for this lane's evaluation.
 // part[q * kWave + lane]: q = 0 cost, 1 clearance, 2 + j d cost / d q_j.
 template <int MAXS, bool GRAD, typename QV>
 __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const Problem& pb, int row,
-                                          int t, bool valid, QV&& qval, float* part, int lane) {
+                                          int t, bool valid, int h, int H, QV&& qval, float* part,
+                                          int lane) {
   const int D = a.rb.dof;
   // per-link tables through the constant address space (wave-uniform)
   const v4i info = *(cv4i*)(a.wl.info + l);
@@ -47,10 +58,13 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
 
   float cost = 0.0f, mc = a.pr.eta;
   float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, Mx = 0.0f, My = 0.0f, Mz = 0.0f;
-  if (ee >= 0 && t == pb.T - 1) pose_term(a, p, ee, T, valid ? row : -1, cost, Fx, Fy, Fz, Mx, My, Mz);
+  if (ee >= 0 && h == 0 && t == pb.T - 1)
+    pose_term(a, p, ee, T, valid ? row : -1, cost, Fx, Fy, Fz, Mx, My, Mz);
 
-  // ---- world collision of the link's spheres ----
-  const int w0 = a.world_off[pb.world], w1 = a.world_off[pb.world + 1];
+  // ---- world collision of the link's spheres, cuboid slice h of H ----
+  const int wa = a.world_off[pb.world], wb = a.world_off[pb.world + 1];
+  const int per = (wb - wa + H - 1) / H;
+  const int w0 = min(wb, wa + h * per), w1 = min(wb, w0 + per);
   if (ns > 0 && w1 > w0) {
     const float w = a.pr.w_coll, eta = a.pr.eta, inv_eta = 1.0f / fmaxf(eta, 1e-30f);
     cv4f* sph = (cv4f*)(a.wl.sphere + l * MAXS);
@@ -205,16 +219,18 @@ __global__ __launch_bounds__(1024) void eval_wl_kernel(const EvalArgs a) {
     return v;
   };
 
+  // cuboid slice of this workgroup (gridDim.y slices share a chunk)
+  const int h = blockIdx.y, H = gridDim.y;
   const int NP = 2 + D;
   float* part = s_part + (size_t)wave * NP * kWave;
   if (wave < L) {
-    link_wave<MAXS, GRAD>(a, wave, p, pb, row, t, valid, qval, part, lane);
+    link_wave<MAXS, GRAD>(a, wave, p, pb, row, t, valid, h, H, qval, part, lane);
   } else {
-    // joint limits (Eq.(17)) and smoothness (Eq.(16)) of every joint
+    // joint limits (Eq.(17)) and smoothness (Eq.(16)): joints j = h mod H
     float jc = 0.0f;
     for (int j = 0; j < D; ++j) {
       float js = 0.0f;
-      joint_terms(a, pb, p, row, t, j, qval(row, j), qval, jc, js);
+      if (j % H == h) joint_terms(a, pb, p, row, t, j, qval(row, j), qval, jc, js);
       part[(2 + j) * kWave + lane] = js;
     }
     part[0 * kWave + lane] = jc;
@@ -229,12 +245,49 @@ __global__ __launch_bounds__(1024) void eval_wl_kernel(const EvalArgs a) {
     cost += s_part[(v * NP + 0) * kWave + lane];
     mc = fminf(mc, s_part[(v * NP + 1) * kWave + lane]);
   }
+  if (H > 1) {
+    // park this slice's sums; the last workgroup of the chunk to arrive
+    // adds the slices in slice order (deterministic whatever the arrival
+    // order) and finishes the evaluation
+    const size_t cbase = (size_t)bx * H * NP * kWave;
+    float* mine = a.wl.part + cbase + (size_t)h * NP * kWave;
+    // (agent-scope atomic accesses: the slices may run on different XCDs,
+    // whose L2 caches are not coherent with each other)
+    part_store(mine + 0 * kWave + lane, cost);
+    part_store(mine + 1 * kWave + lane, mc);
+    if (GRAD)
+      for (int j = 0; j < D; ++j) {
+        float g = 0.0f;
+        for (int v = 0; v <= L; ++v) g += s_part[(v * NP + 2 + j) * kWave + lane];
+        part_store(mine + (2 + j) * kWave + lane, g);
+      }
+    __threadfence();
+    int ticket = 0;
+    if (lane == 0) ticket = atomicAdd(a.wl.count + bx, 1);
+    ticket = __shfl(ticket, 0, kWave);
+    if (ticket != H - 1) return;
+    __threadfence();
+    if (lane == 0) __hip_atomic_store(a.wl.count + bx, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cost = 0.0f;
+    mc = 3.0e38f;
+    for (int u = 0; u < H; ++u) {
+      const float* pu = a.wl.part + cbase + (size_t)u * NP * kWave;
+      cost += part_load(pu + lane);
+      mc = fminf(mc, part_load(pu + kWave + lane));
+    }
+  }
   const size_t eo = (size_t)k * a.rows + row;
   float gd = 0.0f;
   if (GRAD) {
     for (int j = 0; j < D; ++j) {
       float g = 0.0f;
-      for (int v = 0; v <= L; ++v) g += s_part[(v * NP + 2 + j) * kWave + lane];
+      if (H > 1) {
+        const size_t cbase = (size_t)bx * H * NP * kWave;
+        for (int u = 0; u < H; ++u)
+          g += part_load(a.wl.part + cbase + ((size_t)u * NP + 2 + j) * kWave + lane);
+      } else {
+        for (int v = 0; v <= L; ++v) g += s_part[(v * NP + 2 + j) * kWave + lane];
+      }
       if (valid) a.grad_e[eo * D + j] = g;
       if (CAND) gd = fmaf(g, dk[(size_t)row * D + j], gd);
     }
@@ -247,11 +300,12 @@ __global__ __launch_bounds__(1024) void eval_wl_kernel(const EvalArgs a) {
 }
 
 template <int MAXS>
-hipError_t launch_eval_wl_s(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s) {
+hipError_t launch_eval_wl_s(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
   const int waves = a.rb.n_links + 1;
-  if (waves * kWave > 1024) return hipErrorInvalidValue;
+  if (waves * kWave > 1024 || slices < 1) return hipErrorInvalidValue;
+  if (slices > 1 && (!a.wl.part || !a.wl.count)) return hipErrorInvalidValue;
   const size_t lds = (size_t)waves * (2 + a.rb.dof) * kWave * sizeof(float);
-  const dim3 grid(grid_x), block(waves * kWave);
+  const dim3 grid(grid_x, slices), block(waves * kWave);
   if (cand && grad) eval_wl_kernel<MAXS, true, true><<<grid, block, lds, s>>>(a);
   else if (grad) eval_wl_kernel<MAXS, false, true><<<grid, block, lds, s>>>(a);
   else if (!cand) eval_wl_kernel<MAXS, false, false><<<grid, block, lds, s>>>(a);

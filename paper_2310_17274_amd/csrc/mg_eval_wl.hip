@@ -2,10 +2,10 @@
 #include "mg_eval_wl.h"
 
 namespace mg {
-hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s) {
-  if (a.wl.maxs == 4) return launch_eval_wl_s<4>(a, grid_x, cand, grad, s);
-  if (a.wl.maxs == 8) return launch_eval_wl_s<8>(a, grid_x, cand, grad, s);
-  if (a.wl.maxs == 16) return launch_eval_wl_s<16>(a, grid_x, cand, grad, s);
+hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
+  if (a.wl.maxs == 4) return launch_eval_wl_s<4>(a, grid_x, slices, cand, grad, s);
+  if (a.wl.maxs == 8) return launch_eval_wl_s<8>(a, grid_x, slices, cand, grad, s);
+  if (a.wl.maxs == 16) return launch_eval_wl_s<16>(a, grid_x, slices, cand, grad, s);
   return hipErrorInvalidValue;
 }
 }  // namespace mg

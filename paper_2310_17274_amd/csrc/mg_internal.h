@@ -74,6 +74,11 @@ struct WaveLinks {
   const float4* sphere;    // [L][maxs] centre in link frame + radius
   const float4* ball;      // [L] ball bounding the link's spheres (link frame): centre, radius
   int maxs;
+  // cuboid slices over workgroups (gridDim.y > 1): per-slice partial sums
+  // [chunk][slice][2 + D][64] and one arrival counter per chunk (zero
+  // between launches; the last workgroup of a chunk resets it)
+  float* part;
+  int* count;
 };
 
 // Cuboid in the library layout: p = A c + b maps a world point into the box
@@ -203,7 +208,7 @@ struct FinalArgs {
 hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s);
 // wave-per-link layout: grid_x workgroups of 64 evaluations (chunk_prefix
 // counts 64-evaluation chunks of rows x K per problem)
-hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s);
+hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 // fuse (optional): compute the next L-BFGS direction from the chosen iterate
 hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, hipStream_t s);

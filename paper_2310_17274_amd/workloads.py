@@ -310,6 +310,39 @@ def goal_configs(robot: Robot, seed: int, n: int, spread: float = 2.5) -> np.nda
     return np.clip(q, robot.q_lo, robot.q_hi)
 
 
+def self_pairs(robot: Robot, min_gap: int = 2) -> np.ndarray:
+    """Sphere pairs checked for self-collision: spheres on links at least
+    `min_gap` apart along the kinematic tree (adjacent links may touch).
+    Returns [n, 2] int32, i < j."""
+    L = robot.n_links
+    depth = np.zeros(L, dtype=np.int64)
+    for l in range(L):
+        depth[l] = 0 if robot.parent[l] < 0 else depth[robot.parent[l]] + 1
+
+    def gap(a, b):
+        # tree distance between links a and b
+        n = 0
+        while a != b:
+            if depth[a] >= depth[b]:
+                a = robot.parent[a]
+            else:
+                b = robot.parent[b]
+            n += 1
+            if a < 0 or b < 0:
+                return 1 << 20     # different roots
+        return n
+    lk = robot.sphere_link
+    out = [(i, j) for i in range(robot.n_spheres) for j in range(i + 1, robot.n_spheres)
+           if gap(int(lk[i]), int(lk[j])) >= min_gap]
+    return np.asarray(out, dtype=np.int32).reshape(-1, 2)
+
+
+def normal_draws(seed: int, shape) -> np.ndarray:
+    """Standard normal draws (float32) for the particle stage."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal(size=shape, dtype=np.float32)
+
+
 def cfg_uneven(seed: int = 4, n_problems: int = 64):
     """Uneven batch: per problem seeds U{4..64}, T in {24,32,48}, its own
     world of U{5..200} oriented cuboids."""

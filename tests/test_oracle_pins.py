@@ -361,7 +361,7 @@ def test_cost_assembly_by_terms(oracle_lib):
     r = ref.Ref(robot)
     c, g, mc, terms = r.traj_cost(boxes, q0, goal, q)
     P = r.params
-    assert np.all(terms > 0)
+    assert np.all(terms[:4] > 0) and terms[4] == 0.0   # no self-collision pairs
     assert c == pytest.approx(terms.sum(), rel=1e-14)
     # smoothness from interpolant derivatives of the padded trajectory
     T, D = q.shape
@@ -614,6 +614,81 @@ def test_particle_stage_samples_and_costs(oracle_lib):
     m0, v0, _ = r.particles(boxes, q0, goal, T, mu, var, np.zeros_like(eps))
     np.testing.assert_allclose(m0, mu, rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(v0, 0.5 * var, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Self-collision, Eq.(9)
+
+def two_link_robot():
+    """Link 0 at the base (no joint motion used: q0 = 0), sphere A at
+    (0.5, 0, 0) r = 0.1; link 1 one metre out along x, rotating about z,
+    sphere B at (-0.45, 0, 0) in its frame, r = 0.1."""
+    eye = [1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]
+    out = [1, 0, 0, 1.0, 0, 1, 0, 0, 0, 0, 1, 0]
+    return wl.Robot(parent=np.array([-1, 0], np.int32), joint=np.array([0, 1], np.int32),
+                    fixed_tf=np.array([eye, out], dtype=float), sphere_link=np.array([0, 1], np.int32),
+                    sphere=np.array([[0.5, 0, 0, 0.1], [-0.45, 0, 0, 0.1]]),
+                    ee_link=np.array([1], np.int32), ee_tf=np.array([eye], dtype=float),
+                    q_lo=np.array([-3.0, -3.0]), q_hi=np.array([3.0, 3.0]))
+
+
+SELF_ONLY = dict(a0=0.0, a1=0.0, a6=0.0, a8=0.0, a9=0.0, w_bound=0.0, w_coll=0.0, w_self=1.0)
+
+
+def test_self_collision_closed_form(oracle_lib):
+    """Sphere B circles the joint at radius 0.45; its distance to A is
+    sqrt(0.25 + 0.2025 - 0.45 cos th), so the penetration is
+    max(0, 0.2 - that) at each waypoint (0.15 at th = 0, none at th = 1)."""
+    robot = two_link_robot()
+    r = ref.Ref(robot, self_pairs=[[0, 1]], **SELF_ONLY)
+    none = ref.Ref(robot, **SELF_ONLY)
+    ths = np.array([0.0, 0.2, 0.35, 1.0])
+    q = np.stack([np.zeros_like(ths), ths], axis=1)
+    goal = np.array([[0, 0, 0, 1, 0, 0, 0]], dtype=float)
+    c, _, _, terms = r.traj_cost(([], []), q[0], goal, q)
+    d = np.sqrt(0.25 + 0.2025 - 0.45 * np.cos(ths))
+    assert c == pytest.approx(np.maximum(0.0, 0.2 - d).sum(), rel=1e-12)
+    assert terms[4] == c and terms[2] == 0.0
+    assert none.traj_cost(([], []), q[0], goal, q)[0] == 0.0
+
+
+def test_self_collision_takes_the_largest_pair_and_only_listed_pairs(oracle_lib):
+    robot = two_link_robot()
+    # a third sphere C on link 1, overlapping A more deeply than B does
+    robot.sphere = np.array([[0.5, 0, 0, 0.1], [-0.45, 0, 0, 0.1], [-0.48, 0, 0, 0.12]])
+    robot.sphere_link = np.array([0, 1, 1], np.int32)
+    q = np.array([[0.0, 0.0]])
+    goal = np.array([[0, 0, 0, 1, 0, 0, 0]], dtype=float)
+    pen_ab, pen_ac = 0.2 - 0.05, 0.22 - 0.02
+    both = ref.Ref(robot, self_pairs=[[0, 1], [0, 2]], **SELF_ONLY).traj_cost(([], []), q[0], goal, q)[0]
+    only_ab = ref.Ref(robot, self_pairs=[[0, 1]], **SELF_ONLY).traj_cost(([], []), q[0], goal, q)[0]
+    assert both == pytest.approx(max(pen_ab, pen_ac), rel=1e-12)
+    assert only_ab == pytest.approx(pen_ab, rel=1e-12)
+
+
+def test_self_collision_gradient_matches_central_differences(oracle_lib):
+    robot = wl.make_arm(seed=0, n_spheres=20)
+    pairs = wl.self_pairs(robot)
+    assert len(pairs) > 0
+    r = ref.Ref(robot, self_pairs=pairs, **SELF_ONLY)
+    rng = np.random.default_rng(9)
+    goal = np.array([[0, 0, 0, 1, 0, 0, 0]], dtype=float)
+    hits = 0
+    for _ in range(40):
+        q = rng.uniform(-2.8, 2.8, (3, 7))
+        c, g, _, _ = r.traj_cost(([], []), q[0], goal, q)
+        if c == 0.0:
+            continue
+        hits += 1
+        h = 1e-6
+        fd = np.zeros_like(q)
+        for idx in np.ndindex(q.shape):
+            qp = q.copy(); qp[idx] += h
+            qm = q.copy(); qm[idx] -= h
+            fd[idx] = (r.traj_cost(([], []), q[0], goal, qp, grad=False)[0] -
+                       r.traj_cost(([], []), q[0], goal, qm, grad=False)[0]) / (2 * h)
+        assert np.linalg.norm(g - fd) <= 1e-5 * np.linalg.norm(fd) + 1e-9
+    assert hits >= 3
 
 
 # --------------------------------------------------------------------------
