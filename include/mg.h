@@ -92,6 +92,7 @@ typedef struct {
   float ls_eta_w;           /* Wolfe constant (default 0.9) */
   float success_pos;        /* success: position error <= (default 0.005 m) */
   float success_rot;        /* success: rotation angle <= (default 0.05 rad) */
+  float w_self;             /* self-collision weight beta_1 of Eq.(9) (default 5000) */
 } mg_params;
 
 void mg_default_params(mg_params *out);
@@ -176,6 +177,17 @@ mg_status mg_solve(mg_ctx *ctx, mg_batch *batch, const float *q_start, const flo
                    float *x, int iters, int m, int K, const float *alpha, int mode,
                    int graph_inner, int use_graph, float *best_cost, int *best_seed,
                    int *success, void *stream);
+
+/* Self-collision (Sec. "Self-Collision Avoidance", Eq.(9)): at every
+ * waypoint, w_self times the largest penetration r_i + r_j - |x_i - x_j|
+ * over the listed sphere pairs (0 if none overlaps); its gradient acts on
+ * the two spheres of the first listed pair reaching the maximum.
+ *   pairs HOST [n_pairs][2] sphere indices (i != j); n_pairs = 0 turns the
+ *   term off.  Copied to the device (not capturable).
+ * The term is evaluated by the wave-per-link layout only: while pairs are
+ * set, every evaluation uses it (robots of at most 15 links, no swept
+ * collision; otherwise MG_ERR_UNSUPPORTED), and mg_particles is refused. */
+mg_status mg_set_self_collision(mg_ctx *ctx, int n_pairs, const int *pairs);
 
 /* Forward kinematics of the end effectors (Sec. "Robot Kinematics", Tab.6):
  * pose (x, y, z, qw, qx, qy, qz; Shepperd's quaternion, sign unspecified)

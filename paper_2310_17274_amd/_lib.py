@@ -24,7 +24,8 @@ EXPORTS = ("mg_default_params", "mg_create", "mg_destroy", "mg_set_params", "mg_
            "mg_batch_create", "mg_batch_destroy", "mg_batch_seeds", "mg_batch_rows",
            "mg_cost_grad", "mg_lbfgs_step", "mg_linesearch", "mg_solve",
            "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
-           "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose", "mg_last_error")
+           "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose", "mg_set_self_collision",
+           "mg_last_error")
 
 
 class RobotDesc(C.Structure):
@@ -39,7 +40,7 @@ class Params(C.Structure):
                 ("w_bound", C.c_float), ("eta2", C.c_float), ("w_coll", C.c_float),
                 ("eta", C.c_float), ("dt", C.c_float), ("vel_all", C.c_int), ("swept", C.c_int),
                 ("sweep_steps", C.c_int), ("ls_eta1", C.c_float), ("ls_eta_w", C.c_float),
-                ("success_pos", C.c_float), ("success_rot", C.c_float)]
+                ("success_pos", C.c_float), ("success_rot", C.c_float), ("w_self", C.c_float)]
 
 
 class MgError(RuntimeError):
@@ -86,6 +87,7 @@ def lib():
                                C.POINTER(C.c_float), _vp]
     L.mg_batch_set_layout.argtypes = [_vp, C.c_int, C.c_int]
     L.mg_ee_pose.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
+    L.mg_set_self_collision.argtypes = [_vp, C.c_int, _ip]
     L.mg_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _fp, C.c_int,
                               C.POINTER(C.c_int), _vp]
     L.mg_eval_time.argtypes = [_vp, C.POINTER(C.c_float), C.POINTER(C.c_int)]
@@ -94,7 +96,8 @@ def lib():
     for name in ("mg_create", "mg_set_params", "mg_set_worlds", "mg_batch_create", "mg_cost_grad",
                  "mg_lbfgs_step", "mg_linesearch", "mg_solve", "mg_batch_seeds", "mg_batch_rows",
                  "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
-                 "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose"):
+                 "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose",
+                 "mg_set_self_collision"):
         getattr(L, name).restype = C.c_int
     _LIB = L
     return L

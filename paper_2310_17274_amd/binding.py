@@ -198,6 +198,12 @@ class Context:
                                   int(bool(use_graph)), _ptr(bc), _ptr(bs), _ptr(ok), _stream()))
         return x, bc, bs, ok
 
+    def mg_set_self_collision(self, pairs):
+        """Sphere pairs [n, 2] checked for self-collision (Eq.(9)); empty turns it off."""
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        check(_lib.lib().mg_set_self_collision(self.handle, pr.shape[0],
+                                               pr.ctypes.data_as(C.POINTER(C.c_int))))
+
     def mg_ee_pose(self, q):
         """End-effector poses [rows, n_ee, 7] (xyz + wxyz) of configurations q [rows, D]."""
         rows = int(q.shape[0])

@@ -85,6 +85,11 @@ struct mg_ctx {
   int4* d_wl_info = nullptr;     // wave-per-link tables
   int* d_wl_chain = nullptr;
   float4* d_wl_ball = nullptr;
+  int* d_slot_sphere = nullptr;  // [L][maxs] sphere index of each slot
+  int max_depth = 0;             // deepest chain
+  int n_self = 0;                // self-collision pairs
+  int self_cap = 0;
+  int4* d_self_pairs = nullptr;
   Box* d_box = nullptr;
   int box_cap = 0, n_boxes = 0;
   int* d_world_off = nullptr;
@@ -167,8 +172,10 @@ mg_status build_lanes(mg_ctx* c) {
       if (c->ee_link[e] == l) ee = e;
     info[l] = make_int4(start, end, count[l], ee);
   }
+  std::vector<int> slot_sphere((size_t)lpe * maxs, 0);
   for (int m = 0; m < c->M; ++m) {
     const int l = c->sphere_link[m];
+    slot_sphere[(size_t)l * maxs + fill[l]] = m;
     sph[(size_t)l * maxs + fill[l]++] =
         make_float4(c->sphere[4 * m + 0], c->sphere[4 * m + 1], c->sphere[4 * m + 2], c->sphere[4 * m + 3]);
   }
@@ -187,6 +194,7 @@ mg_status build_lanes(mg_ctx* c) {
     for (int e = 0; e < c->n_ee; ++e)
       if (c->ee_link[e] == l) ee = e;
     wl_info[l] = make_int4((int)ch.size(), count[l], ee, 0);
+    c->max_depth = std::max(c->max_depth, (int)ch.size());
     if (count[l] == 0) continue;
     float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
     for (int s = 0; s < count[l]; ++s) {
@@ -208,6 +216,7 @@ mg_status build_lanes(mg_ctx* c) {
   if ((st = dev_upload(&c->d_wl_info, wl_info)) != MG_OK) return st;
   if ((st = dev_upload(&c->d_wl_chain, wl_chain)) != MG_OK) return st;
   if ((st = dev_upload(&c->d_wl_ball, wl_ball)) != MG_OK) return st;
+  if ((st = dev_upload(&c->d_slot_sphere, slot_sphere)) != MG_OK) return st;
   return dev_upload(&c->d_lane_sphere, sph);
 }
 
@@ -227,19 +236,27 @@ mg::WaveLinks dev_wave_links(const mg_ctx* c) {
   wl.sphere = c->d_lane_sphere;
   wl.ball = c->d_wl_ball;
   wl.maxs = c->maxs;
+  wl.max_depth = c->max_depth;
   wl.part = nullptr;
   wl.count = nullptr;
+  wl.self_pairs = c->d_self_pairs;
+  wl.slot_sphere = c->d_slot_sphere;
   return wl;
 }
 
 // The wave-per-link layout needs a workgroup of L + 1 waves and takes no
 // swept collision.
-bool wl_possible(const mg_ctx* c) { return c->L + 1 <= 16 && !c->params.swept; }
+bool wl_possible(const mg_ctx* c, bool self) {
+  return c->L + 1 <= 16 && !c->params.swept &&
+         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, self) <= mg::kWlLdsMax;
+}
+bool wl_possible(const mg_ctx* c) { return wl_possible(c, c->n_self > 0); }
 
 // Layout of an evaluation launch with K candidates.
 bool use_wl(const mg_batch* b, int K) {
   const mg_ctx* c = b->ctx;
   if (!wl_possible(c) || K > b->K_max) return false;
+  if (c->n_self > 0) return true;     // self-collision lives in this layout only
   if (b->layout >= 0) return b->layout == 1;
   const char* env = getenv("MG_EVAL_LAYOUT");
   if (env) return atoi(env) == 1;
@@ -254,6 +271,7 @@ mg::Params to_dev(const mg_params& p) {
   d.vel_all = p.vel_all; d.swept = p.swept; d.sweep_steps = p.sweep_steps;
   d.ls_eta1 = p.ls_eta1; d.ls_eta_w = p.ls_eta_w;
   d.success_pos = p.success_pos; d.success_rot = p.success_rot;
+  d.w_self = p.w_self; d.n_self = 0;
   return d;
 }
 
@@ -293,6 +311,7 @@ mg::EvalArgs eval_args(const mg_ctx* c, const mg_batch* b, int hi, const float* 
   a.ln = dev_lanes(c);
   a.wl = dev_wave_links(c);
   a.pr = c->params;
+  a.pr.n_self = c->n_self;
   a.slices = kSlices[hi];
   a.prob = b->d_prob;
   a.chunk_prefix = b->d_chunk[hi];
@@ -348,6 +367,8 @@ hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool gr
 mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
                        const float* x, const float* d, int K, const float* alpha, bool grad,
                        float* grad_out, float* pe_out, hipStream_t s) {
+  if (c->n_self > 0 && !use_wl(b, K))
+    return fail(MG_ERR_UNSUPPORTED, "self-collision needs the wave-per-link layout (at most 15 links, no swept collision)");
   const int hi = pick_slices(b, (long)b->rows * K);
   mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, x, d, K, alpha);
   if (grad_out) a.grad_e = grad_out;
@@ -442,6 +463,7 @@ void mg_default_params(mg_params* p) {
   p->vel_all = 0; p->swept = 0; p->sweep_steps = 4;
   p->ls_eta1 = 1e-4f; p->ls_eta_w = 0.9f;
   p->success_pos = 0.005f; p->success_rot = 0.05f;
+  p->w_self = 5000.0f;
 }
 
 const char* mg_last_error(void) { return g_last_error.c_str(); }
@@ -517,6 +539,7 @@ void mg_destroy(mg_ctx* c) {
   dev_free(c->d_fixed_tf); dev_free(c->d_joint); dev_free(c->d_q_lo); dev_free(c->d_q_hi); dev_free(c->d_ee_tf);
   dev_free(c->d_lane_info); dev_free(c->d_lane_sphere);
   dev_free(c->d_wl_info); dev_free(c->d_wl_chain); dev_free(c->d_wl_ball);
+  dev_free(c->d_slot_sphere); dev_free(c->d_self_pairs);
   dev_free(c->d_box); dev_free(c->d_world_off);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
@@ -710,6 +733,8 @@ mg_status mg_time_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
   if ((st = check_K_alpha(b, K, alpha)) != MG_OK) return st;
   if (!q_start || !goal || !x || !dir || !mean_us) return fail(MG_ERR_ARG, "null argument");
   if (launches < 1) return fail(MG_ERR_ARG, "launches must be >= 1");
+  if (c->n_self > 0 && !use_wl(b, K))
+    return fail(MG_ERR_UNSUPPORTED, "self-collision needs the wave-per-link layout (at most 15 links, no swept collision)");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int hi = pick_slices(b, (long)b->rows * K);
   const mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, x, dir, K, alpha);
@@ -776,13 +801,14 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
   if (launches < 1) return fail(MG_ERR_ARG, "launches must be >= 1");
   // candidates: lane per link with 1, 2 or 4 cuboid slices per workgroup,
   // wave per link with 1, 2 or 4 workgroups per 64 evaluations
-  int best = 0;
+  int best = c->n_self > 0 ? kNumSlices : 0;
   float best_us = 3.0e38f;
   int n_wl = 0;
   if (wl_possible(c))
     for (int h = 1; h <= b->wl_slices_max; h *= 2) ++n_wl;
   const int n_opt = kNumSlices + n_wl;
   for (int o = 0; o < n_opt; ++o) {
+    if (o < kNumSlices && c->n_self > 0) continue;   // not evaluated by lane per link
     b->layout = o < kNumSlices ? 0 : 1;
     b->slices = o < kNumSlices ? o : 0;
     b->wl_slices = o < kNumSlices ? 0 : 1 << (o - kNumSlices);
@@ -802,6 +828,35 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
   b->wl_slices = best < kNumSlices ? 0 : 1 << (best - kNumSlices);
   // lane per link: the slice count; wave per link: minus the workgroups per chunk
   if (slices_out) *slices_out = best < kNumSlices ? kSlices[best] : -b->wl_slices;
+  return MG_OK;
+}
+
+mg_status mg_set_self_collision(mg_ctx* c, int n_pairs, const int* pairs) {
+  if (!c) return fail(MG_ERR_ARG, "null context");
+  if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return fail(MG_ERR_ARG, "bad pair list");
+  if (n_pairs > 0 && !wl_possible(c, true))
+    return fail(MG_ERR_UNSUPPORTED, "self-collision needs at most 15 links, no swept collision and "
+                "workgroup memory for the robot's spheres");
+  std::vector<int4> pr(n_pairs);
+  for (int k = 0; k < n_pairs; ++k) {
+    const int i = pairs[2 * k], j = pairs[2 * k + 1];
+    if (i < 0 || j < 0 || i >= c->M || j >= c->M || i == j)
+      return fail(MG_ERR_ARG, "pair %d: spheres %d, %d out of range or equal", k, i, j);
+    const float rs = c->sphere[4 * i + 3] + c->sphere[4 * j + 3];
+    int bits;
+    memcpy(&bits, &rs, sizeof(bits));
+    pr[k] = make_int4(i, j, c->sphere_link[i] | (c->sphere_link[j] << 16), bits);
+  }
+  if (n_pairs > c->self_cap) {
+    HIP_TRY(hipDeviceSynchronize());
+    dev_free(c->d_self_pairs);
+    c->self_cap = 0;
+    mg_status st = dev_alloc(&c->d_self_pairs, (size_t)n_pairs);
+    if (st != MG_OK) return st;
+    c->self_cap = n_pairs;
+  }
+  if (n_pairs > 0) HIP_TRY(hipMemcpy(c->d_self_pairs, pr.data(), pr.size() * sizeof(int4), hipMemcpyHostToDevice));
+  c->n_self = n_pairs;
   return MG_OK;
 }
 
@@ -867,6 +922,7 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
     return fail(MG_ERR_STATE, "n_particles = %d exceeds the %d reserved (mg_batch_reserve_particles)",
                 n_particles, b->p_cap);
   if (n_iters < 0) return fail(MG_ERR_ARG, "n_iters must be >= 0");
+  if (c->n_self > 0) return fail(MG_ERR_UNSUPPORTED, "the particle stage does not evaluate self-collision");
   if (!q_start || !goal || !mean || !var || (n_iters > 0 && !eps))
     return fail(MG_ERR_ARG, "null q_start, goal, mean, var or eps");
   if (!(k_mu >= 0.0f && k_mu <= 1.0f) || !(k_sigma >= 0.0f && k_sigma <= 1.0f))
@@ -961,7 +1017,7 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
     key_push(key, q_start); key_push(key, goal); key_push(key, x); key_push(key, m); key_push(key, K);
     key_push(key, mode); key_push(key, graph_inner); key_push(key, c->params);
     key_push(key, c->d_box); key_push(key, c->d_world_off); key_push(key, b->slices);
-    key_push(key, b->layout); key_push(key, b->wl_slices);
+    key_push(key, b->layout); key_push(key, b->wl_slices); key_push(key, c->n_self);
     for (int k = 0; k < K; ++k) key_push(key, alpha[k]);
     if (!b->gexec || key != b->gkey) {
       if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }

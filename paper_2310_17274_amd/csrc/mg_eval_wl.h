@@ -27,6 +27,10 @@ namespace {
 
 __device__ __forceinline__ float wave_max(float v) { return -wave_min(-v); }
 
+// Rows staged per workgroup: 64 evaluations cover at most 64 rows, plus the
+// stencils' reach of four rows on either side.
+constexpr int kStageRows = kWlStageRows;
+
 __device__ __forceinline__ void part_store(float* p, float v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -34,13 +38,45 @@ __device__ __forceinline__ float part_load(const float* p) {
   return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Self-collision (Eq.(9)), shared by every wave of the workgroup.  The
+// link waves have parked their sphere centres in s_sph[(m * 3 + c) * 64 +
+// lane]; wave w takes the pairs k = w, w + W, ... and parks its largest
+// penetration (first such pair) in s_best; every wave then reads the same
+// winner: the largest penetration over all pairs, the first pair on ties.
+__device__ __forceinline__ void self_pairs_phase(const EvalArgs& a, int w, int W, const float* s_sph,
+                                                 float* s_best, int lane) {
+  float bv = 0.0f;
+  int bk = -1;
+  cv4i* pairs = (cv4i*)(a.wl.self_pairs);
+  for (int k = w; k < a.pr.n_self; k += W) {
+    const v4i pr = pairs[k];
+    const float dx = s_sph[(pr.x * 3 + 0) * kWave + lane] - s_sph[(pr.y * 3 + 0) * kWave + lane];
+    const float dy = s_sph[(pr.x * 3 + 1) * kWave + lane] - s_sph[(pr.y * 3 + 1) * kWave + lane];
+    const float dz = s_sph[(pr.x * 3 + 2) * kWave + lane] - s_sph[(pr.y * 3 + 2) * kWave + lane];
+    const float pen = __int_as_float(pr.w) - sqrtf(dx * dx + dy * dy + dz * dz);
+    if (pen > bv) { bv = pen; bk = k; }
+  }
+  s_best[(w * 2 + 0) * kWave + lane] = bv;
+  s_best[(w * 2 + 1) * kWave + lane] = __int_as_float(bk);
+}
+
+__device__ __forceinline__ void self_winner(int W, const float* s_best, int lane, float& bv, int& bk) {
+  bv = 0.0f;
+  bk = -1;
+  for (int w = 0; w < W; ++w) {
+    const float v = s_best[(w * 2 + 0) * kWave + lane];
+    const int k = __float_as_int(s_best[(w * 2 + 1) * kWave + lane]);
+    if (v > bv || (v == bv && k >= 0 && (bk < 0 || k < bk))) { bv = v; bk = k; }
+  }
+}
+
 // Collision, pose and adjoint of link l for this lane's evaluation.
-// part[q * kWave + lane]: q = 0 cost, 1 clearance, 2 + j d cost / d q_j.
+// part[q * kWave + lane]: q = 0 cost, 1 clearance, 2 + i d cost / d q of the
+// joint at chain position i (root first).
 template <int MAXS, bool GRAD, typename QV>
 __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const Problem& pb, int row,
                                           int t, bool valid, int h, int H, QV&& qval, float* part,
-                                          int lane) {
-  const int D = a.rb.dof;
+                                          int lane, bool self_on, float* s_sph, float* s_best, int W) {
   // per-link tables through the constant address space (wave-uniform)
   const v4i info = *(cv4i*)(a.wl.info + l);
   const int depth = info.x, ns = info.y, ee = info.z;
@@ -61,24 +97,71 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
   if (ee >= 0 && h == 0 && t == pb.T - 1)
     pose_term(a, p, ee, T, valid ? row : -1, cost, Fx, Fy, Fz, Mx, My, Mz);
 
+  // ---- the link's spheres ----
+  cv4f* sph = (cv4f*)(a.wl.sphere + l * MAXS);
+  float cx[MAXS], cy[MAXS], cz[MAXS], rr[MAXS];
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) {
+    const v4f ls = sph[s];
+    const bool used = s < ns;
+    // unused slots sit far away and never pass the face test
+    cx[s] = used ? T[0] * ls.x + T[1] * ls.y + T[2] * ls.z + T[3] : 1e18f;
+    cy[s] = used ? T[4] * ls.x + T[5] * ls.y + T[6] * ls.z + T[7] : 1e18f;
+    cz[s] = used ? T[8] * ls.x + T[9] * ls.y + T[10] * ls.z + T[11] : 1e18f;
+    rr[s] = used ? ls.w : 0.0f;
+  }
+
+  // ---- self-collision (Eq.(9)): the winning pair's forces on this link ----
+  if (self_on) {
+    cint* sm = (cint*)(a.wl.slot_sphere + l * MAXS);
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s)
+      if (s < ns) {
+        const int m = sm[s];
+        s_sph[(m * 3 + 0) * kWave + lane] = cx[s];
+        s_sph[(m * 3 + 1) * kWave + lane] = cy[s];
+        s_sph[(m * 3 + 2) * kWave + lane] = cz[s];
+      }
+    __syncthreads();
+    self_pairs_phase(a, l, W, s_sph, s_best, lane);
+    __syncthreads();
+    float bv;
+    int bk;
+    self_winner(W, s_best, lane, bv, bk);
+    if (bk >= 0) {
+      const int4 pr = reinterpret_cast<const int4*>(a.wl.self_pairs)[bk];
+      const int li = pr.z & 0xffff, lj = pr.z >> 16;
+      if (li == l || lj == l) {
+        const float xi = s_sph[(pr.x * 3 + 0) * kWave + lane], yi = s_sph[(pr.x * 3 + 1) * kWave + lane];
+        const float zi = s_sph[(pr.x * 3 + 2) * kWave + lane];
+        const float xj = s_sph[(pr.y * 3 + 0) * kWave + lane], yj = s_sph[(pr.y * 3 + 1) * kWave + lane];
+        const float zj = s_sph[(pr.y * 3 + 2) * kWave + lane];
+        const float ux = xi - xj, uy = yi - yj, uz = zi - zj;
+        const float d = sqrtf(ux * ux + uy * uy + uz * uz);
+        if (d > 0.0f) {
+          // d cost / d x_i = -w (x_i - x_j) / d, the opposite on x_j
+          const float f = -a.pr.w_self / d;
+          const float fx = f * ux, fy = f * uy, fz = f * uz;
+          if (li == l) {
+            Fx += fx; Fy += fy; Fz += fz;
+            Mx += yi * fz - zi * fy; My += zi * fx - xi * fz; Mz += xi * fy - yi * fx;
+          }
+          if (lj == l) {
+            Fx -= fx; Fy -= fy; Fz -= fz;
+            Mx -= yj * fz - zj * fy; My -= zj * fx - xj * fz; Mz -= xj * fy - yj * fx;
+          }
+        }
+      }
+    }
+    __syncthreads();   // the spheres' space becomes the parts' space
+  }
+
   // ---- world collision of the link's spheres, cuboid slice h of H ----
   const int wa = a.world_off[pb.world], wb = a.world_off[pb.world + 1];
   const int per = (wb - wa + H - 1) / H;
   const int w0 = min(wb, wa + h * per), w1 = min(wb, w0 + per);
   if (ns > 0 && w1 > w0) {
     const float w = a.pr.w_coll, eta = a.pr.eta, inv_eta = 1.0f / fmaxf(eta, 1e-30f);
-    cv4f* sph = (cv4f*)(a.wl.sphere + l * MAXS);
-    float cx[MAXS], cy[MAXS], cz[MAXS], rr[MAXS];
-#pragma unroll
-    for (int s = 0; s < MAXS; ++s) {
-      const v4f ls = sph[s];
-      const bool used = s < ns;
-      // unused slots sit far away and never pass the face test
-      cx[s] = used ? T[0] * ls.x + T[1] * ls.y + T[2] * ls.z + T[3] : 1e18f;
-      cy[s] = used ? T[4] * ls.x + T[5] * ls.y + T[6] * ls.z + T[7] : 1e18f;
-      cz[s] = used ? T[8] * ls.x + T[9] * ls.y + T[10] * ls.z + T[11] : 1e18f;
-      rr[s] = used ? ls.w : 0.0f;
-    }
     // ball around the link's spheres of every lane: centre of the lanes'
     // bounding box of ball centres, radius half its diagonal + ball radius
     const v4f bl = *(cv4f*)(a.wl.ball + l);
@@ -170,7 +253,6 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
 
   // ---- adjoint: the chain again, joint c's derivative z_c . (M - o_c x F) ----
   if (GRAD) {
-    for (int j = 0; j < D; ++j) part[(2 + j) * kWave + lane] = 0.0f;
     identity(T);
     for (int i = 0; i < depth; ++i) {
       const int c = chain[i];
@@ -181,13 +263,15 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
       const float vx = Mx - (oy * Fz - oz * Fy);
       const float vy = My - (oz * Fx - ox * Fz);
       const float vz = Mz - (ox * Fy - oy * Fx);
-      part[(2 + c) * kWave + lane] = zx * vx + zy * vy + zz * vz;
+      part[(2 + i) * kWave + lane] = zx * vx + zy * vy + zz * vz;
     }
   }
 }
 
-template <int MAXS, bool CAND, bool GRAD>
-__global__ __launch_bounds__(1024) void eval_wl_kernel(const EvalArgs a) {
+// NT: launch bound (512 threads for robots of up to 7 links, which leaves
+// the register budget of two waves per SIMD; 1024 otherwise)
+template <int MAXS, bool CAND, bool GRAD, int NT>
+__global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   extern __shared__ float s_part[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
@@ -208,12 +292,35 @@ __global__ __launch_bounds__(1024) void eval_wl_kernel(const EvalArgs a) {
   const int t = rl % pb.T;
   const int row = pb.row0 + rl;
   const float alpha = CAND ? a.alpha[k < kMaxK ? k : 0] : 0.0f;
-  const float* dk = CAND ? a.d + (size_t)k * a.d_stride : nullptr;
+  const float* dk = CAND ? a.d : nullptr;     // one direction for every candidate
+
+  // LDS: the link waves' parts (2 + deepest chain each), the joint wave's
+  // part (2 + D), self-collision spheres and winners, staged rows
+  const int W = L + 1;
+  const int NP = 2 + D;
+  const int NPL = 2 + a.wl.max_depth;
+  float* s_joint = s_part + (size_t)L * NPL * kWave;
+
+  // the workgroup's rows and the four on either side (the stencils' reach)
+  // are staged in LDS once: every wave reads its joint values from there
+  const int e_first = (bx - a.chunk_prefix[p]) * kWave;
+  const int e_last = min(n_e, e_first + kWave) - 1;
+  const int p_end = pb.row0 + pb.S * pb.T;
+  const int r_lo = max(pb.row0, pb.row0 + e_first / K - 4);
+  const int r_hi = min(p_end - 1, pb.row0 + e_last / K + 4);
+  const int n_st = (r_hi - r_lo + 1) * D;
+  float* s_x = s_part + wl_region_floats(L, D, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0);
+  float* s_d = s_x + kStageRows * D;
+  for (int i = threadIdx.x; i < n_st; i += blockDim.x) {
+    s_x[i] = a.x[(size_t)r_lo * D + i];
+    if (CAND) s_d[i] = dk[(size_t)r_lo * D + i];
+  }
+  __syncthreads();
   auto qval = [&](int r, int j) -> float {
-    const size_t i = (size_t)r * D + j;
-    float v = a.x[i];
+    const int i = (r - r_lo) * D + j;
+    float v = s_x[i];
     if (CAND) {
-      v = a.var ? fmaf(sqrtf(a.var[i]), dk[i], v) : fmaf(alpha, dk[i], v);
+      v = fmaf(alpha, s_d[i], v);
       v = fminf(fmaxf(v, a.rb.q_lo[j]), a.rb.q_hi[j]);
     }
     return v;
@@ -221,13 +328,27 @@ __global__ __launch_bounds__(1024) void eval_wl_kernel(const EvalArgs a) {
 
   // cuboid slice of this workgroup (gridDim.y slices share a chunk)
   const int h = blockIdx.y, H = gridDim.y;
-  const int NP = 2 + D;
-  float* part = s_part + (size_t)wave * NP * kWave;
+  float* part = wave < L ? s_part + (size_t)wave * NPL * kWave : s_joint;
+  // self-collision in the first slice: sphere centres and per-wave winners
+  // follow the wave parts in LDS
+  const bool self_on = a.pr.n_self > 0 && h == 0;
+  float* s_sph = s_part;     // (shares the parts' space, see link_wave)
+  float* s_best = s_sph + (size_t)a.rb.n_spheres * 3 * kWave;
   if (wave < L) {
-    link_wave<MAXS, GRAD>(a, wave, p, pb, row, t, valid, h, H, qval, part, lane);
+    link_wave<MAXS, GRAD>(a, wave, p, pb, row, t, valid, h, H, qval, part, lane, self_on, s_sph, s_best, W);
   } else {
-    // joint limits (Eq.(17)) and smoothness (Eq.(16)): joints j = h mod H
     float jc = 0.0f;
+    if (self_on) {
+      __syncthreads();
+      self_pairs_phase(a, wave, W, s_sph, s_best, lane);
+      __syncthreads();
+      float bv;
+      int bk;
+      self_winner(W, s_best, lane, bv, bk);
+      jc += a.pr.w_self * bv;
+      __syncthreads();   // the spheres' space becomes the parts' space
+    }
+    // joint limits (Eq.(17)) and smoothness (Eq.(16)): joints j = h mod H
     for (int j = 0; j < D; ++j) {
       float js = 0.0f;
       if (j % H == h) joint_terms(a, pb, p, row, t, j, qval(row, j), qval, jc, js);
@@ -239,12 +360,22 @@ __global__ __launch_bounds__(1024) void eval_wl_kernel(const EvalArgs a) {
   __syncthreads();
   if (wave != L) return;
 
-  // ---- the last wave sums the waves' parts in a fixed order ----
+  // ---- the last wave sums the waves' parts in a fixed order: links in
+  //      order, then its own; joint derivatives gather into its part ----
   float cost = 0.0f, mc = 3.0e38f;
-  for (int v = 0; v <= L; ++v) {
-    cost += s_part[(v * NP + 0) * kWave + lane];
-    mc = fminf(mc, s_part[(v * NP + 1) * kWave + lane]);
+  for (int v = 0; v < L; ++v) {
+    cost += s_part[(v * NPL + 0) * kWave + lane];
+    mc = fminf(mc, s_part[(v * NPL + 1) * kWave + lane]);
   }
+  cost += s_joint[lane];
+  mc = fminf(mc, s_joint[kWave + lane]);
+  if (GRAD)
+    for (int v = 0; v < L; ++v) {
+      const int depth = ((cv4i*)(a.wl.info))[v].x;
+      cint* chain = (cint*)(a.wl.chain + v * kMaxDof);
+      for (int i = 0; i < depth; ++i)
+        s_joint[(2 + chain[i]) * kWave + lane] += s_part[(v * NPL + 2 + i) * kWave + lane];
+    }
   if (H > 1) {
     // park this slice's sums; the last workgroup of the chunk to arrive
     // adds the slices in slice order (deterministic whatever the arrival
@@ -256,11 +387,7 @@ __global__ __launch_bounds__(1024) void eval_wl_kernel(const EvalArgs a) {
     part_store(mine + 0 * kWave + lane, cost);
     part_store(mine + 1 * kWave + lane, mc);
     if (GRAD)
-      for (int j = 0; j < D; ++j) {
-        float g = 0.0f;
-        for (int v = 0; v <= L; ++v) g += s_part[(v * NP + 2 + j) * kWave + lane];
-        part_store(mine + (2 + j) * kWave + lane, g);
-      }
+      for (int j = 0; j < D; ++j) part_store(mine + (2 + j) * kWave + lane, s_joint[(2 + j) * kWave + lane]);
     __threadfence();
     int ticket = 0;
     if (lane == 0) ticket = atomicAdd(a.wl.count + bx, 1);
@@ -286,10 +413,10 @@ __global__ __launch_bounds__(1024) void eval_wl_kernel(const EvalArgs a) {
         for (int u = 0; u < H; ++u)
           g += part_load(a.wl.part + cbase + ((size_t)u * NP + 2 + j) * kWave + lane);
       } else {
-        for (int v = 0; v <= L; ++v) g += s_part[(v * NP + 2 + j) * kWave + lane];
+        g = s_joint[(2 + j) * kWave + lane];
       }
       if (valid) a.grad_e[eo * D + j] = g;
-      if (CAND) gd = fmaf(g, dk[(size_t)row * D + j], gd);
+      if (CAND) gd = fmaf(g, s_d[(row - r_lo) * D + j], gd);
     }
   }
   if (valid) {
@@ -304,12 +431,22 @@ hipError_t launch_eval_wl_s(const EvalArgs& a, int grid_x, int slices, bool cand
   const int waves = a.rb.n_links + 1;
   if (waves * kWave > 1024 || slices < 1) return hipErrorInvalidValue;
   if (slices > 1 && (!a.wl.part || !a.wl.count)) return hipErrorInvalidValue;
-  const size_t lds = (size_t)waves * (2 + a.rb.dof) * kWave * sizeof(float);
+  // particle mode (per-candidate draws) is not staged in this layout
+  if (a.var || a.d_stride) return hipErrorInvalidValue;
+  const size_t lds = wl_lds_bytes(a.rb.n_links, a.rb.dof, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0);
+  if (lds > kWlLdsMax) return hipErrorInvalidValue;
   const dim3 grid(grid_x, slices), block(waves * kWave);
-  if (cand && grad) eval_wl_kernel<MAXS, true, true><<<grid, block, lds, s>>>(a);
-  else if (grad) eval_wl_kernel<MAXS, false, true><<<grid, block, lds, s>>>(a);
-  else if (!cand) eval_wl_kernel<MAXS, false, false><<<grid, block, lds, s>>>(a);
-  else eval_wl_kernel<MAXS, true, false><<<grid, block, lds, s>>>(a);
+  if (waves <= 8) {
+    if (cand && grad) eval_wl_kernel<MAXS, true, true, 512><<<grid, block, lds, s>>>(a);
+    else if (grad) eval_wl_kernel<MAXS, false, true, 512><<<grid, block, lds, s>>>(a);
+    else if (!cand) eval_wl_kernel<MAXS, false, false, 512><<<grid, block, lds, s>>>(a);
+    else eval_wl_kernel<MAXS, true, false, 512><<<grid, block, lds, s>>>(a);
+  } else {
+    if (cand && grad) eval_wl_kernel<MAXS, true, true, 1024><<<grid, block, lds, s>>>(a);
+    else if (grad) eval_wl_kernel<MAXS, false, true, 1024><<<grid, block, lds, s>>>(a);
+    else if (!cand) eval_wl_kernel<MAXS, false, false, 1024><<<grid, block, lds, s>>>(a);
+    else eval_wl_kernel<MAXS, true, false, 1024><<<grid, block, lds, s>>>(a);
+  }
   return hipGetLastError();
 }
 

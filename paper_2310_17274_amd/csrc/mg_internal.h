@@ -32,6 +32,8 @@ struct Params {
   int sweep_steps;
   float ls_eta1, ls_eta_w;
   float success_pos, success_rot;
+  float w_self;
+  int n_self;              // self-collision pairs (wave-per-link layout only)
 };
 
 // One motion problem of a batch.  Rows are waypoints: seed s of problem p
@@ -74,12 +76,34 @@ struct WaveLinks {
   const float4* sphere;    // [L][maxs] centre in link frame + radius
   const float4* ball;      // [L] ball bounding the link's spheres (link frame): centre, radius
   int maxs;
+  int max_depth;           // deepest chain (joints from the root)
   // cuboid slices over workgroups (gridDim.y > 1): per-slice partial sums
   // [chunk][slice][2 + D][64] and one arrival counter per chunk (zero
   // between launches; the last workgroup of a chunk resets it)
   float* part;
   int* count;
+  // self-collision: [n_self] pairs {sphere i, sphere j, link_i | link_j << 16,
+  // bits of r_i + r_j}, and the sphere index of every slot [L][maxs]
+  const int4* self_pairs;
+  const int* slot_sphere;
 };
+
+// LDS of a wave-per-link workgroup: the L link waves' parts (2 + deepest
+// chain floats per lane) and the joint wave's (2 + D), or, while the
+// self-collision phase runs, the sphere centres and per-wave winners; then
+// the staged rows (x and d).
+constexpr size_t kWlLdsMax = 64 * 1024;
+constexpr int kWlStageRows = kWave + 8;
+// The self-collision phase runs before any part is written, so its sphere
+// centres and winners share the parts' space.
+__host__ __device__ inline size_t wl_region_floats(int L, int D, int max_depth, int n_spheres, bool self) {
+  const size_t parts = ((size_t)L * (2 + max_depth) + 2 + D) * kWave;
+  const size_t selfb = self ? ((size_t)n_spheres * 3 + 2 * (L + 1)) * kWave : 0;
+  return parts > selfb ? parts : selfb;
+}
+__host__ __device__ inline size_t wl_lds_bytes(int L, int D, int max_depth, int n_spheres, bool self) {
+  return (wl_region_floats(L, D, max_depth, n_spheres, self) + 2 * (size_t)kWlStageRows * D) * sizeof(float);
+}
 
 // Cuboid in the library layout: p = A c + b maps a world point into the box
 // frame (A = R^T, b = -R^T t); h = half side lengths.

@@ -211,11 +211,13 @@ def make_two_arm(seed: int = 0, dof_per_arm: int = 7, n_spheres: int = 120,
                  q_hi=np.full(d2, limit))
 
 
-def make_worlds(seed: int, counts, oriented: bool = True) -> Worlds:
+def make_worlds(seed: int, counts, oriented: bool = True, base_clear: float = 0.12) -> Worlds:
     """Cuboid worlds: sides U(0.05,0.4) m, centers U([-.5,.5]^2 x [0,1]) m.
 
     ``oriented`` draws a uniform random orientation per cuboid (Shoemake),
-    otherwise boxes are axis aligned.
+    otherwise boxes are axis aligned.  Cuboids whose centre lies below 0.6 m
+    and whose enclosing ball comes within ``base_clear`` of the vertical axis
+    through the robot base are redrawn, so the base column is free.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     counts = [int(c) for c in counts]
@@ -224,6 +226,12 @@ def make_worlds(seed: int, counts, oriented: bool = True) -> Worlds:
     centers = np.empty((n, 3))
     centers[:, 0:2] = rng.uniform(-0.5, 0.5, size=(n, 2))
     centers[:, 2] = rng.uniform(0.0, 1.0, size=n)
+    if base_clear > 0:
+        half_diag = 0.5 * np.linalg.norm(dims, axis=1)
+        for i in range(n):
+            while centers[i, 2] < 0.6 and np.hypot(centers[i, 0], centers[i, 1]) < base_clear + half_diag[i]:
+                centers[i, 0:2] = rng.uniform(-0.5, 0.5, size=2)
+                centers[i, 2] = rng.uniform(0.0, 1.0)
     if oriented:
         quat = _random_quaternion(rng, n)
     else:

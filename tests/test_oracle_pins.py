@@ -68,7 +68,7 @@ def test_defaults_match_paper_constants():
     for k in ("a6", "a7", "a8", "a9"):
         assert d[k] == g["smooth_weights"][k]
     assert d["eta2"] == g["bound_band"]["eta2"]
-    assert d["w_bound"] == d["w_coll"] == g["soft_constraint_weight"]["w"]
+    assert d["w_bound"] == d["w_coll"] == d["w_self"] == g["soft_constraint_weight"]["w"]
     assert d["eta"] == g["activation_distance"]["eta"]
     assert d["dt"] == g["first_pass_dt"]["dt"]
     assert tuple(g["line_search_magnitudes"]["alpha"]) == wl.ALPHA_4

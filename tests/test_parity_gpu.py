@@ -30,12 +30,14 @@ def _dev(a):
 class Case:
     """Inputs of one workload on both sides."""
 
-    def __init__(self, robot, worlds, batch, params=None, K_max=16, m_max=8, layout=None):
+    def __init__(self, robot, worlds, batch, params=None, K_max=16, m_max=8, layout=None, self_pairs=None):
         from paper_2310_17274_amd.binding import Context, default_params
         self.robot, self.worlds, self.batch = H.f32_inputs(robot, worlds, batch)
         params = params or {}
         self.ctx = Context(self.robot, default_params(**params))
         self.ctx.mg_set_worlds(self.worlds)
+        if self_pairs is not None:
+            self.ctx.mg_set_self_collision(self_pairs)
         b = self.batch
         self.b = self.ctx.batch(b.seeds, b.horizon, b.world, K_max=K_max, m_max=m_max)
         if layout is not None:
@@ -44,7 +46,8 @@ class Case:
         self.q_start = _dev(b.q_start)
         self.goal = _dev(b.goal.reshape(b.n_problems, -1))
         self.x = _dev(b.x0.reshape(-1, D))
-        self.ref = ref.Ref(self.robot, **params)
+        self.ref = ref.Ref(self.robot, **params) if self_pairs is None else \
+            ref.Ref(self.robot, self_pairs=self_pairs, **params)
 
 
 def make_case(kind, **kw):
@@ -307,6 +310,49 @@ def test_autotuned_layout_keeps_parity():
         torch.cuda.synchronize()
         outs.append((x.cpu().numpy(), bc.cpu().numpy()))
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def _self_case(layout, seed=13, S=6, T=16):
+    robot = wl.make_arm(seed=0, n_spheres=52)
+    worlds = wl.make_worlds(11, [40])
+    batch = wl.make_batch(robot, seed, [S], [T], [0], noise=0.6)
+    return Case(robot, worlds, batch, layout=layout, self_pairs=wl.self_pairs(robot))
+
+
+@pytest.mark.parametrize("layout", [pytest.param(None, id="auto"), pytest.param((1, 4), id="wave4")])
+def test_self_collision_cost_grad_parity(layout):
+    """Self-collision (Eq.(9)) over non-adjacent links' sphere pairs with the
+    world term on; noisy trajectories so that arms fold onto themselves."""
+    case = _self_case(layout)
+    c, g, mc = gpu_cost_grad(case)
+    cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, 7))
+    H.assert_cost_close(c, cr)
+    H.assert_grad_close(g, gr, case.batch)
+    H.assert_verdicts(mc, mcr)
+    selfc = [case.ref.traj_cost(case.worlds.world(0), case.batch.q_start[0], case.batch.goal[0], q,
+                                grad=False)[3][4] for q in case.batch.x0.reshape(6, 16, 7)]
+    assert np.count_nonzero(selfc) >= 2, "the case must contain self-collisions"
+
+
+def test_self_collision_linesearch_parity():
+    case = _self_case(None, seed=17, S=4, T=32)
+    _linesearch_parity(case, wl.ALPHA_4, 1)
+
+
+def test_self_collision_restrictions():
+    """Self-collision lives in the wave-per-link layout: swept collision and
+    the particle stage refuse it."""
+    from paper_2310_17274_amd._lib import MgError
+    case = _self_case(None, S=2, T=8)
+    case.b.mg_batch_reserve_particles(4)
+    eps = torch.zeros((1, 4, 16, 7), device="cuda")
+    var = torch.full_like(case.x, 1e-3)
+    with pytest.raises(MgError):
+        case.ctx.mg_particles(case.b, case.q_start, case.goal, case.x.clone(), var, eps)
+    from paper_2310_17274_amd.binding import Context, default_params
+    ctx = Context(case.robot, default_params(swept=1))
+    with pytest.raises(MgError):
+        ctx.mg_set_self_collision(wl.self_pairs(case.robot))
 
 
 def test_cost_only_matches_cost_grad():
