@@ -55,9 +55,11 @@ def main():
                          "line searches of the benchmark shape (one evaluation launch each), "
                          "'copy' copies 256 MiB five times (HBM byte-counter calibration)")
     ap.add_argument("--launches", type=int, default=10)
-    ap.add_argument("--layout", type=int, choices=[0, 1], default=None,
-                    help="force the evaluation layout (0 lane per link, 1 wave per link) "
-                         "instead of the autotuner's choice")
+    ap.add_argument("--layout", type=int, choices=[0, 1, 2], default=None,
+                    help="force the evaluation layout (0 lane per link, 1 wave per link, "
+                         "2 two waves per link) instead of the autotuner's choice")
+    ap.add_argument("--slices", type=int, choices=[0, 1, 2, 4], default=0,
+                    help="with --layout: cuboid slices (0 automatic)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the uneven-batch and inverse-kinematics measurements")
     args = ap.parse_args()
@@ -98,8 +100,9 @@ def main():
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
     layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
     if args.layout is not None:
-        b.mg_batch_set_layout(args.layout)
-        layout = ("wave_per_link" if args.layout else "lane_per_link") + "/auto"
+        b.mg_batch_set_layout(args.layout, args.slices)
+        layout = ["lane_per_link", "wave_per_link", "two_waves_per_link"][args.layout] + "/" + \
+                 (str(args.slices) if args.slices else "auto")
 
     if args.profile == "eval":
         return profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, args.launches, layout)
@@ -172,7 +175,7 @@ def main():
         "wall_s_timed": wall,
         "best_cost_min": float(best.min()),
         "roofline": {"bound": "alu",
-                     "kernel": ("eval_wl_kernel" if layout.startswith("wave") else "eval_kernel")
+                     "kernel": ("eval_kernel" if layout.startswith("lane") else "eval_wl_kernel")
                                + " (cost + adjoint, 8 candidates)",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(layout),
@@ -205,8 +208,11 @@ def kernel_digest():
 
 
 def layout_name(tuned):
-    """The autotuner's choice as 'lane_per_link/<slices>' or
-    'wave_per_link/<workgroups per 64 evaluations>'."""
+    """The autotuner's choice as 'lane_per_link/<slices>',
+    'wave_per_link/<workgroups per 64 evaluations>' or
+    'two_waves_per_link'."""
+    if tuned == -8:
+        return "two_waves_per_link"
     return f"lane_per_link/{tuned}" if tuned > 0 else f"wave_per_link/{-tuned}"
 
 

@@ -86,6 +86,9 @@ struct mg_ctx {
   int* d_wl_chain = nullptr;
   float4* d_wl_ball = nullptr;
   int* d_slot_sphere = nullptr;  // [L][maxs] sphere index of each slot
+  std::vector<int> slot_of;      // [M] slot (link * maxs + position) of each sphere
+  float4* d_chain_rec = nullptr; // [L][kMaxDof][4] chain transforms and joints
+  int* d_joint_rec = nullptr;    // [D][2] chain position and subtree mask per joint
   int max_depth = 0;             // deepest chain
   int n_self = 0;                // self-collision pairs
   int self_cap = 0;
@@ -124,6 +127,7 @@ struct mg_batch {
   int* d_chunk_wl[mg::kMaxK + 1] = {};
   int chunks_wl[mg::kMaxK + 1] = {};
   int wl_slices = 0;        // wave-per-link cuboid slices over workgroups (0: automatic)
+  int wl_halves = 0;        // wave-per-link waves per link: 1, 2 (0: automatic)
   int wl_slices_max = 1;    // largest the scratch below holds
   float* wl_part = nullptr; // [chunks][slices][2 + D][64]
   int* wl_count = nullptr;  // [chunks], zero between launches
@@ -176,6 +180,7 @@ mg_status build_lanes(mg_ctx* c) {
   for (int m = 0; m < c->M; ++m) {
     const int l = c->sphere_link[m];
     slot_sphere[(size_t)l * maxs + fill[l]] = m;
+    c->slot_of.push_back(l * maxs + fill[l]);
     sph[(size_t)l * maxs + fill[l]++] =
         make_float4(c->sphere[4 * m + 0], c->sphere[4 * m + 1], c->sphere[4 * m + 2], c->sphere[4 * m + 3]);
   }
@@ -184,32 +189,52 @@ mg_status build_lanes(mg_ctx* c) {
   // farthest sphere surface)
   std::vector<int4> wl_info(c->L);
   std::vector<int> wl_chain((size_t)c->L * mg::kMaxDof, 0);
-  std::vector<float4> wl_ball(c->L, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
-  for (int l = 0; l < c->L; ++l) {
-    std::vector<int> ch;
-    for (int u = l; u >= 0; u = c->parent[u]) ch.push_back(u);
-    if ((int)ch.size() > mg::kMaxDof) return fail(MG_ERR_UNSUPPORTED, "chain of link %d deeper than %d", l, mg::kMaxDof);
-    for (size_t i = 0; i < ch.size(); ++i) wl_chain[(size_t)l * mg::kMaxDof + i] = ch[ch.size() - 1 - i];
-    int ee = -1;
-    for (int e = 0; e < c->n_ee; ++e)
-      if (c->ee_link[e] == l) ee = e;
-    wl_info[l] = make_int4((int)ch.size(), count[l], ee, 0);
-    c->max_depth = std::max(c->max_depth, (int)ch.size());
-    if (count[l] == 0) continue;
+  std::vector<float4> chain_rec((size_t)c->L * mg::kMaxDof * 4, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+  std::vector<float4> wl_ball((size_t)c->L * 3, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+  // ball around slots [s0, s1) of link l: centre of their bounding box,
+  // radius to the farthest sphere surface (slightly widened)
+  auto ball_of = [&](int l, int s0, int s1) {
+    if (s1 <= s0) return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
-    for (int s = 0; s < count[l]; ++s) {
+    for (int s = s0; s < s1; ++s) {
       const float4 q = sph[(size_t)l * maxs + s];
       const float v[3] = {q.x, q.y, q.z};
       for (int i = 0; i < 3; ++i) { lo[i] = std::min(lo[i], v[i]); hi[i] = std::max(hi[i], v[i]); }
     }
     const float ctr[3] = {0.5f * (lo[0] + hi[0]), 0.5f * (lo[1] + hi[1]), 0.5f * (lo[2] + hi[2])};
     double rad = 0.0;
-    for (int s = 0; s < count[l]; ++s) {
+    for (int s = s0; s < s1; ++s) {
       const float4 q = sph[(size_t)l * maxs + s];
       const double dx = q.x - ctr[0], dy = q.y - ctr[1], dz = q.z - ctr[2];
       rad = std::max(rad, std::sqrt(dx * dx + dy * dy + dz * dz) + q.w);
     }
-    wl_ball[l] = make_float4(ctr[0], ctr[1], ctr[2], (float)(rad * 1.0001 + 1e-6));
+    return make_float4(ctr[0], ctr[1], ctr[2], (float)(rad * 1.0001 + 1e-6));
+  };
+  for (int l = 0; l < c->L; ++l) {
+    std::vector<int> ch;
+    for (int u = l; u >= 0; u = c->parent[u]) ch.push_back(u);
+    if ((int)ch.size() > mg::kMaxDof) return fail(MG_ERR_UNSUPPORTED, "chain of link %d deeper than %d", l, mg::kMaxDof);
+    for (size_t i = 0; i < ch.size(); ++i) {
+      const int u = ch[ch.size() - 1 - i];
+      wl_chain[(size_t)l * mg::kMaxDof + i] = u;
+      float4* r = &chain_rec[((size_t)l * mg::kMaxDof + i) * 4];
+      for (int k = 0; k < 3; ++k)
+        r[k] = make_float4(c->fixed_tf[u * 12 + 4 * k + 0], c->fixed_tf[u * 12 + 4 * k + 1],
+                           c->fixed_tf[u * 12 + 4 * k + 2], c->fixed_tf[u * 12 + 4 * k + 3]);
+      int j = c->joint[u];
+      float jf;
+      memcpy(&jf, &j, sizeof(jf));
+      r[3] = make_float4(jf, 0.0f, 0.0f, 0.0f);
+    }
+    int ee = -1;
+    for (int e = 0; e < c->n_ee; ++e)
+      if (c->ee_link[e] == l) ee = e;
+    wl_info[l] = make_int4((int)ch.size(), count[l], ee, 0);
+    c->max_depth = std::max(c->max_depth, (int)ch.size());
+    const int half = maxs / 2;
+    wl_ball[3 * l + 0] = ball_of(l, 0, count[l]);
+    wl_ball[3 * l + 1] = ball_of(l, 0, std::min(count[l], half));
+    wl_ball[3 * l + 2] = ball_of(l, half, count[l]);
   }
   mg_status st;
   if ((st = dev_upload(&c->d_lane_info, info)) != MG_OK) return st;
@@ -217,6 +242,19 @@ mg_status build_lanes(mg_ctx* c) {
   if ((st = dev_upload(&c->d_wl_chain, wl_chain)) != MG_OK) return st;
   if ((st = dev_upload(&c->d_wl_ball, wl_ball)) != MG_OK) return st;
   if ((st = dev_upload(&c->d_slot_sphere, slot_sphere)) != MG_OK) return st;
+  if ((st = dev_upload(&c->d_chain_rec, chain_rec)) != MG_OK) return st;
+  // joint j drives link j: its chain position is that link's depth - 1, and
+  // it is on the chain of every link whose chain passes through link j
+  std::vector<int> joint_rec(2 * (size_t)c->D, 0);
+  for (int l = 0; l < c->L; ++l) {
+    const int d = wl_info[l].x;
+    for (int i = 0; i < d; ++i) {
+      const int u = wl_chain[(size_t)l * mg::kMaxDof + i];
+      joint_rec[2 * u + 0] = i;
+      if (l < 31) joint_rec[2 * u + 1] |= 1 << l;
+    }
+  }
+  if ((st = dev_upload(&c->d_joint_rec, joint_rec)) != MG_OK) return st;
   return dev_upload(&c->d_lane_sphere, sph);
 }
 
@@ -237,10 +275,13 @@ mg::WaveLinks dev_wave_links(const mg_ctx* c) {
   wl.ball = c->d_wl_ball;
   wl.maxs = c->maxs;
   wl.max_depth = c->max_depth;
+  wl.halves = 1;
   wl.part = nullptr;
   wl.count = nullptr;
   wl.self_pairs = c->d_self_pairs;
   wl.slot_sphere = c->d_slot_sphere;
+  wl.chain_rec = c->d_chain_rec;
+  wl.joint_rec = c->d_joint_rec;
   return wl;
 }
 
@@ -248,7 +289,12 @@ mg::WaveLinks dev_wave_links(const mg_ctx* c) {
 // swept collision.
 bool wl_possible(const mg_ctx* c, bool self) {
   return c->L + 1 <= 16 && !c->params.swept &&
-         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, self) <= mg::kWlLdsMax;
+         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, self, 1) <= mg::kWlLdsMax;
+}
+// two waves per link: at most 8 links (16 waves) and the LDS for the hand-over
+bool wl_halves_possible(const mg_ctx* c) {
+  return 2 * c->L <= 16 && !c->params.swept &&
+         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, c->n_self > 0, 2) <= mg::kWlLdsMax;
 }
 bool wl_possible(const mg_ctx* c) { return wl_possible(c, c->n_self > 0); }
 
@@ -359,7 +405,11 @@ hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool gr
     a.chunk_prefix = b->d_chunk_wl[a.K];
     a.wl.part = b->wl_part;
     a.wl.count = b->wl_count;
-    return mg::launch_eval_wl(a, b->chunks_wl[a.K], wl_slices(b, a.K), cand, grad, s);
+    // two waves per link where they fit (shorter waves), unless forced
+    const int halves = b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(b->ctx) ? 2 : 1);
+    if (halves == 2 && !wl_halves_possible(b->ctx)) return hipErrorInvalidValue;
+    a.wl.halves = halves;
+    return mg::launch_eval_wl(a, b->chunks_wl[a.K], halves == 2 ? 1 : wl_slices(b, a.K), cand, grad, s);
   }
   return mg::launch_eval(a, b->chunks[hi], cand, grad, s);
 }
@@ -539,7 +589,7 @@ void mg_destroy(mg_ctx* c) {
   dev_free(c->d_fixed_tf); dev_free(c->d_joint); dev_free(c->d_q_lo); dev_free(c->d_q_hi); dev_free(c->d_ee_tf);
   dev_free(c->d_lane_info); dev_free(c->d_lane_sphere);
   dev_free(c->d_wl_info); dev_free(c->d_wl_chain); dev_free(c->d_wl_ball);
-  dev_free(c->d_slot_sphere); dev_free(c->d_self_pairs);
+  dev_free(c->d_slot_sphere); dev_free(c->d_self_pairs); dev_free(c->d_chain_rec); dev_free(c->d_joint_rec);
   dev_free(c->d_box); dev_free(c->d_world_off);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
@@ -799,19 +849,25 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
   if ((st = check_K_alpha(b, K, alpha)) != MG_OK) return st;
   if (!q_start || !goal || !x || !dir) return fail(MG_ERR_ARG, "null argument");
   if (launches < 1) return fail(MG_ERR_ARG, "launches must be >= 1");
-  // candidates: lane per link with 1, 2 or 4 cuboid slices per workgroup,
-  // wave per link with 1, 2 or 4 workgroups per 64 evaluations
-  int best = c->n_self > 0 ? kNumSlices : 0;
-  float best_us = 3.0e38f;
-  int n_wl = 0;
+  // candidates: lane per link with 1, 2 or 4 cuboid slices per workgroup;
+  // wave per link with two waves per link; wave per link with 1, 2 or 4
+  // workgroups per 64 evaluations.  Each is {layout, slices index, halves,
+  // workgroup slices}.
+  struct Opt { int layout, hi, halves, wls; };
+  std::vector<Opt> opts;
+  if (c->n_self == 0)
+    for (int hi = 0; hi < kNumSlices; ++hi) opts.push_back({0, hi, 0, 0});
+  if (wl_halves_possible(c)) opts.push_back({1, -1, 2, 1});
   if (wl_possible(c))
-    for (int h = 1; h <= b->wl_slices_max; h *= 2) ++n_wl;
-  const int n_opt = kNumSlices + n_wl;
-  for (int o = 0; o < n_opt; ++o) {
-    if (o < kNumSlices && c->n_self > 0) continue;   // not evaluated by lane per link
-    b->layout = o < kNumSlices ? 0 : 1;
-    b->slices = o < kNumSlices ? o : 0;
-    b->wl_slices = o < kNumSlices ? 0 : 1 << (o - kNumSlices);
+    for (int h = 1; h <= b->wl_slices_max; h *= 2) opts.push_back({1, -1, 1, h});
+  if (opts.empty()) return fail(MG_ERR_UNSUPPORTED, "no evaluation layout fits this robot");
+  size_t best = 0;
+  float best_us = 3.0e38f;
+  for (size_t o = 0; o < opts.size(); ++o) {
+    b->layout = opts[o].layout;
+    b->slices = opts[o].hi;
+    b->wl_halves = opts[o].halves;
+    b->wl_slices = opts[o].wls;
     float us = 0.0f;
     // one untimed launch per layout first (code upload, caches)
     if ((st = mg_time_eval(c, b, q_start, goal, x, dir, K, alpha, 1, &us, stream)) != MG_OK ||
@@ -819,15 +875,19 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
       b->slices = -1;
       b->layout = -1;
       b->wl_slices = 0;
+      b->wl_halves = 0;
       return st;
     }
     if (us < best_us) { best_us = us; best = o; }
   }
-  b->layout = best < kNumSlices ? 0 : 1;
-  b->slices = best < kNumSlices ? best : -1;
-  b->wl_slices = best < kNumSlices ? 0 : 1 << (best - kNumSlices);
-  // lane per link: the slice count; wave per link: minus the workgroups per chunk
-  if (slices_out) *slices_out = best < kNumSlices ? kSlices[best] : -b->wl_slices;
+  b->layout = opts[best].layout;
+  b->slices = opts[best].hi;
+  b->wl_halves = opts[best].halves;
+  b->wl_slices = opts[best].wls;
+  // lane per link: the slice count; wave per link: minus the workgroups per
+  // 64 evaluations, or -8 for two waves per link
+  if (slices_out)
+    *slices_out = opts[best].layout == 0 ? kSlices[opts[best].hi] : (opts[best].halves == 2 ? -8 : -opts[best].wls);
   return MG_OK;
 }
 
@@ -845,7 +905,9 @@ mg_status mg_set_self_collision(mg_ctx* c, int n_pairs, const int* pairs) {
     const float rs = c->sphere[4 * i + 3] + c->sphere[4 * j + 3];
     int bits;
     memcpy(&bits, &rs, sizeof(bits));
-    pr[k] = make_int4(i, j, c->sphere_link[i] | (c->sphere_link[j] << 16), bits);
+    // owners: link and slot position within the link of each sphere
+    const int pi = c->slot_of[i] % c->maxs, pj = c->slot_of[j] % c->maxs;
+    pr[k] = make_int4(i, j, c->sphere_link[i] | (c->sphere_link[j] << 8) | (pi << 16) | (pj << 24), bits);
   }
   if (n_pairs > c->self_cap) {
     HIP_TRY(hipDeviceSynchronize());
@@ -882,9 +944,19 @@ mg_status mg_ee_pose(mg_ctx* c, int rows, const float* q, float* pose, void* str
 
 mg_status mg_batch_set_layout(mg_batch* b, int layout, int slices) {
   if (!b) return fail(MG_ERR_ARG, "null batch");
-  if (layout < -1 || layout > 1) return fail(MG_ERR_ARG, "layout must be -1, 0 or 1");
-  if (layout == 1 && !wl_possible(b->ctx))
+  if (layout < -1 || layout > 2) return fail(MG_ERR_ARG, "layout must be -1, 0, 1 or 2");
+  if (layout >= 1 && !wl_possible(b->ctx))
     return fail(MG_ERR_UNSUPPORTED, "the wave-per-link layout needs at most 15 links and no swept collision");
+  if (layout == 2 && !wl_halves_possible(b->ctx))
+    return fail(MG_ERR_UNSUPPORTED, "two waves per link need at most 8 links");
+  b->wl_halves = layout == 2 ? 2 : (layout == 1 ? 1 : 0);
+  if (layout == 2) {
+    if (slices > 1) return fail(MG_ERR_ARG, "two waves per link take one workgroup per 64 evaluations");
+    b->layout = 1;
+    b->slices = -1;
+    b->wl_slices = 1;
+    return MG_OK;
+  }
   int hi = -1;
   if (slices != 0) {
     for (int i = 0; i < kNumSlices; ++i)
@@ -1018,6 +1090,7 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
     key_push(key, mode); key_push(key, graph_inner); key_push(key, c->params);
     key_push(key, c->d_box); key_push(key, c->d_world_off); key_push(key, b->slices);
     key_push(key, b->layout); key_push(key, b->wl_slices); key_push(key, c->n_self);
+    key_push(key, b->wl_halves);
     for (int k = 0; k < K; ++k) key_push(key, alpha[k]);
     if (!b->gexec || key != b->gkey) {
       if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }

@@ -95,11 +95,13 @@ __device__ __forceinline__ void pose_term(const EvalArgs& a, int p, int ee, cons
 // whose five-point stencils (centred at t-1..t+3 on the padded trajectory:
 // the start before waypoint 1, the last waypoint after T) touch this state.
 // jc receives the terms this waypoint owns, js d cost / d q_j.  qj is the
-// (candidate) value at row, qval(r, j) the value at another row.
+// (candidate) value at row, qval(r, j) the value at another row; lo_, hi_
+// are joint j's limits and q0 its start value.
 template <typename QV>
-__device__ __forceinline__ void joint_terms(const EvalArgs& a, const Problem& pb, int p, int row, int t,
-                                            int j, float qj, QV&& qval, float& jc, float& js) {
-  const float lo_ = a.rb.q_lo[j], hi_ = a.rb.q_hi[j], e2 = a.pr.eta2, wb = a.pr.w_bound;
+__device__ __forceinline__ void joint_terms(const EvalArgs& a, const Problem& pb, int row, int t, int j,
+                                            float qj, float lo_, float hi_, float q0, QV&& qval,
+                                            float& jc, float& js) {
+  const float e2 = a.pr.eta2, wb = a.pr.w_bound;
   const float inv_e2 = 1.0f / e2;
   float bc = 0.0f, bs = 0.0f;
   if (qj < lo_) { bc += lo_ - qj + 0.5f * e2; bs -= 1.0f; }
@@ -110,9 +112,7 @@ __device__ __forceinline__ void joint_terms(const EvalArgs& a, const Problem& pb
   js += wb * bs;
   if (pb.T <= 1) return;
   // padded states X(s), s = w-4..w+4 around this waypoint w = t+1
-  const int D = a.rb.dof;
   const int w1 = t + 1, Tn = pb.T;
-  const float q0 = a.q_start[(size_t)p * D + j];
   float X[9];
 #pragma unroll
   for (int u = 0; u < 9; ++u) {
@@ -317,7 +317,8 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
     // ---- joint l: limit cost (Eq.(17)) and smoothness (Eq.(16)); every lane
     //      computes (clamped joint), lanes l >= D discard the result ----
     float jc = 0.0f, js = 0.0f;
-    joint_terms(a, pb, p, row, t, lj, ql, qval, jc, js);
+    joint_terms(a, pb, row, t, lj, ql, a.rb.q_lo[lj], a.rb.q_hi[lj], a.q_start[(size_t)p * D + lj], qval,
+                jc, js);
     cost += l < D ? jc : 0.0f;
     gsm = l < D ? js : 0.0f;
   }

@@ -70,35 +70,70 @@ __device__ __forceinline__ void self_winner(int W, const float* s_best, int lane
   }
 }
 
+// Pose of link l: the chain from the root, joint by joint (Tab.6: fixed
+// transform, then the rotation about z).  Each joint's record (fixed
+// transform rows and joint index) is loaded one joint ahead, so the scalar
+// loads overlap the previous joint's arithmetic.  visit(i, T) sees the pose
+// after chain position i.
+template <typename QV, typename VIS>
+__device__ __forceinline__ void chain_fk(const EvalArgs& a, int l, int depth, int row, QV&& qval,
+                                         float* T, VIS&& visit) {
+  cv4f* rec = (cv4f*)(a.wl.chain_rec + (size_t)l * kMaxDof * 4);
+  identity(T);
+  v4f n0 = rec[0], n1 = rec[1], n2 = rec[2], n3 = rec[3];
+  for (int i = 0; i < depth; ++i) {
+    const v4f f0 = n0, f1 = n1, f2 = n2;
+    const int c = __float_as_int(n3.x);
+    if (i + 1 < depth) {
+      n0 = rec[4 * (i + 1) + 0]; n1 = rec[4 * (i + 1) + 1];
+      n2 = rec[4 * (i + 1) + 2]; n3 = rec[4 * (i + 1) + 3];
+    }
+    const float q = qval(row, c);
+    const float sn = __sinf(q), cs = __cosf(q);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const float t0 = T[r * 4 + 0], t1 = T[r * 4 + 1], t2 = T[r * 4 + 2], t3 = T[r * 4 + 3];
+      const float u0 = t0 * f0.x + t1 * f1.x + t2 * f2.x;
+      const float u1 = t0 * f0.y + t1 * f1.y + t2 * f2.y;
+      T[r * 4 + 2] = t0 * f0.z + t1 * f1.z + t2 * f2.z;
+      T[r * 4 + 3] = t0 * f0.w + t1 * f1.w + t2 * f2.w + t3;
+      // then Rz(q): the first two columns mix
+      T[r * 4 + 0] = u0 * cs + u1 * sn;
+      T[r * 4 + 1] = u1 * cs - u0 * sn;
+    }
+    visit(i, T);
+  }
+}
+
 // Collision, pose and adjoint of link l for this lane's evaluation.
 // part[q * kWave + lane]: q = 0 cost, 1 clearance, 2 + i d cost / d q of the
 // joint at chain position i (root first).
+// With HS = 2 a link has two waves, each with half of its sphere slots
+// (hs = 0, 1); the second also owns joint l's limit and smoothness terms and
+// hands its sums to the first (s_ex), which runs the adjoint.  Returns false
+// for a wave whose part is handed over.
 template <int MAXS, bool GRAD, typename QV>
-__device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const Problem& pb, int row,
-                                          int t, bool valid, int h, int H, QV&& qval, float* part,
-                                          int lane, bool self_on, float* s_sph, float* s_best, int W) {
+__device__ __forceinline__ bool link_wave(const EvalArgs& a, int l, int hs, int HS, int p,
+                                          const Problem& pb, int row, int t, bool valid, int h, int H,
+                                          QV&& qval, float* part, int lane, bool self_on, float* s_sph,
+                                          float* s_best, int W, float* s_ex, const float* s_lim) {
   // per-link tables through the constant address space (wave-uniform)
   const v4i info = *(cv4i*)(a.wl.info + l);
-  const int depth = info.x, ns = info.y, ee = info.z;
-  cint* chain = (cint*)(a.wl.chain + l * kMaxDof);
+  const int depth = info.x, ee = info.z;
+  const int sbase = l * a.wl.maxs + hs * MAXS;          // this wave's first slot
+  const int ns = min(max(info.y - hs * MAXS, 0), MAXS);  // and how many it has
 
   // ---- forward kinematics along the chain ----
   float T[12];
-  identity(T);
-  for (int i = 0; i < depth; ++i) {
-    const int c = chain[i];
-    const float q = qval(row, c);
-    compose_u(T, (cfloat*)(a.rb.fixed_tf + c * 12));
-    rotz(T, __sinf(q), __cosf(q));
-  }
+  chain_fk(a, l, depth, row, qval, T, [](int, const float*) {});
 
   float cost = 0.0f, mc = a.pr.eta;
   float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, Mx = 0.0f, My = 0.0f, Mz = 0.0f;
-  if (ee >= 0 && h == 0 && t == pb.T - 1)
+  if (ee >= 0 && hs == 0 && h == 0 && t == pb.T - 1)
     pose_term(a, p, ee, T, valid ? row : -1, cost, Fx, Fy, Fz, Mx, My, Mz);
 
-  // ---- the link's spheres ----
-  cv4f* sph = (cv4f*)(a.wl.sphere + l * MAXS);
+  // ---- the link's spheres (this wave's share) ----
+  cv4f* sph = (cv4f*)(a.wl.sphere + sbase);
   float cx[MAXS], cy[MAXS], cz[MAXS], rr[MAXS];
 #pragma unroll
   for (int s = 0; s < MAXS; ++s) {
@@ -113,7 +148,7 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
 
   // ---- self-collision (Eq.(9)): the winning pair's forces on this link ----
   if (self_on) {
-    cint* sm = (cint*)(a.wl.slot_sphere + l * MAXS);
+    cint* sm = (cint*)(a.wl.slot_sphere + sbase);
 #pragma unroll
     for (int s = 0; s < MAXS; ++s)
       if (s < ns) {
@@ -123,15 +158,20 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
         s_sph[(m * 3 + 2) * kWave + lane] = cz[s];
       }
     __syncthreads();
-    self_pairs_phase(a, l, W, s_sph, s_best, lane);
+    self_pairs_phase(a, l * HS + hs, W, s_sph, s_best, lane);
     __syncthreads();
     float bv;
     int bk;
     self_winner(W, s_best, lane, bv, bk);
+    if (HS == 2 && l == 0 && hs == 1) cost += a.pr.w_self * bv;   // (no joint wave)
     if (bk >= 0) {
       const int4 pr = reinterpret_cast<const int4*>(a.wl.self_pairs)[bk];
-      const int li = pr.z & 0xffff, lj = pr.z >> 16;
-      if (li == l || lj == l) {
+      // owners: link and slot position of each sphere (this wave holds
+      // positions hs * MAXS .. hs * MAXS + MAXS - 1 of its link)
+      const int li = pr.z & 0xff, lj = (pr.z >> 8) & 0xff;
+      const bool own_i = li == l && ((pr.z >> 16) & 0xff) / MAXS == hs;
+      const bool own_j = lj == l && ((pr.z >> 24) & 0xff) / MAXS == hs;
+      if (own_i || own_j) {
         const float xi = s_sph[(pr.x * 3 + 0) * kWave + lane], yi = s_sph[(pr.x * 3 + 1) * kWave + lane];
         const float zi = s_sph[(pr.x * 3 + 2) * kWave + lane];
         const float xj = s_sph[(pr.y * 3 + 0) * kWave + lane], yj = s_sph[(pr.y * 3 + 1) * kWave + lane];
@@ -142,11 +182,11 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
           // d cost / d x_i = -w (x_i - x_j) / d, the opposite on x_j
           const float f = -a.pr.w_self / d;
           const float fx = f * ux, fy = f * uy, fz = f * uz;
-          if (li == l) {
+          if (own_i) {
             Fx += fx; Fy += fy; Fz += fz;
             Mx += yi * fz - zi * fy; My += zi * fx - xi * fz; Mz += xi * fy - yi * fx;
           }
-          if (lj == l) {
+          if (own_j) {
             Fx -= fx; Fy -= fy; Fz -= fz;
             Mx -= yj * fz - zj * fy; My -= zj * fx - xj * fz; Mz -= xj * fy - yj * fx;
           }
@@ -157,14 +197,14 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
   }
 
   // ---- world collision of the link's spheres, cuboid slice h of H ----
-  const int wa = a.world_off[pb.world], wb = a.world_off[pb.world + 1];
+  const int wa = ((cint*)a.world_off)[pb.world], wb = ((cint*)a.world_off)[pb.world + 1];
   const int per = (wb - wa + H - 1) / H;
   const int w0 = min(wb, wa + h * per), w1 = min(wb, w0 + per);
   if (ns > 0 && w1 > w0) {
     const float w = a.pr.w_coll, eta = a.pr.eta, inv_eta = 1.0f / fmaxf(eta, 1e-30f);
     // ball around the link's spheres of every lane: centre of the lanes'
     // bounding box of ball centres, radius half its diagonal + ball radius
-    const v4f bl = *(cv4f*)(a.wl.ball + l);
+    const v4f bl = *(cv4f*)(a.wl.ball + l * 3 + (HS == 2 ? 1 + hs : 0));
     const float bx = T[0] * bl.x + T[1] * bl.y + T[2] * bl.z + T[3];
     const float by = T[4] * bl.x + T[5] * bl.y + T[6] * bl.z + T[7];
     const float bz = T[8] * bl.x + T[9] * bl.y + T[10] * bl.z + T[11];
@@ -194,13 +234,28 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
         const float m3 = fmaxf(fabsf(px) - BH.x, fmaxf(fabsf(py) - BH.y, fabsf(pz) - BH.z));
         cand = m3 < Rw;
       }
-      uint64_t mask = __ballot(cand);
-      while (mask) {
-        const int kk = __builtin_ctzll(mask);
+      // (the mask made scalar, so the candidate index and its loads are too)
+      const uint64_t bal = __ballot(cand);
+      uint64_t mask = ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(bal >> 32)) << 32) |
+                      (unsigned)__builtin_amdgcn_readfirstlane((unsigned)bal);
+      // the next candidate's scalar loads are issued one iteration ahead
+      v4f nA0 = {}, nA1 = {}, nA2 = {}, nH = {};
+      if (mask) {
+        const int ob = base + __builtin_ctzll(mask);
+        nA0 = boxes[4 * ob + 0]; nA1 = boxes[4 * ob + 1];
+        nA2 = boxes[4 * ob + 2]; nH = boxes[4 * ob + 3];
         mask &= mask - 1;
-        const int ob = base + kk;
-        const v4f A0 = boxes[4 * ob + 0], A1 = boxes[4 * ob + 1];
-        const v4f A2 = boxes[4 * ob + 2], Hh = boxes[4 * ob + 3];
+      }
+      bool more = bal != 0;
+      while (more) {
+        const v4f A0 = nA0, A1 = nA1, A2 = nA2, Hh = nH;
+        more = mask != 0;
+        if (more) {
+          const int ob = base + __builtin_ctzll(mask);
+          nA0 = boxes[4 * ob + 0]; nA1 = boxes[4 * ob + 1];
+          nA2 = boxes[4 * ob + 2]; nH = boxes[4 * ob + 3];
+          mask &= mask - 1;
+        }
         // second level: this lane's own ball; the wave skips the cuboid
         // when no lane's ball reaches it
         {
@@ -248,28 +303,47 @@ __device__ __forceinline__ void link_wave(const EvalArgs& a, int l, int p, const
       }
     }
   }
+  float own_js = 0.0f;
+  if (HS == 2) {
+    // the second wave adds joint l's own terms and hands its sums over
+    float* ex = s_ex + (size_t)l * 9 * kWave;
+    if (hs == 1) {
+      float jc = 0.0f, js = 0.0f;
+      joint_terms(a, pb, row, t, l, qval(row, l), s_lim[l], s_lim[a.rb.dof + l], s_lim[2 * a.rb.dof + l],
+                  qval, jc, js);
+      ex[0 * kWave + lane] = cost + jc;
+      ex[1 * kWave + lane] = mc;
+      ex[2 * kWave + lane] = Fx; ex[3 * kWave + lane] = Fy; ex[4 * kWave + lane] = Fz;
+      ex[5 * kWave + lane] = Mx; ex[6 * kWave + lane] = My; ex[7 * kWave + lane] = Mz;
+      ex[8 * kWave + lane] = js;
+    }
+    __syncthreads();
+    if (hs == 1) return false;
+    cost += ex[0 * kWave + lane];
+    mc = fminf(mc, ex[1 * kWave + lane]);
+    Fx += ex[2 * kWave + lane]; Fy += ex[3 * kWave + lane]; Fz += ex[4 * kWave + lane];
+    Mx += ex[5 * kWave + lane]; My += ex[6 * kWave + lane]; Mz += ex[7 * kWave + lane];
+    own_js = ex[8 * kWave + lane];
+  }
   part[0 * kWave + lane] = cost;
   part[1 * kWave + lane] = mc;
+  part[(2 + a.wl.max_depth) * kWave + lane] = own_js;
 
   // ---- adjoint: the chain again, joint c's derivative z_c . (M - o_c x F) ----
   if (GRAD) {
-    identity(T);
-    for (int i = 0; i < depth; ++i) {
-      const int c = chain[i];
-      const float q = qval(row, c);
-      compose_u(T, (cfloat*)(a.rb.fixed_tf + c * 12));
-      rotz(T, __sinf(q), __cosf(q));
-      const float zx = T[2], zy = T[6], zz = T[10], ox = T[3], oy = T[7], oz = T[11];
+    chain_fk(a, l, depth, row, qval, T, [&](int i, const float* P) {
+      const float zx = P[2], zy = P[6], zz = P[10], ox = P[3], oy = P[7], oz = P[11];
       const float vx = Mx - (oy * Fz - oz * Fy);
       const float vy = My - (oz * Fx - ox * Fz);
       const float vz = Mz - (ox * Fy - oy * Fx);
       part[(2 + i) * kWave + lane] = zx * vx + zy * vy + zz * vz;
-    }
+    });
   }
+  return true;
 }
 
-// NT: launch bound (512 threads for robots of up to 7 links, which leaves
-// the register budget of two waves per SIMD; 1024 otherwise)
+// NT: launch bound, 512 threads for robots of up to 7 links (register
+// budget of two waves per SIMD), else 1024.
 template <int MAXS, bool CAND, bool GRAD, int NT>
 __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   extern __shared__ float s_part[];
@@ -278,14 +352,23 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const int L = a.rb.n_links, D = a.rb.dof, K = a.K;
   const int bx = blockIdx.x;
   int lo = 0, hi = a.P;
+  cint* chunk_prefix = (cint*)a.chunk_prefix;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (a.chunk_prefix[mid] <= bx) lo = mid; else hi = mid;
+    if (chunk_prefix[mid] <= bx) lo = mid; else hi = mid;
   }
-  const int p = lo;
-  const Problem pb = a.prob[p];
+  // (the problem, its table row and everything derived from them are wave
+  // uniform; reading them through the constant address space keeps them in
+  // scalar registers, so the cuboid loop below runs on scalar loads)
+  const int p = __builtin_amdgcn_readfirstlane(lo);
+  Problem pb;
+  {
+    const v4i p0 = ((cv4i*)(a.prob + p))[0], p1 = ((cv4i*)(a.prob + p))[1];
+    pb.S = p0.x; pb.T = p0.y; pb.world = p0.z; pb.row0 = p0.w;
+    pb.seed0 = p1.x; pb.pad0 = p1.y; pb.pad1 = p1.z; pb.pad2 = p1.w;
+  }
   const int n_e = pb.S * pb.T * K;
-  const int e0 = (bx - a.chunk_prefix[p]) * kWave + lane;
+  const int e0 = (bx - chunk_prefix[p]) * kWave + lane;
   const bool valid = e0 < n_e;
   const int e = valid ? e0 : n_e - 1;
   const int rl = e / K, k = e - rl * K;       // candidates of a row side by side
@@ -294,26 +377,39 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const float alpha = CAND ? a.alpha[k < kMaxK ? k : 0] : 0.0f;
   const float* dk = CAND ? a.d : nullptr;     // one direction for every candidate
 
-  // LDS: the link waves' parts (2 + deepest chain each), the joint wave's
-  // part (2 + D), self-collision spheres and winners, staged rows
-  const int W = L + 1;
+  // waves: one per link and one for the joint terms (HS = 1), or two per
+  // link with half of its spheres each (HS = 2, robots of up to 8 links)
+  const int HS = a.wl.halves;
+  const int W = HS == 2 ? 2 * L : L + 1;
+  // LDS: the link parts (3 + deepest chain each: cost, clearance, the
+  // chain's derivatives, the own joint's terms), the joint part (2 + D), the
+  // halves' hand-over (9 per link), or, during the self-collision phase, the
+  // sphere centres and winners; then the staged rows
   const int NP = 2 + D;
-  const int NPL = 2 + a.wl.max_depth;
+  const int NPL = 3 + a.wl.max_depth;
   float* s_joint = s_part + (size_t)L * NPL * kWave;
+  float* s_ex = s_joint + (size_t)NP * kWave;
 
   // the workgroup's rows and the four on either side (the stencils' reach)
   // are staged in LDS once: every wave reads its joint values from there
-  const int e_first = (bx - a.chunk_prefix[p]) * kWave;
+  const int e_first = (bx - chunk_prefix[p]) * kWave;
   const int e_last = min(n_e, e_first + kWave) - 1;
   const int p_end = pb.row0 + pb.S * pb.T;
   const int r_lo = max(pb.row0, pb.row0 + e_first / K - 4);
   const int r_hi = min(p_end - 1, pb.row0 + e_last / K + 4);
   const int n_st = (r_hi - r_lo + 1) * D;
-  float* s_x = s_part + wl_region_floats(L, D, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0);
+  float* s_x = s_part + wl_region_floats(L, D, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0, HS);
   float* s_d = s_x + kStageRows * D;
+  // and the joint limits and the problem's start (lower, upper, start)
+  float* s_lim = s_d + kStageRows * D;
   for (int i = threadIdx.x; i < n_st; i += blockDim.x) {
     s_x[i] = a.x[(size_t)r_lo * D + i];
     if (CAND) s_d[i] = dk[(size_t)r_lo * D + i];
+  }
+  for (int i = threadIdx.x; i < D; i += blockDim.x) {
+    s_lim[i] = a.rb.q_lo[i];
+    s_lim[D + i] = a.rb.q_hi[i];
+    s_lim[2 * D + i] = a.q_start[(size_t)p * D + i];
   }
   __syncthreads();
   auto qval = [&](int r, int j) -> float {
@@ -321,21 +417,23 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     float v = s_x[i];
     if (CAND) {
       v = fmaf(alpha, s_d[i], v);
-      v = fminf(fmaxf(v, a.rb.q_lo[j]), a.rb.q_hi[j]);
+      v = fminf(fmaxf(v, s_lim[j]), s_lim[D + j]);
     }
     return v;
   };
 
   // cuboid slice of this workgroup (gridDim.y slices share a chunk)
-  const int h = blockIdx.y, H = gridDim.y;
-  float* part = wave < L ? s_part + (size_t)wave * NPL * kWave : s_joint;
+  const int h = __builtin_amdgcn_readfirstlane(blockIdx.y), H = __builtin_amdgcn_readfirstlane(gridDim.y);
+  const int n_link_waves = L * HS;
+  float* part = wave < n_link_waves ? s_part + (size_t)(wave / HS) * NPL * kWave : s_joint;
   // self-collision in the first slice: sphere centres and per-wave winners
   // follow the wave parts in LDS
   const bool self_on = a.pr.n_self > 0 && h == 0;
   float* s_sph = s_part;     // (shares the parts' space, see link_wave)
   float* s_best = s_sph + (size_t)a.rb.n_spheres * 3 * kWave;
-  if (wave < L) {
-    link_wave<MAXS, GRAD>(a, wave, p, pb, row, t, valid, h, H, qval, part, lane, self_on, s_sph, s_best, W);
+  if (wave < n_link_waves) {
+    link_wave<MAXS, GRAD>(a, wave / HS, wave % HS, HS, p, pb, row, t, valid, h, H, qval, part, lane,
+                          self_on, s_sph, s_best, W, s_ex, s_lim);
   } else {
     float jc = 0.0f;
     if (self_on) {
@@ -351,14 +449,15 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     // joint limits (Eq.(17)) and smoothness (Eq.(16)): joints j = h mod H
     for (int j = 0; j < D; ++j) {
       float js = 0.0f;
-      if (j % H == h) joint_terms(a, pb, p, row, t, j, qval(row, j), qval, jc, js);
+      if (j % H == h)
+        joint_terms(a, pb, row, t, j, qval(row, j), s_lim[j], s_lim[D + j], s_lim[2 * D + j], qval, jc, js);
       part[(2 + j) * kWave + lane] = js;
     }
     part[0 * kWave + lane] = jc;
     part[1 * kWave + lane] = a.pr.eta;
   }
   __syncthreads();
-  if (wave != L) return;
+  if (wave != W - 1) return;
 
   // ---- the last wave sums the waves' parts in a fixed order: links in
   //      order, then its own; joint derivatives gather into its part ----
@@ -367,15 +466,24 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     cost += s_part[(v * NPL + 0) * kWave + lane];
     mc = fminf(mc, s_part[(v * NPL + 1) * kWave + lane]);
   }
-  cost += s_joint[lane];
-  mc = fminf(mc, s_joint[kWave + lane]);
-  if (GRAD)
-    for (int v = 0; v < L; ++v) {
-      const int depth = ((cv4i*)(a.wl.info))[v].x;
-      cint* chain = (cint*)(a.wl.chain + v * kMaxDof);
-      for (int i = 0; i < depth; ++i)
-        s_joint[(2 + chain[i]) * kWave + lane] += s_part[(v * NPL + 2 + i) * kWave + lane];
+  if (HS == 1) {
+    cost += s_joint[lane];
+    mc = fminf(mc, s_joint[kWave + lane]);
+  }
+  if (GRAD) {
+    // joint j sits at chain position pos_j of every link in its subtree;
+    // its own terms come from the joint part (HS = 1) or link j's part
+    cint* jrec = (cint*)(a.wl.joint_rec);
+    for (int j = 0; j < D; ++j) {
+      const int pos = jrec[2 * j], sub = jrec[2 * j + 1];
+      float g = HS == 1 ? s_joint[(2 + j) * kWave + lane]
+                        : s_part[(j * NPL + 2 + a.wl.max_depth) * kWave + lane];
+#pragma unroll
+      for (int v = 0; v < 15; ++v)
+        if (v < L && ((sub >> v) & 1)) g += s_part[(v * NPL + 2 + pos) * kWave + lane];
+      s_joint[(2 + j) * kWave + lane] = g;
     }
+  }
   if (H > 1) {
     // park this slice's sums; the last workgroup of the chunk to arrive
     // adds the slices in slice order (deterministic whatever the arrival
@@ -428,12 +536,13 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
 
 template <int MAXS>
 hipError_t launch_eval_wl_s(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
-  const int waves = a.rb.n_links + 1;
-  if (waves * kWave > 1024 || slices < 1) return hipErrorInvalidValue;
+  const int HS = a.wl.halves;
+  const int waves = HS == 2 ? 2 * a.rb.n_links : a.rb.n_links + 1;
+  if (waves * kWave > 1024 || slices < 1 || (HS == 2 && slices > 1)) return hipErrorInvalidValue;
   if (slices > 1 && (!a.wl.part || !a.wl.count)) return hipErrorInvalidValue;
   // particle mode (per-candidate draws) is not staged in this layout
   if (a.var || a.d_stride) return hipErrorInvalidValue;
-  const size_t lds = wl_lds_bytes(a.rb.n_links, a.rb.dof, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0);
+  const size_t lds = wl_lds_bytes(a.rb.n_links, a.rb.dof, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0, HS);
   if (lds > kWlLdsMax) return hipErrorInvalidValue;
   const dim3 grid(grid_x, slices), block(waves * kWave);
   if (waves <= 8) {

@@ -3,9 +3,12 @@
 
 namespace mg {
 hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
-  if (a.wl.maxs == 4) return launch_eval_wl_s<4>(a, grid_x, slices, cand, grad, s);
-  if (a.wl.maxs == 8) return launch_eval_wl_s<8>(a, grid_x, slices, cand, grad, s);
-  if (a.wl.maxs == 16) return launch_eval_wl_s<16>(a, grid_x, slices, cand, grad, s);
+  // sphere slots per wave: all of a link's, or half with two waves per link
+  const int per = a.wl.halves == 2 ? a.wl.maxs / 2 : a.wl.maxs;
+  if (per == 2) return launch_eval_wl_s<2>(a, grid_x, slices, cand, grad, s);
+  if (per == 4) return launch_eval_wl_s<4>(a, grid_x, slices, cand, grad, s);
+  if (per == 8) return launch_eval_wl_s<8>(a, grid_x, slices, cand, grad, s);
+  if (per == 16) return launch_eval_wl_s<16>(a, grid_x, slices, cand, grad, s);
   return hipErrorInvalidValue;
 }
 }  // namespace mg

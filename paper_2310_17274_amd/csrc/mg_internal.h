@@ -73,10 +73,16 @@ struct Lanes {
 struct WaveLinks {
   const int4* info;        // [L]: chain depth, spheres, end effector or -1, 0
   const int* chain;        // [L][kMaxDof]: links from the root down to l
+  const int* joint_rec;    // [D][2]: chain position of joint j (its link's depth - 1) and
+                           //   the bit mask of the links whose chain contains it
+  const float4* chain_rec; // [L][kMaxDof][4]: fixed transform rows of chain[i], then
+                           //   {joint index (int bits), 0, 0, 0}
   const float4* sphere;    // [L][maxs] centre in link frame + radius
-  const float4* ball;      // [L] ball bounding the link's spheres (link frame): centre, radius
+  const float4* ball;      // [L][3] balls bounding the link's spheres (link frame): centre,
+                           //   radius; all slots, then each half of the slots
   int maxs;
   int max_depth;           // deepest chain (joints from the root)
+  int halves;              // waves per link: 1, or 2 (each with half of the slots)
   // cuboid slices over workgroups (gridDim.y > 1): per-slice partial sums
   // [chunk][slice][2 + D][64] and one arrival counter per chunk (zero
   // between launches; the last workgroup of a chunk resets it)
@@ -96,13 +102,17 @@ constexpr size_t kWlLdsMax = 64 * 1024;
 constexpr int kWlStageRows = kWave + 8;
 // The self-collision phase runs before any part is written, so its sphere
 // centres and winners share the parts' space.
-__host__ __device__ inline size_t wl_region_floats(int L, int D, int max_depth, int n_spheres, bool self) {
-  const size_t parts = ((size_t)L * (2 + max_depth) + 2 + D) * kWave;
-  const size_t selfb = self ? ((size_t)n_spheres * 3 + 2 * (L + 1)) * kWave : 0;
+__host__ __device__ inline size_t wl_region_floats(int L, int D, int max_depth, int n_spheres, bool self,
+                                                   int halves) {
+  const size_t parts = ((size_t)L * (3 + max_depth) + 2 + D + (halves == 2 ? 9 * (size_t)L : 0)) * kWave;
+  const size_t waves = halves == 2 ? 2 * (size_t)L : (size_t)L + 1;
+  const size_t selfb = self ? ((size_t)n_spheres * 3 + 2 * waves) * kWave : 0;
   return parts > selfb ? parts : selfb;
 }
-__host__ __device__ inline size_t wl_lds_bytes(int L, int D, int max_depth, int n_spheres, bool self) {
-  return (wl_region_floats(L, D, max_depth, n_spheres, self) + 2 * (size_t)kWlStageRows * D) * sizeof(float);
+__host__ __device__ inline size_t wl_lds_bytes(int L, int D, int max_depth, int n_spheres, bool self,
+                                               int halves) {
+  return (wl_region_floats(L, D, max_depth, n_spheres, self, halves) + 2 * (size_t)kWlStageRows * D +
+          3 * (size_t)D) * sizeof(float);
 }
 
 // Cuboid in the library layout: p = A c + b maps a world point into the box
