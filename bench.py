@@ -98,11 +98,13 @@ def main():
     # launch-shape autotuner: fastest evaluation layout for this batch
     c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
-    layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
-    if args.layout is not None:
+    if args.layout is None:
+        layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
+    else:
         b.mg_batch_set_layout(args.layout, args.slices)
-        layout = ["lane_per_link", "wave_per_link", "two_waves_per_link"][args.layout] + "/" + \
-                 (str(args.slices) if args.slices else "auto")
+        layout = ("two_waves_per_link" if args.layout == 2 else
+                  ["lane_per_link", "wave_per_link"][args.layout] + "/" +
+                  (str(args.slices) if args.slices else "auto"))
 
     if args.profile == "eval":
         return profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, args.launches, layout)
@@ -217,20 +219,21 @@ def layout_name(tuned):
 
 
 def measured_traffic(layout):
-    """HBM bytes per evaluation launch from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary, or None when the kernel sources or the
-    launch layout changed since the counters were taken (or no summary
-    exists)."""
+    """HBM bytes per evaluation launch of `layout` from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary (one `hbm_bytes_per_launch[<layout>]`
+    line per profiled layout), or None when the kernel sources changed since
+    the counters were taken, the layout was not profiled, or no summary
+    exists."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            fields = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith("#"))
+            fields = dict((k.strip(), v.strip()) for k, v in
+                          (line.split(":", 1) for line in fh if ":" in line and not line.startswith("#")))
     except OSError:
         return None
-    if fields.get("source_digest", "").strip() != kernel_digest():
+    if fields.get("source_digest") != kernel_digest():
         return None
-    if fields.get("layout", "").strip() != layout:
-        return None
-    return float(fields["hbm_bytes_per_launch"])
+    v = fields.get(f"hbm_bytes_per_launch[{layout}]")
+    return float(v) if v is not None else None
 
 
 def _inputs(robot, batch, dev):
@@ -443,13 +446,16 @@ def cpu_baseline(robot, worlds, batch, alpha, iters, seconds):
     r.solve(boxes, batch.q_start[0], batch.goal[0], T, batch.x0, 1, 4, alpha, nthreads=threads)
     one = time.perf_counter() - t0
     n = int(max(1, min(iters, seconds / max(one, 1e-6))))
+    # whole solves are repeated until the sample holds about `seconds` of work
+    reps = int(max(1, seconds / max(one * n, 1e-6)))
     t0 = time.perf_counter()
-    r.solve(boxes, batch.q_start[0], batch.goal[0], T, batch.x0, n, 4, alpha, nthreads=threads)
+    for _ in range(reps):
+        r.solve(boxes, batch.q_start[0], batch.goal[0], T, batch.x0, n, 4, alpha, nthreads=threads)
     dt = time.perf_counter() - t0
     # a solve of n iterations evaluates n*S*T*K candidates plus the initial S*T
-    evals = n * S * T * K + S * T
+    evals = reps * (n * S * T * K + S * T)
     return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 reference solve of the same problem, {n} of {iters} iterations, "
+            "sample": f"FP64 reference solve of the same problem, {reps} x {n} of {iters} iterations, "
                       f"{S} seeds in parallel over {threads} threads ({dt:.1f} s)"}
 
 
