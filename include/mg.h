@@ -206,18 +206,21 @@ mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *s
  * slices' sums in slice order (the batch keeps the scratch and counters).
  * A robot of up to 8 links can also give each link two waves with half of
  * its spheres each (layout 2), the second also taking that link's joint
- * terms: shorter waves, no separate joint wave.
- * mg_batch_set_layout fixes a layout (-1: library default, 0, 1, 2) and a
- * slice count (0: automatic; 1, 2 or 4; layout 2 takes 0 or 1).  Host-only;
- * affects later calls.
+ * terms: shorter waves, no separate joint wave.  Layout 3 keeps one wave
+ * per link but holds 32 evaluations per workgroup, each half of a wave
+ * testing half of the link's sphere slots (twice the workgroups for the
+ * same batch; no self-collision, at least 4 slots per link).
+ * mg_batch_set_layout fixes a layout (-1: library default, 0, 1, 2, 3) and
+ * a slice count (0: automatic; 1, 2 or 4; layouts 2 and 3 take 0 or 1).
+ * Host-only; affects later calls.
  *
  * Autotuner for a batch's launch shape: times the line-search evaluation
  * kernel for K candidates under every layout and slice count the library
  * offers for this robot (mg_time_eval with `launches` launches each) and
  * fixes the fastest for every later call on this batch.  *slices_out (may
  * be NULL) receives the slice count for the lane-per-link layout, minus
- * the workgroups per 64 evaluations for the wave-per-link layout, or -8 for
- * two waves per link.
+ * the workgroups per 64 evaluations for the wave-per-link layout, -8 for
+ * two waves per link, or -16 for two slot groups per wave.
  * Overwrites the batch's evaluation workspaces; not capturable.  Swept
  * collision always uses the lane-per-link layout with one slice. */
 mg_status mg_batch_set_layout(mg_batch *batch, int layout, int slices);

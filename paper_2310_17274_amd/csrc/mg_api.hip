@@ -97,6 +97,9 @@ struct mg_ctx {
   int box_cap = 0, n_boxes = 0;
   int* d_world_off = nullptr;
   int world_cap = 0, n_worlds = 0;
+  size_t lds_max = 64 * 1024;    // LDS one workgroup may hold on this device
+  std::vector<int> world_off;    // host copy of the cuboid offsets
+  std::vector<mg_batch*> batches;   // live batches (their chunk records name cuboid ranges)
   hipStream_t cap_stream = nullptr;
 };
 
@@ -124,12 +127,14 @@ struct mg_batch {
   int slices = -1;    // forced cuboid slices index (-1: automatic)
   int layout = -1;    // evaluation layout: -1 automatic, 0 lane per link, 1 wave per link
   // wave-per-link chunks of 64 evaluations, per candidate count K
-  int* d_chunk_wl[mg::kMaxK + 1] = {};
-  int chunks_wl[mg::kMaxK + 1] = {};
+  // ([K][0]: 64 evaluations per chunk, [K][1]: 32 for two slot groups)
+  mg::WlChunk* d_chunk_wl[mg::kMaxK + 1][2] = {};
+  int chunks_wl[mg::kMaxK + 1][2] = {};
   int wl_slices = 0;        // wave-per-link cuboid slices over workgroups (0: automatic)
   int wl_halves = 0;        // wave-per-link waves per link: 1, 2 (0: automatic)
+  int wl_groups = 1;        // wave-per-link slot groups per wave: 1, 2
   int wl_slices_max = 1;    // largest the scratch below holds
-  float* wl_part = nullptr; // [chunks][slices][2 + D][64]
+  float* wl_part = nullptr; // [chunks][slices][3 + D][64]
   int* wl_count = nullptr;  // [chunks], zero between launches
   // particle stage: per-row costs of every particle [p_cap][rows]
   float* p_cost = nullptr;
@@ -289,14 +294,20 @@ mg::WaveLinks dev_wave_links(const mg_ctx* c) {
 // swept collision.
 bool wl_possible(const mg_ctx* c, bool self) {
   return c->L + 1 <= 16 && !c->params.swept &&
-         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, self, 1) <= mg::kWlLdsMax;
+         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, self, 1, c->maxs, mg::kWave) <= c->lds_max;
 }
 // two waves per link: at most 8 links (16 waves) and the LDS for the hand-over
 bool wl_halves_possible(const mg_ctx* c) {
   return 2 * c->L <= 16 && !c->params.swept &&
-         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, c->n_self > 0, 2) <= mg::kWlLdsMax;
+         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, c->n_self > 0, 2, c->maxs, mg::kWave) <= c->lds_max;
 }
 bool wl_possible(const mg_ctx* c) { return wl_possible(c, c->n_self > 0); }
+// two slot groups per wave (32 evaluations per workgroup): no
+// self-collision, at least four sphere slots per link
+bool wl_groups_possible(const mg_ctx* c) {
+  return c->L + 1 <= 16 && !c->params.swept && c->n_self == 0 && c->maxs >= 4 &&
+         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, false, 1, c->maxs, mg::kWave / 2) <= c->lds_max;
+}
 
 // Layout of an evaluation launch with K candidates.
 bool use_wl(const mg_batch* b, int K) {
@@ -379,6 +390,39 @@ mg::EvalArgs eval_args(const mg_ctx* c, const mg_batch* b, int hi, const float* 
   return a;
 }
 
+// Wave-per-link chunk records of a batch for every K <= K_max and both
+// chunk sizes (64 and 32 evaluations), problem by problem, with the
+// problem's cuboid range in the context's current worlds (empty for a
+// world not set yet).  Allocated on the first call, rewritten in place
+// (synchronously) afterwards.
+mg_status wl_chunks_upload(mg_batch* b) {
+  const mg_ctx* c = b->ctx;
+  for (int K = 1; K <= b->K_max; ++K)
+    for (int gi = 0; gi < 2; ++gi) {
+      const int E = mg::kWave >> gi;
+      std::vector<mg::WlChunk> rec;
+      int r0 = 0;
+      for (int p = 0; p < b->P; ++p) {
+        const int n_e = b->seeds[p] * b->horizon[p] * K;
+        const int w = b->world[p];
+        const bool set = w + 1 < (int)c->world_off.size();
+        const int lo = set ? c->world_off[w] : 0, hi = set ? c->world_off[w + 1] : 0;
+        for (int e = 0; e < n_e; e += E)
+          rec.push_back(mg::WlChunk{p, e, b->seeds[p], b->horizon[p], lo, hi, r0, n_e});
+        r0 += b->seeds[p] * b->horizon[p];
+      }
+      if (!b->d_chunk_wl[K][gi]) {
+        mg_status st = dev_upload(&b->d_chunk_wl[K][gi], rec);
+        if (st != MG_OK) return st;
+        b->chunks_wl[K][gi] = (int)rec.size();
+      } else {
+        HIP_TRY(hipMemcpy(b->d_chunk_wl[K][gi], rec.data(), rec.size() * sizeof(mg::WlChunk),
+                          hipMemcpyHostToDevice));
+      }
+    }
+  return MG_OK;
+}
+
 mg_status common_checks(mg_ctx* c, mg_batch* b) {
   if (!c || !b) return fail(MG_ERR_ARG, "null context or batch");
   if (b->ctx != c) return fail(MG_ERR_ARG, "batch belongs to another context");
@@ -396,20 +440,24 @@ mg_status common_checks(mg_ctx* c, mg_batch* b) {
 int wl_slices(const mg_batch* b, int K) {
   if (b->wl_slices > 0) return std::min(b->wl_slices, b->wl_slices_max);
   int h = 1;
-  while (h < b->wl_slices_max && (long)b->chunks_wl[K] * h < 512) h *= 2;
+  while (h < b->wl_slices_max && (long)b->chunks_wl[K][0] * h < 512) h *= 2;
   return h;
 }
 
 hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool grad, hipStream_t s) {
   if (use_wl(b, a.K)) {
-    a.chunk_prefix = b->d_chunk_wl[a.K];
     a.wl.part = b->wl_part;
     a.wl.count = b->wl_count;
-    // two waves per link where they fit (shorter waves), unless forced
-    const int halves = b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(b->ctx) ? 2 : 1);
+    // two slot groups per wave when chosen; else two waves per link where
+    // they fit (shorter waves), unless forced
+    const int groups = b->wl_groups == 2 && wl_groups_possible(b->ctx) ? 2 : 1;
+    const int halves = groups == 2 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(b->ctx) ? 2 : 1));
     if (halves == 2 && !wl_halves_possible(b->ctx)) return hipErrorInvalidValue;
     a.wl.halves = halves;
-    return mg::launch_eval_wl(a, b->chunks_wl[a.K], halves == 2 ? 1 : wl_slices(b, a.K), cand, grad, s);
+    a.wl.groups = groups;
+    a.wl.chunk = b->d_chunk_wl[a.K][groups - 1];
+    return mg::launch_eval_wl(a, b->chunks_wl[a.K][groups - 1], (halves == 2 || groups == 2) ? 1 : wl_slices(b, a.K),
+                              cand, grad, s);
   }
   return mg::launch_eval(a, b->chunks[hi], cand, grad, s);
 }
@@ -557,6 +605,11 @@ mg_status mg_create(const mg_robot_desc* r, const mg_params* params, mg_ctx** ou
 
   mg_ctx* c = new mg_ctx();
   (void)hipGetDevice(&c->device);
+  {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && v > 0)
+      c->lds_max = std::min((size_t)v, mg::kWlLdsMax);
+  }
   c->L = r->n_links; c->D = r->dof; c->M = r->n_spheres; c->n_ee = r->n_ee;
   c->parent.assign(r->parent, r->parent + c->L);
   c->joint.assign(r->joint, r->joint + c->L);
@@ -586,6 +639,7 @@ mg_status mg_create(const mg_robot_desc* r, const mg_params* params, mg_ctx** ou
 void mg_destroy(mg_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
+  for (mg_batch* b : c->batches) b->ctx = nullptr;   // (batches outliving their context)
   dev_free(c->d_fixed_tf); dev_free(c->d_joint); dev_free(c->d_q_lo); dev_free(c->d_q_hi); dev_free(c->d_ee_tf);
   dev_free(c->d_lane_info); dev_free(c->d_lane_sphere);
   dev_free(c->d_wl_info); dev_free(c->d_wl_chain); dev_free(c->d_wl_ball);
@@ -632,6 +686,10 @@ mg_status mg_set_worlds(mg_ctx* c, int n_worlds, const int* offsets, const float
   HIP_TRY(mg::launch_boxes(pose, dims, n, c->d_box, s));
   c->n_boxes = n;
   c->n_worlds = n_worlds;
+  c->world_off.assign(offsets, offsets + n_worlds + 1);
+  // the batches' chunk records carry their worlds' cuboid ranges
+  for (mg_batch* b : c->batches)
+    if ((st = wl_chunks_upload(b)) != MG_OK) return st;
   return MG_OK;
 }
 
@@ -685,22 +743,18 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
     b->chunks[hi] = pre[P];
     if ((st = dev_upload(&b->d_chunk[hi], pre)) != MG_OK) return bail(st);
   }
-  for (int K = 1; K <= K_max; ++K) {
-    std::vector<int> pre(P + 1, 0);
-    for (int p = 0; p < P; ++p) pre[p + 1] = pre[p] + (seeds[p] * horizon[p] * K + mg::kWave - 1) / mg::kWave;
-    b->chunks_wl[K] = pre[P];
-    if ((st = dev_upload(&b->d_chunk_wl[K], pre)) != MG_OK) return bail(st);
-  }
+  c->batches.push_back(b);
+  if ((st = wl_chunks_upload(b)) != MG_OK) return bail(st);
   {
     // wave-per-link slice scratch: up to 4 slices while it stays under 64 MB
-    const size_t per = (size_t)b->chunks_wl[K_max] * (2 + c->D) * mg::kWave * sizeof(float);
+    const size_t per = (size_t)b->chunks_wl[K_max][0] * (3 + c->D) * mg::kWave * sizeof(float);
     b->wl_slices_max = 1;
     while (b->wl_slices_max < 4 && per * b->wl_slices_max * 2 <= (64u << 20)) b->wl_slices_max *= 2;
     if (b->wl_slices_max > 1) {
       if ((st = dev_alloc(&b->wl_part, per / sizeof(float) * b->wl_slices_max)) != MG_OK ||
-          (st = dev_alloc(&b->wl_count, (size_t)b->chunks_wl[K_max])) != MG_OK)
+          (st = dev_alloc(&b->wl_count, (size_t)b->chunks_wl[K_max][0])) != MG_OK)
         return bail(st);
-      if (hipMemset(b->wl_count, 0, (size_t)b->chunks_wl[K_max] * sizeof(int)) != hipSuccess)
+      if (hipMemset(b->wl_count, 0, (size_t)b->chunks_wl[K_max][0] * sizeof(int)) != hipSuccess)
         return bail(fail(MG_ERR_HIP, "initialising the slice counters failed"));
     }
   }
@@ -727,12 +781,17 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
 void mg_batch_destroy(mg_batch* b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
+  if (b->ctx) {
+    auto& v = b->ctx->batches;
+    v.erase(std::remove(v.begin(), v.end(), b), v.end());
+  }
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   for (auto e : b->ev_start) (void)hipEventDestroy(e);
   for (auto e : b->ev_stop) (void)hipEventDestroy(e);
   dev_free(b->d_prob); dev_free(b->d_seed);
   for (auto& p : b->d_chunk) dev_free(p);
-  for (auto& p : b->d_chunk_wl) dev_free(p);
+  for (auto& pk : b->d_chunk_wl)
+    for (auto& p : pk) dev_free(p);
   dev_free(b->cost_e); dev_free(b->gd_e); dev_free(b->mc_e); dev_free(b->grad_e); dev_free(b->pe_e);
   dev_free(b->c_cur); dev_free(b->g_cur); dev_free(b->dir); dev_free(b->best_c); dev_free(b->best_x);
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
@@ -853,13 +912,14 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
   // wave per link with two waves per link; wave per link with 1, 2 or 4
   // workgroups per 64 evaluations.  Each is {layout, slices index, halves,
   // workgroup slices}.
-  struct Opt { int layout, hi, halves, wls; };
+  struct Opt { int layout, hi, halves, wls, groups; };
   std::vector<Opt> opts;
   if (c->n_self == 0)
-    for (int hi = 0; hi < kNumSlices; ++hi) opts.push_back({0, hi, 0, 0});
-  if (wl_halves_possible(c)) opts.push_back({1, -1, 2, 1});
+    for (int hi = 0; hi < kNumSlices; ++hi) opts.push_back({0, hi, 0, 0, 1});
+  if (wl_groups_possible(c)) opts.push_back({1, -1, 1, 1, 2});
+  if (wl_halves_possible(c)) opts.push_back({1, -1, 2, 1, 1});
   if (wl_possible(c))
-    for (int h = 1; h <= b->wl_slices_max; h *= 2) opts.push_back({1, -1, 1, h});
+    for (int h = 1; h <= b->wl_slices_max; h *= 2) opts.push_back({1, -1, 1, h, 1});
   if (opts.empty()) return fail(MG_ERR_UNSUPPORTED, "no evaluation layout fits this robot");
   size_t best = 0;
   float best_us = 3.0e38f;
@@ -868,6 +928,7 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
     b->slices = opts[o].hi;
     b->wl_halves = opts[o].halves;
     b->wl_slices = opts[o].wls;
+    b->wl_groups = opts[o].groups;
     float us = 0.0f;
     // one untimed launch per layout first (code upload, caches)
     if ((st = mg_time_eval(c, b, q_start, goal, x, dir, K, alpha, 1, &us, stream)) != MG_OK ||
@@ -876,6 +937,7 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
       b->layout = -1;
       b->wl_slices = 0;
       b->wl_halves = 0;
+      b->wl_groups = 1;
       return st;
     }
     if (us < best_us) { best_us = us; best = o; }
@@ -884,10 +946,12 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
   b->slices = opts[best].hi;
   b->wl_halves = opts[best].halves;
   b->wl_slices = opts[best].wls;
+  b->wl_groups = opts[best].groups;
   // lane per link: the slice count; wave per link: minus the workgroups per
-  // 64 evaluations, or -8 for two waves per link
+  // 64 evaluations, -8 for two waves per link, -16 for two slot groups
   if (slices_out)
-    *slices_out = opts[best].layout == 0 ? kSlices[opts[best].hi] : (opts[best].halves == 2 ? -8 : -opts[best].wls);
+    *slices_out = opts[best].layout == 0 ? kSlices[opts[best].hi]
+                  : opts[best].groups == 2 ? -16 : (opts[best].halves == 2 ? -8 : -opts[best].wls);
   return MG_OK;
 }
 
@@ -944,14 +1008,17 @@ mg_status mg_ee_pose(mg_ctx* c, int rows, const float* q, float* pose, void* str
 
 mg_status mg_batch_set_layout(mg_batch* b, int layout, int slices) {
   if (!b) return fail(MG_ERR_ARG, "null batch");
-  if (layout < -1 || layout > 2) return fail(MG_ERR_ARG, "layout must be -1, 0, 1 or 2");
+  if (layout < -1 || layout > 3) return fail(MG_ERR_ARG, "layout must be -1, 0, 1, 2 or 3");
   if (layout >= 1 && !wl_possible(b->ctx))
     return fail(MG_ERR_UNSUPPORTED, "the wave-per-link layout needs at most 15 links and no swept collision");
   if (layout == 2 && !wl_halves_possible(b->ctx))
     return fail(MG_ERR_UNSUPPORTED, "two waves per link need at most 8 links");
-  b->wl_halves = layout == 2 ? 2 : (layout == 1 ? 1 : 0);
-  if (layout == 2) {
-    if (slices > 1) return fail(MG_ERR_ARG, "two waves per link take one workgroup per 64 evaluations");
+  if (layout == 3 && !wl_groups_possible(b->ctx))
+    return fail(MG_ERR_UNSUPPORTED, "two slot groups per wave need no self-collision and 4 or more slots per link");
+  b->wl_halves = layout == 2 ? 2 : (layout == 1 || layout == 3 ? 1 : 0);
+  b->wl_groups = layout == 3 ? 2 : 1;
+  if (layout >= 2) {
+    if (slices > 1) return fail(MG_ERR_ARG, "layouts 2 and 3 take one workgroup per chunk of evaluations");
     b->layout = 1;
     b->slices = -1;
     b->wl_slices = 1;
@@ -1091,6 +1158,7 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
     key_push(key, c->d_box); key_push(key, c->d_world_off); key_push(key, b->slices);
     key_push(key, b->layout); key_push(key, b->wl_slices); key_push(key, c->n_self);
     key_push(key, b->wl_halves);
+    key_push(key, b->wl_groups);
     for (int k = 0; k < K; ++k) key_push(key, alpha[k]);
     if (!b->gexec || key != b->gkey) {
       if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }

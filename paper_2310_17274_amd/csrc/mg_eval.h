@@ -51,16 +51,16 @@ __device__ __forceinline__ void suffix_step(float* W, bool active) {
 // enters as a wrench on the link: force d cost / d p at the tool point and
 // the moment conjugate to a world-frame rotation.  pe_row >= 0 (and ee 0)
 // records the position and angle errors of that row.
-__device__ __forceinline__ void pose_term(const EvalArgs& a, int p, int ee, const float* T, int pe_row,
-                                          float& cost, float& Fx, float& Fy, float& Fz, float& Mx,
-                                          float& My, float& Mz) {
+// etf: the tool transform (3x4), gl: the goal (position, quaternion w x y z).
+__device__ __forceinline__ void pose_term_at(const EvalArgs& a, const float* etf, const float* gl, int ee,
+                                             const float* T, int pe_row, float& cost, float& Fx, float& Fy,
+                                             float& Fz, float& Mx, float& My, float& Mz) {
   float E[12];
 #pragma unroll
   for (int i = 0; i < 12; ++i) E[i] = T[i];
-  compose(E, a.rb.ee_tf + ee * 12);
+  compose(E, etf);
   float qw, qx, qy, qz;
   mat_to_quat(E, qw, qx, qy, qz);
-  const float* gl = a.goal + ((size_t)p * a.rb.n_ee + ee) * 7;
   const float px = E[3], py = E[7], pz = E[11];
   const float ex = gl[0] - px, ey = gl[1] - py, ez = gl[2] - pz;
   const float n = sqrtf(ex * ex + ey * ey + ez * ez);
@@ -88,6 +88,13 @@ __device__ __forceinline__ void pose_term(const EvalArgs& a, int p, int ee, cons
     a.pe_e[(size_t)pe_row * 2 + 0] = n;
     a.pe_e[(size_t)pe_row * 2 + 1] = 2.0f * acosf(fminf(fabsf(dot), 1.0f));
   }
+}
+
+__device__ __forceinline__ void pose_term(const EvalArgs& a, int p, int ee, const float* T, int pe_row,
+                                          float& cost, float& Fx, float& Fy, float& Fz, float& Mx,
+                                          float& My, float& Mz) {
+  pose_term_at(a, a.rb.ee_tf + ee * 12, a.goal + ((size_t)p * a.rb.n_ee + ee) * 7, ee, T, pe_row, cost, Fx,
+               Fy, Fz, Mx, My, Mz);
 }
 
 // Joint j at waypoint row `row` (waypoint t+1 of its seed): joint-limit cost

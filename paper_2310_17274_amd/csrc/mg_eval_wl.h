@@ -5,19 +5,31 @@
 // together in configuration space).  Wave l owns link l: it runs the
 // kinematic chain from the root to l (Tab.6 closed form per joint), places
 // the link's spheres, and tests them against the world's cuboids; the last
-// wave owns the joint-limit and smoothness terms of every joint.  Per
-// cuboid, one test of a ball enclosing the link's spheres over all 64 lanes
-// decides whether the wave looks at that cuboid at all (the distance is
-// 1-Lipschitz, so a cuboid farther than the ball radius + eta from the
+// wave owns the joint-limit and smoothness terms of every joint (or, with
+// two waves per link, each link's second wave owns its joint's).
+//
+// The workgroups of one launch run side by side once, on cold caches, so
+// every dependent read of memory costs a full round trip.  The kernel
+// therefore reads memory in two dependent rounds only: the chunk's record
+// (problem, rows, cuboid range) with this wave's tables, then one staging
+// pass that brings the rows, limits, start, goals, tool transforms, chain
+// records, sphere slots and the first cuboid tile into LDS.  After that
+// every read is from LDS (later cuboid tiles are read a tile ahead).
+//
+// Per cuboid, one test of a ball enclosing the wave's spheres over all 64
+// lanes decides whether the wave looks at that cuboid at all (the distance
+// is 1-Lipschitz, so a cuboid farther than the ball radius + eta from the
 // ball's centre adds no cost and cannot lower the clamped clearance for any
 // lane); for a cuboid that passes, each lane tests a ball around its own
-// copy of the link's spheres, and the wave skips the cuboid when none
-// reaches it.  The adjoint recomputes the chain (Alg.8: no stored transforms)
-// and projects the link's wrench on every joint above it (Tab.7); the waves'
-// partial sums meet in LDS in a fixed order.  The world's cuboids can also
-// be split over gridDim.y workgroups of the same 64 evaluations (more
-// workgroups for small batches); the last of them to finish adds the slices'
-// sums in slice order.
+// copy of the spheres, and the wave skips the cuboid when none reaches it.
+// The adjoint recomputes the chain (Alg.8: no stored transforms) and
+// projects the link's wrench on every joint above it (Tab.7); each link
+// wave also forms its share of the directional derivative.  The waves'
+// partial sums meet in LDS in a fixed order: wave j gathers joint j's
+// derivative, the last wave the cost, clearance and directional derivative.
+// The world's cuboids can also be split over gridDim.y workgroups of the
+// same 64 evaluations; the last of them to finish adds the slices' sums in
+// slice order.
 #pragma once
 
 #include "mg_eval.h"
@@ -71,24 +83,28 @@ __device__ __forceinline__ void self_winner(int W, const float* s_best, int lane
 }
 
 // Pose of link l: the chain from the root, joint by joint (Tab.6: fixed
-// transform, then the rotation about z).  Each joint's record (fixed
-// transform rows and joint index) is loaded one joint ahead, so the scalar
-// loads overlap the previous joint's arithmetic.  visit(i, T) sees the pose
-// after chain position i.
+// transform, then the rotation about z), from the chain records staged in
+// LDS.  The next joint's record and joint value are read while the current
+// joint's arithmetic runs.  visit(i, c, T) sees the pose after chain
+// position i, whose joint is c.
 template <typename QV, typename VIS>
-__device__ __forceinline__ void chain_fk(const EvalArgs& a, int l, int depth, int row, QV&& qval,
-                                         float* T, VIS&& visit) {
-  cv4f* rec = (cv4f*)(a.wl.chain_rec + (size_t)l * kMaxDof * 4);
+__device__ __forceinline__ void chain_fk(const float4* rec, int depth, int row, QV&& qval, float* T,
+                                         VIS&& visit) {
   identity(T);
-  v4f n0 = rec[0], n1 = rec[1], n2 = rec[2], n3 = rec[3];
+  if (depth <= 0) return;
+  float4 f0 = rec[0], f1 = rec[1], f2 = rec[2];
+  int c = __float_as_int(rec[3].x);
+  float q = qval(row, c);
   for (int i = 0; i < depth; ++i) {
-    const v4f f0 = n0, f1 = n1, f2 = n2;
-    const int c = __float_as_int(n3.x);
+    float4 g0 = f0, g1 = f1, g2 = f2;
+    int cn = c;
+    float qn = q;
     if (i + 1 < depth) {
-      n0 = rec[4 * (i + 1) + 0]; n1 = rec[4 * (i + 1) + 1];
-      n2 = rec[4 * (i + 1) + 2]; n3 = rec[4 * (i + 1) + 3];
+      const float4* r = rec + 4 * (i + 1);
+      g0 = r[0]; g1 = r[1]; g2 = r[2];
+      cn = __float_as_int(r[3].x);
+      qn = qval(row, cn);
     }
-    const float q = qval(row, c);
     const float sn = __sinf(q), cs = __cosf(q);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -101,70 +117,306 @@ __device__ __forceinline__ void chain_fk(const EvalArgs& a, int l, int depth, in
       T[r * 4 + 0] = u0 * cs + u1 * sn;
       T[r * 4 + 1] = u1 * cs - u0 * sn;
     }
-    visit(i, T);
+    visit(i, c, T);
+    f0 = g0; f1 = g1; f2 = g2;
+    c = cn;
+    q = qn;
   }
 }
 
-// Collision, pose and adjoint of link l for this lane's evaluation.
-// part[q * kWave + lane]: q = 0 cost, 1 clearance, 2 + i d cost / d q of the
-// joint at chain position i (root first).
-// With HS = 2 a link has two waves, each with half of its sphere slots
-// (hs = 0, 1); the second also owns joint l's limit and smoothness terms and
-// hands its sums to the first (s_ex), which runs the adjoint.  Returns false
-// for a wave whose part is handed over.
-template <int MAXS, bool GRAD, typename QV>
-__device__ __forceinline__ bool link_wave(const EvalArgs& a, int l, int hs, int HS, int p,
-                                          const Problem& pb, int row, int t, bool valid, int h, int H,
-                                          QV&& qval, float* part, int lane, bool self_on, float* s_sph,
-                                          float* s_best, int W, float* s_ex, const float* s_lim) {
-  // per-link tables through the constant address space (wave-uniform)
+// World collision of one link wave's spheres against a staged tile of nb
+// cuboids (Eq.(10)/(11), summed over cuboids and spheres).  Per cuboid, the
+// wave's ball (centre cw, radius Rw, scalar) decides whether the wave looks
+// at it; for one that passes, each lane's own ball (centre b, radius rl)
+// must reach it; then the slots' face tests and, where one passes, the near
+// path.
+template <int MAXS>
+__device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane, float cwx, float cwy,
+                                           float cwz, float Rw, float bx, float by, float bz, float rl,
+                                           const float* cx, const float* cy, const float* cz,
+                                           const float* rr, float w, float eta, float inv_eta, float& cost,
+                                           float& mc, float& Fx, float& Fy, float& Fz, float& Mx,
+                                           float& My, float& Mz) {
+  // lane j tests cuboid j of the tile against the wave's ball
+  bool cand = false;
+  if (lane < nb) {
+    const float4 B0 = tile[4 * lane + 0], B1 = tile[4 * lane + 1];
+    const float4 B2 = tile[4 * lane + 2], BH = tile[4 * lane + 3];
+    const float px = fmaf(B0.x, cwx, fmaf(B0.y, cwy, fmaf(B0.z, cwz, B0.w)));
+    const float py = fmaf(B1.x, cwx, fmaf(B1.y, cwy, fmaf(B1.z, cwz, B1.w)));
+    const float pz = fmaf(B2.x, cwx, fmaf(B2.y, cwy, fmaf(B2.z, cwz, B2.w)));
+    const float m3 = fmaxf(fabsf(px) - BH.x, fmaxf(fabsf(py) - BH.y, fabsf(pz) - BH.z));
+    cand = m3 < Rw;
+  }
+  // (the mask made scalar, so the candidate index is too)
+  const uint64_t bal = __ballot(cand);
+  uint64_t mask = ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(bal >> 32)) << 32) |
+                  (unsigned)__builtin_amdgcn_readfirstlane((unsigned)bal);
+  if (!mask) return;
+  // the next candidate is read one iteration ahead
+  int ob = __builtin_ctzll(mask);
+  mask &= mask - 1;
+  v4f nA0, nA1, nA2, nH;
+  {
+    const float4 q0 = tile[4 * ob + 0], q1 = tile[4 * ob + 1], q2 = tile[4 * ob + 2], q3 = tile[4 * ob + 3];
+    nA0 = {q0.x, q0.y, q0.z, q0.w}; nA1 = {q1.x, q1.y, q1.z, q1.w};
+    nA2 = {q2.x, q2.y, q2.z, q2.w}; nH = {q3.x, q3.y, q3.z, q3.w};
+  }
+  bool more = true;
+  while (more) {
+    const v4f A0 = nA0, A1 = nA1, A2 = nA2, Hh = nH;
+    more = mask != 0;
+    if (more) {
+      ob = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const float4 q0 = tile[4 * ob + 0], q1 = tile[4 * ob + 1], q2 = tile[4 * ob + 2], q3 = tile[4 * ob + 3];
+      nA0 = {q0.x, q0.y, q0.z, q0.w}; nA1 = {q1.x, q1.y, q1.z, q1.w};
+      nA2 = {q2.x, q2.y, q2.z, q2.w}; nH = {q3.x, q3.y, q3.z, q3.w};
+    }
+    // second level: this lane's own ball; the wave skips the cuboid when no
+    // lane's ball reaches it
+    {
+      const float px = fmaf(A0.x, bx, fmaf(A0.y, by, fmaf(A0.z, bz, A0.w)));
+      const float py = fmaf(A1.x, bx, fmaf(A1.y, by, fmaf(A1.z, bz, A1.w)));
+      const float pz = fmaf(A2.x, bx, fmaf(A2.y, by, fmaf(A2.z, bz, A2.w)));
+      const float mb = fmaxf(fabsf(px) - Hh.x, fmaxf(fabsf(py) - Hh.y, fabsf(pz) - Hh.z));
+      if (__ballot(mb < rl) == 0) continue;
+    }
+    // slots in groups of at most 8: face tests, then the near path of the
+    // group (bounds the live face-test results)
+    constexpr int G = MAXS < 8 ? MAXS : 8;
+#pragma unroll
+    for (int g0 = 0; g0 < MAXS; g0 += G) {
+      float m3[G];
+      bool any = false;
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int s = g0 + u;
+        const float px = fmaf(A0.x, cx[s], fmaf(A0.y, cy[s], fmaf(A0.z, cz[s], A0.w)));
+        const float py = fmaf(A1.x, cx[s], fmaf(A1.y, cy[s], fmaf(A1.z, cz[s], A1.w)));
+        const float pz = fmaf(A2.x, cx[s], fmaf(A2.y, cy[s], fmaf(A2.z, cz[s], A2.w)));
+        m3[u] = fmaxf(fabsf(px) - Hh.x, fmaxf(fabsf(py) - Hh.y, fabsf(pz) - Hh.z));
+        any |= m3[u] < rr[s] + eta;
+      }
+      if (any) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+          const int s = g0 + u;
+          if (m3[u] < rr[s] + eta) {
+            const float px = fmaf(A0.x, cx[s], fmaf(A0.y, cy[s], fmaf(A0.z, cz[s], A0.w)));
+            const float py = fmaf(A1.x, cx[s], fmaf(A1.y, cy[s], fmaf(A1.z, cz[s], A1.w)));
+            const float pz = fmaf(A2.x, cx[s], fmaf(A2.y, cy[s], fmaf(A2.z, cz[s], A2.w)));
+            float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+            near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y, fabsf(pz) - Hh.z, rr[s],
+                      w, eta, inv_eta, cost, mc, gx, gy, gz);
+            Fx += gx; Fy += gy; Fz += gz;
+            Mx += cy[s] * gz - cz[s] * gy;
+            My += cz[s] * gx - cx[s] * gz;
+            Mz += cx[s] * gy - cy[s] * gx;
+          }
+        }
+      }
+    }
+  }
+}
+
+// Sum / minimum over the G slot groups of a wave (lanes e, e + E, ...).
+template <int G>
+__device__ __forceinline__ float groups_sum(float v) {
+  if (G >= 4) v = swap16_sum(v);
+  if (G >= 2) v = swap32_sum(v);
+  return v;
+}
+template <int G>
+__device__ __forceinline__ float groups_min(float v) {
+  if (G >= 4) v = swap16_min(v);
+  if (G >= 2) v = swap32_min(v);
+  return v;
+}
+
+// NT: launch bound, 512 threads for robots of up to 7 links (register
+// budget of two waves per SIMD), else 1024.  G: slot groups per wave; a
+// workgroup holds E = 64 / G evaluations and lane g * E + e tests group g
+// of the link's sphere slots for evaluation e (G = 2: twice the workgroups
+// for the same batch, the chain run twice).
+template <int MAXS, bool CAND, bool GRAD, int NT, int G>
+__global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
+  constexpr int E = kWave / G;
+  extern __shared__ float s_mem[];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int g = lane / E, el = lane % E;
+  const int tid = threadIdx.x, nthreads = blockDim.x;
+  const int L = a.rb.n_links, D = a.rb.dof, K = a.K, n_ee = a.rb.n_ee;
+  const int maxd = a.wl.max_depth, maxs = a.wl.maxs;
+  const int bx = blockIdx.x;
+  // cuboid slice of this workgroup (gridDim.y slices share a chunk)
+  const int h = __builtin_amdgcn_readfirstlane(blockIdx.y), H = __builtin_amdgcn_readfirstlane(gridDim.y);
+  // waves: one per link and one for the joint terms (HS = 1), or two per
+  // link with half of its spheres each (HS = 2, robots of up to 8 links)
+  const int HS = a.wl.halves;
+  const int W = HS == 2 ? 2 * L : L + 1;
+  const bool link_w = wave < L * HS;
+  const int l = link_w ? wave / HS : 0, hs = link_w ? wave % HS : 0;
+
+  // ---- everything is read from memory in two dependent rounds: the
+  //      chunk's record and this wave's tables (scalar loads), then the
+  //      workgroup's staging into LDS; after that only LDS is read ----
+  const v4i c0 = ((cv4i*)(a.wl.chunk + bx))[0], c1 = ((cv4i*)(a.wl.chunk + bx))[1];
+  const int p = c0.x, e_first = c0.y;
+  Problem pb;
+  pb.S = c0.z; pb.T = c0.w; pb.world = 0; pb.row0 = c1.z;
+  pb.seed0 = 0; pb.pad0 = 0; pb.pad1 = 0; pb.pad2 = 0;
+  const int box_lo = c1.x, box_hi = c1.y, n_e = c1.w;
   const v4i info = *(cv4i*)(a.wl.info + l);
+  // (the ball of this lane's slot group: all slots, or half of them)
+  const v4f bl = *(cv4f*)(a.wl.ball + l * 3 + (HS == 2 ? 1 + hs : (G == 2 ? 1 + lane / E : 0)));
+  const int jw = wave < D ? wave : 0;
+  const int jpos = ((cint*)a.wl.joint_rec)[2 * jw], jsub = ((cint*)a.wl.joint_rec)[2 * jw + 1];
+
+  const int e0 = e_first + el;
+  const bool valid = e0 < n_e;
+  const int e = valid ? e0 : n_e - 1;
+  const int rl = e / K, k = e - rl * K;       // candidates of a row side by side
+  const int t = rl % pb.T;
+  const int row = pb.row0 + rl;
+  const float alpha = CAND ? a.alpha[k < kMaxK ? k : 0] : 0.0f;
+
+  const WlLds o = wl_lds_layout(L, D, maxd, a.rb.n_spheres, a.pr.n_self > 0, HS, maxs, E);
+  float* s_x = s_mem + o.x;
+  float* s_d = s_mem + o.d;
+  float* s_lim = s_mem + o.lim;               // lower, upper, start
+  float* s_goal = s_mem + o.goal;
+  float* s_etf = s_mem + o.etf;
+  float4* s_chain = reinterpret_cast<float4*>(s_mem + o.chain);
+  float4* s_slot = reinterpret_cast<float4*>(s_mem + o.slot);
+  float4* s_box = reinterpret_cast<float4*>(s_mem + o.box);   // two tiles
+  int* s_tick = reinterpret_cast<int*>(s_mem + o.tick);
+
+  // the workgroup's rows and the four on either side (the stencils' reach)
+  const int e_last = min(n_e, e_first + E) - 1;
+  const int p_end = pb.row0 + pb.S * pb.T;
+  const int r_lo = max(pb.row0, pb.row0 + e_first / K - 4);
+  const int r_hi = min(p_end - 1, pb.row0 + e_last / K + 4);
+  const int n_st = (r_hi - r_lo + 1) * D;
+  // this workgroup's cuboids, staged a tile at a time
+  const int per = (box_hi - box_lo + H - 1) / H;
+  const int w0 = min(box_hi, box_lo + h * per), w1 = min(box_hi, w0 + per);
+  {
+    // scalars: rows of x (and d), limits, start, goals, tool transforms
+    const int nxd = CAND ? 2 * n_st : n_st;
+    const int nf = nxd + 3 * D + n_ee * 19;
+    auto fsrc = [&](int i, float*& dst) -> const float* {
+      if (i < n_st) { dst = s_x + i; return a.x + (size_t)r_lo * D + i; }
+      if (i < nxd) { dst = s_d + (i - n_st); return a.d + (size_t)r_lo * D + (i - n_st); }
+      i -= nxd;
+      if (i < D) { dst = s_lim + i; return a.rb.q_lo + i; }
+      if (i < 2 * D) { dst = s_lim + i; return a.rb.q_hi + (i - D); }
+      if (i < 3 * D) { dst = s_lim + i; return a.q_start + (size_t)p * D + (i - 2 * D); }
+      i -= 3 * D;
+      if (i < n_ee * 7) { dst = s_goal + i; return a.goal + (size_t)p * n_ee * 7 + i; }
+      i -= n_ee * 7;
+      dst = s_etf + i;
+      return a.rb.ee_tf + i;
+    };
+    // float4: chain records (the first maxd of every link), sphere slots,
+    // the first cuboid tile
+    const int nch = L * maxd * 4, nsl = L * maxs;
+    const int nb0 = min(kWlBoxTile, w1 - w0);
+    const int n4 = nch + nsl + 4 * max(nb0, 0);
+    auto f4src = [&](int i) -> const float4* {
+      if (i < nch) {
+        const int lk = i / (maxd * 4), rem = i - lk * (maxd * 4);
+        return a.wl.chain_rec + (size_t)lk * kMaxDof * 4 + rem;
+      }
+      if (i < nch + nsl) return a.wl.sphere + (i - nch);
+      return reinterpret_cast<const float4*>(a.box + w0) + (i - nch - nsl);
+    };
+    // every load of a pass is issued before its LDS stores
+    for (int b0 = 0; b0 < nf || b0 < n4; b0 += 2 * nthreads) {
+      const int i0 = b0 + tid, i1 = i0 + nthreads;
+      float* d0 = nullptr;
+      float* d1 = nullptr;
+      const float v0 = i0 < nf ? *fsrc(i0, d0) : 0.0f;
+      const float v1 = i1 < nf ? *fsrc(i1, d1) : 0.0f;
+      const float4 u0 = i0 < n4 ? *f4src(i0) : float4{};
+      const float4 u1 = i1 < n4 ? *f4src(i1) : float4{};
+      if (i0 < nf) *d0 = v0;
+      if (i1 < nf) *d1 = v1;
+      if (i0 < n4) s_chain[i0] = u0;
+      if (i1 < n4) s_chain[i1] = u1;
+    }
+  }
+  __syncthreads();
+  auto qval = [&](int r, int j) -> float {
+    const int i = (r - r_lo) * D + j;
+    float v = s_x[i];
+    if (CAND) {
+      v = fmaf(alpha, s_d[i], v);
+      v = fminf(fmaxf(v, s_lim[j]), s_lim[D + j]);
+    }
+    return v;
+  };
+
+  // parts: quantity q of evaluation el at part[q * E + el]
+  float* s_part = s_mem;
+  const int NPL = 4 + maxd;
+  float* s_joint = s_part + (size_t)L * NPL * E;
+  float* s_ex = s_joint + (size_t)(3 + D) * E;
+  float* part = link_w ? s_part + (size_t)l * NPL * E : s_joint;
+
+  // ---- link waves: forward kinematics along the chain, the pose term,
+  //      this wave's sphere slots ----
   const int depth = info.x, ee = info.z;
-  const int sbase = l * a.wl.maxs + hs * MAXS;          // this wave's first slot
-  const int ns = min(max(info.y - hs * MAXS, 0), MAXS);  // and how many it has
-
-  // ---- forward kinematics along the chain ----
+  const int sg = HS == 2 ? hs : g;                        // this lane's slot group
+  const int ns = min(max(info.y - sg * MAXS, 0), MAXS);   // and its slots
+  const float4* rec = s_chain + (size_t)l * maxd * 4;
   float T[12];
-  chain_fk(a, l, depth, row, qval, T, [](int, const float*) {});
-
   float cost = 0.0f, mc = a.pr.eta;
   float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, Mx = 0.0f, My = 0.0f, Mz = 0.0f;
-  if (ee >= 0 && hs == 0 && h == 0 && t == pb.T - 1)
-    pose_term(a, p, ee, T, valid ? row : -1, cost, Fx, Fy, Fz, Mx, My, Mz);
-
-  // ---- the link's spheres (this wave's share) ----
-  cv4f* sph = (cv4f*)(a.wl.sphere + sbase);
   float cx[MAXS], cy[MAXS], cz[MAXS], rr[MAXS];
+  if (link_w) {
+    chain_fk(rec, depth, row, qval, T, [](int, int, const float*) {});
+    if (ee >= 0 && sg == 0 && h == 0 && t == pb.T - 1)
+      pose_term_at(a, s_etf + ee * 12, s_goal + ee * 7, ee, T, valid ? row : -1, cost, Fx, Fy, Fz, Mx, My, Mz);
 #pragma unroll
-  for (int s = 0; s < MAXS; ++s) {
-    const v4f ls = sph[s];
-    const bool used = s < ns;
-    // unused slots sit far away and never pass the face test
-    cx[s] = used ? T[0] * ls.x + T[1] * ls.y + T[2] * ls.z + T[3] : 1e18f;
-    cy[s] = used ? T[4] * ls.x + T[5] * ls.y + T[6] * ls.z + T[7] : 1e18f;
-    cz[s] = used ? T[8] * ls.x + T[9] * ls.y + T[10] * ls.z + T[11] : 1e18f;
-    rr[s] = used ? ls.w : 0.0f;
+    for (int s = 0; s < MAXS; ++s) {
+      const float4 ls = s_slot[l * maxs + sg * MAXS + (s < ns ? s : 0)];
+      const bool used = s < ns;
+      // unused slots sit far away and never pass the face test
+      cx[s] = used ? T[0] * ls.x + T[1] * ls.y + T[2] * ls.z + T[3] : 1e18f;
+      cy[s] = used ? T[4] * ls.x + T[5] * ls.y + T[6] * ls.z + T[7] : 1e18f;
+      cz[s] = used ? T[8] * ls.x + T[9] * ls.y + T[10] * ls.z + T[11] : 1e18f;
+      rr[s] = used ? ls.w : 0.0f;
+    }
   }
 
-  // ---- self-collision (Eq.(9)): the winning pair's forces on this link ----
-  if (self_on) {
-    cint* sm = (cint*)(a.wl.slot_sphere + sbase);
+  // ---- self-collision (Eq.(9)), first slice only: sphere centres and
+  //      per-wave winners share the parts' space ----
+  float jc = 0.0f;    // the joint wave's cost
+  if (G == 1 && a.pr.n_self > 0 && h == 0) {
+    float* s_sph = s_part;
+    float* s_best = s_sph + (size_t)a.rb.n_spheres * 3 * kWave;
+    if (link_w) {
+      cint* sm = (cint*)(a.wl.slot_sphere + l * maxs + hs * MAXS);
 #pragma unroll
-    for (int s = 0; s < MAXS; ++s)
-      if (s < ns) {
-        const int m = sm[s];
-        s_sph[(m * 3 + 0) * kWave + lane] = cx[s];
-        s_sph[(m * 3 + 1) * kWave + lane] = cy[s];
-        s_sph[(m * 3 + 2) * kWave + lane] = cz[s];
-      }
+      for (int s = 0; s < MAXS; ++s)
+        if (s < ns) {
+          const int m = sm[s];
+          s_sph[(m * 3 + 0) * kWave + lane] = cx[s];
+          s_sph[(m * 3 + 1) * kWave + lane] = cy[s];
+          s_sph[(m * 3 + 2) * kWave + lane] = cz[s];
+        }
+    }
     __syncthreads();
-    self_pairs_phase(a, l * HS + hs, W, s_sph, s_best, lane);
+    self_pairs_phase(a, wave, W, s_sph, s_best, lane);
     __syncthreads();
     float bv;
     int bk;
     self_winner(W, s_best, lane, bv, bk);
-    if (HS == 2 && l == 0 && hs == 1) cost += a.pr.w_self * bv;   // (no joint wave)
-    if (bk >= 0) {
+    if (!link_w) jc += a.pr.w_self * bv;                        // the joint wave
+    if (HS == 2 && l == 0 && hs == 1) cost += a.pr.w_self * bv;  // (no joint wave)
+    if (link_w && bk >= 0) {
       const int4 pr = reinterpret_cast<const int4*>(a.wl.self_pairs)[bk];
       // owners: link and slot position of each sphere (this wave holds
       // positions hs * MAXS .. hs * MAXS + MAXS - 1 of its link)
@@ -196,367 +448,255 @@ __device__ __forceinline__ bool link_wave(const EvalArgs& a, int l, int hs, int 
     __syncthreads();   // the spheres' space becomes the parts' space
   }
 
-  // ---- world collision of the link's spheres, cuboid slice h of H ----
-  const int wa = ((cint*)a.world_off)[pb.world], wb = ((cint*)a.world_off)[pb.world + 1];
-  const int per = (wb - wa + H - 1) / H;
-  const int w0 = min(wb, wa + h * per), w1 = min(wb, w0 + per);
-  if (ns > 0 && w1 > w0) {
-    const float w = a.pr.w_coll, eta = a.pr.eta, inv_eta = 1.0f / fmaxf(eta, 1e-30f);
-    // ball around the link's spheres of every lane: centre of the lanes'
+  // ---- the joint wave (HS = 1): joint limits (Eq.(17)) and smoothness
+  //      (Eq.(16)) of joints j = h mod H ----
+  //      (slot group g takes joints g, g + G, ...)
+  if (!link_w) {
+    float gdj = 0.0f;
+    for (int j0 = 0; j0 < D; j0 += G) {
+      const int j = j0 + g;
+      if (j < D) {
+        float js = 0.0f;
+        if (j % H == h)
+          joint_terms(a, pb, row, t, j, qval(row, j), s_lim[j], s_lim[D + j], s_lim[2 * D + j], qval, jc, js);
+        part[(3 + j) * E + el] = js;
+        if (CAND) gdj = fmaf(js, s_d[(row - r_lo) * D + j], gdj);
+      }
+    }
+    jc = groups_sum<G>(jc);
+    gdj = groups_sum<G>(gdj);
+    if (g == 0) {
+      part[0 * E + el] = jc;
+      part[1 * E + el] = a.pr.eta;
+      part[2 * E + el] = gdj;
+    }
+  }
+
+  // ---- world collision, a staged tile of cuboids at a time; the next
+  //      tile is read into registers while this one is tested ----
+  const float w = a.pr.w_coll, eta = a.pr.eta, inv_eta = 1.0f / fmaxf(eta, 1e-30f);
+  float cwx = 0.0f, cwy = 0.0f, cwz = 0.0f, Rw = 0.0f, bxl = 0.0f, byl = 0.0f, bzl = 0.0f, rlb = 0.0f;
+  // (wave-uniform: the wave has a sphere in some slot group; a lane whose
+  // group has none tests unused slots, which never pass)
+  const bool wave_sph = link_w && (HS == 2 ? ns > 0 : info.y > 0);
+  if (wave_sph) {
+    // ball around the wave's spheres of every lane: centre of the lanes'
     // bounding box of ball centres, radius half its diagonal + ball radius
-    const v4f bl = *(cv4f*)(a.wl.ball + l * 3 + (HS == 2 ? 1 + hs : 0));
-    const float bx = T[0] * bl.x + T[1] * bl.y + T[2] * bl.z + T[3];
-    const float by = T[4] * bl.x + T[5] * bl.y + T[6] * bl.z + T[7];
-    const float bz = T[8] * bl.x + T[9] * bl.y + T[10] * bl.z + T[11];
-    const float lx = wave_min(bx), ux = wave_max(bx);
-    const float ly = wave_min(by), uy = wave_max(by);
-    const float lz = wave_min(bz), uz = wave_max(bz);
-    const float cwx = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * (lx + ux))));
-    const float cwy = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * (ly + uy))));
-    const float cwz = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * (lz + uz))));
+    bxl = T[0] * bl.x + T[1] * bl.y + T[2] * bl.z + T[3];
+    byl = T[4] * bl.x + T[5] * bl.y + T[6] * bl.z + T[7];
+    bzl = T[8] * bl.x + T[9] * bl.y + T[10] * bl.z + T[11];
+    const float lx = wave_min(bxl), ux = wave_max(bxl);
+    const float ly = wave_min(byl), uy = wave_max(byl);
+    const float lz = wave_min(bzl), uz = wave_max(bzl);
+    cwx = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * (lx + ux))));
+    cwy = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * (ly + uy))));
+    cwz = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * (lz + uz))));
     const float hx = ux - lx, hy = uy - ly, hz = uz - lz;
     // (widened slightly so rounding never drops a cuboid that matters)
-    const float rw = (0.5f * sqrtf(hx * hx + hy * hy + hz * hz) + bl.w + eta) * 1.0001f + 1e-6f;
-    const float Rw = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rw)));
-    const float rl = (bl.w + eta) * 1.0001f + 1e-6f;   // one lane's ball
-
-    cv4f* boxes = (cv4f*)(a.box);
-    for (int base = w0; base < w1; base += kWave) {
-      // lane j tests cuboid base + j against the wave's ball
-      const int o = base + lane;
-      bool cand = false;
-      if (o < w1) {
-        const float4* bq = reinterpret_cast<const float4*>(a.box + o);
-        const float4 B0 = bq[0], B1 = bq[1], B2 = bq[2], BH = bq[3];
-        const float px = fmaf(B0.x, cwx, fmaf(B0.y, cwy, fmaf(B0.z, cwz, B0.w)));
-        const float py = fmaf(B1.x, cwx, fmaf(B1.y, cwy, fmaf(B1.z, cwz, B1.w)));
-        const float pz = fmaf(B2.x, cwx, fmaf(B2.y, cwy, fmaf(B2.z, cwz, B2.w)));
-        const float m3 = fmaxf(fabsf(px) - BH.x, fmaxf(fabsf(py) - BH.y, fabsf(pz) - BH.z));
-        cand = m3 < Rw;
-      }
-      // (the mask made scalar, so the candidate index and its loads are too)
-      const uint64_t bal = __ballot(cand);
-      uint64_t mask = ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(bal >> 32)) << 32) |
-                      (unsigned)__builtin_amdgcn_readfirstlane((unsigned)bal);
-      // the next candidate's scalar loads are issued one iteration ahead
-      v4f nA0 = {}, nA1 = {}, nA2 = {}, nH = {};
-      if (mask) {
-        const int ob = base + __builtin_ctzll(mask);
-        nA0 = boxes[4 * ob + 0]; nA1 = boxes[4 * ob + 1];
-        nA2 = boxes[4 * ob + 2]; nH = boxes[4 * ob + 3];
-        mask &= mask - 1;
-      }
-      bool more = bal != 0;
-      while (more) {
-        const v4f A0 = nA0, A1 = nA1, A2 = nA2, Hh = nH;
-        more = mask != 0;
-        if (more) {
-          const int ob = base + __builtin_ctzll(mask);
-          nA0 = boxes[4 * ob + 0]; nA1 = boxes[4 * ob + 1];
-          nA2 = boxes[4 * ob + 2]; nH = boxes[4 * ob + 3];
-          mask &= mask - 1;
-        }
-        // second level: this lane's own ball; the wave skips the cuboid
-        // when no lane's ball reaches it
-        {
-          const float px = fmaf(A0.x, bx, fmaf(A0.y, by, fmaf(A0.z, bz, A0.w)));
-          const float py = fmaf(A1.x, bx, fmaf(A1.y, by, fmaf(A1.z, bz, A1.w)));
-          const float pz = fmaf(A2.x, bx, fmaf(A2.y, by, fmaf(A2.z, bz, A2.w)));
-          const float mb = fmaxf(fabsf(px) - Hh.x, fmaxf(fabsf(py) - Hh.y, fabsf(pz) - Hh.z));
-          if (__ballot(mb < rl) == 0) continue;
-        }
-        // slots in groups of at most 8: face tests, then the near path of
-        // the group (bounds the live face-test results)
-        constexpr int G = MAXS < 8 ? MAXS : 8;
-#pragma unroll
-        for (int g0 = 0; g0 < MAXS; g0 += G) {
-        float m3[G];
-        bool any = false;
-#pragma unroll
-        for (int u = 0; u < G; ++u) {
-          const int s = g0 + u;
-          const float px = fmaf(A0.x, cx[s], fmaf(A0.y, cy[s], fmaf(A0.z, cz[s], A0.w)));
-          const float py = fmaf(A1.x, cx[s], fmaf(A1.y, cy[s], fmaf(A1.z, cz[s], A1.w)));
-          const float pz = fmaf(A2.x, cx[s], fmaf(A2.y, cy[s], fmaf(A2.z, cz[s], A2.w)));
-          m3[u] = fmaxf(fabsf(px) - Hh.x, fmaxf(fabsf(py) - Hh.y, fabsf(pz) - Hh.z));
-          any |= m3[u] < rr[s] + eta;
-        }
-        if (any) {
-#pragma unroll
-          for (int u = 0; u < G; ++u) {
-            const int s = g0 + u;
-            if (m3[u] < rr[s] + eta) {
-              const float px = fmaf(A0.x, cx[s], fmaf(A0.y, cy[s], fmaf(A0.z, cz[s], A0.w)));
-              const float py = fmaf(A1.x, cx[s], fmaf(A1.y, cy[s], fmaf(A1.z, cz[s], A1.w)));
-              const float pz = fmaf(A2.x, cx[s], fmaf(A2.y, cy[s], fmaf(A2.z, cz[s], A2.w)));
-              float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-              near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y, fabsf(pz) - Hh.z,
-                        rr[s], w, eta, inv_eta, cost, mc, gx, gy, gz);
-              Fx += gx; Fy += gy; Fz += gz;
-              Mx += cy[s] * gz - cz[s] * gy;
-              My += cz[s] * gx - cx[s] * gz;
-              Mz += cx[s] * gy - cy[s] * gx;
-            }
-          }
-        }
-        }
-      }
-    }
+    const float rw = (0.5f * sqrtf(hx * hx + hy * hy + hz * hz) + (G > 1 ? wave_max(bl.w) : bl.w) + eta) * 1.0001f + 1e-6f;
+    Rw = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rw)));
+    rlb = (bl.w + eta) * 1.0001f + 1e-6f;   // one lane's ball
   }
+  for (int tl = w0, buf = 0; tl < w1; tl += kWlBoxTile, buf ^= 1) {
+    const int nb = min(kWlBoxTile, w1 - tl);
+    const int nn = min(kWlBoxTile, w1 - tl - kWlBoxTile);   // next tile (<= 0: none)
+    const float4* nsrc = reinterpret_cast<const float4*>(a.box + tl + kWlBoxTile);
+    const int i0 = tid, i1 = tid + nthreads;   // 2 x 64 threads cover a tile
+    const float4 u0 = i0 < 4 * nn ? nsrc[i0] : float4{};
+    const float4 u1 = i1 < 4 * nn ? nsrc[i1] : float4{};
+    if (wave_sph)
+      world_tile<MAXS>(s_box + buf * kWlBoxTile * 4, nb, lane, cwx, cwy, cwz, Rw, bxl, byl, bzl, rlb, cx, cy,
+                       cz, rr, w, eta, inv_eta, cost, mc, Fx, Fy, Fz, Mx, My, Mz);
+    if (nn <= 0) break;
+    float4* nxt = s_box + (buf ^ 1) * kWlBoxTile * 4;
+    if (i0 < 4 * nn) nxt[i0] = u0;
+    if (i1 < 4 * nn) nxt[i1] = u1;
+    __syncthreads();
+  }
+
+  if (G > 1 && link_w) {
+    // the slot groups' sums meet in every lane of the evaluation
+    cost = groups_sum<G>(cost);
+    mc = groups_min<G>(mc);
+    Fx = groups_sum<G>(Fx); Fy = groups_sum<G>(Fy); Fz = groups_sum<G>(Fz);
+    Mx = groups_sum<G>(Mx); My = groups_sum<G>(My); Mz = groups_sum<G>(Mz);
+  }
+
+  // ---- two waves per link: the second adds joint l's own terms (l < D)
+  //      and hands its sums to the first ----
   float own_js = 0.0f;
   if (HS == 2) {
-    // the second wave adds joint l's own terms and hands its sums over
-    float* ex = s_ex + (size_t)l * 9 * kWave;
+    float* ex = s_ex + (size_t)l * 9 * E;
     if (hs == 1) {
-      float jc = 0.0f, js = 0.0f;
-      joint_terms(a, pb, row, t, l, qval(row, l), s_lim[l], s_lim[a.rb.dof + l], s_lim[2 * a.rb.dof + l],
-                  qval, jc, js);
-      ex[0 * kWave + lane] = cost + jc;
-      ex[1 * kWave + lane] = mc;
-      ex[2 * kWave + lane] = Fx; ex[3 * kWave + lane] = Fy; ex[4 * kWave + lane] = Fz;
-      ex[5 * kWave + lane] = Mx; ex[6 * kWave + lane] = My; ex[7 * kWave + lane] = Mz;
-      ex[8 * kWave + lane] = js;
+      float js = 0.0f;
+      if (l < D)
+        joint_terms(a, pb, row, t, l, qval(row, l), s_lim[l], s_lim[D + l], s_lim[2 * D + l], qval, cost, js);
+      ex[0 * E + el] = cost;
+      ex[1 * E + el] = mc;
+      ex[2 * E + el] = Fx; ex[3 * E + el] = Fy; ex[4 * E + el] = Fz;
+      ex[5 * E + el] = Mx; ex[6 * E + el] = My; ex[7 * E + el] = Mz;
+      ex[8 * E + el] = js;
     }
     __syncthreads();
-    if (hs == 1) return false;
-    cost += ex[0 * kWave + lane];
-    mc = fminf(mc, ex[1 * kWave + lane]);
-    Fx += ex[2 * kWave + lane]; Fy += ex[3 * kWave + lane]; Fz += ex[4 * kWave + lane];
-    Mx += ex[5 * kWave + lane]; My += ex[6 * kWave + lane]; Mz += ex[7 * kWave + lane];
-    own_js = ex[8 * kWave + lane];
+    if (hs == 0) {
+      cost += ex[0 * E + el];
+      mc = fminf(mc, ex[1 * E + el]);
+      Fx += ex[2 * E + el]; Fy += ex[3 * E + el]; Fz += ex[4 * E + el];
+      Mx += ex[5 * E + el]; My += ex[6 * E + el]; Mz += ex[7 * E + el];
+      own_js = ex[8 * E + el];
+    }
   }
-  part[0 * kWave + lane] = cost;
-  part[1 * kWave + lane] = mc;
-  part[(2 + a.wl.max_depth) * kWave + lane] = own_js;
 
-  // ---- adjoint: the chain again, joint c's derivative z_c . (M - o_c x F) ----
-  if (GRAD) {
-    chain_fk(a, l, depth, row, qval, T, [&](int i, const float* P) {
-      const float zx = P[2], zy = P[6], zz = P[10], ox = P[3], oy = P[7], oz = P[11];
-      const float vx = Mx - (oy * Fz - oz * Fy);
-      const float vy = My - (oz * Fx - ox * Fz);
-      const float vz = Mz - (ox * Fy - oy * Fx);
-      part[(2 + i) * kWave + lane] = zx * vx + zy * vy + zz * vz;
-    });
-  }
-  return true;
-}
-
-// NT: launch bound, 512 threads for robots of up to 7 links (register
-// budget of two waves per SIMD), else 1024.
-template <int MAXS, bool CAND, bool GRAD, int NT>
-__global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
-  extern __shared__ float s_part[];
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int lane = threadIdx.x % kWave;
-  const int L = a.rb.n_links, D = a.rb.dof, K = a.K;
-  const int bx = blockIdx.x;
-  int lo = 0, hi = a.P;
-  cint* chunk_prefix = (cint*)a.chunk_prefix;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (chunk_prefix[mid] <= bx) lo = mid; else hi = mid;
-  }
-  // (the problem, its table row and everything derived from them are wave
-  // uniform; reading them through the constant address space keeps them in
-  // scalar registers, so the cuboid loop below runs on scalar loads)
-  const int p = __builtin_amdgcn_readfirstlane(lo);
-  Problem pb;
-  {
-    const v4i p0 = ((cv4i*)(a.prob + p))[0], p1 = ((cv4i*)(a.prob + p))[1];
-    pb.S = p0.x; pb.T = p0.y; pb.world = p0.z; pb.row0 = p0.w;
-    pb.seed0 = p1.x; pb.pad0 = p1.y; pb.pad1 = p1.z; pb.pad2 = p1.w;
-  }
-  const int n_e = pb.S * pb.T * K;
-  const int e0 = (bx - chunk_prefix[p]) * kWave + lane;
-  const bool valid = e0 < n_e;
-  const int e = valid ? e0 : n_e - 1;
-  const int rl = e / K, k = e - rl * K;       // candidates of a row side by side
-  const int t = rl % pb.T;
-  const int row = pb.row0 + rl;
-  const float alpha = CAND ? a.alpha[k < kMaxK ? k : 0] : 0.0f;
-  const float* dk = CAND ? a.d : nullptr;     // one direction for every candidate
-
-  // waves: one per link and one for the joint terms (HS = 1), or two per
-  // link with half of its spheres each (HS = 2, robots of up to 8 links)
-  const int HS = a.wl.halves;
-  const int W = HS == 2 ? 2 * L : L + 1;
-  // LDS: the link parts (3 + deepest chain each: cost, clearance, the
-  // chain's derivatives, the own joint's terms), the joint part (2 + D), the
-  // halves' hand-over (9 per link), or, during the self-collision phase, the
-  // sphere centres and winners; then the staged rows
-  const int NP = 2 + D;
-  const int NPL = 3 + a.wl.max_depth;
-  float* s_joint = s_part + (size_t)L * NPL * kWave;
-  float* s_ex = s_joint + (size_t)NP * kWave;
-
-  // the workgroup's rows and the four on either side (the stencils' reach)
-  // are staged in LDS once: every wave reads its joint values from there
-  const int e_first = (bx - chunk_prefix[p]) * kWave;
-  const int e_last = min(n_e, e_first + kWave) - 1;
-  const int p_end = pb.row0 + pb.S * pb.T;
-  const int r_lo = max(pb.row0, pb.row0 + e_first / K - 4);
-  const int r_hi = min(p_end - 1, pb.row0 + e_last / K + 4);
-  const int n_st = (r_hi - r_lo + 1) * D;
-  float* s_x = s_part + wl_region_floats(L, D, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0, HS);
-  float* s_d = s_x + kStageRows * D;
-  // and the joint limits and the problem's start (lower, upper, start)
-  float* s_lim = s_d + kStageRows * D;
-  for (int i = threadIdx.x; i < n_st; i += blockDim.x) {
-    s_x[i] = a.x[(size_t)r_lo * D + i];
-    if (CAND) s_d[i] = dk[(size_t)r_lo * D + i];
-  }
-  for (int i = threadIdx.x; i < D; i += blockDim.x) {
-    s_lim[i] = a.rb.q_lo[i];
-    s_lim[D + i] = a.rb.q_hi[i];
-    s_lim[2 * D + i] = a.q_start[(size_t)p * D + i];
+  // ---- adjoint: the chain again, joint c's derivative z_c . (M - o_c x F),
+  //      and this link's share of the directional derivative ----
+  if (link_w && hs == 0) {
+    const int xr = (row - r_lo) * D;
+    float gdp = 0.0f;
+    if (GRAD) {
+      chain_fk(rec, depth, row, qval, T, [&](int i, int c, const float* P) {
+        const float zx = P[2], zy = P[6], zz = P[10], ox = P[3], oy = P[7], oz = P[11];
+        const float vx = Mx - (oy * Fz - oz * Fy);
+        const float vy = My - (oz * Fx - ox * Fz);
+        const float vz = Mz - (ox * Fy - oy * Fx);
+        const float gj = zx * vx + zy * vy + zz * vz;
+        if (g == 0) part[(4 + i) * E + el] = gj;
+        if (CAND) gdp = fmaf(gj, s_d[xr + c], gdp);
+      });
+      if (CAND && HS == 2 && l < D) gdp = fmaf(own_js, s_d[xr + l], gdp);
+    }
+    if (g == 0) {
+      part[0 * E + el] = cost;
+      part[1 * E + el] = mc;
+      part[2 * E + el] = gdp;
+      part[3 * E + el] = own_js;
+    }
   }
   __syncthreads();
-  auto qval = [&](int r, int j) -> float {
-    const int i = (r - r_lo) * D + j;
-    float v = s_x[i];
-    if (CAND) {
-      v = fmaf(alpha, s_d[i], v);
-      v = fminf(fmaxf(v, s_lim[j]), s_lim[D + j]);
-    }
-    return v;
-  };
 
-  // cuboid slice of this workgroup (gridDim.y slices share a chunk)
-  const int h = __builtin_amdgcn_readfirstlane(blockIdx.y), H = __builtin_amdgcn_readfirstlane(gridDim.y);
-  const int n_link_waves = L * HS;
-  float* part = wave < n_link_waves ? s_part + (size_t)(wave / HS) * NPL * kWave : s_joint;
-  // self-collision in the first slice: sphere centres and per-wave winners
-  // follow the wave parts in LDS
-  const bool self_on = a.pr.n_self > 0 && h == 0;
-  float* s_sph = s_part;     // (shares the parts' space, see link_wave)
-  float* s_best = s_sph + (size_t)a.rb.n_spheres * 3 * kWave;
-  if (wave < n_link_waves) {
-    link_wave<MAXS, GRAD>(a, wave / HS, wave % HS, HS, p, pb, row, t, valid, h, H, qval, part, lane,
-                          self_on, s_sph, s_best, W, s_ex, s_lim);
-  } else {
-    float jc = 0.0f;
-    if (self_on) {
-      __syncthreads();
-      self_pairs_phase(a, wave, W, s_sph, s_best, lane);
-      __syncthreads();
-      float bv;
-      int bk;
-      self_winner(W, s_best, lane, bv, bk);
-      jc += a.pr.w_self * bv;
-      __syncthreads();   // the spheres' space becomes the parts' space
-    }
-    // joint limits (Eq.(17)) and smoothness (Eq.(16)): joints j = h mod H
-    for (int j = 0; j < D; ++j) {
-      float js = 0.0f;
-      if (j % H == h)
-        joint_terms(a, pb, row, t, j, qval(row, j), s_lim[j], s_lim[D + j], s_lim[2 * D + j], qval, jc, js);
-      part[(2 + j) * kWave + lane] = js;
-    }
-    part[0 * kWave + lane] = jc;
-    part[1 * kWave + lane] = a.pr.eta;
-  }
-  __syncthreads();
-  if (wave != W - 1) return;
-
-  // ---- the last wave sums the waves' parts in a fixed order: links in
-  //      order, then its own; joint derivatives gather into its part ----
-  float cost = 0.0f, mc = 3.0e38f;
-  for (int v = 0; v < L; ++v) {
-    cost += s_part[(v * NPL + 0) * kWave + lane];
-    mc = fminf(mc, s_part[(v * NPL + 1) * kWave + lane]);
-  }
-  if (HS == 1) {
-    cost += s_joint[lane];
-    mc = fminf(mc, s_joint[kWave + lane]);
-  }
-  if (GRAD) {
-    // joint j sits at chain position pos_j of every link in its subtree;
-    // its own terms come from the joint part (HS = 1) or link j's part
-    cint* jrec = (cint*)(a.wl.joint_rec);
-    for (int j = 0; j < D; ++j) {
-      const int pos = jrec[2 * j], sub = jrec[2 * j + 1];
-      float g = HS == 1 ? s_joint[(2 + j) * kWave + lane]
-                        : s_part[(j * NPL + 2 + a.wl.max_depth) * kWave + lane];
-#pragma unroll
-      for (int v = 0; v < 15; ++v)
-        if (v < L && ((sub >> v) & 1)) g += s_part[(v * NPL + 2 + pos) * kWave + lane];
-      s_joint[(2 + j) * kWave + lane] = g;
+  // ---- combine: wave j < D gathers joint j's derivative from the links
+  //      whose chain holds it (in link order); the last wave sums cost,
+  //      clearance and directional derivative over the links in order,
+  //      then the joint wave's ----
+  const size_t eo = (size_t)k * a.rows + row;
+  float gsum = 0.0f;
+  if (GRAD && wave < D) {
+    gsum = HS == 1 ? s_joint[(3 + wave) * E + el] : s_part[((size_t)wave * NPL + 3) * E + el];
+    for (int v = 0; v < L; ++v) {
+      const float x = s_part[((size_t)v * NPL + 4 + jpos) * E + el];
+      gsum += ((jsub >> v) & 1) ? x : 0.0f;
     }
   }
-  if (H > 1) {
+  float tc = 0.0f, tm = 3.0e38f, tg = 0.0f;
+  if (wave == W - 1) {
+    for (int v = 0; v < L; ++v) {
+      tc += s_part[((size_t)v * NPL + 0) * E + el];
+      tm = fminf(tm, s_part[((size_t)v * NPL + 1) * E + el]);
+      tg += s_part[((size_t)v * NPL + 2) * E + el];
+    }
+    if (HS == 1) {
+      tc += s_joint[0 * E + el];
+      tm = fminf(tm, s_joint[1 * E + el]);
+      tg += s_joint[2 * E + el];
+    }
+  }
+  if (G == 1 && H > 1) {
     // park this slice's sums; the last workgroup of the chunk to arrive
     // adds the slices in slice order (deterministic whatever the arrival
-    // order) and finishes the evaluation
+    // order) and finishes the evaluation.  (Agent-scope atomic accesses:
+    // the slices may run on different XCDs, whose L2 caches are not
+    // coherent with each other.)
+    const int NP = 3 + D;
     const size_t cbase = (size_t)bx * H * NP * kWave;
     float* mine = a.wl.part + cbase + (size_t)h * NP * kWave;
-    // (agent-scope atomic accesses: the slices may run on different XCDs,
-    // whose L2 caches are not coherent with each other)
-    part_store(mine + 0 * kWave + lane, cost);
-    part_store(mine + 1 * kWave + lane, mc);
-    if (GRAD)
-      for (int j = 0; j < D; ++j) part_store(mine + (2 + j) * kWave + lane, s_joint[(2 + j) * kWave + lane]);
+    if (GRAD && wave < D) part_store(mine + (3 + wave) * kWave + lane, gsum);
+    if (wave == W - 1) {
+      part_store(mine + 0 * kWave + lane, tc);
+      part_store(mine + 1 * kWave + lane, tm);
+      part_store(mine + 2 * kWave + lane, tg);
+    }
     __threadfence();
-    int ticket = 0;
-    if (lane == 0) ticket = atomicAdd(a.wl.count + bx, 1);
-    ticket = __shfl(ticket, 0, kWave);
+    __syncthreads();
+    if (wave == 0) {
+      int ticket = 0;
+      if (lane == 0) ticket = atomicAdd(a.wl.count + bx, 1);
+      ticket = __shfl(ticket, 0, kWave);
+      if (lane == 0) s_tick[0] = ticket;
+    }
+    __syncthreads();
+    const int ticket = __builtin_amdgcn_readfirstlane(s_tick[0]);
     if (ticket != H - 1) return;
     __threadfence();
-    if (lane == 0) __hip_atomic_store(a.wl.count + bx, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    cost = 0.0f;
-    mc = 3.0e38f;
-    for (int u = 0; u < H; ++u) {
-      const float* pu = a.wl.part + cbase + (size_t)u * NP * kWave;
-      cost += part_load(pu + lane);
-      mc = fminf(mc, part_load(pu + kWave + lane));
+    if (wave == 0 && lane == 0) __hip_atomic_store(a.wl.count + bx, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (GRAD && wave < D) {
+      gsum = 0.0f;
+      for (int u = 0; u < H; ++u)
+        gsum += part_load(a.wl.part + cbase + ((size_t)u * NP + 3 + wave) * kWave + lane);
     }
-  }
-  const size_t eo = (size_t)k * a.rows + row;
-  float gd = 0.0f;
-  if (GRAD) {
-    for (int j = 0; j < D; ++j) {
-      float g = 0.0f;
-      if (H > 1) {
-        const size_t cbase = (size_t)bx * H * NP * kWave;
-        for (int u = 0; u < H; ++u)
-          g += part_load(a.wl.part + cbase + ((size_t)u * NP + 2 + j) * kWave + lane);
-      } else {
-        g = s_joint[(2 + j) * kWave + lane];
+    if (wave == W - 1) {
+      tc = 0.0f; tm = 3.0e38f; tg = 0.0f;
+      for (int u = 0; u < H; ++u) {
+        const float* pu = a.wl.part + cbase + (size_t)u * NP * kWave;
+        tc += part_load(pu + 0 * kWave + lane);
+        tm = fminf(tm, part_load(pu + 1 * kWave + lane));
+        tg += part_load(pu + 2 * kWave + lane);
       }
-      if (valid) a.grad_e[eo * D + j] = g;
-      if (CAND) gd = fmaf(g, s_d[(row - r_lo) * D + j], gd);
     }
   }
-  if (valid) {
-    a.cost_e[eo] = cost;
-    if (a.mc_e) a.mc_e[eo] = mc;
-    if (CAND && GRAD) a.gd_e[eo] = gd;
+  if (!valid || g != 0) return;
+  if (GRAD && wave < D) a.grad_e[eo * D + wave] = gsum;
+  if (wave == W - 1) {
+    a.cost_e[eo] = tc;
+    if (a.mc_e) a.mc_e[eo] = tm;
+    if (CAND && GRAD) a.gd_e[eo] = tg;
   }
+}
+
+// Launch one instantiation; more than 64 KB of LDS needs the kernel's
+// dynamic-LDS limit raised first.
+template <typename KF>
+hipError_t wl_launch(KF kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, const EvalArgs& a) {
+  if (lds > 64 * 1024) {
+    const hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  kern<<<grid, block, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+template <int MAXS, int G>
+hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
+  const int HS = a.wl.halves;
+  const int waves = HS == 2 ? 2 * a.rb.n_links : a.rb.n_links + 1;
+  if (waves * kWave > 1024 || slices < 1 || ((HS == 2 || G > 1) && slices > 1)) return hipErrorInvalidValue;
+  if (G > 1 && (HS != 1 || a.pr.n_self > 0)) return hipErrorInvalidValue;
+  if (slices > 1 && (!a.wl.part || !a.wl.count)) return hipErrorInvalidValue;
+  // particle mode (per-candidate draws) is not staged in this layout
+  if (a.var || a.d_stride) return hipErrorInvalidValue;
+  // every joint has a gathering wave, the last wave is none of them, and
+  // two 64-thread passes cover a cuboid tile
+  if (a.rb.dof > waves - 1 || waves < 2 || !a.wl.chunk) return hipErrorInvalidValue;
+  const size_t lds = wl_lds_bytes(a.rb.n_links, a.rb.dof, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0, HS,
+                                  a.wl.maxs, kWave / G);
+  if (lds > kWlLdsMax) return hipErrorInvalidValue;
+  const dim3 grid(grid_x, slices), block(waves * kWave);
+  if (waves <= 8) {
+    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G>, grid, block, lds, s, a);
+    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G>, grid, block, lds, s, a);
+    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G>, grid, block, lds, s, a);
+    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G>, grid, block, lds, s, a);
+  }
+  if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G>, grid, block, lds, s, a);
+  if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G>, grid, block, lds, s, a);
+  if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G>, grid, block, lds, s, a);
+  return wl_launch(eval_wl_kernel<MAXS, true, false, 1024, G>, grid, block, lds, s, a);
 }
 
 template <int MAXS>
 hipError_t launch_eval_wl_s(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
-  const int HS = a.wl.halves;
-  const int waves = HS == 2 ? 2 * a.rb.n_links : a.rb.n_links + 1;
-  if (waves * kWave > 1024 || slices < 1 || (HS == 2 && slices > 1)) return hipErrorInvalidValue;
-  if (slices > 1 && (!a.wl.part || !a.wl.count)) return hipErrorInvalidValue;
-  // particle mode (per-candidate draws) is not staged in this layout
-  if (a.var || a.d_stride) return hipErrorInvalidValue;
-  const size_t lds = wl_lds_bytes(a.rb.n_links, a.rb.dof, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0, HS);
-  if (lds > kWlLdsMax) return hipErrorInvalidValue;
-  const dim3 grid(grid_x, slices), block(waves * kWave);
-  if (waves <= 8) {
-    if (cand && grad) eval_wl_kernel<MAXS, true, true, 512><<<grid, block, lds, s>>>(a);
-    else if (grad) eval_wl_kernel<MAXS, false, true, 512><<<grid, block, lds, s>>>(a);
-    else if (!cand) eval_wl_kernel<MAXS, false, false, 512><<<grid, block, lds, s>>>(a);
-    else eval_wl_kernel<MAXS, true, false, 512><<<grid, block, lds, s>>>(a);
-  } else {
-    if (cand && grad) eval_wl_kernel<MAXS, true, true, 1024><<<grid, block, lds, s>>>(a);
-    else if (grad) eval_wl_kernel<MAXS, false, true, 1024><<<grid, block, lds, s>>>(a);
-    else if (!cand) eval_wl_kernel<MAXS, false, false, 1024><<<grid, block, lds, s>>>(a);
-    else eval_wl_kernel<MAXS, true, false, 1024><<<grid, block, lds, s>>>(a);
-  }
-  return hipGetLastError();
+  if (a.wl.groups == 2) return launch_eval_wl_g<MAXS, 2>(a, grid_x, slices, cand, grad, s);
+  if (a.wl.groups != 1) return hipErrorInvalidValue;
+  return launch_eval_wl_g<MAXS, 1>(a, grid_x, slices, cand, grad, s);
 }
 
 }  // namespace

@@ -3,8 +3,9 @@
 
 namespace mg {
 hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
-  // sphere slots per wave: all of a link's, or half with two waves per link
-  const int per = a.wl.halves == 2 ? a.wl.maxs / 2 : a.wl.maxs;
+  // sphere slots per lane: all of a link's, or half with two waves per link
+  // or two slot groups per wave
+  const int per = (a.wl.halves == 2 || a.wl.groups == 2) ? a.wl.maxs / 2 : a.wl.maxs;
   if (per == 2) return launch_eval_wl_s<2>(a, grid_x, slices, cand, grad, s);
   if (per == 4) return launch_eval_wl_s<4>(a, grid_x, slices, cand, grad, s);
   if (per == 8) return launch_eval_wl_s<8>(a, grid_x, slices, cand, grad, s);

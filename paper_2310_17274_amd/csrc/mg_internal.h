@@ -67,10 +67,19 @@ struct Lanes {
   const float4* sphere;    // [lpe][maxs] center in link frame + radius
 };
 
+// One 64-evaluation chunk of the wave-per-link layout: its problem, its
+// first evaluation within the problem, the problem's seeds, horizon, first
+// row and evaluation count, and its world's cuboid range.
+struct WlChunk {
+  int p, e_first, S, T;
+  int box_lo, box_hi, row0, n_e;
+};
+
 // Wave-per-link layout of the evaluation kernel: a workgroup holds 64
 // evaluations; wave l owns link l (its kinematic chain, spheres and end
 // effector) for all 64, the last wave owns the joint terms.
 struct WaveLinks {
+  const WlChunk* chunk;    // [workgroups along x] (per candidate count K)
   const int4* info;        // [L]: chain depth, spheres, end effector or -1, 0
   const int* chain;        // [L][kMaxDof]: links from the root down to l
   const int* joint_rec;    // [D][2]: chain position of joint j (its link's depth - 1) and
@@ -83,8 +92,10 @@ struct WaveLinks {
   int maxs;
   int max_depth;           // deepest chain (joints from the root)
   int halves;              // waves per link: 1, or 2 (each with half of the slots)
+  int groups;              // slot groups per wave: 1, or 2 (32 evaluations per workgroup,
+                           //   each half of the wave with half of the slots; halves == 1)
   // cuboid slices over workgroups (gridDim.y > 1): per-slice partial sums
-  // [chunk][slice][2 + D][64] and one arrival counter per chunk (zero
+  // [chunk][slice][3 + D][64] and one arrival counter per chunk (zero
   // between launches; the last workgroup of a chunk resets it)
   float* part;
   int* count;
@@ -94,25 +105,56 @@ struct WaveLinks {
   const int* slot_sphere;
 };
 
-// LDS of a wave-per-link workgroup: the L link waves' parts (2 + deepest
-// chain floats per lane) and the joint wave's (2 + D), or, while the
-// self-collision phase runs, the sphere centres and per-wave winners; then
-// the staged rows (x and d).
-constexpr size_t kWlLdsMax = 64 * 1024;
+// LDS of a wave-per-link workgroup.  First a region that holds, in turn,
+// the self-collision phase's sphere centres and per-wave winners, then the
+// waves' parts: per link 4 + deepest chain floats per lane (cost,
+// clearance, directional derivative, own joint's terms, the chain's joint
+// derivatives), the joint wave's 3 + D (cost, clearance, directional
+// derivative, joint terms), and with two waves per link the halves'
+// hand-over (9 per link).  Then what the workgroup stages once: rows of x
+// and d, joint limits and start, goal poses and tool transforms, the chain
+// records, sphere slots and two cuboid tiles (float4 aligned), and the
+// slice ticket.
+constexpr size_t kWlLdsMax = 160 * 1024;   // LDS of a gfx950 CU (the device may report less)
 constexpr int kWlStageRows = kWave + 8;
-// The self-collision phase runs before any part is written, so its sphere
-// centres and winners share the parts' space.
+constexpr int kWlBoxTile = 64;   // cuboids per staged tile
+// E: evaluations per workgroup (64 / slot groups per wave).
 __host__ __device__ inline size_t wl_region_floats(int L, int D, int max_depth, int n_spheres, bool self,
-                                                   int halves) {
-  const size_t parts = ((size_t)L * (3 + max_depth) + 2 + D + (halves == 2 ? 9 * (size_t)L : 0)) * kWave;
+                                                   int halves, int E) {
+  const size_t parts = ((size_t)L * (4 + max_depth) + 3 + D + (halves == 2 ? 9 * (size_t)L : 0)) * E;
   const size_t waves = halves == 2 ? 2 * (size_t)L : (size_t)L + 1;
   const size_t selfb = self ? ((size_t)n_spheres * 3 + 2 * waves) * kWave : 0;
   return parts > selfb ? parts : selfb;
 }
+// float offsets of the staged tables
+struct WlLds {
+  size_t x, d, lim, goal, etf, chain, slot, box, tick, total;
+};
+__host__ __device__ inline WlLds wl_lds_layout(int L, int D, int max_depth, int n_spheres, bool self,
+                                               int halves, int maxs, int E) {
+  WlLds o;
+  size_t at = wl_region_floats(L, D, max_depth, n_spheres, self, halves, E);
+  auto take = [&at](size_t n) {
+    const size_t r = at;
+    at += (n + 3) & ~(size_t)3;
+    return r;
+  };
+  o.x = take((size_t)kWlStageRows * D);
+  o.d = take((size_t)kWlStageRows * D);
+  o.lim = take(3 * (size_t)D);
+  o.goal = take((size_t)kMaxEE * 7);
+  o.etf = take((size_t)kMaxEE * 12);
+  // chain records, sphere slots and the cuboid tiles are contiguous (float4)
+  o.chain = take((size_t)L * max_depth * 16);
+  o.slot = take((size_t)L * maxs * 4);
+  o.box = take(2 * (size_t)kWlBoxTile * 16);
+  o.tick = take(4);
+  o.total = at;
+  return o;
+}
 __host__ __device__ inline size_t wl_lds_bytes(int L, int D, int max_depth, int n_spheres, bool self,
-                                               int halves) {
-  return (wl_region_floats(L, D, max_depth, n_spheres, self, halves) + 2 * (size_t)kWlStageRows * D +
-          3 * (size_t)D) * sizeof(float);
+                                               int halves, int maxs, int E) {
+  return wl_lds_layout(L, D, max_depth, n_spheres, self, halves, maxs, E).total * sizeof(float);
 }
 
 // Cuboid in the library layout: p = A c + b maps a world point into the box

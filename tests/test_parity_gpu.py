@@ -17,10 +17,12 @@ from tests import harness as H
 pytestmark = pytest.mark.gpu
 
 # evaluation layouts (layout, slices): lane per link (automatic slices),
-# wave per link in one workgroup per 64 evaluations, and split over four
-# workgroups (the last to finish adds the slices)
+# wave per link in one workgroup per 64 evaluations, split over four
+# workgroups (the last to finish adds the slices), two waves per link, and
+# two slot groups per wave (32 evaluations per workgroup)
 LAYOUTS = [pytest.param((0, 0), id="lane"), pytest.param((1, 1), id="wave"),
-           pytest.param((1, 4), id="wave4"), pytest.param((2, 0), id="wave2")]
+           pytest.param((1, 4), id="wave4"), pytest.param((2, 0), id="wave2"),
+           pytest.param((3, 0), id="groups2")]
 
 
 def _dev(a):
@@ -43,6 +45,8 @@ class Case:
         if layout is not None:
             if layout[0] == 2 and self.robot.n_links > 8:
                 pytest.skip("two waves per link need at most 8 links")
+            if layout[0] == 3 and self_pairs is not None:
+                pytest.skip("two slot groups per wave take no self-collision")
             self.b.mg_batch_set_layout(*layout)
         D = self.robot.dof
         self.q_start = _dev(b.q_start)
@@ -299,7 +303,9 @@ def test_autotuned_layout_keeps_parity():
     c0, g0, _ = case.ctx.mg_cost_grad(case.b, case.q_start, case.goal, case.x)
     d = case.ctx.mg_lbfgs_step(case.b, 4, True, case.x, g0)
     h = case.ctx.mg_autotune(case.b, case.q_start, case.goal, case.x, d, wl.ALPHA_4, launches=3)
-    assert h in (1, 2, 4, -1, -2, -4)   # lane-per-link slices or minus wave-per-link workgroups
+    # lane-per-link slices, minus wave-per-link workgroups, two waves per
+    # link (-8) or two slot groups per wave (-16)
+    assert h in (1, 2, 4, -1, -2, -4, -8, -16)
     c, g, mc = gpu_cost_grad(case)
     cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, 7))
     H.assert_cost_close(c, cr)
