@@ -161,49 +161,44 @@ __device__ __forceinline__ void mat_to_quat(const float* T, float& qw, float& qx
 // given a = |p| - h componentwise (Sec. world collision: closest point and
 // inside/outside sign), and its gradient in the box frame.  Inside, the
 // gradient is the outward normal of the nearest face, lowest axis on ties.
+// Branch-free: the outside and inside forms are both formed and selected
+// (the lanes of a wave differ), with the hardware square root.
 __device__ __forceinline__ float box_sdf(float px, float py, float pz, float ax, float ay, float az,
                                          float& gpx, float& gpy, float& gpz) {
   const float qx = fmaxf(ax, 0.0f), qy = fmaxf(ay, 0.0f), qz = fmaxf(az, 0.0f);
   const float n2 = qx * qx + qy * qy + qz * qz;
-  gpx = gpy = gpz = 0.0f;
-  if (n2 > 0.0f) {
-    const float n = sqrtf(n2), inv = __builtin_amdgcn_rcpf(n);
-    gpx = (px >= 0.0f ? qx : -qx) * inv;
-    gpy = (py >= 0.0f ? qy : -qy) * inv;
-    gpz = (pz >= 0.0f ? qz : -qz) * inv;
-    return n;
-  }
-  if (ax >= ay && ax >= az) gpx = px >= 0.0f ? 1.0f : -1.0f;
-  else if (ay >= az) gpy = py >= 0.0f ? 1.0f : -1.0f;
-  else gpz = pz >= 0.0f ? 1.0f : -1.0f;
-  return fmaxf(ax, fmaxf(ay, az));
+  const bool out = n2 > 0.0f;
+  const float n = __builtin_amdgcn_sqrtf(n2);
+  const float inv = __builtin_amdgcn_rcpf(out ? n : 1.0f);
+  const float sx = px >= 0.0f ? 1.0f : -1.0f, sy = py >= 0.0f ? 1.0f : -1.0f, sz = pz >= 0.0f ? 1.0f : -1.0f;
+  const bool ix = ax >= ay && ax >= az, iy = !ix && ay >= az, iz = !ix && !iy;
+  gpx = out ? sx * qx * inv : (ix ? sx : 0.0f);
+  gpy = out ? sy * qy * inv : (iy ? sy : 0.0f);
+  gpz = out ? sz * qz * inv : (iz ? sz : 0.0f);
+  return out ? n : fmaxf(ax, fmaxf(ay, az));
 }
 
 // Eq.(10) smoothed penetration cost w d_c(r - sdf) added to cost; the box-frame
 // gradient (gpx, gpy, gpz) of sdf is rotated back to the world and
-// d cost / d point is accumulated into g.
+// d cost / d point is accumulated into g.  Outside the band (r - sdf <=
+// -eta) both are zero.  Branch-free.
 __device__ __forceinline__ void dc_term(const v4f& A0, const v4f& A1, const v4f& A2, float sdf,
                                         float gpx, float gpy, float gpz, float r, float w,
                                         float eta, float inv_eta, float& cost, float& gx, float& gy,
                                         float& gz) {
   const float pen = r - sdf;
-  if (pen > -eta) {
-    float dcv, slope;
-    if (pen > 0.0f) {
-      dcv = pen + 0.5f * eta;
-      slope = 1.0f;
-    } else {
-      const float u = pen + eta;
-      dcv = 0.5f * u * u * inv_eta;
-      slope = u * inv_eta;
-    }
-    cost += w * dcv;
-    // d cost / d c = -w slope A^T grad_p
-    const float f = -w * slope;
-    gx = fmaf(f, A0.x * gpx + A1.x * gpy + A2.x * gpz, gx);
-    gy = fmaf(f, A0.y * gpx + A1.y * gpy + A2.y * gpz, gy);
-    gz = fmaf(f, A0.z * gpx + A1.z * gpy + A2.z * gpz, gz);
-  }
+  const float u = pen + eta;
+  const bool deep = pen > 0.0f, band = pen > -eta;
+  float dcv = deep ? pen + 0.5f * eta : 0.5f * u * u * inv_eta;
+  float slope = deep ? 1.0f : u * inv_eta;
+  dcv = band ? dcv : 0.0f;
+  slope = band ? slope : 0.0f;
+  cost += w * dcv;
+  // d cost / d c = -w slope A^T grad_p
+  const float f = -w * slope;
+  gx = fmaf(f, A0.x * gpx + A1.x * gpy + A2.x * gpz, gx);
+  gy = fmaf(f, A0.y * gpx + A1.y * gpy + A2.y * gpz, gy);
+  gz = fmaf(f, A0.z * gpx + A1.z * gpy + A2.z * gpz, gz);
 }
 
 // One sphere against one cuboid, taken only when the cheap face test says

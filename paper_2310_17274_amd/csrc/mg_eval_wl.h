@@ -184,18 +184,19 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
     }
     // slots in groups of at most 8: face tests, then the near path of the
     // group (bounds the live face-test results)
+    // (the box-frame points of the group stay live for the near path)
     constexpr int G = MAXS < 8 ? MAXS : 8;
 #pragma unroll
     for (int g0 = 0; g0 < MAXS; g0 += G) {
-      float m3[G];
+      float m3[G], ppx[G], ppy[G], ppz[G];
       bool any = false;
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int s = g0 + u;
-        const float px = fmaf(A0.x, cx[s], fmaf(A0.y, cy[s], fmaf(A0.z, cz[s], A0.w)));
-        const float py = fmaf(A1.x, cx[s], fmaf(A1.y, cy[s], fmaf(A1.z, cz[s], A1.w)));
-        const float pz = fmaf(A2.x, cx[s], fmaf(A2.y, cy[s], fmaf(A2.z, cz[s], A2.w)));
-        m3[u] = fmaxf(fabsf(px) - Hh.x, fmaxf(fabsf(py) - Hh.y, fabsf(pz) - Hh.z));
+        ppx[u] = fmaf(A0.x, cx[s], fmaf(A0.y, cy[s], fmaf(A0.z, cz[s], A0.w)));
+        ppy[u] = fmaf(A1.x, cx[s], fmaf(A1.y, cy[s], fmaf(A1.z, cz[s], A1.w)));
+        ppz[u] = fmaf(A2.x, cx[s], fmaf(A2.y, cy[s], fmaf(A2.z, cz[s], A2.w)));
+        m3[u] = fmaxf(fabsf(ppx[u]) - Hh.x, fmaxf(fabsf(ppy[u]) - Hh.y, fabsf(ppz[u]) - Hh.z));
         any |= m3[u] < rr[s] + eta;
       }
       if (any) {
@@ -203,9 +204,7 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
         for (int u = 0; u < G; ++u) {
           const int s = g0 + u;
           if (m3[u] < rr[s] + eta) {
-            const float px = fmaf(A0.x, cx[s], fmaf(A0.y, cy[s], fmaf(A0.z, cz[s], A0.w)));
-            const float py = fmaf(A1.x, cx[s], fmaf(A1.y, cy[s], fmaf(A1.z, cz[s], A1.w)));
-            const float pz = fmaf(A2.x, cx[s], fmaf(A2.y, cy[s], fmaf(A2.z, cz[s], A2.w)));
+            const float px = ppx[u], py = ppy[u], pz = ppz[u];
             float gx = 0.0f, gy = 0.0f, gz = 0.0f;
             near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y, fabsf(pz) - Hh.z, rr[s],
                       w, eta, inv_eta, cost, mc, gx, gy, gz);
@@ -272,7 +271,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   // (the ball of this lane's slot group: all slots, or half of them)
   const v4f bl = *(cv4f*)(a.wl.ball + l * 3 + (HS == 2 ? 1 + hs : (G == 2 ? 1 + lane / E : 0)));
   const int jw = wave < D ? wave : 0;
-  const int jpos = ((cint*)a.wl.joint_rec)[2 * jw], jsub = ((cint*)a.wl.joint_rec)[2 * jw + 1];
+  const int jsub = ((cint*)a.wl.joint_rec)[2 * jw + 1];
 
   const int e0 = e_first + el;
   const bool valid = e0 < n_e;
@@ -358,9 +357,11 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     return v;
   };
 
-  // parts: quantity q of evaluation el at part[q * E + el]
+  // parts: quantity q of evaluation el at part[q * E + el]; per link
+  // cost, clearance, directional derivative, own joint's terms, the wrench
+  // (F, M about the world origin) and the link frame's z axis and origin
   float* s_part = s_mem;
-  const int NPL = 4 + maxd;
+  constexpr int NPL = kWlPartsPerLink;
   float* s_joint = s_part + (size_t)L * NPL * E;
   float* s_ex = s_joint + (size_t)(3 + D) * E;
   float* part = link_w ? s_part + (size_t)l * NPL * E : s_joint;
@@ -375,8 +376,24 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   float cost = 0.0f, mc = a.pr.eta;
   float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, Mx = 0.0f, My = 0.0f, Mz = 0.0f;
   float cx[MAXS], cy[MAXS], cz[MAXS], rr[MAXS];
+  float wx = 0.0f, wy = 0.0f, wz = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
   if (link_w) {
-    chain_fk(rec, depth, row, qval, T, [](int, int, const float*) {});
+    if (CAND && GRAD) {
+      // the link's velocity under the joint rates d (omega = sum d_c z_c,
+      // v = sum d_c o_c x z_c over its chain): its share of the directional
+      // derivative is then M . omega + F . v
+      const int xr = (row - r_lo) * D;
+      chain_fk(rec, depth, row, qval, T, [&](int, int c, const float* P) {
+        const float dc = s_d[xr + c];
+        const float zx = P[2], zy = P[6], zz = P[10], ox = P[3], oy = P[7], oz = P[11];
+        wx = fmaf(dc, zx, wx); wy = fmaf(dc, zy, wy); wz = fmaf(dc, zz, wz);
+        vx = fmaf(dc, oy * zz - oz * zy, vx);
+        vy = fmaf(dc, oz * zx - ox * zz, vy);
+        vz = fmaf(dc, ox * zy - oy * zx, vz);
+      });
+    } else {
+      chain_fk(rec, depth, row, qval, T, [](int, int, const float*) {});
+    }
     if (ee >= 0 && sg == 0 && h == 0 && t == pb.T - 1)
       pose_term_at(a, s_etf + ee * 12, s_goal + ee * 7, ee, T, valid ? row : -1, cost, Fx, Fy, Fz, Mx, My, Mz);
 #pragma unroll
@@ -547,44 +564,54 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     }
   }
 
-  // ---- adjoint: the chain again, joint c's derivative z_c . (M - o_c x F),
-  //      and this link's share of the directional derivative ----
-  if (link_w && hs == 0) {
-    const int xr = (row - r_lo) * D;
+  // ---- the link's sums, wrench and frame (Alg.8 without a second pass
+  //      along the chain: joint c's derivative is z_c . (M - o_c x F)
+  //      summed over the links below it, formed by the gathering wave) ----
+  if (link_w && hs == 0 && g == 0) {
     float gdp = 0.0f;
-    if (GRAD) {
-      chain_fk(rec, depth, row, qval, T, [&](int i, int c, const float* P) {
-        const float zx = P[2], zy = P[6], zz = P[10], ox = P[3], oy = P[7], oz = P[11];
-        const float vx = Mx - (oy * Fz - oz * Fy);
-        const float vy = My - (oz * Fx - ox * Fz);
-        const float vz = Mz - (ox * Fy - oy * Fx);
-        const float gj = zx * vx + zy * vy + zz * vz;
-        if (g == 0) part[(4 + i) * E + el] = gj;
-        if (CAND) gdp = fmaf(gj, s_d[xr + c], gdp);
-      });
-      if (CAND && HS == 2 && l < D) gdp = fmaf(own_js, s_d[xr + l], gdp);
+    if (CAND && GRAD) {
+      gdp = Mx * wx + My * wy + Mz * wz + (Fx * vx + Fy * vy + Fz * vz);
+      if (HS == 2 && l < D) gdp = fmaf(own_js, s_d[(row - r_lo) * D + l], gdp);
     }
-    if (g == 0) {
-      part[0 * E + el] = cost;
-      part[1 * E + el] = mc;
-      part[2 * E + el] = gdp;
-      part[3 * E + el] = own_js;
+    part[0 * E + el] = cost;
+    part[1 * E + el] = mc;
+    part[2 * E + el] = gdp;
+    part[3 * E + el] = own_js;
+    if (GRAD) {
+      part[4 * E + el] = Fx; part[5 * E + el] = Fy; part[6 * E + el] = Fz;
+      part[7 * E + el] = Mx; part[8 * E + el] = My; part[9 * E + el] = Mz;
+      part[10 * E + el] = T[2]; part[11 * E + el] = T[6]; part[12 * E + el] = T[10];
+      part[13 * E + el] = T[3]; part[14 * E + el] = T[7]; part[15 * E + el] = T[11];
     }
   }
   __syncthreads();
 
-  // ---- combine: wave j < D gathers joint j's derivative from the links
-  //      whose chain holds it (in link order); the last wave sums cost,
-  //      clearance and directional derivative over the links in order,
-  //      then the joint wave's ----
+  // ---- combine: wave j < D forms joint j's derivative from the wrenches
+  //      of the links whose chain holds it (summed in link order) and link
+  //      j's frame; the last wave sums cost, clearance and directional
+  //      derivative over the links in order, then the joint wave's ----
   const size_t eo = (size_t)k * a.rows + row;
   float gsum = 0.0f;
   if (GRAD && wave < D) {
-    gsum = HS == 1 ? s_joint[(3 + wave) * E + el] : s_part[((size_t)wave * NPL + 3) * E + el];
+    const float* pj = s_part + (size_t)wave * NPL * E + el;
+    gsum = HS == 1 ? s_joint[(3 + wave) * E + el] : pj[3 * E];
+    float sF[3] = {0.0f, 0.0f, 0.0f}, sM[3] = {0.0f, 0.0f, 0.0f};
     for (int v = 0; v < L; ++v) {
-      const float x = s_part[((size_t)v * NPL + 4 + jpos) * E + el];
-      gsum += ((jsub >> v) & 1) ? x : 0.0f;
+      const float* pv = s_part + (size_t)v * NPL * E + el;
+      const bool in = (jsub >> v) & 1;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const float f = pv[(4 + q) * E], m = pv[(7 + q) * E];
+        sF[q] += in ? f : 0.0f;
+        sM[q] += in ? m : 0.0f;
+      }
     }
+    const float zx = pj[10 * E], zy = pj[11 * E], zz = pj[12 * E];
+    const float ox = pj[13 * E], oy = pj[14 * E], oz = pj[15 * E];
+    const float ux = sM[0] - (oy * sF[2] - oz * sF[1]);
+    const float uy = sM[1] - (oz * sF[0] - ox * sF[2]);
+    const float uz = sM[2] - (ox * sF[1] - oy * sF[0]);
+    gsum += zx * ux + zy * uy + zz * uz;
   }
   float tc = 0.0f, tm = 3.0e38f, tg = 0.0f;
   if (wave == W - 1) {

@@ -107,9 +107,9 @@ struct WaveLinks {
 
 // LDS of a wave-per-link workgroup.  First a region that holds, in turn,
 // the self-collision phase's sphere centres and per-wave winners, then the
-// waves' parts: per link 4 + deepest chain floats per lane (cost,
-// clearance, directional derivative, own joint's terms, the chain's joint
-// derivatives), the joint wave's 3 + D (cost, clearance, directional
+// waves' parts: per link 16 floats per evaluation (cost, clearance,
+// directional derivative, own joint's terms, wrench, frame z axis and
+// origin), the joint wave's 3 + D (cost, clearance, directional
 // derivative, joint terms), and with two waves per link the halves'
 // hand-over (9 per link).  Then what the workgroup stages once: rows of x
 // and d, joint limits and start, goal poses and tool transforms, the chain
@@ -119,9 +119,10 @@ constexpr size_t kWlLdsMax = 160 * 1024;   // LDS of a gfx950 CU (the device may
 constexpr int kWlStageRows = kWave + 8;
 constexpr int kWlBoxTile = 64;   // cuboids per staged tile
 // E: evaluations per workgroup (64 / slot groups per wave).
+constexpr int kWlPartsPerLink = 16;
 __host__ __device__ inline size_t wl_region_floats(int L, int D, int max_depth, int n_spheres, bool self,
                                                    int halves, int E) {
-  const size_t parts = ((size_t)L * (4 + max_depth) + 3 + D + (halves == 2 ? 9 * (size_t)L : 0)) * E;
+  const size_t parts = ((size_t)L * kWlPartsPerLink + 3 + D + (halves == 2 ? 9 * (size_t)L : 0)) * E;
   const size_t waves = halves == 2 ? 2 * (size_t)L : (size_t)L + 1;
   const size_t selfb = self ? ((size_t)n_spheres * 3 + 2 * waves) * kWave : 0;
   return parts > selfb ? parts : selfb;
