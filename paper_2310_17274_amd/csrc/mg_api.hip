@@ -112,6 +112,7 @@ struct mg_batch {
   int* d_chunk[kNumSlices] = {nullptr, nullptr, nullptr};
   int chunks[kNumSlices] = {0, 0, 0};
   int max_n = 0;      // largest T*D of a seed
+  int uniform_T = 0;  // the horizon when every problem has the same one, else 0
   float *cost_e = nullptr, *gd_e = nullptr, *mc_e = nullptr, *grad_e = nullptr, *pe_e = nullptr;
   float *c_cur = nullptr, *g_cur = nullptr, *dir = nullptr, *best_c = nullptr, *best_x = nullptr;
   int* first = nullptr;
@@ -495,6 +496,7 @@ mg::LbfgsArgs lbfgs_args(mg_ctx* c, mg_batch* b, int m, int reset, const float* 
   mg::LbfgsArgs a;
   memset(&a, 0, sizeof(a));
   a.seeds = b->d_seed;
+  a.uniform_T = b->uniform_T;
   a.n_seeds = b->n_seeds;
   a.rows = b->rows;
   a.dof = c->D;
@@ -502,7 +504,9 @@ mg::LbfgsArgs lbfgs_args(mg_ctx* c, mg_batch* b, int m, int reset, const float* 
   a.reset = reset;
   a.x = x; a.g = g; a.dir = dir;
   a.S = b->S; a.Y = b->Y; a.x_prev = b->x_prev; a.g_prev = b->g_prev;
-  a.rho = b->rho; a.meta = b->meta; a.first = first;
+  a.rho = b->rho; a.meta = b->meta;
+  a.use_first = first != nullptr;
+  a.first = first ? first : b->first;
   a.m_max = b->m_max;
   return a;
 }
@@ -514,6 +518,7 @@ mg_status enqueue_select(mg_ctx* c, mg_batch* b, const float* x, const float* c0
   mg::SelectArgs a;
   memset(&a, 0, sizeof(a));
   a.seeds = b->d_seed;
+  a.uniform_T = b->uniform_T;
   a.n_seeds = b->n_seeds;
   a.rows = b->rows;
   a.dof = c->D;
@@ -527,8 +532,9 @@ mg_status enqueue_select(mg_ctx* c, mg_batch* b, const float* x, const float* c0
   a.x = x; a.c0 = c0; a.g0 = g0; a.d = d;
   a.cost_e = b->cost_e; a.gd_e = b->gd_e; a.mc_e = b->mc_e; a.grad_e = b->grad_e;
   a.x_out = x_out; a.c_out = c_out; a.g_out = g_out; a.chosen = chosen; a.mc_out = mc_out;
-  a.best_c = track ? b->best_c : nullptr;
-  a.best_x = track ? b->best_x : nullptr;
+  a.track = track ? 1 : 0;
+  a.best_c = b->best_c;
+  a.best_x = b->best_x;
   HIP_TRY(mg::launch_select(a, b->max_n, fuse, s));
   return MG_OK;
 }
@@ -720,6 +726,9 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
   b->seeds.assign(seeds, seeds + P);
   b->horizon.assign(horizon, horizon + P);
   b->world.assign(world, world + P);
+  b->uniform_T = horizon[0];
+  for (int p = 1; p < P; ++p)
+    if (horizon[p] != horizon[0]) b->uniform_T = 0;
   std::vector<mg::Problem> prob(P);
   std::vector<mg::SeedInfo> sinfo;
   sinfo.reserve(n_seeds);

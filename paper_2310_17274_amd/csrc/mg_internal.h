@@ -205,6 +205,7 @@ struct ReduceArgs {
 
 struct SelectArgs {
   const SeedInfo* seeds;
+  int uniform_T;           // > 0: every seed has this horizon (seed s starts at row s T)
   int n_seeds, rows, dof, K, mode;
   float alpha[kMaxK];
   float eta1, eta_w;
@@ -223,23 +224,26 @@ struct SelectArgs {
   float* g_out;            // may alias g0
   int* chosen;             // or null
   float* mc_out;           // or null
-  float* best_c;           // or null (no best tracking)
+  int track;               // best tracking: best_c / best_x updated when the cost improves
+  float* best_c;           // [seeds] (read even without tracking)
   float* best_x;
 };
 
 struct LbfgsArgs {
   const SeedInfo* seeds;
+  int uniform_T;           // > 0: every seed has this horizon (seed s starts at row s T)
   int n_seeds, rows, dof, m, reset;
   const float* x;
   const float* g;
   float* dir;
-  float* S;                // [m_max][rows*D]
+  float* S;                // [m_max][rows*D] history pairs, newest first
   float* Y;
   float* x_prev;           // [rows*D]
   float* g_prev;
   float* rho;              // [seeds][m_max]
-  int* meta;               // [seeds][2]: count, head
-  int* first;              // [seeds] or null: 1 forces a reset for that seed, then cleared
+  int* meta;               // [seeds][2]: count, 0
+  int use_first;           // first[] is honoured (and cleared)
+  int* first;              // [seeds] (read even when not used): 1 forces a reset for that seed
   int m_max;
 };
 

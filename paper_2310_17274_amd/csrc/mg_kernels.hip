@@ -102,12 +102,21 @@ __global__ __launch_bounds__(kBlock) void particle_update_kernel(const ParticleA
 }
 
 // --------------------------------------------------------------------------
+// Seed s's first row and horizon: from the table, or arithmetic when every
+// seed has the same horizon (one dependent memory round trip less).
+__device__ __forceinline__ SeedInfo seed_info(const SeedInfo* seeds, int uniform_T, int s) {
+  if (uniform_T > 0) return SeedInfo{s * uniform_T, uniform_T, 0, 0};
+  return seeds[s];
+}
+
 // L-BFGS state of one seed in registers: history (newest first), the
 // previous iterate and gradient.  Loaded before anything it does not depend
-// on is computed, so the loads' latency overlaps that work.
+// on is computed, so the loads' latency overlaps that work.  The history is
+// stored newest first, so every slot is read without waiting for the count
+// (the slots past it are masked once it arrives).
 template <int PL, int MH>
 struct LbfgsRegs {
-  int count, head;
+  int count;
   bool reset;
   float xp[PL], gp[PL];
   float Sh[MH][PL], Yh[MH][PL], rh[MH];
@@ -120,43 +129,59 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
   const size_t base = (size_t)si.row0 * a.dof;
   const size_t stride = (size_t)a.rows * a.dof;
   const int m = a.m;
-  h.count = a.meta[2 * s + 0];
-  h.head = a.meta[2 * s + 1];
-  h.reset = a.reset != 0 || (a.first && a.first[s]);
-  if (h.reset) { h.count = 0; h.head = 0; }
+  // Every load is unconditional, at a clamped (always valid) address, and
+  // masked afterwards: a guarded load becomes a branch around it, which
+  // costs more than the load.  (Per-seed scalars go through the constant
+  // address space: scalar loads, waited for where first used.)
+  const int first = ((cint*)a.first)[s];
+  int count = ((cint*)a.meta)[2 * s + 0];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave;
-    const bool in = e < n && !h.reset;
-    h.xp[u] = in ? a.x_prev[base + e] : 0.0f;
-    h.gp[u] = in ? a.g_prev[base + e] : 0.0f;
+    const int e = lane + u * kWave, ec = min(e, n - 1);
+    h.xp[u] = a.x_prev[base + ec];
+    h.gp[u] = a.g_prev[base + ec];
+    h.xp[u] = e < n ? h.xp[u] : 0.0f;
+    h.gp[u] = e < n ? h.gp[u] : 0.0f;
   }
-  // history slot c (newest first) sits in ring index (head - 1 - c) mod m
 #pragma unroll
   for (int c = 0; c < MH; ++c) {
-    h.rh[c] = 0.0f;
+    const int cc = min(c, max(m - 1, 0));   // (the history holds at least one slot)
+    h.rh[c] = ((cfloat*)a.rho)[(size_t)s * a.m_max + cc];
 #pragma unroll
-    for (int u = 0; u < PL; ++u) { h.Sh[c][u] = 0.0f; h.Yh[c][u] = 0.0f; }
-    if (c < h.count) {
-      const int i = ((h.head - 1 - c) % m + m) % m;
-      h.rh[c] = a.rho[(size_t)s * a.m_max + i];
+    for (int u = 0; u < PL; ++u) {
+      const int e = lane + u * kWave, ec = min(e, n - 1);
+      h.Sh[c][u] = a.S[(size_t)cc * stride + base + ec];
+      h.Yh[c][u] = a.Y[(size_t)cc * stride + base + ec];
+    }
+  }
+  const bool reset = a.reset != 0 || (a.use_first && first != 0);
+  if (reset) count = 0;
+  count = min(count, m);
+  h.count = count;
+  h.reset = reset;
 #pragma unroll
-      for (int u = 0; u < PL; ++u) {
-        const int e = lane + u * kWave;
-        if (e < n) {
-          h.Sh[c][u] = a.S[(size_t)i * stride + base + e];
-          h.Yh[c][u] = a.Y[(size_t)i * stride + base + e];
-        }
-      }
+  for (int u = 0; u < PL; ++u) {
+    h.xp[u] = reset ? 0.0f : h.xp[u];
+    h.gp[u] = reset ? 0.0f : h.gp[u];
+  }
+#pragma unroll
+  for (int c = 0; c < MH; ++c) {
+    const bool live = c < count;
+    h.rh[c] = live ? h.rh[c] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const bool in = live && lane + u * kWave < n;
+      h.Sh[c][u] = in ? h.Sh[c][u] : 0.0f;
+      h.Yh[c][u] = in ? h.Yh[c][u] : 0.0f;
     }
   }
 }
 
 // L-BFGS direction (Alg.6) of one seed held by one wavefront, from its
 // state in registers and the new iterate xv and gradient gv (lane-strided,
-// n = T*D <= 64*PL): stores the last step's pair when its curvature passes
-// the guard, runs the two loops on registers and DPP sums, and writes dir,
-// the new history and x/g_prev.
+// n = T*D <= 64*PL): takes the last step's pair when its curvature passes
+// the guard (the history shifts by one, newest first), runs the two loops
+// on registers and DPP sums, and writes dir, the history and x/g_prev.
 template <int PL, int MH>
 __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
                                              const float* xv, const float* gv, LbfgsRegs<PL, MH>& h) {
@@ -164,7 +189,7 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
   const size_t base = (size_t)si.row0 * a.dof;
   const size_t stride = (size_t)a.rows * a.dof;
   const int m = a.m;
-  int count = h.count, head = h.head;
+  int count = h.count;
   float sv[PL], yv[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
@@ -183,16 +208,8 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
     }
     sy = wave_sum(sy); ss = wave_sum(ss); yy = wave_sum(yy);
     if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy) && sy > 0.0f) {
-#pragma unroll
-      for (int u = 0; u < PL; ++u) {
-        const int e = lane + u * kWave;
-        if (e < n) {
-          a.S[(size_t)head * stride + base + e] = sv[u];
-          a.Y[(size_t)head * stride + base + e] = yv[u];
-        }
-      }
-      if (lane == 0) a.rho[(size_t)s * a.m_max + head] = 1.0f / sy;
-      // shift the register copy: the new pair becomes slot 0
+      // the new pair becomes slot 0, the others move down one (the oldest
+      // of a full history drops out); memory follows the register copy
 #pragma unroll
       for (int c = MH - 1; c > 0; --c) {
         h.rh[c] = h.rh[c - 1];
@@ -202,8 +219,21 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
       h.rh[0] = 1.0f / sy;
 #pragma unroll
       for (int u = 0; u < PL; ++u) { h.Sh[0][u] = sv[u]; h.Yh[0][u] = yv[u]; }
-      head = (head + 1) % m;
       count = count < m ? count + 1 : m;
+#pragma unroll
+      for (int c = 0; c < MH; ++c) {
+        if (c < count) {
+#pragma unroll
+          for (int u = 0; u < PL; ++u) {
+            const int e = lane + u * kWave;
+            if (e < n) {
+              a.S[(size_t)c * stride + base + e] = h.Sh[c][u];
+              a.Y[(size_t)c * stride + base + e] = h.Yh[c][u];
+            }
+          }
+          if (lane == 0) a.rho[(size_t)s * a.m_max + c] = h.rh[c];
+        }
+      }
     }
   }
   // two-loop recursion
@@ -261,25 +291,27 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
   }
   if (lane == 0) {
     a.meta[2 * s + 0] = count;
-    a.meta[2 * s + 1] = head;
-    if (a.first) a.first[s] = 0;
+    a.meta[2 * s + 1] = 0;
+    if (a.use_first) a.first[s] = 0;
   }
 }
 
 template <int PL, int MH>
-__global__ __launch_bounds__(kBlock) void lbfgs_kernel(const LbfgsArgs a) {
-  const int s = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (s >= a.n_seeds) return;        // whole wavefronts only
-  const SeedInfo si = a.seeds[s];
+__global__ __launch_bounds__(kWave) void lbfgs_kernel(const LbfgsArgs a) {
+  const int s = blockIdx.x;          // one wavefront (and workgroup) per seed
+  const int lane = threadIdx.x;
+
+  const SeedInfo si = seed_info(a.seeds, a.uniform_T, s);
   const int n = si.T * a.dof;
   const size_t base = (size_t)si.row0 * a.dof;
   float xv[PL], gv[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave;
-    xv[u] = e < n ? a.x[base + e] : 0.0f;
-    gv[u] = e < n ? a.g[base + e] : 0.0f;
+    const int e = lane + u * kWave, ec = min(e, n - 1);
+    xv[u] = a.x[base + ec];
+    gv[u] = a.g[base + ec];
+    xv[u] = e < n ? xv[u] : 0.0f;
+    gv[u] = e < n ? gv[u] : 0.0f;
   }
   LbfgsRegs<PL, MH> h;
   lbfgs_load<PL, MH>(a, s, lane, si, h);
@@ -287,91 +319,120 @@ __global__ __launch_bounds__(kBlock) void lbfgs_kernel(const LbfgsArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// Line-search choice (Alg.1), one wavefront per seed; lane t holds waypoint
-// t of every candidate, all loads issued before the reductions.  With FUSED
-// the same wavefront then computes the next L-BFGS direction from the chosen
-// iterate, which is still in its registers.
-template <int PL, int MH, bool FUSED>
-__global__ __launch_bounds__(kBlock) void select_kernel(const SelectArgs a, const LbfgsArgs la) {
-  const int s = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (s >= a.n_seeds) return;        // whole wavefronts only
-  const SeedInfo si = a.seeds[s];
+// Line-search choice (Alg.1), one wavefront (and workgroup, so the seeds
+// spread over the CUs) per seed; lane t holds waypoint t of every
+// candidate, all loads issued before the reductions.  KP: the candidate
+// count padded to 4, 8 or 16, so the candidates' sums run unrolled and
+// overlap.  With FUSED the same wavefront then computes the next L-BFGS
+// direction from the chosen iterate, which is still in its registers.
+template <int PL, int MH, bool FUSED, int KP>
+__global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const LbfgsArgs la) {
+  const int s = blockIdx.x;            // (the grid is exactly one workgroup per seed)
+  const int lane = threadIdx.x;
+  const SeedInfo si = seed_info(a.seeds, a.uniform_T, s);
   const int D = a.dof, n = si.T * D;
   const size_t base = (size_t)si.row0 * D;
 
   // everything that does not depend on the choice is loaded first: the
-  // L-BFGS state and, for small K, every candidate's gradient
+  // L-BFGS state, the joint limits, and for up to 8 candidates every
+  // candidate's gradient
   LbfgsRegs<PL, FUSED ? MH : 1> h;
   if constexpr (FUSED) lbfgs_load<PL, MH>(la, s, lane, si, h);
-  constexpr int KG = PL <= 4 ? 8 : 1;
-  const bool pre = a.K <= KG;
+  constexpr int KG = (PL <= 4 && KP <= 8) ? KP : 1;
+  const bool pre = KG > 1;
   float gall[KG][PL];
 #pragma unroll
   for (int k = 0; k < KG; ++k)
 #pragma unroll
     for (int u = 0; u < PL; ++u) {
-      const int e = lane + u * kWave;
-      gall[k][u] = (pre && k < a.K && e < n) ? a.grad_e[((size_t)k * a.rows + si.row0) * D + e] : 0.0f;
+      const int ec = min(lane + u * kWave, n - 1), kc = min(k, a.K - 1);
+      gall[k][u] = pre ? a.grad_e[((size_t)kc * a.rows + si.row0) * D + ec] : 0.0f;
     }
-  const float best_prev = a.best_c ? a.best_c[s] : 0.0f;
-
-  float ck[kMaxK], gk[kMaxK], mk[kMaxK];
+  float qlo[PL], qhi[PL];
 #pragma unroll
-  for (int k = 0; k < kMaxK; ++k) {
-    ck[k] = 0.0f; gk[k] = 0.0f; mk[k] = 3.0e38f;
-    if (k < a.K && lane < si.T) {
-      const size_t e = (size_t)k * a.rows + si.row0 + lane;
-      ck[k] = a.cost_e[e];
-      gk[k] = a.gd_e[e];
-      mk[k] = a.mc_e[e];
-    }
+  for (int u = 0; u < PL; ++u) {
+    const int j = (lane + u * kWave) % D;
+    qlo[u] = a.q_lo[j];
+    qhi[u] = a.q_hi[j];
+  }
+  const float best_prev = ((cfloat*)a.best_c)[s];
+  const float c0 = ((cfloat*)a.c0)[s];
+
+  // candidate sums with the lanes split over the candidates: lane kq * G
+  // + jq takes waypoints jq, jq + G, ... of candidate kq, then a reduction
+  // over its G lanes leaves candidate kq's sums in all of them
+  constexpr int G = kWave / KP;
+  const int kq = lane / G, jq = lane % G;
+  const bool kin = kq < a.K;
+  const size_t erow = (size_t)min(kq, a.K - 1) * a.rows + si.row0;
+  float cq[KP], gq[KP], mq[KP];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) {
+    const int t = jq + G * i;
+    const size_t e = erow + min(t, si.T - 1);
+    cq[i] = a.cost_e[e];
+    gq[i] = a.gd_e[e];
+    mq[i] = a.mc_e[e];
   }
   float gdv[PL], xv[PL], dv[PL];
   float g0d = 0.0f;
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave;
-    gdv[u] = xv[u] = dv[u] = 0.0f;
-    if (e < n) {
-      xv[u] = a.x[base + e];
-      dv[u] = a.d[base + e];
-      g0d = fmaf(a.g0[base + e], dv[u], g0d);
-    }
+    const int e = lane + u * kWave, ec = min(e, n - 1);
+    gdv[u] = 0.0f;
+    xv[u] = a.x[base + ec];
+    dv[u] = a.d[base + ec];
+    const float g0 = a.g0[base + ec];
+    xv[u] = e < n ? xv[u] : 0.0f;
+    dv[u] = e < n ? dv[u] : 0.0f;
+    g0d = fmaf(e < n ? g0 : 0.0f, dv[u], g0d);
   }
   g0d = wave_sum(g0d);
-  const float c0 = a.c0[s];
-  int best = 0;
-  float cb = 0.0f, mcb = 0.0f;
+  float cs = 0.0f, gs = 0.0f, ms = 3.0e38f;
 #pragma unroll
-  for (int k = 0; k < kMaxK; ++k) {
-    if (k < a.K) {
-      const float c = wave_sum(ck[k]), gd = wave_sum(gk[k]), m = wave_min(mk[k]);
-      bool ok = c <= c0 + a.eta1 * a.alpha[k] * g0d;
-      if (a.mode == 1) ok = ok && (gd >= a.eta_w * g0d);
-      if (a.mode == 2) ok = ok && (fabsf(gd) <= a.eta_w * fabsf(g0d));
-      if (k == 0 || ok) { best = k; cb = c; mcb = m; }
-    }
+  for (int i = 0; i < KP; ++i) {
+    const bool in = kin && jq + G * i < si.T;
+    cs += in ? cq[i] : 0.0f;
+    gs += in ? gq[i] : 0.0f;
+    ms = fminf(ms, in ? mq[i] : 3.0e38f);
   }
-  const float al = a.alpha[best];
-  const bool improve = a.best_c && cb < best_prev;
+  cs = group_sum<G>(cs);
+  gs = group_sum<G>(gs);
+  ms = group_min<G>(ms);
+  // Armijo (and Wolfe) test of every candidate; the choice is the last
+  // candidate that passes, else the first
+  float ak = a.alpha[0];
+#pragma unroll
+  for (int k = 1; k < KP; ++k) ak = kq == k ? a.alpha[k] : ak;
+  bool ok = kin && cs <= c0 + a.eta1 * ak * g0d;
+  if (a.mode == 1) ok = ok && (gs >= a.eta_w * g0d);
+  if (a.mode == 2) ok = ok && (fabsf(gs) <= a.eta_w * fabsf(g0d));
+  const uint64_t okm = __ballot(ok && jq == 0 && kq > 0);
+  const int best = okm ? (63 - __builtin_clzll(okm)) / G : 0;
+  const float cb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cs), best * G));
+  const float mcb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ms), best * G));
+  float al = a.alpha[0];
+#pragma unroll
+  for (int k = 1; k < KP; ++k) al = best == k ? a.alpha[k] : al;
+  const bool improve = a.track && cb < best_prev;
   if (pre) {
 #pragma unroll
     for (int k = 0; k < KG; ++k)
-      if (k == best) {
 #pragma unroll
-        for (int u = 0; u < PL; ++u) gdv[u] = gall[k][u];
-      }
+      for (int u = 0; u < PL; ++u) gdv[u] = k == best ? gall[k][u] : gdv[u];
   } else {
     const float* gsrc = a.grad_e + ((size_t)best * a.rows + si.row0) * D;
 #pragma unroll
-    for (int u = 0; u < PL; ++u) gdv[u] = (lane + u * kWave < n) ? gsrc[lane + u * kWave] : 0.0f;
+    for (int u = 0; u < PL; ++u) {
+      const int e = lane + u * kWave;
+      gdv[u] = gsrc[min(e, n - 1)];
+      gdv[u] = e < n ? gdv[u] : 0.0f;
+    }
   }
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     const int e = lane + u * kWave;
-    const int j = e % D;
-    const float v = e < n ? fminf(fmaxf(fmaf(al, dv[u], xv[u]), a.q_lo[j]), a.q_hi[j]) : 0.0f;
+    const float v = e < n ? fminf(fmaxf(fmaf(al, dv[u], xv[u]), qlo[u]), qhi[u]) : 0.0f;
     xv[u] = v;
     if (e < n) {
       a.x_out[base + e] = v;
@@ -497,14 +558,21 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int PL, int KP>
+hipError_t launch_select_k(const SelectArgs& a, const LbfgsArgs* la, hipStream_t s) {
+  const dim3 grid(a.n_seeds);
+  if (!la) select_kernel<PL, 4, false, KP><<<grid, kWave, 0, s>>>(a, LbfgsArgs{});
+  else if (la->m <= 4) select_kernel<PL, 4, true, KP><<<grid, kWave, 0, s>>>(a, *la);
+  else select_kernel<PL, kMaxHist, true, KP><<<grid, kWave, 0, s>>>(a, *la);
+  return hipGetLastError();
+}
+
 template <int PL>
 hipError_t launch_select_pl(const SelectArgs& a, const LbfgsArgs* la, hipStream_t s) {
-  const int wpb = kBlock / kWave;
-  const dim3 grid((a.n_seeds + wpb - 1) / wpb);
-  if (!la) select_kernel<PL, 4, false><<<grid, kBlock, 0, s>>>(a, LbfgsArgs{});
-  else if (la->m <= 4) select_kernel<PL, 4, true><<<grid, kBlock, 0, s>>>(a, *la);
-  else select_kernel<PL, kMaxHist, true><<<grid, kBlock, 0, s>>>(a, *la);
-  return hipGetLastError();
+  if (a.K < 1 || a.K > kMaxK) return hipErrorInvalidValue;
+  if (a.K <= 4) return launch_select_k<PL, 4>(a, la, s);
+  if (a.K <= 8) return launch_select_k<PL, 8>(a, la, s);
+  return launch_select_k<PL, 16>(a, la, s);
 }
 
 hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, hipStream_t s) {
@@ -517,13 +585,12 @@ hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, 
 
 template <int MH>
 hipError_t launch_lbfgs_h(const LbfgsArgs& a, int max_n, hipStream_t s) {
-  const int wpb = kBlock / kWave;
-  const dim3 grid((a.n_seeds + wpb - 1) / wpb);
-  if (max_n <= 64) lbfgs_kernel<1, MH><<<grid, kBlock, 0, s>>>(a);
-  else if (max_n <= 128) lbfgs_kernel<2, MH><<<grid, kBlock, 0, s>>>(a);
-  else if (max_n <= 256) lbfgs_kernel<4, MH><<<grid, kBlock, 0, s>>>(a);
-  else if (max_n <= 512) lbfgs_kernel<8, MH><<<grid, kBlock, 0, s>>>(a);
-  else lbfgs_kernel<16, MH><<<grid, kBlock, 0, s>>>(a);
+  const dim3 grid(a.n_seeds);
+  if (max_n <= 64) lbfgs_kernel<1, MH><<<grid, kWave, 0, s>>>(a);
+  else if (max_n <= 128) lbfgs_kernel<2, MH><<<grid, kWave, 0, s>>>(a);
+  else if (max_n <= 256) lbfgs_kernel<4, MH><<<grid, kWave, 0, s>>>(a);
+  else if (max_n <= 512) lbfgs_kernel<8, MH><<<grid, kWave, 0, s>>>(a);
+  else lbfgs_kernel<16, MH><<<grid, kWave, 0, s>>>(a);
   return hipGetLastError();
 }
 
