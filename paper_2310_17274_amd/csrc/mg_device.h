@@ -85,6 +85,22 @@ __device__ __forceinline__ float group_min(float v) {
   return v;
 }
 
+// The kernel arguments sit in memory that each launch reads cold, and the
+// compiler fetches a field (a scalar load) where it is first used, behind
+// the branches and waits before it, which chains round trips.  Touching
+// every 64-byte line of the argument block at once at the start brings it
+// all into the scalar cache in one round trip.
+template <int BYTES>
+__device__ __forceinline__ void warm_kernargs() {
+  static_assert(BYTES <= 512, "one load per line, at most 8 lines");
+  const cint* kp = (const cint*)__builtin_amdgcn_kernarg_segment_ptr();
+  constexpr int last = (BYTES - 4) / 4;
+  const int v0 = kp[0], v1 = kp[16 < last ? 16 : last], v2 = kp[32 < last ? 32 : last];
+  const int v3 = kp[48 < last ? 48 : last], v4 = kp[64 < last ? 64 : last], v5 = kp[80 < last ? 80 : last];
+  const int v6 = kp[96 < last ? 96 : last], v7 = kp[112 < last ? 112 : last];
+  asm volatile("" ::"s"(v0), "s"(v1), "s"(v2), "s"(v3), "s"(v4), "s"(v5), "s"(v6), "s"(v7));
+}
+
 __device__ __forceinline__ float wave_sum(float v) { return group_sum<kWave>(v); }
 __device__ __forceinline__ float wave_min(float v) { return group_min<kWave>(v); }
 

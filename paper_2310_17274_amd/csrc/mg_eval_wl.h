@@ -245,6 +245,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
   const int g = lane / E, el = lane % E;
+  warm_kernargs<sizeof(EvalArgs)>();
   const int tid = threadIdx.x, nthreads = blockDim.x;
   const int L = a.rb.n_links, D = a.rb.dof, K = a.K, n_ee = a.rb.n_ee;
   const int maxd = a.wl.max_depth, maxs = a.wl.maxs;
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const int HS = a.wl.halves;
   const int W = HS == 2 ? 2 * L : L + 1;
   const bool link_w = wave < L * HS;
-  const int l = link_w ? wave / HS : 0, hs = link_w ? wave % HS : 0;
+  const int l = link_w ? wave >> (HS - 1) : 0, hs = link_w ? wave & (HS - 1) : 0;   // (HS is 1 or 2)
 
   // ---- everything is read from memory in two dependent rounds: the
   //      chunk's record and this wave's tables (scalar loads), then the

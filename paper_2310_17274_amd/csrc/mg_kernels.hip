@@ -300,6 +300,7 @@ template <int PL, int MH>
 __global__ __launch_bounds__(kWave) void lbfgs_kernel(const LbfgsArgs a) {
   const int s = blockIdx.x;          // one wavefront (and workgroup) per seed
   const int lane = threadIdx.x;
+  warm_kernargs<sizeof(LbfgsArgs)>();
 
   const SeedInfo si = seed_info(a.seeds, a.uniform_T, s);
   const int n = si.T * a.dof;
@@ -329,6 +330,7 @@ template <int PL, int MH, bool FUSED, int KP>
 __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const LbfgsArgs la) {
   const int s = blockIdx.x;            // (the grid is exactly one workgroup per seed)
   const int lane = threadIdx.x;
+  warm_kernargs<sizeof(SelectArgs) + (FUSED ? sizeof(LbfgsArgs) + 8 : 0)>();
   const SeedInfo si = seed_info(a.seeds, a.uniform_T, s);
   const int D = a.dof, n = si.T * D;
   const size_t base = (size_t)si.row0 * D;
