@@ -246,6 +246,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
   constexpr int GROUPS = (kBlock / kWave) / H;     // evaluation groups per workgroup
   constexpr int EPB = GROUPS * EPW;                // evaluations per workgroup
   __shared__ float s_part[H > 1 ? 8 * kBlock : 1];
+  warm_kernargs<sizeof(EvalArgs)>();
 
   // wave index as a scalar: the cuboid slice of a wave must be provably
   // uniform for its loads to stay scalar

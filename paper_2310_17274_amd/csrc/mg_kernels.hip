@@ -55,6 +55,7 @@ __device__ __forceinline__ float block_reduce(float v, float* s_red, Op op) {
 __global__ __launch_bounds__(kBlock) void particle_update_kernel(const ParticleArgs a) {
   __shared__ float s_w[kMaxParticles];
   __shared__ float s_red[kBlock / kWave];
+  warm_kernargs<sizeof(ParticleArgs)>();
   const int seed = blockIdx.x;
   const SeedInfo si = a.seeds[seed];
   const int D = a.dof, N = a.N;
