@@ -154,11 +154,15 @@ __device__ __forceinline__ void joint_terms(const EvalArgs& a, const Problem& pb
     }
     if (mine) jc += a.pr.a8 * ac * ac + a.pr.a9 * jk * jk;
     const float ga = 2.0f * a.pr.a8 * ac * ca, gjk = 2.0f * a.pr.a9 * jk * cj;
+    // stencil entry i touches padded state tau - 2 + i; this waypoint's
+    // state is entry 4 - c alone, or, for the last waypoint, every entry
+    // from 4 - c on (the padding after it repeats it)
+    float wv = 0.0f, wa = 0.0f, wj = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      const int s = tau - 2 + i;         // state touched by stencil entry i
-      if (in && s >= 1 && (s < Tn ? s : Tn) == w1) js += gv * kv[i] + ga * ka[i] + gjk * kj[i];
-    }
+    for (int i = 4 - c; i < 5; ++i) { wv += kv[i]; wa += ka[i]; wj += kj[i]; }
+    const bool last = w1 == Tn;
+    const float ev = last ? wv : kv[4 - c], ea = last ? wa : ka[4 - c], ej = last ? wj : kj[4 - c];
+    js += in ? gv * ev + ga * ea + gjk * ej : 0.0f;
   }
 }
 

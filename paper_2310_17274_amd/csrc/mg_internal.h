@@ -236,12 +236,12 @@ struct LbfgsArgs {
   const float* x;
   const float* g;
   float* dir;
-  float* S;                // [m_max][rows*D] history pairs, newest first
+  float* S;                // [m_max][rows*D] history pairs, a ring
   float* Y;
   float* x_prev;           // [rows*D]
   float* g_prev;
   float* rho;              // [seeds][m_max]
-  int* meta;               // [seeds][2]: count, 0
+  int* meta;               // [seeds][2]: count, head (next ring slot)
   int use_first;           // first[] is honoured (and cleared)
   int* first;              // [seeds] (read even when not used): 1 forces a reset for that seed
   int m_max;

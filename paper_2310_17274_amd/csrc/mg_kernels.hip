@@ -112,12 +112,13 @@ __device__ __forceinline__ SeedInfo seed_info(const SeedInfo* seeds, int uniform
 
 // L-BFGS state of one seed in registers: history (newest first), the
 // previous iterate and gradient.  Loaded before anything it does not depend
-// on is computed, so the loads' latency overlaps that work.  The history is
-// stored newest first, so every slot is read without waiting for the count
-// (the slots past it are masked once it arrives).
+// on is computed, so the loads' latency overlaps that work.  Memory holds
+// the history as a ring (slot (head - 1 - c) mod m is the c-th newest);
+// every ring slot is read without waiting for the head and the count, and
+// the newest-first order is formed in registers once they arrive.
 template <int PL, int MH>
 struct LbfgsRegs {
-  int count;
+  int count, head;
   bool reset;
   float xp[PL], gp[PL];
   float Sh[MH][PL], Yh[MH][PL], rh[MH];
@@ -136,6 +137,7 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
   // address space: scalar loads, waited for where first used.)
   const int first = ((cint*)a.first)[s];
   int count = ((cint*)a.meta)[2 * s + 0];
+  int head = ((cint*)a.meta)[2 * s + 1];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     const int e = lane + u * kWave, ec = min(e, n - 1);
@@ -144,45 +146,61 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
     h.xp[u] = e < n ? h.xp[u] : 0.0f;
     h.gp[u] = e < n ? h.gp[u] : 0.0f;
   }
+  float RS[MH][PL], RY[MH][PL], Rr[MH];
 #pragma unroll
-  for (int c = 0; c < MH; ++c) {
-    const int cc = min(c, max(m - 1, 0));   // (the history holds at least one slot)
-    h.rh[c] = ((cfloat*)a.rho)[(size_t)s * a.m_max + cc];
+  for (int r = 0; r < MH; ++r) {
+    const int rc = min(r, max(m - 1, 0));   // (the history holds at least one slot)
+    Rr[r] = ((cfloat*)a.rho)[(size_t)s * a.m_max + rc];
 #pragma unroll
     for (int u = 0; u < PL; ++u) {
       const int e = lane + u * kWave, ec = min(e, n - 1);
-      h.Sh[c][u] = a.S[(size_t)cc * stride + base + ec];
-      h.Yh[c][u] = a.Y[(size_t)cc * stride + base + ec];
+      RS[r][u] = a.S[(size_t)rc * stride + base + ec];
+      RY[r][u] = a.Y[(size_t)rc * stride + base + ec];
     }
   }
   const bool reset = a.reset != 0 || (a.use_first && first != 0);
-  if (reset) count = 0;
+  if (reset) { count = 0; head = 0; }
   count = min(count, m);
   h.count = count;
+  h.head = head;
   h.reset = reset;
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     h.xp[u] = reset ? 0.0f : h.xp[u];
     h.gp[u] = reset ? 0.0f : h.gp[u];
   }
+  // newest first: slot c is ring slot (head - 1 - c) mod m (a uniform
+  // index; selected, since registers cannot be indexed)
 #pragma unroll
   for (int c = 0; c < MH; ++c) {
     const bool live = c < count;
-    h.rh[c] = live ? h.rh[c] : 0.0f;
+    int i = head - 1 - c;
+    i += i < 0 ? m : 0;
+    i += i < 0 ? m : 0;
+    float rv = Rr[0];
+#pragma unroll
+    for (int r = 1; r < MH; ++r) rv = i == r ? Rr[r] : rv;
+    h.rh[c] = live ? rv : 0.0f;
 #pragma unroll
     for (int u = 0; u < PL; ++u) {
+      float sv = RS[0][u], yv = RY[0][u];
+#pragma unroll
+      for (int r = 1; r < MH; ++r) {
+        sv = i == r ? RS[r][u] : sv;
+        yv = i == r ? RY[r][u] : yv;
+      }
       const bool in = live && lane + u * kWave < n;
-      h.Sh[c][u] = in ? h.Sh[c][u] : 0.0f;
-      h.Yh[c][u] = in ? h.Yh[c][u] : 0.0f;
+      h.Sh[c][u] = in ? sv : 0.0f;
+      h.Yh[c][u] = in ? yv : 0.0f;
     }
   }
 }
 
 // L-BFGS direction (Alg.6) of one seed held by one wavefront, from its
 // state in registers and the new iterate xv and gradient gv (lane-strided,
-// n = T*D <= 64*PL): takes the last step's pair when its curvature passes
-// the guard (the history shifts by one, newest first), runs the two loops
-// on registers and DPP sums, and writes dir, the history and x/g_prev.
+// n = T*D <= 64*PL): stores the last step's pair in the ring when its
+// curvature passes the guard, runs the two loops on registers and DPP sums,
+// and writes dir and x/g_prev.
 template <int PL, int MH>
 __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
                                              const float* xv, const float* gv, LbfgsRegs<PL, MH>& h) {
@@ -190,7 +208,7 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
   const size_t base = (size_t)si.row0 * a.dof;
   const size_t stride = (size_t)a.rows * a.dof;
   const int m = a.m;
-  int count = h.count;
+  int count = h.count, head = h.head;
   float sv[PL], yv[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
@@ -209,8 +227,16 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
     }
     sy = wave_sum(sy); ss = wave_sum(ss); yy = wave_sum(yy);
     if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy) && sy > 0.0f) {
-      // the new pair becomes slot 0, the others move down one (the oldest
-      // of a full history drops out); memory follows the register copy
+#pragma unroll
+      for (int u = 0; u < PL; ++u) {
+        const int e = lane + u * kWave;
+        if (e < n) {
+          a.S[(size_t)head * stride + base + e] = sv[u];
+          a.Y[(size_t)head * stride + base + e] = yv[u];
+        }
+      }
+      if (lane == 0) a.rho[(size_t)s * a.m_max + head] = 1.0f / sy;
+      // shift the register copy: the new pair becomes slot 0
 #pragma unroll
       for (int c = MH - 1; c > 0; --c) {
         h.rh[c] = h.rh[c - 1];
@@ -220,21 +246,8 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
       h.rh[0] = 1.0f / sy;
 #pragma unroll
       for (int u = 0; u < PL; ++u) { h.Sh[0][u] = sv[u]; h.Yh[0][u] = yv[u]; }
+      head = (head + 1) % m;
       count = count < m ? count + 1 : m;
-#pragma unroll
-      for (int c = 0; c < MH; ++c) {
-        if (c < count) {
-#pragma unroll
-          for (int u = 0; u < PL; ++u) {
-            const int e = lane + u * kWave;
-            if (e < n) {
-              a.S[(size_t)c * stride + base + e] = h.Sh[c][u];
-              a.Y[(size_t)c * stride + base + e] = h.Yh[c][u];
-            }
-          }
-          if (lane == 0) a.rho[(size_t)s * a.m_max + c] = h.rh[c];
-        }
-      }
     }
   }
   // two-loop recursion
@@ -292,7 +305,7 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
   }
   if (lane == 0) {
     a.meta[2 * s + 0] = count;
-    a.meta[2 * s + 1] = 0;
+    a.meta[2 * s + 1] = head;
     if (a.use_first) a.first[s] = 0;
   }
 }
