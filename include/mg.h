@@ -185,8 +185,8 @@ mg_status mg_solve(mg_ctx *ctx, mg_batch *batch, const float *q_start, const flo
  *   pairs HOST [n_pairs][2] sphere indices (i != j); n_pairs = 0 turns the
  *   term off.  Copied to the device (not capturable).
  * The term is evaluated by the wave-per-link layout only: while pairs are
- * set, every evaluation uses it (robots of at most 15 links, no swept
- * collision; otherwise MG_ERR_UNSUPPORTED), and mg_particles is refused. */
+ * set, every evaluation uses it (robots of at most 15 links; otherwise
+ * MG_ERR_UNSUPPORTED), and mg_particles is refused. */
 mg_status mg_set_self_collision(mg_ctx *ctx, int n_pairs, const int *pairs);
 
 /* Forward kinematics of the end effectors (Sec. "Robot Kinematics", Tab.6):
@@ -200,7 +200,8 @@ mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *s
  * waves ("slices").  Wave per link (layout 1): 64 evaluations per
  * workgroup, one wave per link plus one for the joint terms, each wave
  * skipping the cuboids that a ball around its link's spheres over all 64
- * lanes cannot reach; needs at most 15 links and no swept collision.
+ * lanes cannot reach (with swept collision, the ball grows by half the
+ * longer segment); needs at most 15 links; the particle stage does not use it.
  * For small batches the wave-per-link layout can also split the cuboids
  * over 2 or 4 workgroups per 64 evaluations; the last to finish adds the
  * slices' sums in slice order (the batch keeps the scratch and counters).
@@ -221,8 +222,8 @@ mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *s
  * be NULL) receives the slice count for the lane-per-link layout, minus
  * the workgroups per 64 evaluations for the wave-per-link layout, -8 for
  * two waves per link, or -16 for two slot groups per wave.
- * Overwrites the batch's evaluation workspaces; not capturable.  Swept
- * collision always uses the lane-per-link layout with one slice. */
+ * Overwrites the batch's evaluation workspaces; not capturable.  With
+ * swept collision the lane-per-link layout takes one slice. */
 mg_status mg_batch_set_layout(mg_batch *batch, int layout, int slices);
 mg_status mg_autotune(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
                       const float *x, const float *dir, int K, const float *alpha, int launches,

@@ -291,22 +291,21 @@ mg::WaveLinks dev_wave_links(const mg_ctx* c) {
   return wl;
 }
 
-// The wave-per-link layout needs a workgroup of L + 1 waves and takes no
-// swept collision.
+// The wave-per-link layout needs a workgroup of L + 1 waves.
 bool wl_possible(const mg_ctx* c, bool self) {
-  return c->L + 1 <= 16 && !c->params.swept &&
+  return c->L + 1 <= 16 &&
          mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, self, 1, c->maxs, mg::kWave) <= c->lds_max;
 }
 // two waves per link: at most 8 links (16 waves) and the LDS for the hand-over
 bool wl_halves_possible(const mg_ctx* c) {
-  return 2 * c->L <= 16 && !c->params.swept &&
+  return 2 * c->L <= 16 &&
          mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, c->n_self > 0, 2, c->maxs, mg::kWave) <= c->lds_max;
 }
 bool wl_possible(const mg_ctx* c) { return wl_possible(c, c->n_self > 0); }
 // two slot groups per wave (32 evaluations per workgroup): no
 // self-collision, at least four sphere slots per link
 bool wl_groups_possible(const mg_ctx* c) {
-  return c->L + 1 <= 16 && !c->params.swept && c->n_self == 0 && c->maxs >= 4 &&
+  return c->L + 1 <= 16 && c->n_self == 0 && c->maxs >= 4 &&
          mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, false, 1, c->maxs, mg::kWave / 2) <= c->lds_max;
 }
 
@@ -467,7 +466,7 @@ mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
                        const float* x, const float* d, int K, const float* alpha, bool grad,
                        float* grad_out, float* pe_out, hipStream_t s) {
   if (c->n_self > 0 && !use_wl(b, K))
-    return fail(MG_ERR_UNSUPPORTED, "self-collision needs the wave-per-link layout (at most 15 links, no swept collision)");
+    return fail(MG_ERR_UNSUPPORTED, "self-collision needs the wave-per-link layout (at most 15 links)");
   const int hi = pick_slices(b, (long)b->rows * K);
   mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, x, d, K, alpha);
   if (grad_out) a.grad_e = grad_out;
@@ -852,7 +851,7 @@ mg_status mg_time_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
   if (!q_start || !goal || !x || !dir || !mean_us) return fail(MG_ERR_ARG, "null argument");
   if (launches < 1) return fail(MG_ERR_ARG, "launches must be >= 1");
   if (c->n_self > 0 && !use_wl(b, K))
-    return fail(MG_ERR_UNSUPPORTED, "self-collision needs the wave-per-link layout (at most 15 links, no swept collision)");
+    return fail(MG_ERR_UNSUPPORTED, "self-collision needs the wave-per-link layout (at most 15 links)");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int hi = pick_slices(b, (long)b->rows * K);
   const mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, x, dir, K, alpha);
@@ -968,7 +967,7 @@ mg_status mg_set_self_collision(mg_ctx* c, int n_pairs, const int* pairs) {
   if (!c) return fail(MG_ERR_ARG, "null context");
   if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return fail(MG_ERR_ARG, "bad pair list");
   if (n_pairs > 0 && !wl_possible(c, true))
-    return fail(MG_ERR_UNSUPPORTED, "self-collision needs at most 15 links, no swept collision and "
+    return fail(MG_ERR_UNSUPPORTED, "self-collision needs at most 15 links and "
                 "workgroup memory for the robot's spheres");
   std::vector<int4> pr(n_pairs);
   for (int k = 0; k < n_pairs; ++k) {
@@ -1019,7 +1018,7 @@ mg_status mg_batch_set_layout(mg_batch* b, int layout, int slices) {
   if (!b) return fail(MG_ERR_ARG, "null batch");
   if (layout < -1 || layout > 3) return fail(MG_ERR_ARG, "layout must be -1, 0, 1, 2 or 3");
   if (layout >= 1 && !wl_possible(b->ctx))
-    return fail(MG_ERR_UNSUPPORTED, "the wave-per-link layout needs at most 15 links and no swept collision");
+    return fail(MG_ERR_UNSUPPORTED, "the wave-per-link layout needs at most 15 links");
   if (layout == 2 && !wl_halves_possible(b->ctx))
     return fail(MG_ERR_UNSUPPORTED, "two waves per link need at most 8 links");
   if (layout == 3 && !wl_groups_possible(b->ctx))

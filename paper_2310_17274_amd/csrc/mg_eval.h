@@ -192,13 +192,13 @@ __device__ __forceinline__ void link_pose(const float* __restrict__ fixed_tf, in
 // step by the clearance (by r + eta inside the band) while short of the
 // half-way point, at most sweep_steps samples per side, each costed with the
 // Eq.(10) profile.  (px, py, pz) is c in the box frame, sdf its distance.
-__device__ __forceinline__ void sweep_pair(const EvalArgs& a, int slot, const float* Tp,
-                                           const float* Tn, bool has_next, float cx, float cy,
-                                           float cz, const v4f& A0, const v4f& A1, const v4f& A2,
-                                           const v4f& Hh, float px, float py, float pz, float sdf,
-                                           float r, float w, float eta, float inv_eta, float& cost,
-                                           float& gx, float& gy, float& gz) {
-  const float4 ls = a.ln.sphere[slot];
+// ls: the sphere in its link's frame; Tp, Tn: the link's poses at the
+// neighbouring waypoints.
+__device__ __forceinline__ void sweep_pair_ls(const float4 ls, int steps, const float* Tp, const float* Tn,
+                                              bool has_next, float cx, float cy, float cz, const v4f& A0,
+                                              const v4f& A1, const v4f& A2, const v4f& Hh, float px, float py,
+                                              float pz, float sdf, float r, float w, float eta, float inv_eta,
+                                              float& cost, float& gx, float& gy, float& gz) {
   const float rh = r + eta;
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -217,7 +217,7 @@ __device__ __forceinline__ void sweep_pair(const EvalArgs& a, int slot, const fl
     const float vz = A2.x * ux + A2.y * uy + A2.z * uz;
     const float half = 0.5f * len;
     float j = sdf < rh ? rh : sdf - rh;
-    for (int st = 0; st < a.pr.sweep_steps && j < half; ++st) {
+    for (int st = 0; st < steps && j < half; ++st) {
       const float qx = fmaf(j, vx, px), qy = fmaf(j, vy, py), qz = fmaf(j, vz, pz);
       float gpx, gpy, gpz;
       const float s2 = box_sdf(qx, qy, qz, fabsf(qx) - Hh.x, fabsf(qy) - Hh.y, fabsf(qz) - Hh.z,
@@ -226,6 +226,16 @@ __device__ __forceinline__ void sweep_pair(const EvalArgs& a, int slot, const fl
       j += s2 - rh > 0.0f ? s2 - rh : rh;
     }
   }
+}
+
+__device__ __forceinline__ void sweep_pair(const EvalArgs& a, int slot, const float* Tp,
+                                           const float* Tn, bool has_next, float cx, float cy,
+                                           float cz, const v4f& A0, const v4f& A1, const v4f& A2,
+                                           const v4f& Hh, float px, float py, float pz, float sdf,
+                                           float r, float w, float eta, float inv_eta, float& cost,
+                                           float& gx, float& gy, float& gz) {
+  sweep_pair_ls(a.ln.sphere[slot], a.pr.sweep_steps, Tp, Tn, has_next, cx, cy, cz, A0, A1, A2, Hh, px, py,
+                pz, sdf, r, w, eta, inv_eta, cost, gx, gy, gz);
 }
 
 // Lane layout: lane l of an evaluation owns link l.  A wave holds 64/LPE

@@ -129,14 +129,26 @@ __device__ __forceinline__ void chain_fk(const float4* rec, int depth, int row, 
 // wave's ball (centre cw, radius Rw, scalar) decides whether the wave looks
 // at it; for one that passes, each lane's own ball (centre b, radius rl)
 // must reach it; then the slots' face tests and, where one passes, the near
-// path.
-template <int MAXS>
+// path.  rho: each slot's cull radius (r + eta, plus half the longer
+// segment with swept collision).
+//
+// Swept collision (SW): the lane's link poses at the neighbouring waypoints
+// and its slots' spheres in the link frame (for the trace, Alg.11-12).
+struct SweepCtx {
+  const float* Tp;
+  const float* Tn;
+  const float4* sl;        // this lane's first slot (LDS)
+  int steps;
+  bool on, has_next;
+};
+
+template <int MAXS, bool SW>
 __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane, float cwx, float cwy,
                                            float cwz, float Rw, float bx, float by, float bz, float rl,
                                            const float* cx, const float* cy, const float* cz,
-                                           const float* rr, float w, float eta, float inv_eta, float& cost,
-                                           float& mc, float& Fx, float& Fy, float& Fz, float& Mx,
-                                           float& My, float& Mz) {
+                                           const float* rr, const float* rho, const SweepCtx& sw, float w,
+                                           float eta, float inv_eta, float& cost, float& mc, float& Fx,
+                                           float& Fy, float& Fz, float& Mx, float& My, float& Mz) {
   // lane j tests cuboid j of the tile against the wave's ball
   bool cand = false;
   if (lane < nb) {
@@ -197,17 +209,20 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
         ppy[u] = fmaf(A1.x, cx[s], fmaf(A1.y, cy[s], fmaf(A1.z, cz[s], A1.w)));
         ppz[u] = fmaf(A2.x, cx[s], fmaf(A2.y, cy[s], fmaf(A2.z, cz[s], A2.w)));
         m3[u] = fmaxf(fabsf(ppx[u]) - Hh.x, fmaxf(fabsf(ppy[u]) - Hh.y, fabsf(ppz[u]) - Hh.z));
-        any |= m3[u] < rr[s] + eta;
+        any |= m3[u] < rho[s];
       }
       if (any) {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
           const int s = g0 + u;
-          if (m3[u] < rr[s] + eta) {
+          if (m3[u] < rho[s]) {
             const float px = ppx[u], py = ppy[u], pz = ppz[u];
             float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-            near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y, fabsf(pz) - Hh.z, rr[s],
-                      w, eta, inv_eta, cost, mc, gx, gy, gz);
+            const float sdf = near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y,
+                                        fabsf(pz) - Hh.z, rr[s], w, eta, inv_eta, cost, mc, gx, gy, gz);
+            if (SW && sw.on)
+              sweep_pair_ls(sw.sl[s], sw.steps, sw.Tp, sw.Tn, sw.has_next, cx[s], cy[s], cz[s], A0, A1, A2,
+                            Hh, px, py, pz, sdf, rr[s], w, eta, inv_eta, cost, gx, gy, gz);
             Fx += gx; Fy += gy; Fz += gz;
             Mx += cy[s] * gz - cz[s] * gy;
             My += cz[s] * gx - cx[s] * gz;
@@ -217,6 +232,13 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
       }
     }
   }
+}
+
+// The value of lane i +- 32 (the other slot group's lane for the same
+// evaluation when G = 2).
+__device__ __forceinline__ float other32(float v, int lane) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return __int_as_float(lane < 32 ? (int)r[1] : (int)r[0]);
 }
 
 // Sum / minimum over the G slot groups of a wave (lanes e, e + E, ...).
@@ -238,7 +260,8 @@ __device__ __forceinline__ float groups_min(float v) {
 // workgroup holds E = 64 / G evaluations and lane g * E + e tests group g
 // of the link's sphere slots for evaluation e (G = 2: twice the workgroups
 // for the same batch, the chain run twice).
-template <int MAXS, bool CAND, bool GRAD, int NT, int G>
+// SW: swept collision (the chain also runs at the neighbouring waypoints).
+template <int MAXS, bool CAND, bool GRAD, int NT, int G, bool SW>
 __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   constexpr int E = kWave / G;
   extern __shared__ float s_mem[];
@@ -376,27 +399,87 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   float T[12];
   float cost = 0.0f, mc = a.pr.eta;
   float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f, Mx = 0.0f, My = 0.0f, Mz = 0.0f;
-  float cx[MAXS], cy[MAXS], cz[MAXS], rr[MAXS];
+  float cx[MAXS], cy[MAXS], cz[MAXS], rr[MAXS], rho[MAXS];
   float wx = 0.0f, wy = 0.0f, wz = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
+  // swept collision: the link's poses at the neighbouring waypoints (the
+  // start before waypoint 1; one waypoint alone has no segments)
+  float Tp[SW ? 12 : 1], Tn[SW ? 12 : 1];
+  const bool sweep = SW && pb.T > 1;
+  const bool has_next = sweep && t + 1 < pb.T;
+  float ext = 0.0f;   // the largest half segment over this lane's slots
   if (link_w) {
-    if (CAND && GRAD) {
-      // the link's velocity under the joint rates d (omega = sum d_c z_c,
-      // v = sum d_c o_c x z_c over its chain): its share of the directional
-      // derivative is then M . omega + F . v
-      const int xr = (row - r_lo) * D;
-      chain_fk(rec, depth, row, qval, T, [&](int, int c, const float* P) {
+    // With CAND and GRAD the pass also forms the link's velocity under the
+    // joint rates d (omega = sum d_c z_c, v = sum d_c o_c x z_c over its
+    // chain): its share of the directional derivative is M . omega + F . v.
+    const int xr = (row - r_lo) * D;
+    auto twist = [&](int, int c, const float* P) {
+      if (CAND && GRAD) {
         const float dc = s_d[xr + c];
         const float zx = P[2], zy = P[6], zz = P[10], ox = P[3], oy = P[7], oz = P[11];
         wx = fmaf(dc, zx, wx); wy = fmaf(dc, zy, wy); wz = fmaf(dc, zz, wz);
         vx = fmaf(dc, oy * zz - oz * zy, vx);
         vy = fmaf(dc, oz * zx - ox * zz, vy);
         vz = fmaf(dc, ox * zy - oy * zx, vz);
-      });
-    } else {
-      chain_fk(rec, depth, row, qval, T, [](int, int, const float*) {});
+      }
+    };
+    auto none = [](int, int, const float*) {};
+    // the link's pose at joint values qv into To; with G = 2 the two slot
+    // groups split the chain: group 0 composes its first half (world frame),
+    // group 1 the rest from the identity; the halves are swapped and both
+    // form the same product P0 P1 (tw: the velocity is formed as well)
+    auto link_fk = [&](auto&& qv, float* To, auto&& vis, bool tw) {
+      if constexpr (G == 2) {
+        const int split = (depth + 1) >> 1;
+        float Pp[12];
+        chain_fk(rec + (g ? 4 * split : 0), g ? depth - split : split, row, qv, Pp, vis);
+        float Po[12];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) Po[e] = other32(Pp[e], lane);
+        const float* P0 = g ? Po : Pp;
+        const float* P1 = g ? Pp : Po;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const float a0 = P0[r * 4 + 0], a1 = P0[r * 4 + 1], a2 = P0[r * 4 + 2], a3 = P0[r * 4 + 3];
+          To[r * 4 + 0] = a0 * P1[0] + a1 * P1[4] + a2 * P1[8];
+          To[r * 4 + 1] = a0 * P1[1] + a1 * P1[5] + a2 * P1[9];
+          To[r * 4 + 2] = a0 * P1[2] + a1 * P1[6] + a2 * P1[10];
+          To[r * 4 + 3] = a0 * P1[3] + a1 * P1[7] + a2 * P1[11] + a3;
+        }
+        if (CAND && GRAD && tw) {
+          // group 1's velocity is in P0's frame: omega_1 = R0 omega_1',
+          // v_1 = R0 v_1' + p0 x omega_1
+          float w1[3] = {g ? wx : other32(wx, lane), g ? wy : other32(wy, lane), g ? wz : other32(wz, lane)};
+          float u1[3] = {g ? vx : other32(vx, lane), g ? vy : other32(vy, lane), g ? vz : other32(vz, lane)};
+          float w0[3] = {g ? other32(wx, lane) : wx, g ? other32(wy, lane) : wy, g ? other32(wz, lane) : wz};
+          float u0[3] = {g ? other32(vx, lane) : vx, g ? other32(vy, lane) : vy, g ? other32(vz, lane) : vz};
+          float Rw[3], Ru[3];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            Rw[r] = P0[r * 4 + 0] * w1[0] + P0[r * 4 + 1] * w1[1] + P0[r * 4 + 2] * w1[2];
+            Ru[r] = P0[r * 4 + 0] * u1[0] + P0[r * 4 + 1] * u1[1] + P0[r * 4 + 2] * u1[2];
+          }
+          const float px = P0[3], py = P0[7], pz = P0[11];
+          wx = w0[0] + Rw[0]; wy = w0[1] + Rw[1]; wz = w0[2] + Rw[2];
+          vx = u0[0] + Ru[0] + (py * Rw[2] - pz * Rw[1]);
+          vy = u0[1] + Ru[1] + (pz * Rw[0] - px * Rw[2]);
+          vz = u0[2] + Ru[2] + (px * Rw[1] - py * Rw[0]);
+        }
+      } else {
+        chain_fk(rec, depth, row, qv, To, vis);
+      }
+    };
+    link_fk(qval, T, twist, true);
+    if constexpr (SW) {
+      if (sweep) {
+        auto qprev = [&](int r, int j) -> float { return t >= 1 ? qval(r - 1, j) : s_lim[2 * D + j]; };
+        auto qnext = [&](int r, int j) -> float { return has_next ? qval(r + 1, j) : qval(r, j); };
+        link_fk(qprev, Tp, none, false);
+        link_fk(qnext, Tn, none, false);
+      }
     }
     if (ee >= 0 && sg == 0 && h == 0 && t == pb.T - 1)
       pose_term_at(a, s_etf + ee * 12, s_goal + ee * 7, ee, T, valid ? row : -1, cost, Fx, Fy, Fz, Mx, My, Mz);
+    const float eta = a.pr.eta;
 #pragma unroll
     for (int s = 0; s < MAXS; ++s) {
       const float4 ls = s_slot[l * maxs + sg * MAXS + (s < ns ? s : 0)];
@@ -406,6 +489,27 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
       cy[s] = used ? T[4] * ls.x + T[5] * ls.y + T[6] * ls.z + T[7] : 1e18f;
       cz[s] = used ? T[8] * ls.x + T[9] * ls.y + T[10] * ls.z + T[11] : 1e18f;
       rr[s] = used ? ls.w : 0.0f;
+      rho[s] = rr[s] + eta;
+      if constexpr (SW) {
+        // every trace sample lies within half a segment of the centre and the
+        // distance is 1-Lipschitz, so r + eta + L/2 bounds the cull
+        if (sweep && used) {
+          const float bx = Tp[0] * ls.x + Tp[1] * ls.y + Tp[2] * ls.z + Tp[3] - cx[s];
+          const float by = Tp[4] * ls.x + Tp[5] * ls.y + Tp[6] * ls.z + Tp[7] - cy[s];
+          const float bz = Tp[8] * ls.x + Tp[9] * ls.y + Tp[10] * ls.z + Tp[11] - cz[s];
+          float l2 = bx * bx + by * by + bz * bz;
+          if (has_next) {
+            const float fx = Tn[0] * ls.x + Tn[1] * ls.y + Tn[2] * ls.z + Tn[3] - cx[s];
+            const float fy = Tn[4] * ls.x + Tn[5] * ls.y + Tn[6] * ls.z + Tn[7] - cy[s];
+            const float fz = Tn[8] * ls.x + Tn[9] * ls.y + Tn[10] * ls.z + Tn[11] - cz[s];
+            l2 = fmaxf(l2, fx * fx + fy * fy + fz * fz);
+          }
+          // (slightly widened so rounding never culls a sample the trace takes)
+          const float e = 0.5f * sqrtf(l2) * 1.0001f + 1e-6f;
+          rho[s] += e;
+          ext = fmaxf(ext, e);
+        }
+      }
     }
   }
 
@@ -511,10 +615,19 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     cwz = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(0.5f * (lz + uz))));
     const float hx = ux - lx, hy = uy - ly, hz = uz - lz;
     // (widened slightly so rounding never drops a cuboid that matters)
-    const float rw = (0.5f * sqrtf(hx * hx + hy * hy + hz * hz) + (G > 1 ? wave_max(bl.w) : bl.w) + eta) * 1.0001f + 1e-6f;
+    const float rb = bl.w + ext;   // (ext: the sweep's reach, 0 without)
+    const float rw = (0.5f * sqrtf(hx * hx + hy * hy + hz * hz) + (G > 1 || SW ? wave_max(rb) : rb) + eta) * 1.0001f +
+                     1e-6f;
     Rw = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rw)));
-    rlb = (bl.w + eta) * 1.0001f + 1e-6f;   // one lane's ball
+    rlb = (bl.w + eta) * 1.0001f + 1e-6f + ext;   // one lane's ball
   }
+  SweepCtx swc;
+  swc.Tp = Tp;
+  swc.Tn = Tn;
+  swc.sl = s_slot + l * maxs + sg * MAXS;
+  swc.steps = a.pr.sweep_steps;
+  swc.on = sweep;
+  swc.has_next = has_next;
   for (int tl = w0, buf = 0; tl < w1; tl += kWlBoxTile, buf ^= 1) {
     const int nb = min(kWlBoxTile, w1 - tl);
     const int nn = min(kWlBoxTile, w1 - tl - kWlBoxTile);   // next tile (<= 0: none)
@@ -523,8 +636,8 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     const float4 u0 = i0 < 4 * nn ? nsrc[i0] : float4{};
     const float4 u1 = i1 < 4 * nn ? nsrc[i1] : float4{};
     if (wave_sph)
-      world_tile<MAXS>(s_box + buf * kWlBoxTile * 4, nb, lane, cwx, cwy, cwz, Rw, bxl, byl, bzl, rlb, cx, cy,
-                       cz, rr, w, eta, inv_eta, cost, mc, Fx, Fy, Fz, Mx, My, Mz);
+      world_tile<MAXS, SW>(s_box + buf * kWlBoxTile * 4, nb, lane, cwx, cwy, cwz, Rw, bxl, byl, bzl, rlb, cx, cy,
+                           cz, rr, rho, swc, w, eta, inv_eta, cost, mc, Fx, Fy, Fz, Mx, My, Mz);
     if (nn <= 0) break;
     float4* nxt = s_box + (buf ^ 1) * kWlBoxTile * 4;
     if (i0 < 4 * nn) nxt[i0] = u0;
@@ -708,16 +821,29 @@ hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand
                                   a.wl.maxs, kWave / G);
   if (lds > kWlLdsMax) return hipErrorInvalidValue;
   const dim3 grid(grid_x, slices), block(waves * kWave);
-  if (waves <= 8) {
-    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G>, grid, block, lds, s, a);
-    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G>, grid, block, lds, s, a);
-    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G>, grid, block, lds, s, a);
-    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G>, grid, block, lds, s, a);
+  if (a.pr.swept && waves <= 8) {
+    // (swept collision: no particle mode)
+    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, true>, grid, block, lds, s, a);
+    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, true>, grid, block, lds, s, a);
+    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, true>, grid, block, lds, s, a);
+    return hipErrorInvalidValue;
   }
-  if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G>, grid, block, lds, s, a);
-  if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G>, grid, block, lds, s, a);
-  if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G>, grid, block, lds, s, a);
-  return wl_launch(eval_wl_kernel<MAXS, true, false, 1024, G>, grid, block, lds, s, a);
+  if (a.pr.swept) {
+    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G, true>, grid, block, lds, s, a);
+    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G, true>, grid, block, lds, s, a);
+    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G, true>, grid, block, lds, s, a);
+    return hipErrorInvalidValue;
+  }
+  if (waves <= 8) {
+    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, false>, grid, block, lds, s, a);
+    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, false>, grid, block, lds, s, a);
+    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, false>, grid, block, lds, s, a);
+    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G, false>, grid, block, lds, s, a);
+  }
+  if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G, false>, grid, block, lds, s, a);
+  if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G, false>, grid, block, lds, s, a);
+  if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G, false>, grid, block, lds, s, a);
+  return wl_launch(eval_wl_kernel<MAXS, true, false, 1024, G, false>, grid, block, lds, s, a);
 }
 
 template <int MAXS>

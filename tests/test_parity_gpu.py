@@ -125,12 +125,13 @@ def test_cost_grad_parity_with_collisions_and_limits(layout):
 SWEPT = dict(swept=1, sweep_steps=4)
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("kind", ["adjoint_small", "uneven", "tree"])
-def test_swept_cost_grad_parity(kind):
+def test_swept_cost_grad_parity(kind, layout):
     """Continuous collision: trace samples toward both neighbouring waypoints
     (the start before waypoint 1), horizons 2..64, worlds of 0..200 cuboids,
     the two-arm tree."""
-    case = make_case(kind, params=SWEPT)
+    case = make_case(kind, params=SWEPT, layout=layout)
     c, g, mc = gpu_cost_grad(case)
     cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, case.robot.dof))
     H.assert_cost_close(c, cr)
@@ -142,7 +143,8 @@ def test_swept_cost_grad_parity(kind):
     assert np.all(cr >= cd) and np.any(cr > cd)
 
 
-def test_swept_tunnelling_example_on_gpu():
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_swept_tunnelling_example_on_gpu(layout):
     """The thin-wall example worked by hand in the reference's pins: both
     waypoints clear of the wall, the segment through it; swept cost 0.136
     against 0.001 discrete (unit collision weight, other terms off)."""
@@ -155,7 +157,7 @@ def test_swept_tunnelling_example_on_gpu():
     batch = wl.Batch(seeds=np.array([1], np.int32), horizon=np.array([2], np.int32),
                      world=np.array([0], np.int32), q_start=np.array([[-phi]]),
                      goal=np.array([[[0, 0, 0, 1, 0, 0, 0]]], dtype=float), x0=np.array([-phi, phi]))
-    case = Case(robot, worlds, batch, params=dict(COLLISION_ONLY, **SWEPT))
+    case = Case(robot, worlds, batch, params=dict(COLLISION_ONLY, **SWEPT), layout=layout)
     c, g, mc = gpu_cost_grad(case)
     assert c[0] == pytest.approx(0.136, rel=1e-4)
     assert mc[0] == pytest.approx(0.02, rel=1e-4)
@@ -163,12 +165,13 @@ def test_swept_tunnelling_example_on_gpu():
     assert gpu_cost_grad(cd)[0][0] == pytest.approx(0.001, rel=1e-4)
 
 
-def test_large_tree_swept_linesearch_sampled():
+@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2")])
+def test_large_tree_swept_linesearch_sampled(layout):
     """Two-arm tree (14 joints, 120 spheres) against 500 cuboids with swept
     collision, 128 seeds x 48 waypoints x 4 candidates in one line-search
     launch; sampled seeds checked one by one at the chosen candidate."""
     robot, worlds, batch, meta = wl.cfg_large()
-    case = Case(robot, worlds, batch, params=SWEPT)
+    case = Case(robot, worlds, batch, params=SWEPT, layout=layout)
     D, S, T = robot.dof, 128, 48
     rng = np.random.default_rng(1)
     d = rng.normal(0, 0.03, case.batch.x0.shape).astype(np.float32).astype(np.float64)
@@ -349,8 +352,8 @@ def test_self_collision_linesearch_parity():
 
 
 def test_self_collision_restrictions():
-    """Self-collision lives in the wave-per-link layout: swept collision and
-    the particle stage refuse it."""
+    """Self-collision lives in the wave-per-link layout: the particle stage
+    refuses it."""
     from paper_2310_17274_amd._lib import MgError
     case = _self_case(None, S=2, T=8)
     case.b.mg_batch_reserve_particles(4)
@@ -358,10 +361,20 @@ def test_self_collision_restrictions():
     var = torch.full_like(case.x, 1e-3)
     with pytest.raises(MgError):
         case.ctx.mg_particles(case.b, case.q_start, case.goal, case.x.clone(), var, eps)
-    from paper_2310_17274_amd.binding import Context, default_params
-    ctx = Context(case.robot, default_params(swept=1))
-    with pytest.raises(MgError):
-        ctx.mg_set_self_collision(wl.self_pairs(case.robot))
+
+
+@pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((2, 0), id="wave2")])
+def test_self_collision_with_swept_parity(layout):
+    """Self-collision and swept collision together (both wave-per-link)."""
+    robot = wl.make_arm(seed=0, n_spheres=52)
+    worlds = wl.make_worlds(8, [40])
+    batch = wl.make_batch(robot, 81, [3], [16], [0])
+    case = Case(robot, worlds, batch, params=SWEPT, layout=layout, self_pairs=wl.self_pairs(robot))
+    c, g, mc = gpu_cost_grad(case)
+    cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, robot.dof))
+    H.assert_cost_close(c, cr)
+    H.assert_grad_close(g, gr, case.batch)
+    H.assert_verdicts(mc, mcr)
 
 
 def test_cost_only_matches_cost_grad():
