@@ -110,6 +110,54 @@ __device__ __forceinline__ SeedInfo seed_info(const SeedInfo* seeds, int uniform
   return seeds[s];
 }
 
+// A seed's row block of n = T*D floats held PL per lane: element u of a
+// lane is lane + 64 u (strided), or with V4 lane PL + u (contiguous, moved
+// as float4: the block is a multiple of 4 floats and 16-byte aligned).
+template <int PL, bool V4>
+__device__ __forceinline__ int el_idx(int lane, int u) {
+  return V4 ? lane * PL + u : lane + u * kWave;
+}
+// Loads at clamped (always valid) addresses, masked afterwards (zero
+// outside the block).
+template <int PL, bool V4>
+__device__ __forceinline__ void ld_row(const float* p, int n, int lane, float* v) {
+  if constexpr (V4) {
+#pragma unroll
+    for (int c = 0; c < PL / 4; ++c) {
+      const int e = lane * PL + 4 * c;
+      const float4 q = *reinterpret_cast<const float4*>(p + min(e, n - 4));
+      const bool in = e < n;
+      v[4 * c + 0] = in ? q.x : 0.0f;
+      v[4 * c + 1] = in ? q.y : 0.0f;
+      v[4 * c + 2] = in ? q.z : 0.0f;
+      v[4 * c + 3] = in ? q.w : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int e = lane + u * kWave;
+      v[u] = p[min(e, n - 1)];
+      v[u] = e < n ? v[u] : 0.0f;
+    }
+  }
+}
+template <int PL, bool V4>
+__device__ __forceinline__ void st_row(float* p, int n, int lane, const float* v) {
+  if constexpr (V4) {
+#pragma unroll
+    for (int c = 0; c < PL / 4; ++c) {
+      const int e = lane * PL + 4 * c;
+      if (e < n) *reinterpret_cast<float4*>(p + e) = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) {
+      const int e = lane + u * kWave;
+      if (e < n) p[e] = v[u];
+    }
+  }
+}
+
 // L-BFGS state of one seed in registers: history (newest first), the
 // previous iterate and gradient.  Loaded before anything it does not depend
 // on is computed, so the loads' latency overlaps that work.  Memory holds
@@ -124,7 +172,7 @@ struct LbfgsRegs {
   float Sh[MH][PL], Yh[MH][PL], rh[MH];
 };
 
-template <int PL, int MH>
+template <int PL, int MH, bool V4>
 __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
                                            LbfgsRegs<PL, MH>& h) {
   const int n = si.T * a.dof;
@@ -138,25 +186,15 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
   const int first = ((cint*)a.first)[s];
   int count = ((cint*)a.meta)[2 * s + 0];
   int head = ((cint*)a.meta)[2 * s + 1];
-#pragma unroll
-  for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave, ec = min(e, n - 1);
-    h.xp[u] = a.x_prev[base + ec];
-    h.gp[u] = a.g_prev[base + ec];
-    h.xp[u] = e < n ? h.xp[u] : 0.0f;
-    h.gp[u] = e < n ? h.gp[u] : 0.0f;
-  }
+  ld_row<PL, V4>(a.x_prev + base, n, lane, h.xp);
+  ld_row<PL, V4>(a.g_prev + base, n, lane, h.gp);
   float RS[MH][PL], RY[MH][PL], Rr[MH];
 #pragma unroll
   for (int r = 0; r < MH; ++r) {
     const int rc = min(r, max(m - 1, 0));   // (the history holds at least one slot)
     Rr[r] = ((cfloat*)a.rho)[(size_t)s * a.m_max + rc];
-#pragma unroll
-    for (int u = 0; u < PL; ++u) {
-      const int e = lane + u * kWave, ec = min(e, n - 1);
-      RS[r][u] = a.S[(size_t)rc * stride + base + ec];
-      RY[r][u] = a.Y[(size_t)rc * stride + base + ec];
-    }
+    ld_row<PL, V4>(a.S + (size_t)rc * stride + base, n, lane, RS[r]);
+    ld_row<PL, V4>(a.Y + (size_t)rc * stride + base, n, lane, RY[r]);
   }
   const bool reset = a.reset != 0 || (a.use_first && first != 0);
   if (reset) { count = 0; head = 0; }
@@ -189,7 +227,7 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
         sv = i == r ? RS[r][u] : sv;
         yv = i == r ? RY[r][u] : yv;
       }
-      const bool in = live && lane + u * kWave < n;
+      const bool in = live && el_idx<PL, V4>(lane, u) < n;
       h.Sh[c][u] = in ? sv : 0.0f;
       h.Yh[c][u] = in ? yv : 0.0f;
     }
@@ -201,7 +239,7 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
 // n = T*D <= 64*PL): stores the last step's pair in the ring when its
 // curvature passes the guard, runs the two loops on registers and DPP sums,
 // and writes dir and x/g_prev.
-template <int PL, int MH>
+template <int PL, int MH, bool V4>
 __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
                                              const float* xv, const float* gv, LbfgsRegs<PL, MH>& h) {
   const int n = si.T * a.dof;
@@ -212,7 +250,7 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
   float sv[PL], yv[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const bool in = lane + u * kWave < n && !h.reset;
+    const bool in = el_idx<PL, V4>(lane, u) < n && !h.reset;
     sv[u] = in ? xv[u] - h.xp[u] : 0.0f;
     yv[u] = in ? gv[u] - h.gp[u] : 0.0f;
   }
@@ -227,14 +265,8 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
     }
     sy = wave_sum(sy); ss = wave_sum(ss); yy = wave_sum(yy);
     if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy) && sy > 0.0f) {
-#pragma unroll
-      for (int u = 0; u < PL; ++u) {
-        const int e = lane + u * kWave;
-        if (e < n) {
-          a.S[(size_t)head * stride + base + e] = sv[u];
-          a.Y[(size_t)head * stride + base + e] = yv[u];
-        }
-      }
+      st_row<PL, V4>(a.S + (size_t)head * stride + base, n, lane, sv);
+      st_row<PL, V4>(a.Y + (size_t)head * stride + base, n, lane, yv);
       if (lane == 0) a.rho[(size_t)s * a.m_max + head] = 1.0f / sy;
       // shift the register copy: the new pair becomes slot 0
 #pragma unroll
@@ -295,14 +327,10 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
     }
   }
 #pragma unroll
-  for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave;
-    if (e < n) {
-      a.dir[base + e] = -q[u];
-      a.x_prev[base + e] = xv[u];
-      a.g_prev[base + e] = gv[u];
-    }
-  }
+  for (int u = 0; u < PL; ++u) q[u] = -q[u];
+  st_row<PL, V4>(a.dir + base, n, lane, q);
+  st_row<PL, V4>(a.x_prev + base, n, lane, xv);
+  st_row<PL, V4>(a.g_prev + base, n, lane, gv);
   if (lane == 0) {
     a.meta[2 * s + 0] = count;
     a.meta[2 * s + 1] = head;
@@ -310,7 +338,7 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
   }
 }
 
-template <int PL, int MH>
+template <int PL, int MH, bool V4>
 __global__ __launch_bounds__(kWave) void lbfgs_kernel(const LbfgsArgs a) {
   const int s = blockIdx.x;          // one wavefront (and workgroup) per seed
   const int lane = threadIdx.x;
@@ -320,17 +348,11 @@ __global__ __launch_bounds__(kWave) void lbfgs_kernel(const LbfgsArgs a) {
   const int n = si.T * a.dof;
   const size_t base = (size_t)si.row0 * a.dof;
   float xv[PL], gv[PL];
-#pragma unroll
-  for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave, ec = min(e, n - 1);
-    xv[u] = a.x[base + ec];
-    gv[u] = a.g[base + ec];
-    xv[u] = e < n ? xv[u] : 0.0f;
-    gv[u] = e < n ? gv[u] : 0.0f;
-  }
+  ld_row<PL, V4>(a.x + base, n, lane, xv);
+  ld_row<PL, V4>(a.g + base, n, lane, gv);
   LbfgsRegs<PL, MH> h;
-  lbfgs_load<PL, MH>(a, s, lane, si, h);
-  lbfgs_finish<PL, MH>(a, s, lane, si, xv, gv, h);
+  lbfgs_load<PL, MH, V4>(a, s, lane, si, h);
+  lbfgs_finish<PL, MH, V4>(a, s, lane, si, xv, gv, h);
 }
 
 // --------------------------------------------------------------------------
@@ -340,7 +362,7 @@ __global__ __launch_bounds__(kWave) void lbfgs_kernel(const LbfgsArgs a) {
 // count padded to 4, 8 or 16, so the candidates' sums run unrolled and
 // overlap.  With FUSED the same wavefront then computes the next L-BFGS
 // direction from the chosen iterate, which is still in its registers.
-template <int PL, int MH, bool FUSED, int KP>
+template <int PL, int MH, bool FUSED, int KP, bool V4>
 __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const LbfgsArgs la) {
   const int s = blockIdx.x;            // (the grid is exactly one workgroup per seed)
   const int lane = threadIdx.x;
@@ -353,21 +375,18 @@ __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const
   // L-BFGS state, the joint limits, and for up to 8 candidates every
   // candidate's gradient
   LbfgsRegs<PL, FUSED ? MH : 1> h;
-  if constexpr (FUSED) lbfgs_load<PL, MH>(la, s, lane, si, h);
+  if constexpr (FUSED) lbfgs_load<PL, MH, V4>(la, s, lane, si, h);
   constexpr int KG = (PL <= 4 && KP <= 8) ? KP : 1;
   const bool pre = KG > 1;
   float gall[KG][PL];
 #pragma unroll
-  for (int k = 0; k < KG; ++k)
-#pragma unroll
-    for (int u = 0; u < PL; ++u) {
-      const int ec = min(lane + u * kWave, n - 1), kc = min(k, a.K - 1);
-      gall[k][u] = pre ? a.grad_e[((size_t)kc * a.rows + si.row0) * D + ec] : 0.0f;
-    }
+  for (int k = 0; k < KG; ++k) {
+    if (pre) ld_row<PL, V4>(a.grad_e + ((size_t)min(k, a.K - 1) * a.rows + si.row0) * D, n, lane, gall[k]);
+  }
   float qlo[PL], qhi[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const int j = (lane + u * kWave) % D;
+    const int j = el_idx<PL, V4>(lane, u) % D;
     qlo[u] = a.q_lo[j];
     qhi[u] = a.q_hi[j];
   }
@@ -390,18 +409,15 @@ __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const
     gq[i] = a.gd_e[e];
     mq[i] = a.mc_e[e];
   }
-  float gdv[PL], xv[PL], dv[PL];
+  float gdv[PL], xv[PL], dv[PL], g0v[PL];
+  ld_row<PL, V4>(a.x + base, n, lane, xv);
+  ld_row<PL, V4>(a.d + base, n, lane, dv);
+  ld_row<PL, V4>(a.g0 + base, n, lane, g0v);
   float g0d = 0.0f;
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave, ec = min(e, n - 1);
     gdv[u] = 0.0f;
-    xv[u] = a.x[base + ec];
-    dv[u] = a.d[base + ec];
-    const float g0 = a.g0[base + ec];
-    xv[u] = e < n ? xv[u] : 0.0f;
-    dv[u] = e < n ? dv[u] : 0.0f;
-    g0d = fmaf(e < n ? g0 : 0.0f, dv[u], g0d);
+    g0d = fmaf(g0v[u], dv[u], g0d);
   }
   g0d = wave_sum(g0d);
   float cs = 0.0f, gs = 0.0f, ms = 3.0e38f;
@@ -437,32 +453,23 @@ __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const
 #pragma unroll
       for (int u = 0; u < PL; ++u) gdv[u] = k == best ? gall[k][u] : gdv[u];
   } else {
-    const float* gsrc = a.grad_e + ((size_t)best * a.rows + si.row0) * D;
-#pragma unroll
-    for (int u = 0; u < PL; ++u) {
-      const int e = lane + u * kWave;
-      gdv[u] = gsrc[min(e, n - 1)];
-      gdv[u] = e < n ? gdv[u] : 0.0f;
-    }
+    ld_row<PL, V4>(a.grad_e + ((size_t)best * a.rows + si.row0) * D, n, lane, gdv);
   }
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const int e = lane + u * kWave;
-    const float v = e < n ? fminf(fmaxf(fmaf(al, dv[u], xv[u]), qlo[u]), qhi[u]) : 0.0f;
-    xv[u] = v;
-    if (e < n) {
-      a.x_out[base + e] = v;
-      a.g_out[base + e] = gdv[u];
-      if (improve) a.best_x[base + e] = v;
-    }
+    const int e = el_idx<PL, V4>(lane, u);
+    xv[u] = e < n ? fminf(fmaxf(fmaf(al, dv[u], xv[u]), qlo[u]), qhi[u]) : 0.0f;
   }
+  st_row<PL, V4>(a.x_out + base, n, lane, xv);
+  st_row<PL, V4>(a.g_out + base, n, lane, gdv);
+  if (improve) st_row<PL, V4>(a.best_x + base, n, lane, xv);
   if (lane == 0) {
     a.c_out[s] = cb;
     if (a.chosen) a.chosen[s] = best;
     if (a.mc_out) a.mc_out[s] = mcb;
     if (improve) a.best_c[s] = cb;
   }
-  if constexpr (FUSED) lbfgs_finish<PL, MH>(la, s, lane, si, xv, gdv, h);
+  if constexpr (FUSED) lbfgs_finish<PL, MH, V4>(la, s, lane, si, xv, gdv, h);
 }
 
 // --------------------------------------------------------------------------
@@ -574,21 +581,41 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int PL, int KP>
+template <int PL, int KP, bool V4>
 hipError_t launch_select_k(const SelectArgs& a, const LbfgsArgs* la, hipStream_t s) {
   const dim3 grid(a.n_seeds);
-  if (!la) select_kernel<PL, 4, false, KP><<<grid, kWave, 0, s>>>(a, LbfgsArgs{});
-  else if (la->m <= 4) select_kernel<PL, 4, true, KP><<<grid, kWave, 0, s>>>(a, *la);
-  else select_kernel<PL, kMaxHist, true, KP><<<grid, kWave, 0, s>>>(a, *la);
+  if (!la) select_kernel<PL, 4, false, KP, V4><<<grid, kWave, 0, s>>>(a, LbfgsArgs{});
+  else if (la->m <= 4) select_kernel<PL, 4, true, KP, V4><<<grid, kWave, 0, s>>>(a, *la);
+  else select_kernel<PL, kMaxHist, true, KP, V4><<<grid, kWave, 0, s>>>(a, *la);
   return hipGetLastError();
+}
+
+// Row blocks move as float4 when every seed's block is a multiple of 4
+// floats and every array is 16-byte aligned.
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+bool rows_v4(int uniform_T, int dof) { return uniform_T > 0 && (uniform_T * dof) % 4 == 0; }
+bool select_v4(const SelectArgs& a, const LbfgsArgs* la) {
+  bool ok = rows_v4(a.uniform_T, a.dof) && aligned16(a.x) && aligned16(a.d) && aligned16(a.g0) &&
+            aligned16(a.x_out) && aligned16(a.g_out) && aligned16(a.best_x) && aligned16(a.grad_e);
+  if (la)
+    ok = ok && aligned16(la->S) && aligned16(la->Y) && aligned16(la->x_prev) && aligned16(la->g_prev) &&
+         aligned16(la->dir) && (la->rows * la->dof) % 4 == 0;
+  return ok;
 }
 
 template <int PL>
 hipError_t launch_select_pl(const SelectArgs& a, const LbfgsArgs* la, hipStream_t s) {
   if (a.K < 1 || a.K > kMaxK) return hipErrorInvalidValue;
-  if (a.K <= 4) return launch_select_k<PL, 4>(a, la, s);
-  if (a.K <= 8) return launch_select_k<PL, 8>(a, la, s);
-  return launch_select_k<PL, 16>(a, la, s);
+  if constexpr (PL >= 4) {
+    if (select_v4(a, la)) {
+      if (a.K <= 4) return launch_select_k<PL, 4, true>(a, la, s);
+      if (a.K <= 8) return launch_select_k<PL, 8, true>(a, la, s);
+      return launch_select_k<PL, 16, true>(a, la, s);
+    }
+  }
+  if (a.K <= 4) return launch_select_k<PL, 4, false>(a, la, s);
+  if (a.K <= 8) return launch_select_k<PL, 8, false>(a, la, s);
+  return launch_select_k<PL, 16, false>(a, la, s);
 }
 
 hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, hipStream_t s) {
@@ -602,11 +629,16 @@ hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, 
 template <int MH>
 hipError_t launch_lbfgs_h(const LbfgsArgs& a, int max_n, hipStream_t s) {
   const dim3 grid(a.n_seeds);
-  if (max_n <= 64) lbfgs_kernel<1, MH><<<grid, kWave, 0, s>>>(a);
-  else if (max_n <= 128) lbfgs_kernel<2, MH><<<grid, kWave, 0, s>>>(a);
-  else if (max_n <= 256) lbfgs_kernel<4, MH><<<grid, kWave, 0, s>>>(a);
-  else if (max_n <= 512) lbfgs_kernel<8, MH><<<grid, kWave, 0, s>>>(a);
-  else lbfgs_kernel<16, MH><<<grid, kWave, 0, s>>>(a);
+  const bool v4 = rows_v4(a.uniform_T, a.dof) && (a.rows * a.dof) % 4 == 0 && aligned16(a.x) && aligned16(a.g) &&
+                  aligned16(a.S) && aligned16(a.Y) && aligned16(a.x_prev) && aligned16(a.g_prev) && aligned16(a.dir);
+  if (max_n <= 64) lbfgs_kernel<1, MH, false><<<grid, kWave, 0, s>>>(a);
+  else if (max_n <= 128) lbfgs_kernel<2, MH, false><<<grid, kWave, 0, s>>>(a);
+  else if (max_n <= 256 && v4) lbfgs_kernel<4, MH, true><<<grid, kWave, 0, s>>>(a);
+  else if (max_n <= 256) lbfgs_kernel<4, MH, false><<<grid, kWave, 0, s>>>(a);
+  else if (max_n <= 512 && v4) lbfgs_kernel<8, MH, true><<<grid, kWave, 0, s>>>(a);
+  else if (max_n <= 512) lbfgs_kernel<8, MH, false><<<grid, kWave, 0, s>>>(a);
+  else if (v4) lbfgs_kernel<16, MH, true><<<grid, kWave, 0, s>>>(a);
+  else lbfgs_kernel<16, MH, false><<<grid, kWave, 0, s>>>(a);
   return hipGetLastError();
 }
 
