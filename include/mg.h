@@ -186,7 +186,8 @@ mg_status mg_solve(mg_ctx *ctx, mg_batch *batch, const float *q_start, const flo
  *   term off.  Copied to the device (not capturable).
  * The term is evaluated by the wave-per-link layout only: while pairs are
  * set, every evaluation uses it (robots of at most 15 links; otherwise
- * MG_ERR_UNSUPPORTED), and mg_particles is refused. */
+ * MG_ERR_UNSUPPORTED), mg_particles included (with the particle count of
+ * the last mg_batch_reserve_particles, at least 2). */
 mg_status mg_set_self_collision(mg_ctx *ctx, int n_pairs, const int *pairs);
 
 /* Forward kinematics of the end effectors (Sec. "Robot Kinematics", Tab.6):
@@ -245,6 +246,8 @@ mg_status mg_autotune(mg_ctx *ctx, mg_batch *batch, const float *q_start, const 
  *   mean, var DEVICE [rows][D] in/out (var per element, rad^2)
  *   eps       DEVICE [n_iters][n_particles][rows][D] standard normal draws
  *   costs_out DEVICE [n_iters][seeds][n_particles] particle costs, or NULL
+ * The costing launch takes the batch's layout (lane or wave per link) when
+ * n_particles is the last reserved count, else lane per link.
  * MG_ERR_STATE if n_particles exceeds the reservation.  Capturable. */
 mg_status mg_batch_reserve_particles(mg_batch *batch, int n_particles);
 mg_status mg_particles(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,

@@ -137,9 +137,13 @@ struct mg_batch {
   int wl_slices_max = 1;    // largest the scratch below holds
   float* wl_part = nullptr; // [chunks][slices][3 + D][64]
   int* wl_count = nullptr;  // [chunks], zero between launches
-  // particle stage: per-row costs of every particle [p_cap][rows]
+  // particle stage: per-row costs of every particle [p_cap][rows], and
+  // wave-per-link chunk records for pm_K particles per row
   float* p_cost = nullptr;
   int p_cap = 0;
+  int pm_K = 0;
+  mg::WlChunk* d_chunk_pm[2] = {};
+  int chunks_pm[2] = {};
 };
 
 namespace {
@@ -390,36 +394,45 @@ mg::EvalArgs eval_args(const mg_ctx* c, const mg_batch* b, int hi, const float* 
   return a;
 }
 
-// Wave-per-link chunk records of a batch for every K <= K_max and both
-// chunk sizes (64 and 32 evaluations), problem by problem, with the
-// problem's cuboid range in the context's current worlds (empty for a
-// world not set yet).  Allocated on the first call, rewritten in place
-// (synchronously) afterwards.
-mg_status wl_chunks_upload(mg_batch* b) {
+// Wave-per-link chunk records of a batch for K candidates per row and E
+// evaluations per chunk, problem by problem, with the problem's cuboid
+// range in the context's current worlds (empty for a world not set yet).
+// Allocated on the first call, rewritten in place (synchronously) after.
+mg_status wl_records(mg_batch* b, int K, int E, mg::WlChunk** dptr, int* count) {
   const mg_ctx* c = b->ctx;
+  std::vector<mg::WlChunk> rec;
+  int r0 = 0;
+  for (int p = 0; p < b->P; ++p) {
+    const int n_e = b->seeds[p] * b->horizon[p] * K;
+    const int w = b->world[p];
+    const bool set = w + 1 < (int)c->world_off.size();
+    const int lo = set ? c->world_off[w] : 0, hi = set ? c->world_off[w + 1] : 0;
+    for (int e = 0; e < n_e; e += E) rec.push_back(mg::WlChunk{p, e, b->seeds[p], b->horizon[p], lo, hi, r0, n_e});
+    r0 += b->seeds[p] * b->horizon[p];
+  }
+  if (!*dptr || *count != (int)rec.size()) {
+    dev_free(*dptr);
+    mg_status st = dev_upload(dptr, rec);
+    if (st != MG_OK) return st;
+    *count = (int)rec.size();
+  } else {
+    HIP_TRY(hipMemcpy(*dptr, rec.data(), rec.size() * sizeof(mg::WlChunk), hipMemcpyHostToDevice));
+  }
+  return MG_OK;
+}
+
+// Every K <= K_max and both chunk sizes (64 and 32 evaluations), and the
+// particle stage's records when particles are reserved.
+mg_status wl_chunks_upload(mg_batch* b) {
+  mg_status st;
   for (int K = 1; K <= b->K_max; ++K)
-    for (int gi = 0; gi < 2; ++gi) {
-      const int E = mg::kWave >> gi;
-      std::vector<mg::WlChunk> rec;
-      int r0 = 0;
-      for (int p = 0; p < b->P; ++p) {
-        const int n_e = b->seeds[p] * b->horizon[p] * K;
-        const int w = b->world[p];
-        const bool set = w + 1 < (int)c->world_off.size();
-        const int lo = set ? c->world_off[w] : 0, hi = set ? c->world_off[w + 1] : 0;
-        for (int e = 0; e < n_e; e += E)
-          rec.push_back(mg::WlChunk{p, e, b->seeds[p], b->horizon[p], lo, hi, r0, n_e});
-        r0 += b->seeds[p] * b->horizon[p];
-      }
-      if (!b->d_chunk_wl[K][gi]) {
-        mg_status st = dev_upload(&b->d_chunk_wl[K][gi], rec);
-        if (st != MG_OK) return st;
-        b->chunks_wl[K][gi] = (int)rec.size();
-      } else {
-        HIP_TRY(hipMemcpy(b->d_chunk_wl[K][gi], rec.data(), rec.size() * sizeof(mg::WlChunk),
-                          hipMemcpyHostToDevice));
-      }
-    }
+    for (int gi = 0; gi < 2; ++gi)
+      if ((st = wl_records(b, K, mg::kWave >> gi, &b->d_chunk_wl[K][gi], &b->chunks_wl[K][gi])) != MG_OK)
+        return st;
+  if (b->pm_K > 0)
+    for (int gi = 0; gi < 2; ++gi)
+      if ((st = wl_records(b, b->pm_K, mg::kWave >> gi, &b->d_chunk_pm[gi], &b->chunks_pm[gi])) != MG_OK)
+        return st;
   return MG_OK;
 }
 
@@ -800,6 +813,7 @@ void mg_batch_destroy(mg_batch* b) {
   for (auto& p : b->d_chunk) dev_free(p);
   for (auto& pk : b->d_chunk_wl)
     for (auto& p : pk) dev_free(p);
+  for (auto& p : b->d_chunk_pm) dev_free(p);
   dev_free(b->cost_e); dev_free(b->gd_e); dev_free(b->mc_e); dev_free(b->grad_e); dev_free(b->pe_e);
   dev_free(b->c_cur); dev_free(b->g_cur); dev_free(b->dir); dev_free(b->best_c); dev_free(b->best_x);
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
@@ -1050,13 +1064,19 @@ mg_status mg_batch_reserve_particles(mg_batch* b, int n_particles) {
   if (!b) return fail(MG_ERR_ARG, "null batch");
   if (n_particles < 1 || n_particles > mg::kMaxParticles)
     return fail(MG_ERR_SHAPE, "n_particles = %d outside 1..%d", n_particles, mg::kMaxParticles);
-  if (n_particles <= b->p_cap) return MG_OK;
   HIP_TRY(hipDeviceSynchronize());
-  dev_free(b->p_cost);
-  b->p_cap = 0;
-  mg_status st = dev_alloc(&b->p_cost, (size_t)n_particles * b->rows);
-  if (st != MG_OK) return st;
-  b->p_cap = n_particles;
+  mg_status st;
+  if (n_particles > b->p_cap) {
+    dev_free(b->p_cost);
+    b->p_cap = 0;
+    if ((st = dev_alloc(&b->p_cost, (size_t)n_particles * b->rows)) != MG_OK) return st;
+    b->p_cap = n_particles;
+  }
+  // wave-per-link records for this particle count
+  b->pm_K = n_particles;
+  for (int gi = 0; gi < 2; ++gi)
+    if ((st = wl_records(b, n_particles, mg::kWave >> gi, &b->d_chunk_pm[gi], &b->chunks_pm[gi])) != MG_OK)
+      return st;
   return MG_OK;
 }
 
@@ -1069,11 +1089,25 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
     return fail(MG_ERR_STATE, "n_particles = %d exceeds the %d reserved (mg_batch_reserve_particles)",
                 n_particles, b->p_cap);
   if (n_iters < 0) return fail(MG_ERR_ARG, "n_iters must be >= 0");
-  if (c->n_self > 0) return fail(MG_ERR_UNSUPPORTED, "the particle stage does not evaluate self-collision");
   if (!q_start || !goal || !mean || !var || (n_iters > 0 && !eps))
     return fail(MG_ERR_ARG, "null q_start, goal, mean, var or eps");
   if (!(k_mu >= 0.0f && k_mu <= 1.0f) || !(k_sigma >= 0.0f && k_sigma <= 1.0f))
     return fail(MG_ERR_ARG, "k_mu and k_sigma must lie in [0, 1]");
+  // the batch's wave-per-link layout where it was chosen or self-collision
+  // is on (and the records are for this particle count), else lane per link
+  const int groups = b->wl_groups == 2 && wl_groups_possible(c) ? 2 : 1;
+  const int halves = groups == 2 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(c) ? 2 : 1));
+  const int E = mg::kWave / groups;
+  // rows a chunk of E particles touches, with the stencils' four on either side
+  const int pm_rows = (E - 1) / n_particles + 10;
+  const bool wl = (b->layout == 1 || c->n_self > 0) && wl_possible(c) && n_particles == b->pm_K &&
+                  pm_rows <= mg::kWlStageRows &&
+                  mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, c->n_self > 0, halves, c->maxs, E, pm_rows) <=
+                      c->lds_max;
+  if (c->n_self > 0 && !wl)
+    return fail(MG_ERR_UNSUPPORTED,
+                "self-collision in the particle stage needs the wave-per-link layout for %d particles "
+                "(the last mg_batch_reserve_particles count, at least 2)", n_particles);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t draws = (size_t)n_particles * b->rows * c->D;
   const int hi = pick_slices(b, (long)b->rows * n_particles);
@@ -1086,7 +1120,15 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
     a.mc_e = nullptr;
     a.gd_e = nullptr;
     a.grad_e = nullptr;
-    HIP_TRY(mg::launch_eval(a, b->chunks[hi], true, false, s));
+    if (wl) {
+      a.wl.halves = halves;
+      a.wl.groups = groups;
+      a.wl.chunk = b->d_chunk_pm[groups - 1];
+      a.wl.pm_rows = pm_rows;
+      HIP_TRY(mg::launch_eval_wl(a, b->chunks_pm[groups - 1], 1, true, false, s));
+    } else {
+      HIP_TRY(mg::launch_eval(a, b->chunks[hi], true, false, s));
+    }
     mg::ParticleArgs pa;
     memset(&pa, 0, sizeof(pa));
     pa.seeds = b->d_seed;

@@ -305,7 +305,11 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const int row = pb.row0 + rl;
   const float alpha = CAND ? a.alpha[k < kMaxK ? k : 0] : 0.0f;
 
-  const WlLds o = wl_lds_layout(L, D, maxd, a.rb.n_spheres, a.pr.n_self > 0, HS, maxs, E);
+  // particle mode (cost only): candidate k of row r is clip(x + sqrt(var) eps_k)
+  // with the draws eps_k = d + k d_stride (Alg.5); var is staged in d's place
+  const bool pm = CAND && !GRAD && a.var != nullptr;
+  const int pm_rows = pm ? a.wl.pm_rows : 0;
+  const WlLds o = wl_lds_layout(L, D, maxd, a.rb.n_spheres, a.pr.n_self > 0, HS, maxs, E, pm_rows);
   float* s_x = s_mem + o.x;
   float* s_d = s_mem + o.d;
   float* s_lim = s_mem + o.lim;               // lower, upper, start
@@ -315,6 +319,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   float4* s_slot = reinterpret_cast<float4*>(s_mem + o.slot);
   float4* s_box = reinterpret_cast<float4*>(s_mem + o.box);   // two tiles
   int* s_tick = reinterpret_cast<int*>(s_mem + o.tick);
+  float* s_eps = s_mem + o.eps;
 
   // the workgroup's rows and the four on either side (the stencils' reach)
   const int e_last = min(n_e, e_first + E) - 1;
@@ -326,13 +331,24 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const int per = (box_hi - box_lo + H - 1) / H;
   const int w0 = min(box_hi, box_lo + h * per), w1 = min(box_hi, w0 + per);
   {
-    // scalars: rows of x (and d), limits, start, goals, tool transforms
+    // scalars: rows of x (and d, or var), limits, start, goals, tool
+    // transforms, and in particle mode each lane's draws over the rows
     const int nxd = CAND ? 2 * n_st : n_st;
-    const int nf = nxd + 3 * D + n_ee * 19;
+    const int n_eps = pm ? min(r_hi - r_lo + 1, pm_rows) * E * D : 0;
+    const int nf = nxd + 3 * D + n_ee * 19 + n_eps;
+    const float* dsrc = pm ? a.var : a.d;
     auto fsrc = [&](int i, float*& dst) -> const float* {
       if (i < n_st) { dst = s_x + i; return a.x + (size_t)r_lo * D + i; }
-      if (i < nxd) { dst = s_d + (i - n_st); return a.d + (size_t)r_lo * D + (i - n_st); }
+      if (i < nxd) { dst = s_d + (i - n_st); return dsrc + (size_t)r_lo * D + (i - n_st); }
       i -= nxd;
+      if (i < n_eps) {
+        // item (row rr, lane ee, joint j): lane ee's particle at row r_lo + rr
+        dst = s_eps + i;
+        const int rr = i / (E * D), rem = i - rr * (E * D), ee = rem / D, j = rem - ee * D;
+        const int ke = min(e_first + ee, n_e - 1) % K;
+        return a.d + (size_t)ke * a.d_stride + (size_t)(r_lo + rr) * D + j;
+      }
+      i -= n_eps;
       if (i < D) { dst = s_lim + i; return a.rb.q_lo + i; }
       if (i < 2 * D) { dst = s_lim + i; return a.rb.q_hi + (i - D); }
       if (i < 3 * D) { dst = s_lim + i; return a.q_start + (size_t)p * D + (i - 2 * D); }
@@ -375,7 +391,8 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     const int i = (r - r_lo) * D + j;
     float v = s_x[i];
     if (CAND) {
-      v = fmaf(alpha, s_d[i], v);
+      if (pm) v = fmaf(sqrtf(s_d[i]), s_eps[((r - r_lo) * E + el) * D + j], v);
+      else v = fmaf(alpha, s_d[i], v);
       v = fminf(fmaxf(v, s_lim[j]), s_lim[D + j]);
     }
     return v;
@@ -812,27 +829,28 @@ hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand
   if (waves * kWave > 1024 || slices < 1 || ((HS == 2 || G > 1) && slices > 1)) return hipErrorInvalidValue;
   if (G > 1 && (HS != 1 || a.pr.n_self > 0)) return hipErrorInvalidValue;
   if (slices > 1 && (!a.wl.part || !a.wl.count)) return hipErrorInvalidValue;
-  // particle mode (per-candidate draws) is not staged in this layout
-  if (a.var || a.d_stride) return hipErrorInvalidValue;
+  // particle mode (per-candidate draws): cost only, draws staged per row
+  const bool pm = a.var != nullptr;
+  if (pm && (!cand || grad || a.K < 1 || a.wl.pm_rows < (kWave / G - 1) / a.K + 10 || a.wl.pm_rows > kWlStageRows))
+    return hipErrorInvalidValue;
   // every joint has a gathering wave, the last wave is none of them, and
   // two 64-thread passes cover a cuboid tile
   if (a.rb.dof > waves - 1 || waves < 2 || !a.wl.chunk) return hipErrorInvalidValue;
   const size_t lds = wl_lds_bytes(a.rb.n_links, a.rb.dof, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0, HS,
-                                  a.wl.maxs, kWave / G);
+                                  a.wl.maxs, kWave / G, pm ? a.wl.pm_rows : 0);
   if (lds > kWlLdsMax) return hipErrorInvalidValue;
   const dim3 grid(grid_x, slices), block(waves * kWave);
   if (a.pr.swept && waves <= 8) {
-    // (swept collision: no particle mode)
     if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, true>, grid, block, lds, s, a);
     if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, true>, grid, block, lds, s, a);
     if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, true>, grid, block, lds, s, a);
-    return hipErrorInvalidValue;
+    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G, true>, grid, block, lds, s, a);
   }
   if (a.pr.swept) {
     if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G, true>, grid, block, lds, s, a);
     if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G, true>, grid, block, lds, s, a);
     if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G, true>, grid, block, lds, s, a);
-    return hipErrorInvalidValue;
+    return wl_launch(eval_wl_kernel<MAXS, true, false, 1024, G, true>, grid, block, lds, s, a);
   }
   if (waves <= 8) {
     if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, false>, grid, block, lds, s, a);

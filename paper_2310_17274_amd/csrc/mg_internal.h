@@ -94,6 +94,7 @@ struct WaveLinks {
   int halves;              // waves per link: 1, or 2 (each with half of the slots)
   int groups;              // slot groups per wave: 1, or 2 (32 evaluations per workgroup,
                            //   each half of the wave with half of the slots; halves == 1)
+  int pm_rows;             // particle mode: rows of draws staged per workgroup (else 0)
   // cuboid slices over workgroups (gridDim.y > 1): per-slice partial sums
   // [chunk][slice][3 + D][64] and one arrival counter per chunk (zero
   // between launches; the last workgroup of a chunk resets it)
@@ -129,10 +130,12 @@ __host__ __device__ inline size_t wl_region_floats(int L, int D, int max_depth, 
 }
 // float offsets of the staged tables
 struct WlLds {
-  size_t x, d, lim, goal, etf, chain, slot, box, tick, total;
+  size_t x, d, lim, goal, etf, chain, slot, box, tick, eps, total;
 };
+// pm_rows > 0 (particle mode): the draws of every lane's particle over the
+// staged rows, [pm_rows][E][D]
 __host__ __device__ inline WlLds wl_lds_layout(int L, int D, int max_depth, int n_spheres, bool self,
-                                               int halves, int maxs, int E) {
+                                               int halves, int maxs, int E, int pm_rows = 0) {
   WlLds o;
   size_t at = wl_region_floats(L, D, max_depth, n_spheres, self, halves, E);
   auto take = [&at](size_t n) {
@@ -150,12 +153,13 @@ __host__ __device__ inline WlLds wl_lds_layout(int L, int D, int max_depth, int 
   o.slot = take((size_t)L * maxs * 4);
   o.box = take(2 * (size_t)kWlBoxTile * 16);
   o.tick = take(4);
+  o.eps = take((size_t)pm_rows * E * D);
   o.total = at;
   return o;
 }
 __host__ __device__ inline size_t wl_lds_bytes(int L, int D, int max_depth, int n_spheres, bool self,
-                                               int halves, int maxs, int E) {
-  return wl_lds_layout(L, D, max_depth, n_spheres, self, halves, maxs, E).total * sizeof(float);
+                                               int halves, int maxs, int E, int pm_rows = 0) {
+  return wl_lds_layout(L, D, max_depth, n_spheres, self, halves, maxs, E, pm_rows).total * sizeof(float);
 }
 
 // Cuboid in the library layout: p = A c + b maps a world point into the box

@@ -210,11 +210,16 @@ def _particle_round_reference(case, mean, var, eps_round, costs_gpu, boxes, p=0)
     return out_m, out_v
 
 
-def test_particle_stage_parity():
+PARTICLE_LAYOUTS = [pytest.param((0, 0), id="lane"), pytest.param((1, 1), id="wave"),
+                    pytest.param((2, 0), id="wave2"), pytest.param((3, 0), id="groups2")]
+
+
+@pytest.mark.parametrize("layout", PARTICLE_LAYOUTS)
+def test_particle_stage_parity(layout):
     """Two rounds of 64 particles per seed (Alg.5): each round's particle
     costs against the reference's, and the mean / variance update against
     the reference update fed the GPU's costs (fp32 sums of 64 terms)."""
-    case = make_case("adjoint_small")
+    case = make_case("adjoint_small", layout=layout)
     S, T, D, N = 5, 32, 7, 64
     rng = np.random.default_rng(12)
     eps = rng.normal(0, 1, (2, N, S * T, D)).astype(np.float32).astype(np.float64)
@@ -263,13 +268,14 @@ def test_particle_stage_end_to_end_against_reference():
         assert np.abs(mg[s] - m_ref[s]).max() <= 1e-2 * moved + 1e-5, s
 
 
-def test_large_tree_swept_particle_stage_sampled():
+@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2")])
+def test_large_tree_swept_particle_stage_sampled(layout):
     """Particle stage at full size: two-arm tree, 128 seeds x 48 waypoints,
     256 particles, 2 rounds, 500 cuboids, swept collision.  Sampled particle
     costs against the reference, the update of sampled seeds against the
     reference update fed the GPU's costs."""
     robot, worlds, batch, meta = wl.cfg_large()
-    case = Case(robot, worlds, batch, params=SWEPT)
+    case = Case(robot, worlds, batch, params=SWEPT, layout=layout)
     S, T, D, N = 128, 48, robot.dof, 256
     rng = np.random.default_rng(14)
     eps = rng.normal(0, 1, (1, N, S * T, D)).astype(np.float32)
@@ -353,14 +359,35 @@ def test_self_collision_linesearch_parity():
 
 def test_self_collision_restrictions():
     """Self-collision lives in the wave-per-link layout: the particle stage
-    refuses it."""
+    takes it only with the particle count its records were built for."""
     from paper_2310_17274_amd._lib import MgError
     case = _self_case(None, S=2, T=8)
-    case.b.mg_batch_reserve_particles(4)
+    case.b.mg_batch_reserve_particles(8)
     eps = torch.zeros((1, 4, 16, 7), device="cuda")
     var = torch.full_like(case.x, 1e-3)
     with pytest.raises(MgError):
         case.ctx.mg_particles(case.b, case.q_start, case.goal, case.x.clone(), var, eps)
+
+
+@pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((2, 0), id="wave2")])
+def test_self_collision_particle_stage_parity(layout):
+    """One particle round with self-collision on: every particle's cost
+    against the reference's, and the update fed the GPU's costs."""
+    case = _self_case(layout, seed=19, S=3, T=16)
+    S, T, D, N = 3, 16, 7, 24
+    rng = np.random.default_rng(20)
+    eps = rng.normal(0, 1, (1, N, S * T, D)).astype(np.float32).astype(np.float64)
+    case.b.mg_batch_reserve_particles(N)
+    mean = case.x.clone()
+    var = torch.full_like(mean, 0.1 ** 2)
+    m_in = mean.double().cpu().numpy().reshape(S, T, D)
+    v_in = var.double().cpu().numpy().reshape(S, T, D)
+    _, _, costs = case.ctx.mg_particles(case.b, case.q_start, case.goal, mean, var, _dev(eps), costs=True)
+    torch.cuda.synchronize()
+    m_ref, v_ref = _particle_round_reference(case, m_in, v_in, eps[0].reshape(N, S, T, D),
+                                             costs.cpu().numpy()[0], case.worlds.world(0))
+    np.testing.assert_allclose(mean.cpu().numpy().reshape(S, T, D), m_ref, rtol=0, atol=5e-6)
+    np.testing.assert_allclose(var.cpu().numpy().reshape(S, T, D), v_ref, rtol=2e-4, atol=1e-9)
 
 
 @pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((2, 0), id="wave2")])
