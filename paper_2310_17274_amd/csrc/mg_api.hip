@@ -127,6 +127,7 @@ struct mg_batch {
   int ev_next = 0, ev_count = 0;
   int slices = -1;    // forced cuboid slices index (-1: automatic)
   int layout = -1;    // evaluation layout: -1 automatic, 0 lane per link, 1 wave per link
+  bool layout_set = false;   // the layout came from mg_batch_set_layout (not the autotuner)
   // wave-per-link chunks of 64 evaluations, per candidate count K
   // ([K][0]: 64 evaluations per chunk, [K][1]: 32 for two slot groups)
   mg::WlChunk* d_chunk_wl[mg::kMaxK + 1][2] = {};
@@ -965,6 +966,7 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
     if (us < best_us) { best_us = us; best = o; }
   }
   b->layout = opts[best].layout;
+  b->layout_set = false;
   b->slices = opts[best].hi;
   b->wl_halves = opts[best].halves;
   b->wl_slices = opts[best].wls;
@@ -1039,6 +1041,7 @@ mg_status mg_batch_set_layout(mg_batch* b, int layout, int slices) {
     return fail(MG_ERR_UNSUPPORTED, "two slot groups per wave need no self-collision and 4 or more slots per link");
   b->wl_halves = layout == 2 ? 2 : (layout == 1 || layout == 3 ? 1 : 0);
   b->wl_groups = layout == 3 ? 2 : 1;
+  b->layout_set = layout >= 0;
   if (layout >= 2) {
     if (slices > 1) return fail(MG_ERR_ARG, "layouts 2 and 3 take one workgroup per chunk of evaluations");
     b->layout = 1;
@@ -1093,15 +1096,19 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
     return fail(MG_ERR_ARG, "null q_start, goal, mean, var or eps");
   if (!(k_mu >= 0.0f && k_mu <= 1.0f) || !(k_sigma >= 0.0f && k_sigma <= 1.0f))
     return fail(MG_ERR_ARG, "k_mu and k_sigma must lie in [0, 1]");
-  // the batch's wave-per-link layout where it was chosen or self-collision
-  // is on (and the records are for this particle count), else lane per link
   const int groups = b->wl_groups == 2 && wl_groups_possible(c) ? 2 : 1;
   const int halves = groups == 2 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(c) ? 2 : 1));
   const int E = mg::kWave / groups;
   // rows a chunk of E particles touches, with the stencils' four on either side
   const int pm_rows = (E - 1) / n_particles + 10;
-  const bool wl = (b->layout == 1 || c->n_self > 0) && wl_possible(c) && n_particles == b->pm_K &&
-                  pm_rows <= mg::kWlStageRows &&
+  // wave per link where self-collision is on or that layout was set by
+  // mg_batch_set_layout (and the records are for this particle count), else
+  // lane per link.  The autotuner's choice for line-search candidates is not
+  // carried over: on the two-arm tree with 500 cuboids and swept collision
+  // it picks wave per link, yet a particle round measured 13% faster lane
+  // per link.
+  const bool wl = ((b->layout_set && b->layout == 1) || c->n_self > 0) && wl_possible(c) &&
+                  n_particles == b->pm_K && pm_rows <= mg::kWlStageRows &&
                   mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, c->n_self > 0, halves, c->maxs, E, pm_rows) <=
                       c->lds_max;
   if (c->n_self > 0 && !wl)
