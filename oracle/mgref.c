@@ -225,6 +225,31 @@ void mgref_derivatives(int T, int D, const double *q0, const double *q,
     }
 }
 
+/* Retiming (Alg.4, appendix 'Time-step Descretization and Temporal Weight
+ * Scaling'): the waypoint spacing at which the trajectory's largest
+ * velocity, acceleration or jerk reaches the robot's limit.  The stencil
+ * derivatives of order k scale as dt^-k, so re-spacing the same waypoints
+ * at dt' gives |v| dt / dt', |a| (dt / dt')^2, |j| (dt / dt')^3; each meets
+ * its limit at dt' = dt |v| / vmax, dt sqrt(|a| / amax), dt cbrt(|j| / jmax).
+ * The result is the largest of these over t = 0..T and every joint (the
+ * first limit reached as dt' shrinks).  A limit <= 0 leaves its kind out. */
+double mgref_retime(int T, int D, const double *q0, const double *q, double dt,
+                    const double *vmax, const double *amax, const double *jmax) {
+  double *v = (double *)malloc(sizeof(double) * (size_t)(T + 1) * D * 3);
+  double *a = v + (size_t)(T + 1) * D, *j = a + (size_t)(T + 1) * D;
+  mgref_derivatives(T, D, q0, q, dt, v, a, j);
+  double r = 0.0;
+  for (int tau = 0; tau <= T; ++tau)
+    for (int d = 0; d < D; ++d) {
+      const size_t i = (size_t)tau * D + d;
+      if (vmax[d] > 0) r = fmax(r, fabs(v[i]) / vmax[d]);
+      if (amax[d] > 0) r = fmax(r, sqrt(fabs(a[i]) / amax[d]));
+      if (jmax[d] > 0) r = fmax(r, cbrt(fabs(j[i]) / jmax[d]));
+    }
+  free(v);
+  return dt * r;
+}
+
 /* Eq.(16): alpha6 * sum_{t in Q} logcosh(alpha7 v_t) + sum_{t=0..T}
  * (alpha8 |a_t|^2 + alpha9 |j_t|^2).  Reading: Q is not defined in the
  * paper; Q = {T} (stop at the goal, Eq.(6)) unless vel_all is set. */

@@ -74,6 +74,10 @@ double mgref_bound(double x, double lo, double hi, double eta2, double *slope);
  * times).  q0[D], q[T][D]; v, a, j are [T+1][D] (each may be NULL). */
 void mgref_derivatives(int T, int D, const double *q0, const double *q,
                        double dt, double *v, double *a, double *j);
+/* Alg.4 retime: the spacing at which the largest |v|/vmax, |a|/amax or
+ * |j|/jmax over t = 0..T reaches 1 (limits <= 0 are left out). */
+double mgref_retime(int T, int D, const double *q0, const double *q, double dt,
+                    const double *vmax, const double *amax, const double *jmax);
 
 /* Total cost of one trajectory and its exact gradient.
  * q0[D] start, goal[n_ee][7], q[T][D].  T == 1 is the inverse-kinematics

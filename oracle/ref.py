@@ -66,6 +66,7 @@ def lib():
         L.mgref_bound.restype = C.c_double
         L.mgref_ls_select.restype = C.c_int
         L.mgref_linesearch.restype = C.c_int
+        L.mgref_retime.restype = C.c_double
         _LIB = L
     return _LIB
 
@@ -259,6 +260,15 @@ def derivatives(q0, q, dt):
     v = np.zeros((T + 1, D)); a = np.zeros((T + 1, D)); j = np.zeros((T + 1, D))
     lib().mgref_derivatives(T, D, _d(q0)[1], _d(q)[1], C.c_double(dt), _d(v)[1], _d(a)[1], _d(j)[1])
     return v, a, j
+
+
+def retime(q0, q, dt, vmax, amax, jmax):
+    """Alg.4 retime of one trajectory q [T, D] with start q0 at spacing dt."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    T, D = q.shape
+    q0, vmax, amax, jmax = (_d(np.broadcast_to(np.asarray(z, dtype=np.float64), (D,)).copy())
+                            for z in (q0, vmax, amax, jmax))
+    return lib().mgref_retime(T, D, q0[1], _d(q)[1], C.c_double(dt), vmax[1], amax[1], jmax[1])
 
 
 def lbfgs_step(n, m, reset, state, x, g):

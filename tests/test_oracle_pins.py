@@ -799,3 +799,58 @@ def test_solve_reaches_reachable_goal(oracle_lib, T):
         assert pe[0] < 5e-3 and re_[0] < 5e-2
     c_init = r.cost_grad_batch(none, q0, ee, T, x.reshape(-1), grad=False)[0]
     assert best.max() < 0.1 * c_init.min()
+
+
+# ---------------------------------------------------------------------------
+# Retiming (Alg.4).  A ramp q_t = c t (t = 1..T) from q0 = 0 has, through the
+# padded five-point stencils worked out by hand, |v| at most 13c / (12 dt)
+# (at t = 1 and T - 1; c / dt in the interior), |a| at most 7c / (6 dt^2)
+# (at t = 0 and T) and |j| at most c / (2 dt^3) (at t = 1 and T - 1).  The
+# spacing that puts each on its limit is therefore 13c / (12 vmax),
+# sqrt(7c / (6 amax)) and cbrt(c / (2 jmax)), whatever dt the ramp came with.
+
+def _ramp(c, T):
+    c = np.atleast_1d(np.asarray(c, dtype=np.float64))
+    return np.arange(1, T + 1)[:, None] * c[None, :]
+
+
+@pytest.mark.parametrize("dt", [0.25, 0.03])
+def test_retime_ramp_closed_forms(oracle_lib, dt):
+    T, c, inf = 12, 0.3, 0.0      # a limit of 0 leaves its kind out
+    q = _ramp(c, T)
+    assert math.isclose(ref.retime([0.0], q, dt, [2.0], [inf], [inf]), 13 * c / (12 * 2.0), rel_tol=1e-12)
+    assert math.isclose(ref.retime([0.0], q, dt, [inf], [5.0], [inf]), math.sqrt(7 * c / (6 * 5.0)), rel_tol=1e-12)
+    assert math.isclose(ref.retime([0.0], q, dt, [inf], [inf], [40.0]), (c / (2 * 40.0)) ** (1 / 3), rel_tol=1e-12)
+    # all three: the largest spacing (the first limit met as dt shrinks)
+    want = max(13 * c / 24, math.sqrt(7 * c / 30), (c / 80) ** (1 / 3))
+    assert math.isclose(ref.retime([0.0], q, dt, [2.0], [5.0], [40.0]), want, rel_tol=1e-12)
+
+
+def test_retime_takes_the_binding_joint_and_ignores_the_start_offset(oracle_lib):
+    """Per-joint limits: the joint with the largest ratio decides; shifting
+    the whole trajectory and its start by a constant changes nothing."""
+    T = 10
+    c = np.array([0.2, -0.5, 0.05])
+    vmax = np.array([1.0, 4.0, 0.1])
+    q = _ramp(c, T)
+    per_joint = [13 * abs(ci) / (12 * vi) for ci, vi in zip(c, vmax)]   # 0.2167, 0.1354, 0.5417
+    z = np.zeros(3)
+    assert math.isclose(ref.retime(z, q, 0.25, vmax, z, z), max(per_joint), rel_tol=1e-12)
+    off = np.array([1.0, -2.0, 0.5])
+    assert math.isclose(ref.retime(off, q + off, 0.25, vmax, z, z), max(per_joint), rel_tol=1e-12)
+
+
+def test_retime_at_rest_and_retimed_trajectory_sits_on_its_limit(oracle_lib):
+    """A trajectory that never leaves q0 needs no time (up to the cube root
+    of the stencils' rounding residue); a generic one,
+    re-spaced at its retimed dt, has its largest limit ratio equal to 1."""
+    T, D = 16, 4
+    q0 = np.array([0.1, -0.2, 0.3, 0.0])
+    lim = np.array([1.5, 2.0, 1.0, 3.0]), np.array([4.0, 6.0, 5.0, 8.0]), np.array([30.0, 50.0, 40.0, 90.0])
+    assert ref.retime(q0, np.tile(q0, (T, 1)), 0.25, *lim) < 1e-7
+    rng = np.random.default_rng(3)
+    q = q0 + np.cumsum(rng.normal(0, 0.08, (T, D)), axis=0)
+    dt = ref.retime(q0, q, 0.25, *lim)
+    v, a, j = ref.derivatives(q0, q, dt)
+    worst = max((np.abs(v) / lim[0]).max(), np.sqrt(np.abs(a) / lim[1]).max(), np.cbrt(np.abs(j) / lim[2]).max())
+    assert math.isclose(worst, 1.0, rel_tol=1e-12)
