@@ -440,7 +440,7 @@ double mgref_traj_cost(const mgref_robot *rb, const mgref_params *pr,
   double *tf = (double *)malloc((size_t)(T + 1) * L * 12 * sizeof(double));
   double *sp = (double *)malloc((size_t)(T + 1) * M * 3 * sizeof(double));
   double *ee = (double *)malloc((size_t)(T + 1) * (E > 0 ? E : 1) * 7 * sizeof(double));
-  if (T > 1) mgref_fk(rb, q0, tf, sp, ee);
+  if (T > 1 || pr->speed) mgref_fk(rb, q0, tf, sp, ee);
   for (int t = 1; t <= T; ++t)
     mgref_fk(rb, q + (t - 1) * D, tf + t * L * 12, sp + t * M * 3, ee + t * E * 7);
 
@@ -454,16 +454,31 @@ double mgref_traj_cost(const mgref_robot *rb, const mgref_params *pr,
       c_bound += pr->w_bound * mgref_bound(qt[d], rb->q_lo[d], rb->q_hi[d], pr->eta2, &s);
       if (gt) gt[d] += pr->w_bound * s;
     }
-    /* world collision, Eq.(11) without the speed factor; summed over
-     * cuboids (Alg.10 accumulates every cuboid) and spheres */
+    /* world collision, Eq.(11); summed over cuboids (Alg.10 accumulates
+     * every cuboid) and spheres.  The speed factor (Sec. 'Speeding through
+     * obstacles'), when on, scales the sphere's collision cost by the
+     * sphere's speed from the central difference of its neighbouring
+     * positions, |c(t+1) - c(t-1)| / (2 dt), on the padded trajectory (the
+     * start before waypoint 1, waypoint T repeated after it).  Reading: the
+     * gradient holds the speed fixed and acts through the collision distance
+     * at c(t) only, as the swept surrogate does. */
     for (int m = 0; m < M; ++m) {
       const double *c = sp + (t * M + m) * 3;
       double r = rb->sphere[m * 4 + 3];
       const double *prev = (pr->swept && T > 1) ? sp + ((t - 1) * M + m) * 3 : NULL;
       const double *next = (pr->swept && T > 1 && t < T) ? sp + ((t + 1) * M + m) * 3 : NULL;
       double gc[3] = {0, 0, 0};
+      double cm = 0.0;
       for (int k = 0; k < n_box; ++k)
-        c_coll += sphere_box(pr, box_pose + k * 7, box_dims + k * 3, c, r, prev, next, gc, &mc);
+        cm += sphere_box(pr, box_pose + k * 7, box_dims + k * 3, c, r, prev, next, gc, &mc);
+      if (pr->speed) {
+        const double *cp = sp + ((t - 1) * M + m) * 3, *cn = t < T ? sp + ((t + 1) * M + m) * 3 : c;
+        double u[3] = {cn[0] - cp[0], cn[1] - cp[1], cn[2] - cp[2]};
+        const double speed = sqrt(dot3(u, u)) / (2.0 * pr->dt);
+        cm *= speed;
+        for (int i = 0; i < 3; ++i) gc[i] *= speed;
+      }
+      c_coll += cm;
       if (gt && (gc[0] != 0 || gc[1] != 0 || gc[2] != 0)) {
         /* Tab.7 revolute-z: d c / d q_j = z_j x (c - o_j) for every joint on
          * the chain from the sphere's link to the base */

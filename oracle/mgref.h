@@ -46,6 +46,7 @@ typedef struct {
   double w_self;            /* self-collision weight beta_1, Eq.(9) */
   int n_self;               /* sphere pairs checked for self-collision (the set S of Eq.(9)) */
   const int *self_pairs;    /* [n_self][2] sphere indices, or NULL */
+  int speed;                /* 1: speed metric on the world collision term, Eq.(11) */
 } mgref_params;
 
 /* Forward kinematics of one configuration q[D] (Sec. 'Robot Kinematics', Alg.7, Tab.6).

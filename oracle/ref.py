@@ -30,6 +30,8 @@ DEFAULTS = dict(
     # Eq.(9) self-collision: weight 5000 like every soft constraint; the
     # checked sphere pairs are a robot property (none by default)
     w_self=5000.0, n_self=0,
+    # Eq.(11) speed metric, off unless asked for
+    speed=0,
 )
 # Line search constants (Reading: the Nocedal & Wright defaults).
 ETA1 = 1e-4
@@ -52,7 +54,7 @@ class _Params(C.Structure):
                 ("w_bound", C.c_double), ("eta2", C.c_double), ("w_coll", C.c_double),
                 ("eta", C.c_double), ("dt", C.c_double), ("vel_all", C.c_int),
                 ("swept", C.c_int), ("sweep_steps", C.c_int), ("w_self", C.c_double),
-                ("n_self", C.c_int), ("self_pairs", _ip)]
+                ("n_self", C.c_int), ("self_pairs", _ip), ("speed", C.c_int)]
 
 
 def lib():

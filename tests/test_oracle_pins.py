@@ -854,3 +854,55 @@ def test_retime_at_rest_and_retimed_trajectory_sits_on_its_limit(oracle_lib):
     v, a, j = ref.derivatives(q0, q, dt)
     worst = max((np.abs(v) / lim[0]).max(), np.sqrt(np.abs(a) / lim[1]).max(), np.cbrt(np.abs(j) / lim[2]).max())
     assert math.isclose(worst, 1.0, rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Speed metric (Eq.(11), Sec. 'Speeding through obstacles').  The one-link
+# robot turns its sphere (radius 0.05) on the unit circle by delta per
+# waypoint from angle 0 at the start.  A 4 cm cube sits 6 cm radially out and
+# 3 cm ahead of the sphere's position at waypoint k only (its edge at
+# distance sqrt(0.04^2 + 0.01^2) there, so the distance gradient has a
+# component along the motion; the other positions a chord of ~0.49 m away),
+# so the collision term lives at k alone.  The sphere's central-difference speed there is the chord between
+# its neighbours over 2 dt: 2 sin(delta) / (2 dt) inside the trajectory
+# (waypoint 1's left neighbour is the start) and 2 sin(delta / 2) / (2 dt)
+# at T, whose right neighbour is itself.
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_speed_metric_scales_the_collision_term(oracle_lib, k):
+    robot = one_link_robot()
+    delta, dt, T = 0.5, 0.1, 3
+    th = k * delta
+    cx = 1.06 * math.cos(th) - 0.03 * math.sin(th)
+    cy = 1.06 * math.sin(th) + 0.03 * math.cos(th)
+    cube = (np.array([[cx, cy, 0.0, math.cos(th / 2), 0.0, 0.0, math.sin(th / 2)]]), np.array([[0.04, 0.04, 0.04]]))
+    q = delta * np.arange(1, T + 1, dtype=float)[:, None]
+    goal = np.array([[0, 0, 0, 1, 0, 0, 0]], dtype=float)
+    plain = ref.Ref(robot, dt=dt, **COLLISION_ONLY).traj_cost(cube, [0.0], goal, q)
+    fast = ref.Ref(robot, dt=dt, speed=1, **COLLISION_ONLY).traj_cost(cube, [0.0], goal, q)
+    factor = (math.sin(delta) if k < T else math.sin(delta / 2)) / dt
+    assert plain[0] > 0 and plain[2] == pytest.approx(math.hypot(0.04, 0.01) - 0.05, abs=1e-12)
+    assert fast[0] == pytest.approx(factor * plain[0], rel=1e-12)
+    # the gradient holds the speed fixed: the same factor, waypoint k only
+    assert np.count_nonzero(plain[1]) == 1 and plain[1][k - 1, 0] != 0
+    np.testing.assert_allclose(fast[1], factor * plain[1], rtol=1e-12, atol=0)
+    assert fast[2] == plain[2]
+
+
+def test_speed_metric_at_rest_and_far_away(oracle_lib):
+    """A sphere that does not move costs nothing in collision with the speed
+    metric on; away from every cuboid the metric changes nothing."""
+    robot = wl.make_arm(seed=0, n_spheres=20)
+    worlds = wl.make_worlds(5, [30])
+    boxes = worlds.world(0)
+    rng = np.random.default_rng(8)
+    q0 = rng.uniform(-1, 1, 7)
+    goal = np.array([[0.3, 0.2, 0.4, 1, 0, 0, 0]], dtype=float)
+    s = ref.Ref(robot, speed=1)
+    terms = lambda q: s.traj_cost(boxes, q0, goal, q)[3]
+    assert terms(np.tile(q0, (6, 1)))[2] == 0.0
+    far = (np.array([[50.0, 0, 0, 1, 0, 0, 0]]), np.array([[1.0, 1.0, 1.0]]))
+    q = q0 + np.cumsum(rng.normal(0, 0.1, (6, 7)), axis=0)
+    a = ref.Ref(robot).traj_cost(far, q0, goal, q)
+    b = s.traj_cost(far, q0, goal, q)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
