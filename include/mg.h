@@ -93,6 +93,11 @@ typedef struct {
   float success_pos;        /* success: position error <= (default 0.005 m) */
   float success_rot;        /* success: rotation angle <= (default 0.05 rad) */
   float w_self;             /* self-collision weight beta_1 of Eq.(9) (default 5000) */
+  int speed;                /* 1: speed metric of Eq.(11) (default 0): each sphere's world
+                               collision cost times its speed |c(t+1) - c(t-1)| / (2 dt) on
+                               the padded trajectory (start before waypoint 1, waypoint T
+                               after T); the gradient holds the speed fixed.  Evaluated by
+                               the wave-per-link layout only (robots of at most 15 links). */
 } mg_params;
 
 void mg_default_params(mg_params *out);
@@ -255,6 +260,43 @@ mg_status mg_batch_reserve_particles(mg_batch *batch, int n_particles);
 mg_status mg_particles(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
                        float *mean, float *var, int n_particles, int n_iters, const float *eps,
                        float beta, float k_mu, float k_sigma, float *costs_out, void *stream);
+
+/* Retiming (Alg.4 retime, appendix "Time-step Descretization and Temporal
+ * Weight Scaling"): for every seed, the waypoint spacing at which the
+ * seed's largest joint velocity, acceleration or jerk reaches its limit.
+ * The five-point stencils at the context's dt (start padded with q_start,
+ * t = 0..T) give v, a, j; derivatives of order k scale as dt^-k, so the
+ * result is dt times the largest of |v| / vmax, sqrt(|a| / amax),
+ * cbrt(|j| / jmax) over waypoints and joints.
+ *   q_start DEVICE [P][D]; x DEVICE [rows][D]
+ *   vmax, amax, jmax HOST [D] per-joint limits (rad/s, rad/s^2, rad/s^3); a
+ *     limit <= 0 leaves its kind out; NaN is MG_ERR_ARG
+ *   dt_out DEVICE [seeds] (0 for a seed that never leaves its start).
+ * Capturable. */
+mg_status mg_retime(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *x,
+                    const float *vmax, const float *amax, const float *jmax, float *dt_out,
+                    void *stream);
+
+/* Time-step optimization (Alg.4): two solves with the spacing re-chosen in
+ * between.  (1) mg_solve for iters1 iterations at the context's dt with the
+ * jerk weight a9 set to 0; (2) dt_opt = the largest mg_retime of the
+ * problems' best seeds, at least dt_min (one spacing for the whole batch);
+ * (3) with rho = dt_opt / dt the derivative weights become a7 rho, a8 rho^4
+ * and a9 rho^6 (the paper's "scale weights by the new dt", read as keeping
+ * the cost of the same waypoints unchanged, since v, a, j scale as rho^-1,
+ * rho^-2, rho^-3), jerk back on; (4) mg_solve for iters2 iterations from the
+ * first pass's best iterates at dt_opt; (5) dt_f = the largest retime of the
+ * new best seeds.  The context's parameters are restored on return.
+ *   x DEVICE [rows][D] seeds in, best iterates out; best_cost, best_seed,
+ *   success as mg_solve (of the second pass); vmax, amax, jmax as mg_retime;
+ *   dt_out HOST [2] = {dt_opt, dt_f}.
+ * Not capturable (allocates two small buffers, reads the spacings on the
+ * host between the passes). */
+mg_status mg_solve_timestep(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
+                            float *x, int iters1, int iters2, int m, int K, const float *alpha,
+                            int mode, int graph_inner, int use_graph, const float *vmax,
+                            const float *amax, const float *jmax, float dt_min, float *best_cost,
+                            int *best_seed, int *success, float *dt_out, void *stream);
 
 /* Measurement hooks.  mg_set_timing(batch, 1) clears the batch's timing
  * record and from then on brackets every direct evaluation-kernel launch

@@ -25,7 +25,7 @@ EXPORTS = ("mg_default_params", "mg_create", "mg_destroy", "mg_set_params", "mg_
            "mg_cost_grad", "mg_lbfgs_step", "mg_linesearch", "mg_solve",
            "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
            "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose", "mg_set_self_collision",
-           "mg_last_error")
+           "mg_retime", "mg_solve_timestep", "mg_last_error")
 
 
 class RobotDesc(C.Structure):
@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("w_bound", C.c_float), ("eta2", C.c_float), ("w_coll", C.c_float),
                 ("eta", C.c_float), ("dt", C.c_float), ("vel_all", C.c_int), ("swept", C.c_int),
                 ("sweep_steps", C.c_int), ("ls_eta1", C.c_float), ("ls_eta_w", C.c_float),
-                ("success_pos", C.c_float), ("success_rot", C.c_float), ("w_self", C.c_float)]
+                ("success_pos", C.c_float), ("success_rot", C.c_float), ("w_self", C.c_float), ("speed", C.c_int)]
 
 
 class MgError(RuntimeError):
@@ -91,13 +91,17 @@ def lib():
     L.mg_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _fp, C.c_int,
                               C.POINTER(C.c_int), _vp]
     L.mg_eval_time.argtypes = [_vp, C.POINTER(C.c_float), C.POINTER(C.c_int)]
+    L.mg_retime.argtypes = [_vp, _vp, _vp, _vp, _fp, _fp, _fp, _vp, _vp]
+    L.mg_solve_timestep.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, _fp,
+                                    C.c_int, C.c_int, C.c_int, _fp, _fp, _fp, C.c_float, _vp, _vp, _vp,
+                                    _fp, _vp]
     L.mg_last_error.argtypes = []
     L.mg_last_error.restype = C.c_char_p
     for name in ("mg_create", "mg_set_params", "mg_set_worlds", "mg_batch_create", "mg_cost_grad",
                  "mg_lbfgs_step", "mg_linesearch", "mg_solve", "mg_batch_seeds", "mg_batch_rows",
                  "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
                  "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose",
-                 "mg_set_self_collision"):
+                 "mg_set_self_collision", "mg_retime", "mg_solve_timestep"):
         getattr(L, name).restype = C.c_int
     _LIB = L
     return L

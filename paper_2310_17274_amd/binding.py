@@ -199,6 +199,35 @@ class Context:
                                   int(bool(use_graph)), _ptr(bc), _ptr(bs), _ptr(ok), _stream()))
         return x, bc, bs, ok
 
+    def _limits(self, vmax, amax, jmax):
+        D = self.robot.dof
+        return tuple((C.c_float * D)(*np.broadcast_to(np.asarray(z, dtype=np.float32), (D,)).tolist())
+                     for z in (vmax, amax, jmax))
+
+    def mg_retime(self, b: Batch, q_start, x, vmax, amax, jmax, out=None):
+        """Per-seed spacing [seeds] at which x's largest velocity,
+        acceleration or jerk meets its limit (Alg.4 retime)."""
+        lim = self._limits(vmax, amax, jmax)
+        out = torch.empty(b.n_seeds, dtype=torch.float32, device=self.device) if out is None else out
+        check(_lib.lib().mg_retime(self.handle, b.handle, _ptr(q_start), _ptr(x), *lim, _ptr(out), _stream()))
+        return out
+
+    def mg_solve_timestep(self, b: Batch, q_start, goal, x, iters1, iters2, m, alpha, vmax, amax, jmax,
+                          dt_min=1e-3, mode=1, graph_inner=25, use_graph=True):
+        """Two-pass time-step optimization (Alg.4) in place on x; returns
+        (x, best_cost, best_seed, success, (dt_opt, dt_f))."""
+        al = (C.c_float * len(alpha))(*alpha)
+        lim = self._limits(vmax, amax, jmax)
+        bc = torch.empty(b.n_seeds, dtype=torch.float32, device=self.device)
+        bs = torch.empty(b.P, dtype=torch.int32, device=self.device)
+        ok = torch.empty(b.P, dtype=torch.int32, device=self.device)
+        dt = (C.c_float * 2)()
+        check(_lib.lib().mg_solve_timestep(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(x),
+                                           int(iters1), int(iters2), int(m), len(alpha), al, int(mode),
+                                           int(graph_inner), int(bool(use_graph)), *lim, float(dt_min),
+                                           _ptr(bc), _ptr(bs), _ptr(ok), dt, _stream()))
+        return x, bc, bs, ok, (dt[0], dt[1])
+
     def mg_set_self_collision(self, pairs):
         """Sphere pairs [n, 2] checked for self-collision (Eq.(9)); empty turns it off."""
         pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -307,6 +308,8 @@ bool wl_halves_possible(const mg_ctx* c) {
          mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, c->n_self > 0, 2, c->maxs, mg::kWave) <= c->lds_max;
 }
 bool wl_possible(const mg_ctx* c) { return wl_possible(c, c->n_self > 0); }
+// terms only the wave-per-link layout evaluates: self-collision, the speed metric
+bool needs_wl(const mg_ctx* c) { return c->n_self > 0 || c->params.speed; }
 // two slot groups per wave (32 evaluations per workgroup): no
 // self-collision, at least four sphere slots per link
 bool wl_groups_possible(const mg_ctx* c) {
@@ -318,7 +321,7 @@ bool wl_groups_possible(const mg_ctx* c) {
 bool use_wl(const mg_batch* b, int K) {
   const mg_ctx* c = b->ctx;
   if (!wl_possible(c) || K > b->K_max) return false;
-  if (c->n_self > 0) return true;     // self-collision lives in this layout only
+  if (needs_wl(c)) return true;     // self-collision and the speed metric live in this layout only
   if (b->layout >= 0) return b->layout == 1;
   const char* env = getenv("MG_EVAL_LAYOUT");
   if (env) return atoi(env) == 1;
@@ -333,7 +336,7 @@ mg::Params to_dev(const mg_params& p) {
   d.vel_all = p.vel_all; d.swept = p.swept; d.sweep_steps = p.sweep_steps;
   d.ls_eta1 = p.ls_eta1; d.ls_eta_w = p.ls_eta_w;
   d.success_pos = p.success_pos; d.success_rot = p.success_rot;
-  d.w_self = p.w_self; d.n_self = 0;
+  d.w_self = p.w_self; d.n_self = 0; d.speed = p.speed;
   return d;
 }
 
@@ -343,6 +346,7 @@ mg_status check_params(const mg_params* p) {
   if (!(p->eta >= 0) || !(p->eta2 > 0)) return fail(MG_ERR_ARG, "eta must be >= 0 and eta2 > 0");
   if (p->swept && (p->sweep_steps < 0 || p->sweep_steps > 64))
     return fail(MG_ERR_ARG, "sweep_steps must be in [0, 64] (got %d)", p->sweep_steps);
+  if (p->speed != 0 && p->speed != 1) return fail(MG_ERR_ARG, "speed must be 0 or 1");
   return MG_OK;
 }
 
@@ -479,8 +483,8 @@ hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool gr
 mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
                        const float* x, const float* d, int K, const float* alpha, bool grad,
                        float* grad_out, float* pe_out, hipStream_t s) {
-  if (c->n_self > 0 && !use_wl(b, K))
-    return fail(MG_ERR_UNSUPPORTED, "self-collision needs the wave-per-link layout (at most 15 links)");
+  if (needs_wl(c) && !use_wl(b, K))
+    return fail(MG_ERR_UNSUPPORTED, "self-collision and the speed metric need the wave-per-link layout (at most 15 links)");
   const int hi = pick_slices(b, (long)b->rows * K);
   mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, x, d, K, alpha);
   if (grad_out) a.grad_e = grad_out;
@@ -672,6 +676,8 @@ mg_status mg_set_params(mg_ctx* c, const mg_params* params) {
   if (!c) return fail(MG_ERR_ARG, "null context");
   mg_status st = check_params(params);
   if (st != MG_OK) return st;
+  if (params->speed && !wl_possible(c))
+    return fail(MG_ERR_UNSUPPORTED, "the speed metric needs the wave-per-link layout (at most 15 links)");
   c->params = to_dev(*params);
   return MG_OK;
 }
@@ -865,8 +871,8 @@ mg_status mg_time_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
   if ((st = check_K_alpha(b, K, alpha)) != MG_OK) return st;
   if (!q_start || !goal || !x || !dir || !mean_us) return fail(MG_ERR_ARG, "null argument");
   if (launches < 1) return fail(MG_ERR_ARG, "launches must be >= 1");
-  if (c->n_self > 0 && !use_wl(b, K))
-    return fail(MG_ERR_UNSUPPORTED, "self-collision needs the wave-per-link layout (at most 15 links)");
+  if (needs_wl(c) && !use_wl(b, K))
+    return fail(MG_ERR_UNSUPPORTED, "self-collision and the speed metric need the wave-per-link layout (at most 15 links)");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int hi = pick_slices(b, (long)b->rows * K);
   const mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, x, dir, K, alpha);
@@ -937,7 +943,7 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
   // workgroup slices}.
   struct Opt { int layout, hi, halves, wls, groups; };
   std::vector<Opt> opts;
-  if (c->n_self == 0)
+  if (!needs_wl(c))
     for (int hi = 0; hi < kNumSlices; ++hi) opts.push_back({0, hi, 0, 0, 1});
   if (wl_groups_possible(c)) opts.push_back({1, -1, 1, 1, 2});
   if (wl_halves_possible(c)) opts.push_back({1, -1, 2, 1, 1});
@@ -1107,13 +1113,13 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
   // carried over: on the two-arm tree with 500 cuboids and swept collision
   // it picks wave per link, yet a particle round measured 13% faster lane
   // per link.
-  const bool wl = ((b->layout_set && b->layout == 1) || c->n_self > 0) && wl_possible(c) &&
+  const bool wl = ((b->layout_set && b->layout == 1) || needs_wl(c)) && wl_possible(c) &&
                   n_particles == b->pm_K && pm_rows <= mg::kWlStageRows &&
                   mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, c->n_self > 0, halves, c->maxs, E, pm_rows) <=
                       c->lds_max;
-  if (c->n_self > 0 && !wl)
+  if (needs_wl(c) && !wl)
     return fail(MG_ERR_UNSUPPORTED,
-                "self-collision in the particle stage needs the wave-per-link layout for %d particles "
+                "self-collision or the speed metric in the particle stage needs the wave-per-link layout for %d particles "
                 "(the last mg_batch_reserve_particles count, at least 2)", n_particles);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t draws = (size_t)n_particles * b->rows * c->D;
@@ -1248,6 +1254,105 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
     HIP_TRY(mg::launch_final(fa, s));
   }
   return MG_OK;
+}
+
+mg_status mg_retime(mg_ctx* c, mg_batch* b, const float* q_start, const float* x, const float* vmax,
+                    const float* amax, const float* jmax, float* dt_out, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if (!q_start || !x || !dt_out || !vmax || !amax || !jmax)
+    return fail(MG_ERR_ARG, "null q_start, x, dt_out or limits");
+  mg::RetimeArgs a;
+  memset(&a, 0, sizeof(a));
+  a.seeds = b->d_seed;
+  a.n_seeds = b->n_seeds;
+  a.dof = c->D;
+  a.dt = c->params.dt;
+  for (int d = 0; d < c->D; ++d) {
+    if (std::isnan(vmax[d]) || std::isnan(amax[d]) || std::isnan(jmax[d]))
+      return fail(MG_ERR_ARG, "NaN limit for joint %d", d);
+    a.inv_v[d] = vmax[d] > 0.0f ? 1.0f / vmax[d] : 0.0f;
+    a.inv_a[d] = amax[d] > 0.0f ? 1.0f / amax[d] : 0.0f;
+    a.inv_j[d] = jmax[d] > 0.0f ? 1.0f / jmax[d] : 0.0f;
+  }
+  a.q_start = q_start;
+  a.x = x;
+  a.dt_out = dt_out;
+  HIP_TRY(mg::launch_retime(a, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
+mg_status mg_solve_timestep(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* x,
+                            int iters1, int iters2, int m, int K, const float* alpha, int mode,
+                            int graph_inner, int use_graph, const float* vmax, const float* amax,
+                            const float* jmax, float dt_min, float* best_cost, int* best_seed,
+                            int* success, float* dt_out, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if (!best_cost || !dt_out || !vmax || !amax || !jmax) return fail(MG_ERR_ARG, "null best_cost, dt_out or limits");
+  if (iters1 < 0 || iters2 < 0) return fail(MG_ERR_ARG, "iters1 and iters2 must be >= 0");
+  if (!(dt_min > 0.0f)) return fail(MG_ERR_ARG, "dt_min must be > 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const mg::Params p0 = c->params;
+  float* d_dt = nullptr;
+  int* d_bs = nullptr;
+  if ((st = dev_alloc(&d_dt, b->n_seeds)) != MG_OK) return st;
+  if ((st = dev_alloc(&d_bs, b->P)) != MG_OK) {
+    dev_free(d_dt);
+    return st;
+  }
+  std::vector<float> h_dt(b->n_seeds);
+  std::vector<int> h_bs(b->P);
+  // the largest retimed spacing over the problems' best seeds
+  auto retime_best = [&](float* out) -> mg_status {
+    mg_status r = mg_retime(c, b, q_start, x, vmax, amax, jmax, d_dt, stream);
+    if (r != MG_OK) return r;
+    HIP_TRY(hipMemcpyAsync(h_dt.data(), d_dt, h_dt.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_bs.data(), d_bs, h_bs.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float dt = 0.0f;
+    int seed0 = 0;
+    for (int p = 0; p < b->P; ++p) {
+      dt = std::max(dt, h_dt[seed0 + h_bs[p]]);
+      seed0 += b->seeds[p];
+    }
+    *out = std::max(dt, dt_min);
+    return MG_OK;
+  };
+  auto run = [&]() -> mg_status {
+    // first pass at the context's spacing without the jerk term
+    c->params.a9 = 0.0f;
+    mg_status r = mg_solve(c, b, q_start, goal, x, iters1, m, K, alpha, mode, graph_inner, use_graph,
+                           best_cost, d_bs, nullptr, stream);
+    if (r != MG_OK) return r;
+    float dt_opt;
+    if ((r = retime_best(&dt_opt)) != MG_OK) return r;
+    // weights of the derivative terms rescaled so that the same waypoints
+    // cost what they cost at the first spacing (v, a, j scale as rho^-1,
+    // rho^-2, rho^-3), and the jerk term switched on
+    const float rho = dt_opt / p0.dt;
+    c->params = p0;
+    c->params.dt = dt_opt;
+    c->params.a7 = p0.a7 * rho;
+    const float rho2 = rho * rho, rho3 = rho2 * rho;
+    c->params.a8 = p0.a8 * (rho2 * rho2);
+    c->params.a9 = p0.a9 * (rho3 * rho3);
+    if ((r = mg_solve(c, b, q_start, goal, x, iters2, m, K, alpha, mode, graph_inner, use_graph, best_cost, d_bs,
+                      success, stream)) != MG_OK)
+      return r;
+    float dt_f;
+    if ((r = retime_best(&dt_f)) != MG_OK) return r;
+    if (best_seed) HIP_TRY(hipMemcpyAsync(best_seed, d_bs, b->P * sizeof(int), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    dt_out[0] = dt_opt;
+    dt_out[1] = dt_f;
+    return MG_OK;
+  };
+  st = run();
+  c->params = p0;
+  dev_free(d_dt);
+  dev_free(d_bs);
+  return st;
 }
 
 }  // extern "C"

@@ -134,6 +134,8 @@ __device__ __forceinline__ void chain_fk(const float4* rec, int depth, int row, 
 //
 // Swept collision (SW): the lane's link poses at the neighbouring waypoints
 // and its slots' spheres in the link frame (for the trace, Alg.11-12).
+// ws: each slot's collision weight (w_coll, times the sphere's speed under
+// the speed metric of Eq.(11)).
 struct SweepCtx {
   const float* Tp;
   const float* Tn;
@@ -146,7 +148,7 @@ template <int MAXS, bool SW>
 __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane, float cwx, float cwy,
                                            float cwz, float Rw, float bx, float by, float bz, float rl,
                                            const float* cx, const float* cy, const float* cz,
-                                           const float* rr, const float* rho, const SweepCtx& sw, float w,
+                                           const float* rr, const float* rho, const SweepCtx& sw, const float* ws,
                                            float eta, float inv_eta, float& cost, float& mc, float& Fx,
                                            float& Fy, float& Fz, float& Mx, float& My, float& Mz) {
   // lane j tests cuboid j of the tile against the wave's ball
@@ -219,10 +221,10 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
             const float px = ppx[u], py = ppy[u], pz = ppz[u];
             float gx = 0.0f, gy = 0.0f, gz = 0.0f;
             const float sdf = near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y,
-                                        fabsf(pz) - Hh.z, rr[s], w, eta, inv_eta, cost, mc, gx, gy, gz);
+                                        fabsf(pz) - Hh.z, rr[s], ws[s], eta, inv_eta, cost, mc, gx, gy, gz);
             if (SW && sw.on)
               sweep_pair_ls(sw.sl[s], sw.steps, sw.Tp, sw.Tn, sw.has_next, cx[s], cy[s], cz[s], A0, A1, A2,
-                            Hh, px, py, pz, sdf, rr[s], w, eta, inv_eta, cost, gx, gy, gz);
+                            Hh, px, py, pz, sdf, rr[s], ws[s], eta, inv_eta, cost, gx, gy, gz);
             Fx += gx; Fy += gy; Fz += gz;
             Mx += cy[s] * gz - cz[s] * gy;
             My += cz[s] * gx - cx[s] * gz;
@@ -420,9 +422,17 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   float wx = 0.0f, wy = 0.0f, wz = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
   // swept collision: the link's poses at the neighbouring waypoints (the
   // start before waypoint 1; one waypoint alone has no segments)
+  // SW also carries the speed metric (Eq.(11)): each sphere's collision
+  // weight times |c(t+1) - c(t-1)| / (2 dt), the start before waypoint 1 and
+  // waypoint T after T; the gradient holds the speed fixed
   float Tp[SW ? 12 : 1], Tn[SW ? 12 : 1];
-  const bool sweep = SW && pb.T > 1;
-  const bool has_next = sweep && t + 1 < pb.T;
+  const bool sweep = SW && a.pr.swept && pb.T > 1;
+  const bool spd = SW && a.pr.speed;
+  const bool nxt = t + 1 < pb.T;
+  const bool has_next = sweep && nxt;
+  float ws[MAXS];
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) ws[s] = a.pr.w_coll;
   float ext = 0.0f;   // the largest half segment over this lane's slots
   if (link_w) {
     // With CAND and GRAD the pass also forms the link's velocity under the
@@ -487,9 +497,9 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     };
     link_fk(qval, T, twist, true);
     if constexpr (SW) {
-      if (sweep) {
+      if (sweep || spd) {
         auto qprev = [&](int r, int j) -> float { return t >= 1 ? qval(r - 1, j) : s_lim[2 * D + j]; };
-        auto qnext = [&](int r, int j) -> float { return has_next ? qval(r + 1, j) : qval(r, j); };
+        auto qnext = [&](int r, int j) -> float { return nxt ? qval(r + 1, j) : qval(r, j); };
         link_fk(qprev, Tp, none, false);
         link_fk(qnext, Tn, none, false);
       }
@@ -508,6 +518,12 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
       rr[s] = used ? ls.w : 0.0f;
       rho[s] = rr[s] + eta;
       if constexpr (SW) {
+        if (spd && used) {
+          const float ux = (Tn[0] - Tp[0]) * ls.x + (Tn[1] - Tp[1]) * ls.y + (Tn[2] - Tp[2]) * ls.z + (Tn[3] - Tp[3]);
+          const float uy = (Tn[4] - Tp[4]) * ls.x + (Tn[5] - Tp[5]) * ls.y + (Tn[6] - Tp[6]) * ls.z + (Tn[7] - Tp[7]);
+          const float uz = (Tn[8] - Tp[8]) * ls.x + (Tn[9] - Tp[9]) * ls.y + (Tn[10] - Tp[10]) * ls.z + (Tn[11] - Tp[11]);
+          ws[s] = a.pr.w_coll * sqrtf(ux * ux + uy * uy + uz * uz) * (0.5f / a.pr.dt);
+        }
         // every trace sample lies within half a segment of the centre and the
         // distance is 1-Lipschitz, so r + eta + L/2 bounds the cull
         if (sweep && used) {
@@ -613,7 +629,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
 
   // ---- world collision, a staged tile of cuboids at a time; the next
   //      tile is read into registers while this one is tested ----
-  const float w = a.pr.w_coll, eta = a.pr.eta, inv_eta = 1.0f / fmaxf(eta, 1e-30f);
+  const float eta = a.pr.eta, inv_eta = 1.0f / fmaxf(eta, 1e-30f);
   float cwx = 0.0f, cwy = 0.0f, cwz = 0.0f, Rw = 0.0f, bxl = 0.0f, byl = 0.0f, bzl = 0.0f, rlb = 0.0f;
   // (wave-uniform: the wave has a sphere in some slot group; a lane whose
   // group has none tests unused slots, which never pass)
@@ -654,7 +670,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     const float4 u1 = i1 < 4 * nn ? nsrc[i1] : float4{};
     if (wave_sph)
       world_tile<MAXS, SW>(s_box + buf * kWlBoxTile * 4, nb, lane, cwx, cwy, cwz, Rw, bxl, byl, bzl, rlb, cx, cy,
-                           cz, rr, rho, swc, w, eta, inv_eta, cost, mc, Fx, Fy, Fz, Mx, My, Mz);
+                           cz, rr, rho, swc, ws, eta, inv_eta, cost, mc, Fx, Fy, Fz, Mx, My, Mz);
     if (nn <= 0) break;
     float4* nxt = s_box + (buf ^ 1) * kWlBoxTile * 4;
     if (i0 < 4 * nn) nxt[i0] = u0;
@@ -840,13 +856,14 @@ hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand
                                   a.wl.maxs, kWave / G, pm ? a.wl.pm_rows : 0);
   if (lds > kWlLdsMax) return hipErrorInvalidValue;
   const dim3 grid(grid_x, slices), block(waves * kWave);
-  if (a.pr.swept && waves <= 8) {
+  // (the swept kernels also carry the speed metric)
+  if ((a.pr.swept || a.pr.speed) && waves <= 8) {
     if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, true>, grid, block, lds, s, a);
     if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, true>, grid, block, lds, s, a);
     if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, true>, grid, block, lds, s, a);
     return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G, true>, grid, block, lds, s, a);
   }
-  if (a.pr.swept) {
+  if (a.pr.swept || a.pr.speed) {
     if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G, true>, grid, block, lds, s, a);
     if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G, true>, grid, block, lds, s, a);
     if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G, true>, grid, block, lds, s, a);

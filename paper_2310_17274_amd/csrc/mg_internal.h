@@ -34,6 +34,7 @@ struct Params {
   float success_pos, success_rot;
   float w_self;
   int n_self;              // self-collision pairs (wave-per-link layout only)
+  int speed;               // speed metric (wave-per-link layout only)
 };
 
 // One motion problem of a batch.  Rows are waypoints: seed s of problem p
@@ -266,6 +267,20 @@ struct ParticleArgs {
   float* costs_out;        // [n_seeds][N] or null
 };
 
+// Retiming (Alg.4) of every seed: the spacing at which the seed's largest
+// velocity, acceleration or jerk ratio to its limit reaches 1.
+struct RetimeArgs {
+  const SeedInfo* seeds;
+  int n_seeds, dof;
+  float dt;                // the spacing the trajectories are read at
+  float inv_v[kMaxDof];    // 1 / limit per joint; 0 leaves the kind out
+  float inv_a[kMaxDof];
+  float inv_j[kMaxDof];
+  const float* q_start;    // [P][D]
+  const float* x;          // [rows][D]
+  float* dt_out;           // [n_seeds]
+};
+
 // End-effector poses of every row (forward kinematics only).
 struct EePoseArgs {
   int rows, dof, n_ee;
@@ -300,6 +315,7 @@ hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, 
 hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s);
 
 hipError_t launch_particle_update(const ParticleArgs& a, hipStream_t s);
+hipError_t launch_retime(const RetimeArgs& a, hipStream_t s);
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);
 hipError_t launch_ee_pose(const EePoseArgs& a, hipStream_t s);
 hipError_t launch_boxes(const float* pose, const float* dims, int n, Box* out, hipStream_t s);

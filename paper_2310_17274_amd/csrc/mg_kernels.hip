@@ -10,6 +10,7 @@
 // lbfgs_kernel     two-loop L-BFGS direction, one wavefront per seed.
 // particle_update_kernel  particle-stage weights, mean and variance update.
 // final_kernel     per-problem best seed and success verdict.
+// retime_kernel    per-seed spacing that puts the trajectory on its limits.
 #include "mg_device.h"
 #include "mg_eval.h"
 
@@ -474,6 +475,41 @@ __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const
 
 // --------------------------------------------------------------------------
 // Per problem: best seed (lowest index on ties) and success verdict.
+// --------------------------------------------------------------------------
+// Retiming (Alg.4), one wave per seed.  Read at spacing h, the five-point
+// stencils of the padded trajectory (start copied below t = 1, the last
+// waypoint above T) give v, a, j at t = 0..T; derivatives of order k scale
+// as h^-k, so the spacing that puts each on its limit is h |v| / vmax,
+// h sqrt(|a| / amax), h cbrt(|j| / jmax), and the seed's result is the
+// largest over waypoints and joints (the first limit met as h shrinks).
+__global__ __launch_bounds__(kWave) void retime_kernel(const RetimeArgs a) {
+  const int seed = blockIdx.x, lane = threadIdx.x;
+  const SeedInfo si = a.seeds[seed];
+  const int D = a.dof, T = si.T;
+  const float* q0 = a.q_start + (size_t)si.prob * D;
+  const float* q = a.x + (size_t)si.row0 * D;
+  auto X = [&](int tau, int d) { return tau <= 0 ? q0[d] : q[(size_t)(min(tau, T) - 1) * D + d]; };
+  const float h = a.dt;
+  const float kv = 1.0f / (12.0f * h), ka = 1.0f / (12.0f * h * h), kj = 1.0f / (2.0f * h * h * h);
+  float r = 0.0f;
+  for (int i = lane; i < (T + 1) * D; i += kWave) {
+    const int tau = i / D, d = i - tau * D;
+    // offsets from the centre value (the stencil weights sum to zero for
+    // a, so it drops out): exactly zero where the trajectory rests
+    const float x0 = X(tau, d);
+    const float m2 = X(tau - 2, d) - x0, m1 = X(tau - 1, d) - x0, p1 = X(tau + 1, d) - x0, p2 = X(tau + 2, d) - x0;
+    const float v = ((m2 - p2) + 8.0f * (p1 - m1)) * kv;
+    const float ac = (16.0f * (m1 + p1) - (m2 + p2)) * ka;
+    const float jk = ((p2 - m2) + 2.0f * (m1 - p1)) * kj;
+    r = fmaxf(r, fabsf(v) * a.inv_v[d]);
+    r = fmaxf(r, sqrtf(fabsf(ac) * a.inv_a[d]));
+    r = fmaxf(r, cbrtf(fabsf(jk) * a.inv_j[d]));
+  }
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) r = fmaxf(r, __shfl_xor(r, o, kWave));
+  if (lane == 0) a.dt_out[seed] = h * r;
+}
+
 __global__ __launch_bounds__(kBlock) void final_kernel(const FinalArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.P) return;
@@ -566,6 +602,7 @@ int blocks_for(size_t n) {
 }  // namespace
 
 hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s) {
+  if (a.pr.speed) return hipErrorInvalidValue;   // evaluated by the wave-per-link layout only
   const int L = a.ln.lpe, S = a.ln.maxs;
   if (L == 8 && S == 4) return launch_eval_l8s4(a, grid_x, cand, grad, s);
   if (L == 8 && S == 8) return launch_eval_l8s8(a, grid_x, cand, grad, s);
@@ -650,6 +687,13 @@ hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s) {
 hipError_t launch_particle_update(const ParticleArgs& a, hipStream_t s) {
   if (a.N < 1 || a.N > kMaxParticles) return hipErrorInvalidValue;
   particle_update_kernel<<<a.n_seeds, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_retime(const RetimeArgs& a, hipStream_t s) {
+  if (a.n_seeds == 0) return hipSuccess;
+  if (a.dof < 1 || a.dof > kMaxDof || !(a.dt > 0.0f)) return hipErrorInvalidValue;
+  retime_kernel<<<a.n_seeds, kWave, 0, s>>>(a);
   return hipGetLastError();
 }
 
