@@ -7,6 +7,7 @@ reference's plain double arrays and calls ``libmgref.so``.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -296,3 +297,48 @@ def ls_select(alpha, c0, g0d, c, gd, mode, eta1=ETA1, eta_w=ETA_W):
     return lib().mgref_ls_select(len(al), _d(al)[1], C.c_double(c0), C.c_double(g0d),
                                  _d(c)[1], _d(gd)[1], int(mode), C.c_double(eta1),
                                  C.c_double(eta_w))
+
+
+# ---------------------------------------------------------------------------
+# Motion generation around the solver (Sec. 'Global Motion Generation'
+# overview, App. 'Evaluating Optimized Trajectories').  Plain definitions.
+
+def max_jerk(q0, q, dt):
+    """Largest |jerk| over t = 0..T and the joints at spacing dt."""
+    return float(np.abs(derivatives(q0, q, dt)[2]).max())
+
+
+def ik_rank(q, q0, pos_err, rot_err, clear, cost, pos_tol, rot_tol, w_dist):
+    """IK seeds of one problem: the valid ones (within the success
+    tolerances and collision free) in increasing pos_err + rot_err +
+    w_dist |q - q0|, ties to the lower index.  With none valid, every seed
+    in increasing cost.  Returns (order, number valid)."""
+    S = len(pos_err)
+    valid = [pos_err[s] <= pos_tol and rot_err[s] <= rot_tol and clear[s] >= 0 for s in range(S)]
+    if any(valid):
+        key = {s: pos_err[s] + rot_err[s] + w_dist * float(np.linalg.norm(np.asarray(q[s]) - np.asarray(q0)))
+               for s in range(S) if valid[s]}
+    else:
+        key = {s: cost[s] for s in range(S)}
+    order = sorted(key, key=lambda s: (key[s], s))
+    return order, sum(valid)
+
+
+def linear_seeds(q0, q_goal, T):
+    """Waypoints t = 1..T on the line from q0 to q_goal: q0 + t/T (q_goal - q0)."""
+    q0, q_goal = np.asarray(q0, dtype=np.float64), np.asarray(q_goal, dtype=np.float64)
+    return np.array([q0 + (t / T) * (q_goal - q0) for t in range(1, T + 1)])
+
+
+def traj_select(T, pos_err, rot_err, clear, cost, jerk, dt, pos_tol, rot_tol, w_jerk, w_time):
+    """Trajectory seeds of one problem: among the valid ones (goal reached
+    within the tolerances, collision free), the lowest pos_err + rot_err +
+    w_jerk jerk + w_time (T - 1) dt, ties to the lower index; with none
+    valid, the lowest cost.  Returns (seed, valid)."""
+    S = len(pos_err)
+    valid = [pos_err[s] <= pos_tol and rot_err[s] <= rot_tol and clear[s] >= 0 for s in range(S)]
+    if any(valid):
+        score = [pos_err[s] + rot_err[s] + w_jerk * jerk[s] + w_time * (T - 1) * dt[s] if valid[s] else math.inf
+                 for s in range(S)]
+        return int(np.argmin(score)), True
+    return int(np.argmin(cost)), False

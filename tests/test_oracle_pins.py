@@ -906,3 +906,56 @@ def test_speed_metric_at_rest_and_far_away(oracle_lib):
     a = ref.Ref(robot).traj_cost(far, q0, goal, q)
     b = s.traj_cost(far, q0, goal, q)
     assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------------------
+# Motion generation around the solver: seed ranking, linear seeds, selection
+# (App. 'Evaluating Optimized Trajectories'), against hand-worked tables.
+
+def test_max_jerk_ramp_closed_form(oracle_lib):
+    """The ramp's largest jerk is c / (2 dt^3) (worked out above); read at
+    its jerk-retimed spacing it equals the jerk limit."""
+    T, c = 12, 0.3
+    q = _ramp(c, T)
+    assert math.isclose(ref.max_jerk([0.0], q, 0.2), c / (2 * 0.2 ** 3), rel_tol=1e-12)
+    dt = ref.retime([0.0], q, 0.25, [0.0], [0.0], [40.0])
+    assert math.isclose(ref.max_jerk([0.0], q, dt), 40.0, rel_tol=1e-12)
+
+
+def test_ik_rank_table(oracle_lib):
+    """Five seeds, start at the origin.  Seed 1 misses the position
+    tolerance, seed 3 collides; the valid seeds 0, 2, 4 score
+    0.001 + 0.01 + 0.1 * 2 = 0.211, 0.002 + 0.0 + 0.1 * 1 = 0.102 and
+    0.0 + 0.02 + 0.1 * 1 = 0.12."""
+    q = np.array([[2.0, 0.0], [0.1, 0.0], [0.0, 1.0], [0.0, 0.5], [-1.0, 0.0]])
+    pos = [0.001, 0.01, 0.002, 0.0, 0.0]
+    rot = [0.01, 0.0, 0.0, 0.0, 0.02]
+    clear = [0.01, 0.01, 0.0, -0.001, 0.02]
+    cost = [5.0, 1.0, 4.0, 2.0, 3.0]
+    order, nv = ref.ik_rank(q, [0.0, 0.0], pos, rot, clear, cost, 0.005, 0.05, 0.1)
+    assert nv == 3 and order == [2, 4, 0]
+    # equal scores go to the lower index
+    order, _ = ref.ik_rank(q[[2, 4]], [0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [0.0, 0.0], [1.0, 1.0], 0.005, 0.05, 0.1)
+    assert order == [0, 1]
+    # none valid: every seed by cost
+    order, nv = ref.ik_rank(q, [0.0, 0.0], [1.0] * 5, rot, clear, cost, 0.005, 0.05, 0.1)
+    assert nv == 0 and order == [1, 3, 4, 2, 0]
+
+
+def test_linear_seeds(oracle_lib):
+    x = ref.linear_seeds([1.0, -1.0], [3.0, 1.0], 4)
+    np.testing.assert_array_equal(x, [[1.5, -0.5], [2.0, 0.0], [2.5, 0.5], [3.0, 1.0]])
+
+
+def test_traj_select_table(oracle_lib):
+    """Four seeds, T = 32.  Seed 0 is invalid (rotation), seed 2 collides.
+    Valid: seed 1 scores 0.001 + 0.01 * 50 + 0.1 * 31 * 0.05 = 0.656, seed 3
+    0.0 + 0.01 * 20 + 0.1 * 31 * 0.1 = 0.51.  With the time weight 1 seed 1
+    wins (2.051 against 3.3)."""
+    pos, rot = [0.0, 0.001, 0.0, 0.0], [0.06, 0.0, 0.0, 0.0]
+    clear, cost = [0.1, 0.0, -0.01, 0.2], [1.0, 3.0, 0.5, 2.0]
+    jerk, dt = [10.0, 50.0, 1.0, 20.0], [0.01, 0.05, 0.01, 0.1]
+    assert ref.traj_select(32, pos, rot, clear, cost, jerk, dt, 0.005, 0.05, 0.01, 0.1) == (3, True)
+    assert ref.traj_select(32, pos, rot, clear, cost, jerk, dt, 0.005, 0.05, 0.01, 1.0) == (1, True)
+    # none valid: the lowest cost
+    assert ref.traj_select(32, [1.0] * 4, rot, clear, cost, jerk, dt, 0.005, 0.05, 0.01, 0.1) == (2, False)
