@@ -62,7 +62,7 @@ def main():
     ap.add_argument("--slices", type=int, choices=[0, 1, 2, 4], default=0,
                     help="with --layout: cuboid slices (0 automatic)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the uneven-batch and inverse-kinematics measurements")
+                    help="skip the uneven-batch, inverse-kinematics, large and motion-generation measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
@@ -191,6 +191,7 @@ def main():
         line["uneven"] = bench_uneven(args.warmup)
         line["ik"] = bench_ik(args.warmup)
         line["large"] = bench_large(args.warmup)
+        line["motion_gen"] = bench_motion_gen(args.warmup)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(robot, worlds, batch, alpha, iters, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -363,6 +364,60 @@ def bench_ik(warmup):
             "layout": layout,
             "note": "goals are end-effector poses of the clearest of 16 random configurations "
                     "U(-2.5,2.5)^7 each (reachable); success = 5 mm / 0.05 rad and collision free"}
+
+
+def bench_motion_gen(warmup):
+    """Motion generation (IK -> seeds -> two-pass trajectory optimization ->
+    choice) on the 7-DOF arm with 52 spheres among 40 oriented cuboids:
+    one problem alone, then 64 problems in one call.  IK 32 seeds x 100
+    iterations; trajectories 12 seeds x T=32, 100 + 100 iterations."""
+    import torch
+    from paper_2310_17274_amd import workloads as wl
+    from paper_2310_17274_amd.binding import Context
+    robot, worlds, batch, meta = wl.cfg_cost_adjoint()
+    robot, worlds = wl.robot_f32(robot), wl.worlds_f32(worlds)
+    dev = torch.device("cuda:0")
+    ctx = Context(robot)
+    ctx.mg_set_worlds(worlds)
+    alpha, D = wl.ALPHA_4, robot.dof
+    vmax, amax, jmax = [2.175] * 4 + [2.61] * 3, [15.0, 7.5, 10.0, 12.5, 15.0, 20.0, 20.0], \
+        [7500.0, 3750.0, 5000.0, 6250.0, 7500.0, 10000.0, 10000.0]
+    rng = np.random.default_rng(60)
+    out = {}
+    for P in (1, 64):
+        # reachable goals: end-effector poses of the clearest of 16 random
+        # configurations per problem (the library's own kinematics and cost)
+        cand = wl.goal_configs(robot, 61 + P, 16 * P)
+        qc = torch.as_tensor(cand, dtype=torch.float32, device=dev).contiguous()
+        bc = ctx.batch([cand.shape[0]], [1], [0], K_max=1, m_max=0)
+        q_start = torch.as_tensor(rng.uniform(-1, 1, (P, D)), dtype=torch.float32, device=dev).contiguous()
+        dummy_goal = ctx.mg_ee_pose(q_start[:1].contiguous()).reshape(1, -1).contiguous()
+        _, _, clear = ctx.mg_cost_grad(bc, q_start[:1].contiguous(), dummy_goal, qc, grad=False)
+        order = torch.argsort(clear, descending=True, stable=True)[:P]
+        goal = ctx.mg_ee_pose(qc[order].contiguous()).reshape(P, -1).contiguous()
+        ik = ctx.batch(np.full(P, 32), np.ones(P, int), np.zeros(P, int), K_max=4, m_max=4)
+        to = ctx.batch(np.full(P, 12), np.full(P, 32), np.zeros(P, int), K_max=4, m_max=4)
+        x_ik0 = torch.as_tensor(rng.uniform(-2.5, 2.5, (P * 32, D)), dtype=torch.float32, device=dev)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for rep in range(max(1, warmup) + 1):
+            x_ik = x_ik0.clone()
+            torch.cuda.synchronize()
+            ev0.record()
+            _, ik_ok, bs, ok, mt, dts = ctx.mg_motion_gen(ik, to, q_start, goal, x_ik, 100, 100, 100, 4, alpha,
+                                                          vmax, amax, jmax)
+            ev1.record()
+            torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        out[f"P{P}"] = {"ms_per_call": ms, "ms_per_problem": ms / P,
+                        "ik_found_fraction": ik_ok.float().mean().item(),
+                        "success_fraction": ok.float().mean().item(),
+                        "mean_motion_time_s": mt.mean().item(), "dt_opt": dts[0], "dt_final": dts[1]}
+    out["workload"] = ("7-DOF arm, 52 spheres, 40 oriented cuboids; IK 32 seeds x 100 iterations (K=4), "
+                       "12 linear seeds x T=32, 100 iterations at dt 0.25 without jerk, retime, 100 "
+                       "iterations at the retimed dt with rescaled weights, retime, choice")
+    out["note"] = ("goals are end-effector poses of the clearest of 16 random configurations; the "
+                   "straight-line seeds are not cleared of every cuboid in this budget")
+    return out
 
 
 def bench_large(warmup):

@@ -271,11 +271,13 @@ mg_status mg_particles(mg_ctx *ctx, mg_batch *batch, const float *q_start, const
  *   q_start DEVICE [P][D]; x DEVICE [rows][D]
  *   vmax, amax, jmax HOST [D] per-joint limits (rad/s, rad/s^2, rad/s^3); a
  *     limit <= 0 leaves its kind out; NaN is MG_ERR_ARG
- *   dt_out DEVICE [seeds] (0 for a seed that never leaves its start).
+ *   dt_out DEVICE [seeds] (0 for a seed that never leaves its start)
+ *   jerk_out DEVICE [seeds] or NULL: the seed's largest |jerk| read at its
+ *     retimed spacing (the selection's jerk metric; 0 at rest).
  * Capturable. */
 mg_status mg_retime(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *x,
                     const float *vmax, const float *amax, const float *jmax, float *dt_out,
-                    void *stream);
+                    float *jerk_out, void *stream);
 
 /* Time-step optimization (Alg.4): two solves with the spacing re-chosen in
  * between.  (1) mg_solve for iters1 iterations at the context's dt with the
@@ -297,6 +299,51 @@ mg_status mg_solve_timestep(mg_ctx *ctx, mg_batch *batch, const float *q_start, 
                             int mode, int graph_inner, int use_graph, const float *vmax,
                             const float *amax, const float *jmax, float dt_min, float *best_cost,
                             int *best_seed, int *success, float *dt_out, void *stream);
+
+/* Seeds for trajectory optimization from collision-free IK (the paper's
+ * global motion generation: IK, then seeds, then trajectory optimization;
+ * App. "Evaluating Optimized Trajectories" for the ranking).  The IK seeds
+ * x_ik are evaluated as given; per problem, those within success_pos /
+ * success_rot of the goal and collision free are ranked by
+ * pos_err + rot_err + w_dist |q - q_start| (the paper's weighted sum of pose
+ * error and distance to the current configuration), ties to the lower
+ * index; a problem with none ranks every seed by cost and reports
+ * ik_ok = 0.  Trajectory seed i of the problem is the line from q_start to
+ * the (i mod count)-th ranked solution: waypoint t = q_start + t/T (q - q_start).
+ *   ik_batch: horizon 1 for every problem, at most 1024 seeds each; to_batch:
+ *   the same problems (any seeds and horizons)
+ *   x_ik DEVICE [ik rows][D]; x_to DEVICE [to rows][D] out; ik_ok DEVICE [P] or NULL.
+ * Capturable. */
+mg_status mg_ik_seeds(mg_ctx *ctx, mg_batch *ik_batch, mg_batch *to_batch, const float *q_start,
+                      const float *goal, const float *x_ik, float w_dist, float *x_to, int *ik_ok,
+                      void *stream);
+
+/* Choice among the trajectory seeds of every problem (App. "Evaluating
+ * Optimized Trajectories": a blend of pose error, largest jerk and motion
+ * time).  The seeds x are evaluated; those that reach the goal within the
+ * success tolerances and are collision free score
+ *   pos_err + rot_err + w_jerk max|jerk| + w_time (T - 1) dt_s
+ * with dt_s the seed's retimed spacing (mg_retime) and max|jerk| read at it;
+ * the lowest wins (ties to the lower index).  A problem with no such seed
+ * takes its lowest-cost seed and success = 0.
+ *   best_seed DEVICE [P]; success, motion_time ((T - 1) dt_s of the chosen
+ *   seed) DEVICE [P] or NULL.  Capturable. */
+mg_status mg_traj_select(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
+                         const float *x, const float *vmax, const float *amax, const float *jmax,
+                         float w_jerk, float w_time, int *best_seed, int *success,
+                         float *motion_time, void *stream);
+
+/* Motion generation for every problem: mg_solve on ik_batch (iters_ik
+ * iterations from the seeds in x_ik), mg_ik_seeds into x_to,
+ * mg_solve_timestep on to_batch (iters1, iters2), mg_traj_select.
+ * Arguments as in those calls; x_ik and x_to hold the IK and trajectory
+ * iterates on return.  Not capturable (mg_solve_timestep). */
+mg_status mg_motion_gen(mg_ctx *ctx, mg_batch *ik_batch, mg_batch *to_batch, const float *q_start,
+                        const float *goal, float *x_ik, float *x_to, int iters_ik, int iters1,
+                        int iters2, int m, int K, const float *alpha, int mode, const float *vmax,
+                        const float *amax, const float *jmax, float dt_min, float w_dist,
+                        float w_jerk, float w_time, int *ik_ok, int *best_seed, int *success,
+                        float *motion_time, float *dt_out, void *stream);
 
 /* Measurement hooks.  mg_set_timing(batch, 1) clears the batch's timing
  * record and from then on brackets every direct evaluation-kernel launch

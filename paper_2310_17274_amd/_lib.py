@@ -25,7 +25,8 @@ EXPORTS = ("mg_default_params", "mg_create", "mg_destroy", "mg_set_params", "mg_
            "mg_cost_grad", "mg_lbfgs_step", "mg_linesearch", "mg_solve",
            "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
            "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose", "mg_set_self_collision",
-           "mg_retime", "mg_solve_timestep", "mg_last_error")
+           "mg_retime", "mg_solve_timestep", "mg_ik_seeds", "mg_traj_select", "mg_motion_gen",
+           "mg_last_error")
 
 
 class RobotDesc(C.Structure):
@@ -91,7 +92,13 @@ def lib():
     L.mg_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _fp, C.c_int,
                               C.POINTER(C.c_int), _vp]
     L.mg_eval_time.argtypes = [_vp, C.POINTER(C.c_float), C.POINTER(C.c_int)]
-    L.mg_retime.argtypes = [_vp, _vp, _vp, _vp, _fp, _fp, _fp, _vp, _vp]
+    L.mg_retime.argtypes = [_vp, _vp, _vp, _vp, _fp, _fp, _fp, _vp, _vp, _vp]
+    L.mg_ik_seeds.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp]
+    L.mg_traj_select.argtypes = [_vp, _vp, _vp, _vp, _vp, _fp, _fp, _fp, C.c_float, C.c_float, _vp, _vp, _vp,
+                                 _vp]
+    L.mg_motion_gen.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                _fp, C.c_int, _fp, _fp, _fp, C.c_float, C.c_float, C.c_float, C.c_float, _vp, _vp,
+                                _vp, _vp, _fp, _vp]
     L.mg_solve_timestep.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, _fp,
                                     C.c_int, C.c_int, C.c_int, _fp, _fp, _fp, C.c_float, _vp, _vp, _vp,
                                     _fp, _vp]
@@ -101,7 +108,8 @@ def lib():
                  "mg_lbfgs_step", "mg_linesearch", "mg_solve", "mg_batch_seeds", "mg_batch_rows",
                  "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
                  "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose",
-                 "mg_set_self_collision", "mg_retime", "mg_solve_timestep"):
+                 "mg_set_self_collision", "mg_retime", "mg_solve_timestep", "mg_ik_seeds",
+                 "mg_traj_select", "mg_motion_gen"):
         getattr(L, name).restype = C.c_int
     _LIB = L
     return L

@@ -204,13 +204,52 @@ class Context:
         return tuple((C.c_float * D)(*np.broadcast_to(np.asarray(z, dtype=np.float32), (D,)).tolist())
                      for z in (vmax, amax, jmax))
 
-    def mg_retime(self, b: Batch, q_start, x, vmax, amax, jmax, out=None):
+    def mg_retime(self, b: Batch, q_start, x, vmax, amax, jmax, out=None, jerk=False):
         """Per-seed spacing [seeds] at which x's largest velocity,
-        acceleration or jerk meets its limit (Alg.4 retime)."""
+        acceleration or jerk meets its limit (Alg.4 retime); with jerk=True
+        also the largest |jerk| [seeds] read at that spacing."""
         lim = self._limits(vmax, amax, jmax)
         out = torch.empty(b.n_seeds, dtype=torch.float32, device=self.device) if out is None else out
-        check(_lib.lib().mg_retime(self.handle, b.handle, _ptr(q_start), _ptr(x), *lim, _ptr(out), _stream()))
-        return out
+        jk = torch.empty(b.n_seeds, dtype=torch.float32, device=self.device) if jerk else None
+        check(_lib.lib().mg_retime(self.handle, b.handle, _ptr(q_start), _ptr(x), *lim, _ptr(out),
+                                   _ptr(jk) if jerk else None, _stream()))
+        return (out, jk) if jerk else out
+
+    def mg_ik_seeds(self, ik: Batch, to: Batch, q_start, goal, x_ik, w_dist=0.1):
+        """Trajectory seeds [to rows, D] on the lines to the ranked IK
+        solutions, and ik_ok [P]."""
+        x_to = torch.empty((to.rows, self.robot.dof), dtype=torch.float32, device=self.device)
+        ok = torch.empty(ik.P, dtype=torch.int32, device=self.device)
+        check(_lib.lib().mg_ik_seeds(self.handle, ik.handle, to.handle, _ptr(q_start), _ptr(goal), _ptr(x_ik),
+                                     float(w_dist), _ptr(x_to), _ptr(ok), _stream()))
+        return x_to, ok
+
+    def mg_traj_select(self, b: Batch, q_start, goal, x, vmax, amax, jmax, w_jerk=1e-3, w_time=1.0):
+        """(best_seed [P], success [P], motion_time [P]) among x's seeds."""
+        lim = self._limits(vmax, amax, jmax)
+        bs = torch.empty(b.P, dtype=torch.int32, device=self.device)
+        ok = torch.empty(b.P, dtype=torch.int32, device=self.device)
+        mt = torch.empty(b.P, dtype=torch.float32, device=self.device)
+        check(_lib.lib().mg_traj_select(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(x), *lim,
+                                        float(w_jerk), float(w_time), _ptr(bs), _ptr(ok), _ptr(mt), _stream()))
+        return bs, ok, mt
+
+    def mg_motion_gen(self, ik: Batch, to: Batch, q_start, goal, x_ik, iters_ik, iters1, iters2, m, alpha,
+                      vmax, amax, jmax, dt_min=1e-3, w_dist=0.1, w_jerk=1e-3, w_time=1.0, mode=1):
+        """IK, seeds, time-step optimization, selection.  x_ik is updated in
+        place; returns (x_to, ik_ok, best_seed, success, motion_time,
+        (dt_opt, dt_f))."""
+        al = (C.c_float * len(alpha))(*alpha)
+        lim = self._limits(vmax, amax, jmax)
+        x_to = torch.empty((to.rows, self.robot.dof), dtype=torch.float32, device=self.device)
+        ik_ok, bs, ok = (torch.empty(ik.P, dtype=torch.int32, device=self.device) for _ in range(3))
+        mt = torch.empty(ik.P, dtype=torch.float32, device=self.device)
+        dt = (C.c_float * 2)()
+        check(_lib.lib().mg_motion_gen(self.handle, ik.handle, to.handle, _ptr(q_start), _ptr(goal), _ptr(x_ik),
+                                       _ptr(x_to), int(iters_ik), int(iters1), int(iters2), int(m), len(alpha), al,
+                                       int(mode), *lim, float(dt_min), float(w_dist), float(w_jerk),
+                                       float(w_time), _ptr(ik_ok), _ptr(bs), _ptr(ok), _ptr(mt), dt, _stream()))
+        return x_to, ik_ok, bs, ok, mt, (dt[0], dt[1])
 
     def mg_solve_timestep(self, b: Batch, q_start, goal, x, iters1, iters2, m, alpha, vmax, amax, jmax,
                           dt_min=1e-3, mode=1, graph_inner=25, use_graph=True):

@@ -116,6 +116,7 @@ struct mg_batch {
   int uniform_T = 0;  // the horizon when every problem has the same one, else 0
   float *cost_e = nullptr, *gd_e = nullptr, *mc_e = nullptr, *grad_e = nullptr, *pe_e = nullptr;
   float *c_cur = nullptr, *g_cur = nullptr, *dir = nullptr, *best_c = nullptr, *best_x = nullptr;
+  float *sel_dt = nullptr, *sel_jerk = nullptr;   // per-seed retimed spacing and jerk (selection)
   int* first = nullptr;
   float *S = nullptr, *Y = nullptr, *x_prev = nullptr, *g_prev = nullptr, *rho = nullptr;
   int* meta = nullptr;
@@ -795,7 +796,8 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
       (st = dev_alloc(&b->first, n_seeds)) != MG_OK || (st = dev_alloc(&b->S, mm * RD)) != MG_OK ||
       (st = dev_alloc(&b->Y, mm * RD)) != MG_OK || (st = dev_alloc(&b->x_prev, RD)) != MG_OK ||
       (st = dev_alloc(&b->g_prev, RD)) != MG_OK || (st = dev_alloc(&b->rho, n_seeds * mm)) != MG_OK ||
-      (st = dev_alloc(&b->meta, 2 * n_seeds)) != MG_OK)
+      (st = dev_alloc(&b->meta, 2 * n_seeds)) != MG_OK || (st = dev_alloc(&b->sel_dt, n_seeds)) != MG_OK ||
+      (st = dev_alloc(&b->sel_jerk, n_seeds)) != MG_OK)
     return bail(st);
   // zero the history metadata so a first step without reset is well defined
   if (hipMemset(b->meta, 0, 2 * n_seeds * sizeof(int)) != hipSuccess ||
@@ -824,7 +826,7 @@ void mg_batch_destroy(mg_batch* b) {
   dev_free(b->cost_e); dev_free(b->gd_e); dev_free(b->mc_e); dev_free(b->grad_e); dev_free(b->pe_e);
   dev_free(b->c_cur); dev_free(b->g_cur); dev_free(b->dir); dev_free(b->best_c); dev_free(b->best_x);
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
-  dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost);
+  dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost); dev_free(b->sel_dt); dev_free(b->sel_jerk);
   dev_free(b->wl_part); dev_free(b->wl_count);
   delete b;
 }
@@ -1257,7 +1259,7 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
 }
 
 mg_status mg_retime(mg_ctx* c, mg_batch* b, const float* q_start, const float* x, const float* vmax,
-                    const float* amax, const float* jmax, float* dt_out, void* stream) {
+                    const float* amax, const float* jmax, float* dt_out, float* jerk_out, void* stream) {
   mg_status st = common_checks(c, b);
   if (st != MG_OK) return st;
   if (!q_start || !x || !dt_out || !vmax || !amax || !jmax)
@@ -1278,6 +1280,7 @@ mg_status mg_retime(mg_ctx* c, mg_batch* b, const float* q_start, const float* x
   a.q_start = q_start;
   a.x = x;
   a.dt_out = dt_out;
+  a.jerk_out = jerk_out;
   HIP_TRY(mg::launch_retime(a, static_cast<hipStream_t>(stream)));
   return MG_OK;
 }
@@ -1305,7 +1308,7 @@ mg_status mg_solve_timestep(mg_ctx* c, mg_batch* b, const float* q_start, const 
   std::vector<int> h_bs(b->P);
   // the largest retimed spacing over the problems' best seeds
   auto retime_best = [&](float* out) -> mg_status {
-    mg_status r = mg_retime(c, b, q_start, x, vmax, amax, jmax, d_dt, stream);
+    mg_status r = mg_retime(c, b, q_start, x, vmax, amax, jmax, d_dt, nullptr, stream);
     if (r != MG_OK) return r;
     HIP_TRY(hipMemcpyAsync(h_dt.data(), d_dt, h_dt.size() * sizeof(float), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h_bs.data(), d_bs, h_bs.size() * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1353,6 +1356,93 @@ mg_status mg_solve_timestep(mg_ctx* c, mg_batch* b, const float* q_start, const 
   dev_free(d_dt);
   dev_free(d_bs);
   return st;
+}
+
+mg_status mg_ik_seeds(mg_ctx* c, mg_batch* ik, mg_batch* to, const float* q_start, const float* goal,
+                      const float* x_ik, float w_dist, float* x_to, int* ik_ok, void* stream) {
+  mg_status st = common_checks(c, ik);
+  if (st != MG_OK || (st = common_checks(c, to)) != MG_OK) return st;
+  if (!q_start || !goal || !x_ik || !x_to) return fail(MG_ERR_ARG, "null q_start, goal, x_ik or x_to");
+  if (ik->P != to->P) return fail(MG_ERR_SHAPE, "the IK and trajectory batches hold %d and %d problems", ik->P, to->P);
+  for (int p = 0; p < ik->P; ++p) {
+    if (ik->horizon[p] != 1) return fail(MG_ERR_SHAPE, "IK problem %d has horizon %d (must be 1)", p, ik->horizon[p]);
+    if (ik->seeds[p] > mg::kMaxIkSeeds)
+      return fail(MG_ERR_SHAPE, "IK problem %d has %d seeds (at most %d)", p, ik->seeds[p], mg::kMaxIkSeeds);
+  }
+  if (!(w_dist >= 0.0f)) return fail(MG_ERR_ARG, "w_dist must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // pose error, clearance and cost of every IK seed as given
+  if ((st = enqueue_eval(c, ik, q_start, goal, x_ik, nullptr, 1, nullptr, false, nullptr, ik->pe_e, s)) != MG_OK)
+    return st;
+  mg::IkSeedArgs a;
+  memset(&a, 0, sizeof(a));
+  a.ik = ik->d_prob;
+  a.to = to->d_prob;
+  a.P = ik->P;
+  a.dof = c->D;
+  a.q_start = q_start;
+  a.x_ik = x_ik;
+  a.cost_e = ik->cost_e;
+  a.mc_e = ik->mc_e;
+  a.pe_e = ik->pe_e;
+  a.pos_tol = c->params.success_pos;
+  a.rot_tol = c->params.success_rot;
+  a.w_dist = w_dist;
+  a.x_to = x_to;
+  a.ik_ok = ik_ok;
+  HIP_TRY(mg::launch_ik_seeds(a, s));
+  return MG_OK;
+}
+
+mg_status mg_traj_select(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, const float* x,
+                         const float* vmax, const float* amax, const float* jmax, float w_jerk, float w_time,
+                         int* best_seed, int* success, float* motion_time, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if (!q_start || !goal || !x || !best_seed) return fail(MG_ERR_ARG, "null q_start, goal, x or best_seed");
+  if (!(w_jerk >= 0.0f) || !(w_time >= 0.0f)) return fail(MG_ERR_ARG, "w_jerk and w_time must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = enqueue_eval(c, b, q_start, goal, x, nullptr, 1, nullptr, false, nullptr, b->pe_e, s)) != MG_OK)
+    return st;
+  if ((st = mg_retime(c, b, q_start, x, vmax, amax, jmax, b->sel_dt, b->sel_jerk, stream)) != MG_OK) return st;
+  mg::TrajSelectArgs a;
+  memset(&a, 0, sizeof(a));
+  a.prob = b->d_prob;
+  a.P = b->P;
+  a.cost_e = b->cost_e;
+  a.mc_e = b->mc_e;
+  a.pe_e = b->pe_e;
+  a.dt_s = b->sel_dt;
+  a.jerk_s = b->sel_jerk;
+  a.pos_tol = c->params.success_pos;
+  a.rot_tol = c->params.success_rot;
+  a.w_jerk = w_jerk;
+  a.w_time = w_time;
+  a.best_seed = best_seed;
+  a.success = success;
+  a.motion_time = motion_time;
+  HIP_TRY(mg::launch_traj_select(a, s));
+  return MG_OK;
+}
+
+mg_status mg_motion_gen(mg_ctx* c, mg_batch* ik, mg_batch* to, const float* q_start, const float* goal,
+                        float* x_ik, float* x_to, int iters_ik, int iters1, int iters2, int m, int K,
+                        const float* alpha, int mode, const float* vmax, const float* amax, const float* jmax,
+                        float dt_min, float w_dist, float w_jerk, float w_time, int* ik_ok, int* best_seed,
+                        int* success, float* motion_time, float* dt_out, void* stream) {
+  mg_status st = common_checks(c, ik);
+  if (st != MG_OK || (st = common_checks(c, to)) != MG_OK) return st;
+  if (!dt_out || !best_seed) return fail(MG_ERR_ARG, "null dt_out or best_seed");
+  // collision-free IK, seeds on the lines to its solutions, trajectory
+  // optimization with the time-step passes, choice per problem
+  if ((st = mg_solve(c, ik, q_start, goal, x_ik, iters_ik, m, K, alpha, mode, 25, 1, ik->sel_dt, nullptr, nullptr,
+                     stream)) != MG_OK ||
+      (st = mg_ik_seeds(c, ik, to, q_start, goal, x_ik, w_dist, x_to, ik_ok, stream)) != MG_OK ||
+      (st = mg_solve_timestep(c, to, q_start, goal, x_to, iters1, iters2, m, K, alpha, mode, 25, 1, vmax, amax,
+                              jmax, dt_min, to->sel_dt, nullptr, nullptr, dt_out, stream)) != MG_OK)
+    return st;
+  return mg_traj_select(c, to, q_start, goal, x_to, vmax, amax, jmax, w_jerk, w_time, best_seed, success,
+                        motion_time, stream);
 }
 
 }  // extern "C"

@@ -262,8 +262,9 @@ __device__ __forceinline__ float groups_min(float v) {
 // workgroup holds E = 64 / G evaluations and lane g * E + e tests group g
 // of the link's sphere slots for evaluation e (G = 2: twice the workgroups
 // for the same batch, the chain run twice).
-// SW: swept collision (the chain also runs at the neighbouring waypoints).
-template <int MAXS, bool CAND, bool GRAD, int NT, int G, bool SW>
+// SW: the chain also runs at the neighbouring waypoints, for swept
+// collision and the speed metric; SP: the speed metric (Eq.(11)).
+template <int MAXS, bool CAND, bool GRAD, int NT, int G, bool SW, bool SP>
 __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   constexpr int E = kWave / G;
   extern __shared__ float s_mem[];
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   // waypoint T after T; the gradient holds the speed fixed
   float Tp[SW ? 12 : 1], Tn[SW ? 12 : 1];
   const bool sweep = SW && a.pr.swept && pb.T > 1;
-  const bool spd = SW && a.pr.speed;
+  const bool spd = SP && a.pr.speed;
   const bool nxt = t + 1 < pb.T;
   const bool has_next = sweep && nxt;
   float ws[MAXS];
@@ -838,6 +839,21 @@ hipError_t wl_launch(KF kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, 
   return hipGetLastError();
 }
 
+template <int MAXS, int G, bool SW, bool SP>
+hipError_t wl_pick(const EvalArgs& a, dim3 grid, dim3 block, size_t lds, int waves, bool cand, bool grad,
+                   hipStream_t s) {
+  if (waves <= 8) {
+    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, SW, SP>, grid, block, lds, s, a);
+    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, SW, SP>, grid, block, lds, s, a);
+    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, SW, SP>, grid, block, lds, s, a);
+    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G, SW, SP>, grid, block, lds, s, a);
+  }
+  if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G, SW, SP>, grid, block, lds, s, a);
+  if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G, SW, SP>, grid, block, lds, s, a);
+  if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G, SW, SP>, grid, block, lds, s, a);
+  return wl_launch(eval_wl_kernel<MAXS, true, false, 1024, G, SW, SP>, grid, block, lds, s, a);
+}
+
 template <int MAXS, int G>
 hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
   const int HS = a.wl.halves;
@@ -856,29 +872,11 @@ hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand
                                   a.wl.maxs, kWave / G, pm ? a.wl.pm_rows : 0);
   if (lds > kWlLdsMax) return hipErrorInvalidValue;
   const dim3 grid(grid_x, slices), block(waves * kWave);
-  // (the swept kernels also carry the speed metric)
-  if ((a.pr.swept || a.pr.speed) && waves <= 8) {
-    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, true>, grid, block, lds, s, a);
-    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, true>, grid, block, lds, s, a);
-    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, true>, grid, block, lds, s, a);
-    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G, true>, grid, block, lds, s, a);
-  }
-  if (a.pr.swept || a.pr.speed) {
-    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G, true>, grid, block, lds, s, a);
-    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G, true>, grid, block, lds, s, a);
-    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G, true>, grid, block, lds, s, a);
-    return wl_launch(eval_wl_kernel<MAXS, true, false, 1024, G, true>, grid, block, lds, s, a);
-  }
-  if (waves <= 8) {
-    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, false>, grid, block, lds, s, a);
-    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, false>, grid, block, lds, s, a);
-    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, false>, grid, block, lds, s, a);
-    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G, false>, grid, block, lds, s, a);
-  }
-  if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G, false>, grid, block, lds, s, a);
-  if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G, false>, grid, block, lds, s, a);
-  if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G, false>, grid, block, lds, s, a);
-  return wl_launch(eval_wl_kernel<MAXS, true, false, 1024, G, false>, grid, block, lds, s, a);
+  // SW: poses at the neighbouring waypoints (swept collision, the speed
+  // metric); SP: the speed metric
+  if (a.pr.speed) return wl_pick<MAXS, G, true, true>(a, grid, block, lds, waves, cand, grad, s);
+  if (a.pr.swept) return wl_pick<MAXS, G, true, false>(a, grid, block, lds, waves, cand, grad, s);
+  return wl_pick<MAXS, G, false, false>(a, grid, block, lds, waves, cand, grad, s);
 }
 
 template <int MAXS>

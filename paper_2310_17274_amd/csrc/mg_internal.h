@@ -279,6 +279,39 @@ struct RetimeArgs {
   const float* q_start;    // [P][D]
   const float* x;          // [rows][D]
   float* dt_out;           // [n_seeds]
+  float* jerk_out;         // [n_seeds] largest |jerk| at the retimed spacing, or null
+};
+
+// Motion generation: IK seeds of every problem ranked, trajectory seeds on
+// the line from the start to them (one workgroup per problem).
+constexpr int kMaxIkSeeds = 1024;
+struct IkSeedArgs {
+  const Problem* ik;       // [P] (T = 1: one row per seed)
+  const Problem* to;       // [P]
+  int P, dof;
+  const float* q_start;    // [P][D]
+  const float* x_ik;       // [ik rows][D]
+  const float* cost_e;     // [ik rows] cost of each IK seed
+  const float* mc_e;       // [ik rows] clearance
+  const float* pe_e;       // [ik rows][2] position / rotation error
+  float pos_tol, rot_tol, w_dist;
+  float* x_to;             // [to rows][D]
+  int* ik_ok;              // [P] or null
+};
+
+// Trajectory selection among the seeds of every problem (one thread each).
+struct TrajSelectArgs {
+  const Problem* prob;
+  int P;
+  const float* cost_e;     // [rows]
+  const float* mc_e;       // [rows]
+  const float* pe_e;       // [rows][2]
+  const float* dt_s;       // [seeds] retimed spacing
+  const float* jerk_s;     // [seeds] largest |jerk| at that spacing
+  float pos_tol, rot_tol, w_jerk, w_time;
+  int* best_seed;          // [P]
+  int* success;            // [P] or null
+  float* motion_time;      // [P] or null
 };
 
 // End-effector poses of every row (forward kinematics only).
@@ -316,6 +349,8 @@ hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s);
 
 hipError_t launch_particle_update(const ParticleArgs& a, hipStream_t s);
 hipError_t launch_retime(const RetimeArgs& a, hipStream_t s);
+hipError_t launch_ik_seeds(const IkSeedArgs& a, hipStream_t s);
+hipError_t launch_traj_select(const TrajSelectArgs& a, hipStream_t s);
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);
 hipError_t launch_ee_pose(const EePoseArgs& a, hipStream_t s);
 hipError_t launch_boxes(const float* pose, const float* dims, int n, Box* out, hipStream_t s);

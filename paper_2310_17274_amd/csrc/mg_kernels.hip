@@ -11,6 +11,8 @@
 // particle_update_kernel  particle-stage weights, mean and variance update.
 // final_kernel     per-problem best seed and success verdict.
 // retime_kernel    per-seed spacing that puts the trajectory on its limits.
+// ik_seed_kernel   IK seeds ranked per problem, linear trajectory seeds.
+// traj_select_kernel  per-problem choice among trajectory seeds.
 #include "mg_device.h"
 #include "mg_eval.h"
 
@@ -491,7 +493,7 @@ __global__ __launch_bounds__(kWave) void retime_kernel(const RetimeArgs a) {
   auto X = [&](int tau, int d) { return tau <= 0 ? q0[d] : q[(size_t)(min(tau, T) - 1) * D + d]; };
   const float h = a.dt;
   const float kv = 1.0f / (12.0f * h), ka = 1.0f / (12.0f * h * h), kj = 1.0f / (2.0f * h * h * h);
-  float r = 0.0f;
+  float r = 0.0f, jm = 0.0f;
   for (int i = lane; i < (T + 1) * D; i += kWave) {
     const int tau = i / D, d = i - tau * D;
     // offsets from the centre value (the stencil weights sum to zero for
@@ -504,10 +506,101 @@ __global__ __launch_bounds__(kWave) void retime_kernel(const RetimeArgs a) {
     r = fmaxf(r, fabsf(v) * a.inv_v[d]);
     r = fmaxf(r, sqrtf(fabsf(ac) * a.inv_a[d]));
     r = fmaxf(r, cbrtf(fabsf(jk) * a.inv_j[d]));
+    jm = fmaxf(jm, fabsf(jk));
   }
 #pragma unroll
-  for (int o = kWave / 2; o >= 1; o >>= 1) r = fmaxf(r, __shfl_xor(r, o, kWave));
-  if (lane == 0) a.dt_out[seed] = h * r;
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    r = fmaxf(r, __shfl_xor(r, o, kWave));
+    jm = fmaxf(jm, __shfl_xor(jm, o, kWave));
+  }
+  if (lane == 0) {
+    a.dt_out[seed] = h * r;
+    // jerk read at spacing h r is jerk at h over r^3
+    if (a.jerk_out) a.jerk_out[seed] = r > 0.0f ? jm / (r * r * r) : 0.0f;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Seeds for trajectory optimization from collision-free IK (the overview of
+// global motion generation; App. 'Evaluating Optimized Trajectories').  Per
+// problem: the IK seeds within the success tolerances and collision free,
+// ranked by pos_err + rot_err + w_dist |q - q_start| (ties to the lower
+// index); with none, every seed ranked by cost.  Trajectory seed i runs on
+// the line from the start to the (i mod count)-th ranked IK solution.
+__global__ __launch_bounds__(kBlock) void ik_seed_kernel(const IkSeedArgs a) {
+  __shared__ float s_key[kMaxIkSeeds];
+  __shared__ int s_ok[kMaxIkSeeds];
+  __shared__ int s_order[kMaxIkSeeds];
+  __shared__ int s_nvalid;
+  const int p = blockIdx.x, D = a.dof;
+  const Problem ik = a.ik[p], to = a.to[p];
+  const float* q0 = a.q_start + (size_t)p * D;
+  if (threadIdx.x == 0) s_nvalid = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < ik.S; s += kBlock) {
+    const int r = ik.row0 + s;
+    const bool ok = a.pe_e[2 * r] <= a.pos_tol && a.pe_e[2 * r + 1] <= a.rot_tol && a.mc_e[r] >= 0.0f;
+    float d2 = 0.0f;
+    for (int j = 0; j < D; ++j) {
+      const float u = a.x_ik[(size_t)r * D + j] - q0[j];
+      d2 = fmaf(u, u, d2);
+    }
+    s_ok[s] = ok;
+    s_key[s] = ok ? a.pe_e[2 * r] + a.pe_e[2 * r + 1] + a.w_dist * sqrtf(d2) : a.cost_e[r];
+    if (ok) atomicAdd(&s_nvalid, 1);
+  }
+  __syncthreads();
+  const int nv = s_nvalid;
+  // rank among the eligible seeds: smaller key, then lower index
+  for (int s = threadIdx.x; s < ik.S; s += kBlock) {
+    if (nv > 0 && !s_ok[s]) continue;
+    const float k = s_key[s];
+    int rank = 0;
+    for (int u = 0; u < ik.S; ++u)
+      rank += (nv == 0 || s_ok[u]) && (s_key[u] < k || (s_key[u] == k && u < s));
+    s_order[rank] = s;
+  }
+  __syncthreads();
+  const int n_use = nv > 0 ? nv : ik.S;
+  const float inv_T = 1.0f / (float)to.T;
+  for (int e = threadIdx.x; e < to.S * to.T * D; e += kBlock) {
+    const int i = e / (to.T * D), rem = e - i * (to.T * D), t = rem / D, j = rem - t * D;
+    const int g = s_order[i % n_use];
+    const float qs = q0[j], qg = a.x_ik[(size_t)(ik.row0 + g) * D + j];
+    a.x_to[(size_t)(to.row0 + i * to.T + t) * D + j] = fmaf((float)(t + 1) * inv_T, qg - qs, qs);
+  }
+  if (a.ik_ok && threadIdx.x == 0) a.ik_ok[p] = nv > 0;
+}
+
+// Choice among the trajectory seeds of a problem: the seeds that reach the
+// goal within the success tolerances collision free, by pos_err + rot_err +
+// w_jerk max|jerk| + w_time (T - 1) dt (the seed's retimed spacing), ties
+// to the lower index; with none, the lowest cost.
+__global__ __launch_bounds__(kBlock) void traj_select_kernel(const TrajSelectArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.P) return;
+  const Problem pb = a.prob[p];
+  int best_v = -1, best_c = 0;
+  float sv = 3.0e38f, sc = 3.0e38f;
+  for (int s = 0; s < pb.S; ++s) {
+    const int r0 = pb.row0 + s * pb.T, rl = r0 + pb.T - 1;
+    float c = 0.0f, m = 3.0e38f;
+    for (int t = 0; t < pb.T; ++t) {
+      c += a.cost_e[r0 + t];
+      m = fminf(m, a.mc_e[r0 + t]);
+    }
+    const float pe = a.pe_e[2 * rl], re = a.pe_e[2 * rl + 1];
+    if (c < sc) { sc = c; best_c = s; }
+    if (pe <= a.pos_tol && re <= a.rot_tol && m >= 0.0f) {
+      const int seed = pb.seed0 + s;
+      const float v = pe + re + a.w_jerk * a.jerk_s[seed] + a.w_time * (float)(pb.T - 1) * a.dt_s[seed];
+      if (v < sv) { sv = v; best_v = s; }
+    }
+  }
+  const int b = best_v >= 0 ? best_v : best_c;
+  a.best_seed[p] = b;
+  if (a.success) a.success[p] = best_v >= 0;
+  if (a.motion_time) a.motion_time[p] = (float)(pb.T - 1) * a.dt_s[pb.seed0 + b];
 }
 
 __global__ __launch_bounds__(kBlock) void final_kernel(const FinalArgs a) {
@@ -694,6 +787,18 @@ hipError_t launch_retime(const RetimeArgs& a, hipStream_t s) {
   if (a.n_seeds == 0) return hipSuccess;
   if (a.dof < 1 || a.dof > kMaxDof || !(a.dt > 0.0f)) return hipErrorInvalidValue;
   retime_kernel<<<a.n_seeds, kWave, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ik_seeds(const IkSeedArgs& a, hipStream_t s) {
+  if (a.P == 0) return hipSuccess;
+  ik_seed_kernel<<<a.P, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_traj_select(const TrajSelectArgs& a, hipStream_t s) {
+  if (a.P == 0) return hipSuccess;
+  traj_select_kernel<<<(a.P + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 

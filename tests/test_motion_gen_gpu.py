@@ -1,0 +1,167 @@
+"""Motion generation around the solver on the GPU through the C ABI: seeds
+from ranked IK solutions, the choice among trajectory seeds, and the whole
+pipeline against its steps issued one by one.  The FP64 reference supplies
+the pose errors, clearances, costs, retimed spacings and jerks, and its
+plain ranking and selection."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_2310_17274_amd import workloads as wl
+from paper_2310_17274_amd.binding import Context, default_params
+from tests.test_timestep_gpu import AMAX, JMAX, VMAX
+
+pytestmark = pytest.mark.gpu
+
+F32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+POS_TOL, ROT_TOL = 0.005, 0.05
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a), dtype=torch.float32, device="cuda").contiguous()
+
+
+class World:
+    """An arm, a sparse world, reachable goals (end-effector poses of known
+    configurations q*) and a context holding both batches."""
+
+    def __init__(self, P=4, S_ik=24, S_to=6, T=32, seed=40, boxes=6):
+        rng = np.random.default_rng(seed)
+        self.robot = wl.robot_f32(wl.make_arm(seed=0, n_spheres=20))
+        self.worlds = wl.worlds_f32(wl.make_worlds(seed, [boxes] * P))
+        self.ref = ref.Ref(self.robot)
+        self.P, self.S_ik, self.S_to, self.T, D = P, S_ik, S_to, T, 7
+        self.q0 = F32(rng.uniform(-1, 1, (P, D)))
+        self.qstar = F32(rng.uniform(-1.5, 1.5, (P, D)))
+        self.goal = np.stack([F32(self.ref.fk(self.qstar[p])[2][0]) for p in range(P)])   # [P, 7]
+        self.ctx = Context(self.robot, default_params())
+        self.ctx.mg_set_worlds(self.worlds)
+        w = np.arange(P)
+        self.ik = self.ctx.batch(np.full(P, S_ik), np.ones(P, int), w, K_max=4, m_max=4)
+        self.to = self.ctx.batch(np.full(P, S_to), np.full(P, T), w, K_max=4, m_max=4)
+        self.q_start = _dev(self.q0)
+        self.goal_d = _dev(self.goal.reshape(P, -1))
+
+    def boxes(self, p):
+        return self.worlds.world(p)
+
+    def ik_seed_metrics(self, x_ik):
+        """Per IK seed: position and rotation error, clearance, cost."""
+        out = []
+        for p in range(self.P):
+            rows = []
+            for s in range(self.S_ik):
+                q = x_ik[p * self.S_ik + s]
+                c, _, mc, _ = self.ref.traj_cost(self.boxes(p), self.q0[p], self.goal[p][None], q[None], grad=False)
+                pe, re_ = self.ref.pose_error(q, self.goal[p][None])
+                rows.append((pe[0], re_[0], mc, c))
+            out.append(rows)
+        return out
+
+
+def _ik_inputs(wd, rng):
+    """Problem 0..P-2: a few seeds near q* (valid, distinct scores), the rest
+    random; the last problem: random seeds only (none valid)."""
+    D = 7
+    x = rng.uniform(-2.5, 2.5, (wd.P, wd.S_ik, D))
+    for p in range(wd.P - 1):
+        for k, mag in enumerate([0.0, 2e-3, 5e-3, 1e-3]):
+            u = rng.normal(0, 1, D)
+            x[p, 3 * k + 1] = wd.qstar[p] + mag * u / np.linalg.norm(u)
+    return F32(x.reshape(-1, D))
+
+
+def test_ik_seeds_parity():
+    wd = World()
+    rng = np.random.default_rng(41)
+    x_ik = _ik_inputs(wd, rng)
+    x_to, ok = wd.ctx.mg_ik_seeds(wd.ik, wd.to, wd.q_start, wd.goal_d, _dev(x_ik), w_dist=0.1)
+    torch.cuda.synchronize()
+    x_to = x_to.cpu().numpy().reshape(wd.P, wd.S_to, wd.T, 7)
+    ok = ok.cpu().numpy()
+    met = wd.ik_seed_metrics(x_ik)
+    n_valid_seen = 0
+    for p in range(wd.P):
+        pe, re_, mc, c = (np.array(v) for v in zip(*met[p]))
+        q = x_ik[p * wd.S_ik:(p + 1) * wd.S_ik]
+        order, nv = ref.ik_rank(q, wd.q0[p], pe, re_, mc, c, POS_TOL, ROT_TOL, 0.1)
+        assert ok[p] == (nv > 0), p
+        n_valid_seen += nv
+        n_use = nv if nv else wd.S_ik
+        for i in range(wd.S_to):
+            want = ref.linear_seeds(wd.q0[p], q[order[i % n_use]], wd.T)
+            np.testing.assert_allclose(x_to[p, i], want, rtol=0, atol=2e-6, err_msg=f"problem {p} seed {i}")
+    assert ok[-1] == 0 and n_valid_seen >= 2 * (wd.P - 1)
+
+
+def _traj_inputs(wd, rng):
+    """Trajectory seeds: lines from the start to q* plus an end offset of
+    0 .. 0.3 rad (some miss the goal), at different detours."""
+    D, T = 7, wd.T
+    x = np.empty((wd.P, wd.S_to, T, D))
+    for p in range(wd.P):
+        for s in range(wd.S_to):
+            end = wd.qstar[p] + (0.0 if s % 3 == 0 else 0.3 * rng.uniform(-1, 1, D) * (s % 3 == 2))
+            bump = rng.uniform(0.0, 0.4) * np.sin(np.pi * np.arange(1, T + 1) / T)[:, None] * rng.uniform(-1, 1, D)
+            x[p, s] = ref.linear_seeds(wd.q0[p], end, T) + bump * (s % 3 == 0)
+    return F32(x.reshape(-1, D))
+
+
+@pytest.mark.parametrize("w_time", [1.0, 0.0])
+def test_traj_select_parity(w_time):
+    wd = World(seed=42)
+    rng = np.random.default_rng(43)
+    x = _traj_inputs(wd, rng)
+    w_jerk = 1e-3
+    bs, ok, mt = wd.ctx.mg_traj_select(wd.to, wd.q_start, wd.goal_d, _dev(x), VMAX, AMAX, JMAX, w_jerk=w_jerk,
+                                       w_time=w_time)
+    torch.cuda.synchronize()
+    bs, ok, mt = bs.cpu().numpy(), ok.cpu().numpy(), mt.cpu().numpy()
+    X = x.reshape(wd.P, wd.S_to, wd.T, 7)
+    any_valid = False
+    for p in range(wd.P):
+        pe, re_, mc, c, jk, dts = [], [], [], [], [], []
+        for s in range(wd.S_to):
+            ci, _, mci, _ = wd.ref.traj_cost(wd.boxes(p), wd.q0[p], wd.goal[p][None], X[p, s], grad=False)
+            e, r = wd.ref.pose_error(X[p, s, -1], wd.goal[p][None])
+            dt = ref.retime(wd.q0[p], X[p, s], 0.25, VMAX, AMAX, JMAX)
+            pe.append(e[0]); re_.append(r[0]); mc.append(mci); c.append(ci); dts.append(dt)
+            jk.append(ref.max_jerk(wd.q0[p], X[p, s], dt))
+        want, valid = ref.traj_select(wd.T, pe, re_, mc, c, jk, dts, POS_TOL, ROT_TOL, w_jerk, w_time)
+        any_valid |= valid
+        assert ok[p] == valid, p
+        if bs[p] != want:
+            # only a near tie may go the other way
+            sc = lambda s: pe[s] + re_[s] + w_jerk * jk[s] + w_time * (wd.T - 1) * dts[s] if valid else c[s]
+            assert abs(sc(bs[p]) - sc(want)) <= 1e-4 * abs(sc(want)), (p, bs[p], want)
+        assert math.isclose(mt[p], (wd.T - 1) * dts[bs[p]], rel_tol=1e-4)
+    assert any_valid
+
+
+@pytest.mark.parametrize("use_graph", [True])
+def test_motion_gen_equals_its_steps(use_graph):
+    """The pipeline against mg_solve (IK), mg_ik_seeds, mg_solve_timestep
+    and mg_traj_select issued one by one on a second context: bit-identical.
+    Reachable goals: IK finds some; the chosen trajectories have a positive
+    motion time.  (Straight-line seeds through this world's cuboids are not
+    cleared in 70 iterations, so trajectory success is not asserted.)"""
+    alpha = wl.ALPHA_4
+    it_ik, it1, it2 = 60, 40, 30
+    rng = np.random.default_rng(44)
+    a, b = World(seed=45, boxes=3), World(seed=45, boxes=3)
+    x_ik0 = F32(rng.uniform(-2.0, 2.0, (a.P * a.S_ik, 7)))
+    xa = _dev(x_ik0)
+    x_to, ik_ok, bs, ok, mt, dts = a.ctx.mg_motion_gen(a.ik, a.to, a.q_start, a.goal_d, xa, it_ik, it1, it2, 4,
+                                                       alpha, VMAX, AMAX, JMAX)
+    xb = _dev(x_ik0)
+    b.ctx.mg_solve(b.ik, b.q_start, b.goal_d, xb, it_ik, 4, alpha, mode=1, graph_inner=25, use_graph=True)
+    xt, ok_b = b.ctx.mg_ik_seeds(b.ik, b.to, b.q_start, b.goal_d, xb, w_dist=0.1)
+    xt, _, _, _, dts_b = b.ctx.mg_solve_timestep(b.to, b.q_start, b.goal_d, xt, it1, it2, 4, alpha, VMAX, AMAX, JMAX)
+    bs_b, ok2_b, mt_b = b.ctx.mg_traj_select(b.to, b.q_start, b.goal_d, xt, VMAX, AMAX, JMAX)
+    torch.cuda.synchronize()
+    assert torch.equal(xa, xb) and torch.equal(x_to, xt) and torch.equal(ik_ok, ok_b)
+    assert torch.equal(bs, bs_b) and torch.equal(ok, ok2_b) and torch.equal(mt, mt_b) and dts == dts_b
+    assert int(ik_ok.sum()) >= 1 and bool(torch.all(torch.isfinite(mt) & (mt > 0)))
