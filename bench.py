@@ -398,13 +398,15 @@ def bench_motion_gen(warmup):
         ik = ctx.batch(np.full(P, 32), np.ones(P, int), np.zeros(P, int), K_max=4, m_max=4)
         to = ctx.batch(np.full(P, 12), np.full(P, 32), np.zeros(P, int), K_max=4, m_max=4)
         x_ik0 = torch.as_tensor(rng.uniform(-2.5, 2.5, (P * 32, D)), dtype=torch.float32, device=dev)
+        x_ik = torch.empty_like(x_ik0)
+        x_to = torch.empty((to.rows, D), dtype=torch.float32, device=dev)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         for rep in range(max(1, warmup) + 1):
-            x_ik = x_ik0.clone()
+            x_ik.copy_(x_ik0)
             torch.cuda.synchronize()
             ev0.record()
             _, ik_ok, bs, ok, mt, dts = ctx.mg_motion_gen(ik, to, q_start, goal, x_ik, 100, 100, 100, 4, alpha,
-                                                          vmax, amax, jmax)
+                                                          vmax, amax, jmax, x_to=x_to)
             ev1.record()
             torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1)

@@ -337,7 +337,8 @@ mg_status mg_traj_select(mg_ctx *ctx, mg_batch *batch, const float *q_start, con
  * iterations from the seeds in x_ik), mg_ik_seeds into x_to,
  * mg_solve_timestep on to_batch (iters1, iters2), mg_traj_select.
  * Arguments as in those calls; x_ik and x_to hold the IK and trajectory
- * iterates on return.  Not capturable (mg_solve_timestep). */
+ * iterates on return.  The solves launch their kernels directly (each pass
+ * runs once with its own parameters).  Not capturable (mg_solve_timestep). */
 mg_status mg_motion_gen(mg_ctx *ctx, mg_batch *ik_batch, mg_batch *to_batch, const float *q_start,
                         const float *goal, float *x_ik, float *x_to, int iters_ik, int iters1,
                         int iters2, int m, int K, const float *alpha, int mode, const float *vmax,

@@ -235,13 +235,14 @@ class Context:
         return bs, ok, mt
 
     def mg_motion_gen(self, ik: Batch, to: Batch, q_start, goal, x_ik, iters_ik, iters1, iters2, m, alpha,
-                      vmax, amax, jmax, dt_min=1e-3, w_dist=0.1, w_jerk=1e-3, w_time=1.0, mode=1):
+                      vmax, amax, jmax, dt_min=1e-3, w_dist=0.1, w_jerk=1e-3, w_time=1.0, mode=1, x_to=None):
         """IK, seeds, time-step optimization, selection.  x_ik is updated in
         place; returns (x_to, ik_ok, best_seed, success, motion_time,
         (dt_opt, dt_f))."""
         al = (C.c_float * len(alpha))(*alpha)
         lim = self._limits(vmax, amax, jmax)
-        x_to = torch.empty((to.rows, self.robot.dof), dtype=torch.float32, device=self.device)
+        if x_to is None:
+            x_to = torch.empty((to.rows, self.robot.dof), dtype=torch.float32, device=self.device)
         ik_ok, bs, ok = (torch.empty(ik.P, dtype=torch.int32, device=self.device) for _ in range(3))
         mt = torch.empty(ik.P, dtype=torch.float32, device=self.device)
         dt = (C.c_float * 2)()

@@ -1434,11 +1434,13 @@ mg_status mg_motion_gen(mg_ctx* c, mg_batch* ik, mg_batch* to, const float* q_st
   if (st != MG_OK || (st = common_checks(c, to)) != MG_OK) return st;
   if (!dt_out || !best_seed) return fail(MG_ERR_ARG, "null dt_out or best_seed");
   // collision-free IK, seeds on the lines to its solutions, trajectory
-  // optimization with the time-step passes, choice per problem
-  if ((st = mg_solve(c, ik, q_start, goal, x_ik, iters_ik, m, K, alpha, mode, 25, 1, ik->sel_dt, nullptr, nullptr,
+  // optimization with the time-step passes, choice per problem.  Kernels
+  // are launched directly: each pass runs once with its own parameters, so
+  // a captured graph would not be replayed.
+  if ((st = mg_solve(c, ik, q_start, goal, x_ik, iters_ik, m, K, alpha, mode, 25, 0, ik->sel_dt, nullptr, nullptr,
                      stream)) != MG_OK ||
       (st = mg_ik_seeds(c, ik, to, q_start, goal, x_ik, w_dist, x_to, ik_ok, stream)) != MG_OK ||
-      (st = mg_solve_timestep(c, to, q_start, goal, x_to, iters1, iters2, m, K, alpha, mode, 25, 1, vmax, amax,
+      (st = mg_solve_timestep(c, to, q_start, goal, x_to, iters1, iters2, m, K, alpha, mode, 25, 0, vmax, amax,
                               jmax, dt_min, to->sel_dt, nullptr, nullptr, dt_out, stream)) != MG_OK)
     return st;
   return mg_traj_select(c, to, q_start, goal, x_to, vmax, amax, jmax, w_jerk, w_time, best_seed, success,

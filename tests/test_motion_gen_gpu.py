@@ -141,8 +141,7 @@ def test_traj_select_parity(w_time):
     assert any_valid
 
 
-@pytest.mark.parametrize("use_graph", [True])
-def test_motion_gen_equals_its_steps(use_graph):
+def test_motion_gen_equals_its_steps():
     """The pipeline against mg_solve (IK), mg_ik_seeds, mg_solve_timestep
     and mg_traj_select issued one by one on a second context: bit-identical.
     Reachable goals: IK finds some; the chosen trajectories have a positive
@@ -157,9 +156,10 @@ def test_motion_gen_equals_its_steps(use_graph):
     x_to, ik_ok, bs, ok, mt, dts = a.ctx.mg_motion_gen(a.ik, a.to, a.q_start, a.goal_d, xa, it_ik, it1, it2, 4,
                                                        alpha, VMAX, AMAX, JMAX)
     xb = _dev(x_ik0)
-    b.ctx.mg_solve(b.ik, b.q_start, b.goal_d, xb, it_ik, 4, alpha, mode=1, graph_inner=25, use_graph=True)
+    b.ctx.mg_solve(b.ik, b.q_start, b.goal_d, xb, it_ik, 4, alpha, mode=1, graph_inner=25, use_graph=False)
     xt, ok_b = b.ctx.mg_ik_seeds(b.ik, b.to, b.q_start, b.goal_d, xb, w_dist=0.1)
-    xt, _, _, _, dts_b = b.ctx.mg_solve_timestep(b.to, b.q_start, b.goal_d, xt, it1, it2, 4, alpha, VMAX, AMAX, JMAX)
+    xt, _, _, _, dts_b = b.ctx.mg_solve_timestep(b.to, b.q_start, b.goal_d, xt, it1, it2, 4, alpha, VMAX, AMAX, JMAX,
+                                                 use_graph=False)
     bs_b, ok2_b, mt_b = b.ctx.mg_traj_select(b.to, b.q_start, b.goal_d, xt, VMAX, AMAX, JMAX)
     torch.cuda.synchronize()
     assert torch.equal(xa, xb) and torch.equal(x_to, xt) and torch.equal(ik_ok, ok_b)
