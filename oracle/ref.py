@@ -342,3 +342,29 @@ def traj_select(T, pos_err, rot_err, clear, cost, jerk, dt, pos_tol, rot_tol, w_
                  for s in range(S)]
         return int(np.argmin(score)), True
     return int(np.argmin(cost)), False
+
+
+def steer(r_eval, boxes, q_from, q_to, res, q_lo, q_hi):
+    """Parallel steering of one edge (Alg.3): n = floor(max_j |g_j| / res) + 1
+    steps of g / n from q_from toward q_to (g = q_to - q_from); samples
+    l_i = q_from + (i / n) g, i = 0..n, are valid when within the joint
+    limits and collision free (clearance >= 0 against the cuboids).  The
+    edge keeps the last valid sample before the first invalid one: returns
+    (h, l_h, |l_h - q_from|) with h = n when every sample is valid and
+    h = -1 (no progress: q_from, 0) when q_from itself is invalid."""
+    q_from, q_to = np.asarray(q_from, dtype=np.float64), np.asarray(q_to, dtype=np.float64)
+    g = q_to - q_from
+    n = int(math.floor(np.abs(g).max() / res)) + 1
+    goal = np.array([[0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0]] * r_eval.robot.n_ee)
+    h = n
+    for i in range(n + 1):
+        q = q_from + (i / n) * g
+        inside = np.all(q >= q_lo) and np.all(q <= q_hi)
+        clear = r_eval.traj_cost(boxes, q, goal, q[None], grad=False)[2]
+        if not (inside and clear >= 0):
+            h = i - 1
+            break
+    if h < 0:
+        return -1, q_from.copy(), 0.0
+    v = q_from + (h / n) * g
+    return h, v, float(np.linalg.norm(v - q_from))

@@ -959,3 +959,36 @@ def test_traj_select_table(oracle_lib):
     assert ref.traj_select(32, pos, rot, clear, cost, jerk, dt, 0.005, 0.05, 0.01, 1.0) == (1, True)
     # none valid: the lowest cost
     assert ref.traj_select(32, [1.0] * 4, rot, clear, cost, jerk, dt, 0.005, 0.05, 0.01, 0.1) == (2, False)
+
+
+# ---------------------------------------------------------------------------
+# Parallel steering (Alg.3).  The one-link robot turns its sphere (r = 0.05)
+# from angle 0 toward 1.0 rad at resolution 0.12: n = floor(1 / 0.12) + 1 = 9
+# steps of 1/9 rad.  A wall 4 cm thick (half 0.02) stands radially at angle
+# phi, so a sample at angle a collides when |sin(a - phi)| < 0.07, that is
+# |a - phi| < asin(0.07) = 0.0701.  With phi = 0.5 the samples 3/9 (0.167
+# away) and 4/9 (0.056 away) straddle it: h = 3, the edge reaches 1/3 rad.
+
+def _wall(phi):
+    return (np.array([[math.cos(phi), math.sin(phi), 0.0, math.cos(phi / 2), 0.0, 0.0, math.sin(phi / 2)]]),
+            np.array([[1.0, 0.04, 1.0]]))
+
+
+@pytest.mark.parametrize("phi, h", [(0.5, 3), (2.0, 9), (0.0, -1), (1.0, 8)])
+def test_steer_worked_example(oracle_lib, phi, h):
+    robot = one_link_robot()
+    r = ref.Ref(robot)
+    got_h, v, dist = ref.steer(r, _wall(phi), [0.0], [1.0], 0.12, robot.q_lo, robot.q_hi)
+    assert got_h == h
+    want = max(h, 0) / 9
+    assert v[0] == pytest.approx(want, abs=1e-15) and dist == pytest.approx(want, abs=1e-15)
+
+
+def test_steer_stops_at_the_joint_limit(oracle_lib):
+    """No cuboid near; the edge from 2.5 toward 3.5 rad crosses the limit
+    q_hi = 3: n = floor(1 / 0.12) + 1 = 9, samples 2.5 + i/9, the first
+    beyond 3 is i = 5, so h = 4."""
+    robot = one_link_robot()
+    far = (np.array([[50.0, 0, 0, 1, 0, 0, 0]]), np.array([[1.0, 1.0, 1.0]]))
+    h, v, dist = ref.steer(ref.Ref(robot), far, [2.5], [3.5], 0.12, robot.q_lo, robot.q_hi)
+    assert h == 4 and v[0] == pytest.approx(2.5 + 4 / 9, abs=1e-15) and dist == pytest.approx(4 / 9, abs=1e-15)
