@@ -346,6 +346,22 @@ mg_status mg_motion_gen(mg_ctx *ctx, mg_batch *ik_batch, mg_batch *to_batch, con
                         float w_jerk, float w_time, int *ik_ok, int *best_seed, int *success,
                         float *motion_time, float *dt_out, void *stream);
 
+/* Parallel steering (Sec. "Parallel Geometric Planner", Alg.3) of n_edges
+ * graph edges at once.  Edge e from a = from[e] toward b = to[e] takes
+ * n = floor(max_j |b_j - a_j| / res) + 1 steps; its samples
+ * a + (i / n)(b - a), i = 0..n, are checked in one launch (joint limits,
+ * clearance >= 0 against the batch's world; self-collision is not part of
+ * the check).  The edge keeps the last sample before the first that
+ * fails: last[e] = that index (n when none fails, -1 when the start fails:
+ * reach = a, dist = 0; -2 when n > n_max: not checked, reach = a).
+ *   batch: one problem of horizon 1 with n_edges (n_max + 1) seeds (the
+ *   sample grid; its workspaces hold the samples)
+ *   from, to DEVICE [n_edges][D]; reach DEVICE [n_edges][D];
+ *   last DEVICE [n_edges]; dist DEVICE [n_edges] (|reach - a|) or NULL.
+ * Capturable. */
+mg_status mg_steer(mg_ctx *ctx, mg_batch *batch, int n_edges, const float *from, const float *to,
+                   float res, int n_max, float *reach, int *last, float *dist, void *stream);
+
 /* Measurement hooks.  mg_set_timing(batch, 1) clears the batch's timing
  * record and from then on brackets every direct evaluation-kernel launch
  * made for the batch with a pair of HIP events on the launch stream

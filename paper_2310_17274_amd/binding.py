@@ -215,6 +215,18 @@ class Context:
                                    _ptr(jk) if jerk else None, _stream()))
         return (out, jk) if jerk else out
 
+    def mg_steer(self, b: Batch, q_from, q_to, res, n_max):
+        """Parallel steering (Alg.3) of edges q_from -> q_to [n, D]; b holds
+        one problem of horizon 1 with n (n_max + 1) seeds.  Returns
+        (reach [n, D], last [n], dist [n])."""
+        n = int(q_from.shape[0])
+        reach = torch.empty_like(q_from)
+        last = torch.empty(n, dtype=torch.int32, device=self.device)
+        dist = torch.empty(n, dtype=torch.float32, device=self.device)
+        check(_lib.lib().mg_steer(self.handle, b.handle, n, _ptr(q_from), _ptr(q_to), float(res), int(n_max),
+                                  _ptr(reach), _ptr(last), _ptr(dist), _stream()))
+        return reach, last, dist
+
     def mg_ik_seeds(self, ik: Batch, to: Batch, q_start, goal, x_ik, w_dist=0.1):
         """Trajectory seeds [to rows, D] on the lines to the ranked IK
         solutions, and ik_ok [P]."""

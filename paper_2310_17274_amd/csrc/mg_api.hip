@@ -77,6 +77,8 @@ struct mg_ctx {
   std::vector<float> fixed_tf, sphere, ee_tf, q_lo, q_hi;
   mg::Params params{};
   float* d_fixed_tf = nullptr;
+  float* d_zero = nullptr;     // zeros standing in for a start where none matters
+  float* d_goal_id = nullptr;  // identity poses standing in for a goal where none matters
   int* d_joint = nullptr;
   float* d_q_lo = nullptr;
   float* d_q_hi = nullptr;
@@ -296,6 +298,13 @@ mg::WaveLinks dev_wave_links(const mg_ctx* c) {
   wl.chain_rec = c->d_chain_rec;
   wl.joint_rec = c->d_joint_rec;
   return wl;
+}
+
+// Identity poses (xyz 0, quaternion 1 0 0 0), one per end effector.
+mg_status upload_identity_goals(mg_ctx* c) {
+  std::vector<float> g((size_t)7 * c->n_ee, 0.0f);
+  for (int e = 0; e < c->n_ee; ++e) g[7 * e + 3] = 1.0f;
+  return dev_upload(&c->d_goal_id, g);
 }
 
 // The wave-per-link layout needs a workgroup of L + 1 waves.
@@ -650,6 +659,8 @@ mg_status mg_create(const mg_robot_desc* r, const mg_params* params, mg_ctx** ou
       (st = dev_upload(&c->d_q_lo, c->q_lo)) != MG_OK ||
       (st = dev_upload(&c->d_q_hi, c->q_hi)) != MG_OK ||
       (st = dev_upload(&c->d_ee_tf, c->ee_tf)) != MG_OK ||
+      (st = dev_upload(&c->d_zero, std::vector<float>(c->D, 0.0f))) != MG_OK ||
+      (st = upload_identity_goals(c)) != MG_OK ||
       (st = build_lanes(c)) != MG_OK) {
     mg_destroy(c);
     return st;
@@ -665,6 +676,7 @@ void mg_destroy(mg_ctx* c) {
   (void)hipDeviceSynchronize();
   for (mg_batch* b : c->batches) b->ctx = nullptr;   // (batches outliving their context)
   dev_free(c->d_fixed_tf); dev_free(c->d_joint); dev_free(c->d_q_lo); dev_free(c->d_q_hi); dev_free(c->d_ee_tf);
+  dev_free(c->d_zero); dev_free(c->d_goal_id);
   dev_free(c->d_lane_info); dev_free(c->d_lane_sphere);
   dev_free(c->d_wl_info); dev_free(c->d_wl_chain); dev_free(c->d_wl_ball);
   dev_free(c->d_slot_sphere); dev_free(c->d_self_pairs); dev_free(c->d_chain_rec); dev_free(c->d_joint_rec);
@@ -1445,6 +1457,42 @@ mg_status mg_motion_gen(mg_ctx* c, mg_batch* ik, mg_batch* to, const float* q_st
     return st;
   return mg_traj_select(c, to, q_start, goal, x_to, vmax, amax, jmax, w_jerk, w_time, best_seed, success,
                         motion_time, stream);
+}
+
+mg_status mg_steer(mg_ctx* c, mg_batch* b, int n_edges, const float* from, const float* to, float res,
+                   int n_max, float* reach, int* last, float* dist, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if (n_edges < 1 || n_max < 1) return fail(MG_ERR_ARG, "n_edges and n_max must be >= 1");
+  if (!from || !to || !reach || !last) return fail(MG_ERR_ARG, "null from, to, reach or last");
+  if (!(res > 0.0f)) return fail(MG_ERR_ARG, "res must be > 0");
+  if (b->P != 1 || b->horizon[0] != 1 || (long)b->seeds[0] != (long)n_edges * (n_max + 1))
+    return fail(MG_ERR_SHAPE, "the batch must hold one problem of horizon 1 with n_edges x (n_max + 1) = %ld seeds",
+                (long)n_edges * (n_max + 1));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  mg::SteerArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n_edges = n_edges;
+  a.n_max = n_max;
+  a.dof = c->D;
+  a.res = res;
+  a.from = from;
+  a.to = to;
+  a.q_lo = c->d_q_lo;
+  a.q_hi = c->d_q_hi;
+  a.pts = b->g_cur;      // the batch's [rows][D] workspace holds the samples
+  a.mc = b->mc_e;
+  a.reach = reach;
+  a.last = last;
+  a.dist = dist;
+  HIP_TRY(mg::launch_steer_points(a, s));
+  // clearance of every sample (a start and goal are not used at horizon 1
+  // for the clearance)
+  if ((st = enqueue_eval(c, b, c->d_zero, c->d_goal_id, b->g_cur, nullptr, 1, nullptr, false, nullptr, nullptr, s)) !=
+      MG_OK)
+    return st;
+  HIP_TRY(mg::launch_steer_scan(a, s));
+  return MG_OK;
 }
 
 }  // extern "C"

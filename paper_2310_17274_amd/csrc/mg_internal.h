@@ -299,6 +299,21 @@ struct IkSeedArgs {
   int* ik_ok;              // [P] or null
 };
 
+// Parallel steering (Alg.3): samples of every edge, then the last valid one.
+struct SteerArgs {
+  int n_edges, n_max, dof;
+  float res;               // largest joint step between samples
+  const float* from;       // [n_edges][D]
+  const float* to;         // [n_edges][D]
+  const float* q_lo;
+  const float* q_hi;
+  float* pts;              // [n_edges][n_max + 1][D] samples
+  const float* mc;         // [n_edges][n_max + 1] clearance of every sample
+  float* reach;            // [n_edges][D]
+  int* last;               // [n_edges]
+  float* dist;             // [n_edges] or null
+};
+
 // Trajectory selection among the seeds of every problem (one thread each).
 struct TrajSelectArgs {
   const Problem* prob;
@@ -351,6 +366,8 @@ hipError_t launch_particle_update(const ParticleArgs& a, hipStream_t s);
 hipError_t launch_retime(const RetimeArgs& a, hipStream_t s);
 hipError_t launch_ik_seeds(const IkSeedArgs& a, hipStream_t s);
 hipError_t launch_traj_select(const TrajSelectArgs& a, hipStream_t s);
+hipError_t launch_steer_points(const SteerArgs& a, hipStream_t s);
+hipError_t launch_steer_scan(const SteerArgs& a, hipStream_t s);
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);
 hipError_t launch_ee_pose(const EePoseArgs& a, hipStream_t s);
 hipError_t launch_boxes(const float* pose, const float* dims, int n, Box* out, hipStream_t s);

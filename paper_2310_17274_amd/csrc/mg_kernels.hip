@@ -13,6 +13,7 @@
 // retime_kernel    per-seed spacing that puts the trajectory on its limits.
 // ik_seed_kernel   IK seeds ranked per problem, linear trajectory seeds.
 // traj_select_kernel  per-problem choice among trajectory seeds.
+// steer_points_kernel, steer_scan_kernel  parallel steering of graph edges.
 #include "mg_device.h"
 #include "mg_eval.h"
 
@@ -787,6 +788,74 @@ hipError_t launch_retime(const RetimeArgs& a, hipStream_t s) {
   if (a.n_seeds == 0) return hipSuccess;
   if (a.dof < 1 || a.dof > kMaxDof || !(a.dt > 0.0f)) return hipErrorInvalidValue;
   retime_kernel<<<a.n_seeds, kWave, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// Parallel steering (Alg.3).  Edge e from a to b takes n = floor(max_j
+// |b_j - a_j| / res) + 1 steps; sample i (0..n) is a + (i / n)(b - a).  An
+// edge needing more than n_max steps is not checked.  Samples past n repeat
+// the end so every slot of the fixed sample grid holds a configuration.
+__device__ __forceinline__ int steer_steps(const SteerArgs& a, int e) {
+  float gm = 0.0f;
+  for (int j = 0; j < a.dof; ++j)
+    gm = fmaxf(gm, fabsf(a.to[(size_t)e * a.dof + j] - a.from[(size_t)e * a.dof + j]));
+  return (int)floorf(gm / a.res) + 1;
+}
+
+__global__ __launch_bounds__(kBlock) void steer_points_kernel(const SteerArgs a) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = a.n_max + 1;
+  if (k >= (long)a.n_edges * per) return;
+  const int e = (int)(k / per), i = (int)(k - (long)e * per);
+  const int n = steer_steps(a, e);
+  const float f = n <= a.n_max ? (float)min(i, n) / (float)n : 0.0f;
+  for (int j = 0; j < a.dof; ++j) {
+    const float q0 = a.from[(size_t)e * a.dof + j];
+    a.pts[(size_t)k * a.dof + j] = fmaf(f, a.to[(size_t)e * a.dof + j] - q0, q0);
+  }
+}
+
+// The first sample outside the joint limits or in collision (clearance < 0)
+// ends the edge: it keeps the sample before (h = n when none fails, -1 when
+// the start fails: no progress; -2: the edge needs more than n_max steps).
+__global__ __launch_bounds__(kBlock) void steer_scan_kernel(const SteerArgs a) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n_edges) return;
+  const int n = steer_steps(a, e), per = a.n_max + 1, D = a.dof;
+  int h = -2;
+  if (n <= a.n_max) {
+    h = n;
+    for (int i = 0; i <= n; ++i) {
+      const size_t k = (size_t)e * per + i;
+      bool ok = a.mc[k] >= 0.0f;
+      for (int j = 0; j < D; ++j) {
+        const float q = a.pts[k * D + j];
+        ok = ok && q >= a.q_lo[j] && q <= a.q_hi[j];
+      }
+      if (!ok) { h = i - 1; break; }
+    }
+  }
+  const size_t src = (size_t)e * per + (h >= 0 ? h : 0);
+  float d2 = 0.0f;
+  for (int j = 0; j < D; ++j) {
+    const float q = h >= 0 ? a.pts[src * D + j] : a.from[(size_t)e * D + j];
+    const float u = q - a.from[(size_t)e * D + j];
+    d2 = fmaf(u, u, d2);
+    a.reach[(size_t)e * D + j] = q;
+  }
+  a.last[e] = h;
+  if (a.dist) a.dist[e] = sqrtf(d2);
+}
+
+hipError_t launch_steer_points(const SteerArgs& a, hipStream_t s) {
+  const long n = (long)a.n_edges * (a.n_max + 1);
+  steer_points_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_steer_scan(const SteerArgs& a, hipStream_t s) {
+  steer_scan_kernel<<<(a.n_edges + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
   return hipGetLastError();
 }
 

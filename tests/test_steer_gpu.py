@@ -1,0 +1,83 @@
+"""Parallel steering (Alg.3) on the GPU through the C ABI against the FP64
+reference: the worked wall example, and random edges among 40 oriented
+cuboids (index of the last valid sample exact unless the deciding sample's
+clearance or the step count sits within rounding of its threshold)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_2310_17274_amd import workloads as wl
+from paper_2310_17274_amd.binding import Context, default_params
+from tests.test_oracle_pins import _wall, one_link_robot
+
+pytestmark = pytest.mark.gpu
+
+F32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _dev(a):
+    return torch.as_tensor(np.asarray(a), dtype=torch.float32, device="cuda").contiguous()
+
+
+def _ctx(robot, worlds, n_edges, n_max):
+    ctx = Context(robot, default_params())
+    ctx.mg_set_worlds(worlds)
+    b = ctx.batch([n_edges * (n_max + 1)], [1], [0], K_max=1, m_max=0)
+    return ctx, b
+
+
+def test_steer_worked_example_on_gpu():
+    """The wall at 0.5, 2.0, 0.0 and 1.0 rad: last valid sample 3, 9, -1, 8
+    of 9 steps of 1/9 rad (the reference's pins)."""
+    robot = one_link_robot()
+    cases = [(0.5, 3), (2.0, 9), (0.0, -1), (1.0, 8)]
+    for phi, h in cases:
+        pose, dims = _wall(phi)
+        worlds = wl.Worlds(offsets=np.array([0, 1], np.int32), pose=F32(pose), dims=F32(dims))
+        ctx, b = _ctx(robot, worlds, 1, 12)
+        reach, last, dist = ctx.mg_steer(b, _dev([[0.0]]), _dev([[1.0]]), 0.12, 12)
+        torch.cuda.synchronize()
+        assert int(last[0]) == h, phi
+        want = max(h, 0) / 9
+        assert abs(float(reach[0, 0]) - want) < 1e-6 and abs(float(dist[0]) - want) < 1e-6
+
+
+def test_steer_random_edges_parity():
+    robot = wl.robot_f32(wl.make_arm(seed=0, n_spheres=52))
+    worlds = wl.worlds_f32(wl.make_worlds(2, [40]))
+    boxes = worlds.world(0)
+    r = ref.Ref(robot)
+    rng = np.random.default_rng(70)
+    n, n_max, res = 96, 40, 0.05
+    a = F32(rng.uniform(-2.0, 2.0, (n, 7)))
+    b_ = F32(a + rng.uniform(-1.2, 1.2, (n, 7)))
+    b_[-1] = F32(a[-1] + 3.0)         # needs more than n_max steps: not checked
+    ctx, b = _ctx(robot, worlds, n, n_max)
+    reach, last, dist = ctx.mg_steer(b, _dev(a), _dev(b_), res, n_max)
+    torch.cuda.synchronize()
+    reach, last, dist = reach.cpu().numpy(), last.cpu().numpy(), dist.cpu().numpy()
+    goal = np.array([[0, 0, 0, 1, 0, 0, 0.0]])
+    seen = set()
+    for e in range(n):
+        g = b_[e] - a[e]
+        steps = int(math.floor(np.abs(g).max() / res)) + 1
+        if steps > n_max:
+            assert last[e] == -2 and np.array_equal(reach[e], a[e].astype(np.float32)) and dist[e] == 0
+            seen.add("long")
+            continue
+        h, v, d = ref.steer(r, boxes, a[e], b_[e], res, robot.q_lo, robot.q_hi)
+        if last[e] != h:
+            # the deciding sample sits on the threshold within rounding
+            i = min(last[e], h) + 1
+            q = a[e] + (i / steps) * g
+            clear = r.traj_cost(boxes, q, goal, q[None], grad=False)[2]
+            lim = min((q - robot.q_lo).min(), (robot.q_hi - q).min())
+            assert abs(clear) < 1e-5 or abs(lim) < 1e-5, (e, last[e], h, clear, lim)
+            continue
+        seen.add("full" if h == steps else ("none" if h < 0 else "part"))
+        np.testing.assert_allclose(reach[e], v, rtol=0, atol=2e-6)
+        assert abs(dist[e] - d) <= 2e-6 * max(1.0, d)
+    assert {"long", "part", "full"} <= seen, seen
