@@ -1448,7 +1448,9 @@ mg_status mg_motion_gen(mg_ctx* c, mg_batch* ik, mg_batch* to, const float* q_st
   // collision-free IK, seeds on the lines to its solutions, trajectory
   // optimization with the time-step passes, choice per problem.  Kernels
   // are launched directly: each pass runs once with its own parameters, so
-  // a captured graph would not be replayed.
+  // a captured graph would not be replayed.  The solves' per-seed best
+  // costs go to each batch's selection scratch (sel_dt), which nothing
+  // reads before mg_traj_select rewrites it.
   if ((st = mg_solve(c, ik, q_start, goal, x_ik, iters_ik, m, K, alpha, mode, 25, 0, ik->sel_dt, nullptr, nullptr,
                      stream)) != MG_OK ||
       (st = mg_ik_seeds(c, ik, to, q_start, goal, x_ik, w_dist, x_to, ik_ok, stream)) != MG_OK ||

@@ -421,11 +421,16 @@ def test_cost_grad_is_deterministic(layout):
         assert np.array_equal(u, v)
 
 
+@pytest.mark.parametrize("params", [pytest.param(None, id="default"),
+                                    pytest.param(dict(speed=1), id="speed"),
+                                    pytest.param(dict(speed=1, swept=1, sweep_steps=4), id="speed_swept")])
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_full_size_cost_adjoint_sampled(layout):
+def test_full_size_cost_adjoint_sampled(layout, params):
     """Full 32 seeds x 32 waypoints x 8 candidates workload through the
-    line-search launch; candidates of sampled seeds checked one by one."""
-    case = make_case("adjoint", layout=layout)
+    line-search launch; candidates of sampled seeds checked one by one.
+    Also with the speed metric, and with it and swept collision (both
+    wave per link: a lane-per-link request falls back to it)."""
+    case = make_case("adjoint", layout=layout, params=params)
     D = 7
     rng = np.random.default_rng(0)
     d = rng.normal(0, 0.05, case.batch.x0.shape).astype(np.float32).astype(np.float64)
