@@ -362,6 +362,28 @@ mg_status mg_motion_gen(mg_ctx *ctx, mg_batch *ik_batch, mg_batch *to_batch, con
 mg_status mg_steer(mg_ctx *ctx, mg_batch *batch, int n_edges, const float *from, const float *to,
                    float res, int n_max, float *reach, int *last, float *dist, void *stream);
 
+/* Geometric planning (Sec. "Parallel Geometric Planner", Alg.2) of one
+ * start / goal pair in the batch's world, every steering step a batched
+ * mg_steer launch.  The start, goal and (optional) retract configuration are
+ * steer-connected both ways; while no path joins start and goal, a round
+ * samples configurations uniformly within the joint limits and, after the
+ * first round, within the informed region |q - start| + |q - goal| <= c_max,
+ * and steers from each sample's k nearest graph nodes toward it (an edge
+ * that stops short adds its last valid sample as a node).  A failed round
+ * widens c_max by a quarter of the start-goal distance and grows the sample
+ * and neighbour counts by a quarter (at most 4x n_samples, 2x k_near).  The shortest path (Dijkstra) is then shortcut:
+ * from each waypoint, the farthest later waypoint reachable directly.
+ *   batch: one problem of horizon 1 with a multiple of (n_max + 1) seeds
+ *   (that multiple is the number of edges per launch)
+ *   start, goal HOST [D]; retract HOST [D] or NULL; seed: host sampler
+ *   path HOST [max_waypoints][D]; n_waypoints HOST: waypoints written (0:
+ *   no path within max_rounds).
+ * Not capturable (host graph, synchronises after every launch). */
+mg_status mg_plan(mg_ctx *ctx, mg_batch *batch, const float *start, const float *goal,
+                  const float *retract, float res, int n_max, int n_samples, int k_near,
+                  int max_rounds, unsigned seed, int max_waypoints, float *path, int *n_waypoints,
+                  void *stream);
+
 /* Measurement hooks.  mg_set_timing(batch, 1) clears the batch's timing
  * record and from then on brackets every direct evaluation-kernel launch
  * made for the batch with a pair of HIP events on the launch stream

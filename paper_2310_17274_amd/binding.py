@@ -227,6 +227,20 @@ class Context:
                                   _ptr(reach), _ptr(last), _ptr(dist), _stream()))
         return reach, last, dist
 
+    def mg_plan(self, b: Batch, start, goal, res, n_max, retract=None, n_samples=64, k_near=4, max_rounds=20,
+                seed=0, max_waypoints=256):
+        """Geometric plan (Alg.2) from start to goal (host [D]); b holds one
+        problem of horizon 1 with a multiple of n_max + 1 seeds.  Returns the
+        waypoints [n, D] (n = 0: none found)."""
+        D = self.robot.dof
+        f = lambda a: (C.c_float * D)(*np.asarray(a, dtype=np.float32).tolist())
+        path = (C.c_float * (max_waypoints * D))()
+        n = C.c_int(0)
+        check(_lib.lib().mg_plan(self.handle, b.handle, f(start), f(goal), f(retract) if retract is not None else None,
+                                 float(res), int(n_max), int(n_samples), int(k_near), int(max_rounds), int(seed),
+                                 int(max_waypoints), path, C.byref(n), _stream()))
+        return np.frombuffer(path, dtype=np.float32, count=n.value * D).reshape(n.value, D).copy()
+
     def mg_ik_seeds(self, ik: Batch, to: Batch, q_start, goal, x_ik, w_dist=0.1):
         """Trajectory seeds [to rows, D] on the lines to the ranked IK
         solutions, and ik_ok [P]."""

@@ -11,6 +11,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <queue>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -1495,6 +1498,182 @@ mg_status mg_steer(mg_ctx* c, mg_batch* b, int n_edges, const float* from, const
     return st;
   HIP_TRY(mg::launch_steer_scan(a, s));
   return MG_OK;
+}
+
+mg_status mg_plan(mg_ctx* c, mg_batch* b, const float* start, const float* goal, const float* retract,
+                  float res, int n_max, int n_samples, int k_near, int max_rounds, unsigned seed,
+                  int max_waypoints, float* path, int* n_waypoints, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if (!start || !goal || !path || !n_waypoints) return fail(MG_ERR_ARG, "null start, goal, path or n_waypoints");
+  if (n_samples < 1 || k_near < 1 || max_rounds < 0 || max_waypoints < 2)
+    return fail(MG_ERR_ARG, "need n_samples, k_near >= 1, max_rounds >= 0, max_waypoints >= 2");
+  if (b->P != 1 || b->horizon[0] != 1 || b->seeds[0] % (n_max + 1) != 0)
+    return fail(MG_ERR_SHAPE, "the batch must hold one problem of horizon 1 with a multiple of n_max + 1 seeds");
+  const int D = c->D, cap = b->seeds[0] / (n_max + 1);   // edges per steering launch
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  *n_waypoints = 0;
+  std::vector<std::vector<float>> node;                  // graph nodes (host)
+  std::vector<std::vector<std::pair<int, float>>> adj;   // undirected weighted edges
+  auto add_node = [&](const float* q) {
+    node.emplace_back(q, q + D);
+    adj.emplace_back();
+    return (int)node.size() - 1;
+  };
+  auto dist = [&](const float* a, const float* bq) {
+    double d2 = 0.0;
+    for (int j = 0; j < D; ++j) d2 += ((double)a[j] - bq[j]) * ((double)a[j] - bq[j]);
+    return (float)std::sqrt(d2);
+  };
+  float *d_from = nullptr, *d_to = nullptr, *d_reach = nullptr;
+  int* d_last = nullptr;
+  if ((st = dev_alloc(&d_from, (size_t)cap * D)) != MG_OK || (st = dev_alloc(&d_to, (size_t)cap * D)) != MG_OK ||
+      (st = dev_alloc(&d_reach, (size_t)cap * D)) != MG_OK || (st = dev_alloc(&d_last, (size_t)cap)) != MG_OK) {
+    dev_free(d_from); dev_free(d_to); dev_free(d_reach); dev_free(d_last);
+    return st;
+  }
+  std::vector<float> h_from((size_t)cap * D), h_to((size_t)cap * D), h_reach((size_t)cap * D);
+  std::vector<int> h_last(cap);
+  // steer_connect (Alg.3 on every edge, in launches of cap edges): an edge
+  // that reaches its target joins the two nodes; one that stops short adds
+  // its last valid sample as a node joined to the source (when it moved)
+  auto steer_connect = [&](const std::vector<std::pair<int, int>>& edges, const std::vector<std::vector<float>>* tgt,
+                           std::vector<int>* reached) -> mg_status {
+    for (size_t e0 = 0; e0 < edges.size(); e0 += cap) {
+      const int ne = (int)std::min(edges.size() - e0, (size_t)cap);
+      for (int e = 0; e < cap; ++e) {
+        const int k = (int)e0 + std::min(e, ne - 1);   // padding repeats the last edge
+        const float* a = node[edges[k].first].data();
+        const float* t = edges[k].second >= 0 ? node[edges[k].second].data() : (*tgt)[k].data();
+        std::copy(a, a + D, &h_from[(size_t)e * D]);
+        std::copy(t, t + D, &h_to[(size_t)e * D]);
+      }
+      HIP_TRY(hipMemcpyAsync(d_from, h_from.data(), h_from.size() * 4, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipMemcpyAsync(d_to, h_to.data(), h_to.size() * 4, hipMemcpyHostToDevice, s));
+      mg_status r = mg_steer(c, b, cap, d_from, d_to, res, n_max, d_reach, d_last, nullptr, stream);
+      if (r != MG_OK) return r;
+      HIP_TRY(hipMemcpyAsync(h_reach.data(), d_reach, h_reach.size() * 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(h_last.data(), d_last, h_last.size() * 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (int e = 0; e < ne; ++e) {
+        const int k = (int)e0 + e, from = edges[k].first;
+        const float* v = &h_reach[(size_t)e * D];
+        const float* t = &h_to[(size_t)e * D];
+        int to = -1;
+        if (h_last[e] < 1) continue;                       // no progress or not checked
+        // (the last sample is the target up to the rounding of a + (b - a))
+        const bool full = dist(v, t) <= 1e-5f;
+        if (full && edges[k].second >= 0) to = edges[k].second;
+        else to = add_node(v);
+        const float d = dist(node[from].data(), node[to].data());
+        adj[from].push_back({to, d});
+        adj[to].push_back({from, d});
+        if (reached && full) (*reached)[k] = to;
+      }
+    }
+    return MG_OK;
+  };
+  // shortest path from node 0 (start) to node 1 (goal), Dijkstra on a heap
+  auto shortest = [&](std::vector<int>& out) {
+    const size_t n = node.size();
+    std::vector<float> dd(n, 3.0e38f);
+    std::vector<int> prev(n, -1);
+    std::priority_queue<std::pair<float, int>, std::vector<std::pair<float, int>>, std::greater<>> pq;
+    dd[0] = 0.0f;
+    pq.push({0.0f, 0});
+    while (!pq.empty()) {
+      const auto [du, u] = pq.top();
+      pq.pop();
+      if (du > dd[u]) continue;
+      if (u == 1) break;
+      for (auto& [v, w] : adj[u])
+        if (du + w < dd[v]) { dd[v] = du + w; prev[v] = u; pq.push({dd[v], v}); }
+    }
+    out.clear();
+    if (dd[1] >= 3.0e38f) return 3.0e38f;
+    for (int v = 1; v >= 0; v = prev[v]) out.push_back(v);
+    std::reverse(out.begin(), out.end());
+    return dd[1];
+  };
+  auto run = [&]() -> mg_status {
+    add_node(start);
+    add_node(goal);
+    std::vector<std::pair<int, int>> e0 = {{0, 1}, {1, 0}};
+    if (retract) {
+      const int r = add_node(retract);
+      e0.insert(e0.end(), {{0, r}, {r, 0}, {1, r}, {r, 1}});
+    }
+    mg_status r = steer_connect(e0, nullptr, nullptr);
+    if (r != MG_OK) return r;
+    std::vector<int> route;
+    float len = shortest(route);
+    // informed sampling: sum of distances to start and goal within c_max
+    const float c_min = dist(start, goal);
+    float c_max = 3.0e38f;
+    int k_n = k_near, p_n = n_samples;
+    std::mt19937 rng(seed);
+    for (int round = 0; route.empty() && round < max_rounds; ++round) {
+      std::vector<std::vector<float>> smp;
+      for (int tries = 0; (int)smp.size() < p_n && tries < 100 * p_n; ++tries) {
+        std::vector<float> q(D);
+        for (int j = 0; j < D; ++j)
+          q[j] = c->q_lo[j] + (c->q_hi[j] - c->q_lo[j]) * std::uniform_real_distribution<float>(0.0f, 1.0f)(rng);
+        if (dist(q.data(), start) + dist(q.data(), goal) <= c_max) smp.push_back(q);
+      }
+      // each sample steered from its k_n nearest nodes
+      std::vector<std::pair<int, int>> edges;
+      std::vector<std::vector<float>> tgt;
+      for (auto& q : smp) {
+        std::vector<std::pair<float, int>> near;
+        for (size_t i = 0; i < node.size(); ++i) near.push_back({dist(node[i].data(), q.data()), (int)i});
+        const int kk = std::min<int>(k_n, (int)near.size());
+        std::partial_sort(near.begin(), near.begin() + kk, near.end());
+        for (int i = 0; i < kk; ++i) { edges.push_back({near[i].second, -1}); tgt.push_back(q); }
+      }
+      std::vector<int> reached(edges.size(), -1);
+      if ((r = steer_connect(edges, &tgt, &reached)) != MG_OK) return r;
+      // samples reached from several nodes become one node (joined edges)
+      for (size_t k = 0; k < edges.size(); ++k)
+        for (size_t k2 = k + 1; k2 < edges.size() && reached[k] >= 0; ++k2)
+          if (reached[k2] >= 0 && tgt[k2] == tgt[k] && reached[k2] != reached[k]) {
+            adj[reached[k]].push_back({reached[k2], 0.0f});
+            adj[reached[k2]].push_back({reached[k], 0.0f});
+          }
+      len = shortest(route);
+      // a failed round widens the region and grows the counts by a quarter
+      // (capped at 4x the samples and 2x the neighbours asked for)
+      if (route.empty()) {
+        if (c_max >= 3.0e38f) c_max = 2.0f * c_min;
+        c_max += 0.25f * c_min;
+        p_n = std::min(p_n + std::max(1, p_n / 4), 4 * n_samples);
+        k_n = std::min(k_n + std::max(1, k_n / 4), 2 * k_near);
+      }
+    }
+    if (route.empty()) return MG_OK;
+    // shortcut: from each waypoint, the farthest later one reachable directly
+    std::vector<int> sc = {route[0]};
+    for (size_t i = 0; i + 1 < route.size();) {
+      std::vector<std::pair<int, int>> edges;
+      for (size_t j = route.size() - 1; j > i + 1; --j) edges.push_back({route[i], route[j]});
+      size_t next = i + 1;
+      if (!edges.empty()) {
+        std::vector<int> reached(edges.size(), -1);
+        if ((r = steer_connect(edges, nullptr, &reached)) != MG_OK) return r;
+        for (size_t k = 0; k < edges.size(); ++k)
+          if (reached[k] == edges[k].second) { next = route.size() - 1 - k; break; }
+      }
+      sc.push_back(route[next]);
+      i = next;
+    }
+    (void)len;
+    if ((int)sc.size() > max_waypoints) return fail(MG_ERR_SHAPE, "the path has %d waypoints (max %d)", (int)sc.size(), max_waypoints);
+    for (size_t i = 0; i < sc.size(); ++i) std::copy(node[sc[i]].begin(), node[sc[i]].end(), path + i * D);
+    *n_waypoints = (int)sc.size();
+    return MG_OK;
+  };
+  st = run();
+  dev_free(d_from); dev_free(d_to); dev_free(d_reach); dev_free(d_last);
+  return st;
 }
 
 }  // extern "C"

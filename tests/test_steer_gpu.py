@@ -81,3 +81,53 @@ def test_steer_random_edges_parity():
         np.testing.assert_allclose(reach[e], v, rtol=0, atol=2e-6)
         assert abs(dist[e] - d) <= 2e-6 * max(1.0, d)
     assert {"long", "part", "full"} <= seen, seen
+
+
+def _path_valid(r, boxes, path, res, robot):
+    """Every segment of the path steers through to its end (the reference's
+    Alg.3 at the same resolution)."""
+    for i in range(len(path) - 1):
+        g = path[i + 1] - path[i]
+        steps = int(math.floor(np.abs(g).max() / res)) + 1
+        h, _, _ = ref.steer(r, boxes, path[i], path[i + 1], res, robot.q_lo, robot.q_hi)
+        if h != steps:
+            return False
+    return True
+
+
+def test_plan_direct_edge_in_free_space():
+    robot = wl.robot_f32(wl.make_arm(seed=0, n_spheres=20))
+    worlds = wl.Worlds(offsets=np.array([0, 1], np.int32), pose=np.array([[50.0, 0, 0, 1, 0, 0, 0]]),
+                       dims=np.array([[1.0, 1.0, 1.0]]))
+    ctx, b = _ctx(robot, worlds, 16, 64)
+    start, goal = F32([0.1] * 7), F32([0.8, -0.5, 0.3, 1.0, -0.2, 0.4, 0.0])
+    path = ctx.mg_plan(b, start, goal, 0.05, 64)
+    assert path.shape == (2, 7)
+    np.testing.assert_array_equal(path[0], start.astype(np.float32))
+    np.testing.assert_array_equal(path[1], goal.astype(np.float32))
+
+
+def test_plan_around_obstacles_is_valid():
+    """Start and goal collision free with the direct edge blocked by a
+    10-cuboid world: the planner's path starts and ends there and every
+    segment steers through in the reference."""
+    robot = wl.robot_f32(wl.make_arm(seed=0, n_spheres=52))
+    worlds = wl.worlds_f32(wl.make_worlds(2, [10]))
+    boxes = worlds.world(0)
+    r = ref.Ref(robot)
+    rng = np.random.default_rng(71)
+    goal_pose = np.array([[0, 0, 0, 1, 0, 0, 0.0]])
+    res, pair = 0.05, None
+    for _ in range(400):
+        a, bq = F32(rng.uniform(-2.5, 2.5, 7)), F32(rng.uniform(-2.5, 2.5, 7))
+        ok = all(r.traj_cost(boxes, q, goal_pose, q[None], grad=False)[2] >= 0.01 for q in (a, bq))
+        if ok and ref.steer(r, boxes, a, bq, res, robot.q_lo, robot.q_hi)[0] < 0.5 * (np.abs(bq - a).max() / res):
+            pair = (a, bq)
+            break
+    assert pair is not None
+    ctx, b = _ctx(robot, worlds, 128, 128)
+    path = ctx.mg_plan(b, pair[0], pair[1], res, 128, n_samples=64, k_near=4, max_rounds=8, seed=3)
+    assert len(path) >= 3, "a path around the obstacles"
+    np.testing.assert_array_equal(path[0], pair[0].astype(np.float32))
+    np.testing.assert_array_equal(path[-1], pair[1].astype(np.float32))
+    assert _path_valid(r, boxes, path.astype(np.float64), res, robot)
