@@ -65,8 +65,8 @@ def main():
                     help="skip the uneven-batch, inverse-kinematics, large and motion-generation measurements")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
-              "plan is described in DESIGN.md and not implemented", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several "
+              "GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.profile == "copy":
         return profile_copy()
