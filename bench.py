@@ -385,16 +385,19 @@ def bench_motion_gen(warmup):
     rng = np.random.default_rng(60)
     out = {}
     for P in (1, 64):
-        # reachable goals: end-effector poses of the clearest of 16 random
-        # configurations per problem (the library's own kinematics and cost)
-        cand = wl.goal_configs(robot, 61 + P, 16 * P)
+        # collision-free starts and reachable collision-free goals: the
+        # clearest of 128 random configurations per problem (the library's
+        # own kinematics and clearance), alternately start and goal
+        cand = wl.goal_configs(robot, 61 + P, 128 * P)
         qc = torch.as_tensor(cand, dtype=torch.float32, device=dev).contiguous()
         bc = ctx.batch([cand.shape[0]], [1], [0], K_max=1, m_max=0)
-        q_start = torch.as_tensor(rng.uniform(-1, 1, (P, D)), dtype=torch.float32, device=dev).contiguous()
-        dummy_goal = ctx.mg_ee_pose(q_start[:1].contiguous()).reshape(1, -1).contiguous()
-        _, _, clear = ctx.mg_cost_grad(bc, q_start[:1].contiguous(), dummy_goal, qc, grad=False)
-        order = torch.argsort(clear, descending=True, stable=True)[:P]
-        goal = ctx.mg_ee_pose(qc[order].contiguous()).reshape(P, -1).contiguous()
+        z = torch.zeros((1, D), dtype=torch.float32, device=dev)
+        zg = ctx.mg_ee_pose(z).reshape(1, -1).contiguous()
+        _, _, clear = ctx.mg_cost_grad(bc, z, zg, qc, grad=False)
+        order = torch.argsort(clear, descending=True, stable=True)[:2 * P]
+        free = (clear[order] >= 0.0).float().mean().item()
+        q_start = qc[order[0::2]].contiguous()
+        goal = ctx.mg_ee_pose(qc[order[1::2]].contiguous()).reshape(P, -1).contiguous()
         ik = ctx.batch(np.full(P, 32), np.ones(P, int), np.zeros(P, int), K_max=4, m_max=4)
         to = ctx.batch(np.full(P, 12), np.full(P, 32), np.zeros(P, int), K_max=4, m_max=4)
         x_ik0 = torch.as_tensor(rng.uniform(-2.5, 2.5, (P * 32, D)), dtype=torch.float32, device=dev)
@@ -413,12 +416,14 @@ def bench_motion_gen(warmup):
         out[f"P{P}"] = {"ms_per_call": ms, "ms_per_problem": ms / P,
                         "ik_found_fraction": ik_ok.float().mean().item(),
                         "success_fraction": ok.float().mean().item(),
-                        "mean_motion_time_s": mt.mean().item(), "dt_opt": dts[0], "dt_final": dts[1]}
+                        "mean_motion_time_s": mt.mean().item(), "dt_opt": dts[0], "dt_final": dts[1],
+                        "start_goal_collision_free": free}
     out["workload"] = ("7-DOF arm, 52 spheres, 40 oriented cuboids; IK 32 seeds x 100 iterations (K=4), "
                        "12 linear seeds x T=32, 100 iterations at dt 0.25 without jerk, retime, 100 "
                        "iterations at the retimed dt with rescaled weights, retime, choice")
-    out["note"] = ("goals are end-effector poses of the clearest of 16 random configurations; the "
-                   "straight-line seeds are not cleared of every cuboid in this budget")
+    out["note"] = ("starts and goal configurations are the clearest of 128 random configurations "
+                   "U(-2.5,2.5)^7 per problem (about 6% of random configurations are collision free "
+                   "in this world); success = goal within 5 mm / 0.05 rad and collision free")
     return out
 
 

@@ -145,8 +145,8 @@ def test_motion_gen_equals_its_steps():
     """The pipeline against mg_solve (IK), mg_ik_seeds, mg_solve_timestep
     and mg_traj_select issued one by one on a second context: bit-identical.
     Reachable goals: IK finds some; the chosen trajectories have a positive
-    motion time.  (Straight-line seeds through this world's cuboids are not
-    cleared in 70 iterations, so trajectory success is not asserted.)"""
+    motion time.  (The random starts here may lie in collision, so
+    trajectory success is not asserted.)"""
     alpha = wl.ALPHA_4
     it_ik, it1, it2 = 60, 40, 30
     rng = np.random.default_rng(44)
