@@ -120,3 +120,25 @@ def test_solve_timestep_equals_its_steps(use_graph):
     assert dt_f == np.float32(max(float(dts2[seed0 + bs2.cpu().numpy()].max()), 1e-3))
     # the retimed second pass sits on its limits: at dt_f no best seed exceeds them
     assert 0 < dt_f and dt_opt < 0.25
+
+
+def test_retime_jerk_parity():
+    """The largest |jerk| read at each seed's retimed spacing against the
+    reference's (uneven batch: horizons 2..64)."""
+    case = make_case("uneven")
+    x = case.x.clone()
+    lim = (VMAX, AMAX, JMAX)
+    dt, jk = case.ctx.mg_retime(case.b, case.q_start, x, *lim, jerk=True)
+    dt, jk = dt.cpu().numpy().astype(np.float64), jk.cpu().numpy().astype(np.float64)
+    b, D = case.batch, 7
+    xs = x.cpu().numpy().astype(np.float64)
+    seed, r0 = 0, 0
+    for p in range(b.n_problems):
+        for _ in range(int(b.seeds[p])):
+            T = int(b.horizon[p])
+            q0 = _f32(b.q_start[p])
+            dref = ref.retime(q0, xs[r0:r0 + T], 0.25, *lim)
+            want = ref.max_jerk(q0, xs[r0:r0 + T], dref)
+            assert abs(jk[seed] - want) <= 1e-3 * want + 1e-6, (p, seed, jk[seed], want)
+            seed += 1
+            r0 += T
