@@ -5,6 +5,12 @@
  * Plain, slow and literal on purpose: every quantity is computed from its
  * definition in double precision, with no blocking or fusion.  Readings of
  * passages the paper leaves open are marked "Reading:".
+ *
+ * Parity unpinned (no value in the paper to check against; pinned only by
+ * the written definition and by invariants): the swept trace's stopping
+ * rule and its surrogate gradient, the particle-stage constants (initial
+ * variance, temperature, mixing rates), and the speed metric's gradient
+ * reading (speed held fixed).
  */
 #include "mgref.h"
 

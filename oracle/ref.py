@@ -2,7 +2,10 @@
 
 Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
 import this module.  It converts the seeded workload description into the
-reference's plain double arrays and calls ``libmgref.so``.
+reference's plain double arrays and calls ``libmgref.so``.  The plain
+definitions at the end (seed ranking, linear seeds, trajectory choice,
+steering) are pinned by worked tables; the blend weights of the choice have
+no paper values (parity unpinned beyond those tables).
 """
 from __future__ import annotations
 
