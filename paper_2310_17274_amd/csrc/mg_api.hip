@@ -286,7 +286,7 @@ mg::Lanes dev_lanes(const mg_ctx* c) {
 }
 
 mg::WaveLinks dev_wave_links(const mg_ctx* c) {
-  mg::WaveLinks wl;
+  mg::WaveLinks wl{};
   wl.info = c->d_wl_info;
   wl.chain = c->d_wl_chain;
   wl.sphere = c->d_lane_sphere;
@@ -468,6 +468,21 @@ mg_status common_checks(mg_ctx* c, mg_batch* b) {
 // index hi) or wave per link.
 // Wave-per-link slices: the forced count, else enough workgroups for two
 // per CU.
+// One problem: the wave-per-link kernel forms its chunk records from the
+// workgroup index (the same records the table holds).
+void wl_single(const mg_batch* b, int K, mg::WaveLinks& wl) {
+  wl.one.S = 0;
+  if (b->P != 1) return;
+  const mg_ctx* c = b->ctx;
+  const int w = b->world[0];
+  const bool set = w + 1 < (int)c->world_off.size();
+  wl.one.S = b->seeds[0];
+  wl.one.T = b->horizon[0];
+  wl.one.box_lo = set ? c->world_off[w] : 0;
+  wl.one.box_hi = set ? c->world_off[w + 1] : 0;
+  wl.one.n_e = b->seeds[0] * b->horizon[0] * K;
+}
+
 int wl_slices(const mg_batch* b, int K) {
   if (b->wl_slices > 0) return std::min(b->wl_slices, b->wl_slices_max);
   int h = 1;
@@ -487,6 +502,7 @@ hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool gr
     a.wl.halves = halves;
     a.wl.groups = groups;
     a.wl.chunk = b->d_chunk_wl[a.K][groups - 1];
+    wl_single(b, a.K, a.wl);
     return mg::launch_eval_wl(a, b->chunks_wl[a.K][groups - 1], (halves == 2 || groups == 2) ? 1 : wl_slices(b, a.K),
                               cand, grad, s);
   }
@@ -1154,6 +1170,7 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
       a.wl.halves = halves;
       a.wl.groups = groups;
       a.wl.chunk = b->d_chunk_pm[groups - 1];
+      wl_single(b, n_particles, a.wl);
       a.wl.pm_rows = pm_rows;
       HIP_TRY(mg::launch_eval_wl(a, b->chunks_pm[groups - 1], 1, true, false, s));
     } else {
@@ -1239,6 +1256,8 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
     key_push(key, b->layout); key_push(key, b->wl_slices); key_push(key, c->n_self);
     key_push(key, b->wl_halves);
     key_push(key, b->wl_groups);
+    // (one-problem launches carry the world's cuboid range by value)
+    for (int v : c->world_off) key_push(key, v);
     for (int k = 0; k < K; ++k) key_push(key, alpha[k]);
     if (!b->gexec || key != b->gkey) {
       if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }

@@ -288,7 +288,16 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   // ---- everything is read from memory in two dependent rounds: the
   //      chunk's record and this wave's tables (scalar loads), then the
   //      workgroup's staging into LDS; after that only LDS is read ----
-  const v4i c0 = ((cv4i*)(a.wl.chunk + bx))[0], c1 = ((cv4i*)(a.wl.chunk + bx))[1];
+  // (one problem: the record follows from the workgroup index, one memory
+  // round fewer)
+  v4i c0, c1;
+  if (a.wl.one.S > 0) {
+    c0 = v4i{0, bx * E, a.wl.one.S, a.wl.one.T};
+    c1 = v4i{a.wl.one.box_lo, a.wl.one.box_hi, 0, a.wl.one.n_e};
+  } else {
+    c0 = ((cv4i*)(a.wl.chunk + bx))[0];
+    c1 = ((cv4i*)(a.wl.chunk + bx))[1];
+  }
   const int p = c0.x, e_first = c0.y;
   Problem pb;
   pb.S = c0.z; pb.T = c0.w; pb.world = 0; pb.row0 = c1.z;

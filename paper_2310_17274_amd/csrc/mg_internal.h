@@ -81,6 +81,11 @@ struct WlChunk {
 // effector) for all 64, the last wave owns the joint terms.
 struct WaveLinks {
   const WlChunk* chunk;    // [workgroups along x] (per candidate count K)
+  // one problem (one.S > 0): chunk x is {0, x E, one.S, one.T, one.box_lo,
+  // one.box_hi, 0, one.n_e}, formed without reading the table
+  struct {
+    int S, T, box_lo, box_hi, n_e;
+  } one;
   const int4* info;        // [L]: chain depth, spheres, end effector or -1, 0
   const int* chain;        // [L][kMaxDof]: links from the root down to l
   const int* joint_rec;    // [D][2]: chain position of joint j (its link's depth - 1) and
