@@ -315,7 +315,8 @@ def ik_rank(q, q0, pos_err, rot_err, clear, cost, pos_tol, rot_tol, w_dist):
     """IK seeds of one problem: the valid ones (within the success
     tolerances and collision free) in increasing pos_err + rot_err +
     w_dist |q - q0|, ties to the lower index.  With none valid, every seed
-    in increasing cost.  Returns (order, number valid)."""
+    in increasing cost.  A NaN key counts as +inf.  Returns (order, number
+    valid)."""
     S = len(pos_err)
     valid = [pos_err[s] <= pos_tol and rot_err[s] <= rot_tol and clear[s] >= 0 for s in range(S)]
     if any(valid):
@@ -323,6 +324,8 @@ def ik_rank(q, q0, pos_err, rot_err, clear, cost, pos_tol, rot_tol, w_dist):
                for s in range(S) if valid[s]}
     else:
         key = {s: cost[s] for s in range(S)}
+    # a NaN key ranks last (the order stays total)
+    key = {s: (math.inf if math.isnan(v) else v) for s, v in key.items()}
     order = sorted(key, key=lambda s: (key[s], s))
     return order, sum(valid)
 
@@ -336,12 +339,13 @@ def linear_seeds(q0, q_goal, T):
 def traj_select(T, pos_err, rot_err, clear, cost, jerk, dt, pos_tol, rot_tol, w_jerk, w_time):
     """Trajectory seeds of one problem: among the valid ones (goal reached
     within the tolerances, collision free), the lowest pos_err + rot_err +
-    w_jerk jerk + w_time (T - 1) dt, ties to the lower index; with none
+    w_jerk jerk + w_time T dt (the motion time: T intervals from the start
+    at t = 0 to waypoint T), ties to the lower index; with none
     valid, the lowest cost.  Returns (seed, valid)."""
     S = len(pos_err)
     valid = [pos_err[s] <= pos_tol and rot_err[s] <= rot_tol and clear[s] >= 0 for s in range(S)]
     if any(valid):
-        score = [pos_err[s] + rot_err[s] + w_jerk * jerk[s] + w_time * (T - 1) * dt[s] if valid[s] else math.inf
+        score = [pos_err[s] + rot_err[s] + w_jerk * jerk[s] + w_time * T * dt[s] if valid[s] else math.inf
                  for s in range(S)]
         return int(np.argmin(score)), True
     return int(np.argmin(cost)), False

@@ -25,14 +25,20 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-result"]
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
-    """Compile every source to an object (in parallel), then link libmg.so."""
+def build(verbose: bool = False, jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile every source to an object (in parallel), then link libmg.so.
+    incremental=True skips a source whose object is newer than it and than
+    every header."""
     os.makedirs(OBJDIR, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
+    hdr_t = max(os.path.getmtime(h) for h in HEADERS + [__file__])
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
         objs.append(obj)
+        if incremental and os.path.exists(obj) and \
+                os.path.getmtime(obj) > max(hdr_t, os.path.getmtime(src)):
+            continue
         cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -67,4 +73,4 @@ def is_stale() -> bool:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)

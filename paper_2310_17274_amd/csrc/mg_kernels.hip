@@ -546,13 +546,17 @@ __global__ __launch_bounds__(kBlock) void ik_seed_kernel(const IkSeedArgs a) {
       const float u = a.x_ik[(size_t)r * D + j] - q0[j];
       d2 = fmaf(u, u, d2);
     }
+    const float key = ok ? a.pe_e[2 * r] + a.pe_e[2 * r + 1] + a.w_dist * sqrtf(d2) : a.cost_e[r];
     s_ok[s] = ok;
-    s_key[s] = ok ? a.pe_e[2 * r] + a.pe_e[2 * r + 1] + a.w_dist * sqrtf(d2) : a.cost_e[r];
+    // a NaN key (a NaN cost or seed) ranks last: the order stays total
+    s_key[s] = key == key ? key : INFINITY;
+    s_order[s] = s;
     if (ok) atomicAdd(&s_nvalid, 1);
   }
   __syncthreads();
   const int nv = s_nvalid;
-  // rank among the eligible seeds: smaller key, then lower index
+  // rank among the eligible seeds: smaller key, then lower index (a
+  // permutation of 0 .. eligible - 1, so every used slot is written)
   for (int s = threadIdx.x; s < ik.S; s += kBlock) {
     if (nv > 0 && !s_ok[s]) continue;
     const float k = s_key[s];
@@ -566,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void ik_seed_kernel(const IkSeedArgs a) {
   const float inv_T = 1.0f / (float)to.T;
   for (int e = threadIdx.x; e < to.S * to.T * D; e += kBlock) {
     const int i = e / (to.T * D), rem = e - i * (to.T * D), t = rem / D, j = rem - t * D;
-    const int g = s_order[i % n_use];
+    const int g = min(max(s_order[i % n_use], 0), ik.S - 1);
     const float qs = q0[j], qg = a.x_ik[(size_t)(ik.row0 + g) * D + j];
     a.x_to[(size_t)(to.row0 + i * to.T + t) * D + j] = fmaf((float)(t + 1) * inv_T, qg - qs, qs);
   }
@@ -575,8 +579,9 @@ __global__ __launch_bounds__(kBlock) void ik_seed_kernel(const IkSeedArgs a) {
 
 // Choice among the trajectory seeds of a problem: the seeds that reach the
 // goal within the success tolerances collision free, by pos_err + rot_err +
-// w_jerk max|jerk| + w_time (T - 1) dt (the seed's retimed spacing), ties
-// to the lower index; with none, the lowest cost.
+// w_jerk max|jerk| + w_time T dt (motion time: T intervals from the start
+// at t = 0 to the last waypoint at the seed's retimed spacing dt), ties to
+// the lower index; with none, the lowest cost.
 __global__ __launch_bounds__(kBlock) void traj_select_kernel(const TrajSelectArgs a) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= a.P) return;
@@ -594,14 +599,14 @@ __global__ __launch_bounds__(kBlock) void traj_select_kernel(const TrajSelectArg
     if (c < sc) { sc = c; best_c = s; }
     if (pe <= a.pos_tol && re <= a.rot_tol && m >= 0.0f) {
       const int seed = pb.seed0 + s;
-      const float v = pe + re + a.w_jerk * a.jerk_s[seed] + a.w_time * (float)(pb.T - 1) * a.dt_s[seed];
+      const float v = pe + re + a.w_jerk * a.jerk_s[seed] + a.w_time * (float)pb.T * a.dt_s[seed];
       if (v < sv) { sv = v; best_v = s; }
     }
   }
   const int b = best_v >= 0 ? best_v : best_c;
   a.best_seed[p] = b;
   if (a.success) a.success[p] = best_v >= 0;
-  if (a.motion_time) a.motion_time[p] = (float)(pb.T - 1) * a.dt_s[pb.seed0 + b];
+  if (a.motion_time) a.motion_time[p] = (float)pb.T * a.dt_s[pb.seed0 + b];
 }
 
 __global__ __launch_bounds__(kBlock) void final_kernel(const FinalArgs a) {

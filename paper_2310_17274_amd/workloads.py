@@ -126,8 +126,15 @@ def _random_quaternion(rng: np.random.Generator, n: int) -> np.ndarray:
     return np.stack([qw, qx, qy, qz], axis=1)
 
 
+def asymmetric_limits(seed: int, dof: int):
+    """Per-joint limits that differ from joint to joint and are not
+    symmetric about 0: q_lo ~ U(-2.9, -0.6), q_hi ~ U(0.6, 2.9) rad."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-2.9, -0.6, size=dof), rng.uniform(0.6, 2.9, size=dof)
+
+
 def make_arm(seed: int = 0, dof: int = 7, n_spheres: int = 52,
-             limit: float = 2.8) -> Robot:
+             limit: float = 2.8, limits=None) -> Robot:
     """Synthetic serial arm with revolute z joints.
 
     Link l (0-based) carries joint l.  Link 0 sits on the base z axis at
@@ -136,7 +143,8 @@ def make_arm(seed: int = 0, dof: int = 7, n_spheres: int = 52,
     axes could not reach random orientations).  Offsets l ~ U(0.05, 0.35) m,
     tool = Trans(0,0,0.10).  Sphere m hangs on link (m mod D) at a fraction
     U(0.1, 0.9) of the segment to the next joint, with N(0, 0.02^2) lateral
-    scatter and radius U(0.03, 0.08) m.
+    scatter and radius U(0.03, 0.08) m.  Limits are +-limit on every joint,
+    or the per-joint arrays ``limits = (q_lo, q_hi)``.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     lengths = rng.uniform(0.05, 0.35, size=dof)
@@ -163,8 +171,8 @@ def make_arm(seed: int = 0, dof: int = 7, n_spheres: int = 52,
                  sphere=sph,
                  ee_link=np.array([dof - 1], dtype=np.int32),
                  ee_tf=ee_tf,
-                 q_lo=np.full(dof, -limit),
-                 q_hi=np.full(dof, limit))
+                 q_lo=np.full(dof, -limit) if limits is None else np.asarray(limits[0], dtype=np.float64).copy(),
+                 q_hi=np.full(dof, limit) if limits is None else np.asarray(limits[1], dtype=np.float64).copy())
 
 
 def make_two_arm(seed: int = 0, dof_per_arm: int = 7, n_spheres: int = 120,

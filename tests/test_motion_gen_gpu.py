@@ -97,6 +97,35 @@ def test_ik_seeds_parity():
     assert ok[-1] == 0 and n_valid_seen >= 2 * (wd.P - 1)
 
 
+def test_ik_seeds_with_nan_seeds():
+    """IK seeds with NaN joint values: their costs are NaN and they rank
+    last (a total order), so every trajectory seed still comes from a
+    ranked seed.  Problem 0 keeps valid seeds; problems 1.. have none."""
+    wd = World(P=3, S_ik=8, S_to=12)
+    rng = np.random.default_rng(43)
+    x = rng.uniform(-2.5, 2.5, (wd.P, wd.S_ik, 7))
+    x[0, 2] = wd.qstar[0]
+    x[0, 5] = np.nan
+    x[1, [0, 3, 4]] = np.nan
+    x[2, :] = np.nan
+    x_ik = F32(x.reshape(-1, 7))
+    x_to, ok = wd.ctx.mg_ik_seeds(wd.ik, wd.to, wd.q_start, wd.goal_d, _dev(x_ik), w_dist=0.1)
+    torch.cuda.synchronize()
+    x_to = x_to.cpu().numpy().reshape(wd.P, wd.S_to, wd.T, 7)
+    ok = ok.cpu().numpy()
+    met = wd.ik_seed_metrics(x_ik)
+    assert list(ok) == [1, 0, 0]
+    for p in range(wd.P):
+        pe, re_, mc, c = (np.array(v) for v in zip(*met[p]))
+        q = x_ik[p * wd.S_ik:(p + 1) * wd.S_ik]
+        order, nv = ref.ik_rank(q, wd.q0[p], pe, re_, mc, c, POS_TOL, ROT_TOL, 0.1)
+        n_use = nv if nv else wd.S_ik
+        for i in range(wd.S_to):
+            want = ref.linear_seeds(wd.q0[p], q[order[i % n_use]], wd.T)
+            np.testing.assert_allclose(x_to[p, i], want, rtol=0, atol=2e-6, err_msg=f"problem {p} seed {i}")
+    assert np.all(np.isfinite(x_to[0])) and np.all(np.isfinite(x_to[1, :5]))
+
+
 def _traj_inputs(wd, rng):
     """Trajectory seeds: lines from the start to q* plus an end offset of
     0 .. 0.3 rad (some miss the goal), at different detours."""
@@ -135,9 +164,9 @@ def test_traj_select_parity(w_time):
         assert ok[p] == valid, p
         if bs[p] != want:
             # only a near tie may go the other way
-            sc = lambda s: pe[s] + re_[s] + w_jerk * jk[s] + w_time * (wd.T - 1) * dts[s] if valid else c[s]
+            sc = lambda s: pe[s] + re_[s] + w_jerk * jk[s] + w_time * wd.T * dts[s] if valid else c[s]
             assert abs(sc(bs[p]) - sc(want)) <= 1e-4 * abs(sc(want)), (p, bs[p], want)
-        assert math.isclose(mt[p], (wd.T - 1) * dts[bs[p]], rel_tol=1e-4)
+        assert math.isclose(mt[p], wd.T * dts[bs[p]], rel_tol=1e-4)
     assert any_valid
 
 

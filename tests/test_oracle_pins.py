@@ -940,6 +940,10 @@ def test_ik_rank_table(oracle_lib):
     # none valid: every seed by cost
     order, nv = ref.ik_rank(q, [0.0, 0.0], [1.0] * 5, rot, clear, cost, 0.005, 0.05, 0.1)
     assert nv == 0 and order == [1, 3, 4, 2, 0]
+    # a NaN cost ranks last; the order stays a permutation
+    order, nv = ref.ik_rank(q, [0.0, 0.0], [1.0] * 5, rot, clear, [5.0, math.nan, 4.0, math.nan, 3.0],
+                            0.005, 0.05, 0.1)
+    assert nv == 0 and order == [4, 2, 0, 1, 3]
 
 
 def test_linear_seeds(oracle_lib):
@@ -948,10 +952,11 @@ def test_linear_seeds(oracle_lib):
 
 
 def test_traj_select_table(oracle_lib):
-    """Four seeds, T = 32.  Seed 0 is invalid (rotation), seed 2 collides.
-    Valid: seed 1 scores 0.001 + 0.01 * 50 + 0.1 * 31 * 0.05 = 0.656, seed 3
-    0.0 + 0.01 * 20 + 0.1 * 31 * 0.1 = 0.51.  With the time weight 1 seed 1
-    wins (2.051 against 3.3)."""
+    """Four seeds, T = 32 (motion time 32 dt: 32 intervals from the start to
+    waypoint 32).  Seed 0 is invalid (rotation), seed 2 collides.  Valid:
+    seed 1 scores 0.001 + 0.01 * 50 + 0.1 * 32 * 0.05 = 0.661, seed 3
+    0.0 + 0.01 * 20 + 0.1 * 32 * 0.1 = 0.52.  With the time weight 1 seed 1
+    wins (2.101 against 3.4)."""
     pos, rot = [0.0, 0.001, 0.0, 0.0], [0.06, 0.0, 0.0, 0.0]
     clear, cost = [0.1, 0.0, -0.01, 0.2], [1.0, 3.0, 0.5, 2.0]
     jerk, dt = [10.0, 50.0, 1.0, 20.0], [0.01, 0.05, 0.01, 0.1]
@@ -992,3 +997,130 @@ def test_steer_stops_at_the_joint_limit(oracle_lib):
     far = (np.array([[50.0, 0, 0, 1, 0, 0, 0]]), np.array([[1.0, 1.0, 1.0]]))
     h, v, dist = ref.steer(ref.Ref(robot), far, [2.5], [3.5], 0.12, robot.q_lo, robot.q_hi)
     assert h == 4 and v[0] == pytest.approx(2.5 + 4 / 9, abs=1e-15) and dist == pytest.approx(4 / 9, abs=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Success check: position error |p_g - p| and rotation angle of the relative
+# rotation between the goal and end-effector frames (the cfg tolerances
+# 5 mm / 0.05 rad are read against these).  Goals are built from the FK pose
+# by a known offset and a known rotation (scipy), so the expected errors are
+# the offset's length and the rotation's angle.
+
+@pytest.mark.parametrize("tree", [False, True], ids=["arm", "tree"])
+def test_pose_error_is_offset_length_and_rotation_angle(oracle_lib, tree):
+    robot = wl.make_two_arm(seed=0, n_spheres=8) if tree else wl.make_arm(seed=0, n_spheres=8)
+    r = ref.Ref(robot)
+    rng = np.random.default_rng(31)
+    phis = [0.0, 1e-3, 0.04, 0.7, 2.0, 3.1]
+    lens = [0.0, 0.003, 0.01, 0.2, 1.0, 0.5]
+    for phi, ln in zip(phis, lens):
+        q = rng.uniform(-2.0, 2.0, robot.dof)
+        _, _, ee = r.fk(q)
+        goal = ee.copy()
+        want_p, want_r = [], []
+        for e in range(robot.n_ee):
+            # each end effector its own offset and angle (index mix-ups fail)
+            ph, lg = phi * (1.0 - 0.3 * e), ln * (1.0 + 0.5 * e)
+            axis = rng.normal(size=3); axis /= np.linalg.norm(axis)
+            off = rng.normal(size=3); off *= lg / np.linalg.norm(off)
+            Rg = Rotation.from_quat(ee[e, [4, 5, 6, 3]]) * Rotation.from_rotvec(ph * axis)
+            x, y, z, w = Rg.as_quat()
+            goal[e, :3] = ee[e, :3] + off
+            goal[e, 3:] = (1 if e == 0 else -1) * np.array([w, x, y, z])   # the sign is free
+            want_p.append(lg)
+            want_r.append(ph)
+        pe, re = r.pose_error(q, goal)
+        np.testing.assert_allclose(pe, want_p, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(re, want_r, rtol=0, atol=2e-7)
+
+
+# ---------------------------------------------------------------------------
+# Per-joint limits (Eq.(17) and the box constraint of the candidates and
+# particles) on a robot whose limits differ from joint to joint and are not
+# symmetric: each joint is placed in a different branch of Eq.(17) for its
+# own limits, so a joint index taken from the wrong joint (or lo / hi
+# swapped) changes the result.
+
+EMPTY = (np.zeros((0, 7)), np.zeros((0, 3)))
+
+
+def _asym_arm(n_spheres=12):
+    lo, hi = wl.asymmetric_limits(7, 7)
+    return wl.make_arm(seed=0, n_spheres=n_spheres, limits=(lo, hi)), lo, hi
+
+
+def _bound_by_hand(x, l, u, eta):
+    """Eq.(17) written out branch by branch (both bands add if they overlap)."""
+    v, s = 0.0, 0.0
+    if x < l:
+        v, s = v + l - x + eta / 2, s - 1.0
+    elif x < l + eta:
+        v, s = v + (l - x + eta) ** 2 / (2 * eta), s - (l - x + eta) / eta
+    if x > u:
+        v, s = v + x - u + eta / 2, s + 1.0
+    elif x > u - eta:
+        v, s = v + (x - u + eta) ** 2 / (2 * eta), s + (x - u + eta) / eta
+    return v, s
+
+
+def test_joint_limit_cost_uses_each_joints_own_limits(oracle_lib):
+    arm_a, lo, hi = _asym_arm()
+    arm_w = wl.make_arm(seed=0, n_spheres=12, limit=10.0)   # same geometry, limits far away
+    assert np.unique(lo).size == 7 and np.unique(hi).size == 7 and np.all(lo != -hi)
+    eta = ref.DEFAULTS["eta2"]
+    T = 4
+    # branch of joint d at waypoint t: below, lower band, free, upper band, above
+    place = [lambda l, u: l - 0.03, lambda l, u: l + 0.04, lambda l, u: 0.5 * (l + u),
+             lambda l, u: u - 0.06, lambda l, u: u + 0.2]
+    q = np.array([[place[(t + d) % 5](lo[d], hi[d]) for d in range(7)] for t in range(T)])
+    q0 = np.zeros(7)
+    goal = np.array([[0.3, 0.2, 0.4, 1, 0, 0, 0]], dtype=float)
+    ca, ga, _, ta = ref.Ref(arm_a).traj_cost(EMPTY, q0, goal, q)
+    cw, gw, _, tw = ref.Ref(arm_w).traj_cost(EMPTY, q0, goal, q)
+    assert tw[1] == 0.0
+    want_c = sum(_bound_by_hand(q[t, d], lo[d], hi[d], eta)[0] for t in range(T) for d in range(7))
+    want_g = np.array([[_bound_by_hand(q[t, d], lo[d], hi[d], eta)[1] for d in range(7)] for t in range(T)])
+    wb = ref.DEFAULTS["w_bound"]
+    assert ta[1] == pytest.approx(wb * want_c, rel=1e-12)
+    assert ca - cw == pytest.approx(wb * want_c, rel=1e-9)
+    np.testing.assert_allclose(ga - gw, wb * want_g, rtol=1e-9, atol=1e-6)
+
+
+def test_linesearch_candidates_clip_to_each_joints_limits(oracle_lib):
+    """One candidate (alpha = 1) is always the choice; it must equal
+    clip(x + d) against the joint's own limits, computed here by numpy."""
+    arm_a, lo, hi = _asym_arm()
+    r = ref.Ref(arm_a)
+    rng = np.random.default_rng(41)
+    T = 5
+    x = rng.uniform(0.5 * lo, 0.5 * hi, (T, 7))
+    d = rng.choice([-4.0, 4.0], (T, 7)) * rng.uniform(0.2, 1.0, (T, 7))
+    q0 = np.zeros(7)
+    goal = np.array([[0.3, 0.2, 0.4, 1, 0, 0, 0]], dtype=float)
+    c0, g0, _, _ = r.traj_cost(EMPTY, q0, goal, x)
+    i, xo, co, go, _ = r.linesearch(EMPTY, q0, goal, x, c0, g0, d, [1.0], mode=0)
+    want = np.clip(x + d, lo, hi)
+    assert i == 0
+    assert np.any(want == lo) and np.any(want == hi)
+    np.testing.assert_array_equal(xo, want)
+    assert co == pytest.approx(r.traj_cost(EMPTY, q0, goal, want, grad=False)[0], rel=1e-14)
+
+
+def test_particles_clip_to_each_joints_limits(oracle_lib):
+    """Identical particles carry equal weights, so with k_mu = 1 the new mean
+    is the particle itself: clip(mu + sqrt(var) eps) against each joint's
+    own limits, computed here by numpy."""
+    arm_a, lo, hi = _asym_arm()
+    r = ref.Ref(arm_a)
+    rng = np.random.default_rng(42)
+    S, T, N = 2, 3, 4
+    mu = rng.uniform(0.5 * lo, 0.5 * hi, (S, T, 7))
+    var = np.full((S, T, 7), 4.0)
+    one = rng.normal(0.0, 1.5, (S, T, 7))
+    eps = np.broadcast_to(one, (1, N, S, T, 7)).copy()
+    q0 = np.zeros(7)
+    goal = np.array([[0.3, 0.2, 0.4, 1, 0, 0, 0]], dtype=float)
+    m, v, costs = r.particles(EMPTY, q0, goal, T, mu, var, eps, beta=0.0, k_mu=1.0, k_sigma=0.5)
+    want = np.clip(mu + 2.0 * one, lo, hi)
+    assert np.any(want == lo) and np.any(want == hi)
+    np.testing.assert_allclose(m, want, rtol=0, atol=1e-15)
