@@ -169,6 +169,21 @@ mg_status mg_linesearch(mg_ctx *ctx, mg_batch *batch, const float *q_start,
                         int mode, float *x_out, float *c_out, float *g_out, int *chosen,
                         float *min_clear, void *stream);
 
+/* The batched evaluation of the line-search candidates (Alg.1: every
+ * candidate of every seed costed with its gradient in one launch), without
+ * the choice: candidate k < K of a seed is clip(x + alpha_k dir, q_lo, q_hi)
+ * and is evaluated by the same launch mg_linesearch and mg_solve make for
+ * these K candidates (layout, workgroups and all).
+ *   x, dir DEVICE [rows][D]; alpha HOST [K], K <= K_max
+ *   cost DEVICE [K][seeds] total cost of each candidate
+ *   gd   DEVICE [K][seeds] directional derivative <grad C(x_k), dir>
+ *   grad DEVICE [K][rows][D] gradient of each candidate, or NULL
+ *   min_clear DEVICE [K][seeds] clearance (as mg_cost_grad), or NULL.
+ * Capturable. */
+mg_status mg_linesearch_eval(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
+                             const float *x, const float *dir, int K, const float *alpha, float *cost,
+                             float *gd, float *grad, float *min_clear, void *stream);
+
 /* Full solve (Sec. "Parallel L-BFGS Optimization"): iters iterations of
  * direction + line search + best tracking for every seed, in place.
  *   x        DEVICE [rows][D]: seeds on entry, best iterate per seed on exit
@@ -322,11 +337,13 @@ mg_status mg_ik_seeds(mg_ctx *ctx, mg_batch *ik_batch, mg_batch *to_batch, const
  * Optimized Trajectories": a blend of pose error, largest jerk and motion
  * time).  The seeds x are evaluated; those that reach the goal within the
  * success tolerances and are collision free score
- *   pos_err + rot_err + w_jerk max|jerk| + w_time (T - 1) dt_s
- * with dt_s the seed's retimed spacing (mg_retime) and max|jerk| read at it;
+ *   pos_err + rot_err + w_jerk max|jerk| + w_time T dt_s
+ * with dt_s the seed's retimed spacing (mg_retime) and max|jerk| read at it
+ * (T dt_s is the motion time: T intervals from the start, waypoint 0, to
+ * the last waypoint T);
  * the lowest wins (ties to the lower index).  A problem with no such seed
  * takes its lowest-cost seed and success = 0.
- *   best_seed DEVICE [P]; success, motion_time ((T - 1) dt_s of the chosen
+ *   best_seed DEVICE [P]; success, motion_time (T dt_s of the chosen
  *   seed) DEVICE [P] or NULL.  Capturable. */
 mg_status mg_traj_select(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
                          const float *x, const float *vmax, const float *amax, const float *jmax,

@@ -185,6 +185,19 @@ class Context:
                                        _ptr(xo), _ptr(co), _ptr(go), _ptr(ch), _ptr(mc), _stream()))
         return xo, co, go, ch, mc
 
+    def mg_linesearch_eval(self, b: Batch, q_start, goal, x, d, alpha, grad=True, min_clear=True):
+        """Every line-search candidate costed (no choice): cost, <g_k, d>,
+        min clearance [K, seeds] and gradient [K, rows, D] (or None)."""
+        K = len(alpha)
+        al = (C.c_float * K)(*alpha)
+        cost = torch.empty((K, b.n_seeds), dtype=torch.float32, device=self.device)
+        gd = torch.empty_like(cost)
+        mc = torch.empty_like(cost) if min_clear else None
+        g = torch.empty((K, b.rows, self.dof), dtype=torch.float32, device=self.device) if grad else None
+        check(_lib.lib().mg_linesearch_eval(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(x), _ptr(d),
+                                            K, al, _ptr(cost), _ptr(gd), _ptr(g), _ptr(mc), _stream()))
+        return cost, gd, g, mc
+
     def mg_solve(self, b: Batch, q_start, goal, x, iters, m, alpha, mode=1, graph_inner=25,
                  use_graph=True, outputs=None):
         """Solve in place on x; returns (x, best_cost, best_seed, success)."""

@@ -490,7 +490,10 @@ int wl_slices(const mg_batch* b, int K) {
   return h;
 }
 
-hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool grad, hipStream_t s) {
+// slices_ok = false keeps the wave-per-link layout at one workgroup per
+// chunk (no slice scratch or arrival counters of the batch).
+hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool grad, hipStream_t s,
+                         bool slices_ok = true) {
   if (use_wl(b, a.K)) {
     a.wl.part = b->wl_part;
     a.wl.count = b->wl_count;
@@ -503,20 +506,32 @@ hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool gr
     a.wl.groups = groups;
     a.wl.chunk = b->d_chunk_wl[a.K][groups - 1];
     wl_single(b, a.K, a.wl);
-    return mg::launch_eval_wl(a, b->chunks_wl[a.K][groups - 1], (halves == 2 || groups == 2) ? 1 : wl_slices(b, a.K),
-                              cand, grad, s);
+    const int wls = (halves == 2 || groups == 2 || !slices_ok) ? 1 : wl_slices(b, a.K);
+    return mg::launch_eval_wl(a, b->chunks_wl[a.K][groups - 1], wls, cand, grad, s);
   }
   return mg::launch_eval(a, b->chunks[hi], cand, grad, s);
 }
 
+// Per-(candidate, row) outputs of an evaluation launch held outside the
+// batch.
+struct EvalOut {
+  float *cost_e, *gd_e, *mc_e, *grad_e;
+};
+
 mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
                        const float* x, const float* d, int K, const float* alpha, bool grad,
-                       float* grad_out, float* pe_out, hipStream_t s) {
+                       float* grad_out, float* pe_out, hipStream_t s, const EvalOut* eo = nullptr) {
   if (needs_wl(c) && !use_wl(b, K))
     return fail(MG_ERR_UNSUPPORTED, "self-collision and the speed metric need the wave-per-link layout (at most 15 links)");
   const int hi = pick_slices(b, (long)b->rows * K);
   mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, x, d, K, alpha);
   if (grad_out) a.grad_e = grad_out;
+  if (eo) {
+    a.cost_e = eo->cost_e;
+    a.gd_e = eo->gd_e;
+    a.mc_e = eo->mc_e;
+    a.grad_e = eo->grad_e;
+  }
   a.pe_e = pe_out;
   const int slot = b->ev_next;
   // events are recorded around direct launches only (an event recorded while
@@ -528,7 +543,7 @@ mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
     timed = cs == hipStreamCaptureStatusNone;
   }
   if (timed) HIP_TRY(hipEventRecord(b->ev_start[slot], s));
-  HIP_TRY(launch_layout(b, a, hi, d != nullptr, grad, s));
+  HIP_TRY(launch_layout(b, a, hi, d != nullptr, grad, s, eo == nullptr));
   if (timed) {
     HIP_TRY(hipEventRecord(b->ev_stop[slot], s));
     b->ev_next = (slot + 1) % (int)b->ev_start.size();
@@ -560,7 +575,7 @@ mg::LbfgsArgs lbfgs_args(mg_ctx* c, mg_batch* b, int m, int reset, const float* 
 mg_status enqueue_select(mg_ctx* c, mg_batch* b, const float* x, const float* c0, const float* g0,
                          const float* d, int K, const float* alpha, int mode, float* x_out,
                          float* c_out, float* g_out, int* chosen, float* mc_out, bool track,
-                         const mg::LbfgsArgs* fuse, hipStream_t s) {
+                         const mg::LbfgsArgs* fuse, hipStream_t s, const EvalOut* eo = nullptr) {
   mg::SelectArgs a;
   memset(&a, 0, sizeof(a));
   a.seeds = b->d_seed;
@@ -577,6 +592,7 @@ mg_status enqueue_select(mg_ctx* c, mg_batch* b, const float* x, const float* c0
   a.q_hi = c->d_q_hi;
   a.x = x; a.c0 = c0; a.g0 = g0; a.d = d;
   a.cost_e = b->cost_e; a.gd_e = b->gd_e; a.mc_e = b->mc_e; a.grad_e = b->grad_e;
+  if (eo) { a.cost_e = eo->cost_e; a.gd_e = eo->gd_e; a.mc_e = eo->mc_e; a.grad_e = eo->grad_e; }
   a.x_out = x_out; a.c_out = c_out; a.g_out = g_out; a.chosen = chosen; a.mc_out = mc_out;
   a.track = track ? 1 : 0;
   a.best_c = b->best_c;
@@ -960,6 +976,28 @@ mg_status mg_linesearch(mg_ctx* c, mg_batch* b, const float* q_start, const floa
   if ((st = enqueue_eval(c, b, q_start, goal, x, dir, K, alpha, true, nullptr, nullptr, s)) != MG_OK) return st;
   return enqueue_select(c, b, x, c0, g0, dir, K, alpha, mode, x_out, c_out, g_out, chosen, min_clear, false,
                         nullptr, s);
+}
+
+mg_status mg_linesearch_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
+                             const float* x, const float* dir, int K, const float* alpha, float* cost,
+                             float* gd, float* grad, float* min_clear, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if ((st = check_K_alpha(b, K, alpha)) != MG_OK) return st;
+  if (!q_start || !goal || !x || !dir || !cost || !gd) return fail(MG_ERR_ARG, "null argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the launch mg_linesearch and mg_solve make for these K candidates
+  if ((st = enqueue_eval(c, b, q_start, goal, x, dir, K, alpha, true, nullptr, nullptr, s)) != MG_OK) return st;
+  const size_t R = b->rows;
+  for (int k = 0; k < K; ++k) {
+    mg::ReduceArgs rc{b->d_seed, b->n_seeds, b->cost_e + k * R, b->mc_e + k * R, cost + (size_t)k * b->n_seeds,
+                      min_clear ? min_clear + (size_t)k * b->n_seeds : nullptr};
+    HIP_TRY(mg::launch_reduce(rc, s));
+    mg::ReduceArgs rg{b->d_seed, b->n_seeds, b->gd_e + k * R, b->mc_e + k * R, gd + (size_t)k * b->n_seeds, nullptr};
+    HIP_TRY(mg::launch_reduce(rg, s));
+  }
+  if (grad) HIP_TRY(mg::launch_copy(b->grad_e, grad, (size_t)K * R * c->D, s));
+  return MG_OK;
 }
 
 mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,

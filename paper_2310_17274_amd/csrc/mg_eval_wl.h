@@ -485,10 +485,15 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
         if (CAND && GRAD && tw) {
           // group 1's velocity is in P0's frame: omega_1 = R0 omega_1',
           // v_1 = R0 v_1' + p0 x omega_1
-          float w1[3] = {g ? wx : other32(wx, lane), g ? wy : other32(wy, lane), g ? wz : other32(wz, lane)};
-          float u1[3] = {g ? vx : other32(vx, lane), g ? vy : other32(vy, lane), g ? vz : other32(vz, lane)};
-          float w0[3] = {g ? other32(wx, lane) : wx, g ? other32(wy, lane) : wy, g ? other32(wz, lane) : wz};
-          float u0[3] = {g ? other32(vx, lane) : vx, g ? other32(vy, lane) : vy, g ? other32(vz, lane) : vz};
+          // (the other group's values are fetched by every lane first: a
+          // conditional operator evaluates only the operand it selects, and
+          // a lane swap inside one would run with half the wave inactive)
+          const float ox_[6] = {other32(wx, lane), other32(wy, lane), other32(wz, lane),
+                                other32(vx, lane), other32(vy, lane), other32(vz, lane)};
+          float w1[3] = {g ? wx : ox_[0], g ? wy : ox_[1], g ? wz : ox_[2]};
+          float u1[3] = {g ? vx : ox_[3], g ? vy : ox_[4], g ? vz : ox_[5]};
+          float w0[3] = {g ? ox_[0] : wx, g ? ox_[1] : wy, g ? ox_[2] : wz};
+          float u0[3] = {g ? ox_[3] : vx, g ? ox_[4] : vy, g ? ox_[5] : vz};
           float Rw[3], Ru[3];
 #pragma unroll
           for (int r = 0; r < 3; ++r) {
