@@ -184,6 +184,25 @@ mg_status mg_linesearch_eval(mg_ctx *ctx, mg_batch *batch, const float *q_start,
                              const float *x, const float *dir, int K, const float *alpha, float *cost,
                              float *gd, float *grad, float *min_clear, void *stream);
 
+/* mg_linesearch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, checks and results as mg_linesearch, but the
+ * per-(candidate, row) costs, directional derivatives, clearances and
+ * gradients of the call live in a static device array of the library
+ * (16 MiB per GPU, held until the process ends) instead of the batch's
+ * workspace.  The call allocates nothing; K * rows * (3 + D) floats (each
+ * of the first three parts rounded up to 64) must fit in 4 Mi floats, else
+ * MG_ERR_SHAPE.  The wave-per-link layout runs with one workgroup per
+ * chunk (no cuboid slices over workgroups).  Every call on one GPU shares
+ * that GPU's array and overwrites it: calls that overlap on one GPU (other
+ * streams, other threads, other contexts) race.  Nothing in the array needs
+ * clearing between calls.  Capturable. */
+mg_status mg_linesearch_noalloc(mg_ctx *ctx, mg_batch *batch, const float *q_start,
+                                const float *goal, const float *x, const float *c0,
+                                const float *g0, const float *dir, int K, const float *alpha,
+                                int mode, float *x_out, float *c_out, float *g_out, int *chosen,
+                                float *min_clear, void *stream);
+
 /* Full solve (Sec. "Parallel L-BFGS Optimization"): iters iterations of
  * direction + line search + best tracking for every seed, in place.
  *   x        DEVICE [rows][D]: seeds on entry, best iterate per seed on exit

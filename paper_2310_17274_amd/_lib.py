@@ -22,7 +22,7 @@ STATUS = {0: "MG_OK", -1: "MG_ERR_ARG", -2: "MG_ERR_SHAPE", -3: "MG_ERR_HIP",
 # Every symbol include/mg.h declares.
 EXPORTS = ("mg_default_params", "mg_create", "mg_destroy", "mg_set_params", "mg_set_worlds",
            "mg_batch_create", "mg_batch_destroy", "mg_batch_seeds", "mg_batch_rows",
-           "mg_cost_grad", "mg_lbfgs_step", "mg_linesearch", "mg_linesearch_eval",
+           "mg_cost_grad", "mg_lbfgs_step", "mg_linesearch", "mg_linesearch_eval", "mg_linesearch_noalloc",
            "mg_solve",
            "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
            "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose", "mg_set_self_collision",
@@ -79,6 +79,7 @@ def lib():
     L.mg_lbfgs_step.argtypes = [_vp, _vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp]
     L.mg_linesearch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _fp, C.c_int,
                                 _vp, _vp, _vp, _vp, _vp, _vp]
+    L.mg_linesearch_noalloc.argtypes = L.mg_linesearch.argtypes
     L.mg_linesearch_eval.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _fp, _vp, _vp, _vp, _vp, _vp]
     L.mg_solve.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, C.c_int, _fp, C.c_int,
                            C.c_int, C.c_int, _vp, _vp, _vp, _vp]
@@ -110,7 +111,7 @@ def lib():
     L.mg_last_error.argtypes = []
     L.mg_last_error.restype = C.c_char_p
     for name in ("mg_create", "mg_set_params", "mg_set_worlds", "mg_batch_create", "mg_cost_grad",
-                 "mg_lbfgs_step", "mg_linesearch", "mg_linesearch_eval", "mg_solve",
+                 "mg_lbfgs_step", "mg_linesearch", "mg_linesearch_eval", "mg_linesearch_noalloc", "mg_solve",
                  "mg_batch_seeds", "mg_batch_rows",
                  "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
                  "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose",

@@ -198,6 +198,20 @@ class Context:
                                             K, al, _ptr(cost), _ptr(gd), _ptr(g), _ptr(mc), _stream()))
         return cost, gd, g, mc
 
+    def mg_linesearch_noalloc(self, b: Batch, q_start, goal, x, c0, g0, d, alpha, mode=1, out=None):
+        """mg_linesearch with its per-candidate results in the library's static
+        scratch (no device allocation in the call); out as mg_linesearch's."""
+        al = (C.c_float * len(alpha))(*alpha)
+        if out is None:
+            out = (torch.empty_like(x), torch.empty_like(c0), torch.empty_like(g0),
+                   torch.empty(b.n_seeds, dtype=torch.int32, device=self.device),
+                   torch.empty(b.n_seeds, dtype=torch.float32, device=self.device))
+        xo, co, go, ch, mc = out
+        check(_lib.lib().mg_linesearch_noalloc(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(x),
+                                               _ptr(c0), _ptr(g0), _ptr(d), len(alpha), al, int(mode),
+                                               _ptr(xo), _ptr(co), _ptr(go), _ptr(ch), _ptr(mc), _stream()))
+        return xo, co, go, ch, mc
+
     def mg_solve(self, b: Batch, q_start, goal, x, iters, m, alpha, mode=1, graph_inner=25,
                  use_graph=True, outputs=None):
         """Solve in place on x; returns (x, best_cost, best_seed, success)."""

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <queue>
 #include <random>
 #include <string>
@@ -107,6 +108,7 @@ struct mg_ctx {
   std::vector<int> world_off;    // host copy of the cuboid offsets
   std::vector<mg_batch*> batches;   // live batches (their chunk records name cuboid ranges)
   hipStream_t cap_stream = nullptr;
+  float* d_scratch = nullptr;    // this device's copy of the static scratch array
 };
 
 struct mg_batch {
@@ -513,7 +515,7 @@ hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool gr
 }
 
 // Per-(candidate, row) outputs of an evaluation launch held outside the
-// batch.
+// batch (the allocation-free entry point's static scratch).
 struct EvalOut {
   float *cost_e, *gd_e, *mc_e, *grad_e;
 };
@@ -618,6 +620,38 @@ mg_status check_K_alpha(const mg_batch* b, int K, const float* alpha) {
 
 }  // namespace
 
+// Scratch of the allocation-free line search (mg_linesearch_noalloc): the
+// per-(candidate, row) cost, directional derivative, clearance and
+// gradient of one call.  Every GPU the library runs on holds its own copy
+// (16 MiB) until the process ends.  Host code never passes the array's name
+// to a kernel (on the host it is a stand-in, not a device address); it uses
+// the per-device address from hipGetSymbolAddress.
+static constexpr size_t kScratchFloats = (size_t)4 << 20;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<float*> g_scratch_dev;   // per device ordinal: the address of `scratch`
+
+// The current device's address of `scratch`, looked up once per device.
+mg_status scratch_address(int device, float** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0) return fail(MG_ERR_ARG, "bad device ordinal %d", device);
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize(device + 1, nullptr);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MG_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[device] = static_cast<float*>(p);
+  }
+  *out = g_scratch_dev[device];
+  return MG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void mg_default_params(mg_params* p) {
@@ -673,6 +707,10 @@ mg_status mg_create(const mg_robot_desc* r, const mg_params* params, mg_ctx** ou
 
   mg_ctx* c = new mg_ctx();
   (void)hipGetDevice(&c->device);
+  if ((st = scratch_address(c->device, &c->d_scratch)) != MG_OK) {
+    delete c;
+    return st;
+  }
   {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess && v > 0)
@@ -998,6 +1036,31 @@ mg_status mg_linesearch_eval(mg_ctx* c, mg_batch* b, const float* q_start, const
   }
   if (grad) HIP_TRY(mg::launch_copy(b->grad_e, grad, (size_t)K * R * c->D, s));
   return MG_OK;
+}
+
+mg_status mg_linesearch_noalloc(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
+                                const float* x, const float* c0, const float* g0, const float* dir, int K,
+                                const float* alpha, int mode, float* x_out, float* c_out, float* g_out,
+                                int* chosen, float* min_clear, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if ((st = check_K_alpha(b, K, alpha)) != MG_OK) return st;
+  if (mode < 0 || mode > 2) return fail(MG_ERR_ARG, "mode must be 0, 1 or 2");
+  if (!q_start || !goal || !x || !c0 || !g0 || !dir || !x_out || !c_out || !g_out)
+    return fail(MG_ERR_ARG, "null argument");
+  if (!c->d_scratch) return fail(MG_ERR_STATE, "no scratch address for this context's device");
+  // [K][rows] cost, directional derivative, clearance, then [K][rows][D]
+  // gradient, each part starting on a 256-byte boundary
+  const size_t KR = (size_t)K * b->rows, part = (KR + 63) & ~(size_t)63;
+  const size_t need = 3 * part + KR * c->D;
+  if (need > kScratchFloats)
+    return fail(MG_ERR_SHAPE, "K * rows * (3 + D) = %zu floats exceeds the static scratch of %zu floats",
+                need, kScratchFloats);
+  const EvalOut eo{c->d_scratch, c->d_scratch + part, c->d_scratch + 2 * part, c->d_scratch + 3 * part};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if ((st = enqueue_eval(c, b, q_start, goal, x, dir, K, alpha, true, nullptr, nullptr, s, &eo)) != MG_OK) return st;
+  return enqueue_select(c, b, x, c0, g0, dir, K, alpha, mode, x_out, c_out, g_out, chosen, min_clear, false,
+                        nullptr, s, &eo);
 }
 
 mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal,
