@@ -8,9 +8,8 @@
  *
  * Parity unpinned (no value in the paper to check against; pinned only by
  * the written definition and by invariants): the swept trace's stopping
- * rule and its surrogate gradient, the particle-stage constants (initial
- * variance, temperature, mixing rates), and the speed metric's gradient
- * reading (speed held fixed).
+ * rule and its surrogate gradient, and the particle-stage constants
+ * (initial variance, temperature, mixing rates).
  */
 #include "mgref.h"
 
@@ -465,9 +464,12 @@ double mgref_traj_cost(const mgref_robot *rb, const mgref_params *pr,
      * obstacles'), when on, scales the sphere's collision cost by the
      * sphere's speed from the central difference of its neighbouring
      * positions, |c(t+1) - c(t-1)| / (2 dt), on the padded trajectory (the
-     * start before waypoint 1, waypoint T repeated after it).  Reading: the
-     * gradient holds the speed fixed and acts through the collision distance
-     * at c(t) only, as the swept surrogate does. */
+     * start before waypoint 1, waypoint T repeated after it).  The gradient
+     * is the derivative of that product: the speed times the collision
+     * gradient at c(t), plus the collision cost times the speed's gradient,
+     * which acts on the two neighbouring positions (the unit chord / (2 dt)
+     * on c(t+1), or on c(t) itself at t = T, and its negative on c(t-1),
+     * none on the constant start). */
     for (int m = 0; m < M; ++m) {
       const double *c = sp + (t * M + m) * 3;
       double r = rb->sphere[m * 4 + 3];
@@ -480,7 +482,19 @@ double mgref_traj_cost(const mgref_robot *rb, const mgref_params *pr,
       if (pr->speed) {
         const double *cp = sp + ((t - 1) * M + m) * 3, *cn = t < T ? sp + ((t + 1) * M + m) * 3 : c;
         double u[3] = {cn[0] - cp[0], cn[1] - cp[1], cn[2] - cp[2]};
-        const double speed = sqrt(dot3(u, u)) / (2.0 * pr->dt);
+        const double un = sqrt(dot3(u, u));
+        const double speed = un / (2.0 * pr->dt);
+        if (grad && cm != 0.0 && un > 0.0) {
+          /* d speed / d cn = u / (|u| 2 dt), d speed / d cp = -u / (|u| 2 dt) */
+          double gs[3];
+          for (int i = 0; i < 3; ++i) gs[i] = cm * u[i] / (un * 2.0 * pr->dt);
+          const int tn = t < T ? t + 1 : t;
+          project_point(rb, tf + tn * L * 12, rb->sphere_link[m], cn, gs, grad + (tn - 1) * D);
+          if (t >= 2) {
+            for (int i = 0; i < 3; ++i) gs[i] = -gs[i];
+            project_point(rb, tf + (t - 1) * L * 12, rb->sphere_link[m], cp, gs, grad + (t - 2) * D);
+          }
+        }
         cm *= speed;
         for (int i = 0; i < 3; ++i) gc[i] *= speed;
       }

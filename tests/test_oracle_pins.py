@@ -866,7 +866,12 @@ def test_retime_at_rest_and_retimed_trajectory_sits_on_its_limit(oracle_lib):
 # so the collision term lives at k alone.  The sphere's central-difference speed there is the chord between
 # its neighbours over 2 dt: 2 sin(delta) / (2 dt) inside the trajectory
 # (waypoint 1's left neighbour is the start) and 2 sin(delta / 2) / (2 dt)
-# at T, whose right neighbour is itself.
+# at T, whose right neighbour is itself.  The speed's gradient moves the
+# neighbours along the chord: with the plain collision cost D at k, the unit
+# chord u and the joint's point velocity z x c (tangent to the circle), the
+# neighbour k + 1 gets D (u . z x c(k+1)) / (2 dt) = D cos(delta) / (2 dt)
+# and k - 1 the negative (none for the start); at T the chord is c(T) -
+# c(T - 1), and T itself gets D cos(delta / 2) / (2 dt), T - 1 the negative.
 
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_speed_metric_scales_the_collision_term(oracle_lib, k):
@@ -883,10 +888,37 @@ def test_speed_metric_scales_the_collision_term(oracle_lib, k):
     factor = (math.sin(delta) if k < T else math.sin(delta / 2)) / dt
     assert plain[0] > 0 and plain[2] == pytest.approx(math.hypot(0.04, 0.01) - 0.05, abs=1e-12)
     assert fast[0] == pytest.approx(factor * plain[0], rel=1e-12)
-    # the gradient holds the speed fixed: the same factor, waypoint k only
+    # the gradient: the speed times the plain gradient at k, plus the speed's
+    # gradient on the neighbours (closed forms above)
     assert np.count_nonzero(plain[1]) == 1 and plain[1][k - 1, 0] != 0
-    np.testing.assert_allclose(fast[1], factor * plain[1], rtol=1e-12, atol=0)
+    D = plain[0]
+    want = factor * plain[1].copy()
+    if k < T:
+        want[k, 0] += D * math.cos(delta) / (2 * dt)
+        if k >= 2:
+            want[k - 2, 0] -= D * math.cos(delta) / (2 * dt)
+    else:
+        want[k - 1, 0] += D * math.cos(delta / 2) / (2 * dt)
+        want[k - 2, 0] -= D * math.cos(delta / 2) / (2 * dt)
+    np.testing.assert_allclose(fast[1], want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
     assert fast[2] == plain[2]
+
+
+@pytest.mark.parametrize("vel_all", [0, 1])
+def test_speed_metric_gradient_matches_central_differences(oracle_lib, vel_all):
+    """With the speed metric on (no swept trace), the gradient is the exact
+    derivative of the cost: FP64 central differences, as for P5."""
+    robot, boxes, q0, goal, q = make_problem(seed=9, T=6)
+    r = ref.Ref(robot, speed=1, vel_all=vel_all)
+    c, g, _, terms = r.traj_cost(boxes, q0, goal, q)
+    assert terms[2] > 0
+    h = 1e-6
+    fd = np.zeros_like(q)
+    for idx in np.ndindex(q.shape):
+        qp = q.copy(); qp[idx] += h
+        qm = q.copy(); qm[idx] -= h
+        fd[idx] = (r.traj_cost(boxes, q0, goal, qp, grad=False)[0] - r.traj_cost(boxes, q0, goal, qm, grad=False)[0]) / (2 * h)
+    assert np.linalg.norm(g - fd) <= 1e-6 * np.linalg.norm(fd)
 
 
 def test_speed_metric_at_rest_and_far_away(oracle_lib):
