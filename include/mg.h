@@ -96,8 +96,12 @@ typedef struct {
   int speed;                /* 1: speed metric of Eq.(11) (default 0): each sphere's world
                                collision cost times its speed |c(t+1) - c(t-1)| / (2 dt) on
                                the padded trajectory (start before waypoint 1, waypoint T
-                               after T); the gradient holds the speed fixed.  Evaluated by
-                               the wave-per-link layout only (robots of at most 15 links). */
+                               after T), with its exact gradient (the speed's gradient acts
+                               on the neighbouring waypoints; a second launch adds it).
+                               Evaluated by the wave-per-link layout only (robots of at
+                               most 15 links), one workgroup per 64 evaluations; batches
+                               keep a [K_max][rows][spheres] float4 buffer for it while it
+                               is on (allocated by mg_batch_create / mg_set_params). */
 } mg_params;
 
 void mg_default_params(mg_params *out);
@@ -193,7 +197,8 @@ mg_status mg_linesearch_eval(mg_ctx *ctx, mg_batch *batch, const float *q_start,
  * workspace.  The call allocates nothing; K * rows * (3 + D) floats (each
  * of the first three parts rounded up to 64) must fit in 4 Mi floats, else
  * MG_ERR_SHAPE.  The wave-per-link layout runs with one workgroup per
- * chunk (no cuboid slices over workgroups).  Every call on one GPU shares
+ * chunk (no cuboid slices over workgroups); with the speed metric on it
+ * returns MG_ERR_UNSUPPORTED.  Every call on one GPU shares
  * that GPU's array and overwrites it: calls that overlap on one GPU (other
  * streams, other threads, other contexts) race.  Nothing in the array needs
  * clearing between calls.  Capturable. */

@@ -154,6 +154,9 @@ struct mg_batch {
   int pm_K = 0;
   mg::WlChunk* d_chunk_pm[2] = {};
   int chunks_pm[2] = {};
+  // speed metric with gradients: per (candidate, row, sphere) terms of the
+  // speed's gradient [K_max][rows][M] (allocated while the metric is on)
+  float4* sp_h = nullptr;
 };
 
 namespace {
@@ -411,7 +414,15 @@ mg::EvalArgs eval_args(const mg_ctx* c, const mg_batch* b, int hi, const float* 
   a.mc_e = b->mc_e;
   a.grad_e = b->grad_e;
   a.pe_e = nullptr;
+  a.sp_h = c->params.speed ? b->sp_h : nullptr;
   return a;
+}
+
+// The speed metric's per-(candidate, row, sphere) buffer of a batch,
+// allocated once the metric is on.
+mg_status ensure_speed_buf(mg_batch* b) {
+  if (b->sp_h || !b->ctx || !b->ctx->params.speed || b->ctx->M == 0) return MG_OK;
+  return dev_alloc(&b->sp_h, (size_t)b->K_max * b->rows * b->ctx->M);
 }
 
 // Wave-per-link chunk records of a batch for K candidates per row and E
@@ -508,7 +519,8 @@ hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool gr
     a.wl.groups = groups;
     a.wl.chunk = b->d_chunk_wl[a.K][groups - 1];
     wl_single(b, a.K, a.wl);
-    const int wls = (halves == 2 || groups == 2 || !slices_ok) ? 1 : wl_slices(b, a.K);
+    // (the speed's gradient terms need every cuboid of a sphere in one workgroup)
+    const int wls = (halves == 2 || groups == 2 || !slices_ok || (a.sp_h && grad)) ? 1 : wl_slices(b, a.K);
     return mg::launch_eval_wl(a, b->chunks_wl[a.K][groups - 1], wls, cand, grad, s);
   }
   return mg::launch_eval(a, b->chunks[hi], cand, grad, s);
@@ -545,11 +557,40 @@ mg_status enqueue_eval(mg_ctx* c, mg_batch* b, const float* q_start, const float
     timed = cs == hipStreamCaptureStatusNone;
   }
   if (timed) HIP_TRY(hipEventRecord(b->ev_start[slot], s));
+  if (c->params.speed && grad && !a.sp_h && c->M > 0)
+    return fail(MG_ERR_STATE, "the speed metric's gradient buffer is missing");
   HIP_TRY(launch_layout(b, a, hi, d != nullptr, grad, s, eo == nullptr));
   if (timed) {
     HIP_TRY(hipEventRecord(b->ev_stop[slot], s));
     b->ev_next = (slot + 1) % (int)b->ev_start.size();
     b->ev_count = std::min(b->ev_count + 1, (int)b->ev_start.size());
+  }
+  if (a.sp_h && grad) {
+    // the speed's gradient on the neighbouring waypoints (Eq.(11))
+    mg::SpeedAdjArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    sa.seeds = b->d_seed;
+    sa.n_seeds = b->n_seeds;
+    sa.rows = b->rows;
+    sa.dof = c->D;
+    sa.n_links = c->L;
+    sa.n_spheres = c->M;
+    sa.K = K;
+    sa.maxs = c->maxs;
+    for (int k = 0; k < K; ++k) sa.alpha[k] = alpha ? alpha[k] : 0.0f;
+    sa.cand = d != nullptr;
+    sa.fixed_tf = c->d_fixed_tf;
+    sa.q_lo = c->d_q_lo;
+    sa.q_hi = c->d_q_hi;
+    sa.info = c->d_wl_info;
+    sa.sphere = c->d_lane_sphere;
+    sa.slot_sphere = c->d_slot_sphere;
+    sa.x = x;
+    sa.d = d;
+    sa.sp_h = a.sp_h;
+    sa.grad_e = a.grad_e;
+    sa.gd_e = a.gd_e;
+    HIP_TRY(mg::launch_speed_adjoint(sa, s));
   }
   return MG_OK;
 }
@@ -765,6 +806,8 @@ mg_status mg_set_params(mg_ctx* c, const mg_params* params) {
   if (params->speed && !wl_possible(c))
     return fail(MG_ERR_UNSUPPORTED, "the speed metric needs the wave-per-link layout (at most 15 links)");
   c->params = to_dev(*params);
+  for (mg_batch* b : c->batches)
+    if ((st = ensure_speed_buf(b)) != MG_OK) return st;
   return MG_OK;
 }
 
@@ -884,6 +927,7 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
       (st = dev_alloc(&b->meta, 2 * n_seeds)) != MG_OK || (st = dev_alloc(&b->sel_dt, n_seeds)) != MG_OK ||
       (st = dev_alloc(&b->sel_jerk, n_seeds)) != MG_OK)
     return bail(st);
+  if ((st = ensure_speed_buf(b)) != MG_OK) return bail(st);
   // zero the history metadata so a first step without reset is well defined
   if (hipMemset(b->meta, 0, 2 * n_seeds * sizeof(int)) != hipSuccess ||
       hipMemset(b->first, 0, n_seeds * sizeof(int)) != hipSuccess ||
@@ -912,7 +956,7 @@ void mg_batch_destroy(mg_batch* b) {
   dev_free(b->c_cur); dev_free(b->g_cur); dev_free(b->dir); dev_free(b->best_c); dev_free(b->best_x);
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
   dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost); dev_free(b->sel_dt); dev_free(b->sel_jerk);
-  dev_free(b->wl_part); dev_free(b->wl_count);
+  dev_free(b->wl_part); dev_free(b->wl_count); dev_free(b->sp_h);
   delete b;
 }
 
@@ -1049,6 +1093,8 @@ mg_status mg_linesearch_noalloc(mg_ctx* c, mg_batch* b, const float* q_start, co
   if (!q_start || !goal || !x || !c0 || !g0 || !dir || !x_out || !c_out || !g_out)
     return fail(MG_ERR_ARG, "null argument");
   if (!c->d_scratch) return fail(MG_ERR_STATE, "no scratch address for this context's device");
+  if (c->params.speed)
+    return fail(MG_ERR_UNSUPPORTED, "the speed metric's gradient needs the batch's workspace (use mg_linesearch)");
   // [K][rows] cost, directional derivative, clearance, then [K][rows][D]
   // gradient, each part starting on a 256-byte boundary
   const size_t KR = (size_t)K * b->rows, part = (KR + 63) & ~(size_t)63;

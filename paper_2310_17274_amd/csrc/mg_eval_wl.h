@@ -144,13 +144,16 @@ struct SweepCtx {
   bool on, has_next;
 };
 
-template <int MAXS, bool SW>
+// SP (speed metric): ws holds each slot's speed; the pair's cost and
+// gradient are formed at weight w0 (w_coll), summed per slot into dsl (the
+// slot's collision cost before the speed) and scaled by the speed.
+template <int MAXS, bool SW, bool SP>
 __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane, float cwx, float cwy,
                                            float cwz, float Rw, float bx, float by, float bz, float rl,
                                            const float* cx, const float* cy, const float* cz,
                                            const float* rr, const float* rho, const SweepCtx& sw, const float* ws,
-                                           float eta, float inv_eta, float& cost, float& mc, float& Fx,
-                                           float& Fy, float& Fz, float& Mx, float& My, float& Mz) {
+                                           float w0, float* dsl, float eta, float inv_eta, float& cost, float& mc,
+                                           float& Fx, float& Fy, float& Fz, float& Mx, float& My, float& Mz) {
   // lane j tests cuboid j of the tile against the wave's ball
   bool cand = false;
   if (lane < nb) {
@@ -220,11 +223,19 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
           if (m3[u] < rho[s]) {
             const float px = ppx[u], py = ppy[u], pz = ppz[u];
             float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+            float cs = 0.0f;
+            float& cacc = SP ? cs : cost;
+            const float wp = SP ? w0 : ws[s];
             const float sdf = near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y,
-                                        fabsf(pz) - Hh.z, rr[s], ws[s], eta, inv_eta, cost, mc, gx, gy, gz);
+                                        fabsf(pz) - Hh.z, rr[s], wp, eta, inv_eta, cacc, mc, gx, gy, gz);
             if (SW && sw.on)
               sweep_pair_ls(sw.sl[s], sw.steps, sw.Tp, sw.Tn, sw.has_next, cx[s], cy[s], cz[s], A0, A1, A2,
-                            Hh, px, py, pz, sdf, rr[s], ws[s], eta, inv_eta, cost, gx, gy, gz);
+                            Hh, px, py, pz, sdf, rr[s], wp, eta, inv_eta, cacc, gx, gy, gz);
+            if constexpr (SP) {
+              dsl[s] += cs;
+              cost = fmaf(ws[s], cs, cost);
+              gx *= ws[s]; gy *= ws[s]; gz *= ws[s];
+            }
             Fx += gx; Fy += gy; Fz += gz;
             Mx += cy[s] * gz - cz[s] * gy;
             My += cz[s] * gx - cx[s] * gz;
@@ -433,16 +444,21 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   // swept collision: the link's poses at the neighbouring waypoints (the
   // start before waypoint 1; one waypoint alone has no segments)
   // SW also carries the speed metric (Eq.(11)): each sphere's collision
-  // weight times |c(t+1) - c(t-1)| / (2 dt), the start before waypoint 1 and
-  // waypoint T after T; the gradient holds the speed fixed
+  // cost times |c(t+1) - c(t-1)| / (2 dt), the start before waypoint 1 and
+  // waypoint T after T; the speed's own gradient, on the neighbouring
+  // waypoints, is added by speed_adjoint_kernel from the per-sphere terms
+  // written below (sp_h)
   float Tp[SW ? 12 : 1], Tn[SW ? 12 : 1];
   const bool sweep = SW && a.pr.swept && pb.T > 1;
   const bool spd = SP && a.pr.speed;
   const bool nxt = t + 1 < pb.T;
   const bool has_next = sweep && nxt;
-  float ws[MAXS];
+  float ws[MAXS];    // each slot's collision weight (SP: its speed)
+  float dsl[SP ? MAXS : 1];   // SP: each slot's collision cost before the speed
 #pragma unroll
-  for (int s = 0; s < MAXS; ++s) ws[s] = a.pr.w_coll;
+  for (int s = 0; s < MAXS; ++s) ws[s] = SP ? 0.0f : a.pr.w_coll;
+#pragma unroll
+  for (int s = 0; s < (SP ? MAXS : 1); ++s) dsl[s] = 0.0f;
   float ext = 0.0f;   // the largest half segment over this lane's slots
   if (link_w) {
     // With CAND and GRAD the pass also forms the link's velocity under the
@@ -537,7 +553,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
           const float ux = (Tn[0] - Tp[0]) * ls.x + (Tn[1] - Tp[1]) * ls.y + (Tn[2] - Tp[2]) * ls.z + (Tn[3] - Tp[3]);
           const float uy = (Tn[4] - Tp[4]) * ls.x + (Tn[5] - Tp[5]) * ls.y + (Tn[6] - Tp[6]) * ls.z + (Tn[7] - Tp[7]);
           const float uz = (Tn[8] - Tp[8]) * ls.x + (Tn[9] - Tp[9]) * ls.y + (Tn[10] - Tp[10]) * ls.z + (Tn[11] - Tp[11]);
-          ws[s] = a.pr.w_coll * sqrtf(ux * ux + uy * uy + uz * uz) * (0.5f / a.pr.dt);
+          ws[s] = sqrtf(ux * ux + uy * uy + uz * uz) * (0.5f / a.pr.dt);
         }
         // every trace sample lies within half a segment of the centre and the
         // distance is 1-Lipschitz, so r + eta + L/2 bounds the cull
@@ -684,13 +700,35 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     const float4 u0 = i0 < 4 * nn ? nsrc[i0] : float4{};
     const float4 u1 = i1 < 4 * nn ? nsrc[i1] : float4{};
     if (wave_sph)
-      world_tile<MAXS, SW>(s_box + buf * kWlBoxTile * 4, nb, lane, cwx, cwy, cwz, Rw, bxl, byl, bzl, rlb, cx, cy,
-                           cz, rr, rho, swc, ws, eta, inv_eta, cost, mc, Fx, Fy, Fz, Mx, My, Mz);
+      world_tile<MAXS, SW, SP>(s_box + buf * kWlBoxTile * 4, nb, lane, cwx, cwy, cwz, Rw, bxl, byl, bzl, rlb, cx,
+                               cy, cz, rr, rho, swc, ws, a.pr.w_coll, dsl, eta, inv_eta, cost, mc, Fx, Fy, Fz, Mx, My,
+                               Mz);
     if (nn <= 0) break;
     float4* nxt = s_box + (buf ^ 1) * kWlBoxTile * 4;
     if (i0 < 4 * nn) nxt[i0] = u0;
     if (i1 < 4 * nn) nxt[i1] = u1;
     __syncthreads();
+  }
+
+  if constexpr (SP && GRAD) {
+    // the speed's gradient acts on the neighbouring waypoints: each sphere's
+    // collision cost times its unit chord / (2 dt), for speed_adjoint_kernel
+    // (every sphere has one slot, so the sums are whole; one slice only)
+    if (spd && link_w && valid && a.sp_h) {
+      const size_t hb = ((size_t)k * a.rows + row) * a.rb.n_spheres;
+#pragma unroll
+      for (int s = 0; s < MAXS; ++s)
+        if (s < ns) {
+          const float4 ls = s_slot[l * maxs + sg * MAXS + s];
+          const float ux = (Tn[0] - Tp[0]) * ls.x + (Tn[1] - Tp[1]) * ls.y + (Tn[2] - Tp[2]) * ls.z + (Tn[3] - Tp[3]);
+          const float uy = (Tn[4] - Tp[4]) * ls.x + (Tn[5] - Tp[5]) * ls.y + (Tn[6] - Tp[6]) * ls.z + (Tn[7] - Tp[7]);
+          const float uz = (Tn[8] - Tp[8]) * ls.x + (Tn[9] - Tp[9]) * ls.y + (Tn[10] - Tp[10]) * ls.z + (Tn[11] - Tp[11]);
+          const float un = sqrtf(ux * ux + uy * uy + uz * uz);
+          const float f = un > 0.0f ? dsl[s] * (0.5f / a.pr.dt) / un : 0.0f;
+          const int m = a.wl.slot_sphere[l * maxs + sg * MAXS + s];
+          a.sp_h[hb + m] = float4{f * ux, f * uy, f * uz, 0.0f};
+        }
+    }
   }
 
   if (G > 1 && link_w) {

@@ -202,6 +202,32 @@ struct EvalArgs {
   float* mc_e;             // [K][rows]
   float* grad_e;           // [K][rows][D] (gradient mode)
   float* pe_e;             // [rows][2] position / rotation error at the last waypoint, or null
+  // speed metric with gradients: per (candidate, row, sphere) the sphere's
+  // collision cost times its unit chord / (2 dt), for the speed's gradient on
+  // the neighbouring waypoints (speed_adjoint_kernel), or null
+  float4* sp_h;            // [K][rows][M]
+};
+
+// The speed metric's gradient on the neighbouring waypoints (Eq.(11)): for
+// every (candidate, row) the force h(t-1) - h(t+1) (+ h(t) at the last
+// waypoint) on each sphere, projected on the joints and added to the
+// evaluation's gradient (and directional derivative).
+struct SpeedAdjArgs {
+  const SeedInfo* seeds;
+  int n_seeds, rows, dof, n_links, n_spheres, K, maxs;
+  float alpha[kMaxK];
+  int cand;                // candidates clip(x + alpha_k d) (else x itself)
+  const float* fixed_tf;   // [L][12]
+  const float* q_lo;
+  const float* q_hi;
+  const int4* info;        // [L]: chain depth, spheres, ...
+  const float4* sphere;    // [L][maxs] centre in link frame + radius
+  const int* slot_sphere;  // [L][maxs]
+  const float* x;          // [rows][D]
+  const float* d;          // [rows][D] or null
+  const float4* sp_h;      // [K][rows][M]
+  float* grad_e;           // [K][rows][D]
+  float* gd_e;             // [K][rows] (candidates)
 };
 
 struct ReduceArgs {
@@ -363,6 +389,7 @@ hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipS
 // counts 64-evaluation chunks of rows x K per problem)
 hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+hipError_t launch_speed_adjoint(const SpeedAdjArgs& a, hipStream_t s);
 // fuse (optional): compute the next L-BFGS direction from the chosen iterate
 hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, hipStream_t s);
 hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s);

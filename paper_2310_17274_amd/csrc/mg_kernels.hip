@@ -36,6 +36,90 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(const ReduceArgs a) {
 }
 
 // --------------------------------------------------------------------------
+// The speed metric's gradient on the neighbouring waypoints (Eq.(11)).  The
+// evaluation kernel left, per (candidate k, row, sphere m), h = C_m u / (|u|
+// 2 dt): the sphere's collision cost times its unit chord between the
+// neighbouring positions.  The speed at waypoint t is |c(t+1) - c(t-1)| /
+// (2 dt) (the start before waypoint 1, waypoint T repeated after T), so
+// sphere m at row t feels h(t-1) from its left neighbour's speed, -h(t+1)
+// from its right neighbour's, and h(t) itself at the last waypoint.  One
+// wave per (seed, candidate), lane = waypoint: the link frames (Tab.6, in
+// LDS), each link's wrench of those forces, and joint j's derivative
+// z_j . (M - o_j x F) over the links below it (Tab.7), added to the
+// evaluation's gradient and directional derivative.
+__global__ __launch_bounds__(kWave) void speed_adjoint_kernel(const SpeedAdjArgs a) {
+  extern __shared__ float s_tf[];   // [lane][L][12]
+  const int seed = blockIdx.x, k = blockIdx.y, t = threadIdx.x;
+  const SeedInfo si = a.seeds[seed];
+  if (t >= si.T) return;
+  const int D = a.dof, L = a.n_links, M = a.n_spheres;
+  const int row = si.row0 + t;
+  float* tf = s_tf + (size_t)t * L * 12;
+  const float al = a.alpha[k];
+  // link frames at the evaluation's configuration (the candidate exactly
+  // as the evaluation kernel formed it)
+  for (int l = 0; l < L; ++l) {
+    float q = a.x[(size_t)row * D + l];
+    if (a.cand) q = fminf(fmaxf(fmaf(al, a.d[(size_t)row * D + l], q), a.q_lo[l]), a.q_hi[l]);
+    float sn, cs;
+    sincosf(q, &sn, &cs);
+    const float* F = a.fixed_tf + l * 12;
+    float P[12];
+    if (a.info[l].x > 1) {
+      for (int e = 0; e < 12; ++e) P[e] = tf[(l - 1) * 12 + e];
+    } else {
+      identity(P);
+    }
+    float* To = tf + l * 12;
+    for (int r = 0; r < 3; ++r) {
+      const float t0 = P[r * 4 + 0], t1 = P[r * 4 + 1], t2 = P[r * 4 + 2], t3 = P[r * 4 + 3];
+      const float u0 = t0 * F[0] + t1 * F[4] + t2 * F[8];
+      const float u1 = t0 * F[1] + t1 * F[5] + t2 * F[9];
+      To[r * 4 + 2] = t0 * F[2] + t1 * F[6] + t2 * F[10];
+      To[r * 4 + 3] = t0 * F[3] + t1 * F[7] + t2 * F[11] + t3;
+      To[r * 4 + 0] = u0 * cs + u1 * sn;
+      To[r * 4 + 1] = u1 * cs - u0 * sn;
+    }
+  }
+  const float4* hb = a.sp_h + ((size_t)k * a.rows + row) * M;
+  const bool has_prev = t >= 1, has_next = t + 1 < si.T, last = t + 1 == si.T;
+  // links from the last to the first: wrench sums over each arm's tail
+  float SF[3] = {0.0f, 0.0f, 0.0f}, SM[3] = {0.0f, 0.0f, 0.0f};
+  float gd = 0.0f;
+  float* g = a.grad_e + ((size_t)k * a.rows + row) * D;
+  for (int l = L - 1; l >= 0; --l) {
+    const float* T = tf + l * 12;
+    const int ns = a.info[l].y;
+    for (int s = 0; s < ns; ++s) {
+      const float4 ls = a.sphere[l * a.maxs + s];
+      const int m = a.slot_sphere[l * a.maxs + s];
+      float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+      if (has_prev) { const float4 h = hb[m - M]; fx += h.x; fy += h.y; fz += h.z; }
+      if (has_next) { const float4 h = hb[m + M]; fx -= h.x; fy -= h.y; fz -= h.z; }
+      if (last) { const float4 h = hb[m]; fx += h.x; fy += h.y; fz += h.z; }
+      if (fx == 0.0f && fy == 0.0f && fz == 0.0f) continue;
+      const float cx = T[0] * ls.x + T[1] * ls.y + T[2] * ls.z + T[3];
+      const float cy = T[4] * ls.x + T[5] * ls.y + T[6] * ls.z + T[7];
+      const float cz = T[8] * ls.x + T[9] * ls.y + T[10] * ls.z + T[11];
+      SF[0] += fx; SF[1] += fy; SF[2] += fz;
+      SM[0] += cy * fz - cz * fy; SM[1] += cz * fx - cx * fz; SM[2] += cx * fy - cy * fx;
+    }
+    const float zx = T[2], zy = T[6], zz = T[10], ox = T[3], oy = T[7], oz = T[11];
+    const float dg = zx * (SM[0] - (oy * SF[2] - oz * SF[1])) + zy * (SM[1] - (oz * SF[0] - ox * SF[2])) +
+                     zz * (SM[2] - (ox * SF[1] - oy * SF[0]));
+    if (l < D) {
+      g[l] += dg;
+      if (a.cand) gd = fmaf(dg, a.d[(size_t)row * D + l], gd);
+    }
+    if (a.info[l].x <= 1) {   // the root of an arm: the next arm's sums start afresh
+      SF[0] = SF[1] = SF[2] = 0.0f;
+      SM[0] = SM[1] = SM[2] = 0.0f;
+    }
+  }
+  if (a.cand) a.gd_e[(size_t)k * a.rows + row] += gd;
+}
+
+// --------------------------------------------------------------------------
 // Particle-based optimization update (Alg.5, Eq.(12)-(13)) of one seed per
 // workgroup: particle costs from the per-row sums, exponential-utility
 // weights w = softmax(-(C - min C) / beta), then per element
@@ -714,6 +798,15 @@ hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipS
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   reduce_kernel<<<(a.n_seeds + kBlock - 1) / kBlock, kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_speed_adjoint(const SpeedAdjArgs& a, hipStream_t s) {
+  if (a.n_links < 1 || a.n_links > kMaxDof || a.K < 1 || a.K > kMaxK || !a.sp_h || !a.grad_e ||
+      (a.cand && (!a.d || !a.gd_e)))
+    return hipErrorInvalidValue;
+  const size_t lds = (size_t)kWave * a.n_links * 12 * sizeof(float);
+  speed_adjoint_kernel<<<dim3(a.n_seeds, a.K), kWave, lds, s>>>(a);
   return hipGetLastError();
 }
 

@@ -1,7 +1,9 @@
 """Speed metric (Eq.(11)) on the GPU through the C ABI against the FP64
 reference: each sphere's world collision cost times its central-difference
-speed, the gradient holding the speed fixed.  The term lives in the
-wave-per-link layout; a lane-per-link request falls back to it."""
+speed, with the exact gradient (the speed's own gradient acts on the
+neighbouring waypoints; the reference's is pinned by finite differences).
+The term lives in the wave-per-link layout; a lane-per-link request falls
+back to it, and the cuboid split over workgroups is not used with it."""
 import numpy as np
 import pytest
 import torch
