@@ -12,9 +12,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libmg.so")
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in
-           ["mg_api.hip", "mg_kernels.hip", "mg_eval_wl.hip"] +
+           ["mg_api.hip", "mg_kernels.hip", "mg_lbfgs.hip", "mg_eval_wl.hip"] +
+           [f"mg_select_p{pl}.hip" for pl in (1, 2, 4, 8, 16)] + ["mg_select_p16h.hip"] +
+           [f"mg_eval_wl_s{slots}g{groups}.hip" for slots, groups in
+            ((2, 1), (4, 1), (8, 1), (16, 1), (2, 2), (4, 2), (8, 2))] +
            [f"mg_eval_l{lanes}s{slots}.hip" for lanes in (8, 16) for slots in (4, 8, 16)]]
-HEADERS = [os.path.join(CSRC, f) for f in ("mg_internal.h", "mg_device.h", "mg_eval.h", "mg_eval_wl.h")] + \
+HEADERS = [os.path.join(CSRC, f) for f in ("mg_internal.h", "mg_device.h", "mg_eval.h", "mg_eval_wl.h",
+                                           "mg_solver.h")] + \
           [os.path.join(os.path.dirname(HERE), "include", "mg.h")]
 OBJDIR = os.path.join(HERE, "_build")
 

@@ -931,12 +931,18 @@ hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand
   return wl_pick<MAXS, G, false, false>(a, grid, block, lds, waves, cand, grad, s);
 }
 
-template <int MAXS>
-hipError_t launch_eval_wl_s(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
-  if (a.wl.groups == 2) return launch_eval_wl_g<MAXS, 2>(a, grid_x, slices, cand, grad, s);
-  if (a.wl.groups != 1) return hipErrorInvalidValue;
-  return launch_eval_wl_g<MAXS, 1>(a, grid_x, slices, cand, grad, s);
-}
-
 }  // namespace
+
+// One compilation unit per (slots per lane, slot groups) so the variants
+// compile in parallel: mg_eval_wl_s<MAXS>g<G>.hip.
+#define MG_WL_LAUNCHER(S, G)                                                                         \
+  hipError_t launch_eval_wl_s##S##g##G(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, \
+                                       hipStream_t s)
+MG_WL_LAUNCHER(2, 1);
+MG_WL_LAUNCHER(4, 1);
+MG_WL_LAUNCHER(8, 1);
+MG_WL_LAUNCHER(16, 1);
+MG_WL_LAUNCHER(2, 2);
+MG_WL_LAUNCHER(4, 2);
+MG_WL_LAUNCHER(8, 2);
 }  // namespace mg

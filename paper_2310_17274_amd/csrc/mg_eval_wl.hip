@@ -1,4 +1,4 @@
-// Evaluation kernel instantiations, wave-per-link layout.
+// Evaluation kernel, wave-per-link layout: choice of the instantiation.
 #include "mg_eval_wl.h"
 
 namespace mg {
@@ -6,10 +6,17 @@ hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, int slices, bool cand, 
   // sphere slots per lane: all of a link's, or half with two waves per link
   // or two slot groups per wave
   const int per = (a.wl.halves == 2 || a.wl.groups == 2) ? a.wl.maxs / 2 : a.wl.maxs;
-  if (per == 2) return launch_eval_wl_s<2>(a, grid_x, slices, cand, grad, s);
-  if (per == 4) return launch_eval_wl_s<4>(a, grid_x, slices, cand, grad, s);
-  if (per == 8) return launch_eval_wl_s<8>(a, grid_x, slices, cand, grad, s);
-  if (per == 16) return launch_eval_wl_s<16>(a, grid_x, slices, cand, grad, s);
+  if (a.wl.groups == 2) {
+    if (per == 2) return launch_eval_wl_s2g2(a, grid_x, slices, cand, grad, s);
+    if (per == 4) return launch_eval_wl_s4g2(a, grid_x, slices, cand, grad, s);
+    if (per == 8) return launch_eval_wl_s8g2(a, grid_x, slices, cand, grad, s);
+    return hipErrorInvalidValue;
+  }
+  if (a.wl.groups != 1) return hipErrorInvalidValue;
+  if (per == 2) return launch_eval_wl_s2g1(a, grid_x, slices, cand, grad, s);
+  if (per == 4) return launch_eval_wl_s4g1(a, grid_x, slices, cand, grad, s);
+  if (per == 8) return launch_eval_wl_s8g1(a, grid_x, slices, cand, grad, s);
+  if (per == 16) return launch_eval_wl_s16g1(a, grid_x, slices, cand, grad, s);
   return hipErrorInvalidValue;
 }
 }  // namespace mg

@@ -1,0 +1,7 @@
+// Evaluation kernel instantiations, wave-per-link layout: 8 sphere slots per
+// lane, 1 slot group per wave.
+#include "mg_eval_wl.h"
+
+namespace mg {
+MG_WL_LAUNCHER(8, 1) { return launch_eval_wl_g<8, 1>(a, grid_x, slices, cand, grad, s); }
+}  // namespace mg
