@@ -213,6 +213,53 @@ class Ref:
         return mu, var, costs
 
 
+def timestep_params(params, dt_opt):
+    """Second-pass parameters of Alg.4 (App. 'Time-step Descretization and
+    Temporal Weight Scaling'): spacing dt_opt and, with rho = dt_opt / dt,
+    the derivative weights a7 rho, a8 rho^4, a9 rho^6.  Reading: 'scale the
+    weights by the new dt' keeps the cost of the same waypoints unchanged,
+    since velocity, acceleration and jerk scale as rho^-1, rho^-2, rho^-3."""
+    p = dict(DEFAULTS)
+    p.update(params)
+    rho = dt_opt / p["dt"]
+    out = dict(params)
+    out.update(dt=dt_opt, a7=p["a7"] * rho, a8=p["a8"] * rho ** 4, a9=p["a9"] * rho ** 6)
+    return out
+
+
+def solve_timestep(robot, problems, iters1, iters2, m, alpha, vmax, amax, jmax, dt_min, mode=1,
+                   nthreads=1, **params):
+    """Time-step optimization (Alg.4) of a batch of problems sharing one
+    spacing, in the paper's order: (1) a solve at the first spacing dt with
+    the jerk term off (a9 = 0); (2) dt_opt = the largest retime of the
+    problems' best seeds (lowest index on ties), at least dt_min; (3) the
+    derivative weights rescaled to dt_opt (timestep_params), jerk on; (4) a
+    solve from the first pass's best iterates; (5) dt_f = the largest
+    retime of the new best seeds.
+    problems: list of (boxes, q0, goal, T, x [S*T*D]).  Returns (x per
+    problem, best costs per problem, (dt_opt, dt_f))."""
+    D = robot.dof
+    p = dict(DEFAULTS)
+    p.update(params)
+    r1 = Ref(robot, **dict(params, a9=0.0))
+    first = [r1.solve(b, q0, g, T, x, iters1, m, alpha, mode=mode, nthreads=nthreads)[:2]
+             for b, q0, g, T, x in problems]
+
+    def largest_retime(results, dt):
+        out = 0.0
+        for (b, q0, g, T, _), (x, best) in zip(problems, results):
+            s = int(np.argmin(best))
+            out = max(out, retime(q0, x.reshape(-1, T, D)[s], dt, vmax, amax, jmax))
+        return max(out, dt_min)
+
+    dt_opt = largest_retime(first, p["dt"])
+    r2 = Ref(robot, **timestep_params(params, dt_opt))
+    second = [r2.solve(b, q0, g, T, x1, iters2, m, alpha, mode=mode, nthreads=nthreads)[:2]
+              for (b, q0, g, T, _), (x1, _) in zip(problems, first)]
+    dt_f = largest_retime(second, dt_opt)
+    return [x for x, _ in second], [c for _, c in second], (dt_opt, dt_f)
+
+
 # Particle stage constants.  The paper gives none of them (Alg.5 takes sigma0
 # as an input); these are the documented builder choices: initial per-element
 # variance 0.05^2 rad^2, adaptive temperature (beta <= 0: 0.1 x cost range),

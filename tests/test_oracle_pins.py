@@ -1156,3 +1156,46 @@ def test_particles_clip_to_each_joints_limits(oracle_lib):
     want = np.clip(mu + 2.0 * one, lo, hi)
     assert np.any(want == lo) and np.any(want == hi)
     np.testing.assert_allclose(m, want, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Time-step optimization driver (Alg.4).  The second pass's weights keep the
+# cost of the same waypoints: read at spacing rho dt with a7 rho, a8 rho^4,
+# a9 rho^6 every trajectory costs what it costs at dt with a7, a8, a9 (v, a
+# and j scale as 1/rho, 1/rho^2, 1/rho^3).  A wrong exponent or a weight
+# left out breaks the identity.
+
+@pytest.mark.parametrize("rho", [0.13, 0.5, 1.7])
+def test_timestep_weights_keep_the_cost(oracle_lib, rho):
+    robot, boxes, q0, goal, q = make_problem(seed=4, T=8)
+    base = dict(a9=3.0, vel_all=1)
+    c0, g0, _, t0 = ref.Ref(robot, **base).traj_cost(boxes, q0, goal, q)
+    p2 = ref.timestep_params(base, rho * ref.DEFAULTS["dt"])
+    assert p2["dt"] == pytest.approx(rho * 0.25) and p2["a9"] == pytest.approx(3.0 * rho ** 6)
+    c1, g1, _, t1 = ref.Ref(robot, **p2).traj_cost(boxes, q0, goal, q)
+    assert t0[0] > 0 and c1 == pytest.approx(c0, rel=1e-12)
+    np.testing.assert_allclose(g1, g0, rtol=1e-10, atol=1e-9 * np.abs(g0).max())
+
+
+def test_timestep_driver_follows_its_steps(oracle_lib):
+    """The driver equals its steps written out here: a first solve with the
+    jerk weight 0, the retime of its best seed, a second solve at the
+    rescaled weights, the final retime."""
+    robot = wl.make_arm(seed=0, n_spheres=12)
+    worlds = wl.make_worlds(3, [4])
+    batch = wl.make_batch(robot, 5, [3], [10], [0])
+    boxes = worlds.world(0)
+    vmax, amax, jmax = np.full(7, 2.0), np.full(7, 10.0), np.full(7, 5000.0)
+    xs, bcs, (dt_opt, dt_f) = ref.solve_timestep(robot, [(boxes, batch.q_start[0], batch.goal[0], 10, batch.x0)],
+                                                 6, 5, 4, wl.ALPHA_4, vmax, amax, jmax, 1e-3)
+    x1, b1, _ = ref.Ref(robot, a9=0.0).solve(boxes, batch.q_start[0], batch.goal[0], 10, batch.x0, 6, 4, wl.ALPHA_4)
+    want_opt = max(ref.retime(batch.q_start[0], x1.reshape(3, 10, 7)[int(np.argmin(b1))], 0.25, vmax, amax, jmax),
+                   1e-3)
+    assert dt_opt == want_opt and 0 < dt_opt < 0.25
+    rho = dt_opt / 0.25
+    r2 = ref.Ref(robot, dt=dt_opt, a7=50.0 * rho, a8=5000.0 * rho ** 4, a9=1.0 * rho ** 6)
+    x2, b2, _ = r2.solve(boxes, batch.q_start[0], batch.goal[0], 10, x1, 5, 4, wl.ALPHA_4)
+    np.testing.assert_array_equal(xs[0], x2)
+    np.testing.assert_array_equal(bcs[0], b2)
+    assert dt_f == max(ref.retime(batch.q_start[0], x2.reshape(3, 10, 7)[int(np.argmin(b2))], dt_opt,
+                                  vmax, amax, jmax), 1e-3)

@@ -142,3 +142,33 @@ def test_retime_jerk_parity():
             assert abs(jk[seed] - want) <= 1e-3 * want + 1e-6, (p, seed, jk[seed], want)
             seed += 1
             r0 += T
+
+
+def test_solve_timestep_against_the_oracle_driver():
+    """mg_solve_timestep against the FP64 oracle's Alg.4 driver on the same
+    inputs, with few iterations so that the fp32 and fp64 iterates stay
+    close: dt_opt, dt_f and the best costs to 1e-3.  Independently of the
+    iterates, the GPU's best costs must be the oracle's cost of the GPU's
+    final trajectories at its dt_opt with the rescaled weights (a7 rho,
+    a8 rho^4, a9 rho^6, jerk on): the exponents and the pass order."""
+    from tests import harness as H
+    case = make_case("plain")
+    it1, it2, lim = 4, 3, (VMAX, AMAX, JMAX)
+    x = case.x.clone()
+    x, bc, bs, ok, (dt_opt, dt_f) = case.ctx.mg_solve_timestep(case.b, case.q_start, case.goal, x, it1, it2, 4,
+                                                               wl.ALPHA_4, *lim, use_graph=False)
+    torch.cuda.synchronize()
+    bc = bc.cpu().numpy().astype(np.float64)
+    xg = x.cpu().numpy().astype(np.float64).reshape(-1)
+    b = case.batch
+    boxes = case.worlds.world(0)
+    xs_r, bc_r, (o_opt, o_f) = ref.solve_timestep(case.robot, [(boxes, b.q_start[0], b.goal[0], 32, b.x0)], it1,
+                                                  it2, 4, wl.ALPHA_4, *lim, 1e-3, nthreads=4)
+    assert abs(dt_opt - o_opt) <= 1e-3 * o_opt and abs(dt_f - o_f) <= 1e-3 * o_f, (dt_opt, o_opt, dt_f, o_f)
+    np.testing.assert_allclose(bc, bc_r[0], rtol=1e-3)
+    r2 = ref.Ref(case.robot, **ref.timestep_params({}, float(dt_opt)))
+    c_re = r2.cost_grad_batch(boxes, b.q_start[0], b.goal[0], 32, xg, grad=False)[0]
+    H.assert_cost_close(bc, c_re, "best cost at the rescaled weights")
+    # the jerk weight matters here: without it the same trajectories cost less
+    r_nj = ref.Ref(case.robot, **ref.timestep_params(dict(a9=0.0), float(dt_opt)))
+    assert np.all(r_nj.cost_grad_batch(boxes, b.q_start[0], b.goal[0], 32, xg, grad=False)[0] < c_re)
