@@ -793,3 +793,48 @@ void mgref_particles(const mgref_robot *rb, const mgref_params *pr,
   }
   (void)nthreads;
 }
+
+/* ------------------------------------------------------------------ */
+/* Philox-4x64-10 (Salmon et al., SC'11): ten rounds of the S-box that
+ * multiplies counter words 0 and 2 by the two round multipliers (high and
+ * low 64-bit halves of the 128-bit products), mixes in the key and swaps the
+ * words; the key is bumped by the two Weyl constants between rounds. */
+static void mul64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo) {
+  const unsigned __int128 p = (unsigned __int128)a * b;
+  *hi = (uint64_t)(p >> 64);
+  *lo = (uint64_t)p;
+}
+
+void mgref_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+  uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    uint64_t hi0, lo0, hi1, lo1;
+    mul64(c0, M0, &hi0, &lo0);
+    mul64(c2, M1, &hi1, &lo1);
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+double mgref_philox_normal(uint64_t seed, int it, int k, int64_t e) {
+  const uint64_t ctr[4] = {(uint64_t)(e >> 2), (uint64_t)(uint32_t)k, (uint64_t)(uint32_t)it, 0};
+  const uint64_t key[2] = {seed, 0};
+  uint64_t w[4];
+  mgref_philox4x64(ctr, key, w);
+  const uint64_t x = w[e & 3];
+  const double u1 = ((double)(x >> 40) + 0.5) / 16777216.0;
+  const double u2 = ((double)((x >> 8) & 0xFFFFFFULL) + 0.5) / 16777216.0;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925287 * u2);   /* 2 pi */
+}
+
+void mgref_philox_normals(uint64_t seed, int n_iters, int N, int rows, int D, double *out) {
+  const int64_t n = (int64_t)rows * D;
+  for (int it = 0; it < n_iters; ++it)
+    for (int k = 0; k < N; ++k)
+      for (int64_t e = 0; e < n; ++e) out[((int64_t)it * N + k) * n + e] = mgref_philox_normal(seed, it, k, e);
+}

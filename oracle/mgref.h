@@ -14,6 +14,8 @@
 #ifndef MGREF_H
 #define MGREF_H
 
+#include <stdint.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -165,6 +167,19 @@ void mgref_particles(const mgref_robot *rb, const mgref_params *pr,
                      const double *q0, const double *goal, int T, int S, double *mu,
                      double *var, int N, int n_iters, const double *eps, double beta,
                      double k_mu, double k_sigma, double *cost_out, int nthreads);
+
+/* Counter-based normal draws of the particle stage (Alg.5 samples its
+ * particles from a zero-mean Gaussian).  Philox-4x64 with 10 rounds (Salmon,
+ * Moraes, Dror, Shaw, 'Parallel random numbers: as easy as 1, 2, 3', SC'11):
+ * out = philox(ctr, key).  The draw of element e (= row * D + joint of the
+ * batch's rows), particle k and round it under seed s takes word e mod 4 of
+ * philox({e / 4, k, it, 0}, {s, 0}); its bits 40..63 and 8..31 give
+ * u1, u2 = (24-bit integer + 1/2) / 2^24, and the draw is the Box-Muller
+ * value sqrt(-2 ln u1) cos(2 pi u2). */
+void mgref_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+double mgref_philox_normal(uint64_t seed, int it, int k, int64_t e);
+/* [n_iters][N][rows][D] draws of rounds 0..n_iters-1, particles 0..N-1. */
+void mgref_philox_normals(uint64_t seed, int n_iters, int N, int rows, int D, double *out);
 
 #ifdef __cplusplus
 }

@@ -73,6 +73,8 @@ def lib():
         L.mgref_ls_select.restype = C.c_int
         L.mgref_linesearch.restype = C.c_int
         L.mgref_retime.restype = C.c_double
+        L.mgref_philox_normal.restype = C.c_double
+        L.mgref_philox_normal.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int64]
         _LIB = L
     return _LIB
 
@@ -258,6 +260,24 @@ def solve_timestep(robot, problems, iters1, iters2, m, alpha, vmax, amax, jmax, 
               for (b, q0, g, T, _), (x1, _) in zip(problems, first)]
     dt_f = largest_retime(second, dt_opt)
     return [x for x, _ in second], [c for _, c in second], (dt_opt, dt_f)
+
+
+def philox4x64(ctr, key):
+    """Philox-4x64-10 of one counter block: four 64-bit words."""
+    c = (C.c_uint64 * 4)(*[int(v) & ((1 << 64) - 1) for v in ctr])
+    k = (C.c_uint64 * 2)(*[int(v) & ((1 << 64) - 1) for v in key])
+    o = (C.c_uint64 * 4)()
+    lib().mgref_philox4x64(c, k, o)
+    return [int(v) for v in o]
+
+
+def philox_normals(seed, n_iters, N, rows, D):
+    """Counter-based standard normal draws [n_iters, N, rows, D] of the
+    particle stage (Philox-4x64-10 + Box-Muller, mgref.h)."""
+    out = np.zeros((n_iters, N, rows, D))
+    lib().mgref_philox_normals(C.c_uint64(seed), int(n_iters), int(N), int(rows), int(D),
+                               out.ctypes.data_as(_dp))
+    return out
 
 
 # Particle stage constants.  The paper gives none of them (Alg.5 takes sigma0

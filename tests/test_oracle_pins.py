@@ -1199,3 +1199,45 @@ def test_timestep_driver_follows_its_steps(oracle_lib):
     np.testing.assert_array_equal(bcs[0], b2)
     assert dt_f == max(ref.retime(batch.q_start[0], x2.reshape(3, 10, 7)[int(np.argmin(b2))], dt_opt,
                                   vmax, amax, jmax), 1e-3)
+
+
+# ---------------------------------------------------------------------------
+# Particle-stage noise: Philox-4x64-10 (Salmon et al., SC'11) against numpy's
+# independent implementation of the same generator (numpy.random.Philox,
+# whose stream is philox(counter + 1), philox(counter + 2), ...), then the
+# Box-Muller draws: closed form at chosen words, and the standard normal's
+# moments and distribution over many draws.
+
+@pytest.mark.parametrize("key,ctr", [((0, 0), (0, 0, 0, 0)), ((0x123456789, 0xABCDEF), (5, 7, 0, 0)),
+                                     ((2 ** 64 - 1, 2 ** 63 + 5), (2 ** 64 - 2, 1, 2, 3)),
+                                     ((42, 0), (1000, 255, 1, 0))])
+def test_philox_matches_numpy(oracle_lib, key, ctr):
+    # numpy advances its 256-bit counter before each block: start one below
+    v = (sum(int(w) << (64 * i) for i, w in enumerate(ctr)) - 1) % 2 ** 256
+    c = [(v >> (64 * i)) & (2 ** 64 - 1) for i in range(4)]
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(c, dtype=np.uint64))
+    want = [int(v) for v in bg.random_raw(4)]
+    assert ref.philox4x64(ctr, key) == want
+    # and the next block is the next counter
+    nxt = list(ctr)
+    nxt[0] = (nxt[0] + 1) % 2 ** 64
+    assert ref.philox4x64(nxt, key) == [int(v) for v in bg.random_raw(4)]
+
+
+def test_philox_normal_box_muller(oracle_lib):
+    L = ref.lib()
+    seed, it, k = 7, 1, 3
+    for e in (0, 1, 2, 3, 4, 5, 1234567, 2 ** 40 + 3):
+        w = ref.philox4x64([e >> 2, k, it, 0], [seed, 0])[e & 3]
+        u1 = ((w >> 40) + 0.5) / 2 ** 24
+        u2 = (((w >> 8) & 0xFFFFFF) + 0.5) / 2 ** 24
+        want = math.sqrt(-2.0 * math.log(u1)) * math.cos(2 * math.pi * u2)
+        assert L.mgref_philox_normal(seed, it, k, e) == pytest.approx(want, rel=1e-15, abs=1e-15)
+    from scipy import stats
+    z = ref.philox_normals(11, 2, 16, 1000, 7).reshape(-1)
+    assert z.size == 224000
+    assert abs(z.mean()) < 5 * (1 / math.sqrt(z.size)) and abs(z.var() - 1) < 5 * math.sqrt(2 / z.size)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    # rounds, particles and elements draw different numbers
+    a = ref.philox_normals(11, 2, 2, 3, 7)
+    assert len(np.unique(a)) == a.size
