@@ -31,16 +31,32 @@ PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
 
-def flops_per_eval(M, N, L, D, pose_at_row_fraction):
+def flops_per_eval(M, N, L, D, M_active=0):
     """Algorithmic FP32 operations of one (seed, waypoint, candidate) cost +
-    gradient evaluation (FMA = 2, other arithmetic = 1; sin/cos/sqrt not
-    counted):
-      24 per sphere-cuboid pair (box-frame transform 18, |p|-h 3, max3 2,
-         compare 1), 33 per sphere (centre 18, wrench 15),
-      180 per link (forward chain 90 + adjoint recompute 90),
-      120 per joint (limit, smoothness stencils, adjoint projection 20),
-      150 per pose evaluation (last waypoint only)."""
+    gradient evaluation, counted as every pair is tested (FMA = 2, other
+    operations = 1, sqrt/sin/cos = 1):
+      37 per sphere-cuboid pair (box-frame transform 18, |p| - h 3, clamp 3,
+         squared norm 5, inner max/min 3, add/compare 3, clearance 1),
+      18 per sphere (centre), 2 x 85 per link (chain forward and again for
+         the adjoint), 200 per joint (limits, stencils, smoothness, forward
+         and adjoint), 300 per evaluation (pose), 70 per sphere within reach
+         of a cuboid (its gradient through the joints above it; 0 here, a
+         lower bound)."""
+    return 37 * M * N + 18 * M + 2 * 85 * L + 200 * D + 300 + 70 * M_active
+
+
+def flops_per_eval_executed(M, N, L, D, pose_at_row_fraction):
+    """A closer count of what the culling kernel executes per evaluation:
+    24 per pair face test (box-frame transform 18, |p|-h 3, max3 2, compare
+    1), 33 per sphere (centre 18, wrench 15), 180 per link, 120 per joint,
+    150 per pose evaluation (last waypoint only)."""
     return 24 * M * N + 33 * M + 180 * L + 120 * D + 150 * pose_at_row_fraction
+
+
+def pct(samples):
+    """median and p90 of a list of timings."""
+    a = np.asarray(samples, dtype=np.float64)
+    return {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)), "n": int(a.size)}
 
 
 def main():
@@ -120,14 +136,16 @@ def main():
         solve(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for i in range(args.steps):
         solve(True)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_batched = ev0.elapsed_time(ev1) / args.steps
+    ms_batched = evs[0].elapsed_time(evs[-1]) / args.steps
+    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     # plain path: the same solve with every kernel launched directly
     for _ in range(max(1, args.warmup // 2)):
@@ -151,7 +169,9 @@ def main():
     best = outs[0].cpu().numpy()
     evals_per_step = S * T * K * iters
     value = evals_per_step / (ms_batched * 1e-3)
-    fl = flops_per_eval(robot.n_spheres, worlds.pose.shape[0], robot.n_links, D, 1.0 / T)
+    N = int(worlds.pose.shape[0])
+    fl = flops_per_eval(robot.n_spheres, N, robot.n_links, D)
+    fl_x = flops_per_eval_executed(robot.n_spheres, N, robot.n_links, D, 1.0 / T)
     achieved = fl * S * T * K / (eval_us * 1e-6) / 1e12 if eval_us > 0 else 0.0
 
     line = {
@@ -173,6 +193,7 @@ def main():
                    "seeds": S, "horizon": T, "candidates": K, "iterations": iters,
                    "spheres": robot.n_spheres, "cuboids": int(worlds.pose.shape[0])},
         "ms_per_solve_batched": ms_batched,
+        "ms_per_step_pct": pct(step_ms),
         "ms_per_solve_plain": ms_plain,
         "speedup_batched_vs_plain": ms_plain / ms_batched,
         "wall_s_timed": wall,
@@ -184,10 +205,16 @@ def main():
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(layout),
                      "eval_kernel_us": eval_us, "eval_launches_timed": n_ev,
                      "layout": layout,
-                     "flop_per_eval": fl, "evals_per_launch": S * T * K},
+                     "flop_per_eval": fl, "flop_count": "every pair tested (37 M N + 18 M + 170 L + 200 D + 300)",
+                     "flop_per_eval_executed": fl_x,
+                     "frac_executed": fl_x * S * T * K / (eval_us * 1e-6) / 1e12 / PEAK_FP32_TFLOPS
+                     if eval_us > 0 else 0.0,
+                     "frac_unpacked_peak": achieved / (PEAK_FP32_TFLOPS / 2),
+                     "evals_per_launch": S * T * K},
     }
 
     if not args.no_extra:
+        line["plain"] = bench_plain(args.warmup)
         line["uneven"] = bench_uneven(args.warmup)
         line["ik"] = bench_ik(args.warmup)
         line["large"] = bench_large(args.warmup)
@@ -249,9 +276,10 @@ def _inputs(robot, batch, dev):
     return q_start, goal, x0
 
 
-def _time_solves(ctx, b, q_start, goal, x0, iters, alpha, use_graph, reps, warmup):
+def _time_solves(ctx, b, q_start, goal, x0, iters, alpha, use_graph, reps, warmup, samples=None):
     """Mean ms per call of mg_solve over `reps` calls (HIP events on the
-    current stream), and the last call's outputs."""
+    current stream between calls), and the last call's outputs; each call's
+    ms is appended to `samples` when given."""
     import torch
     x = x0.clone()
     dev = x0.device
@@ -266,14 +294,47 @@ def _time_solves(ctx, b, q_start, goal, x0, iters, alpha, use_graph, reps, warmu
     for _ in range(warmup):
         run()
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
+    evs[0].record(stream)
+    for i in range(reps):
         run()
-    e1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / reps, outs
+    if samples is not None:
+        samples.extend(evs[i].elapsed_time(evs[i + 1]) for i in range(reps))
+    return evs[0].elapsed_time(evs[-1]) / reps, outs
+
+
+def bench_plain(warmup, reps=20):
+    """The plain method on one problem: 7-DOF arm, 20 spheres, 10
+    axis-aligned cuboids, 4 seeds x T=32, K=4, 100 iterations.  Latency-bound:
+    ms per solve and us per iteration, graph replays against direct
+    launches."""
+    import torch
+    from paper_2310_17274_amd import workloads as wl
+    from paper_2310_17274_amd.binding import Context
+    robot, worlds, batch, meta = wl.cfg_plain()
+    robot, worlds, batch = wl.robot_f32(robot), wl.worlds_f32(worlds), wl.to_f32(batch)
+    dev = torch.device("cuda:0")
+    ctx = Context(robot)
+    ctx.mg_set_worlds(worlds)
+    alpha, iters = meta["alpha"], meta["iters"]
+    b = ctx.batch(batch.seeds, batch.horizon, batch.world, K_max=len(alpha), m_max=4)
+    q_start, goal, x0 = _inputs(robot, batch, dev)
+    c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
+    dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
+    layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
+    sg, sp = [], []
+    ms_g, outs = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, True, reps, max(1, warmup), sg)
+    ms_p, _ = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, False, reps, max(1, warmup), sp)
+    return {"workload": f"1 problem, {int(batch.seeds[0])} seeds x T={int(batch.horizon[0])}, "
+                        f"{robot.n_spheres} spheres, {int(worlds.offsets[-1])} axis-aligned cuboids, "
+                        f"K={len(alpha)}, {iters} iterations",
+            "ms_per_solve_batched": pct(sg), "ms_per_solve_plain": pct(sp),
+            "us_per_iteration_batched": 1000.0 * ms_g / iters, "us_per_iteration_plain": 1000.0 * ms_p / iters,
+            "speedup_batched_vs_plain": ms_p / ms_g, "best_cost_min": float(outs[0].min().item()),
+            "layout": layout}
 
 
 def bench_uneven(warmup):
@@ -294,7 +355,8 @@ def bench_uneven(warmup):
     c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
     layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
-    ms_b, _ = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, True, 3, max(1, warmup))
+    sb = []
+    ms_b, _ = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, True, 20, max(1, warmup), sb)
     # plain: one batch per problem, every kernel launched directly
     singles, r0 = [], 0
     for p in range(P):
@@ -313,23 +375,32 @@ def bench_uneven(warmup):
             ctx.mg_solve(bp, qs, gl, x, iters, 4, alpha, mode=1, use_graph=False, outputs=outs)
     plain()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(torch.cuda.current_stream())
-    plain()
-    e1.record(torch.cuda.current_stream())
+    reps = 20
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    evs[0].record(torch.cuda.current_stream())
+    for i in range(reps):
+        plain()
+        evs[i + 1].record(torch.cuda.current_stream())
     torch.cuda.synchronize()
-    ms_p = e0.elapsed_time(e1)
+    sp = [evs[i].elapsed_time(evs[i + 1]) for i in range(reps)]
+    ms_p = evs[0].elapsed_time(evs[-1]) / reps
     evals = int(np.sum(batch.seeds * batch.horizon)) * len(alpha) * iters
     return {"workload": f"{P} problems, seeds U{{4..64}} (total {int(batch.seeds.sum())}), T in {{24,32,48}}, "
                         f"{int(worlds.offsets[-1])} cuboids in {P} worlds, K={len(alpha)}, {iters} iterations",
             "ms_per_solve_batched": ms_b / P, "ms_per_solve_plain": ms_p / P,
             "speedup_batched_vs_plain": ms_p / ms_b, "evals_per_s_batched": evals / (ms_b * 1e-3),
+            "ms_per_batch_batched": pct(sb), "ms_per_batch_plain": pct(sp),
             "layout": layout}
 
 
 def bench_ik(warmup):
     """Collision-free inverse kinematics: 4096 goal poses x 32 seeds (T = 1),
-    40 oriented cuboids, K = 4, 100 iterations as graphs of 25."""
+    40 oriented cuboids, K = 4, 100 iterations as graphs of 25.  Timed on the
+    configured goals (positions uniform in the 0.3-0.8 m shell, uniform
+    orientation: many are unreachable or in collision), with the success
+    fraction on them, and the success fraction on a feasible set: end-effector
+    poses of collision-free random configurations (reachable and
+    collision-free by construction)."""
     import torch
     from paper_2310_17274_amd import workloads as wl
     from paper_2310_17274_amd.binding import Context
@@ -341,29 +412,37 @@ def bench_ik(warmup):
     alpha, iters, P = meta["alpha"], meta["iters"], batch.n_problems
     b = ctx.batch(batch.seeds, batch.horizon, batch.world, K_max=len(alpha), m_max=4)
     q_start, goal, x0 = _inputs(robot, batch, dev)
-    # reachable goals: end-effector poses (the library's own forward
-    # kinematics) of the random configurations with the largest clearance
-    # (the library's own collision cost at T = 1) among 16 per goal
-    cand = wl.goal_configs(robot, 33, 16 * P)
-    qc = torch.as_tensor(cand, dtype=torch.float32, device=dev).contiguous()
-    bc = ctx.batch([cand.shape[0]], [1], [0], K_max=1, m_max=0)
-    _, _, clear = ctx.mg_cost_grad(bc, q_start[:1].contiguous(), goal[:1].contiguous(), qc, grad=False)
-    order = torch.argsort(clear, descending=True, stable=True)[:P]
-    goal_free = (clear[order] >= 0.0).float().mean().item()
-    goal = ctx.mg_ee_pose(qc[order].contiguous()).reshape(P, -1).contiguous()
     c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
     layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
-    ms, outs = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, True, 3, max(1, warmup))
-    ok = outs[2].float().mean().item()
+    samples = []
+    ms, outs = _time_solves(ctx, b, q_start, goal, x0, iters, alpha, True, 20, max(1, warmup), samples)
+    ok_cfg = outs[2].float().mean().item()
+    # feasible goals: poses of collision-free random configurations (the
+    # library's own kinematics and clearance at T = 1)
+    cand = wl.goal_configs(robot, 33, 32 * P)
+    qc = torch.as_tensor(cand, dtype=torch.float32, device=dev).contiguous()
+    bc = ctx.batch([cand.shape[0]], [1], [0], K_max=1, m_max=0)
+    _, _, clear = ctx.mg_cost_grad(bc, q_start[:1].contiguous(), goal[:1].contiguous(), qc, grad=False)
+    free = torch.nonzero(clear >= 0.0).flatten()
+    n_free = int(free.numel())
+    pick = free[:P] if n_free >= P else torch.cat([free, torch.argsort(clear, descending=True)[:P - n_free]])
+    goal_f = ctx.mg_ee_pose(qc[pick].contiguous()).reshape(P, -1).contiguous()
+    ms_f, outs_f = _time_solves(ctx, b, q_start, goal_f, x0, iters, alpha, True, 3, 1)
+    ok_f = outs_f[2].float().mean().item()
     return {"workload": f"{P} goals x {int(batch.seeds[0])} seeds, T=1, {int(worlds.offsets[-1])} oriented "
                         f"cuboids, K={len(alpha)}, {iters} iterations (graphs of 25)",
-            "ik_per_s": P / (ms * 1e-3), "ms_per_batch": ms, "success_fraction": ok,
-            "goal_configs_collision_free": goal_free,
+            "ik_per_s": P / (ms * 1e-3), "ms_per_batch": ms, "ms_per_batch_pct": pct(samples),
+            "success_fraction": ok_cfg,
+            "success_fraction_feasible": ok_f, "ms_per_batch_feasible": ms_f,
+            "feasible_goals_collision_free_configs": min(n_free, P),
             "evals_per_s": int(batch.seeds.sum()) * len(alpha) * iters / (ms * 1e-3),
             "layout": layout,
-            "note": "goals are end-effector poses of the clearest of 16 random configurations "
-                    "U(-2.5,2.5)^7 each (reachable); success = 5 mm / 0.05 rad and collision free"}
+            "note": "success = best seed within 5 mm / 0.05 rad of the goal and collision free. "
+                    "success_fraction: goals as configured (positions uniform in the 0.3-0.8 m shell, "
+                    "uniform orientation; reachability and clearance not enforced). "
+                    "success_fraction_feasible: goals at end-effector poses of collision-free "
+                    "configurations U(-2.5,2.5)^7 (reachable and collision free by construction)"}
 
 
 def bench_motion_gen(warmup):
@@ -404,7 +483,8 @@ def bench_motion_gen(warmup):
         x_ik = torch.empty_like(x_ik0)
         x_to = torch.empty((to.rows, D), dtype=torch.float32, device=dev)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        for rep in range(max(1, warmup) + 1):
+        calls = []
+        for rep in range(max(1, warmup) + 20):
             x_ik.copy_(x_ik0)
             torch.cuda.synchronize()
             ev0.record()
@@ -412,8 +492,10 @@ def bench_motion_gen(warmup):
                                                           vmax, amax, jmax, x_to=x_to)
             ev1.record()
             torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1)
-        out[f"P{P}"] = {"ms_per_call": ms, "ms_per_problem": ms / P,
+            if rep >= max(1, warmup):
+                calls.append(ev0.elapsed_time(ev1))
+        ms = float(np.median(calls))
+        out[f"P{P}"] = {"ms_per_call": ms, "ms_per_call_pct": pct(calls), "ms_per_problem": ms / P,
                         "ik_found_fraction": ik_ok.float().mean().item(),
                         "success_fraction": ok.float().mean().item(),
                         "mean_motion_time_s": mt.mean().item(), "dt_opt": dts[0], "dt_final": dts[1],
@@ -427,11 +509,11 @@ def bench_motion_gen(warmup):
     return out
 
 
-def bench_large(warmup):
+def bench_large(warmup, reps=10):
     """Two-arm tree (14 joints, 120 spheres), 500 oriented cuboids, swept
     collision (4 trace steps), 128 seeds x 48 waypoints: the particle stage
-    (2 rounds x 256 particles per seed) then 100 L-BFGS iterations with 4
-    line-search candidates (graphs of 25)."""
+    (2 rounds x 256 particles per seed, noise drawn on the device) then 100
+    L-BFGS iterations with 4 line-search candidates (graphs of 25)."""
     import torch
     from paper_2310_17274_amd import workloads as wl
     from paper_2310_17274_amd.binding import Context, default_params
@@ -448,27 +530,31 @@ def bench_large(warmup):
     c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
     dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
     layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha, launches=3))
-    eps = torch.as_tensor(wl.normal_draws(55, (R, N, S * T, D)), dtype=torch.float32, device=dev)
     mean, var = x0.clone(), torch.empty_like(x0)
     e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
     stream = torch.cuda.current_stream()
-    for rep in range(max(1, warmup) + 1):
+    tp, ts = [], []
+    for rep in range(max(1, warmup) + reps):
         mean.copy_(x0)
         var.fill_(0.05 ** 2)
         torch.cuda.synchronize()
         e0.record(stream)
-        ctx.mg_particles(b, q_start, goal, mean, var, eps)
+        ctx.mg_particles_seeded(b, q_start, goal, mean, var, N, R, 55)
         e1.record(stream)
         ctx.mg_solve(b, q_start, goal, mean, iters, 4, alpha, mode=1, graph_inner=25, use_graph=True)
         e2.record(stream)
         torch.cuda.synchronize()
-    ms_p, ms_s = e0.elapsed_time(e1), e1.elapsed_time(e2)
+        if rep >= max(1, warmup):
+            tp.append(e0.elapsed_time(e1))
+            ts.append(e1.elapsed_time(e2))
+    ms_p, ms_s = float(np.mean(tp)), float(np.mean(ts))
     return {"workload": f"two-arm tree ({D} joints, {robot.n_spheres} spheres), {int(worlds.offsets[-1])} "
                         f"oriented cuboids, swept collision (4 steps), {S} seeds x T={T}; particle stage "
-                        f"{R} x {N}, then {iters} L-BFGS iterations with K={len(alpha)} (graphs of 25)",
+                        f"{R} x {N} (device Philox noise), then {iters} L-BFGS iterations with K={len(alpha)} (graphs of 25)",
             "ms_particle_stage": ms_p, "ms_lbfgs_solve": ms_s, "ms_per_solve": ms_p + ms_s,
             "particle_evals_per_s": R * N * S * T / (ms_p * 1e-3),
             "lbfgs_evals_per_s": S * T * len(alpha) * iters / (ms_s * 1e-3),
+            "ms_particle_stage_pct": pct(tp), "ms_lbfgs_solve_pct": pct(ts),
             "layout": layout}
 
 
@@ -496,32 +582,80 @@ def profile_copy():
     print(json.dumps({"profile": "copy", "bytes": n * 4, "copies": 5}), flush=True)
 
 
-def cpu_baseline(robot, worlds, batch, alpha, iters, seconds):
-    """The FP64 reference solve on the host cores, on a bounded sample: the
-    same 32-seed problem for as many iterations as fit in ~`seconds`,
-    scaled to evals/s."""
-    from oracle import ref
-    threads = min(16, os.cpu_count() or 1)
-    r = ref.Ref(robot)
-    T = int(batch.horizon[0])
-    S = int(batch.seeds[0])
-    K = len(alpha)
-    boxes = worlds.world(0)
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_solve_rate(r, boxes, q0, goal, T, x, K, alpha, iters, threads, seconds):
+    """Oracle evaluations per second of whole solves repeated to fill about
+    `seconds` (each solve of n iterations evaluates n S T K candidates plus
+    the initial S T)."""
+    S = x.size // (T * r.robot.dof)
     t0 = time.perf_counter()
-    r.solve(boxes, batch.q_start[0], batch.goal[0], T, batch.x0, 1, 4, alpha, nthreads=threads)
+    r.solve(boxes, q0, goal, T, x, 1, 4, alpha, nthreads=threads)
     one = time.perf_counter() - t0
     n = int(max(1, min(iters, seconds / max(one, 1e-6))))
-    # whole solves are repeated until the sample holds about `seconds` of work
     reps = int(max(1, seconds / max(one * n, 1e-6)))
     t0 = time.perf_counter()
     for _ in range(reps):
-        r.solve(boxes, batch.q_start[0], batch.goal[0], T, batch.x0, n, 4, alpha, nthreads=threads)
+        r.solve(boxes, q0, goal, T, x, n, 4, alpha, nthreads=threads)
     dt = time.perf_counter() - t0
-    # a solve of n iterations evaluates n*S*T*K candidates plus the initial S*T
-    evals = reps * (n * S * T * K + S * T)
-    return {"value": evals / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+    return reps * (n * S * T * K + S * T) / dt, reps, n, dt
+
+
+def cpu_baseline(robot, worlds, batch, alpha, iters, seconds):
+    """The FP64 reference solve on the host cores, on bounded samples: the
+    same 32-seed problem on all threads of the machine's CPU share (16 at most)
+    and on one thread, and seeded subsets of the IK, uneven and large
+    workloads with their whole-workload solve times extrapolated."""
+    from oracle import ref
+    from paper_2310_17274_amd import workloads as wl
+    threads = min(16, os.cpu_count() or 1)
+    r = ref.Ref(robot)
+    T, S, K = int(batch.horizon[0]), int(batch.seeds[0]), len(alpha)
+    boxes = worlds.world(0)
+    v, reps, n, dt = _oracle_solve_rate(r, boxes, batch.q_start[0], batch.goal[0], T, batch.x0, K, alpha, iters,
+                                        threads, seconds)
+    v1, reps1, n1, dt1 = _oracle_solve_rate(r, boxes, batch.q_start[0], batch.goal[0], T, batch.x0, K, alpha,
+                                            iters, 1, seconds / 2)
+    subsets = {}
+    # IK: 4 goals x 32 seeds; uneven: problems 0 and 1; large: 2 seeds
+    for name, (rb, wd, bt, meta), pick, sw in (
+            ("ik", wl.cfg_ik(), lambda bt: [(p, 32) for p in range(4)], 0),
+            ("uneven", wl.cfg_uneven(), lambda bt: [(0, int(bt.seeds[0])), (1, int(bt.seeds[1]))], 0),
+            ("large", wl.cfg_large(), lambda bt: [(0, 2)], 1)):
+        rb, wd, bt = wl.robot_f32(rb), wl.worlds_f32(wd), wl.to_f32(bt)
+        rr = ref.Ref(rb, swept=sw, sweep_steps=4)
+        offs = bt.row_offsets(rb.dof)
+        seed0 = np.concatenate([[0], np.cumsum(bt.seeds)])
+        evals, secs = 0.0, 0.0
+        for p, ns in pick(bt):
+            Tp = int(bt.horizon[p])
+            a, b_ = offs[seed0[p]], offs[seed0[p] + ns]
+            rate, rp, nn, tt = _oracle_solve_rate(rr, wd.world(int(bt.world[p])), bt.q_start[p], bt.goal[p], Tp,
+                                                  bt.x0[a:b_], len(meta["alpha"]), meta["alpha"], meta["iters"],
+                                                  threads, seconds / 6)
+            evals += rate * tt
+            secs += tt
+        rate = evals / secs
+        total = float(np.sum(bt.seeds * bt.horizon)) * len(meta["alpha"]) * meta["iters"]
+        subsets[name] = {"evals_per_s": rate, "sample_s": secs,
+                         "extrapolated_solve_s": total / rate, "sample": str([q for q in pick(bt)]) +
+                         " (problem, seeds) solved with the oracle"}
+    return {"value": v, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 reference solve of the same problem, {reps} x {n} of {iters} iterations, "
-                      f"{S} seeds in parallel over {threads} threads ({dt:.1f} s)"}
+                      f"{S} seeds in parallel over {threads} threads ({dt:.1f} s)",
+            "single_thread": {"value": v1, "unit": "evals/s", "cores": 1,
+                              "sample": f"{reps1} x {n1} iterations on one thread ({dt1:.1f} s)"},
+            "cpu_model": _cpu_model(),
+            "subsets_extrapolated": subsets}
 
 
 if __name__ == "__main__":

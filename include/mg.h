@@ -300,6 +300,26 @@ mg_status mg_particles(mg_ctx *ctx, mg_batch *batch, const float *q_start, const
                        float *mean, float *var, int n_particles, int n_iters, const float *eps,
                        float beta, float k_mu, float k_sigma, float *costs_out, void *stream);
 
+/* The particle stage with its noise drawn on the device: as mg_particles,
+ * with round it's draws eps[k][row][j] the counter-based standard normals of
+ * mg_philox_normals(seed, it, ...), generated into the batch's reserved
+ * buffer before each round (no host draws, no upload).  Capturable. */
+mg_status mg_particles_seeded(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
+                              float *mean, float *var, int n_particles, int n_iters,
+                              unsigned long long seed, float beta, float k_mu, float k_sigma,
+                              float *costs_out, void *stream);
+
+/* Counter-based standard normal draws (Alg.5 samples its particles from a
+ * zero-mean Gaussian): out[i][k][e] for rounds it = it0 + i, particles k and
+ * elements e = row * dof + joint is word e mod 4 of Philox-4x64-10 (Salmon,
+ * Moraes, Dror, Shaw, SC'11) at counter {e / 4, k, it, 0} and key {seed, 0},
+ * turned into a normal by Box-Muller: bits 41..63 and 9..31 give u1, u2 =
+ * (23-bit integer + 1/2) / 2^23, draw = sqrt(-2 ln u1) cos(2 pi u2).
+ *   out DEVICE [n_iters][n_particles][rows][dof], 16-byte aligned.
+ * Capturable. */
+mg_status mg_philox_normals(unsigned long long seed, int it0, int n_iters, int n_particles, int rows,
+                            int dof, float *out, void *stream);
+
 /* Retiming (Alg.4 retime, appendix "Time-step Descretization and Temporal
  * Weight Scaling"): for every seed, the waypoint spacing at which the
  * seed's largest joint velocity, acceleration or jerk reaches its limit.

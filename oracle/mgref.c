@@ -827,8 +827,8 @@ double mgref_philox_normal(uint64_t seed, int it, int k, int64_t e) {
   uint64_t w[4];
   mgref_philox4x64(ctr, key, w);
   const uint64_t x = w[e & 3];
-  const double u1 = ((double)(x >> 40) + 0.5) / 16777216.0;
-  const double u2 = ((double)((x >> 8) & 0xFFFFFFULL) + 0.5) / 16777216.0;
+  const double u1 = ((double)(x >> 41) + 0.5) / 8388608.0;
+  const double u2 = ((double)((x >> 9) & 0x7FFFFFULL) + 0.5) / 8388608.0;
   return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925287 * u2);   /* 2 pi */
 }
 

@@ -173,8 +173,8 @@ void mgref_particles(const mgref_robot *rb, const mgref_params *pr,
  * Moraes, Dror, Shaw, 'Parallel random numbers: as easy as 1, 2, 3', SC'11):
  * out = philox(ctr, key).  The draw of element e (= row * D + joint of the
  * batch's rows), particle k and round it under seed s takes word e mod 4 of
- * philox({e / 4, k, it, 0}, {s, 0}); its bits 40..63 and 8..31 give
- * u1, u2 = (24-bit integer + 1/2) / 2^24, and the draw is the Box-Muller
+ * philox({e / 4, k, it, 0}, {s, 0}); its bits 41..63 and 9..31 give
+ * u1, u2 = (23-bit integer + 1/2) / 2^23, and the draw is the Box-Muller
  * value sqrt(-2 ln u1) cos(2 pi u2). */
 void mgref_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 double mgref_philox_normal(uint64_t seed, int it, int k, int64_t e);

@@ -24,8 +24,8 @@ EXPORTS = ("mg_default_params", "mg_create", "mg_destroy", "mg_set_params", "mg_
            "mg_batch_create", "mg_batch_destroy", "mg_batch_seeds", "mg_batch_rows",
            "mg_cost_grad", "mg_lbfgs_step", "mg_linesearch", "mg_linesearch_eval", "mg_linesearch_noalloc",
            "mg_solve",
-           "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
-           "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose", "mg_set_self_collision",
+           "mg_batch_reserve_particles", "mg_particles", "mg_particles_seeded", "mg_philox_normals",
+           "mg_set_timing", "mg_eval_time", "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose", "mg_set_self_collision",
            "mg_retime", "mg_solve_timestep", "mg_ik_seeds", "mg_traj_select", "mg_motion_gen",
            "mg_steer", "mg_plan", "mg_last_error")
 
@@ -86,6 +86,9 @@ def lib():
     L.mg_batch_reserve_particles.argtypes = [_vp, C.c_int]
     L.mg_particles.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, _vp, C.c_float,
                                C.c_float, C.c_float, _vp, _vp]
+    L.mg_particles_seeded.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, C.c_ulonglong, C.c_float,
+                                      C.c_float, C.c_float, _vp, _vp]
+    L.mg_philox_normals.argtypes = [C.c_ulonglong, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp]
     L.mg_set_timing.argtypes = [_vp, C.c_int]
     L.mg_time_eval.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _fp, C.c_int,
                                C.POINTER(C.c_float), _vp]
@@ -113,7 +116,8 @@ def lib():
     for name in ("mg_create", "mg_set_params", "mg_set_worlds", "mg_batch_create", "mg_cost_grad",
                  "mg_lbfgs_step", "mg_linesearch", "mg_linesearch_eval", "mg_linesearch_noalloc", "mg_solve",
                  "mg_batch_seeds", "mg_batch_rows",
-                 "mg_batch_reserve_particles", "mg_particles", "mg_set_timing", "mg_eval_time",
+                 "mg_batch_reserve_particles", "mg_particles", "mg_particles_seeded", "mg_philox_normals",
+                 "mg_set_timing", "mg_eval_time",
                  "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose",
                  "mg_set_self_collision", "mg_retime", "mg_solve_timestep", "mg_ik_seeds",
                  "mg_traj_select", "mg_motion_gen", "mg_steer", "mg_plan"):

@@ -351,6 +351,18 @@ class Context:
                                      len(alpha), al, int(launches), C.byref(h), _stream()))
         return h.value
 
+    def mg_particles_seeded(self, b: Batch, q_start, goal, mean, var, n_particles, n_iters, seed, beta=0.0,
+                            k_mu=0.9, k_sigma=0.5, costs=False):
+        """Particle stage with device-drawn noise (mg_philox_normals); in
+        place on mean and var.  Returns (mean, var, costs or None)."""
+        out = torch.empty((n_iters, b.n_seeds, n_particles), dtype=torch.float32, device=self.device) \
+            if costs else None
+        check(_lib.lib().mg_particles_seeded(self.handle, b.handle, _ptr(q_start), _ptr(goal), _ptr(mean),
+                                             _ptr(var), int(n_particles), int(n_iters), C.c_ulonglong(seed),
+                                             float(beta), float(k_mu), float(k_sigma),
+                                             _ptr(out) if costs else None, _stream()))
+        return mean, var, out
+
     def mg_particles(self, b: Batch, q_start, goal, mean, var, eps, beta=0.0, k_mu=0.9,
                      k_sigma=0.5, costs=False):
         """Particle stage in place on mean and var ([rows, D]); eps is
@@ -362,6 +374,15 @@ class Context:
                                       _ptr(var), N, n_iters, _ptr(eps), float(beta), float(k_mu),
                                       float(k_sigma), _ptr(out) if costs else None, _stream()))
         return mean, var, out
+
+
+def mg_philox_normals(seed, it0, n_iters, n_particles, rows, dof, device="cuda"):
+    """Counter-based standard normal draws [n_iters, n_particles, rows, dof]
+    of rounds it0.. (the particle stage's device noise)."""
+    out = torch.empty((n_iters, n_particles, rows, dof), dtype=torch.float32, device=device)
+    check(_lib.lib().mg_philox_normals(C.c_ulonglong(seed), int(it0), int(n_iters), int(n_particles), int(rows),
+                                       int(dof), _ptr(out), _stream()))
+    return out
 
 
 class MgCost(torch.autograd.Function):

@@ -151,6 +151,7 @@ struct mg_batch {
   // wave-per-link chunk records for pm_K particles per row
   float* p_cost = nullptr;
   int p_cap = 0;
+  float* p_eps = nullptr;   // one round's device-drawn noise [p_cap][rows][D] (mg_particles_seeded)
   int pm_K = 0;
   mg::WlChunk* d_chunk_pm[2] = {};
   int chunks_pm[2] = {};
@@ -955,7 +956,8 @@ void mg_batch_destroy(mg_batch* b) {
   dev_free(b->cost_e); dev_free(b->gd_e); dev_free(b->mc_e); dev_free(b->grad_e); dev_free(b->pe_e);
   dev_free(b->c_cur); dev_free(b->g_cur); dev_free(b->dir); dev_free(b->best_c); dev_free(b->best_x);
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
-  dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost); dev_free(b->sel_dt); dev_free(b->sel_jerk);
+  dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost); dev_free(b->p_eps); dev_free(b->sel_dt);
+  dev_free(b->sel_jerk);
   dev_free(b->wl_part); dev_free(b->wl_count); dev_free(b->sp_h);
   delete b;
 }
@@ -1257,8 +1259,10 @@ mg_status mg_batch_reserve_particles(mg_batch* b, int n_particles) {
   mg_status st;
   if (n_particles > b->p_cap) {
     dev_free(b->p_cost);
+    dev_free(b->p_eps);
     b->p_cap = 0;
     if ((st = dev_alloc(&b->p_cost, (size_t)n_particles * b->rows)) != MG_OK) return st;
+    if ((st = dev_alloc(&b->p_eps, (size_t)n_particles * b->rows * b->ctx->D)) != MG_OK) return st;
     b->p_cap = n_particles;
   }
   // wave-per-link records for this particle count
@@ -1342,6 +1346,39 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
     pa.costs_out = costs_out ? costs_out + (size_t)it * b->n_seeds * n_particles : nullptr;
     HIP_TRY(mg::launch_particle_update(pa, s));
   }
+  return MG_OK;
+}
+
+mg_status mg_particles_seeded(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* mean,
+                              float* var, int n_particles, int n_iters, unsigned long long seed, float beta,
+                              float k_mu, float k_sigma, float* costs_out, void* stream) {
+  mg_status st = common_checks(c, b);
+  if (st != MG_OK) return st;
+  if (n_particles < 1 || n_particles > b->p_cap || !b->p_eps)
+    return fail(MG_ERR_STATE, "n_particles = %d exceeds the %d reserved (mg_batch_reserve_particles)",
+                n_particles, b->p_cap);
+  if (n_iters < 0) return fail(MG_ERR_ARG, "n_iters must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long n = (long long)b->rows * c->D;
+  for (int it = 0; it < n_iters; ++it) {
+    // this round's draws, then the round on them
+    HIP_TRY(mg::launch_philox_normals(seed, it, 1, n_particles, n, b->p_eps, s));
+    if ((st = mg_particles(c, b, q_start, goal, mean, var, n_particles, 1, b->p_eps, beta, k_mu, k_sigma,
+                           costs_out ? costs_out + (size_t)it * b->n_seeds * n_particles : nullptr, stream)) !=
+        MG_OK)
+      return st;
+  }
+  return MG_OK;
+}
+
+mg_status mg_philox_normals(unsigned long long seed, int it0, int n_iters, int n_particles, int rows, int dof,
+                            float* out, void* stream) {
+  if (!out) return fail(MG_ERR_ARG, "null out");
+  if (it0 < 0 || n_iters < 1 || n_particles < 1 || rows < 1 || dof < 1 || n_iters > 65535 || n_particles > 65535)
+    return fail(MG_ERR_SHAPE, "bad draw shape");
+  if (((uintptr_t)out) & 15) return fail(MG_ERR_ARG, "out must be 16-byte aligned");
+  HIP_TRY(mg::launch_philox_normals(seed, it0, n_iters, n_particles, (long long)rows * dof, out,
+                                    static_cast<hipStream_t>(stream)));
   return MG_OK;
 }
 

@@ -231,5 +231,34 @@ __device__ __forceinline__ float near_pair(const v4f& A0, const v4f& A1, const v
   return sdf;
 }
 
+// Counter-based normal draws of the particle stage: Philox-4x64 with 10
+// rounds (Salmon et al., SC'11) and Box-Muller.  Element e (= row * D +
+// joint), particle k and round it under seed s take word e mod 4 of
+// philox({e / 4, k, it, 0}, {s, 0}); bits 41..63 and 9..31 give the
+// uniforms u1, u2 = (23-bit integer + 1/2) / 2^23 and the draw is
+// sqrt(-2 ln u1) cos(2 pi u2).
+__device__ __forceinline__ void philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0,
+                                           uint64_t k1, uint64_t* out) {
+  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t hi0 = __umul64hi(c0, M0), lo0 = c0 * M0;
+    const uint64_t hi1 = __umul64hi(c2, M1), lo1 = c2 * M1;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+__device__ __forceinline__ float box_muller(uint64_t w) {
+  const float u1 = ((float)(unsigned)(w >> 41) + 0.5f) * (1.0f / 8388608.0f);
+  const float u2 = ((float)(unsigned)((w >> 9) & 0x7FFFFFu) + 0.5f) * (1.0f / 8388608.0f);
+  // (cos(2 pi u2) as cospi(2 u2): no rounding of the angle)
+  return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
 }  // namespace
 }  // namespace mg

@@ -395,6 +395,10 @@ hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, 
 hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s);
 
 hipError_t launch_particle_update(const ParticleArgs& a, hipStream_t s);
+// standard normal draws [n_iters][N][n] of rounds it0 .. it0 + n_iters - 1
+// (Philox-4x64-10 + Box-Muller, mg_device.h)
+hipError_t launch_philox_normals(unsigned long long seed, int it0, int n_iters, int N, long long n, float* out,
+                                 hipStream_t s);
 hipError_t launch_retime(const RetimeArgs& a, hipStream_t s);
 hipError_t launch_ik_seeds(const IkSeedArgs& a, hipStream_t s);
 hipError_t launch_traj_select(const TrajSelectArgs& a, hipStream_t s);

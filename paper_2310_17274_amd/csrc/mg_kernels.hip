@@ -120,6 +120,27 @@ __global__ __launch_bounds__(kWave) void speed_adjoint_kernel(const SpeedAdjArgs
 }
 
 // --------------------------------------------------------------------------
+// Standard normal draws of the particle stage, one thread per four
+// consecutive elements of a (round, particle): one Philox block gives the
+// four words (float4 stores where the row block allows).
+__global__ __launch_bounds__(kBlock) void philox_normals_kernel(unsigned long long seed, int it0, int N,
+                                                                long long n, float* out) {
+  const long long q = (long long)blockIdx.x * kBlock + threadIdx.x;   // group of four elements
+  const int k = blockIdx.y, it = it0 + blockIdx.z;
+  if (4 * q >= n) return;
+  uint64_t w[4];
+  philox4x64((uint64_t)q, (uint64_t)(unsigned)k, (uint64_t)(unsigned)it, 0, seed, 0, w);
+  float* o = out + ((size_t)blockIdx.z * N + k) * n + 4 * q;
+  if ((n & 3) == 0) {
+    *reinterpret_cast<float4*>(o) = float4{box_muller(w[0]), box_muller(w[1]), box_muller(w[2]), box_muller(w[3])};
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (4 * q + i < n) o[i] = box_muller(w[i]);
+  }
+}
+
+// --------------------------------------------------------------------------
 // Particle-based optimization update (Alg.5, Eq.(12)-(13)) of one seed per
 // workgroup: particle costs from the per-row sums, exponential-utility
 // weights w = softmax(-(C - min C) / beta), then per element
@@ -437,6 +458,15 @@ hipError_t launch_speed_adjoint(const SpeedAdjArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;
   const size_t lds = (size_t)kWave * a.n_links * 12 * sizeof(float);
   speed_adjoint_kernel<<<dim3(a.n_seeds, a.K), kWave, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_philox_normals(unsigned long long seed, int it0, int n_iters, int N, long long n, float* out,
+                                 hipStream_t s) {
+  if (n_iters < 1 || N < 1 || n < 1 || N > 65535 || n_iters > 65535 || (((uintptr_t)out) & 15)) return hipErrorInvalidValue;
+  const long long groups = (n + 3) / 4;
+  const dim3 grid((unsigned)((groups + kBlock - 1) / kBlock), N, n_iters);
+  philox_normals_kernel<<<grid, kBlock, 0, s>>>(seed, it0, N, n, out);
   return hipGetLastError();
 }
 

@@ -1229,8 +1229,8 @@ def test_philox_normal_box_muller(oracle_lib):
     seed, it, k = 7, 1, 3
     for e in (0, 1, 2, 3, 4, 5, 1234567, 2 ** 40 + 3):
         w = ref.philox4x64([e >> 2, k, it, 0], [seed, 0])[e & 3]
-        u1 = ((w >> 40) + 0.5) / 2 ** 24
-        u2 = (((w >> 8) & 0xFFFFFF) + 0.5) / 2 ** 24
+        u1 = ((w >> 41) + 0.5) / 2 ** 23
+        u2 = (((w >> 9) & 0x7FFFFF) + 0.5) / 2 ** 23
         want = math.sqrt(-2.0 * math.log(u1)) * math.cos(2 * math.pi * u2)
         assert L.mgref_philox_normal(seed, it, k, e) == pytest.approx(want, rel=1e-15, abs=1e-15)
     from scipy import stats

@@ -640,3 +640,42 @@ def test_gpu_gradient_against_central_differences():
     # fp32 cost rounding bounds the difference quotient's accuracy
     noise = 4 * float(c.sum()) * 6e-8 / (2 * h)
     assert np.linalg.norm(fd - gi) <= 2e-2 * np.linalg.norm(gi) + noise * np.sqrt(len(idx))
+
+
+def test_device_noise_matches_the_oracle():
+    """Counter-based draws on the device (Philox-4x64-10 + Box-Muller)
+    against the oracle's: the same integer stream, so the normals agree to
+    fp32 evaluation of sqrt(-2 ln u1) (at most 5.9, a few ulp) times
+    cospi(2 u2) (a few ulp): 4e-6 absolute."""
+    from paper_2310_17274_amd.binding import mg_philox_normals
+    for seed, it0, n_it, N, rows, D in ((7, 0, 2, 5, 33, 7), (2 ** 63 + 11, 3, 1, 16, 96, 14), (0, 0, 1, 3, 5, 3)):
+        got = mg_philox_normals(seed, it0, n_it, N, rows, D).cpu().numpy().astype(np.float64)
+        want = ref.philox_normals(seed, it0 + n_it, N, rows, D)[it0:]
+        np.testing.assert_allclose(got, want, rtol=0, atol=4e-6)
+
+
+@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2")])
+def test_seeded_particle_stage(layout):
+    """The particle stage with device-drawn noise equals the stage fed the
+    same draws from memory (bit for bit), and agrees with the oracle's stage
+    on the oracle's draws."""
+    from paper_2310_17274_amd.binding import mg_philox_normals
+    case = make_case("plain", layout=layout)
+    S, T, D, N, seed = 4, 32, 7, 64, 1234
+    case.b.mg_batch_reserve_particles(N)
+    m1, v1 = case.x.clone(), torch.full_like(case.x, 0.05 ** 2)
+    _, _, c1 = case.ctx.mg_particles_seeded(case.b, case.q_start, case.goal, m1, v1, N, 2, seed, costs=True)
+    eps = mg_philox_normals(seed, 0, 2, N, S * T, D)
+    m2, v2 = case.x.clone(), torch.full_like(case.x, 0.05 ** 2)
+    _, _, c2 = case.ctx.mg_particles(case.b, case.q_start, case.goal, m2, v2, eps, costs=True)
+    torch.cuda.synchronize()
+    assert torch.equal(m1, m2) and torch.equal(v1, v2) and torch.equal(c1, c2)
+    x0 = case.batch.x0.reshape(S, T, D)
+    eps_ref = ref.philox_normals(seed, 2, N, S * T, D).reshape(2, N, S, T, D)
+    m_ref, _, _ = case.ref.particles(case.worlds.world(0), case.batch.q_start[0], case.batch.goal[0], T, x0,
+                                     np.full_like(x0, np.float32(0.05 ** 2)), eps_ref)
+    mg = m1.cpu().numpy().reshape(S, T, D)
+    for s in range(S):
+        moved = np.abs(m_ref[s] - x0[s]).max()
+        assert moved > 1e-3
+        assert np.abs(mg[s] - m_ref[s]).max() <= 1e-2 * moved + 1e-5, s
