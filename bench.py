@@ -66,10 +66,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile", choices=["eval", "copy"],
+    ap.add_argument("--profile", choices=["eval", "copy", "large"],
                     help="profiling driver instead of the benchmark: 'eval' runs --launches "
                          "line searches of the benchmark shape (one evaluation launch each), "
-                         "'copy' copies 256 MiB five times (HBM byte-counter calibration)")
+                         "'large' one particle round and --launches line searches of the large "
+                         "two-arm workload, 'copy' copies 256 MiB five times (HBM byte-counter "
+                         "calibration)")
     ap.add_argument("--launches", type=int, default=10)
     ap.add_argument("--layout", type=int, choices=[0, 1, 2, 3], default=None,
                     help="force the evaluation layout (0 lane per link, 1 wave per link, "
@@ -86,6 +88,8 @@ def main():
         sys.exit(2)
     if args.profile == "copy":
         return profile_copy()
+    if args.profile == "large":
+        return profile_large(args.launches, args.layout)
 
     import torch
     from paper_2310_17274_amd import workloads as wl
@@ -566,6 +570,37 @@ def profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, launches, layou
     torch.cuda.synchronize()
     print(json.dumps({"profile": "eval", "launches": launches, "kernel_digest": kernel_digest(),
                       "layout": layout}), flush=True)
+
+
+def profile_large(launches, layout=None):
+    """The large two-arm workload for hardware-counter runs: one particle
+    round (256 particles per seed, device noise) and `launches` line searches
+    (one evaluation launch each, K = 4)."""
+    import torch
+    from paper_2310_17274_amd import workloads as wl
+    from paper_2310_17274_amd.binding import Context, default_params
+    robot, worlds, batch, meta = wl.cfg_large()
+    robot, worlds, batch = wl.robot_f32(robot), wl.worlds_f32(worlds), wl.to_f32(batch)
+    dev = torch.device("cuda:0")
+    ctx = Context(robot, default_params(swept=1, sweep_steps=4))
+    ctx.mg_set_worlds(worlds)
+    alpha = meta["alpha"]
+    b = ctx.batch(batch.seeds, batch.horizon, batch.world, K_max=len(alpha), m_max=4)
+    b.mg_batch_reserve_particles(256)
+    q_start, goal, x0 = _inputs(robot, batch, dev)
+    c0, g0, _ = ctx.mg_cost_grad(b, q_start, goal, x0)
+    dvec = ctx.mg_lbfgs_step(b, 4, True, x0, g0)
+    if layout is None:
+        tuned = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha, launches=3))
+    else:
+        b.mg_batch_set_layout(layout, 0)
+        tuned = f"forced {layout}"
+    mean, var = x0.clone(), torch.full_like(x0, 0.05 ** 2)
+    ctx.mg_particles_seeded(b, q_start, goal, mean, var, 256, 1, 55)
+    for _ in range(launches):
+        ctx.mg_linesearch(b, q_start, goal, x0, c0, g0, dvec, alpha, 1)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": "large", "launches": launches, "layout": tuned}), flush=True)
 
 
 def profile_copy():

@@ -300,6 +300,10 @@ mg::WaveLinks dev_wave_links(const mg_ctx* c) {
   wl.maxs = c->maxs;
   wl.max_depth = c->max_depth;
   wl.halves = 1;
+  // at most 8 waves per workgroup (two per SIMD, the full register budget):
+  // a robot of more than 7 links runs its links in passes of 7, except with
+  // self-collision, whose phase needs every link's spheres at once
+  wl.link_waves = (c->n_self == 0 && c->L + 1 > 8) ? 7 : c->L;
   wl.part = nullptr;
   wl.count = nullptr;
   wl.self_pairs = c->d_self_pairs;

@@ -289,12 +289,16 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const int bx = blockIdx.x;
   // cuboid slice of this workgroup (gridDim.y slices share a chunk)
   const int h = __builtin_amdgcn_readfirstlane(blockIdx.y), H = __builtin_amdgcn_readfirstlane(gridDim.y);
-  // waves: one per link and one for the joint terms (HS = 1), or two per
-  // link with half of its spheres each (HS = 2, robots of up to 8 links)
+  // waves: link waves and one for the joint terms (HS = 1), or two per link
+  // with half of its spheres each (HS = 2, robots of up to 8 links).  With
+  // HS = 1 there are LW <= L link waves: link wave w takes links w, w + LW,
+  // ... in passes (a workgroup of at most 8 waves keeps the register budget
+  // of two waves per SIMD for a longer robot)
   const int HS = a.wl.halves;
-  const int W = HS == 2 ? 2 * L : L + 1;
-  const bool link_w = wave < L * HS;
-  const int l = link_w ? wave >> (HS - 1) : 0, hs = link_w ? wave & (HS - 1) : 0;   // (HS is 1 or 2)
+  const int LW = HS == 2 ? 2 * L : a.wl.link_waves;
+  const int W = HS == 2 ? 2 * L : LW + 1;
+  const int npass = HS == 2 ? 1 : (L + LW - 1) / LW;
+  const bool joint_w = HS == 1 && wave == W - 1;
 
   // ---- everything is read from memory in two dependent rounds: the
   //      chunk's record and this wave's tables (scalar loads), then the
@@ -314,11 +318,11 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   pb.S = c0.z; pb.T = c0.w; pb.world = 0; pb.row0 = c1.z;
   pb.seed0 = 0; pb.pad0 = 0; pb.pad1 = 0; pb.pad2 = 0;
   const int box_lo = c1.x, box_hi = c1.y, n_e = c1.w;
-  const v4i info = *(cv4i*)(a.wl.info + l);
+  // (this wave's first link: its tables are read with the chunk record)
+  const int l0 = HS == 2 ? wave >> 1 : min(wave, L - 1);
+  v4i info = *(cv4i*)(a.wl.info + l0);
   // (the ball of this lane's slot group: all slots, or half of them)
-  const v4f bl = *(cv4f*)(a.wl.ball + l * 3 + (HS == 2 ? 1 + hs : (G == 2 ? 1 + lane / E : 0)));
-  const int jw = wave < D ? wave : 0;
-  const int jsub = ((cint*)a.wl.joint_rec)[2 * jw + 1];
+  v4f bl = *(cv4f*)(a.wl.ball + l0 * 3 + (HS == 2 ? 1 + (wave & 1) : (G == 2 ? 1 + lane / E : 0)));
 
   const int e0 = e_first + el;
   const bool valid = e0 < n_e;
@@ -428,7 +432,23 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   constexpr int NPL = kWlPartsPerLink;
   float* s_joint = s_part + (size_t)L * NPL * E;
   float* s_ex = s_joint + (size_t)(3 + D) * E;
+
+  for (int pass = 0; pass < npass; ++pass) {
+  const int lp = HS == 2 ? wave >> 1 : wave + pass * LW;
+  const bool link_w = HS == 2 ? wave < 2 * L : (wave < LW && lp < L);
+  const int l = link_w ? lp : 0, hs = HS == 2 ? wave & 1 : 0;
+  if (pass > 0 && link_w) {
+    info = *(cv4i*)(a.wl.info + l);
+    bl = *(cv4f*)(a.wl.ball + l * 3 + (G == 2 ? 1 + lane / E : 0));
+  }
   float* part = link_w ? s_part + (size_t)l * NPL * E : s_joint;
+  if (pass > 0) {
+    // the first cuboid tile again (the previous pass's tiles overwrote it)
+    __syncthreads();
+    const int nb0 = min(kWlBoxTile, w1 - w0);
+    for (int i = tid; i < 4 * nb0; i += nthreads) s_box[i] = reinterpret_cast<const float4*>(a.box + w0)[i];
+    __syncthreads();
+  }
 
   // ---- link waves: forward kinematics along the chain, the pose term,
   //      this wave's sphere slots ----
@@ -600,7 +620,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     float bv;
     int bk;
     self_winner(W, s_best, lane, bv, bk);
-    if (!link_w) jc += a.pr.w_self * bv;                        // the joint wave
+    if (joint_w) jc += a.pr.w_self * bv;                        // the joint wave
     if (HS == 2 && l == 0 && hs == 1) cost += a.pr.w_self * bv;  // (no joint wave)
     if (link_w && bk >= 0) {
       const int4 pr = reinterpret_cast<const int4*>(a.wl.self_pairs)[bk];
@@ -637,7 +657,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   // ---- the joint wave (HS = 1): joint limits (Eq.(17)) and smoothness
   //      (Eq.(16)) of joints j = h mod H ----
   //      (slot group g takes joints g, g + G, ...)
-  if (!link_w) {
+  if (joint_w && pass == 0) {
     float gdj = 0.0f;
     for (int j0 = 0; j0 < D; j0 += G) {
       const int j = j0 + g;
@@ -784,17 +804,23 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
       part[13 * E + el] = T[3]; part[14 * E + el] = T[7]; part[15 * E + el] = T[11];
     }
   }
+  }   // passes
   __syncthreads();
 
   // ---- combine: wave j < D forms joint j's derivative from the wrenches
   //      of the links whose chain holds it (summed in link order) and link
   //      j's frame; the last wave sums cost, clearance and directional
   //      derivative over the links in order, then the joint wave's ----
+  //      (wave w gathers joints w, w + W: a workgroup of W >= D / 2 waves)
   const size_t eo = (size_t)k * a.rows + row;
-  float gsum = 0.0f;
-  if (GRAD && wave < D) {
-    const float* pj = s_part + (size_t)wave * NPL * E + el;
-    gsum = HS == 1 ? s_joint[(3 + wave) * E + el] : pj[3 * E];
+  float gsv[2] = {0.0f, 0.0f};
+#pragma unroll
+  for (int qj = 0; qj < 2; ++qj) {
+    const int jj = wave + qj * W;
+    if (!GRAD || jj >= D) continue;
+    const int jsub = ((cint*)a.wl.joint_rec)[2 * jj + 1];
+    const float* pj = s_part + (size_t)jj * NPL * E + el;
+    float gsum = HS == 1 ? s_joint[(3 + jj) * E + el] : pj[3 * E];
     float sF[3] = {0.0f, 0.0f, 0.0f}, sM[3] = {0.0f, 0.0f, 0.0f};
     for (int v = 0; v < L; ++v) {
       const float* pv = s_part + (size_t)v * NPL * E + el;
@@ -811,7 +837,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     const float ux = sM[0] - (oy * sF[2] - oz * sF[1]);
     const float uy = sM[1] - (oz * sF[0] - ox * sF[2]);
     const float uz = sM[2] - (ox * sF[1] - oy * sF[0]);
-    gsum += zx * ux + zy * uy + zz * uz;
+    gsv[qj] = gsum + (zx * ux + zy * uy + zz * uz);
   }
   float tc = 0.0f, tm = 3.0e38f, tg = 0.0f;
   if (wave == W - 1) {
@@ -835,7 +861,9 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     const int NP = 3 + D;
     const size_t cbase = (size_t)bx * H * NP * kWave;
     float* mine = a.wl.part + cbase + (size_t)h * NP * kWave;
-    if (GRAD && wave < D) part_store(mine + (3 + wave) * kWave + lane, gsum);
+#pragma unroll
+    for (int qj = 0; qj < 2; ++qj)
+      if (GRAD && wave + qj * W < D) part_store(mine + (3 + wave + qj * W) * kWave + lane, gsv[qj]);
     if (wave == W - 1) {
       part_store(mine + 0 * kWave + lane, tc);
       part_store(mine + 1 * kWave + lane, tm);
@@ -854,11 +882,14 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     if (ticket != H - 1) return;
     __threadfence();
     if (wave == 0 && lane == 0) __hip_atomic_store(a.wl.count + bx, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (GRAD && wave < D) {
-      gsum = 0.0f;
-      for (int u = 0; u < H; ++u)
-        gsum += part_load(a.wl.part + cbase + ((size_t)u * NP + 3 + wave) * kWave + lane);
-    }
+#pragma unroll
+    for (int qj = 0; qj < 2; ++qj)
+      if (GRAD && wave + qj * W < D) {
+        float gsum = 0.0f;
+        for (int u = 0; u < H; ++u)
+          gsum += part_load(a.wl.part + cbase + ((size_t)u * NP + 3 + wave + qj * W) * kWave + lane);
+        gsv[qj] = gsum;
+      }
     if (wave == W - 1) {
       tc = 0.0f; tm = 3.0e38f; tg = 0.0f;
       for (int u = 0; u < H; ++u) {
@@ -870,7 +901,9 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     }
   }
   if (!valid || g != 0) return;
-  if (GRAD && wave < D) a.grad_e[eo * D + wave] = gsum;
+#pragma unroll
+  for (int qj = 0; qj < 2; ++qj)
+    if (GRAD && wave + qj * W < D) a.grad_e[eo * D + wave + qj * W] = gsv[qj];
   if (wave == W - 1) {
     a.cost_e[eo] = tc;
     if (a.mc_e) a.mc_e[eo] = tm;
@@ -909,17 +942,23 @@ hipError_t wl_pick(const EvalArgs& a, dim3 grid, dim3 block, size_t lds, int wav
 template <int MAXS, int G>
 hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
   const int HS = a.wl.halves;
-  const int waves = HS == 2 ? 2 * a.rb.n_links : a.rb.n_links + 1;
+  const int L = a.rb.n_links;
+  const int LW = a.wl.link_waves;
+  const int waves = HS == 2 ? 2 * L : LW + 1;
   if (waves * kWave > 1024 || slices < 1 || ((HS == 2 || G > 1) && slices > 1)) return hipErrorInvalidValue;
+  // link passes: every link covered, every joint gathered (two per wave at
+  // most), self-collision in one pass only
+  if (HS == 1 && (LW < 1 || LW > L || 2 * waves < a.rb.dof || (a.pr.n_self > 0 && LW != L)))
+    return hipErrorInvalidValue;
   if (G > 1 && (HS != 1 || a.pr.n_self > 0)) return hipErrorInvalidValue;
   if (slices > 1 && (!a.wl.part || !a.wl.count)) return hipErrorInvalidValue;
   // particle mode (per-candidate draws): cost only, draws staged per row
   const bool pm = a.var != nullptr;
   if (pm && (!cand || grad || a.K < 1 || a.wl.pm_rows < (kWave / G - 1) / a.K + 10 || a.wl.pm_rows > kWlStageRows))
     return hipErrorInvalidValue;
-  // every joint has a gathering wave, the last wave is none of them, and
-  // two 64-thread passes cover a cuboid tile
-  if (a.rb.dof > waves - 1 || waves < 2 || !a.wl.chunk) return hipErrorInvalidValue;
+  // the joint gathers fit (two per wave), and two 64-thread passes cover a
+  // cuboid tile
+  if (a.rb.dof > 2 * waves || waves < 2 || !a.wl.chunk) return hipErrorInvalidValue;
   const size_t lds = wl_lds_bytes(a.rb.n_links, a.rb.dof, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0, HS,
                                   a.wl.maxs, kWave / G, pm ? a.wl.pm_rows : 0);
   if (lds > kWlLdsMax) return hipErrorInvalidValue;

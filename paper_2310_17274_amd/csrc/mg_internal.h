@@ -98,6 +98,8 @@ struct WaveLinks {
   int maxs;
   int max_depth;           // deepest chain (joints from the root)
   int halves;              // waves per link: 1, or 2 (each with half of the slots)
+  int link_waves;          // halves == 1: link waves (<= n_links); wave w takes links w,
+                           //   w + link_waves, ... in passes
   int groups;              // slot groups per wave: 1, or 2 (32 evaluations per workgroup,
                            //   each half of the wave with half of the slots; halves == 1)
   int pm_rows;             // particle mode: rows of draws staged per workgroup (else 0)
