@@ -290,10 +290,12 @@ mg_status mg_autotune(mg_ctx *ctx, mg_batch *batch, const float *q_start, const 
  *   mean, var DEVICE [rows][D] in/out (var per element, rad^2)
  *   eps       DEVICE [n_iters][n_particles][rows][D] standard normal draws
  *   costs_out DEVICE [n_iters][seeds][n_particles] particle costs, or NULL
- * The costing launch is wave per link when self-collision is on or that
- * layout was set with mg_batch_set_layout, and n_particles is the last
- * reserved count; otherwise lane per link (the autotuner's choice for
- * line-search candidates is not carried over).
+ * The costing launch is wave per link (one slot group per wave, unless
+ * mg_batch_set_layout chose two) when n_particles is the last reserved
+ * count and the layout fits the robot, lane per link when
+ * mg_batch_set_layout chose it (self-collision and the speed metric keep
+ * wave per link); the autotuner's choice for line-search candidates is not
+ * carried over.
  * MG_ERR_STATE if n_particles exceeds the reservation.  Capturable. */
 mg_status mg_batch_reserve_particles(mg_batch *batch, int n_particles);
 mg_status mg_particles(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,

@@ -1290,18 +1290,20 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
     return fail(MG_ERR_ARG, "null q_start, goal, mean, var or eps");
   if (!(k_mu >= 0.0f && k_mu <= 1.0f) || !(k_sigma >= 0.0f && k_sigma <= 1.0f))
     return fail(MG_ERR_ARG, "k_mu and k_sigma must lie in [0, 1]");
-  const int groups = b->wl_groups == 2 && wl_groups_possible(c) ? 2 : 1;
+  // wave per link with one slot group (64 particles of one row per
+  // workgroup: their spheres lie close together, so the wave-level cuboid
+  // cull is tight) unless mg_batch_set_layout chose another layout; the
+  // autotuner's choice for line-search candidates is not carried over (on
+  // the two-arm tree with 500 cuboids and swept collision a particle round
+  // measured 139 ms with one slot group, 244 ms with two, 350 ms lane per
+  // link)
+  const bool lane_set = b->layout_set && b->layout == 0;
+  const int groups = b->layout_set && b->wl_groups == 2 && wl_groups_possible(c) ? 2 : 1;
   const int halves = groups == 2 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(c) ? 2 : 1));
   const int E = mg::kWave / groups;
   // rows a chunk of E particles touches, with the stencils' four on either side
   const int pm_rows = (E - 1) / n_particles + 10;
-  // wave per link where self-collision is on or that layout was set by
-  // mg_batch_set_layout (and the records are for this particle count), else
-  // lane per link.  The autotuner's choice for line-search candidates is not
-  // carried over: on the two-arm tree with 500 cuboids and swept collision
-  // it picks wave per link, yet a particle round measured 13% faster lane
-  // per link.
-  const bool wl = ((b->layout_set && b->layout == 1) || needs_wl(c)) && wl_possible(c) &&
+  const bool wl = (!lane_set || needs_wl(c)) && wl_possible(c) &&
                   n_particles == b->pm_K && pm_rows <= mg::kWlStageRows &&
                   mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, c->n_self > 0, halves, c->maxs, E, pm_rows) <=
                       c->lds_max;

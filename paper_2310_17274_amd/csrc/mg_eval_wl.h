@@ -275,7 +275,10 @@ __device__ __forceinline__ float groups_min(float v) {
 // for the same batch, the chain run twice).
 // SW: the chain also runs at the neighbouring waypoints, for swept
 // collision and the speed metric; SP: the speed metric (Eq.(11)).
-template <int MAXS, bool CAND, bool GRAD, int NT, int G, bool SW, bool SP>
+// LP: link passes (HS = 1, more links than link waves); without it the
+// pass loop runs once and compiles away (the register budget of the
+// one-pass kernel stays what it was).
+template <int MAXS, bool CAND, bool GRAD, int NT, int G, bool SW, bool SP, bool LP>
 __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   constexpr int E = kWave / G;
   extern __shared__ float s_mem[];
@@ -295,9 +298,9 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   // ... in passes (a workgroup of at most 8 waves keeps the register budget
   // of two waves per SIMD for a longer robot)
   const int HS = a.wl.halves;
-  const int LW = HS == 2 ? 2 * L : a.wl.link_waves;
+  const int LW = HS == 2 ? 2 * L : (LP ? a.wl.link_waves : L);
   const int W = HS == 2 ? 2 * L : LW + 1;
-  const int npass = HS == 2 ? 1 : (L + LW - 1) / LW;
+  const int npass = LP ? (L + LW - 1) / LW : 1;
   const bool joint_w = HS == 1 && wave == W - 1;
 
   // ---- everything is read from memory in two dependent rounds: the
@@ -323,6 +326,10 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   v4i info = *(cv4i*)(a.wl.info + l0);
   // (the ball of this lane's slot group: all slots, or half of them)
   v4f bl = *(cv4f*)(a.wl.ball + l0 * 3 + (HS == 2 ? 1 + (wave & 1) : (G == 2 ? 1 + lane / E : 0)));
+  // subtree masks of the joints this wave gathers (wave and wave + W), read
+  // with the first round
+  const int jsub0 = ((cint*)a.wl.joint_rec)[2 * min(wave, D - 1) + 1];
+  const int jsub1 = LP ? ((cint*)a.wl.joint_rec)[2 * min(wave + W, D - 1) + 1] : 0;
 
   const int e0 = e_first + el;
   const bool valid = e0 < n_e;
@@ -433,16 +440,17 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   float* s_joint = s_part + (size_t)L * NPL * E;
   float* s_ex = s_joint + (size_t)(3 + D) * E;
 
-  for (int pass = 0; pass < npass; ++pass) {
+  // one pass over this wave's link (LP: one per link of the wave in turn)
+  auto link_pass = [&](const int pass) {
   const int lp = HS == 2 ? wave >> 1 : wave + pass * LW;
-  const bool link_w = HS == 2 ? wave < 2 * L : (wave < LW && lp < L);
+  const bool link_w = HS == 2 ? wave < 2 * L : (LP ? wave < LW && lp < L : wave < L);
   const int l = link_w ? lp : 0, hs = HS == 2 ? wave & 1 : 0;
-  if (pass > 0 && link_w) {
+  if (LP && pass > 0 && link_w) {
     info = *(cv4i*)(a.wl.info + l);
     bl = *(cv4f*)(a.wl.ball + l * 3 + (G == 2 ? 1 + lane / E : 0));
   }
   float* part = link_w ? s_part + (size_t)l * NPL * E : s_joint;
-  if (pass > 0) {
+  if (LP && pass > 0) {
     // the first cuboid tile again (the previous pass's tiles overwrote it)
     __syncthreads();
     const int nb0 = min(kWlBoxTile, w1 - w0);
@@ -620,7 +628,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     float bv;
     int bk;
     self_winner(W, s_best, lane, bv, bk);
-    if (joint_w) jc += a.pr.w_self * bv;                        // the joint wave
+    if (!link_w) jc += a.pr.w_self * bv;                        // the joint wave (one pass)
     if (HS == 2 && l == 0 && hs == 1) cost += a.pr.w_self * bv;  // (no joint wave)
     if (link_w && bk >= 0) {
       const int4 pr = reinterpret_cast<const int4*>(a.wl.self_pairs)[bk];
@@ -657,7 +665,9 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   // ---- the joint wave (HS = 1): joint limits (Eq.(17)) and smoothness
   //      (Eq.(16)) of joints j = h mod H ----
   //      (slot group g takes joints g, g + G, ...)
-  if (joint_w && pass == 0) {
+  // (written as !link_w so that the compiler sees the link-wave and
+  // joint-wave paths exclude each other and shares their registers)
+  if (!link_w && (!LP || (joint_w && pass == 0))) {
     float gdj = 0.0f;
     for (int j0 = 0; j0 < D; j0 += G) {
       const int j = j0 + g;
@@ -804,7 +814,12 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
       part[13 * E + el] = T[3]; part[14 * E + el] = T[7]; part[15 * E + el] = T[11];
     }
   }
-  }   // passes
+  };
+  if constexpr (LP) {
+    for (int pass = 0; pass < npass; ++pass) link_pass(pass);
+  } else {
+    link_pass(0);
+  }
   __syncthreads();
 
   // ---- combine: wave j < D forms joint j's derivative from the wrenches
@@ -813,12 +828,13 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   //      derivative over the links in order, then the joint wave's ----
   //      (wave w gathers joints w, w + W: a workgroup of W >= D / 2 waves)
   const size_t eo = (size_t)k * a.rows + row;
+  constexpr int NJ = LP ? 2 : 1;   // joints gathered per wave
   float gsv[2] = {0.0f, 0.0f};
 #pragma unroll
-  for (int qj = 0; qj < 2; ++qj) {
+  for (int qj = 0; qj < NJ; ++qj) {
     const int jj = wave + qj * W;
     if (!GRAD || jj >= D) continue;
-    const int jsub = ((cint*)a.wl.joint_rec)[2 * jj + 1];
+    const int jsub = qj == 0 ? jsub0 : jsub1;
     const float* pj = s_part + (size_t)jj * NPL * E + el;
     float gsum = HS == 1 ? s_joint[(3 + jj) * E + el] : pj[3 * E];
     float sF[3] = {0.0f, 0.0f, 0.0f}, sM[3] = {0.0f, 0.0f, 0.0f};
@@ -862,7 +878,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     const size_t cbase = (size_t)bx * H * NP * kWave;
     float* mine = a.wl.part + cbase + (size_t)h * NP * kWave;
 #pragma unroll
-    for (int qj = 0; qj < 2; ++qj)
+    for (int qj = 0; qj < NJ; ++qj)
       if (GRAD && wave + qj * W < D) part_store(mine + (3 + wave + qj * W) * kWave + lane, gsv[qj]);
     if (wave == W - 1) {
       part_store(mine + 0 * kWave + lane, tc);
@@ -883,7 +899,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     __threadfence();
     if (wave == 0 && lane == 0) __hip_atomic_store(a.wl.count + bx, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
-    for (int qj = 0; qj < 2; ++qj)
+    for (int qj = 0; qj < NJ; ++qj)
       if (GRAD && wave + qj * W < D) {
         float gsum = 0.0f;
         for (int u = 0; u < H; ++u)
@@ -902,7 +918,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   }
   if (!valid || g != 0) return;
 #pragma unroll
-  for (int qj = 0; qj < 2; ++qj)
+  for (int qj = 0; qj < NJ; ++qj)
     if (GRAD && wave + qj * W < D) a.grad_e[eo * D + wave + qj * W] = gsv[qj];
   if (wave == W - 1) {
     a.cost_e[eo] = tc;
@@ -927,16 +943,24 @@ hipError_t wl_launch(KF kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, 
 template <int MAXS, int G, bool SW, bool SP>
 hipError_t wl_pick(const EvalArgs& a, dim3 grid, dim3 block, size_t lds, int waves, bool cand, bool grad,
                    hipStream_t s) {
-  if (waves <= 8) {
-    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, SW, SP>, grid, block, lds, s, a);
-    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, SW, SP>, grid, block, lds, s, a);
-    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, SW, SP>, grid, block, lds, s, a);
-    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G, SW, SP>, grid, block, lds, s, a);
+  if (a.wl.halves == 1 && a.wl.link_waves < a.rb.n_links) {
+    // link passes: at most 8 waves by construction
+    if (waves > 8) return hipErrorInvalidValue;
+    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, SW, SP, true>, grid, block, lds, s, a);
+    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, SW, SP, true>, grid, block, lds, s, a);
+    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, SW, SP, true>, grid, block, lds, s, a);
+    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G, SW, SP, true>, grid, block, lds, s, a);
   }
-  if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G, SW, SP>, grid, block, lds, s, a);
-  if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G, SW, SP>, grid, block, lds, s, a);
-  if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G, SW, SP>, grid, block, lds, s, a);
-  return wl_launch(eval_wl_kernel<MAXS, true, false, 1024, G, SW, SP>, grid, block, lds, s, a);
+  if (waves <= 8) {
+    if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 512, G, SW, SP, false>, grid, block, lds, s, a);
+    if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 512, G, SW, SP, false>, grid, block, lds, s, a);
+    if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 512, G, SW, SP, false>, grid, block, lds, s, a);
+    return wl_launch(eval_wl_kernel<MAXS, true, false, 512, G, SW, SP, false>, grid, block, lds, s, a);
+  }
+  if (cand && grad) return wl_launch(eval_wl_kernel<MAXS, true, true, 1024, G, SW, SP, false>, grid, block, lds, s, a);
+  if (grad) return wl_launch(eval_wl_kernel<MAXS, false, true, 1024, G, SW, SP, false>, grid, block, lds, s, a);
+  if (!cand) return wl_launch(eval_wl_kernel<MAXS, false, false, 1024, G, SW, SP, false>, grid, block, lds, s, a);
+  return wl_launch(eval_wl_kernel<MAXS, true, false, 1024, G, SW, SP, false>, grid, block, lds, s, a);
 }
 
 template <int MAXS, int G>
@@ -948,7 +972,7 @@ hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand
   if (waves * kWave > 1024 || slices < 1 || ((HS == 2 || G > 1) && slices > 1)) return hipErrorInvalidValue;
   // link passes: every link covered, every joint gathered (two per wave at
   // most), self-collision in one pass only
-  if (HS == 1 && (LW < 1 || LW > L || 2 * waves < a.rb.dof || (a.pr.n_self > 0 && LW != L)))
+  if (HS == 1 && (LW < 1 || LW > L || (LW < L ? 2 * waves : waves) < a.rb.dof || (a.pr.n_self > 0 && LW != L)))
     return hipErrorInvalidValue;
   if (G > 1 && (HS != 1 || a.pr.n_self > 0)) return hipErrorInvalidValue;
   if (slices > 1 && (!a.wl.part || !a.wl.count)) return hipErrorInvalidValue;
