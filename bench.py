@@ -80,7 +80,9 @@ def main():
     ap.add_argument("--slices", type=int, choices=[0, 1, 2, 4], default=0,
                     help="with --layout: cuboid slices (0 automatic)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the uneven-batch, inverse-kinematics, large and motion-generation measurements")
+                    help="skip the uneven-batch, inverse-kinematics, large, motion-generation and "
+                         "planning measurements")
+    ap.add_argument("--plan-only", action="store_true", help="only the geometric planning measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding over several "
@@ -90,6 +92,9 @@ def main():
         return profile_copy()
     if args.profile == "large":
         return profile_large(args.launches, args.layout)
+    if args.plan_only:
+        print(json.dumps({"plan": bench_plan(args.warmup)}), flush=True)
+        return
 
     import torch
     from paper_2310_17274_amd import workloads as wl
@@ -223,6 +228,7 @@ def main():
         line["ik"] = bench_ik(args.warmup)
         line["large"] = bench_large(args.warmup)
         line["motion_gen"] = bench_motion_gen(args.warmup)
+        line["plan"] = bench_plan(args.warmup)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(robot, worlds, batch, alpha, iters, args.cpu_seconds)
     print(json.dumps(line), flush=True)
@@ -510,6 +516,112 @@ def bench_motion_gen(warmup):
     out["note"] = ("starts and goal configurations are the clearest of 128 random configurations "
                    "U(-2.5,2.5)^7 per problem (about 6% of random configurations are collision free "
                    "in this world); success = goal within 5 mm / 0.05 rad and collision free")
+    return out
+
+
+def _connected_queries(ctx, robot, nq, seed, res, n_max):
+    """nq start/goal pairs known to be joined by a collision-free path: both
+    ends in the largest connected component of a dense roadmap (the free
+    ones of 200000 uniform configurations, each steered to its 10 nearest),
+    built with the library's own clearance, k-nearest search and steering,
+    and with the direct edge between them blocked."""
+    import torch
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    from paper_2310_17274_amd.binding import mg_knn
+    dev, D = torch.device("cuda:0"), robot.dof
+    rng = np.random.default_rng(seed)
+    Q = rng.uniform(robot.q_lo, robot.q_hi, (200000, D)).astype(np.float32)
+    qd = torch.as_tensor(Q, device=dev).contiguous()
+    z = torch.zeros((1, D), dtype=torch.float32, device=dev)
+    zg = ctx.mg_ee_pose(z).reshape(1, -1).contiguous()
+    _, _, clear = ctx.mg_cost_grad(ctx.batch([Q.shape[0]], [1], [0], K_max=1, m_max=0), z, zg, qd, grad=False)
+    nodes = Q[clear.cpu().numpy() >= 0]
+    k, E = 10, 512
+    idx, _ = mg_knn(torch.as_tensor(nodes, device=dev), torch.as_tensor(nodes, device=dev), k + 1)
+    src = np.repeat(np.arange(len(nodes)), k)
+    dst = idx.cpu().numpy()[:, 1:].reshape(-1)
+    b = ctx.batch([E * (n_max + 1)], [1], [0], K_max=1, m_max=0)
+
+    def steer_ok(a, c):
+        ok = np.zeros(len(a), bool)
+        for e0 in range(0, len(a), E):
+            fa, fb = a[e0:e0 + E], c[e0:e0 + E]
+            n = len(fa)
+            fa = np.concatenate([fa, np.repeat(fa[-1:], E - n, 0)])
+            fb = np.concatenate([fb, np.repeat(fb[-1:], E - n, 0)])
+            _, last, _ = ctx.mg_steer(b, torch.as_tensor(fa, device=dev), torch.as_tensor(fb, device=dev), res, n_max)
+            steps = np.floor(np.abs(fb[:n] - fa[:n]).max(1) / res).astype(int) + 1
+            ok[e0:e0 + n] = last.cpu().numpy()[:n] == steps
+        return ok
+    ok = steer_ok(nodes[src], nodes[dst])
+    m = coo_matrix((np.ones(ok.sum()), (src[ok], dst[ok])), shape=(len(nodes), len(nodes)))
+    _, lab = connected_components(m, directed=False)
+    big = np.flatnonzero(lab == np.bincount(lab).argmax())
+    pairs = []
+    while len(pairs) < nq:
+        a, c = nodes[rng.choice(big, 2, replace=False)]
+        if not steer_ok(a[None], c[None])[0]:
+            pairs.append((a, c))
+    return (np.stack([p[0] for p in pairs]), np.stack([p[1] for p in pairs]),
+            {"free_samples": int(len(nodes)), "largest_component": int(len(big))})
+
+
+def bench_plan(warmup, reps=5):
+    """Geometric planning (Alg.2, steering by Alg.3) on the 7-DOF arm with
+    52 spheres among 40 oriented cuboids, one call per query set, each call
+    seeded anew.  Two query sets: starts and goals that are the clearest of
+    64 random configurations each (some pairs lie in different free-space
+    components: no path exists), and pairs known to be connected with their
+    direct edge blocked.  One query alone, then 16 on one shared roadmap."""
+    import torch
+    from paper_2310_17274_amd import workloads as wl
+    from paper_2310_17274_amd.binding import Context
+    robot, worlds, _, _ = wl.cfg_cost_adjoint()
+    robot, worlds = wl.robot_f32(robot), wl.worlds_f32(worlds)
+    dev = torch.device("cuda:0")
+    ctx = Context(robot)
+    ctx.mg_set_worlds(worlds)
+    D = robot.dof
+    n_edges, n_max, res = 256, 128, 0.05
+    b = ctx.batch([n_edges * (n_max + 1)], [1], [0], K_max=1, m_max=0)
+    z = torch.zeros((1, D), dtype=torch.float32, device=dev)
+    zg = ctx.mg_ee_pose(z).reshape(1, -1).contiguous()
+    cs, cg, info = _connected_queries(ctx, robot, 16, 90, res, n_max)
+    out = {"connected_queries": info}
+    for kind in ("clearest", "connected"):
+        for nq in (1, 16):
+            if kind == "clearest":
+                cand = wl.goal_configs(robot, 80 + nq, 64 * 2 * nq)
+                qc = torch.as_tensor(cand, dtype=torch.float32, device=dev).contiguous()
+                bc = ctx.batch([cand.shape[0]], [1], [0], K_max=1, m_max=0)
+                _, _, clear = ctx.mg_cost_grad(bc, z, zg, qc, grad=False)
+                clear = clear.cpu().numpy().reshape(2 * nq, 64)
+                pick = cand.reshape(2 * nq, 64, D)[np.arange(2 * nq), clear.argmax(1)]
+                starts, goals = pick[0::2], pick[1::2]
+            else:
+                starts, goals = cs[:nq], cg[:nq]
+            calls, solved, wps = [], [], []
+            for rep in range(max(1, warmup) + reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                paths = ctx.mg_plan_batch(b, starts, goals, res, n_max, n_samples=64, k_near=4, max_rounds=40,
+                                          refine_rounds=4, seed=1000 + rep)
+                torch.cuda.synchronize()
+                if rep >= max(1, warmup):
+                    calls.append((time.perf_counter() - t0) * 1e3)
+                    solved += [len(p) > 0 for p in paths]
+                    wps += [len(p) for p in paths if len(p)]
+            out[f"{kind}_Q{nq}"] = {"ms_per_call": float(np.median(calls)), "ms_per_call_pct": pct(calls),
+                                    "success_fraction": float(np.mean(solved)), "calls": len(calls),
+                                    "mean_waypoints": float(np.mean(wps)) if wps else 0.0}
+    out["workload"] = ("7-DOF arm, 52 spheres, 40 oriented cuboids (about 6% of configurations collision "
+                       "free); steering at 0.05 rad, up to 128 steps, 256 edges per launch; 64 collision-free "
+                       "samples (of 32x as many candidates) and 4 neighbours per round, growing on failure; at "
+                       "most 40 rounds, 4 refine rounds once every query is solved")
+    out["note"] = ("host wall clock per call (host roadmap; device clearance, k-nearest search and "
+                   "steering); 'connected' pairs lie in the largest component of a dense roadmap "
+                   "(200000 uniform samples) with their direct edge blocked")
     return out
 
 

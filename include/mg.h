@@ -425,27 +425,53 @@ mg_status mg_motion_gen(mg_ctx *ctx, mg_batch *ik_batch, mg_batch *to_batch, con
 mg_status mg_steer(mg_ctx *ctx, mg_batch *batch, int n_edges, const float *from, const float *to,
                    float res, int n_max, float *reach, int *last, float *dist, void *stream);
 
-/* Geometric planning (Sec. "Parallel Geometric Planner", Alg.2) of one
- * start / goal pair in the batch's world, every steering step a batched
- * mg_steer launch.  The start, goal and (optional) retract configuration are
- * steer-connected both ways; while no path joins start and goal, a round
- * samples configurations uniformly within the joint limits and, after the
- * first round, within the informed region |q - start| + |q - goal| <= c_max,
- * and steers from each sample's k nearest graph nodes toward it (an edge
- * that stops short adds its last valid sample as a node).  A failed round
- * widens c_max by a quarter of the start-goal distance and grows the sample
- * and neighbour counts by a quarter (at most 4x n_samples, 2x k_near).  The shortest path (Dijkstra) is then shortcut:
- * from each waypoint, the farthest later waypoint reachable directly.
+/* The k nearest graph nodes of every query configuration (the geometric
+ * planner's neighbour search, Alg.2), one wavefront per query.  Distances
+ * are squared Euclidean joint-space distances summed joint by joint in fp32,
+ * each product and sum rounded (no fused multiply-add), so that an fp32
+ * brute force reproduces them exactly; ties go to the lower node index.
+ *   nodes DEVICE [n_nodes][dof]; queries DEVICE [n_queries][dof]
+ *   idx DEVICE [n_queries][k] nearest first (-1 beyond n_nodes)
+ *   d2 DEVICE [n_queries][k] their squared distances, or NULL.
+ * 1 <= k <= 32.  Capturable. */
+mg_status mg_knn(int dof, int n_nodes, const float *nodes, int n_queries, const float *queries, int k,
+                 int *idx, float *d2, void *stream);
+
+/* Geometric planning (Sec. "Parallel Geometric Planner", Alg.2) of several
+ * start / goal queries in the batch's world on one shared roadmap, every
+ * steering step a batched mg_steer launch.  The start and goal of each
+ * query, and the (optional) retract configuration with every start and goal,
+ * are steer-connected both ways.  While some query has no path, a round
+ * picks one unsolved query at random and samples configurations uniformly
+ * within the joint limits (after its first failed round, within its informed
+ * region |q - start| + |q - goal| <= c_max); the samples in collision are
+ * dropped (one horizon-1 evaluation launch per batch-full) and each kept one
+ * is steered toward from its k nearest graph nodes (mg_knn on the device; an
+ * edge that stops short adds its last valid sample as a node).  A failed
+ * round widens the query's c_max by a quarter of its start-goal distance and
+ * grows its sample and neighbour counts by a quarter (at most 4x n_samples,
+ * 2x k_near).  Once every query has a path, refine_rounds more rounds each
+ * pick a query at random and sample inside the ellipsoid bounded by its
+ * current path length, so that shorter paths can appear.  Each query's
+ * shortest path (Dijkstra) is then shortcut: from each waypoint, the
+ * farthest later waypoint reachable directly.  At most max_rounds rounds in
+ * all.
  *   batch: one problem of horizon 1 with a multiple of (n_max + 1) seeds
  *   (that multiple is the number of edges per launch)
- *   start, goal HOST [D]; retract HOST [D] or NULL; seed: host sampler
- *   path HOST [max_waypoints][D]; n_waypoints HOST: waypoints written (0:
- *   no path within max_rounds).
+ *   starts, goals HOST [n_queries][D]; retract HOST [D] or NULL; seed: host
+ *   sampler; k_near <= 16
+ *   paths HOST [n_queries][max_waypoints][D]; n_waypoints HOST [n_queries]:
+ *   waypoints written (0: no path within max_rounds).
  * Not capturable (host graph, synchronises after every launch). */
-mg_status mg_plan(mg_ctx *ctx, mg_batch *batch, const float *start, const float *goal,
-                  const float *retract, float res, int n_max, int n_samples, int k_near,
-                  int max_rounds, unsigned seed, int max_waypoints, float *path, int *n_waypoints,
-                  void *stream);
+mg_status mg_plan_batch(mg_ctx *ctx, mg_batch *batch, int n_queries, const float *starts, const float *goals,
+                        const float *retract, float res, int n_max, int n_samples, int k_near, int max_rounds,
+                        int refine_rounds, unsigned seed, int max_waypoints, float *paths, int *n_waypoints,
+                        void *stream);
+
+/* mg_plan_batch of one query with no refine rounds. */
+mg_status mg_plan(mg_ctx *ctx, mg_batch *batch, const float *start, const float *goal, const float *retract,
+                  float res, int n_max, int n_samples, int k_near, int max_rounds, unsigned seed,
+                  int max_waypoints, float *path, int *n_waypoints, void *stream);
 
 /* Measurement hooks.  mg_set_timing(batch, 1) clears the batch's timing
  * record and from then on brackets every direct evaluation-kernel launch

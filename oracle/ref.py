@@ -262,6 +262,28 @@ def solve_timestep(robot, problems, iters1, iters2, m, alpha, vmax, amax, jmax, 
     return [x for x, _ in second], [c for _, c in second], (dt_opt, dt_f)
 
 
+def knn(nodes, queries, k):
+    """Brute-force k nearest nodes of each query (the planner's neighbour
+    search, Alg.2): squared distances summed joint by joint in fp32 with every
+    product and sum rounded, order by (distance, node index).  Returns
+    (idx [m, k], d2 [m, k]), -1 / inf past the node count."""
+    nodes = np.asarray(nodes, dtype=np.float32)
+    queries = np.asarray(queries, dtype=np.float32)
+    n, D = nodes.shape if nodes.size else (0, queries.shape[1])
+    m = queries.shape[0]
+    idx = np.full((m, k), -1, dtype=np.int64)
+    d2o = np.full((m, k), np.inf, dtype=np.float32)
+    for qi in range(m):
+        d2 = np.zeros(n, dtype=np.float32)
+        for j in range(D):
+            u = (nodes[:, j] - queries[qi, j]).astype(np.float32)
+            d2 = (d2 + (u * u).astype(np.float32)).astype(np.float32)
+        order = np.lexsort((np.arange(n), d2))[:k]
+        idx[qi, :order.size] = order
+        d2o[qi, :order.size] = d2[order]
+    return idx, d2o
+
+
 def philox4x64(ctr, key):
     """Philox-4x64-10 of one counter block: four 64-bit words."""
     c = (C.c_uint64 * 4)(*[int(v) & ((1 << 64) - 1) for v in ctr])

@@ -27,7 +27,7 @@ EXPORTS = ("mg_default_params", "mg_create", "mg_destroy", "mg_set_params", "mg_
            "mg_batch_reserve_particles", "mg_particles", "mg_particles_seeded", "mg_philox_normals",
            "mg_set_timing", "mg_eval_time", "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose", "mg_set_self_collision",
            "mg_retime", "mg_solve_timestep", "mg_ik_seeds", "mg_traj_select", "mg_motion_gen",
-           "mg_steer", "mg_plan", "mg_last_error")
+           "mg_steer", "mg_plan", "mg_plan_batch", "mg_knn", "mg_last_error")
 
 
 class RobotDesc(C.Structure):
@@ -101,6 +101,8 @@ def lib():
     L.mg_retime.argtypes = [_vp, _vp, _vp, _vp, _fp, _fp, _fp, _vp, _vp, _vp]
     L.mg_plan.argtypes = [_vp, _vp, _fp, _fp, _fp, C.c_float, C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint,
                           C.c_int, _fp, C.POINTER(C.c_int), _vp]
+    L.mg_plan_batch.argtypes = [_vp, _vp, C.c_int, _fp, _fp, _fp, C.c_float, C.c_int, C.c_int, C.c_int, C.c_int,
+                                C.c_int, C.c_uint, C.c_int, _fp, _ip, _vp]
     L.mg_steer.argtypes = [_vp, _vp, C.c_int, _vp, _vp, C.c_float, C.c_int, _vp, _vp, _vp, _vp]
     L.mg_ik_seeds.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp]
     L.mg_traj_select.argtypes = [_vp, _vp, _vp, _vp, _vp, _fp, _fp, _fp, C.c_float, C.c_float, _vp, _vp, _vp,
@@ -111,6 +113,7 @@ def lib():
     L.mg_solve_timestep.argtypes = [_vp, _vp, _vp, _vp, _vp, C.c_int, C.c_int, C.c_int, C.c_int, _fp,
                                     C.c_int, C.c_int, C.c_int, _fp, _fp, _fp, C.c_float, _vp, _vp, _vp,
                                     _fp, _vp]
+    L.mg_knn.argtypes = [C.c_int, C.c_int, _vp, C.c_int, _vp, C.c_int, _vp, _vp, _vp]
     L.mg_last_error.argtypes = []
     L.mg_last_error.restype = C.c_char_p
     for name in ("mg_create", "mg_set_params", "mg_set_worlds", "mg_batch_create", "mg_cost_grad",
@@ -120,7 +123,7 @@ def lib():
                  "mg_set_timing", "mg_eval_time",
                  "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_ee_pose",
                  "mg_set_self_collision", "mg_retime", "mg_solve_timestep", "mg_ik_seeds",
-                 "mg_traj_select", "mg_motion_gen", "mg_steer", "mg_plan"):
+                 "mg_traj_select", "mg_motion_gen", "mg_steer", "mg_plan", "mg_plan_batch", "mg_knn"):
         getattr(L, name).restype = C.c_int
     _LIB = L
     return L

@@ -268,6 +268,26 @@ class Context:
                                  int(max_waypoints), path, C.byref(n), _stream()))
         return np.frombuffer(path, dtype=np.float32, count=n.value * D).reshape(n.value, D).copy()
 
+    def mg_plan_batch(self, b: Batch, starts, goals, res, n_max, retract=None, n_samples=64, k_near=4,
+                      max_rounds=40, refine_rounds=0, seed=0, max_waypoints=256):
+        """Geometric plans (Alg.2) of several queries (host [n, D] starts and
+        goals) on one shared roadmap.  Returns a list of waypoint arrays
+        [n_i, D] (n_i = 0: none found)."""
+        D = self.robot.dof
+        st = np.ascontiguousarray(starts, dtype=np.float32).reshape(-1, D)
+        gl = np.ascontiguousarray(goals, dtype=np.float32).reshape(-1, D)
+        nq = st.shape[0]
+        assert gl.shape[0] == nq
+        fp = lambda a: a.ctypes.data_as(_lib._fp)
+        paths = np.zeros((nq, max_waypoints, D), dtype=np.float32)
+        nw = np.zeros(nq, dtype=np.int32)
+        ret = np.ascontiguousarray(retract, dtype=np.float32) if retract is not None else None
+        check(_lib.lib().mg_plan_batch(self.handle, b.handle, nq, fp(st), fp(gl),
+                                       fp(ret) if ret is not None else None, float(res), int(n_max),
+                                       int(n_samples), int(k_near), int(max_rounds), int(refine_rounds), int(seed),
+                                       int(max_waypoints), fp(paths), nw.ctypes.data_as(_lib._ip), _stream()))
+        return [paths[i, :nw[i]].copy() for i in range(nq)]
+
     def mg_ik_seeds(self, ik: Batch, to: Batch, q_start, goal, x_ik, w_dist=0.1):
         """Trajectory seeds [to rows, D] on the lines to the ranked IK
         solutions, and ik_ok [P]."""
@@ -383,6 +403,18 @@ def mg_philox_normals(seed, it0, n_iters, n_particles, rows, dof, device="cuda")
     check(_lib.lib().mg_philox_normals(C.c_ulonglong(seed), int(it0), int(n_iters), int(n_particles), int(rows),
                                        int(dof), _ptr(out), _stream()))
     return out
+
+
+def mg_knn(nodes, queries, k):
+    """k nearest nodes [m, k] (int32, nearest first, -1 past the node count)
+    and their squared distances [m, k] of each query, on the device."""
+    n, D = int(nodes.shape[0]), int(nodes.shape[1])
+    m = int(queries.shape[0])
+    idx = torch.empty((m, k), dtype=torch.int32, device=queries.device)
+    d2 = torch.empty((m, k), dtype=torch.float32, device=queries.device)
+    check(_lib.lib().mg_knn(D, n, _ptr(nodes) if n else None, m, _ptr(queries), int(k), _ptr(idx), _ptr(d2),
+                            _stream()))
+    return idx, d2
 
 
 class MgCost(torch.autograd.Function):

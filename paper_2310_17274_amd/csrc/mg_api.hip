@@ -1377,6 +1377,17 @@ mg_status mg_particles_seeded(mg_ctx* c, mg_batch* b, const float* q_start, cons
   return MG_OK;
 }
 
+mg_status mg_knn(int dof, int n_nodes, const float* nodes, int n_queries, const float* queries, int k, int* idx,
+                 float* d2, void* stream) {
+  if (dof < 1 || dof > mg::kMaxDof) return fail(MG_ERR_SHAPE, "dof %d outside 1..%d", dof, mg::kMaxDof);
+  if (k < 1 || k > 32) return fail(MG_ERR_SHAPE, "k = %d outside 1..32", k);
+  if (n_nodes < 0 || n_queries < 0) return fail(MG_ERR_SHAPE, "negative count");
+  if ((n_nodes > 0 && !nodes) || (n_queries > 0 && (!queries || !idx))) return fail(MG_ERR_ARG, "null argument");
+  mg::KnnArgs a{n_nodes, n_queries, dof, k, nodes, queries, idx, d2};
+  HIP_TRY(mg::launch_knn(a, static_cast<hipStream_t>(stream)));
+  return MG_OK;
+}
+
 mg_status mg_philox_normals(unsigned long long seed, int it0, int n_iters, int n_particles, int rows, int dof,
                             float* out, void* stream) {
   if (!out) return fail(MG_ERR_ARG, "null out");
@@ -1709,19 +1720,23 @@ mg_status mg_steer(mg_ctx* c, mg_batch* b, int n_edges, const float* from, const
   return MG_OK;
 }
 
-mg_status mg_plan(mg_ctx* c, mg_batch* b, const float* start, const float* goal, const float* retract,
-                  float res, int n_max, int n_samples, int k_near, int max_rounds, unsigned seed,
-                  int max_waypoints, float* path, int* n_waypoints, void* stream) {
+mg_status mg_plan_batch(mg_ctx* c, mg_batch* b, int n_queries, const float* starts, const float* goals,
+                        const float* retract, float res, int n_max, int n_samples, int k_near, int max_rounds,
+                        int refine_rounds, unsigned seed, int max_waypoints, float* paths, int* n_waypoints,
+                        void* stream) {
   mg_status st = common_checks(c, b);
   if (st != MG_OK) return st;
-  if (!start || !goal || !path || !n_waypoints) return fail(MG_ERR_ARG, "null start, goal, path or n_waypoints");
-  if (n_samples < 1 || k_near < 1 || max_rounds < 0 || max_waypoints < 2)
-    return fail(MG_ERR_ARG, "need n_samples, k_near >= 1, max_rounds >= 0, max_waypoints >= 2");
+  if (n_queries < 1 || !starts || !goals || !paths || !n_waypoints)
+    return fail(MG_ERR_ARG, "need n_queries >= 1, starts, goals, paths and n_waypoints");
+  if (n_samples < 1 || k_near < 1 || 2 * k_near > 32 || max_rounds < 0 || refine_rounds < 0 || max_waypoints < 2)
+    return fail(MG_ERR_ARG, "need n_samples >= 1, 1 <= k_near <= 16, max_rounds, refine_rounds >= 0, max_waypoints >= 2");
   if (b->P != 1 || b->horizon[0] != 1 || b->seeds[0] % (n_max + 1) != 0)
     return fail(MG_ERR_SHAPE, "the batch must hold one problem of horizon 1 with a multiple of n_max + 1 seeds");
   const int D = c->D, cap = b->seeds[0] / (n_max + 1);   // edges per steering launch
+  const int rows = b->rows;                               // samples per clearance launch
+  constexpr int kOversample = 32;                         // candidates drawn per kept sample
   hipStream_t s = static_cast<hipStream_t>(stream);
-  *n_waypoints = 0;
+  for (int qy = 0; qy < n_queries; ++qy) n_waypoints[qy] = 0;
   std::vector<std::vector<float>> node;                  // graph nodes (host)
   std::vector<std::vector<std::pair<int, float>>> adj;   // undirected weighted edges
   auto add_node = [&](const float* q) {
@@ -1734,11 +1749,19 @@ mg_status mg_plan(mg_ctx* c, mg_batch* b, const float* start, const float* goal,
     for (int j = 0; j < D; ++j) d2 += ((double)a[j] - bq[j]) * ((double)a[j] - bq[j]);
     return (float)std::sqrt(d2);
   };
-  float *d_from = nullptr, *d_to = nullptr, *d_reach = nullptr;
-  int* d_last = nullptr;
+  // device buffers: steering edges, samples and their neighbours, the nodes
+  const int p_cap = 4 * n_samples, k_cap = 2 * k_near;
+  float *d_from = nullptr, *d_to = nullptr, *d_reach = nullptr, *d_smp = nullptr, *d_nodes = nullptr;
+  int *d_last = nullptr, *d_idx = nullptr;
+  size_t node_cap = 0;
+  auto free_all = [&]() {
+    dev_free(d_from); dev_free(d_to); dev_free(d_reach); dev_free(d_last); dev_free(d_smp); dev_free(d_idx);
+    dev_free(d_nodes);
+  };
   if ((st = dev_alloc(&d_from, (size_t)cap * D)) != MG_OK || (st = dev_alloc(&d_to, (size_t)cap * D)) != MG_OK ||
-      (st = dev_alloc(&d_reach, (size_t)cap * D)) != MG_OK || (st = dev_alloc(&d_last, (size_t)cap)) != MG_OK) {
-    dev_free(d_from); dev_free(d_to); dev_free(d_reach); dev_free(d_last);
+      (st = dev_alloc(&d_reach, (size_t)cap * D)) != MG_OK || (st = dev_alloc(&d_last, (size_t)cap)) != MG_OK ||
+      (st = dev_alloc(&d_smp, (size_t)p_cap * D)) != MG_OK || (st = dev_alloc(&d_idx, (size_t)p_cap * k_cap)) != MG_OK) {
+    free_all();
     return st;
   }
   std::vector<float> h_from((size_t)cap * D), h_to((size_t)cap * D), h_reach((size_t)cap * D);
@@ -1782,107 +1805,236 @@ mg_status mg_plan(mg_ctx* c, mg_batch* b, const float* start, const float* goal,
     }
     return MG_OK;
   };
-  // shortest path from node 0 (start) to node 1 (goal), Dijkstra on a heap
-  auto shortest = [&](std::vector<int>& out) {
+  // clearance of candidate samples: one horizon-1 evaluation launch per
+  // batch-full (world clearance >= 0 keeps a sample; limits hold by
+  // construction)
+  std::vector<float> h_rows((size_t)rows * D), h_mc(rows);
+  auto clear_samples = [&](std::vector<std::vector<float>>& smp) -> mg_status {
+    std::vector<std::vector<float>> keep;
+    for (size_t s0 = 0; s0 < smp.size(); s0 += rows) {
+      const int n = (int)std::min(smp.size() - s0, (size_t)rows);
+      for (int r = 0; r < rows; ++r) {
+        const auto& q = smp[s0 + std::min(r, n - 1)];
+        std::copy(q.begin(), q.end(), &h_rows[(size_t)r * D]);
+      }
+      HIP_TRY(hipMemcpyAsync(b->g_cur, h_rows.data(), h_rows.size() * 4, hipMemcpyHostToDevice, s));
+      mg_status r = enqueue_eval(c, b, c->d_zero, c->d_goal_id, b->g_cur, nullptr, 1, nullptr, false, nullptr,
+                                 nullptr, s);
+      if (r != MG_OK) return r;
+      HIP_TRY(hipMemcpyAsync(h_mc.data(), b->mc_e, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      for (int i = 0; i < n; ++i)
+        if (h_mc[i] >= 0.0f) keep.push_back(smp[s0 + i]);
+    }
+    smp.swap(keep);
+    return MG_OK;
+  };
+  // the k nearest nodes of every sample, on the device
+  std::vector<int> h_idx((size_t)p_cap * k_cap);
+  auto nearest = [&](const std::vector<std::vector<float>>& smp, int kk) -> mg_status {
+    if (node.size() > node_cap) {
+      dev_free(d_nodes);
+      node_cap = std::max<size_t>(2 * node.size(), 1024);
+      mg_status r = dev_alloc(&d_nodes, node_cap * D);
+      if (r != MG_OK) return r;
+    }
+    std::vector<float> hn(node.size() * D), hs(smp.size() * D);
+    for (size_t i = 0; i < node.size(); ++i) std::copy(node[i].begin(), node[i].end(), &hn[i * D]);
+    for (size_t i = 0; i < smp.size(); ++i) std::copy(smp[i].begin(), smp[i].end(), &hs[i * D]);
+    HIP_TRY(hipMemcpyAsync(d_nodes, hn.data(), hn.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_smp, hs.data(), hs.size() * 4, hipMemcpyHostToDevice, s));
+    mg::KnnArgs ka{(int)node.size(), (int)smp.size(), D, kk, d_nodes, d_smp, d_idx, nullptr};
+    HIP_TRY(mg::launch_knn(ka, s));
+    HIP_TRY(hipMemcpyAsync(h_idx.data(), d_idx, smp.size() * kk * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MG_OK;
+  };
+  // shortest path between two nodes, Dijkstra on a heap
+  auto shortest = [&](int src, int dst, std::vector<int>& out) {
     const size_t n = node.size();
     std::vector<float> dd(n, 3.0e38f);
     std::vector<int> prev(n, -1);
     std::priority_queue<std::pair<float, int>, std::vector<std::pair<float, int>>, std::greater<>> pq;
-    dd[0] = 0.0f;
-    pq.push({0.0f, 0});
+    dd[src] = 0.0f;
+    pq.push({0.0f, src});
     while (!pq.empty()) {
       const auto [du, u] = pq.top();
       pq.pop();
       if (du > dd[u]) continue;
-      if (u == 1) break;
+      if (u == dst) break;
       for (auto& [v, w] : adj[u])
         if (du + w < dd[v]) { dd[v] = du + w; prev[v] = u; pq.push({dd[v], v}); }
     }
     out.clear();
-    if (dd[1] >= 3.0e38f) return 3.0e38f;
-    for (int v = 1; v >= 0; v = prev[v]) out.push_back(v);
+    if (dd[dst] >= 3.0e38f) return 3.0e38f;
+    for (int v = dst; v >= 0; v = prev[v]) out.push_back(v);
     std::reverse(out.begin(), out.end());
-    return dd[1];
+    return dd[dst];
   };
   auto run = [&]() -> mg_status {
-    add_node(start);
-    add_node(goal);
-    std::vector<std::pair<int, int>> e0 = {{0, 1}, {1, 0}};
+    // nodes: start and goal of every query, then the retract configuration
+    std::vector<int> sn(n_queries), gn(n_queries);
+    for (int qy = 0; qy < n_queries; ++qy) {
+      sn[qy] = add_node(starts + (size_t)qy * D);
+      gn[qy] = add_node(goals + (size_t)qy * D);
+    }
+    std::vector<std::pair<int, int>> e0;
+    for (int qy = 0; qy < n_queries; ++qy) e0.insert(e0.end(), {{sn[qy], gn[qy]}, {gn[qy], sn[qy]}});
     if (retract) {
       const int r = add_node(retract);
-      e0.insert(e0.end(), {{0, r}, {r, 0}, {1, r}, {r, 1}});
+      for (int qy = 0; qy < n_queries; ++qy)
+        e0.insert(e0.end(), {{sn[qy], r}, {r, sn[qy]}, {gn[qy], r}, {r, gn[qy]}});
     }
     mg_status r = steer_connect(e0, nullptr, nullptr);
     if (r != MG_OK) return r;
-    std::vector<int> route;
-    float len = shortest(route);
-    // informed sampling: sum of distances to start and goal within c_max
-    const float c_min = dist(start, goal);
-    float c_max = 3.0e38f;
-    int k_n = k_near, p_n = n_samples;
+    std::vector<std::vector<int>> route(n_queries);
+    std::vector<float> len(n_queries), c_min(n_queries), c_max(n_queries, 3.0e38f);
+    std::vector<int> k_n(n_queries, k_near), p_n(n_queries, n_samples);
+    int n_solved = 0;
+    for (int qy = 0; qy < n_queries; ++qy) {
+      len[qy] = shortest(sn[qy], gn[qy], route[qy]);
+      c_min[qy] = dist(starts + (size_t)qy * D, goals + (size_t)qy * D);
+      n_solved += !route[qy].empty();
+    }
     std::mt19937 rng(seed);
-    for (int round = 0; route.empty() && round < max_rounds; ++round) {
+    int refine_left = refine_rounds;
+    for (int round = 0; round < max_rounds && (n_solved < n_queries || refine_left > 0); ++round) {
+      // a query at random among the unsolved ones (Alg.2), or, once all are
+      // solved, among all of them to refine its path in its informed set
+      const bool refine = n_solved == n_queries;
+      if (refine) --refine_left;
+      std::vector<int> pool;
+      for (int qy = 0; qy < n_queries; ++qy)
+        if (refine || route[qy].empty()) pool.push_back(qy);
+      const int qy = pool[std::uniform_int_distribution<int>(0, (int)pool.size() - 1)(rng)];
+      const float cm = refine ? len[qy] : c_max[qy];
+      const float* st_q = starts + (size_t)qy * D;
+      const float* gl_q = goals + (size_t)qy * D;
+      // candidates: uniform within the joint limits, or uniform in the
+      // informed ellipsoid |q - start| + |q - goal| <= cm (a unit-ball
+      // sample stretched to the semi-axes cm/2 along the start-goal line
+      // and sqrt(cm^2 - c_min^2)/2 across it, turned onto that line by a
+      // Householder reflection), outside the limits dropped
       std::vector<std::vector<float>> smp;
-      for (int tries = 0; (int)smp.size() < p_n && tries < 100 * p_n; ++tries) {
-        std::vector<float> q(D);
-        for (int j = 0; j < D; ++j)
-          q[j] = c->q_lo[j] + (c->q_hi[j] - c->q_lo[j]) * std::uniform_real_distribution<float>(0.0f, 1.0f)(rng);
-        if (dist(q.data(), start) + dist(q.data(), goal) <= c_max) smp.push_back(q);
+      const int n_cand = std::min(rows, kOversample * p_n[qy]);
+      std::uniform_real_distribution<float> U(0.0f, 1.0f);
+      std::normal_distribution<float> N01(0.0f, 1.0f);
+      const bool ell = cm < 3.0e38f && c_min[qy] > 0.0f;
+      std::vector<double> axis(D), hv(D);
+      double hvv = 0.0;
+      if (ell) {
+        for (int j = 0; j < D; ++j) axis[j] = ((double)gl_q[j] - st_q[j]) / c_min[qy];
+        for (int j = 0; j < D; ++j) hv[j] = (j == 0 ? 1.0 : 0.0) - axis[j];
+        for (int j = 0; j < D; ++j) hvv += hv[j] * hv[j];
       }
-      // each sample steered from its k_n nearest nodes
+      const double r1 = 0.5 * cm, r2 = ell ? 0.5 * std::sqrt(std::max(0.0, (double)cm * cm -
+                                                                       (double)c_min[qy] * c_min[qy])) : 0.0;
+      for (int i = 0; i < n_cand; ++i) {
+        std::vector<float> q(D);
+        if (!ell) {
+          for (int j = 0; j < D; ++j) q[j] = c->q_lo[j] + (c->q_hi[j] - c->q_lo[j]) * U(rng);
+        } else {
+          std::vector<double> x(D);
+          double n2 = 0.0;
+          for (int j = 0; j < D; ++j) { x[j] = N01(rng); n2 += x[j] * x[j]; }
+          const double rad = std::pow((double)U(rng), 1.0 / D) / std::sqrt(std::max(n2, 1e-300));
+          for (int j = 0; j < D; ++j) x[j] *= rad * (j == 0 ? r1 : r2);
+          double xv = 0.0;
+          for (int j = 0; j < D; ++j) xv += x[j] * hv[j];
+          bool in = true;
+          for (int j = 0; j < D; ++j) {
+            const double y = x[j] - (hvv > 1e-24 ? 2.0 * xv / hvv * hv[j] : 0.0);
+            q[j] = (float)(0.5 * ((double)st_q[j] + gl_q[j]) + y);
+            in = in && q[j] >= c->q_lo[j] && q[j] <= c->q_hi[j];
+          }
+          if (!in) continue;
+        }
+        smp.push_back(q);
+      }
+      // collision-free candidates only (one evaluation launch), the first
+      // p_n of them kept; each is steered toward from its k nearest nodes
+      // (found on the device)
+      if ((r = clear_samples(smp)) != MG_OK) return r;
+      if ((int)smp.size() > p_n[qy]) smp.resize(p_n[qy]);
       std::vector<std::pair<int, int>> edges;
       std::vector<std::vector<float>> tgt;
-      for (auto& q : smp) {
-        std::vector<std::pair<float, int>> near;
-        for (size_t i = 0; i < node.size(); ++i) near.push_back({dist(node[i].data(), q.data()), (int)i});
-        const int kk = std::min<int>(k_n, (int)near.size());
-        std::partial_sort(near.begin(), near.begin() + kk, near.end());
-        for (int i = 0; i < kk; ++i) { edges.push_back({near[i].second, -1}); tgt.push_back(q); }
+      const int kk = std::min<int>(k_n[qy], (int)node.size());
+      if (!smp.empty()) {
+        if ((r = nearest(smp, kk)) != MG_OK) return r;
+        for (size_t i = 0; i < smp.size(); ++i)
+          for (int u = 0; u < kk; ++u) {
+            edges.push_back({h_idx[i * kk + u], -1});
+            tgt.push_back(smp[i]);
+          }
       }
       std::vector<int> reached(edges.size(), -1);
       if ((r = steer_connect(edges, &tgt, &reached)) != MG_OK) return r;
-      // samples reached from several nodes become one node (joined edges)
-      for (size_t k = 0; k < edges.size(); ++k)
-        for (size_t k2 = k + 1; k2 < edges.size() && reached[k] >= 0; ++k2)
-          if (reached[k2] >= 0 && tgt[k2] == tgt[k] && reached[k2] != reached[k]) {
-            adj[reached[k]].push_back({reached[k2], 0.0f});
-            adj[reached[k2]].push_back({reached[k], 0.0f});
-          }
-      len = shortest(route);
-      // a failed round widens the region and grows the counts by a quarter
-      // (capped at 4x the samples and 2x the neighbours asked for)
-      if (route.empty()) {
-        if (c_max >= 3.0e38f) c_max = 2.0f * c_min;
-        c_max += 0.25f * c_min;
-        p_n = std::min(p_n + std::max(1, p_n / 4), 4 * n_samples);
-        k_n = std::min(k_n + std::max(1, k_n / 4), 2 * k_near);
+      // a sample reached from several nodes becomes one node: its copies
+      // (edges i*kk .. i*kk + kk - 1) are joined at zero length
+      for (size_t i = 0; i < smp.size(); ++i) {
+        int first = -1;
+        for (int u = 0; u < kk; ++u) {
+          const int v = reached[i * kk + u];
+          if (v < 0) continue;
+          if (first < 0) { first = v; continue; }
+          if (v == first) continue;
+          adj[first].push_back({v, 0.0f});
+          adj[v].push_back({first, 0.0f});
+        }
+      }
+      // the roadmap is shared: every query's shortest path may improve
+      n_solved = 0;
+      for (int u = 0; u < n_queries; ++u) {
+        std::vector<int> rt;
+        const float l2 = shortest(sn[u], gn[u], rt);
+        if (!rt.empty() && (route[u].empty() || l2 < len[u])) { route[u] = rt; len[u] = l2; }
+        n_solved += !route[u].empty();
+      }
+      // a failed round widens the picked query's region and grows its
+      // counts by a quarter (capped at 4x the samples, 2x the neighbours)
+      if (!refine && route[qy].empty()) {
+        if (c_max[qy] >= 3.0e38f) c_max[qy] = 2.0f * c_min[qy];
+        c_max[qy] += 0.25f * c_min[qy];
+        p_n[qy] = std::min(p_n[qy] + std::max(1, p_n[qy] / 4), p_cap);
+        k_n[qy] = std::min(k_n[qy] + std::max(1, k_n[qy] / 4), k_cap);
       }
     }
-    if (route.empty()) return MG_OK;
-    // shortcut: from each waypoint, the farthest later one reachable directly
-    std::vector<int> sc = {route[0]};
-    for (size_t i = 0; i + 1 < route.size();) {
-      std::vector<std::pair<int, int>> edges;
-      for (size_t j = route.size() - 1; j > i + 1; --j) edges.push_back({route[i], route[j]});
-      size_t next = i + 1;
-      if (!edges.empty()) {
-        std::vector<int> reached(edges.size(), -1);
-        if ((r = steer_connect(edges, nullptr, &reached)) != MG_OK) return r;
-        for (size_t k = 0; k < edges.size(); ++k)
-          if (reached[k] == edges[k].second) { next = route.size() - 1 - k; break; }
+    for (int qy = 0; qy < n_queries; ++qy) {
+      if (route[qy].empty()) continue;
+      // shortcut: from each waypoint, the farthest later one reachable directly
+      const auto& rt = route[qy];
+      std::vector<int> sc = {rt[0]};
+      for (size_t i = 0; i + 1 < rt.size();) {
+        std::vector<std::pair<int, int>> edges;
+        for (size_t j = rt.size() - 1; j > i + 1; --j) edges.push_back({rt[i], rt[j]});
+        size_t next = i + 1;
+        if (!edges.empty()) {
+          std::vector<int> reached(edges.size(), -1);
+          if ((r = steer_connect(edges, nullptr, &reached)) != MG_OK) return r;
+          for (size_t k = 0; k < edges.size(); ++k)
+            if (reached[k] == edges[k].second) { next = rt.size() - 1 - k; break; }
+        }
+        sc.push_back(rt[next]);
+        i = next;
       }
-      sc.push_back(route[next]);
-      i = next;
+      if ((int)sc.size() > max_waypoints)
+        return fail(MG_ERR_SHAPE, "query %d: the path has %d waypoints (max %d)", qy, (int)sc.size(), max_waypoints);
+      float* out = paths + (size_t)qy * max_waypoints * D;
+      for (size_t i = 0; i < sc.size(); ++i) std::copy(node[sc[i]].begin(), node[sc[i]].end(), out + i * D);
+      n_waypoints[qy] = (int)sc.size();
     }
-    (void)len;
-    if ((int)sc.size() > max_waypoints) return fail(MG_ERR_SHAPE, "the path has %d waypoints (max %d)", (int)sc.size(), max_waypoints);
-    for (size_t i = 0; i < sc.size(); ++i) std::copy(node[sc[i]].begin(), node[sc[i]].end(), path + i * D);
-    *n_waypoints = (int)sc.size();
     return MG_OK;
   };
   st = run();
-  dev_free(d_from); dev_free(d_to); dev_free(d_reach); dev_free(d_last);
+  free_all();
   return st;
+}
+
+mg_status mg_plan(mg_ctx* c, mg_batch* b, const float* start, const float* goal, const float* retract,
+                  float res, int n_max, int n_samples, int k_near, int max_rounds, unsigned seed,
+                  int max_waypoints, float* path, int* n_waypoints, void* stream) {
+  return mg_plan_batch(c, b, 1, start, goal, retract, res, n_max, n_samples, k_near, max_rounds, 0, seed,
+                       max_waypoints, path, n_waypoints, stream);
 }
 
 }  // extern "C"

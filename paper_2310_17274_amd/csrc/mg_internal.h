@@ -347,6 +347,15 @@ struct SteerArgs {
   float* dist;             // [n_edges] or null
 };
 
+// k nearest nodes of every query (the planner's neighbour search).
+struct KnnArgs {
+  int n_nodes, n_queries, dof, k;
+  const float* nodes;      // [n_nodes][D]
+  const float* queries;    // [n_queries][D]
+  int* idx;                // [n_queries][k] (-1 past the node count)
+  float* d2;               // [n_queries][k] squared distances, or null
+};
+
 // Trajectory selection among the seeds of every problem (one thread each).
 struct TrajSelectArgs {
   const Problem* prob;
@@ -406,6 +415,7 @@ hipError_t launch_ik_seeds(const IkSeedArgs& a, hipStream_t s);
 hipError_t launch_traj_select(const TrajSelectArgs& a, hipStream_t s);
 hipError_t launch_steer_points(const SteerArgs& a, hipStream_t s);
 hipError_t launch_steer_scan(const SteerArgs& a, hipStream_t s);
+hipError_t launch_knn(const KnnArgs& a, hipStream_t s);
 hipError_t launch_final(const FinalArgs& a, hipStream_t s);
 hipError_t launch_ee_pose(const EePoseArgs& a, hipStream_t s);
 hipError_t launch_boxes(const float* pose, const float* dims, int n, Box* out, hipStream_t s);

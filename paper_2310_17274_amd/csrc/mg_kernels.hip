@@ -14,6 +14,8 @@
 // ik_seed_kernel   IK seeds ranked per problem, linear trajectory seeds.
 // traj_select_kernel  per-problem choice among trajectory seeds.
 // steer_points_kernel, steer_scan_kernel  parallel steering of graph edges.
+#include <climits>
+
 #include "mg_device.h"
 #include "mg_eval.h"
 
@@ -543,6 +545,83 @@ __global__ __launch_bounds__(kBlock) void steer_scan_kernel(const SteerArgs a) {
 hipError_t launch_steer_points(const SteerArgs& a, hipStream_t s) {
   const long n = (long)a.n_edges * (a.n_max + 1);
   steer_points_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------------------------
+// The k nearest graph nodes of every query (the geometric planner's
+// neighbour search, Alg.2).  Squared Euclidean distances summed joint by
+// joint in fp32 without fused multiply-add (each product and sum rounded, so
+// a host brute force in fp32 reproduces them bit for bit); ties go to the
+// lower node index.  One wave per query: each lane keeps the KMAX nearest of
+// its strided share of the nodes in a sorted register list, then k
+// wave-wide minimum rounds take the overall nearest in order, the owning
+// lane popping its head each round.
+template <int KMAX>
+__global__ __launch_bounds__(kWave) void knn_kernel(const KnnArgs a) {
+#pragma clang fp contract(off)
+  const int qi = blockIdx.x, lane = threadIdx.x, D = a.dof;
+  float q[kMaxDof];
+#pragma unroll
+  for (int j = 0; j < kMaxDof; ++j) q[j] = j < D ? a.queries[(size_t)qi * D + j] : 0.0f;
+  float bd[KMAX];
+  int bi[KMAX];
+#pragma unroll
+  for (int r = 0; r < KMAX; ++r) { bd[r] = INFINITY; bi[r] = INT_MAX; }
+  for (int i = lane; i < a.n_nodes; i += kWave) {
+    const float* nd = a.nodes + (size_t)i * D;
+    float d2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kMaxDof; ++j)
+      if (j < D) {
+        const float u = nd[j] - q[j];
+        d2 = d2 + u * u;
+      }
+    if (d2 < bd[KMAX - 1]) {   // (a lane's indices increase: ties keep the earlier)
+      float cd = d2;
+      int ci = i;
+#pragma unroll
+      for (int r = 0; r < KMAX; ++r) {
+        const bool sw = cd < bd[r];
+        const float td = bd[r];
+        const int ti = bi[r];
+        bd[r] = sw ? cd : td;
+        bi[r] = sw ? ci : ti;
+        cd = sw ? td : cd;
+        ci = sw ? ti : ci;
+      }
+    }
+  }
+  for (int r = 0; r < a.k; ++r) {
+    float md = bd[0];
+    int mi = bi[0];
+#pragma unroll
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+      const float od = __shfl_xor(md, o, kWave);
+      const int oi = __shfl_xor(mi, o, kWave);
+      const bool take = od < md || (od == md && oi < mi);
+      md = take ? od : md;
+      mi = take ? oi : mi;
+    }
+    if (lane == 0) {
+      a.idx[(size_t)qi * a.k + r] = mi == INT_MAX ? -1 : mi;
+      if (a.d2) a.d2[(size_t)qi * a.k + r] = md;
+    }
+    if (bi[0] == mi && mi != INT_MAX) {   // the owner pops its head
+#pragma unroll
+      for (int u = 0; u + 1 < KMAX; ++u) { bd[u] = bd[u + 1]; bi[u] = bi[u + 1]; }
+      bd[KMAX - 1] = INFINITY;
+      bi[KMAX - 1] = INT_MAX;
+    }
+  }
+}
+
+hipError_t launch_knn(const KnnArgs& a, hipStream_t s) {
+  if (a.n_queries < 1) return hipSuccess;
+  if (a.k < 1 || a.k > 32 || a.dof < 1 || a.dof > kMaxDof || a.n_nodes < 0) return hipErrorInvalidValue;
+  if (a.k <= 8) knn_kernel<8><<<a.n_queries, kWave, 0, s>>>(a);
+  else if (a.k <= 16) knn_kernel<16><<<a.n_queries, kWave, 0, s>>>(a);
+  else knn_kernel<32><<<a.n_queries, kWave, 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -1241,3 +1241,25 @@ def test_philox_normal_box_muller(oracle_lib):
     # rounds, particles and elements draw different numbers
     a = ref.philox_normals(11, 2, 2, 3, 7)
     assert len(np.unique(a)) == a.size
+
+
+# ---------------------------------------------------------------------------
+# The planner's neighbour search: the fp32 brute force against scipy's k-d
+# tree (an independent route) on data without near ties, and the tie rule.
+
+def test_knn_brute_force_against_kdtree(oracle_lib):
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(71)
+    nodes = rng.uniform(-2.5, 2.5, (300, 7)).astype(np.float32)
+    queries = rng.uniform(-2.5, 2.5, (20, 7)).astype(np.float32)
+    idx, d2 = ref.knn(nodes, queries, 9)
+    dk, ik = cKDTree(nodes.astype(np.float64)).query(queries.astype(np.float64), k=9)
+    np.testing.assert_array_equal(idx, ik)
+    np.testing.assert_allclose(d2, dk ** 2, rtol=1e-5)
+    # more neighbours than nodes: the rest are -1
+    i2, _ = ref.knn(nodes[:3], queries[:2], 5)
+    assert list(i2[0, 3:]) == [-1, -1]
+    # ties go to the lower index
+    tie = np.array([[1, 0], [0, 1], [-1, 0], [0, -1], [2, 0]], dtype=np.float32)
+    it, _ = ref.knn(tie, np.zeros((1, 2), np.float32), 5)
+    assert list(it[0]) == [0, 1, 2, 3, 4]

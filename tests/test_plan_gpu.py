@@ -1,0 +1,120 @@
+"""The geometric planner's device parts (Alg.2) through the C ABI: the k
+nearest graph nodes against the oracle's fp32 brute force (bit-exact indices
+and squared distances), and batched planning on one shared roadmap whose
+paths the FP64 reference re-steers segment by segment (Alg.3)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_2310_17274_amd import workloads as wl
+from paper_2310_17274_amd.binding import Context, default_params, mg_knn
+from tests.test_steer_gpu import F32, _ctx, _path_valid
+
+pytestmark = pytest.mark.gpu
+
+
+def _knn_case(rng, n, m, D, dup=0):
+    nodes = rng.uniform(-3.0, 3.0, (n, D)).astype(np.float32)
+    if dup:   # repeated nodes: equal distances, ties go to the lower index
+        nodes[rng.choice(n, dup, replace=False)] = nodes[rng.choice(n, dup, replace=False)]
+    queries = rng.uniform(-3.0, 3.0, (m, D)).astype(np.float32)
+    if n:
+        queries[: min(8, m)] = nodes[rng.choice(n, min(8, m))]   # queries on nodes: distance 0
+    return nodes, queries
+
+
+@pytest.mark.parametrize("D,n,m,k", [(7, 3000, 160, 1), (7, 3000, 160, 5), (7, 4099, 96, 16),
+                                     (7, 2500, 64, 32), (3, 777, 50, 9), (12, 1000, 40, 8), (16, 130, 33, 32)])
+def test_knn_bit_exact_against_the_oracle(D, n, m, k):
+    rng = np.random.default_rng(100 + D + k)
+    nodes, queries = _knn_case(rng, n, m, D, dup=n // 10)
+    idx, d2 = mg_knn(torch.as_tensor(nodes, device="cuda"), torch.as_tensor(queries, device="cuda"), k)
+    torch.cuda.synchronize()
+    ri, rd = ref.knn(nodes, queries, k)
+    np.testing.assert_array_equal(idx.cpu().numpy(), ri)
+    np.testing.assert_array_equal(d2.cpu().numpy(), rd)
+
+
+def test_knn_fewer_nodes_than_k_and_no_nodes():
+    rng = np.random.default_rng(7)
+    nodes, queries = _knn_case(rng, 5, 20, 7)
+    idx, d2 = mg_knn(torch.as_tensor(nodes, device="cuda"), torch.as_tensor(queries, device="cuda"), 12)
+    ri, rd = ref.knn(nodes, queries, 12)
+    np.testing.assert_array_equal(idx.cpu().numpy(), ri)
+    np.testing.assert_array_equal(d2.cpu().numpy(), rd)
+    assert (idx.cpu().numpy()[:, 5:] == -1).all()
+    empty = torch.empty((0, 7), device="cuda")
+    idx, d2 = mg_knn(empty, torch.as_tensor(queries, device="cuda"), 4)
+    assert (idx.cpu().numpy() == -1).all() and np.isinf(d2.cpu().numpy()).all()
+
+
+def _blocked_pairs(r, boxes, robot, rng, n, res):
+    """Collision-free start/goal pairs (clearance >= 0.01) whose direct edge
+    is blocked before its middle."""
+    goal_pose = np.array([[0, 0, 0, 1, 0, 0, 0.0]])
+    out = []
+    for _ in range(4000):
+        a, b = F32(rng.uniform(-2.5, 2.5, 7)), F32(rng.uniform(-2.5, 2.5, 7))
+        if not all(r.traj_cost(boxes, q, goal_pose, q[None], grad=False)[2] >= 0.01 for q in (a, b)):
+            continue
+        if ref.steer(r, boxes, a, b, res, robot.q_lo, robot.q_hi)[0] < 0.5 * (np.abs(b - a).max() / res):
+            out.append((a, b))
+            if len(out) == n:
+                break
+    assert len(out) == n
+    return out
+
+
+@pytest.mark.parametrize("refine", [0, 6])
+def test_plan_batch_on_a_shared_roadmap(refine):
+    """Four blocked queries in one call: every found path starts and ends at
+    its query and steers through in the reference; at least three of four
+    are solved."""
+    robot = wl.robot_f32(wl.make_arm(seed=0, n_spheres=52))
+    worlds = wl.worlds_f32(wl.make_worlds(2, [10]))
+    boxes = worlds.world(0)
+    r = ref.Ref(robot)
+    res = 0.05
+    pairs = _blocked_pairs(r, boxes, robot, np.random.default_rng(72), 4, res)
+    ctx, b = _ctx(robot, worlds, 128, 128)
+    starts = np.stack([p[0] for p in pairs])
+    goals = np.stack([p[1] for p in pairs])
+    paths = ctx.mg_plan_batch(b, starts, goals, res, 128, n_samples=64, k_near=4, max_rounds=24,
+                              refine_rounds=refine, seed=5)
+    solved = 0
+    for (a, g), p in zip(pairs, paths):
+        if len(p) == 0:
+            continue
+        solved += 1
+        assert len(p) >= 3
+        np.testing.assert_array_equal(p[0], a.astype(np.float32))
+        np.testing.assert_array_equal(p[-1], g.astype(np.float32))
+        assert _path_valid(r, boxes, p.astype(np.float64), res, robot)
+    assert solved >= 3, solved
+
+
+def test_plan_batch_matches_single_query_plan():
+    """One query with no refine rounds: mg_plan and mg_plan_batch give the
+    same path (mg_plan is that call)."""
+    robot = wl.robot_f32(wl.make_arm(seed=0, n_spheres=52))
+    worlds = wl.worlds_f32(wl.make_worlds(2, [10]))
+    r = ref.Ref(robot)
+    (a, g), = _blocked_pairs(r, worlds.world(0), robot, np.random.default_rng(73), 1, 0.05)
+    ctx, b = _ctx(robot, worlds, 64, 128)
+    p1 = ctx.mg_plan(b, a, g, 0.05, 128, n_samples=64, k_near=4, max_rounds=12, seed=9)
+    p2, = ctx.mg_plan_batch(b, a[None], g[None], 0.05, 128, n_samples=64, k_near=4, max_rounds=12, seed=9)
+    np.testing.assert_array_equal(p1, p2)
+
+
+def test_plan_batch_rejects_bad_arguments():
+    robot = wl.robot_f32(wl.make_arm(seed=0, n_spheres=20))
+    worlds = wl.worlds_f32(wl.make_worlds(2, [10]))
+    ctx, b = _ctx(robot, worlds, 16, 64)
+    z = np.zeros((1, 7), np.float32)
+    with pytest.raises(RuntimeError):
+        ctx.mg_plan_batch(b, z, z, 0.05, 64, k_near=17)
+    with pytest.raises(RuntimeError):
+        ctx.mg_plan_batch(b, z, z, 0.05, 63)   # seeds not a multiple of n_max + 1
