@@ -304,8 +304,10 @@ mg_status mg_particles(mg_ctx *ctx, mg_batch *batch, const float *q_start, const
 
 /* The particle stage with its noise drawn on the device: as mg_particles,
  * with round it's draws eps[k][row][j] the counter-based standard normals of
- * mg_philox_normals(seed, it, ...), generated into the batch's reserved
- * buffer before each round (no host draws, no upload).  Capturable. */
+ * mg_philox_normals(seed, it, ...) (it = 0 .. n_iters - 1 <= 65535).  The
+ * evaluation kernel makes each particle's draws where it forms the particle
+ * and the update kernel makes them again (one Philox block per four
+ * elements): no draw is stored, read back or uploaded.  Capturable. */
 mg_status mg_particles_seeded(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
                               float *mean, float *var, int n_particles, int n_iters,
                               unsigned long long seed, float beta, float k_mu, float k_sigma,

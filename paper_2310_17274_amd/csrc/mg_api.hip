@@ -151,7 +151,6 @@ struct mg_batch {
   // wave-per-link chunk records for pm_K particles per row
   float* p_cost = nullptr;
   int p_cap = 0;
-  float* p_eps = nullptr;   // one round's device-drawn noise [p_cap][rows][D] (mg_particles_seeded)
   int pm_K = 0;
   mg::WlChunk* d_chunk_pm[2] = {};
   int chunks_pm[2] = {};
@@ -960,7 +959,7 @@ void mg_batch_destroy(mg_batch* b) {
   dev_free(b->cost_e); dev_free(b->gd_e); dev_free(b->mc_e); dev_free(b->grad_e); dev_free(b->pe_e);
   dev_free(b->c_cur); dev_free(b->g_cur); dev_free(b->dir); dev_free(b->best_c); dev_free(b->best_x);
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
-  dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost); dev_free(b->p_eps); dev_free(b->sel_dt);
+  dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost); dev_free(b->sel_dt);
   dev_free(b->sel_jerk);
   dev_free(b->wl_part); dev_free(b->wl_count); dev_free(b->sp_h);
   delete b;
@@ -1263,10 +1262,8 @@ mg_status mg_batch_reserve_particles(mg_batch* b, int n_particles) {
   mg_status st;
   if (n_particles > b->p_cap) {
     dev_free(b->p_cost);
-    dev_free(b->p_eps);
     b->p_cap = 0;
     if ((st = dev_alloc(&b->p_cost, (size_t)n_particles * b->rows)) != MG_OK) return st;
-    if ((st = dev_alloc(&b->p_eps, (size_t)n_particles * b->rows * b->ctx->D)) != MG_OK) return st;
     b->p_cap = n_particles;
   }
   // wave-per-link records for this particle count
@@ -1277,17 +1274,22 @@ mg_status mg_batch_reserve_particles(mg_batch* b, int n_particles) {
   return MG_OK;
 }
 
-mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* mean,
-                       float* var, int n_particles, int n_iters, const float* eps, float beta,
-                       float k_mu, float k_sigma, float* costs_out, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The particle stage on draws from memory (eps) or, with eps null, on
+// draws each kernel makes itself (round it's at counter round it0 + it).
+mg_status particle_rounds(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* mean, float* var,
+                          int n_particles, int n_iters, const float* eps, unsigned long long seed, float beta,
+                          float k_mu, float k_sigma, float* costs_out, hipStream_t s) {
   mg_status st = common_checks(c, b);
   if (st != MG_OK) return st;
   if (n_particles < 1 || n_particles > b->p_cap)
     return fail(MG_ERR_STATE, "n_particles = %d exceeds the %d reserved (mg_batch_reserve_particles)",
                 n_particles, b->p_cap);
   if (n_iters < 0) return fail(MG_ERR_ARG, "n_iters must be >= 0");
-  if (!q_start || !goal || !mean || !var || (n_iters > 0 && !eps))
-    return fail(MG_ERR_ARG, "null q_start, goal, mean, var or eps");
+  if (!q_start || !goal || !mean || !var) return fail(MG_ERR_ARG, "null q_start, goal, mean or var");
   if (!(k_mu >= 0.0f && k_mu <= 1.0f) || !(k_sigma >= 0.0f && k_sigma <= 1.0f))
     return fail(MG_ERR_ARG, "k_mu and k_sigma must lie in [0, 1]");
   // wave per link with one slot group (64 particles of one row per
@@ -1311,14 +1313,15 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
     return fail(MG_ERR_UNSUPPORTED,
                 "self-collision or the speed metric in the particle stage needs the wave-per-link layout for %d particles "
                 "(the last mg_batch_reserve_particles count, at least 2)", n_particles);
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t draws = (size_t)n_particles * b->rows * c->D;
   const int hi = pick_slices(b, (long)b->rows * n_particles);
   for (int it = 0; it < n_iters; ++it) {
-    const float* e = eps + (size_t)it * draws;
+    const float* e = eps ? eps + (size_t)it * draws : nullptr;
     mg::EvalArgs a = eval_args(c, b, hi, q_start, goal, mean, e, n_particles, nullptr);
     a.var = var;
-    a.d_stride = (size_t)b->rows * c->D;
+    if (e) a.d_stride = (size_t)b->rows * c->D;
+    else a.pm_seed = seed;
+    a.pm_it = it;
     a.cost_e = b->p_cost;
     a.mc_e = nullptr;
     a.gd_e = nullptr;
@@ -1347,6 +1350,8 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
     pa.q_hi = c->d_q_hi;
     pa.cost_e = b->p_cost;
     pa.eps = e;
+    pa.seed = seed;
+    pa.it = it;
     pa.mean = mean;
     pa.var = var;
     pa.costs_out = costs_out ? costs_out + (size_t)it * b->n_seeds * n_particles : nullptr;
@@ -1355,26 +1360,24 @@ mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float
   return MG_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+mg_status mg_particles(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* mean,
+                       float* var, int n_particles, int n_iters, const float* eps, float beta,
+                       float k_mu, float k_sigma, float* costs_out, void* stream) {
+  if (n_iters > 0 && !eps) return fail(MG_ERR_ARG, "null eps");
+  return particle_rounds(c, b, q_start, goal, mean, var, n_particles, n_iters, eps, 0, beta, k_mu, k_sigma,
+                         costs_out, static_cast<hipStream_t>(stream));
+}
+
 mg_status mg_particles_seeded(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* mean,
                               float* var, int n_particles, int n_iters, unsigned long long seed, float beta,
                               float k_mu, float k_sigma, float* costs_out, void* stream) {
-  mg_status st = common_checks(c, b);
-  if (st != MG_OK) return st;
-  if (n_particles < 1 || n_particles > b->p_cap || !b->p_eps)
-    return fail(MG_ERR_STATE, "n_particles = %d exceeds the %d reserved (mg_batch_reserve_particles)",
-                n_particles, b->p_cap);
-  if (n_iters < 0) return fail(MG_ERR_ARG, "n_iters must be >= 0");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const long long n = (long long)b->rows * c->D;
-  for (int it = 0; it < n_iters; ++it) {
-    // this round's draws, then the round on them
-    HIP_TRY(mg::launch_philox_normals(seed, it, 1, n_particles, n, b->p_eps, s));
-    if ((st = mg_particles(c, b, q_start, goal, mean, var, n_particles, 1, b->p_eps, beta, k_mu, k_sigma,
-                           costs_out ? costs_out + (size_t)it * b->n_seeds * n_particles : nullptr, stream)) !=
-        MG_OK)
-      return st;
-  }
-  return MG_OK;
+  if (n_iters > 65535) return fail(MG_ERR_ARG, "n_iters must be <= 65535");
+  return particle_rounds(c, b, q_start, goal, mean, var, n_particles, n_iters, nullptr, seed, beta, k_mu, k_sigma,
+                         costs_out, static_cast<hipStream_t>(stream));
 }
 
 mg_status mg_knn(int dof, int n_nodes, const float* nodes, int n_queries, const float* queries, int k, int* idx,

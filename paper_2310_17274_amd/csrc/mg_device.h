@@ -260,5 +260,22 @@ __device__ __forceinline__ float box_muller(uint64_t w) {
   return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
 }
 
+// The four standard normal draws of particle k, round it, elements 4q ..
+// 4q + 3 (one Philox block at counter {q, k, it, 0}, key {seed, 0}).
+__device__ __forceinline__ void philox_draws4(uint64_t seed, int k, int it, uint64_t q, float* out4) {
+  uint64_t w[4];
+  philox4x64(q, (uint64_t)(unsigned)k, (uint64_t)(unsigned)it, 0, seed, 0, w);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) out4[i] = box_muller(w[i]);
+}
+
+// The draw of particle k, round it, element e alone (word e mod 4).
+__device__ __forceinline__ float philox_draw(uint64_t seed, int k, int it, uint64_t e) {
+  uint64_t w[4];
+  philox4x64(e >> 2, (uint64_t)(unsigned)k, (uint64_t)(unsigned)it, 0, seed, 0, w);
+  const int i = (int)(e & 3);
+  return box_muller(i == 0 ? w[0] : i == 1 ? w[1] : i == 2 ? w[2] : w[3]);
+}
+
 }  // namespace
 }  // namespace mg

@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
   const int t = rl % pb.T;          // waypoint t+1 of its seed
   const int row = pb.row0 + rl;
   const float alpha = CAND ? a.alpha[k < kMaxK ? k : 0] : 0.0f;
-  const float* dk = CAND ? a.d + (size_t)k * a.d_stride : nullptr;
+  const float* dk = CAND && a.d ? a.d + (size_t)k * a.d_stride : nullptr;
 
   // candidate value of joint j at waypoint row r: clip(x + alpha d) for a
   // line-search candidate, clip(x + sqrt(var) d_k) for a particle
@@ -294,7 +294,8 @@ __global__ __launch_bounds__(kBlock) void eval_kernel(const EvalArgs a) {
     const size_t e = (size_t)r * D + j;
     float v = a.x[e];
     if (CAND) {
-      v = a.var ? fmaf(sqrtf(a.var[e]), dk[e], v) : fmaf(alpha, dk[e], v);
+      if (a.var) v = fmaf(sqrtf(a.var[e]), dk ? dk[e] : philox_draw(a.pm_seed, k, a.pm_it, e), v);
+      else v = fmaf(alpha, dk[e], v);
       v = fminf(fmaxf(v, a.rb.q_lo[j]), a.rb.q_hi[j]);
     }
     return v;

@@ -368,7 +368,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     // scalars: rows of x (and d, or var), limits, start, goals, tool
     // transforms, and in particle mode each lane's draws over the rows
     const int nxd = CAND ? 2 * n_st : n_st;
-    const int n_eps = pm ? min(r_hi - r_lo + 1, pm_rows) * E * D : 0;
+    const int n_eps = pm && a.d ? min(r_hi - r_lo + 1, pm_rows) * E * D : 0;
     const int nf = nxd + 3 * D + n_ee * 19 + n_eps;
     const float* dsrc = pm ? a.var : a.d;
     auto fsrc = [&](int i, float*& dst) -> const float* {
@@ -418,6 +418,27 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
       if (i1 < nf) *d1 = v1;
       if (i0 < n4) s_chain[i0] = u0;
       if (i1 < n4) s_chain[i1] = u1;
+    }
+    if (pm && !a.d) {
+      // each lane's draws over the staged rows, made here: one Philox block
+      // gives elements 4q .. 4q + 3 of the flattened [rows][D] range
+      const int nr = min(r_hi - r_lo + 1, pm_rows);
+      const long long e_lo = (long long)r_lo * D, e_hi = e_lo + (long long)nr * D;
+      const long long q_lo = e_lo >> 2, nq = ((e_hi + 3) >> 2) - q_lo;
+      for (long long i = tid; i < nq * E; i += nthreads) {
+        const int ee = (int)(i / nq);
+        const long long q = q_lo + (i - (long long)ee * nq);
+        const int ke = min(e_first + ee, n_e - 1) % K;
+        float w4[4];
+        philox_draws4(a.pm_seed, ke, a.pm_it, (uint64_t)q, w4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long long e = 4 * q + u;
+          if (e < e_lo || e >= e_hi) continue;
+          const int rr = (int)((e - e_lo) / D), j = (int)(e - e_lo - (long long)rr * D);
+          s_eps[(rr * E + ee) * D + j] = w4[u];
+        }
+      }
     }
   }
   __syncthreads();

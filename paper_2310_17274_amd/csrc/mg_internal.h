@@ -194,11 +194,18 @@ struct EvalArgs {
   const float* x;          // [rows][D]
   const float* d;          // [rows][D] direction (candidate mode) or null
   // particle mode (var != null): candidate k is clip(x + sqrt(var) d_k) with
-  // d_k = d + k * d_stride standard normal draws; alpha is not used
+  // d_k = d + k * d_stride standard normal draws; alpha is not used.  With
+  // d null the kernel makes the draws itself: particle k's draw of element
+  // e = row * D + j is the Philox-4x64-10 normal at counter {e / 4, k,
+  // pm_it, 0}, key {pm_seed, 0}, word e mod 4
   const float* var;        // [rows][D] per-element variance or null
-  size_t d_stride;
+  union {
+    size_t d_stride;               // d != null
+    unsigned long long pm_seed;    // d == null
+  };
   float alpha[kMaxK];
   int K;
+  int pm_it;
   float* cost_e;           // [K][rows]
   float* gd_e;             // [K][rows] (candidate mode)
   float* mc_e;             // [K][rows]
@@ -294,7 +301,10 @@ struct ParticleArgs {
   const float* q_lo;
   const float* q_hi;
   const float* cost_e;     // [N][rows] per-row particle costs
-  const float* eps;        // [N][rows][D] this round's draws
+  const float* eps;        // [N][rows][D] this round's draws, or null: drawn
+                           // here as the evaluation drew them (seed, it)
+  unsigned long long seed;
+  int it;
   float* mean;             // [rows][D] in/out
   float* var;              // [rows][D] in/out
   float* costs_out;        // [n_seeds][N] or null

@@ -195,6 +195,49 @@ __global__ __launch_bounds__(kBlock) void particle_update_kernel(const ParticleA
   __syncthreads();
   const int n = si.T * D;
   const size_t base = (size_t)si.row0 * D, stride = (size_t)a.rows * D;
+  if (!a.eps) {
+    // draws re-made as the evaluation made them, a Philox block (four
+    // consecutive elements) per thread and particle
+    const size_t q0 = base >> 2, nq = ((base + n + 3) >> 2) - q0;
+    for (size_t qi = threadIdx.x; qi < nq; qi += kBlock) {
+      const size_t e0 = 4 * (q0 + qi);
+      float mu[4], v[4], sd[4], lo[4], hi[4], m1[4], m2[4];
+      bool in[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        in[u] = e0 + u >= base && e0 + u < base + n;
+        const size_t e = in[u] ? e0 + u : base;
+        const int j = (int)(e % D);
+        mu[u] = a.mean[e];
+        v[u] = a.var[e];
+        sd[u] = sqrtf(v[u]);
+        lo[u] = a.q_lo[j];
+        hi[u] = a.q_hi[j];
+        m1[u] = 0.0f;
+        m2[u] = 0.0f;
+      }
+      for (int i = 0; i < N; ++i) {
+        float ep[4];
+        philox_draws4(a.seed, i, a.it, q0 + qi, ep);
+        const float w = s_w[i];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float th = fminf(fmaxf(fmaf(sd[u], ep[u], mu[u]), lo[u]), hi[u]);
+          const float dv = th - mu[u];
+          m1[u] = fmaf(w, th, m1[u]);
+          m2[u] = fmaf(w, dv * dv, m2[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (!in[u]) continue;
+        const size_t e = e0 + u;
+        a.var[e] = (1.0f - a.k_sigma) * v[u] + a.k_sigma * (m2[u] * inv_z);
+        a.mean[e] = (1.0f - a.k_mu) * mu[u] + a.k_mu * (m1[u] * inv_z);
+      }
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < n; e += kBlock) {
     const float mu = a.mean[base + e], v = a.var[base + e], sd = sqrtf(v);
     const int j = e % D;

@@ -654,11 +654,12 @@ def test_device_noise_matches_the_oracle():
         np.testing.assert_allclose(got, want, rtol=0, atol=4e-6)
 
 
-@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2")])
+@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param(None, id="default"),
+                                    pytest.param((3, 0), id="groups2")])
 def test_seeded_particle_stage(layout):
-    """The particle stage with device-drawn noise equals the stage fed the
-    same draws from memory (bit for bit), and agrees with the oracle's stage
-    on the oracle's draws."""
+    """The particle stage with its draws made inside the evaluation and
+    update kernels equals the stage fed the same draws from memory (bit for
+    bit), and agrees with the oracle's stage on the oracle's draws."""
     from paper_2310_17274_amd.binding import mg_philox_normals
     case = make_case("plain", layout=layout)
     S, T, D, N, seed = 4, 32, 7, 64, 1234
