@@ -73,10 +73,10 @@ def main():
                          "two-arm workload, 'copy' copies 256 MiB five times (HBM byte-counter "
                          "calibration)")
     ap.add_argument("--launches", type=int, default=10)
-    ap.add_argument("--layout", type=int, choices=[0, 1, 2, 3], default=None,
+    ap.add_argument("--layout", type=int, choices=[0, 1, 2, 3, 4], default=None,
                     help="force the evaluation layout (0 lane per link, 1 wave per link, "
-                         "2 two waves per link, 3 two slot groups per wave) instead of the "
-                         "autotuner's choice")
+                         "2 two waves per link, 3 two slot groups per wave, 4 four slot groups "
+                         "per wave) instead of the autotuner's choice")
     ap.add_argument("--slices", type=int, choices=[0, 1, 2, 4], default=0,
                     help="with --layout: cuboid slices (0 automatic)")
     ap.add_argument("--no-extra", action="store_true",
@@ -128,7 +128,8 @@ def main():
         layout = layout_name(ctx.mg_autotune(b, q_start, goal, x0, dvec, alpha))
     else:
         b.mg_batch_set_layout(args.layout, args.slices)
-        layout = ({2: "two_waves_per_link", 3: "two_slot_groups"}[args.layout] if args.layout >= 2 else
+        layout = ({2: "two_waves_per_link", 3: "two_slot_groups", 4: "four_slot_groups"}[args.layout]
+                  if args.layout >= 2 else
                   ["lane_per_link", "wave_per_link"][args.layout] + "/" +
                   (str(args.slices) if args.slices else "auto"))
 
@@ -250,12 +251,14 @@ def kernel_digest():
 
 def layout_name(tuned):
     """The autotuner's choice as 'lane_per_link/<slices>',
-    'wave_per_link/<workgroups per 64 evaluations>', 'two_waves_per_link'
-    or 'two_slot_groups'."""
+    'wave_per_link/<workgroups per 64 evaluations>', 'two_waves_per_link',
+    'two_slot_groups' or 'four_slot_groups'."""
     if tuned == -8:
         return "two_waves_per_link"
     if tuned == -16:
         return "two_slot_groups"
+    if tuned == -32:
+        return "four_slot_groups"
     return f"lane_per_link/{tuned}" if tuned > 0 else f"wave_per_link/{-tuned}"
 
 

@@ -255,9 +255,12 @@ mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *s
  * terms: shorter waves, no separate joint wave.  Layout 3 keeps one wave
  * per link but holds 32 evaluations per workgroup, each half of a wave
  * testing half of the link's sphere slots (twice the workgroups for the
- * same batch; no self-collision, at least 4 slots per link).
- * mg_batch_set_layout fixes a layout (-1: library default, 0, 1, 2, 3) and
- * a slice count (0: automatic; 1, 2 or 4; layouts 2 and 3 take 0 or 1).
+ * same batch; no self-collision, at least 4 slots per link); layout 4 holds
+ * 16 evaluations per workgroup, each quarter of a wave testing a quarter of
+ * the slots (four times the workgroups; at least 8 slots per link).  In
+ * both, two lane groups split each evaluation's kinematic chain in halves.
+ * mg_batch_set_layout fixes a layout (-1: library default, 0 .. 4) and a
+ * slice count (0: automatic; 1, 2 or 4; layouts 2, 3 and 4 take 0 or 1).
  * Host-only; affects later calls.
  *
  * Autotuner for a batch's launch shape: times the line-search evaluation
@@ -266,7 +269,7 @@ mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *s
  * fixes the fastest for every later call on this batch.  *slices_out (may
  * be NULL) receives the slice count for the lane-per-link layout, minus
  * the workgroups per 64 evaluations for the wave-per-link layout, -8 for
- * two waves per link, or -16 for two slot groups per wave.
+ * two waves per link, -16 for two slot groups per wave or -32 for four.
  * Overwrites the batch's evaluation workspaces; not capturable.  With
  * swept collision the lane-per-link layout takes one slice. */
 mg_status mg_batch_set_layout(mg_batch *batch, int layout, int slices);
@@ -291,7 +294,7 @@ mg_status mg_autotune(mg_ctx *ctx, mg_batch *batch, const float *q_start, const 
  *   eps       DEVICE [n_iters][n_particles][rows][D] standard normal draws
  *   costs_out DEVICE [n_iters][seeds][n_particles] particle costs, or NULL
  * The costing launch is wave per link (one slot group per wave, unless
- * mg_batch_set_layout chose two) when n_particles is the last reserved
+ * mg_batch_set_layout chose two or four) when n_particles is the last reserved
  * count and the layout fits the robot, lane per link when
  * mg_batch_set_layout chose it (self-collision and the speed metric keep
  * wave per link); the autotuner's choice for line-search candidates is not

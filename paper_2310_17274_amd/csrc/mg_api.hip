@@ -138,12 +138,12 @@ struct mg_batch {
   int layout = -1;    // evaluation layout: -1 automatic, 0 lane per link, 1 wave per link
   bool layout_set = false;   // the layout came from mg_batch_set_layout (not the autotuner)
   // wave-per-link chunks of 64 evaluations, per candidate count K
-  // ([K][0]: 64 evaluations per chunk, [K][1]: 32 for two slot groups)
-  mg::WlChunk* d_chunk_wl[mg::kMaxK + 1][2] = {};
-  int chunks_wl[mg::kMaxK + 1][2] = {};
+  // ([K][gi]: 64 >> gi evaluations per chunk, for 1 << gi slot groups)
+  mg::WlChunk* d_chunk_wl[mg::kMaxK + 1][3] = {};
+  int chunks_wl[mg::kMaxK + 1][3] = {};
   int wl_slices = 0;        // wave-per-link cuboid slices over workgroups (0: automatic)
   int wl_halves = 0;        // wave-per-link waves per link: 1, 2 (0: automatic)
-  int wl_groups = 1;        // wave-per-link slot groups per wave: 1, 2
+  int wl_groups = 1;        // wave-per-link slot groups per wave: 1, 2, 4
   int wl_slices_max = 1;    // largest the scratch below holds
   float* wl_part = nullptr; // [chunks][slices][3 + D][64]
   int* wl_count = nullptr;  // [chunks], zero between launches
@@ -152,8 +152,8 @@ struct mg_batch {
   float* p_cost = nullptr;
   int p_cap = 0;
   int pm_K = 0;
-  mg::WlChunk* d_chunk_pm[2] = {};
-  int chunks_pm[2] = {};
+  mg::WlChunk* d_chunk_pm[3] = {};
+  int chunks_pm[3] = {};
   // speed metric with gradients: per (candidate, row, sphere) terms of the
   // speed's gradient [K_max][rows][M] (allocated while the metric is on)
   float4* sp_h = nullptr;
@@ -213,7 +213,7 @@ mg_status build_lanes(mg_ctx* c) {
   std::vector<int4> wl_info(c->L);
   std::vector<int> wl_chain((size_t)c->L * mg::kMaxDof, 0);
   std::vector<float4> chain_rec((size_t)c->L * mg::kMaxDof * 4, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
-  std::vector<float4> wl_ball((size_t)c->L * 3, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
+  std::vector<float4> wl_ball((size_t)c->L * mg::kWlBalls, make_float4(0.0f, 0.0f, 0.0f, 0.0f));
   // ball around slots [s0, s1) of link l: centre of their bounding box,
   // radius to the farthest sphere surface (slightly widened)
   auto ball_of = [&](int l, int s0, int s1) {
@@ -254,10 +254,14 @@ mg_status build_lanes(mg_ctx* c) {
       if (c->ee_link[e] == l) ee = e;
     wl_info[l] = make_int4((int)ch.size(), count[l], ee, 0);
     c->max_depth = std::max(c->max_depth, (int)ch.size());
-    const int half = maxs / 2;
-    wl_ball[3 * l + 0] = ball_of(l, 0, count[l]);
-    wl_ball[3 * l + 1] = ball_of(l, 0, std::min(count[l], half));
-    wl_ball[3 * l + 2] = ball_of(l, half, count[l]);
+    // balls of all the link's slots, of each half and of each quarter
+    const int half = maxs / 2, quarter = maxs / 4;
+    float4* bl = &wl_ball[(size_t)mg::kWlBalls * l];
+    bl[0] = ball_of(l, 0, count[l]);
+    bl[1] = ball_of(l, 0, std::min(count[l], half));
+    bl[2] = ball_of(l, half, count[l]);
+    for (int q = 0; q < 4; ++q)
+      bl[3 + q] = ball_of(l, std::min(count[l], q * quarter), q == 3 ? count[l] : std::min(count[l], (q + 1) * quarter));
   }
   mg_status st;
   if ((st = dev_upload(&c->d_lane_info, info)) != MG_OK) return st;
@@ -332,12 +336,14 @@ bool wl_halves_possible(const mg_ctx* c) {
 bool wl_possible(const mg_ctx* c) { return wl_possible(c, c->n_self > 0); }
 // terms only the wave-per-link layout evaluates: self-collision, the speed metric
 bool needs_wl(const mg_ctx* c) { return c->n_self > 0 || c->params.speed; }
-// two slot groups per wave (32 evaluations per workgroup): no
-// self-collision, at least four sphere slots per link
-bool wl_groups_possible(const mg_ctx* c) {
-  return c->L + 1 <= 16 && c->n_self == 0 && c->maxs >= 4 &&
-         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, false, 1, c->maxs, mg::kWave / 2) <= c->lds_max;
+// G slot groups per wave (64 / G evaluations per workgroup): no
+// self-collision, at least two sphere slots per group
+bool wl_groups_possible(const mg_ctx* c, int G = 2) {
+  return c->L + 1 <= 16 && c->n_self == 0 && c->maxs >= 2 * G &&
+         mg::wl_lds_bytes(c->L, c->D, c->max_depth, c->M, false, 1, c->maxs, mg::kWave / G) <= c->lds_max;
 }
+// index of a slot-group count in the chunk-record tables
+int groups_index(int G) { return G == 4 ? 2 : G == 2 ? 1 : 0; }
 
 // Layout of an evaluation launch with K candidates.
 bool use_wl(const mg_batch* b, int K) {
@@ -461,11 +467,11 @@ mg_status wl_records(mg_batch* b, int K, int E, mg::WlChunk** dptr, int* count) 
 mg_status wl_chunks_upload(mg_batch* b) {
   mg_status st;
   for (int K = 1; K <= b->K_max; ++K)
-    for (int gi = 0; gi < 2; ++gi)
+    for (int gi = 0; gi < 3; ++gi)
       if ((st = wl_records(b, K, mg::kWave >> gi, &b->d_chunk_wl[K][gi], &b->chunks_wl[K][gi])) != MG_OK)
         return st;
   if (b->pm_K > 0)
-    for (int gi = 0; gi < 2; ++gi)
+    for (int gi = 0; gi < 3; ++gi)
       if ((st = wl_records(b, b->pm_K, mg::kWave >> gi, &b->d_chunk_pm[gi], &b->chunks_pm[gi])) != MG_OK)
         return st;
   return MG_OK;
@@ -516,16 +522,16 @@ hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool gr
     a.wl.count = b->wl_count;
     // two slot groups per wave when chosen; else two waves per link where
     // they fit (shorter waves), unless forced
-    const int groups = b->wl_groups == 2 && wl_groups_possible(b->ctx) ? 2 : 1;
-    const int halves = groups == 2 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(b->ctx) ? 2 : 1));
+    const int groups = b->wl_groups > 1 && wl_groups_possible(b->ctx, b->wl_groups) ? b->wl_groups : 1;
+    const int halves = groups > 1 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(b->ctx) ? 2 : 1));
     if (halves == 2 && !wl_halves_possible(b->ctx)) return hipErrorInvalidValue;
     a.wl.halves = halves;
     a.wl.groups = groups;
-    a.wl.chunk = b->d_chunk_wl[a.K][groups - 1];
+    a.wl.chunk = b->d_chunk_wl[a.K][groups_index(groups)];
     wl_single(b, a.K, a.wl);
     // (the speed's gradient terms need every cuboid of a sphere in one workgroup)
-    const int wls = (halves == 2 || groups == 2 || !slices_ok || (a.sp_h && grad)) ? 1 : wl_slices(b, a.K);
-    return mg::launch_eval_wl(a, b->chunks_wl[a.K][groups - 1], wls, cand, grad, s);
+    const int wls = (halves == 2 || groups > 1 || !slices_ok || (a.sp_h && grad)) ? 1 : wl_slices(b, a.K);
+    return mg::launch_eval_wl(a, b->chunks_wl[a.K][groups_index(groups)], wls, cand, grad, s);
   }
   return mg::launch_eval(a, b->chunks[hi], cand, grad, s);
 }
@@ -1130,6 +1136,7 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
   std::vector<Opt> opts;
   if (!needs_wl(c))
     for (int hi = 0; hi < kNumSlices; ++hi) opts.push_back({0, hi, 0, 0, 1});
+  if (wl_groups_possible(c, 4)) opts.push_back({1, -1, 1, 1, 4});
   if (wl_groups_possible(c)) opts.push_back({1, -1, 1, 1, 2});
   if (wl_halves_possible(c)) opts.push_back({1, -1, 2, 1, 1});
   if (wl_possible(c))
@@ -1163,10 +1170,12 @@ mg_status mg_autotune(mg_ctx* c, mg_batch* b, const float* q_start, const float*
   b->wl_slices = opts[best].wls;
   b->wl_groups = opts[best].groups;
   // lane per link: the slice count; wave per link: minus the workgroups per
-  // 64 evaluations, -8 for two waves per link, -16 for two slot groups
+  // 64 evaluations, -8 for two waves per link, -16 for two slot groups, -32
+  // for four
   if (slices_out)
     *slices_out = opts[best].layout == 0 ? kSlices[opts[best].hi]
-                  : opts[best].groups == 2 ? -16 : (opts[best].halves == 2 ? -8 : -opts[best].wls);
+                  : opts[best].groups == 4 ? -32 : opts[best].groups == 2 ? -16
+                  : (opts[best].halves == 2 ? -8 : -opts[best].wls);
   return MG_OK;
 }
 
@@ -1223,18 +1232,20 @@ mg_status mg_ee_pose(mg_ctx* c, int rows, const float* q, float* pose, void* str
 
 mg_status mg_batch_set_layout(mg_batch* b, int layout, int slices) {
   if (!b) return fail(MG_ERR_ARG, "null batch");
-  if (layout < -1 || layout > 3) return fail(MG_ERR_ARG, "layout must be -1, 0, 1, 2 or 3");
+  if (layout < -1 || layout > 4) return fail(MG_ERR_ARG, "layout must be -1, 0, 1, 2, 3 or 4");
   if (layout >= 1 && !wl_possible(b->ctx))
     return fail(MG_ERR_UNSUPPORTED, "the wave-per-link layout needs at most 15 links");
   if (layout == 2 && !wl_halves_possible(b->ctx))
     return fail(MG_ERR_UNSUPPORTED, "two waves per link need at most 8 links");
   if (layout == 3 && !wl_groups_possible(b->ctx))
     return fail(MG_ERR_UNSUPPORTED, "two slot groups per wave need no self-collision and 4 or more slots per link");
-  b->wl_halves = layout == 2 ? 2 : (layout == 1 || layout == 3 ? 1 : 0);
-  b->wl_groups = layout == 3 ? 2 : 1;
+  if (layout == 4 && !wl_groups_possible(b->ctx, 4))
+    return fail(MG_ERR_UNSUPPORTED, "four slot groups per wave need no self-collision and 8 or more slots per link");
+  b->wl_halves = layout == 2 ? 2 : (layout == 1 || layout >= 3 ? 1 : 0);
+  b->wl_groups = layout == 4 ? 4 : layout == 3 ? 2 : 1;
   b->layout_set = layout >= 0;
   if (layout >= 2) {
-    if (slices > 1) return fail(MG_ERR_ARG, "layouts 2 and 3 take one workgroup per chunk of evaluations");
+    if (slices > 1) return fail(MG_ERR_ARG, "layouts 2, 3 and 4 take one workgroup per chunk of evaluations");
     b->layout = 1;
     b->slices = -1;
     b->wl_slices = 1;
@@ -1268,7 +1279,7 @@ mg_status mg_batch_reserve_particles(mg_batch* b, int n_particles) {
   }
   // wave-per-link records for this particle count
   b->pm_K = n_particles;
-  for (int gi = 0; gi < 2; ++gi)
+  for (int gi = 0; gi < 3; ++gi)
     if ((st = wl_records(b, n_particles, mg::kWave >> gi, &b->d_chunk_pm[gi], &b->chunks_pm[gi])) != MG_OK)
       return st;
   return MG_OK;
@@ -1300,8 +1311,9 @@ mg_status particle_rounds(mg_ctx* c, mg_batch* b, const float* q_start, const fl
   // measured 139 ms with one slot group, 244 ms with two, 350 ms lane per
   // link)
   const bool lane_set = b->layout_set && b->layout == 0;
-  const int groups = b->layout_set && b->wl_groups == 2 && wl_groups_possible(c) ? 2 : 1;
-  const int halves = groups == 2 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(c) ? 2 : 1));
+  const int groups =
+      b->layout_set && b->wl_groups > 1 && wl_groups_possible(c, b->wl_groups) ? b->wl_groups : 1;
+  const int halves = groups > 1 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(c) ? 2 : 1));
   const int E = mg::kWave / groups;
   // rows a chunk of E particles touches, with the stencils' four on either side
   const int pm_rows = (E - 1) / n_particles + 10;
@@ -1329,10 +1341,10 @@ mg_status particle_rounds(mg_ctx* c, mg_batch* b, const float* q_start, const fl
     if (wl) {
       a.wl.halves = halves;
       a.wl.groups = groups;
-      a.wl.chunk = b->d_chunk_pm[groups - 1];
+      a.wl.chunk = b->d_chunk_pm[groups_index(groups)];
       wl_single(b, n_particles, a.wl);
       a.wl.pm_rows = pm_rows;
-      HIP_TRY(mg::launch_eval_wl(a, b->chunks_pm[groups - 1], 1, true, false, s));
+      HIP_TRY(mg::launch_eval_wl(a, b->chunks_pm[groups_index(groups)], 1, true, false, s));
     } else {
       HIP_TRY(mg::launch_eval(a, b->chunks[hi], true, false, s));
     }

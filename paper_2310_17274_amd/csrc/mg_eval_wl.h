@@ -247,11 +247,23 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
   }
 }
 
-// The value of lane i +- 32 (the other slot group's lane for the same
-// evaluation when G = 2).
-__device__ __forceinline__ float other32(float v, int lane) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
-  return __int_as_float(lane < 32 ? (int)r[1] : (int)r[0]);
+// The value of the lane that holds the other half of this lane's chain: lane
+// i +- 32 with two slot groups, i +- 16 with four (groups g and g ^ 1 split
+// one evaluation's chain).  Every lane takes part in the swap.
+template <int G>
+__device__ __forceinline__ float chain_partner(float v, int lane) {
+  if constexpr (G == 4) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+    return __int_as_float((lane & 16) ? (int)r[0] : (int)r[1]);
+  } else {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+    return __int_as_float(lane < 32 ? (int)r[1] : (int)r[0]);
+  }
+}
+// This lane's slot-group ball among a link's kWlBalls.
+template <int G>
+__device__ __forceinline__ int group_ball(int g) {
+  return G == 4 ? 3 + g : G == 2 ? 1 + g : 0;
 }
 
 // Sum / minimum over the G slot groups of a wave (lanes e, e + E, ...).
@@ -271,8 +283,8 @@ __device__ __forceinline__ float groups_min(float v) {
 // NT: launch bound, 512 threads for robots of up to 7 links (register
 // budget of two waves per SIMD), else 1024.  G: slot groups per wave; a
 // workgroup holds E = 64 / G evaluations and lane g * E + e tests group g
-// of the link's sphere slots for evaluation e (G = 2: twice the workgroups
-// for the same batch, the chain run twice).
+// of the link's sphere slots for evaluation e (G = 2, 4: G times the
+// workgroups for the same batch; groups g and g ^ 1 split the chain).
 // SW: the chain also runs at the neighbouring waypoints, for swept
 // collision and the speed metric; SP: the speed metric (Eq.(11)).
 // LP: link passes (HS = 1, more links than link waves); without it the
@@ -325,7 +337,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const int l0 = HS == 2 ? wave >> 1 : min(wave, L - 1);
   v4i info = *(cv4i*)(a.wl.info + l0);
   // (the ball of this lane's slot group: all slots, or half of them)
-  v4f bl = *(cv4f*)(a.wl.ball + l0 * 3 + (HS == 2 ? 1 + (wave & 1) : (G == 2 ? 1 + lane / E : 0)));
+  v4f bl = *(cv4f*)(a.wl.ball + l0 * kWlBalls + (HS == 2 ? 1 + (wave & 1) : group_ball<G>(g)));
   // subtree masks of the joints this wave gathers (wave and wave + W), read
   // with the first round
   const int jsub0 = ((cint*)a.wl.joint_rec)[2 * min(wave, D - 1) + 1];
@@ -468,7 +480,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const int l = link_w ? lp : 0, hs = HS == 2 ? wave & 1 : 0;
   if (LP && pass > 0 && link_w) {
     info = *(cv4i*)(a.wl.info + l);
-    bl = *(cv4f*)(a.wl.ball + l * 3 + (G == 2 ? 1 + lane / E : 0));
+    bl = *(cv4f*)(a.wl.ball + l * kWlBalls + group_ball<G>(g));
   }
   float* part = link_w ? s_part + (size_t)l * NPL * E : s_joint;
   if (LP && pass > 0) {
@@ -525,20 +537,22 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
       }
     };
     auto none = [](int, int, const float*) {};
-    // the link's pose at joint values qv into To; with G = 2 the two slot
-    // groups split the chain: group 0 composes its first half (world frame),
-    // group 1 the rest from the identity; the halves are swapped and both
-    // form the same product P0 P1 (tw: the velocity is formed as well)
+    // the link's pose at joint values qv into To; with G > 1 the slot groups
+    // g and g ^ 1 split the chain: the even one composes its first half
+    // (world frame), the odd one the rest from the identity; the halves are
+    // swapped and both form the same product P0 P1 (tw: the velocity is
+    // formed as well)
     auto link_fk = [&](auto&& qv, float* To, auto&& vis, bool tw) {
-      if constexpr (G == 2) {
+      if constexpr (G >= 2) {
+        const int odd = g & 1;
         const int split = (depth + 1) >> 1;
         float Pp[12];
-        chain_fk(rec + (g ? 4 * split : 0), g ? depth - split : split, row, qv, Pp, vis);
+        chain_fk(rec + (odd ? 4 * split : 0), odd ? depth - split : split, row, qv, Pp, vis);
         float Po[12];
 #pragma unroll
-        for (int e = 0; e < 12; ++e) Po[e] = other32(Pp[e], lane);
-        const float* P0 = g ? Po : Pp;
-        const float* P1 = g ? Pp : Po;
+        for (int e = 0; e < 12; ++e) Po[e] = chain_partner<G>(Pp[e], lane);
+        const float* P0 = odd ? Po : Pp;
+        const float* P1 = odd ? Pp : Po;
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
           const float a0 = P0[r * 4 + 0], a1 = P0[r * 4 + 1], a2 = P0[r * 4 + 2], a3 = P0[r * 4 + 3];
@@ -553,12 +567,12 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
           // (the other group's values are fetched by every lane first: a
           // conditional operator evaluates only the operand it selects, and
           // a lane swap inside one would run with half the wave inactive)
-          const float ox_[6] = {other32(wx, lane), other32(wy, lane), other32(wz, lane),
-                                other32(vx, lane), other32(vy, lane), other32(vz, lane)};
-          float w1[3] = {g ? wx : ox_[0], g ? wy : ox_[1], g ? wz : ox_[2]};
-          float u1[3] = {g ? vx : ox_[3], g ? vy : ox_[4], g ? vz : ox_[5]};
-          float w0[3] = {g ? ox_[0] : wx, g ? ox_[1] : wy, g ? ox_[2] : wz};
-          float u0[3] = {g ? ox_[3] : vx, g ? ox_[4] : vy, g ? ox_[5] : vz};
+          const float ox_[6] = {chain_partner<G>(wx, lane), chain_partner<G>(wy, lane), chain_partner<G>(wz, lane),
+                                chain_partner<G>(vx, lane), chain_partner<G>(vy, lane), chain_partner<G>(vz, lane)};
+          float w1[3] = {odd ? wx : ox_[0], odd ? wy : ox_[1], odd ? wz : ox_[2]};
+          float u1[3] = {odd ? vx : ox_[3], odd ? vy : ox_[4], odd ? vz : ox_[5]};
+          float w0[3] = {odd ? ox_[0] : wx, odd ? ox_[1] : wy, odd ? ox_[2] : wz};
+          float u0[3] = {odd ? ox_[3] : vx, odd ? ox_[4] : vy, odd ? ox_[5] : vz};
           float Rw[3], Ru[3];
 #pragma unroll
           for (int r = 0; r < 3; ++r) {
@@ -1029,4 +1043,6 @@ MG_WL_LAUNCHER(16, 1);
 MG_WL_LAUNCHER(2, 2);
 MG_WL_LAUNCHER(4, 2);
 MG_WL_LAUNCHER(8, 2);
+MG_WL_LAUNCHER(2, 4);
+MG_WL_LAUNCHER(4, 4);
 }  // namespace mg

@@ -1,0 +1,7 @@
+// Evaluation kernel instantiations, wave-per-link layout: 2 sphere slots per
+// lane, 4 slot groups per wave.
+#include "mg_eval_wl.h"
+
+namespace mg {
+MG_WL_LAUNCHER(2, 4) { return launch_eval_wl_g<2, 4>(a, grid_x, slices, cand, grad, s); }
+}  // namespace mg

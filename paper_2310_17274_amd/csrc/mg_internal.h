@@ -93,15 +93,16 @@ struct WaveLinks {
   const float4* chain_rec; // [L][kMaxDof][4]: fixed transform rows of chain[i], then
                            //   {joint index (int bits), 0, 0, 0}
   const float4* sphere;    // [L][maxs] centre in link frame + radius
-  const float4* ball;      // [L][3] balls bounding the link's spheres (link frame): centre,
-                           //   radius; all slots, then each half of the slots
+  const float4* ball;      // [L][kWlBalls] balls bounding the link's spheres (link frame):
+                           //   centre, radius; all slots, each half, each quarter
   int maxs;
   int max_depth;           // deepest chain (joints from the root)
   int halves;              // waves per link: 1, or 2 (each with half of the slots)
   int link_waves;          // halves == 1: link waves (<= n_links); wave w takes links w,
                            //   w + link_waves, ... in passes
-  int groups;              // slot groups per wave: 1, or 2 (32 evaluations per workgroup,
-                           //   each half of the wave with half of the slots; halves == 1)
+  int groups;              // slot groups per wave: 1, 2 or 4 (64 / groups evaluations per
+                           //   workgroup, each lane group with its share of the slots;
+                           //   halves == 1)
   int pm_rows;             // particle mode: rows of draws staged per workgroup (else 0)
   // cuboid slices over workgroups (gridDim.y > 1): per-slice partial sums
   // [chunk][slice][3 + D][64] and one arrival counter per chunk (zero
@@ -127,6 +128,9 @@ struct WaveLinks {
 constexpr size_t kWlLdsMax = 160 * 1024;   // LDS of a gfx950 CU (the device may report less)
 constexpr int kWlStageRows = kWave + 8;
 constexpr int kWlBoxTile = 64;   // cuboids per staged tile
+// bounding balls per link (link frame): all its slots, each half of them,
+// each quarter (the slot groups of two and four groups per wave)
+constexpr int kWlBalls = 7;
 // E: evaluations per workgroup (64 / slot groups per wave).
 constexpr int kWlPartsPerLink = 16;
 __host__ __device__ inline size_t wl_region_floats(int L, int D, int max_depth, int n_spheres, bool self,

@@ -175,7 +175,7 @@ def test_uneven_all_problems():
     _check_candidates(case, cost, gd, gk, mck, _oracle_candidates(case, x, d, meta["alpha"]), d)
 
 
-@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2")])
+@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")])
 def test_large_tree_swept_sixteen_seeds_every_candidate(layout):
     """Two-arm tree, 120 spheres, 500 cuboids, swept collision, 128 seeds x
     48 waypoints x 4 candidates in one launch: 16 seeds, every candidate,

@@ -19,10 +19,10 @@ pytestmark = pytest.mark.gpu
 # evaluation layouts (layout, slices): lane per link (automatic slices),
 # wave per link in one workgroup per 64 evaluations, split over four
 # workgroups (the last to finish adds the slices), two waves per link, and
-# two slot groups per wave (32 evaluations per workgroup)
+# two or four slot groups per wave (32 or 16 evaluations per workgroup)
 LAYOUTS = [pytest.param((0, 0), id="lane"), pytest.param((1, 1), id="wave"),
            pytest.param((1, 4), id="wave4"), pytest.param((2, 0), id="wave2"),
-           pytest.param((3, 0), id="groups2")]
+           pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")]
 
 
 def _dev(a):
@@ -45,8 +45,10 @@ class Case:
         if layout is not None:
             if layout[0] == 2 and self.robot.n_links > 8:
                 pytest.skip("two waves per link need at most 8 links")
-            if layout[0] == 3 and self_pairs is not None:
-                pytest.skip("two slot groups per wave take no self-collision")
+            if layout[0] >= 3 and self_pairs is not None:
+                pytest.skip("slot groups per wave take no self-collision")
+            if layout[0] == 4 and np.bincount(self.robot.sphere_link).max() <= 4:
+                pytest.skip("four slot groups per wave need more than 4 spheres on some link")
             self.b.mg_batch_set_layout(*layout)
         D = self.robot.dof
         self.q_start = _dev(b.q_start)
@@ -165,7 +167,7 @@ def test_swept_tunnelling_example_on_gpu(layout):
     assert gpu_cost_grad(cd)[0][0] == pytest.approx(0.001, rel=1e-4)
 
 
-@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2")])
+@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")])
 def test_large_tree_swept_linesearch_sampled(layout):
     """Two-arm tree (14 joints, 120 spheres) against 500 cuboids with swept
     collision, 128 seeds x 48 waypoints x 4 candidates in one line-search
@@ -211,7 +213,7 @@ def _particle_round_reference(case, mean, var, eps_round, costs_gpu, boxes, p=0)
 
 
 PARTICLE_LAYOUTS = [pytest.param((0, 0), id="lane"), pytest.param((1, 1), id="wave"),
-                    pytest.param((2, 0), id="wave2"), pytest.param((3, 0), id="groups2")]
+                    pytest.param((2, 0), id="wave2"), pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")]
 
 
 @pytest.mark.parametrize("layout", PARTICLE_LAYOUTS)
@@ -268,7 +270,7 @@ def test_particle_stage_end_to_end_against_reference():
         assert np.abs(mg[s] - m_ref[s]).max() <= 1e-2 * moved + 1e-5, s
 
 
-@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2")])
+@pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")])
 def test_large_tree_swept_particle_stage_sampled(layout):
     """Particle stage at full size: two-arm tree, 128 seeds x 48 waypoints,
     256 particles, 2 rounds, 500 cuboids, swept collision.  Sampled particle
@@ -313,8 +315,8 @@ def test_autotuned_layout_keeps_parity():
     d = case.ctx.mg_lbfgs_step(case.b, 4, True, case.x, g0)
     h = case.ctx.mg_autotune(case.b, case.q_start, case.goal, case.x, d, wl.ALPHA_4, launches=3)
     # lane-per-link slices, minus wave-per-link workgroups, two waves per
-    # link (-8) or two slot groups per wave (-16)
-    assert h in (1, 2, 4, -1, -2, -4, -8, -16)
+    # link (-8), two or four slot groups per wave (-16, -32)
+    assert h in (1, 2, 4, -1, -2, -4, -8, -16, -32)
     c, g, mc = gpu_cost_grad(case)
     cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, 7))
     H.assert_cost_close(c, cr)
@@ -655,7 +657,7 @@ def test_device_noise_matches_the_oracle():
 
 
 @pytest.mark.parametrize("layout", [pytest.param((0, 0), id="lane"), pytest.param(None, id="default"),
-                                    pytest.param((3, 0), id="groups2")])
+                                    pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")])
 def test_seeded_particle_stage(layout):
     """The particle stage with its draws made inside the evaluation and
     update kernels equals the stage fed the same draws from memory (bit for

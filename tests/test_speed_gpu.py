@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 SPEED = dict(speed=1)
 LAYOUTS = [pytest.param((0, 0), id="lane_request"), pytest.param((1, 1), id="wave"),
            pytest.param((1, 4), id="wave4"), pytest.param((2, 0), id="wave2"),
-           pytest.param((3, 0), id="groups2")]
+           pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")]
 
 
 def _collision_case(params, layout, seed=13):
@@ -53,7 +53,7 @@ def test_speed_cost_grad_parity(layout):
     assert plain > 0 and abs(fast - plain) > 1e-2 * plain
 
 
-@pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((3, 0), id="groups2")])
+@pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")])
 @pytest.mark.parametrize("kind", ["uneven", "tree"])
 def test_speed_cost_grad_parity_uneven_and_tree(kind, layout):
     """Horizons 2..64 (a one-waypoint speed uses the start and itself) and
@@ -62,7 +62,7 @@ def test_speed_cost_grad_parity_uneven_and_tree(kind, layout):
 
 
 @pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((2, 0), id="wave2"),
-                                    pytest.param((3, 0), id="groups2")])
+                                    pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")])
 def test_speed_with_swept_parity(layout):
     _check(_collision_case(dict(speed=1, swept=1, sweep_steps=4), layout, seed=21))
 
@@ -75,7 +75,7 @@ def test_speed_with_self_collision_parity():
     _check(case)
 
 
-@pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((3, 0), id="groups2")])
+@pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")])
 def test_speed_linesearch_parity(layout):
     case = make_case("plain", params=SPEED, layout=layout)
     _linesearch_parity(case, wl.ALPHA_4, 1)

@@ -36,8 +36,9 @@ def _both(case, alpha, mode):
     return [t.cpu().numpy() for t in ref_out], [t.cpu().numpy() for t in na_out]
 
 
-@pytest.mark.parametrize("layout,exact", [((0, 0), True), ((1, 1), True), ((3, 0), True), ((1, 4), False)],
-                         ids=["lane", "wave", "groups2", "wave4"])
+@pytest.mark.parametrize("layout,exact", [((0, 0), True), ((1, 1), True), ((3, 0), True), ((4, 0), True),
+                                          ((1, 4), False)],
+                         ids=["lane", "wave", "groups2", "groups4", "wave4"])
 def test_noalloc_linesearch_matches_linesearch(layout, exact):
     for S, T, K, seed in ((32, 32, 8, 11), (3, 12, 4, 12)):   # the second call is smaller
         case = _case(S, T, layout, seed)
