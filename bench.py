@@ -570,7 +570,7 @@ def _connected_queries(ctx, robot, nq, seed, res, n_max):
             {"free_samples": int(len(nodes)), "largest_component": int(len(big))})
 
 
-def bench_plan(warmup, reps=5):
+def bench_plan(warmup, reps=20):
     """Geometric planning (Alg.2, steering by Alg.3) on the 7-DOF arm with
     52 spheres among 40 oriented cuboids, one call per query set, each call
     seeded anew.  Two query sets: starts and goals that are the clearest of
@@ -628,7 +628,7 @@ def bench_plan(warmup, reps=5):
     return out
 
 
-def bench_large(warmup, reps=10):
+def bench_large(warmup, reps=20):
     """Two-arm tree (14 joints, 120 spheres), 500 oriented cuboids, swept
     collision (4 trace steps), 128 seeds x 48 waypoints: the particle stage
     (2 rounds x 256 particles per seed, noise drawn on the device) then 100
