@@ -1754,10 +1754,21 @@ mg_status mg_plan_batch(mg_ctx* c, mg_batch* b, int n_queries, const float* star
   for (int qy = 0; qy < n_queries; ++qy) n_waypoints[qy] = 0;
   std::vector<std::vector<float>> node;                  // graph nodes (host)
   std::vector<std::vector<std::pair<int, float>>> adj;   // undirected weighted edges
+  std::vector<int> comp;                                 // union-find over the nodes
   auto add_node = [&](const float* q) {
     node.emplace_back(q, q + D);
     adj.emplace_back();
+    comp.push_back((int)comp.size());
     return (int)node.size() - 1;
+  };
+  auto find = [&](int v) {
+    while (comp[v] != v) v = comp[v] = comp[comp[v]];
+    return v;
+  };
+  auto join = [&](int u, int v, float d) {
+    adj[u].push_back({v, d});
+    adj[v].push_back({u, d});
+    comp[find(u)] = find(v);
   };
   auto dist = [&](const float* a, const float* bq) {
     double d2 = 0.0;
@@ -1769,13 +1780,19 @@ mg_status mg_plan_batch(mg_ctx* c, mg_batch* b, int n_queries, const float* star
   float *d_from = nullptr, *d_to = nullptr, *d_reach = nullptr, *d_smp = nullptr, *d_nodes = nullptr;
   int *d_last = nullptr, *d_idx = nullptr;
   size_t node_cap = 0;
+  // (a horizon-1 batch of one round's candidates in the same world, for
+  // their clearance)
+  const int cl_rows = std::min(rows, kOversample * p_cap), one = 1;
+  mg_batch* cb = nullptr;
   auto free_all = [&]() {
     dev_free(d_from); dev_free(d_to); dev_free(d_reach); dev_free(d_last); dev_free(d_smp); dev_free(d_idx);
     dev_free(d_nodes);
+    if (cb) mg_batch_destroy(cb);
   };
   if ((st = dev_alloc(&d_from, (size_t)cap * D)) != MG_OK || (st = dev_alloc(&d_to, (size_t)cap * D)) != MG_OK ||
       (st = dev_alloc(&d_reach, (size_t)cap * D)) != MG_OK || (st = dev_alloc(&d_last, (size_t)cap)) != MG_OK ||
-      (st = dev_alloc(&d_smp, (size_t)p_cap * D)) != MG_OK || (st = dev_alloc(&d_idx, (size_t)p_cap * k_cap)) != MG_OK) {
+      (st = dev_alloc(&d_smp, (size_t)p_cap * D)) != MG_OK || (st = dev_alloc(&d_idx, (size_t)p_cap * k_cap)) != MG_OK ||
+      (st = mg_batch_create(c, 1, &cl_rows, &one, &b->world[0], 1, 0, &cb)) != MG_OK) {
     free_all();
     return st;
   }
@@ -1812,31 +1829,29 @@ mg_status mg_plan_batch(mg_ctx* c, mg_batch* b, int n_queries, const float* star
         const bool full = dist(v, t) <= 1e-5f;
         if (full && edges[k].second >= 0) to = edges[k].second;
         else to = add_node(v);
-        const float d = dist(node[from].data(), node[to].data());
-        adj[from].push_back({to, d});
-        adj[to].push_back({from, d});
+        join(from, to, dist(node[from].data(), node[to].data()));
         if (reached && full) (*reached)[k] = to;
       }
     }
     return MG_OK;
   };
   // clearance of candidate samples: one horizon-1 evaluation launch per
-  // batch-full (world clearance >= 0 keeps a sample; limits hold by
-  // construction)
-  std::vector<float> h_rows((size_t)rows * D), h_mc(rows);
+  // batch-full of a batch sized for one round's candidates (world clearance
+  // >= 0 keeps a sample; limits hold by construction)
+  std::vector<float> h_rows((size_t)cl_rows * D), h_mc(cl_rows);
   auto clear_samples = [&](std::vector<std::vector<float>>& smp) -> mg_status {
     std::vector<std::vector<float>> keep;
-    for (size_t s0 = 0; s0 < smp.size(); s0 += rows) {
-      const int n = (int)std::min(smp.size() - s0, (size_t)rows);
-      for (int r = 0; r < rows; ++r) {
+    for (size_t s0 = 0; s0 < smp.size(); s0 += cl_rows) {
+      const int n = (int)std::min(smp.size() - s0, (size_t)cl_rows);
+      for (int r = 0; r < cl_rows; ++r) {
         const auto& q = smp[s0 + std::min(r, n - 1)];
         std::copy(q.begin(), q.end(), &h_rows[(size_t)r * D]);
       }
-      HIP_TRY(hipMemcpyAsync(b->g_cur, h_rows.data(), h_rows.size() * 4, hipMemcpyHostToDevice, s));
-      mg_status r = enqueue_eval(c, b, c->d_zero, c->d_goal_id, b->g_cur, nullptr, 1, nullptr, false, nullptr,
+      HIP_TRY(hipMemcpyAsync(cb->g_cur, h_rows.data(), h_rows.size() * 4, hipMemcpyHostToDevice, s));
+      mg_status r = enqueue_eval(c, cb, c->d_zero, c->d_goal_id, cb->g_cur, nullptr, 1, nullptr, false, nullptr,
                                  nullptr, s);
       if (r != MG_OK) return r;
-      HIP_TRY(hipMemcpyAsync(h_mc.data(), b->mc_e, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(h_mc.data(), cb->mc_e, (size_t)n * 4, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       for (int i = 0; i < n; ++i)
         if (h_mc[i] >= 0.0f) keep.push_back(smp[s0 + i]);
@@ -1907,7 +1922,7 @@ mg_status mg_plan_batch(mg_ctx* c, mg_batch* b, int n_queries, const float* star
     std::vector<int> k_n(n_queries, k_near), p_n(n_queries, n_samples);
     int n_solved = 0;
     for (int qy = 0; qy < n_queries; ++qy) {
-      len[qy] = shortest(sn[qy], gn[qy], route[qy]);
+      len[qy] = find(sn[qy]) == find(gn[qy]) ? shortest(sn[qy], gn[qy], route[qy]) : 3.0e38f;
       c_min[qy] = dist(starts + (size_t)qy * D, goals + (size_t)qy * D);
       n_solved += !route[qy].empty();
     }
@@ -1993,16 +2008,20 @@ mg_status mg_plan_batch(mg_ctx* c, mg_batch* b, int n_queries, const float* star
           if (v < 0) continue;
           if (first < 0) { first = v; continue; }
           if (v == first) continue;
-          adj[first].push_back({v, 0.0f});
-          adj[v].push_back({first, 0.0f});
+          join(first, v, 0.0f);
         }
       }
-      // the roadmap is shared: every query's shortest path may improve
+      // the roadmap is shared: an unsolved query whose start and goal the
+      // round joined (union-find) takes its shortest path, and a refine
+      // round updates the picked query's
       n_solved = 0;
       for (int u = 0; u < n_queries; ++u) {
-        std::vector<int> rt;
-        const float l2 = shortest(sn[u], gn[u], rt);
-        if (!rt.empty() && (route[u].empty() || l2 < len[u])) { route[u] = rt; len[u] = l2; }
+        const bool look = route[u].empty() ? find(sn[u]) == find(gn[u]) : (refine && u == qy);
+        if (look) {
+          std::vector<int> rt;
+          const float l2 = shortest(sn[u], gn[u], rt);
+          if (!rt.empty() && (route[u].empty() || l2 < len[u])) { route[u] = rt; len[u] = l2; }
+        }
         n_solved += !route[u].empty();
       }
       // a failed round widens the picked query's region and grows its

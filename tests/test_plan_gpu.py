@@ -118,3 +118,30 @@ def test_plan_batch_rejects_bad_arguments():
         ctx.mg_plan_batch(b, z, z, 0.05, 64, k_near=17)
     with pytest.raises(RuntimeError):
         ctx.mg_plan_batch(b, z, z, 0.05, 63)   # seeds not a multiple of n_max + 1
+
+
+def test_plan_batch_with_retract_and_trivial_queries():
+    """A retract configuration joins the roadmap (both ways to every start
+    and goal); a query whose start is its goal returns the two-waypoint path
+    at once; a free-space query alongside it takes the direct edge."""
+    robot = wl.robot_f32(wl.make_arm(seed=0, n_spheres=52))
+    worlds = wl.worlds_f32(wl.make_worlds(2, [10]))
+    boxes = worlds.world(0)
+    r = ref.Ref(robot)
+    res = 0.05
+    (a, g), = _blocked_pairs(r, boxes, robot, np.random.default_rng(74), 1, res)
+    ctx, b = _ctx(robot, worlds, 128, 128)
+    retract = np.zeros(7, np.float32)
+    starts = np.stack([a, a]).astype(np.float32)
+    goals = np.stack([g, a]).astype(np.float32)
+    paths = ctx.mg_plan_batch(b, starts, goals, res, 128, retract=retract, n_samples=64, k_near=4,
+                              max_rounds=24, refine_rounds=2, seed=11)
+    p_same = paths[1]
+    assert p_same.shape == (2, 7)
+    np.testing.assert_array_equal(p_same[0], a.astype(np.float32))
+    np.testing.assert_array_equal(p_same[1], a.astype(np.float32))
+    p = paths[0]
+    if len(p):
+        np.testing.assert_array_equal(p[0], a.astype(np.float32))
+        np.testing.assert_array_equal(p[-1], g.astype(np.float32))
+        assert _path_valid(r, boxes, p.astype(np.float64), res, robot)
