@@ -217,6 +217,25 @@ __device__ __forceinline__ void dc_term(const v4f& A0, const v4f& A1, const v4f&
   gz = fmaf(f, A0.z * gpx + A1.z * gpy + A2.z * gpz, gz);
 }
 
+// dc_term with the gradient left in the box frame: f grad_p accumulated into
+// b (f = -w slope), for several samples against one cuboid that are rotated
+// back to the world once (A^T b).
+__device__ __forceinline__ void dc_term_box(float sdf, float gpx, float gpy, float gpz, float r, float w, float eta,
+                                            float inv_eta, float& cost, float& bx, float& by, float& bz) {
+  const float pen = r - sdf;
+  const float u = pen + eta;
+  const bool deep = pen > 0.0f, band = pen > -eta;
+  float dcv = deep ? pen + 0.5f * eta : 0.5f * u * u * inv_eta;
+  float slope = deep ? 1.0f : u * inv_eta;
+  dcv = band ? dcv : 0.0f;
+  slope = band ? slope : 0.0f;
+  cost += w * dcv;
+  const float f = -w * slope;
+  bx = fmaf(f, gpx, bx);
+  by = fmaf(f, gpy, by);
+  bz = fmaf(f, gpz, bz);
+}
+
 // One sphere against one cuboid, taken only when the cheap face test says
 // the sphere may be within r + eta: exact signed distance, Eq.(10) profile,
 // clearance, and d cost / d centre accumulated into g.  Returns the distance.

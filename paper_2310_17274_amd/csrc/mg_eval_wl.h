@@ -226,11 +226,24 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
             float cs = 0.0f;
             float& cacc = SP ? cs : cost;
             const float wp = SP ? w0 : ws[s];
-            const float sdf = near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y,
-                                        fabsf(pz) - Hh.z, rr[s], wp, eta, inv_eta, cacc, mc, gx, gy, gz);
-            if (SW && sw.on)
-              sweep_pair_ls(sw.sl[s], sw.steps, sw.Tp, sw.Tn, sw.has_next, cx[s], cy[s], cz[s], A0, A1, A2,
-                            Hh, px, py, pz, sdf, rr[s], wp, eta, inv_eta, cacc, gx, gy, gz);
+            if constexpr (SW) {
+              // the pair's samples (its own and the trace's) sum their
+              // gradients in the box frame, rotated back to the world once
+              float gpx, gpy, gpz, bgx = 0.0f, bgy = 0.0f, bgz = 0.0f;
+              const float sdf = box_sdf(px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y, fabsf(pz) - Hh.z, gpx,
+                                        gpy, gpz);
+              mc = fminf(mc, sdf - rr[s]);
+              dc_term_box(sdf, gpx, gpy, gpz, rr[s], wp, eta, inv_eta, cacc, bgx, bgy, bgz);
+              if (sw.on)
+                sweep_pair_box(sw.sl[s], sw.steps, sw.Tp, sw.Tn, sw.has_next, cx[s], cy[s], cz[s], A0, A1, A2,
+                               Hh, px, py, pz, sdf, rr[s], wp, eta, inv_eta, cacc, bgx, bgy, bgz);
+              gx = A0.x * bgx + A1.x * bgy + A2.x * bgz;
+              gy = A0.y * bgx + A1.y * bgy + A2.y * bgz;
+              gz = A0.z * bgx + A1.z * bgy + A2.z * bgz;
+            } else {
+              near_pair(A0, A1, A2, px, py, pz, fabsf(px) - Hh.x, fabsf(py) - Hh.y, fabsf(pz) - Hh.z, rr[s], wp,
+                        eta, inv_eta, cacc, mc, gx, gy, gz);
+            }
             if constexpr (SP) {
               dsl[s] += cs;
               cost = fmaf(ws[s], cs, cost);
