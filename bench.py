@@ -77,7 +77,7 @@ def main():
                     help="force the evaluation layout (0 lane per link, 1 wave per link, "
                          "2 two waves per link, 3 two slot groups per wave, 4 four slot groups "
                          "per wave) instead of the autotuner's choice")
-    ap.add_argument("--slices", type=int, choices=[0, 1, 2, 4], default=0,
+    ap.add_argument("--slices", type=int, choices=[0, 1, 2, 4, 8, 16], default=0,
                     help="with --layout: cuboid slices (0 automatic)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the uneven-batch, inverse-kinematics, large, motion-generation and "

@@ -247,9 +247,10 @@ mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *s
  * skipping the cuboids that a ball around its link's spheres over all 64
  * lanes cannot reach (with swept collision, the ball grows by half the
  * longer segment); needs at most 15 links; the particle stage does not use it.
- * For small batches the wave-per-link layout can also split the cuboids
- * over 2 or 4 workgroups per 64 evaluations; the last to finish adds the
- * slices' sums in slice order (the batch keeps the scratch and counters).
+ * The wave-per-link layout can also split the cuboids over 2, 4, 8 or 16
+ * workgroups per 64 evaluations (as many as the batch's 64 MB of slice
+ * scratch holds); the last to finish adds the slices' sums in slice order
+ * (the batch keeps the scratch and counters).
  * A robot of up to 8 links can also give each link two waves with half of
  * its spheres each (layout 2), the second also taking that link's joint
  * terms: shorter waves, no separate joint wave.  Layout 3 keeps one wave
@@ -260,7 +261,8 @@ mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *s
  * the slots (four times the workgroups; at least 8 slots per link).  In
  * both, two lane groups split each evaluation's kinematic chain in halves.
  * mg_batch_set_layout fixes a layout (-1: library default, 0 .. 4) and a
- * slice count (0: automatic; 1, 2 or 4; layouts 2, 3 and 4 take 0 or 1).
+ * slice count (0: automatic; 1, 2 or 4, and for layout 1 also 8 or 16;
+ * layouts 2, 3 and 4 take 0 or 1).
  * Host-only; affects later calls.
  *
  * Autotuner for a batch's launch shape: times the line-search evaluation

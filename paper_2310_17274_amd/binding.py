@@ -71,8 +71,8 @@ class Batch:
     def mg_batch_set_layout(self, layout: int, slices: int = 0):
         """Fix the evaluation layout (-1 default, 0 lane per link, 1 wave per
         link, 2 two waves per link, 3 two slot groups per wave, 4 four slot
-        groups per wave) and the cuboid slices (0 automatic, 1, 2, 4;
-        layouts 2, 3 and 4: 0 or 1)."""
+        groups per wave) and the cuboid slices (0 automatic, 1, 2, 4, and
+        for layout 1 also 8 or 16; layouts 2, 3 and 4: 0 or 1)."""
         _lib.check(_lib.lib().mg_batch_set_layout(self.handle, int(layout), int(slices)))
 
     def mg_batch_reserve_particles(self, n_particles: int):

@@ -913,10 +913,10 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
   c->batches.push_back(b);
   if ((st = wl_chunks_upload(b)) != MG_OK) return bail(st);
   {
-    // wave-per-link slice scratch: up to 4 slices while it stays under 64 MB
+    // wave-per-link slice scratch: up to 16 slices while it stays under 64 MB
     const size_t per = (size_t)b->chunks_wl[K_max][0] * (3 + c->D) * mg::kWave * sizeof(float);
     b->wl_slices_max = 1;
-    while (b->wl_slices_max < 4 && per * b->wl_slices_max * 2 <= (64u << 20)) b->wl_slices_max *= 2;
+    while (b->wl_slices_max < 16 && per * b->wl_slices_max * 2 <= (64u << 20)) b->wl_slices_max *= 2;
     if (b->wl_slices_max > 1) {
       if ((st = dev_alloc(&b->wl_part, per / sizeof(float) * b->wl_slices_max)) != MG_OK ||
           (st = dev_alloc(&b->wl_count, (size_t)b->chunks_wl[K_max][0])) != MG_OK)
@@ -1255,7 +1255,9 @@ mg_status mg_batch_set_layout(mg_batch* b, int layout, int slices) {
   if (slices != 0) {
     for (int i = 0; i < kNumSlices; ++i)
       if (kSlices[i] == slices) hi = i;
-    if (hi < 0) return fail(MG_ERR_ARG, "slices must be 0 (automatic), 1, 2 or 4");
+    // (wave per link also takes 8 and 16 workgroups per chunk)
+    const bool wl_ok = layout == 1 && (slices == 8 || slices == 16);
+    if (hi < 0 && !wl_ok) return fail(MG_ERR_ARG, "slices must be 0 (automatic), 1, 2 or 4 (wave per link: or 8, 16)");
     if (layout == 1 && slices > b->wl_slices_max)
       return fail(MG_ERR_SHAPE, "this batch holds at most %d wave-per-link slices", b->wl_slices_max);
   }

@@ -145,6 +145,21 @@ def test_swept_cost_grad_parity(kind, layout):
     assert np.all(cr >= cd) and np.any(cr > cd)
 
 
+@pytest.mark.parametrize("layout", [pytest.param((1, 8), id="wave8"), pytest.param((1, 16), id="wave16")])
+@pytest.mark.parametrize("kind,params", [("plain", None), ("uneven", None), ("tree", None),
+                                         ("adjoint_small", SWEPT), ("tree", SWEPT)],
+                         ids=["plain", "uneven", "tree", "adjoint_small-swept", "tree-swept"])
+def test_cost_grad_parity_many_slices(kind, params, layout):
+    """The wave-per-link layout with the world split over 8 and 16
+    workgroups per chunk (the last to finish adds the slices in order)."""
+    case = make_case(kind, layout=layout, params=params)
+    c, g, mc = gpu_cost_grad(case)
+    cr, gr, mcr = H.oracle_cost_grad(case.ref, case.worlds, case.batch, case.batch.x0.reshape(-1, case.robot.dof))
+    H.assert_cost_close(c, cr)
+    H.assert_grad_close(g, gr, case.batch)
+    H.assert_verdicts(mc, mcr)
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_swept_tunnelling_example_on_gpu(layout):
     """The thin-wall example worked by hand in the reference's pins: both
