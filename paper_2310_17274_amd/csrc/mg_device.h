@@ -194,6 +194,21 @@ __device__ __forceinline__ float box_sdf(float px, float py, float pz, float ax,
   return out ? n : fmaxf(ax, fmaxf(ay, az));
 }
 
+// box_sdf without the gradient (cost-only evaluations).
+__device__ __forceinline__ float box_dist(float ax, float ay, float az) {
+  const float qx = fmaxf(ax, 0.0f), qy = fmaxf(ay, 0.0f), qz = fmaxf(az, 0.0f);
+  const float n2 = qx * qx + qy * qy + qz * qz;
+  return n2 > 0.0f ? __builtin_amdgcn_sqrtf(n2) : fmaxf(ax, fmaxf(ay, az));
+}
+
+// Eq.(10) smoothed penetration cost w d_c(r - sdf) alone.
+__device__ __forceinline__ void dc_cost(float sdf, float r, float w, float eta, float inv_eta, float& cost) {
+  const float pen = r - sdf;
+  const float u = pen + eta;
+  const float dcv = pen > 0.0f ? pen + 0.5f * eta : 0.5f * u * u * inv_eta;
+  cost += pen > -eta ? w * dcv : 0.0f;
+}
+
 // Eq.(10) smoothed penetration cost w d_c(r - sdf) added to cost; the box-frame
 // gradient (gpx, gpy, gpz) of sdf is rotated back to the world and
 // d cost / d point is accumulated into g.  Outside the band (r - sdf <=

@@ -263,6 +263,38 @@ __device__ __forceinline__ void sweep_pair_box(const float4 ls, int steps, const
   }
 }
 
+// sweep_pair_box for cost-only evaluations: the trace samples' costs alone.
+__device__ __forceinline__ void sweep_pair_cost(const float4 ls, int steps, const float* Tp, const float* Tn,
+                                                bool has_next, float cx, float cy, float cz, const v4f& A0,
+                                                const v4f& A1, const v4f& A2, const v4f& Hh, float px, float py,
+                                                float pz, float sdf, float r, float w, float eta, float inv_eta,
+                                                float& cost) {
+  const float rh = r + eta;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const float* Tb = side == 0 ? Tp : Tn;
+    if (side == 1 && !has_next) break;
+    float ux = Tb[0] * ls.x + Tb[1] * ls.y + Tb[2] * ls.z + Tb[3] - cx;
+    float uy = Tb[4] * ls.x + Tb[5] * ls.y + Tb[6] * ls.z + Tb[7] - cy;
+    float uz = Tb[8] * ls.x + Tb[9] * ls.y + Tb[10] * ls.z + Tb[11] - cz;
+    const float len = sqrtf(ux * ux + uy * uy + uz * uz);
+    if (!(len > 0.0f)) continue;
+    const float il = 1.0f / len;
+    ux *= il; uy *= il; uz *= il;
+    const float vx = A0.x * ux + A0.y * uy + A0.z * uz;
+    const float vy = A1.x * ux + A1.y * uy + A1.z * uz;
+    const float vz = A2.x * ux + A2.y * uy + A2.z * uz;
+    const float half = 0.5f * len;
+    float j = sdf < rh ? rh : sdf - rh;
+    for (int st = 0; st < steps && j < half; ++st) {
+      const float qx = fmaf(j, vx, px), qy = fmaf(j, vy, py), qz = fmaf(j, vz, pz);
+      const float s2 = box_dist(fabsf(qx) - Hh.x, fabsf(qy) - Hh.y, fabsf(qz) - Hh.z);
+      dc_cost(s2, r, w, eta, inv_eta, cost);
+      j += s2 - rh > 0.0f ? s2 - rh : rh;
+    }
+  }
+}
+
 __device__ __forceinline__ void sweep_pair(const EvalArgs& a, int slot, const float* Tp,
                                            const float* Tn, bool has_next, float cx, float cy,
                                            float cz, const v4f& A0, const v4f& A1, const v4f& A2,

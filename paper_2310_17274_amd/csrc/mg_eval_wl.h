@@ -147,7 +147,8 @@ struct SweepCtx {
 // SP (speed metric): ws holds each slot's speed; the pair's cost and
 // gradient are formed at weight w0 (w_coll), summed per slot into dsl (the
 // slot's collision cost before the speed) and scaled by the speed.
-template <int MAXS, bool SW, bool SP>
+// GRAD = false (cost-only launches): distances and costs alone, no gradient.
+template <int MAXS, bool SW, bool SP, bool GRAD>
 __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane, float cwx, float cwy,
                                            float cwz, float Rw, float bx, float by, float bz, float rl,
                                            const float* cx, const float* cy, const float* cz,
@@ -220,7 +221,23 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
 #pragma unroll
         for (int u = 0; u < G; ++u) {
           const int s = g0 + u;
-          if (m3[u] < rho[s]) {
+          if (!GRAD && m3[u] < rho[s]) {
+            // cost only: the distance, the profile, the clearance
+            const float px = ppx[u], py = ppy[u], pz = ppz[u];
+            float cs = 0.0f;
+            float& cacc = SP ? cs : cost;
+            const float wp = SP ? w0 : ws[s];
+            const float sdf = box_dist(fabsf(px) - Hh.x, fabsf(py) - Hh.y, fabsf(pz) - Hh.z);
+            mc = fminf(mc, sdf - rr[s]);
+            dc_cost(sdf, rr[s], wp, eta, inv_eta, cacc);
+            if (SW && sw.on)
+              sweep_pair_cost(sw.sl[s], sw.steps, sw.Tp, sw.Tn, sw.has_next, cx[s], cy[s], cz[s], A0, A1, A2, Hh,
+                              px, py, pz, sdf, rr[s], wp, eta, inv_eta, cacc);
+            if constexpr (SP) {
+              dsl[s] += cs;
+              cost = fmaf(ws[s], cs, cost);
+            }
+          } else if (GRAD && m3[u] < rho[s]) {
             const float px = ppx[u], py = ppy[u], pz = ppz[u];
             float gx = 0.0f, gy = 0.0f, gz = 0.0f;
             float cs = 0.0f;
@@ -778,7 +795,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
     const float4 u0 = i0 < 4 * nn ? nsrc[i0] : float4{};
     const float4 u1 = i1 < 4 * nn ? nsrc[i1] : float4{};
     if (wave_sph)
-      world_tile<MAXS, SW, SP>(s_box + buf * kWlBoxTile * 4, nb, lane, cwx, cwy, cwz, Rw, bxl, byl, bzl, rlb, cx,
+      world_tile<MAXS, SW, SP, GRAD>(s_box + buf * kWlBoxTile * 4, nb, lane, cwx, cwy, cwz, Rw, bxl, byl, bzl, rlb, cx,
                                cy, cz, rr, rho, swc, ws, a.pr.w_coll, dsl, eta, inv_eta, cost, mc, Fx, Fy, Fz, Mx, My,
                                Mz);
     if (nn <= 0) break;
