@@ -230,7 +230,9 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
             const float sdf = box_dist(fabsf(px) - Hh.x, fabsf(py) - Hh.y, fabsf(pz) - Hh.z);
             mc = fminf(mc, sdf - rr[s]);
             dc_cost(sdf, rr[s], wp, eta, inv_eta, cacc);
-            if (SW && sw.on)
+            // (every trace sample lies within the slot's half segment of its
+            // centre: beyond the cull radius none reaches the band)
+            if (SW && sw.on && sdf < rho[s])
               sweep_pair_cost(sw.sl[s], sw.steps, sw.Tp, sw.Tn, sw.has_next, cx[s], cy[s], cz[s], A0, A1, A2, Hh,
                               px, py, pz, sdf, rr[s], wp, eta, inv_eta, cacc);
             if constexpr (SP) {
@@ -251,7 +253,7 @@ __device__ __forceinline__ void world_tile(const float4* tile, int nb, int lane,
                                         gpy, gpz);
               mc = fminf(mc, sdf - rr[s]);
               dc_term_box(sdf, gpx, gpy, gpz, rr[s], wp, eta, inv_eta, cacc, bgx, bgy, bgz);
-              if (sw.on)
+              if (sw.on && sdf < rho[s])
                 sweep_pair_box(sw.sl[s], sw.steps, sw.Tp, sw.Tn, sw.has_next, cx[s], cy[s], cz[s], A0, A1, A2,
                                Hh, px, py, pz, sdf, rr[s], wp, eta, inv_eta, cacc, bgx, bgy, bgz);
               gx = A0.x * bgx + A1.x * bgy + A2.x * bgz;
