@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libmg.so")
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in
            ["mg_api.hip", "mg_kernels.hip", "mg_lbfgs.hip", "mg_eval_wl.hip"] +
-           [f"mg_select_p{pl}.hip" for pl in (1, 2, 4, 8, 16)] + ["mg_select_p16h.hip"] +
+           [f"mg_select_p{pl}.hip" for pl in (1, 2, 4, 8, 16)] + ["mg_select_p16h.hip", "mg_select_packed.hip"] +
            [f"mg_eval_wl_s{slots}g{groups}.hip" for slots, groups in
             ((2, 1), (4, 1), (8, 1), (16, 1), (2, 2), (4, 2), (8, 2), (2, 4), (4, 4))] +
            [f"mg_eval_l{lanes}s{slots}.hip" for lanes in (8, 16) for slots in (4, 8, 16)]]

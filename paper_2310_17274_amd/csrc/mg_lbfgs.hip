@@ -27,6 +27,7 @@ hipError_t launch_lbfgs(const LbfgsArgs& a, int max_n, hipStream_t s) {
   return launch_lbfgs_h<kMaxHist>(a, max_n, s);
 }
 hipError_t launch_select(const SelectArgs& a, int max_n, const LbfgsArgs* fuse, hipStream_t s) {
+  if (max_n <= 32) return launch_select_packed(a, max_n, fuse, s);
   if (max_n <= 64) return launch_select_p1(a, fuse, s);
   if (max_n <= 128) return launch_select_p2(a, fuse, s);
   if (max_n <= 256) return launch_select_p4(a, fuse, s);

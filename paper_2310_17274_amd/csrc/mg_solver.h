@@ -16,16 +16,25 @@ __device__ __forceinline__ SeedInfo seed_info(const SeedInfo* seeds, int uniform
   return seeds[s];
 }
 
-// A seed's row block of n = T*D floats held PL per lane: element u of a
-// lane is lane + 64 u (strided), or with V4 lane PL + u (contiguous, moved
-// as float4: the block is a multiple of 4 floats and 16-byte aligned).
-template <int PL, bool V4>
+// A seed's row block of n = T*D floats held PL per lane of its W lanes
+// (one wavefront, or W = 8, 16, 32 lanes of one when several seeds share
+// it): element u of a lane is lane + W u (strided), or with V4 lane PL + u
+// (contiguous, moved as float4: the block is a multiple of 4 floats and
+// 16-byte aligned).
+template <int PL, bool V4, int W = kWave>
 __device__ __forceinline__ int el_idx(int lane, int u) {
-  return V4 ? lane * PL + u : lane + u * kWave;
+  return V4 ? lane * PL + u : lane + u * W;
+}
+// A per-seed scalar: through the scalar cache when the seed is the
+// wavefront's own (W = 64), else a vector load.
+template <int W, typename Tv>
+__device__ __forceinline__ Tv ld_seed(const Tv* p) {
+  if constexpr (W == kWave) return *(const __attribute__((address_space(4))) Tv*)p;
+  else return *p;
 }
 // Loads at clamped (always valid) addresses, masked afterwards (zero
 // outside the block).
-template <int PL, bool V4>
+template <int PL, bool V4, int W = kWave>
 __device__ __forceinline__ void ld_row(const float* p, int n, int lane, float* v) {
   if constexpr (V4) {
 #pragma unroll
@@ -41,13 +50,13 @@ __device__ __forceinline__ void ld_row(const float* p, int n, int lane, float* v
   } else {
 #pragma unroll
     for (int u = 0; u < PL; ++u) {
-      const int e = lane + u * kWave;
+      const int e = lane + u * W;
       v[u] = p[min(e, n - 1)];
       v[u] = e < n ? v[u] : 0.0f;
     }
   }
 }
-template <int PL, bool V4>
+template <int PL, bool V4, int W = kWave>
 __device__ __forceinline__ void st_row(float* p, int n, int lane, const float* v) {
   if constexpr (V4) {
 #pragma unroll
@@ -58,7 +67,7 @@ __device__ __forceinline__ void st_row(float* p, int n, int lane, const float* v
   } else {
 #pragma unroll
     for (int u = 0; u < PL; ++u) {
-      const int e = lane + u * kWave;
+      const int e = lane + u * W;
       if (e < n) p[e] = v[u];
     }
   }
@@ -78,7 +87,7 @@ struct LbfgsRegs {
   float Sh[MH][PL], Yh[MH][PL], rh[MH];
 };
 
-template <int PL, int MH, bool V4>
+template <int PL, int MH, bool V4, int W = kWave>
 __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
                                            LbfgsRegs<PL, MH>& h) {
   const int n = si.T * a.dof;
@@ -89,18 +98,18 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
   // masked afterwards: a guarded load becomes a branch around it, which
   // costs more than the load.  (Per-seed scalars go through the constant
   // address space: scalar loads, waited for where first used.)
-  const int first = ((cint*)a.first)[s];
-  int count = ((cint*)a.meta)[2 * s + 0];
-  int head = ((cint*)a.meta)[2 * s + 1];
-  ld_row<PL, V4>(a.x_prev + base, n, lane, h.xp);
-  ld_row<PL, V4>(a.g_prev + base, n, lane, h.gp);
+  const int first = ld_seed<W>(a.first + s);
+  int count = ld_seed<W>(a.meta + 2 * s + 0);
+  int head = ld_seed<W>(a.meta + 2 * s + 1);
+  ld_row<PL, V4, W>(a.x_prev + base, n, lane, h.xp);
+  ld_row<PL, V4, W>(a.g_prev + base, n, lane, h.gp);
   float RS[MH][PL], RY[MH][PL], Rr[MH];
 #pragma unroll
   for (int r = 0; r < MH; ++r) {
     const int rc = min(r, max(m - 1, 0));   // (the history holds at least one slot)
-    Rr[r] = ((cfloat*)a.rho)[(size_t)s * a.m_max + rc];
-    ld_row<PL, V4>(a.S + (size_t)rc * stride + base, n, lane, RS[r]);
-    ld_row<PL, V4>(a.Y + (size_t)rc * stride + base, n, lane, RY[r]);
+    Rr[r] = ld_seed<W>(a.rho + (size_t)s * a.m_max + rc);
+    ld_row<PL, V4, W>(a.S + (size_t)rc * stride + base, n, lane, RS[r]);
+    ld_row<PL, V4, W>(a.Y + (size_t)rc * stride + base, n, lane, RY[r]);
   }
   const bool reset = a.reset != 0 || (a.use_first && first != 0);
   if (reset) { count = 0; head = 0; }
@@ -133,7 +142,7 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
         sv = i == r ? RS[r][u] : sv;
         yv = i == r ? RY[r][u] : yv;
       }
-      const bool in = live && el_idx<PL, V4>(lane, u) < n;
+      const bool in = live && el_idx<PL, V4, W>(lane, u) < n;
       h.Sh[c][u] = in ? sv : 0.0f;
       h.Yh[c][u] = in ? yv : 0.0f;
     }
@@ -145,9 +154,12 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
 // n = T*D <= 64*PL): stores the last step's pair in the ring when its
 // curvature passes the guard, runs the two loops on registers and DPP sums,
 // and writes dir and x/g_prev.
-template <int PL, int MH, bool V4>
+// (st_ok false: a lane group that only pads the last wavefront computes
+// but stores nothing)
+template <int PL, int MH, bool V4, int W = kWave>
 __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
-                                             const float* xv, const float* gv, LbfgsRegs<PL, MH>& h) {
+                                             const float* xv, const float* gv, LbfgsRegs<PL, MH>& h,
+                                             bool st_ok = true) {
   const int n = si.T * a.dof;
   const size_t base = (size_t)si.row0 * a.dof;
   const size_t stride = (size_t)a.rows * a.dof;
@@ -156,7 +168,7 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
   float sv[PL], yv[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const bool in = el_idx<PL, V4>(lane, u) < n && !h.reset;
+    const bool in = el_idx<PL, V4, W>(lane, u) < n && !h.reset;
     sv[u] = in ? xv[u] - h.xp[u] : 0.0f;
     yv[u] = in ? gv[u] - h.gp[u] : 0.0f;
   }
@@ -169,11 +181,13 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
       ss = fmaf(sv[u], sv[u], ss);
       yy = fmaf(yv[u], yv[u], yy);
     }
-    sy = wave_sum(sy); ss = wave_sum(ss); yy = wave_sum(yy);
+    sy = group_sum<W>(sy); ss = group_sum<W>(ss); yy = group_sum<W>(yy);
     if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy) && sy > 0.0f) {
-      st_row<PL, V4>(a.S + (size_t)head * stride + base, n, lane, sv);
-      st_row<PL, V4>(a.Y + (size_t)head * stride + base, n, lane, yv);
-      if (lane == 0) a.rho[(size_t)s * a.m_max + head] = 1.0f / sy;
+      if (st_ok) {
+        st_row<PL, V4, W>(a.S + (size_t)head * stride + base, n, lane, sv);
+        st_row<PL, V4, W>(a.Y + (size_t)head * stride + base, n, lane, yv);
+        if (lane == 0) a.rho[(size_t)s * a.m_max + head] = 1.0f / sy;
+      }
       // shift the register copy: the new pair becomes slot 0
 #pragma unroll
       for (int c = MH - 1; c > 0; --c) {
@@ -200,7 +214,7 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
       float dsq = 0.0f;
 #pragma unroll
       for (int u = 0; u < PL; ++u) dsq = fmaf(h.Sh[c][u], q[u], dsq);
-      const float ai = h.rh[c] * wave_sum(dsq);
+      const float ai = h.rh[c] * group_sum<W>(dsq);
       al[c] = ai;
 #pragma unroll
       for (int u = 0; u < PL; ++u) q[u] = fmaf(-ai, h.Yh[c][u], q[u]);
@@ -211,12 +225,12 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
     float sy = 0.0f, yy = 0.0f;
 #pragma unroll
     for (int u = 0; u < PL; ++u) { sy = fmaf(h.Sh[0][u], h.Yh[0][u], sy); yy = fmaf(h.Yh[0][u], h.Yh[0][u], yy); }
-    gamma = wave_sum(sy) / wave_sum(yy);
+    gamma = group_sum<W>(sy) / group_sum<W>(yy);
   } else {
     float gi = 0.0f;
 #pragma unroll
     for (int u = 0; u < PL; ++u) gi = fmaxf(gi, fabsf(gv[u]));
-    gi = -wave_min(-gi);
+    gi = -group_min<W>(-gi);
     gamma = gi > 0.0f ? fminf(1.0f, 0.1f / gi) : 1.0f;
   }
 #pragma unroll
@@ -227,16 +241,17 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
       float dyr = 0.0f;
 #pragma unroll
       for (int u = 0; u < PL; ++u) dyr = fmaf(h.Yh[c][u], q[u], dyr);
-      const float b = h.rh[c] * wave_sum(dyr);
+      const float b = h.rh[c] * group_sum<W>(dyr);
 #pragma unroll
       for (int u = 0; u < PL; ++u) q[u] = fmaf(al[c] - b, h.Sh[c][u], q[u]);
     }
   }
 #pragma unroll
   for (int u = 0; u < PL; ++u) q[u] = -q[u];
-  st_row<PL, V4>(a.dir + base, n, lane, q);
-  st_row<PL, V4>(a.x_prev + base, n, lane, xv);
-  st_row<PL, V4>(a.g_prev + base, n, lane, gv);
+  if (!st_ok) return;
+  st_row<PL, V4, W>(a.dir + base, n, lane, q);
+  st_row<PL, V4, W>(a.x_prev + base, n, lane, xv);
+  st_row<PL, V4, W>(a.g_prev + base, n, lane, gv);
   if (lane == 0) {
     a.meta[2 * s + 0] = count;
     a.meta[2 * s + 1] = head;
@@ -268,10 +283,21 @@ __global__ __launch_bounds__(kWave) void lbfgs_kernel(const LbfgsArgs a) {
 // count padded to 4, 8 or 16, so the candidates' sums run unrolled and
 // overlap.  With FUSED the same wavefront then computes the next L-BFGS
 // direction from the chosen iterate, which is still in its registers.
-template <int PL, int MH, bool FUSED, int KP, bool V4>
+// W < 64 packs 64 / W seeds into a wavefront, W lanes each, for row blocks
+// of at most W floats (inverse kinematics: T = 1); control flow then
+// diverges between the lane groups but never inside one, so every group
+// reduction sees only its own, active, lanes.
+template <int PL, int MH, bool FUSED, int KP, bool V4, int W = kWave>
 __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const LbfgsArgs la) {
-  const int s = blockIdx.x;            // (the grid is exactly one workgroup per seed)
-  const int lane = threadIdx.x;
+  static_assert(KP <= W && kWave % W == 0, "a candidate needs a lane of its seed's group");
+  constexpr int SPW = kWave / W;       // seeds per wavefront
+  const int sub = SPW > 1 ? (int)threadIdx.x / W : 0;
+  const int lane = SPW > 1 ? (int)threadIdx.x % W : (int)threadIdx.x;
+  // (the grid is exactly one workgroup per SPW seeds; the last one's spare
+  // groups take the last seed and store nothing)
+  const int s_raw = (int)blockIdx.x * SPW + sub;
+  const bool st_ok = SPW == 1 || s_raw < a.n_seeds;
+  const int s = SPW == 1 ? s_raw : min(s_raw, a.n_seeds - 1);
   warm_kernargs<sizeof(SelectArgs) + (FUSED ? sizeof(LbfgsArgs) + 8 : 0)>();
   const SeedInfo si = seed_info(a.seeds, a.uniform_T, s);
   const int D = a.dof, n = si.T * D;
@@ -281,28 +307,28 @@ __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const
   // L-BFGS state, the joint limits, and for up to 8 candidates every
   // candidate's gradient
   LbfgsRegs<PL, FUSED ? MH : 1> h;
-  if constexpr (FUSED) lbfgs_load<PL, MH, V4>(la, s, lane, si, h);
+  if constexpr (FUSED) lbfgs_load<PL, MH, V4, W>(la, s, lane, si, h);
   constexpr int KG = (PL <= 4 && KP <= 8) ? KP : 1;
   const bool pre = KG > 1;
   float gall[KG][PL];
 #pragma unroll
   for (int k = 0; k < KG; ++k) {
-    if (pre) ld_row<PL, V4>(a.grad_e + ((size_t)min(k, a.K - 1) * a.rows + si.row0) * D, n, lane, gall[k]);
+    if (pre) ld_row<PL, V4, W>(a.grad_e + ((size_t)min(k, a.K - 1) * a.rows + si.row0) * D, n, lane, gall[k]);
   }
   float qlo[PL], qhi[PL];
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const int j = el_idx<PL, V4>(lane, u) % D;
+    const int j = el_idx<PL, V4, W>(lane, u) % D;
     qlo[u] = a.q_lo[j];
     qhi[u] = a.q_hi[j];
   }
-  const float best_prev = ((cfloat*)a.best_c)[s];
-  const float c0 = ((cfloat*)a.c0)[s];
+  const float best_prev = ld_seed<W>(a.best_c + s);
+  const float c0 = ld_seed<W>(a.c0 + s);
 
   // candidate sums with the lanes split over the candidates: lane kq * G
   // + jq takes waypoints jq, jq + G, ... of candidate kq, then a reduction
   // over its G lanes leaves candidate kq's sums in all of them
-  constexpr int G = kWave / KP;
+  constexpr int G = W / KP;
   const int kq = lane / G, jq = lane % G;
   const bool kin = kq < a.K;
   const size_t erow = (size_t)min(kq, a.K - 1) * a.rows + si.row0;
@@ -316,16 +342,16 @@ __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const
     mq[i] = a.mc_e[e];
   }
   float gdv[PL], xv[PL], dv[PL], g0v[PL];
-  ld_row<PL, V4>(a.x + base, n, lane, xv);
-  ld_row<PL, V4>(a.d + base, n, lane, dv);
-  ld_row<PL, V4>(a.g0 + base, n, lane, g0v);
+  ld_row<PL, V4, W>(a.x + base, n, lane, xv);
+  ld_row<PL, V4, W>(a.d + base, n, lane, dv);
+  ld_row<PL, V4, W>(a.g0 + base, n, lane, g0v);
   float g0d = 0.0f;
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
     gdv[u] = 0.0f;
     g0d = fmaf(g0v[u], dv[u], g0d);
   }
-  g0d = wave_sum(g0d);
+  g0d = group_sum<W>(g0d);
   float cs = 0.0f, gs = 0.0f, ms = 3.0e38f;
 #pragma unroll
   for (int i = 0; i < KP; ++i) {
@@ -345,10 +371,17 @@ __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const
   bool ok = kin && cs <= c0 + a.eta1 * ak * g0d;
   if (a.mode == 1) ok = ok && (gs >= a.eta_w * g0d);
   if (a.mode == 2) ok = ok && (fabsf(gs) <= a.eta_w * fabsf(g0d));
-  const uint64_t okm = __ballot(ok && jq == 0 && kq > 0);
+  uint64_t okm = __ballot(ok && jq == 0 && kq > 0);
+  if constexpr (SPW > 1) okm = (okm >> (sub * W)) & ((1ull << W) - 1);   // this seed's group
   const int best = okm ? (63 - __builtin_clzll(okm)) / G : 0;
-  const float cb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cs), best * G));
-  const float mcb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ms), best * G));
+  float cb, mcb;
+  if constexpr (SPW == 1) {
+    cb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cs), best * G));
+    mcb = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ms), best * G));
+  } else {
+    cb = __shfl(cs, sub * W + best * G);
+    mcb = __shfl(ms, sub * W + best * G);
+  }
   float al = a.alpha[0];
 #pragma unroll
   for (int k = 1; k < KP; ++k) al = best == k ? a.alpha[k] : al;
@@ -359,23 +392,25 @@ __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const
 #pragma unroll
       for (int u = 0; u < PL; ++u) gdv[u] = k == best ? gall[k][u] : gdv[u];
   } else {
-    ld_row<PL, V4>(a.grad_e + ((size_t)best * a.rows + si.row0) * D, n, lane, gdv);
+    ld_row<PL, V4, W>(a.grad_e + ((size_t)best * a.rows + si.row0) * D, n, lane, gdv);
   }
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
-    const int e = el_idx<PL, V4>(lane, u);
+    const int e = el_idx<PL, V4, W>(lane, u);
     xv[u] = e < n ? fminf(fmaxf(fmaf(al, dv[u], xv[u]), qlo[u]), qhi[u]) : 0.0f;
   }
-  st_row<PL, V4>(a.x_out + base, n, lane, xv);
-  st_row<PL, V4>(a.g_out + base, n, lane, gdv);
-  if (improve) st_row<PL, V4>(a.best_x + base, n, lane, xv);
-  if (lane == 0) {
+  if (st_ok) {
+    st_row<PL, V4, W>(a.x_out + base, n, lane, xv);
+    st_row<PL, V4, W>(a.g_out + base, n, lane, gdv);
+    if (improve) st_row<PL, V4, W>(a.best_x + base, n, lane, xv);
+  }
+  if (lane == 0 && st_ok) {
     a.c_out[s] = cb;
     if (a.chosen) a.chosen[s] = best;
     if (a.mc_out) a.mc_out[s] = mcb;
     if (improve) a.best_c[s] = cb;
   }
-  if constexpr (FUSED) lbfgs_finish<PL, MH, V4>(la, s, lane, si, xv, gdv, h);
+  if constexpr (FUSED) lbfgs_finish<PL, MH, V4, W>(la, s, lane, si, xv, gdv, h, st_ok);
 }
 
 // Row blocks move as float4 when every seed's block is a multiple of 4
@@ -387,6 +422,8 @@ inline bool rows_v4(int uniform_T, int dof) { return uniform_T > 0 && (uniform_T
 
 // select_kernel launchers for PL vector elements per lane (one unit each)
 hipError_t launch_select_p1(const SelectArgs& a, const LbfgsArgs* la, hipStream_t s);
+// several seeds per wavefront: row blocks of at most 32 floats
+hipError_t launch_select_packed(const SelectArgs& a, int max_n, const LbfgsArgs* la, hipStream_t s);
 hipError_t launch_select_p2(const SelectArgs& a, const LbfgsArgs* la, hipStream_t s);
 hipError_t launch_select_p4(const SelectArgs& a, const LbfgsArgs* la, hipStream_t s);
 hipError_t launch_select_p8(const SelectArgs& a, const LbfgsArgs* la, hipStream_t s);
