@@ -68,16 +68,29 @@ def assert_cost_close(c, c_ref, what="cost"):
     assert bad.size == 0, f"{what}: {bad.size} seeds off, worst rel {np.max(err / (np.abs(c_ref) + 1e-30)):.3e} at {bad[:5]}"
 
 
+def block_index(blocks):
+    """Row indices of the listed (first, end) blocks, concatenated, and each
+    block's start in that list (for np.add.reduceat; blocks are non-empty)."""
+    lens = np.array([b - a for a, b in blocks], dtype=np.int64)
+    starts = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    firsts = np.array([a for a, _ in blocks], dtype=np.int64)
+    rows = np.repeat(firsts - starts, lens) + np.arange(int(lens.sum()))
+    return rows, starts
+
+
+def block_sums(v, starts):
+    """Per-block sums of the per-row values v."""
+    return np.add.reduceat(v, starts)
+
+
 def assert_grad_close(g, g_ref, batch, what="grad"):
     g, g_ref = np.asarray(g, np.float64), np.asarray(g_ref, np.float64)
-    worst, nbad = 0.0, 0
-    for a, b in seed_blocks(batch):
-        e = np.linalg.norm(g[a:b] - g_ref[a:b])
-        n = np.linalg.norm(g_ref[a:b])
-        worst = max(worst, e / (n + 1e-30))
-        if e > GRAD_RTOL * n + ABS_TOL:
-            nbad += 1
-    assert nbad == 0, f"{what}: {nbad} seed blocks off, worst rel {worst:.3e}"
+    _, starts = block_index(seed_blocks(batch))
+    e = np.sqrt(block_sums(((g - g_ref) ** 2).sum(1), starts))
+    n = np.sqrt(block_sums((g_ref ** 2).sum(1), starts))
+    bad = np.nonzero(e > GRAD_RTOL * n + ABS_TOL)[0]
+    worst = float(np.max(e / (n + 1e-30))) if e.size else 0.0
+    assert bad.size == 0, f"{what}: {bad.size} seed blocks off, worst rel {worst:.3e} at {bad[:5]}"
 
 
 def assert_verdicts(mc, mc_ref):

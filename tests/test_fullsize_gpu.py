@@ -6,7 +6,7 @@ reference's rule fed the reference's candidate values.
 
   cost+adjoint  32 seeds x 32 waypoints x 8 candidates, every layout and the
                 autotuned one (the launch the benchmark times)
-  IK            256 goals x 32 seeds, T = 1, 4 candidates
+  IK            4096 goals x 32 seeds, T = 1, 4 candidates (and the choice)
   uneven        all 64 problems (seeds 4..64, T in {24,32,48}, 5..200 cuboids)
   large         two-arm tree, 500 cuboids, swept: 16 of the 128 seeds, all
                 4 candidates
@@ -54,23 +54,26 @@ def _seed_rows(batch):
 
 
 def _check_candidates(case, cost, gd, grad, mc, ref_k, d_rows, seeds=None):
+    """Per seed block (vectorised over blocks): cost, verdict, gradient and
+    <g, d> of every candidate against the reference's."""
     blocks = _seed_rows(case.batch)
     if seeds is not None:
         blocks = [blocks[s] for s in seeds]
+    rows, starts = H.block_index(blocks)
+    dsel = d_rows[rows]
+    nd = np.sqrt(H.block_sums((dsel ** 2).sum(1), starts))
+    sel = slice(None) if seeds is None else list(seeds)
     for k, (cr, gr, mcr) in enumerate(ref_k):
-        sel = slice(None) if seeds is None else list(seeds)
         H.assert_cost_close(cost[k][sel], cr, f"candidate {k} cost")
         H.assert_verdicts(mc[k][sel], mcr)
-        r0 = 0
-        for i, (a, b) in enumerate(blocks):
-            n = b - a
-            g_ref = gr[r0:r0 + n]
-            r0 += n
-            e = np.linalg.norm(grad[k][a:b] - g_ref)
-            assert e <= H.GRAD_RTOL * np.linalg.norm(g_ref) + H.ABS_TOL, f"candidate {k} block {i}"
-            gd_ref = float(np.sum(g_ref * d_rows[a:b]))
-            tol = H.GRAD_RTOL * np.linalg.norm(g_ref) * np.linalg.norm(d_rows[a:b]) + H.ABS_TOL
-            assert abs(gd[k][sel][i] - gd_ref) <= tol, f"candidate {k} seed {i}: <g,d> {gd[k][sel][i]} vs {gd_ref}"
+        gk = grad[k][rows].astype(np.float64)
+        e = np.sqrt(H.block_sums(((gk - gr) ** 2).sum(1), starts))
+        n = np.sqrt(H.block_sums((gr ** 2).sum(1), starts))
+        bad = np.nonzero(e > H.GRAD_RTOL * n + H.ABS_TOL)[0]
+        assert bad.size == 0, f"candidate {k}: gradient blocks {bad[:5]} off"
+        gd_ref = H.block_sums((gr * dsel).sum(1), starts)
+        bad = np.nonzero(np.abs(gd[k][sel] - gd_ref) > H.GRAD_RTOL * n * nd + H.ABS_TOL)[0]
+        assert bad.size == 0, f"candidate {k}: <g,d> of seeds {bad[:5]} off"
 
 
 def _gpu_candidates(case, dd, alpha):
@@ -103,22 +106,24 @@ def _check_choice(case, alpha, mode, dd, d_rows, ref_k, seeds):
             g0r[s * T:(s + 1) * T] = g_sub.reshape(-1, case.robot.dof)[i * T:(i + 1) * T]
     else:
         c0r, g0r, _ = H.oracle_cost_grad(case.ref, case.worlds, case.batch, x_rows)
+    rows, starts = H.block_index([blocks[s] for s in seeds])
+    ds = d_rows[rows]
+    dn = np.sqrt(H.block_sums((ds ** 2).sum(1), starts))
+    g0d = H.block_sums((g0r[rows] * ds).sum(1), starts)
+    K = len(alpha)
+    ck = np.stack([np.asarray(ref_k[k][0], np.float64) for k in range(K)], 1)
+    gdk = np.stack([H.block_sums((ref_k[k][1] * ds).sum(1), starts) for k in range(K)], 1)
+    gn = np.stack([np.sqrt(H.block_sums((ref_k[k][1] ** 2).sum(1), starts)) for k in range(K)], 1)
     n_diff = 0
     for i, s in enumerate(seeds):
-        a, b = blocks[s]
-        g0d = float(np.sum(g0r[a:b] * d_rows[a:b]))
-        ck = [float(ref_k[k][0][i]) for k in range(len(alpha))]
-        r0 = sum(blocks[u][1] - blocks[u][0] for u in seeds[:i])
-        gk = [ref_k[k][1][r0:r0 + b - a] for k in range(len(alpha))]
-        gdk = [float(np.sum(g * d_rows[a:b])) for g in gk]
-        want = ref.ls_select(alpha, float(c0r[s]), g0d, ck, gdk, mode)
+        want = ref.ls_select(alpha, float(c0r[s]), float(g0d[i]), ck[i], gdk[i], mode)
         got = int(ch[s])
         if got == want:
             continue
         n_diff += 1
         k = max(got, want)
-        arm = abs(ck[k] - (c0r[s] + ref.ETA1 * alpha[k] * g0d)) <= 1e-4 * abs(c0r[s]) + 1e-6
-        wolfe = abs(gdk[k] - ref.ETA_W * g0d) <= 1e-3 * np.linalg.norm(gk[k]) * np.linalg.norm(d_rows[a:b]) + 1e-6
+        arm = abs(ck[i, k] - (c0r[s] + ref.ETA1 * alpha[k] * g0d[i])) <= 1e-4 * abs(c0r[s]) + 1e-6
+        wolfe = abs(gdk[i, k] - ref.ETA_W * g0d[i]) <= 1e-3 * gn[i, k] * dn[i] + 1e-6
         assert arm or (mode > 0 and wolfe), f"seed {s}: gpu chose {got}, reference {want}"
     assert n_diff <= max(1, len(seeds) // 16)
 
@@ -145,8 +150,9 @@ def test_cost_adjoint_every_candidate(layout):
 
 
 def test_ik_every_seed_and_candidate():
-    """256 goals x 32 seeds at T = 1 (8192 rows), 4 candidates."""
-    robot, worlds, batch, meta = wl.cfg_ik(n_goals=256, n_seeds=32)
+    """4096 goals x 32 seeds at T = 1 (131,072 rows), 4 candidates, and
+    the line-search choice of every seed."""
+    robot, worlds, batch, meta = wl.cfg_ik()
     case = Case(robot, worlds, batch)
     c, g, mc = (t.cpu().numpy() for t in case.ctx.mg_cost_grad(case.b, case.q_start, case.goal, case.x))
     x = case.batch.x0.reshape(-1, 7)
@@ -155,8 +161,11 @@ def test_ik_every_seed_and_candidate():
     H.assert_grad_close(g, gr, case.batch)
     H.assert_verdicts(mc, mcr)
     d = _direction(case, 0.1, 1)
-    cost, gd, gk, mck = _gpu_candidates(case, _dev(d), meta["alpha"])
-    _check_candidates(case, cost, gd, gk, mck, _oracle_candidates(case, x, d, meta["alpha"]), d)
+    dd = _dev(d)
+    cost, gd, gk, mck = _gpu_candidates(case, dd, meta["alpha"])
+    ref_k = _oracle_candidates(case, x, d, meta["alpha"])
+    _check_candidates(case, cost, gd, gk, mck, ref_k, d)
+    _check_choice(case, meta["alpha"], 1, dd, d, ref_k, list(range(case.batch.x0.size // 7)))
 
 
 def test_uneven_all_problems():
