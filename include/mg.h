@@ -275,6 +275,20 @@ mg_status mg_ee_pose(mg_ctx *ctx, int rows, const float *q, float *pose, void *s
  * Overwrites the batch's evaluation workspaces; not capturable.  With
  * swept collision the lane-per-link layout takes one slice. */
 mg_status mg_batch_set_layout(mg_batch *batch, int layout, int slices);
+
+/* Choice folded into the next evaluation (Alg.1 and Alg.6 inside the
+ * iteration loop of Sec. "Parallel L-BFGS Optimization"): with enable != 0
+ * (the default) mg_solve computes each iteration's line-search choice and
+ * next L-BFGS direction at the start of the following iteration's
+ * evaluation launch (every workgroup for its own seed, the seed's first one
+ * storing them) instead of in a launch of its own, where the batch
+ * qualifies: wave-per-link layout with one or two slot groups and at most 7
+ * links, no swept collision or speed metric, one horizon T with T * D <= 256
+ * and a multiple of 4, K <= 8, m <= 4, and x 16-byte aligned.  The results
+ * are those of the separate launches.  enable = 0 keeps the launches
+ * separate.  Host-only; affects later calls.  Errors: MG_ERR_ARG (null
+ * batch). */
+mg_status mg_batch_set_fusion(mg_batch *batch, int enable);
 mg_status mg_autotune(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
                       const float *x, const float *dir, int K, const float *alpha, int launches,
                       int *slices_out, void *stream);

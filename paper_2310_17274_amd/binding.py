@@ -75,6 +75,11 @@ class Batch:
         for layout 1 also 8 or 16; layouts 2, 3 and 4: 0 or 1)."""
         _lib.check(_lib.lib().mg_batch_set_layout(self.handle, int(layout), int(slices)))
 
+    def mg_batch_set_fusion(self, enable: bool):
+        """Fold each line-search choice of mg_solve into the next evaluation
+        launch where the batch qualifies (default on)."""
+        _lib.check(_lib.lib().mg_batch_set_fusion(self.handle, int(bool(enable))))
+
     def mg_batch_reserve_particles(self, n_particles: int):
         _lib.check(_lib.lib().mg_batch_reserve_particles(self.handle, int(n_particles)))
 

@@ -127,6 +127,14 @@ struct mg_batch {
   int* first = nullptr;
   float *S = nullptr, *Y = nullptr, *x_prev = nullptr, *g_prev = nullptr, *rho = nullptr;
   int* meta = nullptr;
+  // the solver's second set of state (iterate, cost, gradient, direction,
+  // history count/head, evaluation outputs) for iterations whose choice is
+  // folded into the next evaluation launch: launch i reads one set and
+  // writes the other
+  float *fs_x = nullptr, *fs_c = nullptr, *fs_g = nullptr, *fs_dir = nullptr;
+  float *fs_cost_e = nullptr, *fs_gd_e = nullptr, *fs_mc_e = nullptr, *fs_grad_e = nullptr;
+  int* fs_meta = nullptr;
+  bool fusion = true;   // mg_batch_set_fusion
   // cached solver graph and the arguments it was captured with
   hipGraphExec_t gexec = nullptr;
   std::vector<char> gkey;
@@ -516,7 +524,7 @@ int wl_slices(const mg_batch* b, int K) {
 // slices_ok = false keeps the wave-per-link layout at one workgroup per
 // chunk (no slice scratch or arrival counters of the batch).
 hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool grad, hipStream_t s,
-                         bool slices_ok = true) {
+                         bool slices_ok = true, const mg::SelFuse* fs = nullptr) {
   if (use_wl(b, a.K)) {
     a.wl.part = b->wl_part;
     a.wl.count = b->wl_count;
@@ -531,8 +539,9 @@ hipError_t launch_layout(mg_batch* b, mg::EvalArgs a, int hi, bool cand, bool gr
     wl_single(b, a.K, a.wl);
     // (the speed's gradient terms need every cuboid of a sphere in one workgroup)
     const int wls = (halves == 2 || groups > 1 || !slices_ok || (a.sp_h && grad)) ? 1 : wl_slices(b, a.K);
-    return mg::launch_eval_wl(a, b->chunks_wl[a.K][groups_index(groups)], wls, cand, grad, s);
+    return mg::launch_eval_wl(a, b->chunks_wl[a.K][groups_index(groups)], wls, cand, grad, s, fs);
   }
+  if (fs) return hipErrorInvalidValue;
   return mg::launch_eval(a, b->chunks[hi], cand, grad, s);
 }
 
@@ -659,6 +668,34 @@ mg_status enqueue_lbfgs(mg_ctx* c, mg_batch* b, int m, int reset, const float* x
   const mg::LbfgsArgs a = lbfgs_args(c, b, m, reset, x, g, dir, first);
   HIP_TRY(mg::launch_lbfgs(a, b->max_n, s));
   return MG_OK;
+}
+
+// The solver folds each line-search choice into the next evaluation launch
+// when the batch's layout and shapes allow it (the conditions of
+// launch_eval_wl's fs path): wave per link with one or two slot groups and
+// no link passes, no swept collision or speed metric, one horizon with
+// blocks of at most 256 floats (a multiple of 4), at most 8 candidates and
+// 4 history pairs, and workgroup chunks inside one seed.
+bool fuse_ok(const mg_ctx* c, const mg_batch* b, int K, int m, const float* x) {
+  if (!b->fusion || !use_wl(b, K) || c->params.swept || c->params.speed) return false;
+  const int groups = b->wl_groups > 1 && wl_groups_possible(c, b->wl_groups) ? b->wl_groups : 1;
+  const int halves = groups > 1 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(c) ? 2 : 1));
+  if (groups > 2 || halves != 1 || c->L + 1 > 8 || c->maxs / groups > 8) return false;
+  const int T = b->uniform_T, E = mg::kWave / groups, n = T * c->D;
+  return T > 0 && n <= 4 * mg::kWave && n % 4 == 0 && K <= 8 && E % K == 0 && T % (E / K) == 0 && m >= 1 &&
+         m <= 4 && ((uintptr_t)x & 15) == 0;
+}
+
+// The two sets of solver state: set 0 is the caller's x and the batch's
+// usual buffers, set 1 the fs_ ones.
+struct StateSet {
+  float *x, *c, *g, *dir, *cost_e, *gd_e, *mc_e, *grad_e;
+  int* meta;
+};
+StateSet state_set(mg_batch* b, float* x, int i) {
+  if (i == 0) return StateSet{x, b->c_cur, b->g_cur, b->dir, b->cost_e, b->gd_e, b->mc_e, b->grad_e, b->meta};
+  return StateSet{b->fs_x, b->fs_c, b->fs_g, b->fs_dir, b->fs_cost_e, b->fs_gd_e, b->fs_mc_e, b->fs_grad_e,
+                  b->fs_meta};
 }
 
 mg_status check_K_alpha(const mg_batch* b, int K, const float* alpha) {
@@ -937,6 +974,12 @@ mg_status mg_batch_create(mg_ctx* c, int P, const int* seeds, const int* horizon
       (st = dev_alloc(&b->meta, 2 * n_seeds)) != MG_OK || (st = dev_alloc(&b->sel_dt, n_seeds)) != MG_OK ||
       (st = dev_alloc(&b->sel_jerk, n_seeds)) != MG_OK)
     return bail(st);
+  if ((st = dev_alloc(&b->fs_x, RD)) != MG_OK || (st = dev_alloc(&b->fs_c, n_seeds)) != MG_OK ||
+      (st = dev_alloc(&b->fs_g, RD)) != MG_OK || (st = dev_alloc(&b->fs_dir, RD)) != MG_OK ||
+      (st = dev_alloc(&b->fs_meta, 2 * n_seeds)) != MG_OK || (st = dev_alloc(&b->fs_cost_e, KR)) != MG_OK ||
+      (st = dev_alloc(&b->fs_gd_e, KR)) != MG_OK || (st = dev_alloc(&b->fs_mc_e, KR)) != MG_OK ||
+      (st = dev_alloc(&b->fs_grad_e, KR * c->D)) != MG_OK)
+    return bail(st);
   if ((st = ensure_speed_buf(b)) != MG_OK) return bail(st);
   // zero the history metadata so a first step without reset is well defined
   if (hipMemset(b->meta, 0, 2 * n_seeds * sizeof(int)) != hipSuccess ||
@@ -967,6 +1010,8 @@ void mg_batch_destroy(mg_batch* b) {
   dev_free(b->first); dev_free(b->S); dev_free(b->Y); dev_free(b->x_prev); dev_free(b->g_prev);
   dev_free(b->rho); dev_free(b->meta); dev_free(b->p_cost); dev_free(b->sel_dt);
   dev_free(b->sel_jerk);
+  dev_free(b->fs_x); dev_free(b->fs_c); dev_free(b->fs_g); dev_free(b->fs_dir); dev_free(b->fs_meta);
+  dev_free(b->fs_cost_e); dev_free(b->fs_gd_e); dev_free(b->fs_mc_e); dev_free(b->fs_grad_e);
   dev_free(b->wl_part); dev_free(b->wl_count); dev_free(b->sp_h);
   delete b;
 }
@@ -1432,6 +1477,50 @@ mg_status enqueue_iteration(mg_ctx* c, mg_batch* b, const float* q_start, const 
                         nullptr, nullptr, true, &la, s);
 }
 
+// One iteration with the previous choice folded in: the launch reads state
+// set `cur` (the last iterate, its candidates' costs and gradients) and
+// writes set 1 - cur (the chosen iterate, its cost and gradient, the next
+// direction and this iteration's candidates).
+mg_status enqueue_fused_iteration(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* x,
+                                  int m, int K, const float* alpha, int mode, int cur, hipStream_t s) {
+  const StateSet a0 = state_set(b, x, cur), a1 = state_set(b, x, 1 - cur);
+  mg::SelFuse f;
+  memset(&f, 0, sizeof(f));
+  mg::SelectArgs& sa = f.sa;
+  sa.seeds = b->d_seed;
+  sa.uniform_T = b->uniform_T;
+  sa.n_seeds = b->n_seeds;
+  sa.rows = b->rows;
+  sa.dof = c->D;
+  sa.K = K;
+  sa.mode = mode;
+  for (int k = 0; k < K; ++k) sa.alpha[k] = alpha[k];
+  sa.eta1 = c->params.ls_eta1;
+  sa.eta_w = c->params.ls_eta_w;
+  sa.q_lo = c->d_q_lo;
+  sa.q_hi = c->d_q_hi;
+  sa.x = a0.x; sa.c0 = a0.c; sa.g0 = a0.g; sa.d = a0.dir;
+  sa.cost_e = a0.cost_e; sa.gd_e = a0.gd_e; sa.mc_e = a0.mc_e; sa.grad_e = a0.grad_e;
+  sa.x_out = a1.x; sa.c_out = a1.c; sa.g_out = a1.g;
+  sa.track = 1;
+  sa.best_c = b->best_c;
+  sa.best_x = b->best_x;
+  // (the previous iterate and gradient are the set being read)
+  mg::LbfgsArgs& la = f.la;
+  la = lbfgs_args(c, b, m, 0, a0.x, a0.g, a1.dir, nullptr);
+  la.x_prev = a0.x;
+  la.g_prev = a0.g;
+  la.keep_prev = 1;
+  la.meta = a0.meta;
+  la.meta_out = a1.meta;
+  const int hi = pick_slices(b, (long)b->rows * K);
+  mg::EvalArgs ea = eval_args(c, b, hi, q_start, goal, a1.x, a1.dir, K, alpha);
+  ea.cost_e = a1.cost_e; ea.gd_e = a1.gd_e; ea.mc_e = a1.mc_e; ea.grad_e = a1.grad_e;
+  ea.pe_e = nullptr;
+  HIP_TRY(launch_layout(b, ea, hi, true, true, s, true, &f));
+  return MG_OK;
+}
+
 template <typename T>
 void key_push(std::vector<char>& k, const T& v) {
   const char* p = reinterpret_cast<const char*>(&v);
@@ -1440,7 +1529,67 @@ void key_push(std::vector<char>& k, const T& v) {
 
 }  // namespace
 
+namespace {
+
+// The solve's iterations with each choice folded into the next evaluation
+// launch (fuse_ok): iteration 0 evaluates the first direction's candidates,
+// iterations 1 .. iters - 1 each choose the previous step and evaluate the
+// next one in one launch (alternating the two state sets; a graph replays
+// an even number of them, so every replay starts from set 0), and the last
+// choice runs alone.  The same arithmetic as the separate launches, so the
+// same results.
+mg_status solve_fused(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* x, int iters,
+                      int m, int K, const float* alpha, int mode, int graph_inner, int use_graph, hipStream_t s) {
+  if (iters < 1) return MG_OK;
+  mg_status st;
+  if ((st = enqueue_eval(c, b, q_start, goal, x, b->dir, K, alpha, true, nullptr, nullptr, s)) != MG_OK) return st;
+  int i = 1;
+  const int gi = graph_inner + (graph_inner & 1);
+  if (use_graph && iters - 1 >= gi) {
+    std::vector<char> key;
+    key_push(key, 1); key_push(key, q_start); key_push(key, goal); key_push(key, x); key_push(key, m);
+    key_push(key, K); key_push(key, mode); key_push(key, gi); key_push(key, c->params);
+    key_push(key, c->d_box); key_push(key, c->d_world_off); key_push(key, b->slices);
+    key_push(key, b->layout); key_push(key, b->wl_slices); key_push(key, c->n_self);
+    key_push(key, b->wl_halves); key_push(key, b->wl_groups);
+    for (int v : c->world_off) key_push(key, v);
+    for (int k = 0; k < K; ++k) key_push(key, alpha[k]);
+    if (!b->gexec || key != b->gkey) {
+      if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+      HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      mg_status cst = MG_OK;
+      for (int j = 0; j < gi && cst == MG_OK; ++j)
+        cst = enqueue_fused_iteration(c, b, q_start, goal, x, m, K, alpha, mode, j & 1, c->cap_stream);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+      if (cst != MG_OK) { if (graph) (void)hipGraphDestroy(graph); return cst; }
+      if (e != hipSuccess) return fail(MG_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) { b->gexec = nullptr; return fail(MG_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e)); }
+      b->gkey = key;
+    }
+    for (; i + gi <= iters; i += gi) HIP_TRY(hipGraphLaunch(b->gexec, s));
+  }
+  for (; i < iters; ++i)
+    if ((st = enqueue_fused_iteration(c, b, q_start, goal, x, m, K, alpha, mode, (i - 1) & 1, s)) != MG_OK)
+      return st;
+  const int cur = (iters - 1) & 1;
+  const StateSet a0 = state_set(b, x, cur), a1 = state_set(b, x, 1 - cur);
+  const EvalOut eo{a0.cost_e, a0.gd_e, a0.mc_e, a0.grad_e};
+  return enqueue_select(c, b, a0.x, a0.c, a0.g, a0.dir, K, alpha, mode, a1.x, a1.c, a1.g, nullptr, nullptr, true,
+                        nullptr, s, &eo);
+}
+
+}  // namespace
+
 extern "C" {
+
+mg_status mg_batch_set_fusion(mg_batch* b, int enable) {
+  if (!b) return fail(MG_ERR_ARG, "null batch");
+  b->fusion = enable != 0;
+  return MG_OK;
+}
 
 mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* x,
                    int iters, int m, int K, const float* alpha, int mode, int graph_inner,
@@ -1465,9 +1614,15 @@ mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* go
   HIP_TRY(mg::launch_fill_i32(b->first, 1, b->n_seeds, s));
   if ((st = enqueue_lbfgs(c, b, m, 1, x, b->g_cur, b->dir, b->first, s)) != MG_OK) return st;
 
+  if (fuse_ok(c, b, K, m, x)) {
+    if ((st = solve_fused(c, b, q_start, goal, x, iters, m, K, alpha, mode, graph_inner, use_graph, s)) != MG_OK)
+      return st;
+    iters = 0;
+  }
   int done = 0;
   if (use_graph && iters >= graph_inner) {
     std::vector<char> key;
+    key_push(key, 0);
     key_push(key, q_start); key_push(key, goal); key_push(key, x); key_push(key, m); key_push(key, K);
     key_push(key, mode); key_push(key, graph_inner); key_push(key, c->params);
     key_push(key, c->d_box); key_push(key, c->d_world_off); key_push(key, b->slices);

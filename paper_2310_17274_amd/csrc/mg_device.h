@@ -90,10 +90,12 @@ __device__ __forceinline__ float group_min(float v) {
 // the branches and waits before it, which chains round trips.  Touching
 // every 64-byte line of the argument block at once at the start brings it
 // all into the scalar cache in one round trip.
-template <int BYTES>
+// (OFF: the range starts OFF bytes into the block, a multiple of 4)
+template <int BYTES, int OFF = 0>
 __device__ __forceinline__ void warm_kernargs() {
   static_assert(BYTES <= 512, "one load per line, at most 8 lines");
-  const cint* kp = (const cint*)__builtin_amdgcn_kernarg_segment_ptr();
+  static_assert(OFF % 4 == 0, "dword aligned");
+  const cint* kp = (const cint*)__builtin_amdgcn_kernarg_segment_ptr() + OFF / 4;
   constexpr int last = (BYTES - 4) / 4;
   const int v0 = kp[0], v1 = kp[16 < last ? 16 : last], v2 = kp[32 < last ? 32 : last];
   const int v3 = kp[48 < last ? 48 : last], v4 = kp[64 < last ? 64 : last], v5 = kp[80 < last ? 80 : last];

@@ -33,6 +33,7 @@
 #pragma once
 
 #include "mg_eval.h"
+#include "mg_solver.h"
 
 namespace mg {
 namespace {
@@ -322,8 +323,17 @@ __device__ __forceinline__ float groups_min(float v) {
 // LP: link passes (HS = 1, more links than link waves); without it the
 // pass loop runs once and compiles away (the register budget of the
 // one-pass kernel stays what it was).
-template <int MAXS, bool CAND, bool GRAD, int NT, int G, bool SW, bool SP, bool LP>
-__global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
+struct NoFuse {};
+
+// FS > 0 (cost and gradient of candidates, link waves alone, no swept
+// collision or speed metric): the previous iteration's line-search choice
+// and next L-BFGS direction (FA = SelFuse) are computed first, by the joint
+// wave while the others stage, for the seed of the workgroup's rows (whose
+// chunk lies within one seed); the new iterate and direction become the
+// staged rows.  FS is the candidate count padded to 4 or 8.
+template <int MAXS, bool CAND, bool GRAD, int NT, int G, bool SW, bool SP, bool LP, int FS, typename FA>
+__device__ __forceinline__ void eval_wl_body(const EvalArgs& a, const FA& fa) {
+  static_assert(FS == 0 || (CAND && GRAD && !SW && !SP && !LP), "the choice folds into line-search evaluations");
   constexpr int E = kWave / G;
   extern __shared__ float s_mem[];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -346,6 +356,7 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   const int W = HS == 2 ? 2 * L : LW + 1;
   const int npass = LP ? (L + LW - 1) / LW : 1;
   const bool joint_w = HS == 1 && wave == W - 1;
+  const bool sel_w = FS > 0 && joint_w;    // (the joint wave computes the choice)
 
   // ---- everything is read from memory in two dependent rounds: the
   //      chunk's record and this wave's tables (scalar loads), then the
@@ -411,12 +422,12 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   {
     // scalars: rows of x (and d, or var), limits, start, goals, tool
     // transforms, and in particle mode each lane's draws over the rows
-    const int nxd = CAND ? 2 * n_st : n_st;
+    const int nxd = FS > 0 ? 0 : (CAND ? 2 * n_st : n_st);
     const int n_eps = pm && a.d ? min(r_hi - r_lo + 1, pm_rows) * E * D : 0;
     const int nf = nxd + 3 * D + n_ee * 19 + n_eps;
     const float* dsrc = pm ? a.var : a.d;
     auto fsrc = [&](int i, float*& dst) -> const float* {
-      if (i < n_st) { dst = s_x + i; return a.x + (size_t)r_lo * D + i; }
+      if (i < (FS > 0 ? 0 : n_st)) { dst = s_x + i; return a.x + (size_t)r_lo * D + i; }
       if (i < nxd) { dst = s_d + (i - n_st); return dsrc + (size_t)r_lo * D + (i - n_st); }
       i -= nxd;
       if (i < n_eps) {
@@ -449,9 +460,11 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
       if (i < nch + nsl) return a.wl.sphere + (i - nch);
       return reinterpret_cast<const float4*>(a.box + w0) + (i - nch - nsl);
     };
-    // every load of a pass is issued before its LDS stores
-    for (int b0 = 0; b0 < nf || b0 < n4; b0 += 2 * nthreads) {
-      const int i0 = b0 + tid, i1 = i0 + nthreads;
+    // every load of a pass is issued before its LDS stores (with FS the
+    // joint wave stages nothing: it is the last wave)
+    const int st_n = FS > 0 ? nthreads - kWave : nthreads;
+    for (int b0 = 0; !sel_w && (b0 < nf || b0 < n4); b0 += 2 * st_n) {
+      const int i0 = b0 + tid, i1 = i0 + st_n;
       float* d0 = nullptr;
       float* d1 = nullptr;
       const float v0 = i0 < nf ? *fsrc(i0, d0) : 0.0f;
@@ -481,6 +494,28 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
           if (e < e_lo || e >= e_hi) continue;
           const int rr = (int)((e - e_lo) / D), j = (int)(e - e_lo - (long long)rr * D);
           s_eps[(rr * E + ee) * D + j] = w4[u];
+        }
+      }
+    }
+    if constexpr (FS > 0) {
+      if (sel_w) {
+        constexpr int off = (int)((sizeof(EvalArgs) + alignof(SelFuse) - 1) / alignof(SelFuse) * alignof(SelFuse));
+        static_assert(sizeof(SelFuse) <= 512, "the choice's arguments fit one warm-up");
+        warm_kernargs<(int)sizeof(SelFuse), off>();
+        const int T = pb.T;
+        const int rl0 = e_first / K;                  // (the chunk's first row in its problem)
+        const int srow0 = pb.row0 + rl0 - rl0 % T;    // the seed's first row
+        const bool writer = rl0 % T == 0 && h == 0;   // the seed's first workgroup stores
+        float xo[4], qo[4];
+        select_seed<4, 4, true, FS, true, kWave>(fa.sa, fa.la, srow0 / T, lane, 0, writer, xo, qo);
+        const int n = T * D, sh = (r_lo - srow0) * D;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = lane * 4 + u, i = e - sh;
+          if (e < n && i >= 0 && i < n_st) {
+            s_x[i] = xo[u];
+            s_d[i] = qo[u];
+          }
         }
       }
     }
@@ -994,22 +1029,41 @@ __global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
   }
 }
 
+template <int MAXS, bool CAND, bool GRAD, int NT, int G, bool SW, bool SP, bool LP>
+__global__ __launch_bounds__(NT) void eval_wl_kernel(const EvalArgs a) {
+  eval_wl_body<MAXS, CAND, GRAD, NT, G, SW, SP, LP, 0>(a, NoFuse{});
+}
+
+template <int MAXS, int G, int FS>
+__global__ __launch_bounds__(512) void eval_wl_fs_kernel(const EvalArgs a, const SelFuse f) {
+  eval_wl_body<MAXS, true, true, 512, G, false, false, false, FS>(a, f);
+}
+
 // Launch one instantiation; more than 64 KB of LDS needs the kernel's
 // dynamic-LDS limit raised first.
-template <typename KF>
-hipError_t wl_launch(KF kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, const EvalArgs& a) {
+template <typename KF, typename... Args>
+hipError_t wl_launch(KF kern, dim3 grid, dim3 block, size_t lds, hipStream_t s, const Args&... args) {
   if (lds > 64 * 1024) {
     const hipError_t e =
         hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  kern<<<grid, block, lds, s>>>(a);
+  kern<<<grid, block, lds, s>>>(args...);
   return hipGetLastError();
 }
 
 template <int MAXS, int G, bool SW, bool SP>
 hipError_t wl_pick(const EvalArgs& a, dim3 grid, dim3 block, size_t lds, int waves, bool cand, bool grad,
-                   hipStream_t s) {
+                   hipStream_t s, const SelFuse* fs) {
+  if (fs) {
+    if constexpr (MAXS <= 8 && G <= 2 && !SW && !SP) {
+      if (a.wl.halves != 1 || a.wl.link_waves < a.rb.n_links || waves > 8 || !cand || !grad)
+        return hipErrorInvalidValue;
+      if (fs->sa.K <= 4) return wl_launch(eval_wl_fs_kernel<MAXS, G, 4>, grid, block, lds, s, a, *fs);
+      return wl_launch(eval_wl_fs_kernel<MAXS, G, 8>, grid, block, lds, s, a, *fs);
+    }
+    return hipErrorInvalidValue;
+  }
   if (a.wl.halves == 1 && a.wl.link_waves < a.rb.n_links) {
     // link passes: at most 8 waves by construction
     if (waves > 8) return hipErrorInvalidValue;
@@ -1031,7 +1085,8 @@ hipError_t wl_pick(const EvalArgs& a, dim3 grid, dim3 block, size_t lds, int wav
 }
 
 template <int MAXS, int G>
-hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s) {
+hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s,
+                            const SelFuse* fs) {
   const int HS = a.wl.halves;
   const int L = a.rb.n_links;
   const int LW = a.wl.link_waves;
@@ -1053,12 +1108,22 @@ hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand
   const size_t lds = wl_lds_bytes(a.rb.n_links, a.rb.dof, a.wl.max_depth, a.rb.n_spheres, a.pr.n_self > 0, HS,
                                   a.wl.maxs, kWave / G, pm ? a.wl.pm_rows : 0);
   if (lds > kWlLdsMax) return hipErrorInvalidValue;
+  if (fs) {
+    // the choice: uniform horizons, blocks of at most 256 floats moved as
+    // float4, at most 8 candidates and 4 history pairs, and every chunk of
+    // E / K rows inside one seed
+    const SelectArgs& sa = fs->sa;
+    const int T = sa.uniform_T, E = kWave / G, n = T * a.rb.dof;
+    if (T < 1 || n > 4 * kWave || n % 4 || sa.K != a.K || sa.K > 8 || E % sa.K || T % (E / sa.K) ||
+        fs->la.m > 4 || fs->la.use_first || !fs->la.keep_prev || !fs->la.meta_out)
+      return hipErrorInvalidValue;
+  }
   const dim3 grid(grid_x, slices), block(waves * kWave);
   // SW: poses at the neighbouring waypoints (swept collision, the speed
   // metric); SP: the speed metric
-  if (a.pr.speed) return wl_pick<MAXS, G, true, true>(a, grid, block, lds, waves, cand, grad, s);
-  if (a.pr.swept) return wl_pick<MAXS, G, true, false>(a, grid, block, lds, waves, cand, grad, s);
-  return wl_pick<MAXS, G, false, false>(a, grid, block, lds, waves, cand, grad, s);
+  if (a.pr.speed) return wl_pick<MAXS, G, true, true>(a, grid, block, lds, waves, cand, grad, s, fs);
+  if (a.pr.swept) return wl_pick<MAXS, G, true, false>(a, grid, block, lds, waves, cand, grad, s, fs);
+  return wl_pick<MAXS, G, false, false>(a, grid, block, lds, waves, cand, grad, s, fs);
 }
 
 }  // namespace
@@ -1067,7 +1132,7 @@ hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand
 // compile in parallel: mg_eval_wl_s<MAXS>g<G>.hip.
 #define MG_WL_LAUNCHER(S, G)                                                                         \
   hipError_t launch_eval_wl_s##S##g##G(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, \
-                                       hipStream_t s)
+                                       hipStream_t s, const SelFuse* fs)
 MG_WL_LAUNCHER(2, 1);
 MG_WL_LAUNCHER(4, 1);
 MG_WL_LAUNCHER(8, 1);

@@ -3,5 +3,5 @@
 #include "mg_eval_wl.h"
 
 namespace mg {
-MG_WL_LAUNCHER(2, 4) { return launch_eval_wl_g<2, 4>(a, grid_x, slices, cand, grad, s); }
+MG_WL_LAUNCHER(2, 4) { return launch_eval_wl_g<2, 4>(a, grid_x, slices, cand, grad, s, fs); }
 }  // namespace mg

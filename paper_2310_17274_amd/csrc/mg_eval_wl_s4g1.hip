@@ -3,5 +3,5 @@
 #include "mg_eval_wl.h"
 
 namespace mg {
-MG_WL_LAUNCHER(4, 1) { return launch_eval_wl_g<4, 1>(a, grid_x, slices, cand, grad, s); }
+MG_WL_LAUNCHER(4, 1) { return launch_eval_wl_g<4, 1>(a, grid_x, slices, cand, grad, s, fs); }
 }  // namespace mg

@@ -294,6 +294,22 @@ struct LbfgsArgs {
   int use_first;           // first[] is honoured (and cleared)
   int* first;              // [seeds] (read even when not used): 1 forces a reset for that seed
   int m_max;
+  // the choice folded into the next evaluation launch: meta is read from
+  // meta and written to meta_out (null: meta), and with keep_prev x_prev /
+  // g_prev are only read (they are the iterate and gradient the choice
+  // started from, which other workgroups of the launch still read)
+  int* meta_out;
+  int keep_prev;
+};
+
+// The line-search choice of the previous iteration and the next L-BFGS
+// direction, computed at the start of an evaluation launch of the solve
+// (every workgroup of a seed computes them; the seed's first workgroup
+// stores them).  sa / la read one set of the solver's state and write the
+// other.
+struct SelFuse {
+  SelectArgs sa;
+  LbfgsArgs la;
 };
 
 // Particle stage update (Eq.(12)-(13)) of every seed after its particles
@@ -412,7 +428,11 @@ struct FinalArgs {
 hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipStream_t s);
 // wave-per-link layout: grid_x workgroups of 64 evaluations (chunk_prefix
 // counts 64-evaluation chunks of rows x K per problem)
-hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s);
+// fs (or null): the previous choice folded into this launch (cost and
+// gradient of candidates, the wave-per-link layout with one or two slot
+// groups, link waves alone, no swept collision or speed metric)
+hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s,
+                          const SelFuse* fs = nullptr);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_speed_adjoint(const SpeedAdjArgs& a, hipStream_t s);
 // fuse (optional): compute the next L-BFGS direction from the chosen iterate

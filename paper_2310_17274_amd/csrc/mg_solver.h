@@ -154,12 +154,13 @@ __device__ __forceinline__ void lbfgs_load(const LbfgsArgs& a, int s, int lane, 
 // n = T*D <= 64*PL): stores the last step's pair in the ring when its
 // curvature passes the guard, runs the two loops on registers and DPP sums,
 // and writes dir and x/g_prev.
-// (st_ok false: a lane group that only pads the last wavefront computes
-// but stores nothing)
+// (st_ok false: a lane group that only pads the last wavefront, or a
+// workgroup that is not its seed's first, computes but stores nothing;
+// q_out, or null, receives the direction)
 template <int PL, int MH, bool V4, int W = kWave>
 __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane, const SeedInfo& si,
                                              const float* xv, const float* gv, LbfgsRegs<PL, MH>& h,
-                                             bool st_ok = true) {
+                                             bool st_ok = true, float* q_out = nullptr) {
   const int n = si.T * a.dof;
   const size_t base = (size_t)si.row0 * a.dof;
   const size_t stride = (size_t)a.rows * a.dof;
@@ -248,13 +249,20 @@ __device__ __forceinline__ void lbfgs_finish(const LbfgsArgs& a, int s, int lane
   }
 #pragma unroll
   for (int u = 0; u < PL; ++u) q[u] = -q[u];
+  if (q_out) {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) q_out[u] = q[u];
+  }
   if (!st_ok) return;
   st_row<PL, V4, W>(a.dir + base, n, lane, q);
-  st_row<PL, V4, W>(a.x_prev + base, n, lane, xv);
-  st_row<PL, V4, W>(a.g_prev + base, n, lane, gv);
+  if (!a.keep_prev) {
+    st_row<PL, V4, W>(a.x_prev + base, n, lane, xv);
+    st_row<PL, V4, W>(a.g_prev + base, n, lane, gv);
+  }
   if (lane == 0) {
-    a.meta[2 * s + 0] = count;
-    a.meta[2 * s + 1] = head;
+    int* mo = a.meta_out ? a.meta_out : a.meta;
+    mo[2 * s + 0] = count;
+    mo[2 * s + 1] = head;
     if (a.use_first) a.first[s] = 0;
   }
 }
@@ -287,18 +295,16 @@ __global__ __launch_bounds__(kWave) void lbfgs_kernel(const LbfgsArgs a) {
 // of at most W floats (inverse kinematics: T = 1); control flow then
 // diverges between the lane groups but never inside one, so every group
 // reduction sees only its own, active, lanes.
-template <int PL, int MH, bool FUSED, int KP, bool V4, int W = kWave>
-__global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const LbfgsArgs la) {
+// Seed s's choice by the W lanes of group sub of a wavefront (lane: the
+// lane within the group); the body of select_kernel, and the prologue of an
+// evaluation launch that folds the choice in.  st_ok false: compute, store
+// nothing.  xo / qo (or null): the new iterate and direction, element
+// el_idx(lane, u) in xo[u] / qo[u].
+template <int PL, int MH, bool FUSED, int KP, bool V4, int W>
+__device__ __forceinline__ void select_seed(const SelectArgs& a, const LbfgsArgs& la, int s, int lane, int sub,
+                                            bool st_ok, float* xo = nullptr, float* qo = nullptr) {
   static_assert(KP <= W && kWave % W == 0, "a candidate needs a lane of its seed's group");
   constexpr int SPW = kWave / W;       // seeds per wavefront
-  const int sub = SPW > 1 ? (int)threadIdx.x / W : 0;
-  const int lane = SPW > 1 ? (int)threadIdx.x % W : (int)threadIdx.x;
-  // (the grid is exactly one workgroup per SPW seeds; the last one's spare
-  // groups take the last seed and store nothing)
-  const int s_raw = (int)blockIdx.x * SPW + sub;
-  const bool st_ok = SPW == 1 || s_raw < a.n_seeds;
-  const int s = SPW == 1 ? s_raw : min(s_raw, a.n_seeds - 1);
-  warm_kernargs<sizeof(SelectArgs) + (FUSED ? sizeof(LbfgsArgs) + 8 : 0)>();
   const SeedInfo si = seed_info(a.seeds, a.uniform_T, s);
   const int D = a.dof, n = si.T * D;
   const size_t base = (size_t)si.row0 * D;
@@ -410,7 +416,25 @@ __global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const
     if (a.mc_out) a.mc_out[s] = mcb;
     if (improve) a.best_c[s] = cb;
   }
-  if constexpr (FUSED) lbfgs_finish<PL, MH, V4, W>(la, s, lane, si, xv, gdv, h, st_ok);
+  if (xo) {
+#pragma unroll
+    for (int u = 0; u < PL; ++u) xo[u] = xv[u];
+  }
+  if constexpr (FUSED) lbfgs_finish<PL, MH, V4, W>(la, s, lane, si, xv, gdv, h, st_ok, qo);
+}
+
+template <int PL, int MH, bool FUSED, int KP, bool V4, int W = kWave>
+__global__ __launch_bounds__(kWave) void select_kernel(const SelectArgs a, const LbfgsArgs la) {
+  constexpr int SPW = kWave / W;       // seeds per wavefront
+  const int sub = SPW > 1 ? (int)threadIdx.x / W : 0;
+  const int lane = SPW > 1 ? (int)threadIdx.x % W : (int)threadIdx.x;
+  // (the grid is exactly one workgroup per SPW seeds; the last one's spare
+  // groups take the last seed and store nothing)
+  const int s_raw = (int)blockIdx.x * SPW + sub;
+  const bool st_ok = SPW == 1 || s_raw < a.n_seeds;
+  const int s = SPW == 1 ? s_raw : min(s_raw, a.n_seeds - 1);
+  warm_kernargs<sizeof(SelectArgs) + (FUSED ? sizeof(LbfgsArgs) + 8 : 0)>();
+  select_seed<PL, MH, FUSED, KP, V4, W>(a, la, s, lane, sub, st_ok);
 }
 
 // Row blocks move as float4 when every seed's block is a multiple of 4

@@ -1,0 +1,62 @@
+"""The solve with each line-search choice (Alg.1) and L-BFGS direction
+(Alg.6) folded into the next evaluation launch against the same solve with
+separate launches: identical bits for the returned trajectories, best costs,
+best seeds and success flags (the fused launch runs the same arithmetic).
+
+  adjoint  32 seeds x 32 waypoints x 8 candidates (the benchmark's solve),
+           wave per link with one slice, four slices, and two slot groups
+  plain    4 seeds x 32 waypoints x 4 candidates
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2310_17274_amd import workloads as wl
+from tests.test_parity_gpu import make_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve(case, fused, use_graph, iters, alpha, m=4, mode=1, graph_inner=25):
+    case.b.mg_batch_set_fusion(fused)
+    x = case.x.clone()
+    x, bc, bs, ok = case.ctx.mg_solve(case.b, case.q_start, case.goal, x, iters, m, alpha, mode=mode,
+                                      graph_inner=graph_inner, use_graph=use_graph)
+    torch.cuda.synchronize()
+    return x.cpu().numpy(), bc.cpu().numpy(), bs.cpu().numpy(), ok.cpu().numpy()
+
+
+def _same(r1, r2):
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((1, 4), id="wave4"),
+                                    pytest.param((3, 0), id="groups2")])
+@pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "direct"])
+def test_fused_solve_equals_separate_launches_adjoint(layout, use_graph):
+    case = make_case("adjoint", layout=layout)
+    alpha = list(wl.cfg_cost_adjoint()[3]["alpha"])
+    _same(_solve(case, True, use_graph, 100, alpha), _solve(case, False, use_graph, 100, alpha))
+
+
+@pytest.mark.parametrize("mode", [0, 2])
+@pytest.mark.parametrize("iters", [1, 2, 27, 60])
+def test_fused_solve_equals_separate_launches_plain(iters, mode):
+    """Iteration counts around the graph length (26 fused iterations per
+    replay), the smallest, and the other line-search rules."""
+    case = make_case("plain", layout=(3, 0))
+    alpha = list(wl.ALPHA_4)
+    _same(_solve(case, True, True, iters, alpha, mode=mode), _solve(case, False, True, iters, alpha, mode=mode))
+
+
+def test_fused_solve_repeated_calls():
+    """Two solves in a row on one batch (the graph is replayed, and the
+    second starts from the first's state sets) equal the separate path."""
+    case = make_case("adjoint", layout=(3, 0))
+    alpha = list(wl.cfg_cost_adjoint()[3]["alpha"])
+    a1 = _solve(case, True, True, 60, alpha)
+    a2 = _solve(case, True, True, 60, alpha)
+    b1 = _solve(case, False, True, 60, alpha)
+    _same(a1, b1)
+    _same(a2, b1)
