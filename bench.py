@@ -66,9 +66,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--profile", choices=["eval", "copy", "large"],
+    ap.add_argument("--profile", choices=["eval", "solve", "copy", "large"],
                     help="profiling driver instead of the benchmark: 'eval' runs --launches "
                          "line searches of the benchmark shape (one evaluation launch each), "
+                         "'solve' --launches solves of the benchmark (graph replay), "
                          "'large' one particle round and --launches line searches of the large "
                          "two-arm workload, 'copy' copies 256 MiB five times (HBM byte-counter "
                          "calibration)")
@@ -135,11 +136,20 @@ def main():
 
     if args.profile == "eval":
         return profile_eval(ctx, b, q_start, goal, x0, c0, g0, dvec, alpha, args.launches, layout)
+    fused = ctx.mg_solve_fuses(b, K, 4, x0)
 
-    def solve(use_graph):
+    def solve(use_graph, n=iters):
         x.copy_(x0)
-        ctx.mg_solve(b, q_start, goal, x, iters, 4, alpha, mode=1, graph_inner=25,
+        ctx.mg_solve(b, q_start, goal, x, n, 4, alpha, mode=1, graph_inner=25,
                      use_graph=use_graph, outputs=outs)
+
+    if args.profile == "solve":
+        for _ in range(args.launches):
+            solve(True)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "solve", "solves": args.launches, "fused": fused, "layout": layout,
+                          "kernel_digest": kernel_digest()}), flush=True)
+        return
 
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -169,12 +179,37 @@ def main():
     torch.cuda.synchronize()
     ms_plain = ev0.elapsed_time(ev1) / n_plain
 
-    # evaluation kernel time: HIP events on the launch stream around 30
+    # the evaluation kernel alone: HIP events on the launch stream around 30
     # back-to-back launches of the solve's evaluation kernel and grid
     # (32 seeds x 32 waypoints x 8 candidates, cost + adjoint)
     n_ev = 30
     ctx.mg_time_eval(b, q_start, goal, x0, dvec, alpha, launches=3)
-    eval_us = ctx.mg_time_eval(b, q_start, goal, x0, dvec, alpha, launches=n_ev)
+    plain_eval_us = ctx.mg_time_eval(b, q_start, goal, x0, dvec, alpha, launches=n_ev)
+
+    def t_solve(n, use_graph=True, reps=10):
+        solve(use_graph, n)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            solve(use_graph, n)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    # With the choice folded in, each iteration after the first is one
+    # launch of the evaluation kernel that also makes the previous choice:
+    # its time per launch is the difference of two graph-replayed solve
+    # lengths (HIP events on the launch stream), which includes the gap
+    # between launches.  The same solve with separate choice launches, for
+    # comparison.
+    half = iters // 2
+    if fused:
+        eval_us = (t_solve(iters) - t_solve(half)) * 1e3 / (iters - half)
+        b.mg_batch_set_fusion(False)
+        ms_separate = t_solve(iters)
+        b.mg_batch_set_fusion(True)
+    else:
+        eval_us, ms_separate = plain_eval_us, None
 
     best = outs[0].cpu().numpy()
     evals_per_step = S * T * K * iters
@@ -205,15 +240,25 @@ def main():
         "ms_per_solve_batched": ms_batched,
         "ms_per_step_pct": pct(step_ms),
         "ms_per_solve_plain": ms_plain,
+        "choice_folded_into_evaluation": fused,
+        "ms_per_solve_choice_separate": ms_separate,
         "speedup_batched_vs_plain": ms_plain / ms_batched,
         "wall_s_timed": wall,
         "best_cost_min": float(best.min()),
         "roofline": {"bound": "alu",
-                     "kernel": ("eval_kernel" if layout.startswith("lane") else "eval_wl_kernel")
-                               + " (cost + adjoint, 8 candidates)",
+                     "kernel": ("eval_wl_fs_kernel (cost + adjoint, 8 candidates, the previous line-search "
+                                "choice and L-BFGS direction folded in)" if fused else
+                                ("eval_kernel" if layout.startswith("lane") else "eval_wl_kernel")
+                                + " (cost + adjoint, 8 candidates)"),
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(layout),
-                     "eval_kernel_us": eval_us, "eval_launches_timed": n_ev,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(layout, fused),
+                     "eval_kernel_us": eval_us,
+                     "eval_kernel_timing": ("(t(%d it.) - t(%d it.)) / %d of graph-replayed solves, 10 each"
+                                            % (iters, half, iters - half)) if fused else
+                                           "%d back-to-back launches (mg_time_eval)" % n_ev,
+                     "plain_eval_kernel_us": plain_eval_us,
+                     "plain_eval_frac": fl * S * T * K / (plain_eval_us * 1e-6) / 1e12 / PEAK_FP32_TFLOPS
+                     if plain_eval_us > 0 else 0.0,
                      "layout": layout,
                      "flop_per_eval": fl, "flop_count": "every pair tested (37 M N + 18 M + 170 L + 200 D + 300)",
                      "flop_per_eval_executed": fl_x,
@@ -237,7 +282,7 @@ def main():
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "eval_kernel_cost_adjoint_32x32x8_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2310_17274_amd", "csrc", f)
-                  for f in ("mg_eval.h", "mg_eval_wl.h", "mg_device.h", "mg_internal.h")]
+                  for f in ("mg_eval.h", "mg_eval_wl.h", "mg_device.h", "mg_internal.h", "mg_solver.h")]
 
 
 def kernel_digest():
@@ -262,11 +307,12 @@ def layout_name(tuned):
     return f"lane_per_link/{tuned}" if tuned > 0 else f"wave_per_link/{-tuned}"
 
 
-def measured_traffic(layout):
-    """HBM bytes per evaluation launch of `layout` from the committed
-    FETCH_SIZE / WRITE_SIZE counter summary (one `hbm_bytes_per_launch[<layout>]`
-    line per profiled layout), or None when the kernel sources changed since
-    the counters were taken, the layout was not profiled, or no summary
+def measured_traffic(layout, fused=False):
+    """HBM bytes per evaluation launch of `layout` (`fused`: the launch that
+    also makes the previous choice, key `fused/<layout>`) from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary (one `hbm_bytes_per_launch[<key>]`
+    line per profiled launch), or None when the kernel sources changed since
+    the counters were taken, the launch was not profiled, or no summary
     exists."""
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -276,7 +322,7 @@ def measured_traffic(layout):
         return None
     if fields.get("source_digest") != kernel_digest():
         return None
-    v = fields.get(f"hbm_bytes_per_launch[{layout}]")
+    v = fields.get(f"hbm_bytes_per_launch[{'fused/' if fused else ''}{layout}]")
     return float(v) if v is not None else None
 
 

@@ -289,6 +289,10 @@ mg_status mg_batch_set_layout(mg_batch *batch, int layout, int slices);
  * separate.  Host-only; affects later calls.  Errors: MG_ERR_ARG (null
  * batch). */
 mg_status mg_batch_set_fusion(mg_batch *batch, int enable);
+/* 1 when mg_solve on this batch with K candidates, history m and iterate x
+ * (device pointer, only its alignment is looked at) folds the choices into
+ * the evaluation launches, else 0 (also for invalid arguments).  Host-only. */
+int mg_solve_fuses(mg_ctx *ctx, mg_batch *batch, int K, int m, const float *x);
 mg_status mg_autotune(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
                       const float *x, const float *dir, int K, const float *alpha, int launches,
                       int *slices_out, void *stream);

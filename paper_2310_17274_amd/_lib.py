@@ -25,8 +25,8 @@ EXPORTS = ("mg_default_params", "mg_create", "mg_destroy", "mg_set_params", "mg_
            "mg_cost_grad", "mg_lbfgs_step", "mg_linesearch", "mg_linesearch_eval", "mg_linesearch_noalloc",
            "mg_solve",
            "mg_batch_reserve_particles", "mg_particles", "mg_particles_seeded", "mg_philox_normals",
-           "mg_set_timing", "mg_eval_time", "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_batch_set_fusion", "mg_ee_pose",
-           "mg_set_self_collision", "mg_retime", "mg_solve_timestep", "mg_ik_seeds", "mg_traj_select", "mg_motion_gen",
+           "mg_set_timing", "mg_eval_time", "mg_time_eval", "mg_autotune", "mg_batch_set_layout", "mg_batch_set_fusion", "mg_solve_fuses",
+           "mg_ee_pose", "mg_set_self_collision", "mg_retime", "mg_solve_timestep", "mg_ik_seeds", "mg_traj_select", "mg_motion_gen",
            "mg_steer", "mg_plan", "mg_plan_batch", "mg_knn", "mg_last_error")
 
 
@@ -94,6 +94,8 @@ def lib():
                                C.POINTER(C.c_float), _vp]
     L.mg_batch_set_layout.argtypes = [_vp, C.c_int, C.c_int]
     L.mg_batch_set_fusion.argtypes = [_vp, C.c_int]
+    L.mg_solve_fuses.argtypes = [_vp, _vp, C.c_int, C.c_int, _vp]
+    L.mg_solve_fuses.restype = C.c_int
     L.mg_ee_pose.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
     L.mg_set_self_collision.argtypes = [_vp, C.c_int, _ip]
     L.mg_autotune.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, C.c_int, _fp, C.c_int,

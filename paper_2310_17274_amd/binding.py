@@ -218,6 +218,10 @@ class Context:
                                                _ptr(xo), _ptr(co), _ptr(go), _ptr(ch), _ptr(mc), _stream()))
         return xo, co, go, ch, mc
 
+    def mg_solve_fuses(self, b: Batch, K, m, x) -> bool:
+        """Whether mg_solve folds each choice into the next evaluation launch."""
+        return bool(_lib.lib().mg_solve_fuses(self.handle, b.handle, int(K), int(m), _ptr(x)))
+
     def mg_solve(self, b: Batch, q_start, goal, x, iters, m, alpha, mode=1, graph_inner=25,
                  use_graph=True, outputs=None):
         """Solve in place on x; returns (x, best_cost, best_seed, success)."""

@@ -1591,6 +1591,11 @@ mg_status mg_batch_set_fusion(mg_batch* b, int enable) {
   return MG_OK;
 }
 
+int mg_solve_fuses(mg_ctx* c, mg_batch* b, int K, int m, const float* x) {
+  if (!c || !b || b->ctx != c || K < 1 || K > b->K_max || m < 0 || m > b->m_max) return 0;
+  return fuse_ok(c, b, K, m, x) ? 1 : 0;
+}
+
 mg_status mg_solve(mg_ctx* c, mg_batch* b, const float* q_start, const float* goal, float* x,
                    int iters, int m, int K, const float* alpha, int mode, int graph_inner,
                    int use_graph, float* best_cost, int* best_seed, int* success, void* stream) {

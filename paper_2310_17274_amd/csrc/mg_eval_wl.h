@@ -340,10 +340,14 @@ __device__ __forceinline__ void eval_wl_body(const EvalArgs& a, const FA& fa) {
   const int lane = threadIdx.x % kWave;
   const int g = lane / E, el = lane % E;
   warm_kernargs<sizeof(EvalArgs)>();
-  const int tid = threadIdx.x, nthreads = blockDim.x;
+  const int tid = threadIdx.x;
   const int L = a.rb.n_links, D = a.rb.dof, K = a.K, n_ee = a.rb.n_ee;
   const int maxd = a.wl.max_depth, maxs = a.wl.maxs;
-  const int bx = blockIdx.x;
+  // (FS: chunks in XCD-sized runs -- workgroups go to the 8 XCDs in turn,
+  // so workgroup b takes chunk (b mod 8) n/8 + b/8 and a seed's chunks share
+  // one XCD's L2 for the choice's reads; any permutation is correct)
+  const int nbx = gridDim.x;
+  const int bx = FS > 0 && nbx % 8 == 0 ? (int)(blockIdx.x % 8) * (nbx / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
   // cuboid slice of this workgroup (gridDim.y slices share a chunk)
   const int h = __builtin_amdgcn_readfirstlane(blockIdx.y), H = __builtin_amdgcn_readfirstlane(gridDim.y);
   // waves: link waves and one for the joint terms (HS = 1), or two per link
@@ -355,6 +359,7 @@ __device__ __forceinline__ void eval_wl_body(const EvalArgs& a, const FA& fa) {
   const int LW = HS == 2 ? 2 * L : (LP ? a.wl.link_waves : L);
   const int W = HS == 2 ? 2 * L : LW + 1;
   const int npass = LP ? (L + LW - 1) / LW : 1;
+  const int nthreads = W * kWave;   // (the launch's block: no read of the dispatch packet)
   const bool joint_w = HS == 1 && wave == W - 1;
   const bool sel_w = FS > 0 && joint_w;    // (the joint wave computes the choice)
 

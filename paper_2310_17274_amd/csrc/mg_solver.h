@@ -309,11 +309,10 @@ __device__ __forceinline__ void select_seed(const SelectArgs& a, const LbfgsArgs
   const int D = a.dof, n = si.T * D;
   const size_t base = (size_t)si.row0 * D;
 
-  // everything that does not depend on the choice is loaded first: the
-  // L-BFGS state, the joint limits, and for up to 8 candidates every
-  // candidate's gradient
-  LbfgsRegs<PL, FUSED ? MH : 1> h;
-  if constexpr (FUSED) lbfgs_load<PL, MH, V4, W>(la, s, lane, si, h);
+  // everything that does not depend on the choice is loaded first: for up
+  // to 8 candidates every candidate's gradient, the joint limits, the
+  // candidates' sums, the rows, then the L-BFGS state (whose per-seed
+  // scalars are waited for inside lbfgs_load, after every load is issued)
   constexpr int KG = (PL <= 4 && KP <= 8) ? KP : 1;
   const bool pre = KG > 1;
   float gall[KG][PL];
@@ -351,6 +350,8 @@ __device__ __forceinline__ void select_seed(const SelectArgs& a, const LbfgsArgs
   ld_row<PL, V4, W>(a.x + base, n, lane, xv);
   ld_row<PL, V4, W>(a.d + base, n, lane, dv);
   ld_row<PL, V4, W>(a.g0 + base, n, lane, g0v);
+  LbfgsRegs<PL, FUSED ? MH : 1> h;
+  if constexpr (FUSED) lbfgs_load<PL, MH, V4, W>(la, s, lane, si, h);
   float g0d = 0.0f;
 #pragma unroll
   for (int u = 0; u < PL; ++u) {
