@@ -215,8 +215,12 @@ mg_status mg_linesearch_noalloc(mg_ctx *ctx, mg_batch *batch, const float *q_sta
  *            ties) or NULL; success DEVICE [P] (best seed within
  *            success_pos / success_rot of the goal and collision free) or NULL.
  * use_graph != 0 captures graph_inner iterations in a hipGraph and replays it
- * (the first call for a new argument set captures; later calls replay);
- * use_graph == 0 launches every kernel directly.  Not capturable itself. */
+ * (the first call for a new argument set captures; later calls replay; when
+ * the choices are folded into the evaluation launches, see
+ * mg_batch_set_fusion, a graph holds graph_inner rounded up to even
+ * iterations); use_graph == 0 launches every kernel directly.  The batch's
+ * L-BFGS history and workspaces are the solve's: their contents after the
+ * call are unspecified.  Not capturable itself. */
 mg_status mg_solve(mg_ctx *ctx, mg_batch *batch, const float *q_start, const float *goal,
                    float *x, int iters, int m, int K, const float *alpha, int mode,
                    int graph_inner, int use_graph, float *best_cost, int *best_seed,
