@@ -50,6 +50,30 @@ def test_fused_solve_equals_separate_launches_plain(iters, mode):
     _same(_solve(case, True, True, iters, alpha, mode=mode), _solve(case, False, True, iters, alpha, mode=mode))
 
 
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_fused_solve_shorter_histories(m):
+    """History lengths below the kernel's four register slots (the ring
+    wraps sooner)."""
+    case = make_case("plain", layout=(1, 1))
+    alpha = list(wl.ALPHA_4)
+    _same(_solve(case, True, True, 60, alpha, m=m), _solve(case, False, True, 60, alpha, m=m))
+
+
+def test_fusion_applies_where_the_batch_qualifies():
+    """The benchmark's batch in the two-slot-group layout folds the choice
+    in; more than 4 history pairs, fusion switched off, an IK batch (7
+    floats per seed) and the lane-per-link layout do not."""
+    case = make_case("adjoint", layout=(3, 0))
+    assert case.ctx.mg_solve_fuses(case.b, 8, 4, case.x)
+    assert not case.ctx.mg_solve_fuses(case.b, 8, 5, case.x)      # more than 4 history pairs
+    case.b.mg_batch_set_fusion(False)
+    assert not case.ctx.mg_solve_fuses(case.b, 8, 4, case.x)
+    ik = make_case("ik", layout=(1, 1))
+    assert not ik.ctx.mg_solve_fuses(ik.b, 4, 4, ik.x)
+    lane = make_case("adjoint", layout=(0, 0))
+    assert not lane.ctx.mg_solve_fuses(lane.b, 8, 4, lane.x)
+
+
 def test_fused_solve_repeated_calls():
     """Two solves in a row on one batch (the graph is replayed, and the
     second starts from the first's state sets) equal the separate path."""
