@@ -340,6 +340,10 @@ __device__ __forceinline__ void eval_wl_body(const EvalArgs& a, const FA& fa) {
   const int lane = threadIdx.x % kWave;
   const int g = lane / E, el = lane % E;
   warm_kernargs<sizeof(EvalArgs)>();
+  // (FS: the choice's arguments follow; brought in with the same round)
+  constexpr int fs_off = (int)((sizeof(EvalArgs) + alignof(SelFuse) - 1) / alignof(SelFuse) * alignof(SelFuse));
+  static_assert(sizeof(SelFuse) <= 512, "the choice's arguments fit one warm-up");
+  if constexpr (FS > 0) warm_kernargs<(int)sizeof(SelFuse), fs_off>();
   const int tid = threadIdx.x;
   const int L = a.rb.n_links, D = a.rb.dof, K = a.K, n_ee = a.rb.n_ee;
   const int maxd = a.wl.max_depth, maxs = a.wl.maxs;
@@ -504,9 +508,6 @@ __device__ __forceinline__ void eval_wl_body(const EvalArgs& a, const FA& fa) {
     }
     if constexpr (FS > 0) {
       if (sel_w) {
-        constexpr int off = (int)((sizeof(EvalArgs) + alignof(SelFuse) - 1) / alignof(SelFuse) * alignof(SelFuse));
-        static_assert(sizeof(SelFuse) <= 512, "the choice's arguments fit one warm-up");
-        warm_kernargs<(int)sizeof(SelFuse), off>();
         const int T = pb.T;
         const int rl0 = e_first / K;                  // (the chunk's first row in its problem)
         const int srow0 = pb.row0 + rl0 - rl0 % T;    // the seed's first row
