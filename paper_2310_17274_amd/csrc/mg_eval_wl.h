@@ -1062,7 +1062,7 @@ template <int MAXS, int G, bool SW, bool SP>
 hipError_t wl_pick(const EvalArgs& a, dim3 grid, dim3 block, size_t lds, int waves, bool cand, bool grad,
                    hipStream_t s, const SelFuse* fs) {
   if (fs) {
-    if constexpr (MAXS <= 8 && G <= 2 && !SW && !SP) {
+    if constexpr (MAXS <= 8 && !SW && !SP) {
       if (a.wl.halves != 1 || a.wl.link_waves < a.rb.n_links || waves > 8 || !cand || !grad)
         return hipErrorInvalidValue;
       if (fs->sa.K <= 4) return wl_launch(eval_wl_fs_kernel<MAXS, G, 4>, grid, block, lds, s, a, *fs);

@@ -429,8 +429,8 @@ hipError_t launch_eval(const EvalArgs& a, int grid_x, bool cand, bool grad, hipS
 // wave-per-link layout: grid_x workgroups of 64 evaluations (chunk_prefix
 // counts 64-evaluation chunks of rows x K per problem)
 // fs (or null): the previous choice folded into this launch (cost and
-// gradient of candidates, the wave-per-link layout with one or two slot
-// groups, link waves alone, no swept collision or speed metric)
+// gradient of candidates, the wave-per-link layout with one joint wave and
+// link waves alone, no swept collision or speed metric)
 hipError_t launch_eval_wl(const EvalArgs& a, int grid_x, int slices, bool cand, bool grad, hipStream_t s,
                           const SelFuse* fs = nullptr);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);

@@ -4,7 +4,7 @@ separate launches: identical bits for the returned trajectories, best costs,
 best seeds and success flags (the fused launch runs the same arithmetic).
 
   adjoint  32 seeds x 32 waypoints x 8 candidates (the benchmark's solve),
-           wave per link with one slice, four slices, and two slot groups
+           wave per link with one slice, four slices, two and four slot groups
   plain    4 seeds x 32 waypoints x 4 candidates
 """
 import numpy as np
@@ -32,7 +32,7 @@ def _same(r1, r2):
 
 
 @pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((1, 4), id="wave4"),
-                                    pytest.param((3, 0), id="groups2")])
+                                    pytest.param((3, 0), id="groups2"), pytest.param((4, 0), id="groups4")])
 @pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "direct"])
 def test_fused_solve_equals_separate_launches_adjoint(layout, use_graph):
     case = make_case("adjoint", layout=layout)
@@ -72,6 +72,10 @@ def test_fusion_applies_where_the_batch_qualifies():
     assert not ik.ctx.mg_solve_fuses(ik.b, 4, 4, ik.x)
     lane = make_case("adjoint", layout=(0, 0))
     assert not lane.ctx.mg_solve_fuses(lane.b, 8, 4, lane.x)
+    halves = make_case("adjoint", layout=(2, 0))                  # two waves per link: no joint wave
+    assert not halves.ctx.mg_solve_fuses(halves.b, 8, 4, halves.x)
+    g4 = make_case("adjoint", layout=(4, 0))
+    assert g4.ctx.mg_solve_fuses(g4.b, 8, 4, g4.x)
 
 
 def test_fused_solve_repeated_calls():
