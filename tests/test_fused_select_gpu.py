@@ -59,6 +59,21 @@ def test_fused_solve_shorter_histories(m):
     _same(_solve(case, True, True, 60, alpha, m=m), _solve(case, False, True, 60, alpha, m=m))
 
 
+@pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((3, 0), id="groups2")])
+def test_fused_solve_several_problems(layout):
+    """Three problems of one horizon with different seed counts and worlds
+    (workgroup chunks from the record table, seeds after the first
+    problem's rows)."""
+    from tests.test_parity_gpu import Case
+    robot = wl.make_arm(seed=0, n_spheres=52)
+    worlds = wl.make_worlds(8, [40, 12, 25])
+    batch = wl.make_batch(robot, 77, [3, 5, 2], [32, 32, 32], [0, 1, 2])
+    case = Case(robot, worlds, batch, layout=layout)
+    alpha = list(wl.cfg_cost_adjoint()[3]["alpha"])
+    assert case.ctx.mg_solve_fuses(case.b, len(alpha), 4, case.x)
+    _same(_solve(case, True, True, 60, alpha), _solve(case, False, True, 60, alpha))
+
+
 def test_fusion_applies_where_the_batch_qualifies():
     """The benchmark's batch in the two-slot-group layout folds the choice
     in; more than 4 history pairs, fusion switched off, an IK batch (7
