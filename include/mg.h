@@ -505,7 +505,8 @@ mg_status mg_plan(mg_ctx *ctx, mg_batch *batch, const float *start, const float 
 /* Measurement hooks.  mg_set_timing(batch, 1) clears the batch's timing
  * record and from then on brackets every direct evaluation-kernel launch
  * made for the batch with a pair of HIP events on the launch stream
- * (launches captured into a graph are not timed); 0 turns it off.
+ * (launches captured into a graph, and mg_solve's launches that fold in
+ * the previous choice, are not timed); 0 turns it off.
  * mg_eval_time waits for the recorded events and returns the mean kernel
  * time in microseconds over the last <= 256 recorded launches and how many
  * that was.  Not capturable. */
