@@ -50,6 +50,16 @@ def test_fused_solve_equals_separate_launches_plain(iters, mode):
     _same(_solve(case, True, True, iters, alpha, mode=mode), _solve(case, False, True, iters, alpha, mode=mode))
 
 
+@pytest.mark.parametrize("K", [1, 2, 8])
+def test_fused_solve_candidate_counts(K):
+    """One, two and eight candidates (padded to 4 or 8 in the choice; with
+    32 evaluations per workgroup a chunk holds 32 / K rows of one seed)."""
+    case = make_case("adjoint", layout=(3, 0))
+    alpha = [float(a) for a in np.linspace(0.05, 1.0, K)]
+    assert case.ctx.mg_solve_fuses(case.b, K, 4, case.x)
+    _same(_solve(case, True, True, 40, alpha), _solve(case, False, True, 40, alpha))
+
+
 @pytest.mark.parametrize("m", [1, 2, 3])
 def test_fused_solve_shorter_histories(m):
     """History lengths below the kernel's four register slots (the ring
