@@ -287,9 +287,10 @@ mg_status mg_batch_set_layout(mg_batch *batch, int layout, int slices);
  * evaluation launch (every workgroup for its own seed, the seed's first one
  * storing them) instead of in a launch of its own, where the batch
  * qualifies: wave-per-link layout with one wave per link and at most 7
- * links (one, two or four slot groups), no swept collision or speed metric, one horizon T with T * D <= 256
- * and a multiple of 4, K <= 8, m <= 4, and x 16-byte aligned.  The results
- * are those of the separate launches.  enable = 0 keeps the launches
+ * links (one, two or four slot groups), no swept collision or speed metric,
+ * one horizon T with 128 < T * D <= 256 and T * D a multiple of 4, K <= 8,
+ * m <= 4, and x 16-byte aligned.  The results are those of the separate
+ * launches, bit for bit.  enable = 0 keeps the launches
  * separate.  Host-only; affects later calls.  Errors: MG_ERR_ARG (null
  * batch). */
 mg_status mg_batch_set_fusion(mg_batch *batch, int enable);

@@ -674,15 +674,17 @@ mg_status enqueue_lbfgs(mg_ctx* c, mg_batch* b, int m, int reset, const float* x
 // when the batch's layout and shapes allow it (the conditions of
 // launch_eval_wl's fs path): wave per link (one, two or four slot groups)
 // with a joint wave and no link passes, no swept collision or speed metric,
-// one horizon with blocks of at most 256 floats (a multiple of 4), at most 8
-// candidates and 4 history pairs, and workgroup chunks inside one seed.
+// one horizon with blocks of 129 to 256 floats (a multiple of 4: the
+// separate choice then holds 4 per lane too, so both sum in the same order),
+// at most 8 candidates and 4 history pairs, and workgroup chunks inside one
+// seed.
 bool fuse_ok(const mg_ctx* c, const mg_batch* b, int K, int m, const float* x) {
   if (!b->fusion || !use_wl(b, K) || c->params.swept || c->params.speed) return false;
   const int groups = b->wl_groups > 1 && wl_groups_possible(c, b->wl_groups) ? b->wl_groups : 1;
   const int halves = groups > 1 ? 1 : (b->wl_halves > 0 ? b->wl_halves : (wl_halves_possible(c) ? 2 : 1));
   if (halves != 1 || c->L + 1 > 8 || c->maxs / groups > 8) return false;
   const int T = b->uniform_T, E = mg::kWave / groups, n = T * c->D;
-  return T > 0 && n <= 4 * mg::kWave && n % 4 == 0 && K <= 8 && E % K == 0 && T % (E / K) == 0 && m >= 1 &&
+  return T > 0 && n > 2 * mg::kWave && n <= 4 * mg::kWave && n % 4 == 0 && K <= 8 && E % K == 0 && T % (E / K) == 0 && m >= 1 &&
          m <= 4 && ((uintptr_t)x & 15) == 0;
 }
 

@@ -1115,12 +1115,12 @@ hipError_t launch_eval_wl_g(const EvalArgs& a, int grid_x, int slices, bool cand
                                   a.wl.maxs, kWave / G, pm ? a.wl.pm_rows : 0);
   if (lds > kWlLdsMax) return hipErrorInvalidValue;
   if (fs) {
-    // the choice: uniform horizons, blocks of at most 256 floats moved as
-    // float4, at most 8 candidates and 4 history pairs, and every chunk of
-    // E / K rows inside one seed
+    // the choice: uniform horizons, blocks of 129 to 256 floats moved as
+    // float4 (four per lane), at most 8 candidates and 4 history pairs, and
+    // every chunk of E / K rows inside one seed
     const SelectArgs& sa = fs->sa;
     const int T = sa.uniform_T, E = kWave / G, n = T * a.rb.dof;
-    if (T < 1 || n > 4 * kWave || n % 4 || sa.K != a.K || sa.K > 8 || E % sa.K || T % (E / sa.K) ||
+    if (T < 1 || n <= 2 * kWave || n > 4 * kWave || n % 4 || sa.K != a.K || sa.K > 8 || E % sa.K || T % (E / sa.K) ||
         fs->la.m > 4 || fs->la.use_first || !fs->la.keep_prev || !fs->la.meta_out)
       return hipErrorInvalidValue;
   }

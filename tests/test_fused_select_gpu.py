@@ -84,6 +84,17 @@ def test_fused_solve_several_problems(layout):
     _same(_solve(case, True, True, 60, alpha), _solve(case, False, True, 60, alpha))
 
 
+@pytest.mark.parametrize("layout", [pytest.param((1, 1), id="wave"), pytest.param((1, 4), id="wave4")])
+def test_fused_solve_self_collision(layout):
+    """Self-collision on (its phase runs after the folded choice, between
+    the staging and the world tiles), horizon 32."""
+    from tests.test_parity_gpu import _self_case
+    case = _self_case(layout, T=32)
+    alpha = list(wl.cfg_cost_adjoint()[3]["alpha"])
+    assert case.ctx.mg_solve_fuses(case.b, len(alpha), 4, case.x)
+    _same(_solve(case, True, True, 40, alpha), _solve(case, False, True, 40, alpha))
+
+
 def test_fusion_applies_where_the_batch_qualifies():
     """The benchmark's batch in the two-slot-group layout folds the choice
     in; more than 4 history pairs, fusion switched off, an IK batch (7
@@ -97,6 +108,9 @@ def test_fusion_applies_where_the_batch_qualifies():
     assert not ik.ctx.mg_solve_fuses(ik.b, 4, 4, ik.x)
     lane = make_case("adjoint", layout=(0, 0))
     assert not lane.ctx.mg_solve_fuses(lane.b, 8, 4, lane.x)
+    from tests.test_parity_gpu import _self_case
+    short = _self_case((1, 1), T=16)                              # 112 floats per seed: 2 per lane apart
+    assert not short.ctx.mg_solve_fuses(short.b, 8, 4, short.x)
     halves = make_case("adjoint", layout=(2, 0))                  # two waves per link: no joint wave
     assert not halves.ctx.mg_solve_fuses(halves.b, 8, 4, halves.x)
     g4 = make_case("adjoint", layout=(4, 0))
