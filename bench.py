@@ -234,7 +234,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"cost+adjoint solve: {S} seeds x T={T} x K={K} candidates, "
                                f"{D}-DOF arm, {robot.n_spheres} spheres, {worlds.pose.shape[0]} "
-                               f"oriented cuboids, {iters} L-BFGS iterations (graphs of 25)",
+                               f"oriented cuboids, {iters} L-BFGS iterations (graph_inner 25; a graph "
+                               f"holds 26 when the choice is folded into the evaluation)",
                    "seeds": S, "horizon": T, "candidates": K, "iterations": iters,
                    "spheres": robot.n_spheres, "cuboids": int(worlds.pose.shape[0])},
         "ms_per_solve_batched": ms_batched,
